@@ -1,0 +1,187 @@
+/*
+ * gc.h -- C ABI of libgc: decoding of Group-codec posting lists on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The codecs are those of Zhao et al., "A General SIMD-based Approach to
+ * Accelerating Compression Algorithms" (arXiv 1502.01916): Group-Simple
+ * (Section 4), Group-Scheme (Section 5), Group-AFOR (Section 6.1) and
+ * Group-PFD (Section 6.2), each storing its control patterns apart from the
+ * packed data, which uses the k-way vertical layout (Section 3.1; the paper's
+ * k is 4, wider k is a GPU-native option).  Decoding is followed by the
+ * d-gap prefix sum that restores docIDs (Section 2.1.1).
+ *
+ * Conventions for every entry point:
+ *   - Returns gc_status: GC_OK (0) or a negative error.  Never throws, never
+ *     aborts, never prints.
+ *   - The caller owns every buffer passed in, host or device; the library
+ *     never frees or retains them past the call (a plan keeps the device
+ *     pointers it captured until it is destroyed or re-executed with others).
+ *   - "d_" pointers are device (HIP) pointers, "h_" pointers host pointers.
+ *   - Decode calls are asynchronous on the given HIP stream (NULL = the null
+ *     stream).  Stream corruption found on the device is not returned by the
+ *     call; it is latched in the context and reported by gc_sync_status.
+ *   - On any error the contents of the output range are unspecified, but the
+ *     library never writes outside it.
+ *
+ * Stream format (little-endian uint32 words, self-describing):
+ *   word 0  version:8 (=1) | codec:4 | log2(k):3 | log2(CG):2 | LD:2 |
+ *           delta:1 | pfd_pos:1 | reserved:11 (zero)
+ *   word 1  n, the number of integers
+ *   word 2  C, control-area words (multiple of 4)
+ *   word 3  D, data-area words (multiple of k)
+ *   then the control area, the data area (word w of component c at k*w + c;
+ *   each component an LSB-first bitstream, straddling values low part first)
+ *   and, for Group-PFD, the exception area; total length a multiple of 4.
+ */
+#ifndef GC_H
+#define GC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GC_OK = 0,
+    GC_EINVAL = -1,       /* bad argument or unsupported parameter combination */
+    GC_ENOSPC = -2,       /* output capacity too small                           */
+    GC_ECORRUPT = -3,     /* malformed stream (host check or latched by device)  */
+    GC_EDEVICE = -4,      /* a HIP runtime call failed                           */
+    GC_EUNSUPPORTED = -5, /* valid stream the GPU path does not handle           */
+    GC_ENOMEM = -6        /* host or device allocation failed                    */
+} gc_status;
+
+/* Codec identifiers (header word 0 bits 8..11). */
+typedef enum {
+    GC_SIMPLE = 0,  /* Group-Simple: 4-bit selectors of Table III, one vector each   */
+    GC_SCHEME = 1,  /* Group-Scheme CG-LD: eq. (1)-(2), unary or binary descriptors   */
+    GC_AFOR = 2,    /* Group-AFOR: frames of 8/16/32 tuples, DP partition            */
+    GC_PFD = 3      /* Group-PFD: 32-tuple blocks, exceptions in a separate area      */
+} gc_codec;
+
+/* Group-Scheme length descriptor (Section 5.2.1). */
+enum { GC_LD_BINARY = 0, GC_LD_CU = 1, GC_LD_IU = 2 };
+/* Group-PFD exception positions: a linked chain through the normal slots
+ * (the paper's "first exception offset", Section 6.2) or a per-block bitmap. */
+enum { GC_PFD_LINKED = 0, GC_PFD_BITMAP = 1 };
+
+/* gc_params.flags */
+#define GC_DELTA 1u   /* input is a docID list: code its d-gaps; decode prefix-sums */
+
+typedef struct {
+    uint32_t k;          /* layout width: 4 (the paper's) .. 64, a power of two      */
+    uint8_t cg;          /* Group-Scheme compression granularity 1, 2, 4, 8 (Sec 5.1) */
+    uint8_t ld;          /* Group-Scheme length descriptor GC_LD_*                    */
+    uint8_t pfd_pos;     /* Group-PFD GC_PFD_LINKED or GC_PFD_BITMAP                  */
+    uint8_t reserved;    /* zero                                                      */
+    uint16_t zeta_num;   /* Group-PFD exception-ratio threshold zeta = num/den,       */
+    uint16_t zeta_den;   /*   0 < zeta < 1 (Section 6.2, step 2); 1/10 in the paper   */
+    uint32_t flags;      /* GC_DELTA                                                  */
+} gc_params;
+
+/* ---- host-side encoding (index build) --------------------------------- */
+
+/* Upper bound, in words, of the stream gc_encode writes for n integers. */
+size_t gc_encoded_bound_words(size_t n, gc_codec codec, const gc_params *p);
+
+/* Encodes h_in[0..n) (host memory) into one stream at h_out (host memory,
+ * capacity out_cap_words).  Group-Simple selection follows Algorithm 1
+ * (Section 4.2), Group-AFOR the optimal DP partition (Section 6.1), Group-PFD
+ * encoding steps 1-4 (Section 6.2).  *out_words receives the stream length.
+ * GC_EINVAL for bad parameters, GC_ENOSPC if the capacity is too small.     */
+gc_status gc_encode(const uint32_t *h_in, size_t n, gc_codec codec, const gc_params *p,
+                    uint32_t *h_out, size_t out_cap_words, size_t *out_words);
+
+/* Sum of gc_encoded_bound_words over the lists of a gc_encode_lists call
+ * (same arguments); 0 on bad arguments.                                    */
+size_t gc_encoded_bound_words_lists(const uint64_t *in_offs, size_t nlists, const gc_codec *codecs,
+                                    const gc_params *params, int one_param);
+
+/* Encodes many lists on all host cores.  List i is h_in[in_offs[i] ..
+ * in_offs[i+1]), coded with codecs[i] / params[i] (params may hold a single
+ * entry used for all lists when one_param != 0).  Streams are written back to
+ * back into h_out; out_offs[i] receives stream i's word offset and
+ * out_offs[nlists] the total.  nthreads = 0 uses every core.               */
+gc_status gc_encode_lists(const uint32_t *h_in, const uint64_t *in_offs, size_t nlists,
+                          const gc_codec *codecs, const gc_params *params, int one_param,
+                          uint32_t *h_out, size_t out_cap_words, uint64_t *out_offs,
+                          int nthreads);
+
+/* ---- device context ---------------------------------------------------- */
+
+typedef struct gc_ctx gc_ctx;     /* opaque, library-owned */
+typedef struct gc_plan gc_plan;   /* opaque, library-owned */
+
+/* Creates a context on HIP device `device` (made current for the call).
+ * Allocates the device status word and the single-list scratch.           */
+gc_status gc_ctx_create(int device, gc_ctx **ctx);
+gc_status gc_ctx_destroy(gc_ctx *ctx);
+
+/* Decodes one stream (device memory, stream_words words) into d_out[0..n),
+ * prefix-summing when the header's delta bit is set.  n must equal the
+ * header's n (the index dictionary knows list lengths, Section 2.1.1, so no
+ * device-to-host read is needed).  Asynchronous on hip_stream.  Calls on one
+ * context must not overlap in time (they share its scratch); use one
+ * context per concurrent stream.  d_stream must be 16-byte aligned.        */
+gc_status gc_decode(gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words, size_t n,
+                    uint32_t *d_out, void *hip_stream);
+
+/* One list of a batch: its stream at d_streams + stream_off_words (16-byte
+ * aligned, stream_words long), its output at d_out + out_off (n words).    */
+typedef struct {
+    uint64_t stream_off_words;
+    uint64_t stream_words;
+    uint64_t out_off;
+    uint32_t n;
+    uint32_t reserved;
+} gc_list_desc;
+
+/* Plan options (zero-initialise for defaults). */
+typedef struct {
+    uint32_t tile_ints;      /* integers per decode tile: 0 = autotuned / default   */
+    uint32_t blocks_per_cu;  /* persistent workgroups per CU: 0 = autotuned/default */
+    uint32_t use_graph;      /* 1 = capture the launch sequence in a hipGraph       */
+    uint32_t autotune;       /* 1 = time candidate configurations at creation       */
+    uint32_t reserved[4];
+} gc_plan_opts;
+
+/* Builds a batched decode plan for nlists lists.  h_headers holds the first
+ * 4 words of every stream (4*nlists words, host memory).  The plan holds the
+ * work queue, the per-tile locate table and look-back flags, and (optionally)
+ * an instantiated hipGraph; it allocates everything here, never at execute.
+ * With opts->autotune the plan times candidate tile sizes and occupancies on
+ * the device buffers given (d_streams, d_out) and keeps the fastest; results
+ * are cached in a JSON file named by $GC_AUTOTUNE_CACHE when set.          */
+gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists,
+                         const uint32_t *h_headers, const gc_plan_opts *opts,
+                         const uint32_t *d_streams, uint32_t *d_out, gc_plan **plan);
+gc_status gc_plan_destroy(gc_plan *plan);
+
+/* Decodes every list of the plan in one persistent launch sequence
+ * (captured in a hipGraph when the plan was created with use_graph).       */
+gc_status gc_decode_batch(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_out,
+                          void *hip_stream);
+
+/* Decodes every list of the plan with one launch sequence per list (the
+ * per-list baseline the batch is compared with).                          */
+gc_status gc_decode_each(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_out,
+                         void *hip_stream);
+
+/* Reports the chosen configuration of a plan. */
+gc_status gc_plan_config(const gc_plan *plan, uint32_t *tile_ints, uint32_t *blocks_per_cu,
+                         uint32_t *grid_blocks);
+
+/* Synchronises hip_stream, then returns (and clears) the first device-side
+ * error latched since the previous call: GC_OK or GC_ECORRUPT.  detail, if
+ * not NULL, receives an implementation-specific code of the failed check.  */
+gc_status gc_sync_status(gc_ctx *ctx, void *hip_stream, uint32_t *detail);
+
+/* Library version string. */
+const char *gc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GC_H */

@@ -1,0 +1,277 @@
+"""Thin ctypes binding of libgc (include/gc.h): argument marshalling only.
+
+Every decode step runs in libgc's HIP kernels; this module only converts
+numpy arrays and torch device tensors into pointers and sizes.  Importing it
+does not load the library; the first call does, and raises if libgc.so has
+not been built (``python -m paper_1502_01916_amd.build``) -- there is no CPU
+fallback.
+
+Device buffers are torch tensors (int32 storage holding uint32 bit patterns);
+streams are ``torch.cuda.current_stream().cuda_stream`` unless given.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+SIMPLE, SCHEME, AFOR, PFD = 0, 1, 2, 3
+LD_BINARY, LD_CU, LD_IU = 0, 1, 2
+PFD_LINKED, PFD_BITMAP = 0, 1
+DELTA = 1
+OK, EINVAL, ENOSPC, ECORRUPT, EDEVICE, EUNSUPPORTED, ENOMEM = 0, -1, -2, -3, -4, -5, -6
+_NAMES = {0: "GC_OK", -1: "GC_EINVAL", -2: "GC_ENOSPC", -3: "GC_ECORRUPT", -4: "GC_EDEVICE",
+          -5: "GC_EUNSUPPORTED", -6: "GC_ENOMEM"}
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgc.so")
+_lib = None
+_lock = threading.Lock()
+
+
+class GcError(RuntimeError):
+    def __init__(self, fn, code, detail=None):
+        self.code = code
+        self.detail = detail
+        msg = "%s returned %s" % (fn, _NAMES.get(code, code))
+        if detail:
+            msg += " (detail %d)" % detail
+        super().__init__(msg)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("cg", ctypes.c_uint8), ("ld", ctypes.c_uint8),
+                ("pfd_pos", ctypes.c_uint8), ("reserved", ctypes.c_uint8),
+                ("zeta_num", ctypes.c_uint16), ("zeta_den", ctypes.c_uint16),
+                ("flags", ctypes.c_uint32)]
+
+
+class ListDesc(ctypes.Structure):
+    _fields_ = [("stream_off_words", ctypes.c_uint64), ("stream_words", ctypes.c_uint64),
+                ("out_off", ctypes.c_uint64), ("n", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("tile_ints", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
+                ("use_graph", ctypes.c_uint32), ("autotune", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 4)]
+
+
+def params(k=4, cg=1, ld=LD_CU, pfd_pos=PFD_LINKED, zeta=(1, 10), delta=False):
+    return Params(int(k), int(cg), int(ld), int(pfd_pos), 0, int(zeta[0]), int(zeta[1]),
+                  DELTA if delta else 0)
+
+
+def lib():
+    """Loads libgc.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libgc.so is not built: run python -m paper_1502_01916_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, u32p = ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint32)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        i = ctypes.c_int
+        L.gc_version.restype = ctypes.c_char_p
+        L.gc_encoded_bound_words.argtypes = [sz, i, ctypes.POINTER(Params)]
+        L.gc_encoded_bound_words.restype = sz
+        L.gc_encode.argtypes = [u32p, sz, i, ctypes.POINTER(Params), u32p, sz, ctypes.POINTER(sz)]
+        L.gc_encoded_bound_words_lists.argtypes = [u64p, sz, ctypes.POINTER(ctypes.c_int),
+                                                   ctypes.POINTER(Params), i]
+        L.gc_encoded_bound_words_lists.restype = sz
+        L.gc_encode_lists.argtypes = [u32p, u64p, sz, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Params),
+                                      i, u32p, sz, u64p, i]
+        L.gc_ctx_create.argtypes = [i, ctypes.POINTER(vp)]
+        L.gc_ctx_destroy.argtypes = [vp]
+        L.gc_decode.argtypes = [vp, vp, sz, sz, vp, vp]
+        L.gc_plan_create.argtypes = [vp, ctypes.POINTER(ListDesc), sz, u32p, ctypes.POINTER(PlanOpts),
+                                     vp, vp, ctypes.POINTER(vp)]
+        L.gc_plan_destroy.argtypes = [vp]
+        L.gc_decode_batch.argtypes = [vp, vp, vp, vp]
+        L.gc_decode_each.argtypes = [vp, vp, vp, vp]
+        L.gc_plan_config.argtypes = [vp, u32p, u32p, u32p]
+        L.gc_sync_status.argtypes = [vp, vp, u32p]
+        for f in ("gc_encode", "gc_encode_lists", "gc_ctx_create", "gc_ctx_destroy", "gc_decode",
+                  "gc_plan_create", "gc_plan_destroy", "gc_decode_batch", "gc_decode_each",
+                  "gc_plan_config", "gc_sync_status"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+        return L
+
+
+def _check(fn, rc, detail=None):
+    if rc != OK:
+        raise GcError(fn, rc, detail)
+
+
+def _u32(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+
+def version():
+    return lib().gc_version().decode()
+
+
+# ---------------------------------------------------------------------------
+# Host encoding.
+
+def encoded_bound_words(n, codec, p: Params):
+    return lib().gc_encoded_bound_words(n, codec, ctypes.byref(p))
+
+
+def encode(x, codec, p: Params):
+    """gc_encode: one uint32 list -> one stream (numpy uint32 words)."""
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    cap = encoded_bound_words(x.size, codec, p)
+    out = np.zeros(max(cap, 4), np.uint32)
+    w = ctypes.c_size_t()
+    _check("gc_encode", lib().gc_encode(_u32(x), x.size, codec, ctypes.byref(p), _u32(out), out.size,
+                                        ctypes.byref(w)))
+    return out[:w.value].copy()
+
+
+def encode_lists(flat, lengths, codecs, plist, nthreads=0):
+    """gc_encode_lists: many lists (concatenated in `flat`) on all host cores.
+    `codecs` is one codec per list; `plist` one Params or one per list.
+    Returns (streams_flat, stream_offsets[nlists+1])."""
+    flat = np.ascontiguousarray(flat, dtype=np.uint32)
+    lengths = np.asarray(lengths, dtype=np.int64)
+    nl = lengths.size
+    in_offs = np.zeros(nl + 1, np.uint64)
+    np.cumsum(lengths, out=in_offs[1:])
+    cod = np.ascontiguousarray(np.broadcast_to(np.asarray(codecs, dtype=np.int32), (nl,)))
+    one = isinstance(plist, Params)
+    parr = (Params * (1 if one else nl))()
+    if one:
+        parr[0] = plist
+    else:
+        for i, p in enumerate(plist):
+            parr[i] = p
+    cap = lib().gc_encoded_bound_words_lists(in_offs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), nl,
+                                             cod.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), parr, int(one))
+    out = np.zeros(cap, np.uint32)
+    offs = np.zeros(nl + 1, np.uint64)
+    rc = lib().gc_encode_lists(_u32(flat), in_offs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), nl,
+                               cod.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), parr, int(one),
+                               _u32(out), out.size, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                               int(nthreads))
+    _check("gc_encode_lists", rc)
+    return out[:int(offs[-1])], offs
+
+
+# ---------------------------------------------------------------------------
+# Device decoding.
+
+def _stream_handle(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """gc_ctx_create / gc_decode / gc_sync_status / gc_ctx_destroy."""
+
+    def __init__(self, device=0):
+        self._h = ctypes.c_void_p()
+        _check("gc_ctx_create", lib().gc_ctx_create(int(device), ctypes.byref(self._h)))
+
+    def decode(self, d_stream, stream_words, n, d_out, stream=None):
+        _check("gc_decode", lib().gc_decode(self._h, _ptr(d_stream), int(stream_words), int(n),
+                                            _ptr(d_out), _stream_handle(stream)))
+
+    def sync_status(self, stream=None):
+        """Returns (status, detail) of the first device error since the last call."""
+        d = ctypes.c_uint32()
+        rc = lib().gc_sync_status(self._h, _stream_handle(stream), ctypes.byref(d))
+        return rc, d.value
+
+    def check(self, stream=None):
+        rc, d = self.sync_status(stream)
+        _check("gc_sync_status", rc, d)
+
+    def close(self):
+        if self._h:
+            lib().gc_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """gc_plan_create / gc_decode_batch / gc_decode_each / gc_plan_destroy."""
+
+    def __init__(self, ctx: Context, descs, headers, d_streams=None, d_out=None, tile_ints=0,
+                 blocks_per_cu=0, use_graph=False, autotune=False):
+        self.ctx = ctx
+        nl = len(descs)
+        arr = (ListDesc * max(nl, 1))()
+        for i, d in enumerate(descs):
+            arr[i] = d
+        hdr = np.ascontiguousarray(headers, dtype=np.uint32).reshape(-1)
+        opts = PlanOpts(int(tile_ints), int(blocks_per_cu), int(bool(use_graph)), int(bool(autotune)))
+        self._h = ctypes.c_void_p()
+        rc = lib().gc_plan_create(ctx._h, arr, nl, _u32(hdr), ctypes.byref(opts),
+                                  _ptr(d_streams) if d_streams is not None else None,
+                                  _ptr(d_out) if d_out is not None else None, ctypes.byref(self._h))
+        _check("gc_plan_create", rc)
+
+    def decode_batch(self, d_streams, d_out, stream=None):
+        _check("gc_decode_batch", lib().gc_decode_batch(self._h, _ptr(d_streams), _ptr(d_out),
+                                                        _stream_handle(stream)))
+
+    def decode_each(self, d_streams, d_out, stream=None):
+        _check("gc_decode_each", lib().gc_decode_each(self._h, _ptr(d_streams), _ptr(d_out),
+                                                      _stream_handle(stream)))
+
+    def config(self):
+        t, b, g = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check("gc_plan_config", lib().gc_plan_config(self._h, ctypes.byref(t), ctypes.byref(b),
+                                                      ctypes.byref(g)))
+        return dict(tile_ints=t.value, blocks_per_cu=b.value, grid_blocks=g.value)
+
+    def close(self):
+        if self._h:
+            lib().gc_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_layout(streams_flat, stream_offs, lengths):
+    """List descriptors and headers for streams concatenated in `streams_flat`
+    (offsets from encode_lists) decoding into one output of sum(lengths)."""
+    lengths = np.asarray(lengths, dtype=np.int64)
+    out_offs = np.zeros(lengths.size + 1, np.int64)
+    np.cumsum(lengths, out=out_offs[1:])
+    so = np.asarray(stream_offs, dtype=np.int64)
+    descs = [ListDesc(int(so[i]), int(so[i + 1] - so[i]), int(out_offs[i]), int(lengths[i]), 0)
+             for i in range(lengths.size)]
+    idx = so[:-1, None] + np.arange(4)[None, :]
+    headers = streams_flat[idx.reshape(-1)].reshape(-1, 4) if lengths.size else np.zeros((0, 4), np.uint32)
+    return descs, np.ascontiguousarray(headers, dtype=np.uint32), out_offs
+
+
+def to_device(a_u32, device="cuda"):
+    """numpy uint32 -> torch int32 device tensor with the same bits."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a_u32, dtype=np.uint32).view(np.int32)).to(device)
+
+
+def to_host(t):
+    return t.cpu().numpy().view(np.uint32)

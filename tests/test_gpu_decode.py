@@ -1,0 +1,266 @@
+"""GPU parity: libgc's HIP decode path (through the C ABI) against the CPU
+oracle, element by element and bit-exact.  Streams are written by the oracle;
+outputs are compared with the oracle's decode of the same stream and with the
+original list."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1502_01916_amd import gc, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_cuda):
+    c = gc.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_decode(torch, ctx, stream, n):
+    d_s = gc.to_device(stream)
+    d_o = torch.full((max(n, 1) + 64,), -1, dtype=torch.int32, device="cuda")
+    ctx.decode(d_s, stream.size, n, d_o)
+    rc, detail = ctx.sync_status()
+    out = gc.to_host(d_o)
+    assert rc == gc.OK, "device status %d detail %d" % (rc, detail)
+    assert np.all(out[max(n, 1):] == 0xFFFFFFFF), "write past the end of the output"
+    return out[:n]
+
+
+VARIANTS = [
+    ("gsim", O.SIMPLE, {}), ("gsc1cu", O.SCHEME, dict(cg=1, ld=O.LD_CU)),
+    ("gsc2cu", O.SCHEME, dict(cg=2, ld=O.LD_CU)), ("gsc4cu", O.SCHEME, dict(cg=4, ld=O.LD_CU)),
+    ("gsc8cu", O.SCHEME, dict(cg=8, ld=O.LD_CU)), ("gsc4iu", O.SCHEME, dict(cg=4, ld=O.LD_IU)),
+    ("gsc8iu", O.SCHEME, dict(cg=8, ld=O.LD_IU)), ("gsc1b", O.SCHEME, dict(cg=1, ld=O.LD_BINARY)),
+    ("gsc2b", O.SCHEME, dict(cg=2, ld=O.LD_BINARY)), ("gsc4b", O.SCHEME, dict(cg=4, ld=O.LD_BINARY)),
+    ("gsc8b", O.SCHEME, dict(cg=8, ld=O.LD_BINARY)), ("afor", O.AFOR, {}),
+    ("pfd", O.PFD, {}), ("pfdbitmap", O.PFD, dict(pfd_pos=O.PFD_BITMAP)),
+    ("bp128", O.PFD, dict(zeta=(1, 32))),
+]
+
+LENGTHS = [1, 3, 4, 5, 127, 128, 129, 4095, 4096, 4097, 3 * 4096 + 17, 70001]
+
+
+def gen_inputs(rng, n):
+    yield "docids", np.sort(rng.choice(1 << 27, n, replace=False)).astype(np.uint32), True
+    yield "widths", (rng.integers(0, 1 << 32, n, dtype=np.uint64)
+                     >> rng.integers(0, 33, n).astype(np.uint64)).astype(np.uint32), False
+    x = rng.geometric(0.3, n).astype(np.uint32)
+    x[rng.integers(0, n, max(1, n // 40))] = rng.integers(1 << 9, 1 << 31, max(1, n // 40)).astype(np.uint32)
+    yield "spiky", x, False
+
+
+@pytest.mark.parametrize("k", [4, 8, 64])
+@pytest.mark.parametrize("vi", range(len(VARIANTS)))
+def test_single_list_parity(torch_cuda, ctx, vi, k):
+    name, codec, kw = VARIANTS[vi]
+    rng = np.random.default_rng(1000 + 17 * vi + k)
+    for n in LENGTHS:
+        for kind, x, delta in gen_inputs(rng, n):
+            say("case", name, "k", k, "n", n, kind)
+            p = O.params(codec, k=k, delta=delta, cg=kw.get("cg", 1), ld=kw.get("ld", O.LD_CU),
+                         pfd_pos=kw.get("pfd_pos", 0), zeta=kw.get("zeta", (1, 10)))
+            s = O.encode(x, p)
+            ref = O.decode(s)
+            got = gpu_decode(torch_cuda, ctx, s, n)
+            if not np.array_equal(got, ref):
+                bad = np.nonzero(got != ref)[0]
+                pytest.fail("%s k=%d n=%d %s: %d mismatches, first at %d: got %d want %d"
+                            % (name, k, n, kind, bad.size, bad[0], got[bad[0]], ref[bad[0]]))
+            assert np.array_equal(ref, x)
+
+
+def test_degenerate_lists(torch_cuda, ctx):
+    for name, codec, kw in VARIANTS:
+        for x in (np.zeros(9000, np.uint32), np.full(9000, 0xFFFFFFFF, np.uint32),
+                  np.full(8193, 1, np.uint32)):
+            say("degenerate", name, x[0], x.size)
+            p = O.params(codec, cg=kw.get("cg", 1), ld=kw.get("ld", O.LD_CU),
+                         pfd_pos=kw.get("pfd_pos", 0), zeta=kw.get("zeta", (1, 10)))
+            s = O.encode(x, p)
+            assert np.array_equal(gpu_decode(torch_cuda, ctx, s, x.size), x)
+        # docIDs that wrap past 2^32 (gaps near 2^31)
+        g = np.full(5000, (1 << 31) - 1, np.uint32)
+        d = O.prefix_sum(g)
+        s = O.encode(d, O.params(codec, delta=True, cg=kw.get("cg", 1), ld=kw.get("ld", O.LD_CU),
+                                 pfd_pos=kw.get("pfd_pos", 0), zeta=kw.get("zeta", (1, 10))))
+        assert np.array_equal(gpu_decode(torch_cuda, ctx, s, d.size), d)
+
+
+def test_cfg1_group_simple(torch_cuda, ctx):
+    d = synth.cfg1()
+    s = O.encode(d, O.params(O.SIMPLE, delta=True))
+    say("cfg1", d.size, s.size)
+    got = gpu_decode(torch_cuda, ctx, s, d.size)
+    assert np.array_equal(got, O.decode(s))
+    assert np.array_equal(got, d)
+
+
+def make_batch(rng, nlists, kmix=(4,), maxlen=40000):
+    lengths = np.clip(np.round(np.exp(rng.normal(np.log(800), 1.6, nlists))), 0, maxlen).astype(np.int64)
+    streams, lists, plist = [], [], []
+    for i, L in enumerate(lengths):
+        name, codec, kw = VARIANTS[i % len(VARIANTS)]
+        k = kmix[i % len(kmix)]
+        delta = (i // len(VARIANTS)) % 2 == 0
+        x = (np.sort(rng.choice(1 << 28, int(L), replace=False)).astype(np.uint32) if delta
+             else rng.geometric(0.2, int(L)).astype(np.uint32))
+        p = O.params(codec, k=k, delta=delta, cg=kw.get("cg", 1), ld=kw.get("ld", O.LD_CU),
+                     pfd_pos=kw.get("pfd_pos", 0), zeta=kw.get("zeta", (1, 10)))
+        streams.append(O.encode(x, p))
+        lists.append(x)
+    offs = np.concatenate([[0], np.cumsum([s.size for s in streams])]).astype(np.int64)
+    flat = np.concatenate(streams) if streams else np.zeros(0, np.uint32)
+    return flat, offs, lengths, lists
+
+
+@pytest.mark.parametrize("tile", [2048, 4096, 8192])
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_parity(torch_cuda, ctx, tile, graph):
+    torch = torch_cuda
+    rng = np.random.default_rng(50 + tile + int(graph))
+    flat, offs, lengths, lists = make_batch(rng, 240, kmix=(4, 4, 8, 64))
+    descs, headers, out_offs = gc.batch_layout(flat, offs, lengths)
+    d_s = gc.to_device(flat)
+    total = int(out_offs[-1])
+    d_o = torch.full((total + 64,), -1, dtype=torch.int32, device="cuda")
+    say("batch tile", tile, "graph", graph, "lists", len(descs), "ints", total)
+    plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=tile, use_graph=graph)
+    want = np.concatenate(lists)
+    for rep in range(3):
+        d_o.fill_(-1)
+        plan.decode_batch(d_s, d_o)
+        rc, det = ctx.sync_status()
+        assert rc == gc.OK, det
+        got = gc.to_host(d_o)
+        assert np.all(got[total:] == 0xFFFFFFFF)
+        assert np.array_equal(got[:total], want), "replay %d" % rep
+        torch.cuda.synchronize()
+        _ = (d_o[:16].sum() + 1).item()     # unrelated eager work between replays
+    d_o.fill_(-1)
+    plan.decode_each(d_s, d_o)
+    rc, det = ctx.sync_status()
+    assert rc == gc.OK, det
+    assert np.array_equal(gc.to_host(d_o)[:total], want)
+    plan.close()
+
+
+def test_autotuned_plan(torch_cuda, ctx, tmp_path, monkeypatch):
+    torch = torch_cuda
+    monkeypatch.setenv("GC_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    rng = np.random.default_rng(77)
+    flat, offs, lengths, lists = make_batch(rng, 120)
+    descs, headers, out_offs = gc.batch_layout(flat, offs, lengths)
+    d_s = gc.to_device(flat)
+    d_o = torch.zeros(int(out_offs[-1]) + 4, dtype=torch.int32, device="cuda")
+    say("autotune")
+    plan = gc.Plan(ctx, descs, headers, d_s, d_o, autotune=True, use_graph=True)
+    cfg = plan.config()
+    assert cfg["tile_ints"] in (2048, 4096, 8192) and cfg["blocks_per_cu"] >= 1
+    plan.decode_batch(d_s, d_o)
+    assert ctx.sync_status()[0] == gc.OK
+    assert np.array_equal(gc.to_host(d_o)[:int(out_offs[-1])], np.concatenate(lists))
+    assert (tmp_path / "tune.json").exists()
+    plan2 = gc.Plan(ctx, descs, headers, d_s, d_o, autotune=True)   # served from the cache
+    assert plan2.config()["tile_ints"] == cfg["tile_ints"]
+
+
+def test_corrupt_streams_latch_status(torch_cuda, ctx):
+    torch = torch_cuda
+    rng = np.random.default_rng(9)
+    d = np.sort(rng.choice(1 << 26, 20000, replace=False)).astype(np.uint32)
+    cases = []
+    s = O.encode(d, O.params(O.SIMPLE, delta=True))
+    bad = s.copy()
+    bad[4 + 3] = 0xCCCCCCCC                          # selectors 12
+    cases.append(("gsim selector", bad))
+    s = O.encode(d, O.params(O.AFOR, delta=True))
+    bad = s.copy()
+    bad[4 + 1] |= 0xC0C0C0C0                         # frame class 3
+    cases.append(("afor class", bad))
+    s = O.encode(d, O.params(O.PFD, delta=True))
+    bad = s.copy()
+    bad[4 + 2] = (int(bad[4 + 2]) & ~63) | 45        # b = 45
+    cases.append(("pfd width", bad))
+    s = O.encode(d, O.params(O.SCHEME, cg=1, ld=O.LD_CU, delta=True))
+    bad = s.copy()
+    bad[4 + 5] = 0xFFFFFFFF
+    bad[4 + 6] = 0xFFFFFFFF                          # a code longer than 32 units
+    cases.append(("gsc unary", bad))
+    for name, b in cases:
+        say("corrupt", name)
+        d_s = gc.to_device(b)
+        d_o = torch.full((d.size + 64,), -1, dtype=torch.int32, device="cuda")
+        ctx.decode(d_s, b.size, d.size, d_o)
+        rc, detail = ctx.sync_status()
+        assert rc == gc.ECORRUPT, name
+        assert np.all(gc.to_host(d_o)[d.size:] == 0xFFFFFFFF)
+    # the context keeps working after an error
+    s = O.encode(d, O.params(O.SIMPLE, delta=True))
+    assert np.array_equal(gpu_decode(torch, ctx, s, d.size), d)
+
+
+def test_host_rejects_bad_headers(torch_cuda, ctx):
+    d = np.arange(1000, dtype=np.uint32)
+    s = O.encode(d, O.params(O.SIMPLE))
+    descs, headers, _ = gc.batch_layout(s, np.array([0, s.size]), np.array([d.size]))
+    headers = headers.copy()
+    headers[0, 0] |= 1 << 30
+    with pytest.raises(gc.GcError) as e:
+        gc.Plan(ctx, descs, headers)
+    assert e.value.code == gc.ECORRUPT
+    descs[0].stream_words = 3
+    with pytest.raises(gc.GcError):
+        gc.Plan(ctx, descs, headers)
+
+
+def test_cfg2_full_size_batch(torch_cuda, ctx):
+    """The benchmark workload at full size, in the launch configuration the
+    benchmark times: every cfg2 list (docIDs and TFs) through one persistent
+    hipGraph launch per codec; outputs equal the generator's lists (the
+    lossless-codec property at any size) and, on sampled lists, the oracle."""
+    torch = torch_cuda
+    lengths, docs, tfs = synth.cfg2()
+    lo = np.concatenate([[0], np.cumsum(lengths)])
+    sample = np.random.default_rng(0).choice(lengths.size, 12, replace=False)
+    codecs = [("gsim", gc.SIMPLE, {}), ("gsc1cu", gc.SCHEME, dict(cg=1, ld=gc.LD_CU)),
+              ("gsc8iu", gc.SCHEME, dict(cg=8, ld=gc.LD_IU)), ("afor", gc.AFOR, {}),
+              ("pfd", gc.PFD, {})]
+    for name, codec, kw in codecs:
+        for what, flat, delta in (("docids", docs, True), ("tf", tfs, False)):
+            say("cfg2", name, what)
+            p = gc.params(delta=delta, **kw)
+            s, offs = gc.encode_lists(flat, lengths, codec, p)
+            descs, headers, out_offs = gc.batch_layout(s, offs, lengths)
+            d_s = gc.to_device(s)
+            d_o = torch.empty(int(out_offs[-1]), dtype=torch.int32, device="cuda")
+            plan = gc.Plan(ctx, descs, headers, d_s, d_o, use_graph=True)
+            plan.decode_batch(d_s, d_o)
+            rc, det = ctx.sync_status()
+            assert rc == gc.OK, det
+            got = gc.to_host(d_o)
+            assert np.array_equal(got, flat), (name, what)
+            op = O.params(codec, delta=delta, cg=kw.get("cg", 1), ld=kw.get("ld", O.LD_CU))
+            for i in sample:
+                seg = s[int(offs[i]):int(offs[i + 1])]
+                assert np.array_equal(seg, O.encode(flat[lo[i]:lo[i + 1]], op))
+                assert np.array_equal(got[lo[i]:lo[i + 1]], O.decode(seg))
+            plan.close()
+            del d_s, d_o
