@@ -1,0 +1,288 @@
+#!/usr/bin/env python3
+"""Throughput of batched Group-codec decoding + d-gap prefix sum on one MI355X.
+
+Workload: 10,000 synthetic posting lists (Zipf lengths clipped to
+[128, 2^22], 2^26 docIDs, universe 2^25, 70% sparse / 30% clustered d-gaps)
+and their TF lists, each coded with Group-Simple, Group-Scheme 1-CU,
+Group-Scheme 8-IU, Group-AFOR and Group-PFD (32-tuple blocks, zeta = 1/10) in
+the paper's 4-way layout: 100,000 streams, about 6.7e8 integers.  One step
+decodes every stream (docID lists prefix-summed) with one persistent launch
+sequence replayed from a hipGraph.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gints/s decoded+prefix-summed, % HBM peak; batched vs per-list on 1 MI355X"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_decode_cfg2.txt")
+DECODE_SRC = os.path.join(ROOT, "paper_1502_01916_amd", "csrc", "decode.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def variants(gc):
+    return [("group-simple", gc.SIMPLE, {}),
+            ("group-scheme-1cu", gc.SCHEME, dict(cg=1, ld=gc.LD_CU)),
+            ("group-scheme-8iu", gc.SCHEME, dict(cg=8, ld=gc.LD_IU)),
+            ("group-afor", gc.AFOR, {}),
+            ("group-pfd", gc.PFD, dict(zeta=(1, 10)))]
+
+
+def build_workload(gc, synth):
+    t = time.time()
+    lengths, docs, tfs = synth.cfg2()
+    log("cfg2 generated: %d lists, %d docIDs (%.1fs)" % (lengths.size, docs.size, time.time() - t))
+    parts = []
+    for name, codec, kw in variants(gc):
+        for kind, flat, delta in (("docids", docs, True), ("tf", tfs, False)):
+            t = time.time()
+            s, offs = gc.encode_lists(flat, lengths, codec, gc.params(delta=delta, **kw))
+            parts.append(dict(name=name, kind=kind, codec=codec, streams=s, offs=offs,
+                              lengths=lengths, flat=flat))
+            log("encoded %-18s %-6s %.2f bits/int (%.1fs)" % (name, kind, 32.0 * s.size / flat.size,
+                                                              time.time() - t))
+    return parts
+
+
+def concat(parts):
+    streams = np.concatenate([p["streams"] for p in parts])
+    offs, base = [np.zeros(1, np.int64)], 0
+    for p in parts:
+        o = p["offs"].astype(np.int64)
+        offs.append(o[1:] + base)
+        base += int(o[-1])
+    lengths = np.concatenate([p["lengths"] for p in parts])
+    return streams, np.concatenate(offs), lengths
+
+
+def read_traffic(units):
+    """HBM bytes per decode launch from the committed rocprofv3 counter
+    summary, if it was taken on the current decode kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    with open(DECODE_SRC, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if kv.get("decode_source_sha256") != sha or kv.get("workload_units") != str(units):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(parts, seconds):
+    """The plain C oracle decoding (and prefix-summing) a random sample of the
+    same streams on one host core, for about `seconds` seconds."""
+    import oracle as O
+    rng = np.random.default_rng(123)
+    order = [(pi, li) for pi in range(len(parts)) for li in range(parts[pi]["lengths"].size)]
+    rng.shuffle(order)
+    done_ints = done_lists = 0
+    t0 = time.perf_counter()
+    for pi, li in order:
+        p = parts[pi]
+        s = p["streams"][int(p["offs"][li]):int(p["offs"][li + 1])]
+        out = O.decode(s)
+        done_ints += out.size
+        done_lists += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=done_ints / dt / 1e9, unit="Gints/s", cores=1, kind="oracle",
+                sample="%d lists (%d integers) drawn at random from the same 100,000 streams, each "
+                       "decoded and prefix-summed once by the single-threaded C oracle in %.1f s"
+                       % (done_lists, done_ints, dt))
+
+
+def timed(plan, d_s, d_o, steps, warmup, torch):
+    for _ in range(warmup):
+        plan.decode_batch(d_s, d_o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.decode_batch(d_s, d_o)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip per-list and per-codec runs")
+    ap.add_argument("--tile", type=int, default=0, help="force a tile size (0 = autotune)")
+    ap.add_argument("--bpc", type=int, default=0, help="force workgroups per CU (with --tile)")
+    ap.add_argument("--no-graph", action="store_true", help="launch kernels directly, no hipGraph")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the decode path is built and measured on a single "
+              "MI355X (lists shard across GPUs with no exchange); --gpus %d is not supported"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1502_01916_amd import gc, synth
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    gc.lib()
+
+    parts = build_workload(gc, synth)
+    streams, offs, lengths = concat(parts)
+    descs, headers, out_offs = gc.batch_layout(streams, offs, lengths, align=4)
+    total = int(lengths.sum())
+    out_len = int(out_offs[-1])
+    stream_bytes = 4 * int(streams.size)
+    ctx = gc.Context(0)
+    d_s = gc.to_device(streams)
+    d_o = torch.empty(out_len, dtype=torch.int32, device="cuda")
+    t = time.time()
+    plan = gc.Plan(ctx, descs, headers, d_s, d_o, use_graph=not args.no_graph, tile_ints=args.tile,
+                   blocks_per_cu=args.bpc, autotune=args.tile == 0,
+                   timing_slots=args.steps + args.warmup)
+    cfg = plan.config()
+    log("plan: %s (%.1fs)" % (cfg, time.time() - t))
+
+    elapsed = timed(plan, d_s, d_o, args.steps, args.warmup, torch)
+    loc_ms, dec_ms = plan.timings(args.steps)
+    rc, detail = ctx.sync_status()
+    if rc != gc.OK:
+        raise SystemExit("device reported %d (detail %d)" % (rc, detail))
+    got = gc.unpad(gc.to_host(d_o), out_offs, lengths)
+    want = np.concatenate([p["flat"] for p in parts])
+    verified = bool(np.array_equal(got, want))
+    del got, want
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = total / (elapsed / args.steps) / 1e9
+    alg_bytes = stream_bytes + 4 * total
+    dec_avg = float(np.mean(dec_ms))
+    achieved = alg_bytes / (dec_avg * 1e-3) / 1e9
+    log("step %.3f ms  %.1f Gints/s  decode kernel %.3f ms (locate %.3f ms)  %.0f GB/s  verified=%s"
+        % (ms_per_step, value, dec_avg, float(np.mean(loc_ms)), achieved, verified))
+    if not verified:
+        raise SystemExit("decoded output differs from the generated lists")
+    traffic = read_traffic(len(descs))
+
+    extra = {}
+    if not args.no_extra:
+        # one launch sequence per list, same kernels (the per-list baseline)
+        plan.decode_each(d_s, d_o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 2
+        for _ in range(reps):
+            plan.decode_each(d_s, d_o)
+        torch.cuda.synchronize()
+        per_list = total / ((time.perf_counter() - t0) / reps) / 1e9
+        extra["per_list"] = dict(value=round(per_list, 3), unit="Gints/s",
+                                 batched_speedup=round(value / per_list, 2))
+        log("per-list launches: %.2f Gints/s, batched speedup %.1fx" % (per_list, value / per_list))
+        per = {}
+        for i in range(0, len(parts), 2):
+            sub = parts[i:i + 2]
+            s2, o2, l2 = concat(sub)
+            de2, h2, oo2 = gc.batch_layout(s2, o2, l2, align=4)
+            ds2 = gc.to_device(s2)
+            do2 = torch.empty(int(oo2[-1]), dtype=torch.int32, device="cuda")
+            p2 = gc.Plan(ctx, de2, h2, ds2, do2, use_graph=True, tile_ints=cfg["tile_ints"],
+                         blocks_per_cu=cfg["blocks_per_cu"], timing_slots=args.steps)
+            el = timed(p2, ds2, do2, args.steps, 2, torch)
+            _, dm = p2.timings(args.steps)
+            n2 = int(l2.sum())
+            ab = 4 * int(s2.size) + 4 * n2
+            gbs = ab / (float(np.mean(dm)) * 1e-3) / 1e9
+            per[sub[0]["name"]] = dict(gints_s=round(n2 / (el / args.steps) / 1e9, 2),
+                                       bits_per_int_docids=round(32.0 * sub[0]["streams"].size / n2 * 2, 3),
+                                       bits_per_int_tf=round(32.0 * sub[1]["streams"].size / n2 * 2, 3),
+                                       decode_kernel_gbs=round(gbs, 1),
+                                       hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+            log("%-18s %s" % (sub[0]["name"], per[sub[0]["name"]]))
+            p2.close()
+            del ds2, do2
+        extra["per_codec"] = per
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(parts, args.cpu_seconds)
+        log("cpu oracle: %.4f Gints/s (%s)" % (cpu["value"], cpu["sample"]))
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "10,000 posting lists (Zipf lengths in [128, 2^22], 2^26 docIDs, universe "
+                        "2^25, 70% sparse / 30% clustered d-gaps) plus their TF lists (geometric "
+                        "p=0.4), each coded with Group-Simple, Group-Scheme 1-CU, Group-Scheme "
+                        "8-IU, Group-AFOR and Group-PFD (zeta 1/10), 4-way layout; all 100,000 "
+                        "streams decoded per step in one persistent hipGraph launch sequence, "
+                        "docID lists prefix-summed; seed 2",
+            "lists": len(descs),
+            "ints_per_step": total,
+            "stream_bytes": stream_bytes,
+            "bits_per_int": round(32.0 * streams.size / total, 3),
+            "tile_ints": cfg["tile_ints"],
+            "blocks_per_cu": cfg["blocks_per_cu"],
+            "verified_bit_exact": verified,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "gc_decode_kernel<%d>" % cfg["tile_ints"],
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "avg_kernel_ms": round(dec_avg, 4),
+            "avg_locate_kernel_ms": round(float(np.mean(loc_ms)), 4),
+        },
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    # plain copy of a known size, so counter runs of this command can be
+    # scaled against it
+    src = torch.empty(1 << 26, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    plan.close()
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

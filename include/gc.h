@@ -120,13 +120,15 @@ gc_status gc_ctx_create(int device, gc_ctx **ctx);
 gc_status gc_ctx_destroy(gc_ctx *ctx);
 
 /* Decodes one stream (device memory, stream_words words) into d_out[0..n),
- * prefix-summing when the header's delta bit is set.  n must equal the
- * header's n (the index dictionary knows list lengths, Section 2.1.1, so no
- * device-to-host read is needed).  Asynchronous on hip_stream.  Calls on one
- * context must not overlap in time (they share its scratch); use one
- * context per concurrent stream.  d_stream must be 16-byte aligned.        */
-gc_status gc_decode(gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words, size_t n,
-                    uint32_t *d_out, void *hip_stream);
+ * prefix-summing when the header's delta bit is set.  h_header is a host
+ * copy of the stream's first 4 words (the index dictionary keeps each list's
+ * length and codec, Section 2.1.1, so no device-to-host read is needed); n is
+ * h_header[1].  The kernels re-check the device copy against it.
+ * Asynchronous on hip_stream.  Calls on one context must not overlap in time
+ * (they share its scratch); use one context per concurrent stream.
+ * d_stream must be 16-byte aligned.  GC_ECORRUPT if h_header is malformed. */
+gc_status gc_decode(gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words,
+                    const uint32_t *h_header, uint32_t *d_out, void *hip_stream);
 
 /* One list of a batch: its stream at d_streams + stream_off_words (16-byte
  * aligned, stream_words long), its output at d_out + out_off (n words).    */
@@ -144,7 +146,10 @@ typedef struct {
     uint32_t blocks_per_cu;  /* persistent workgroups per CU: 0 = autotuned/default */
     uint32_t use_graph;      /* 1 = capture the launch sequence in a hipGraph       */
     uint32_t autotune;       /* 1 = time candidate configurations at creation       */
-    uint32_t reserved[4];
+    uint32_t timing_slots;   /* > 0: record HIP events around the locate and decode
+                                launches of each gc_decode_batch, in this many
+                                rotating slots (see gc_plan_timings)               */
+    uint32_t reserved[3];
 } gc_plan_opts;
 
 /* Builds a batched decode plan for nlists lists.  h_headers holds the first
@@ -168,6 +173,15 @@ gc_status gc_decode_batch(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_
  * per-list baseline the batch is compared with).                          */
 gc_status gc_decode_each(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_out,
                          void *hip_stream);
+
+/* Kernel durations of the last runs of a plan created with timing_slots > 0:
+ * synchronises the recorded HIP events and writes, oldest first, up to
+ * max_runs pairs (locate_ms[i], decode_ms[i]) -- the time between the events
+ * recorded on the launch stream before the locate kernel, between the two
+ * kernels, and after the decode kernel.  *nruns receives the count written.
+ * GC_EINVAL if the plan records no events.                                 */
+gc_status gc_plan_timings(gc_plan *plan, uint32_t max_runs, float *locate_ms, float *decode_ms,
+                          uint32_t *nruns);
 
 /* Reports the chosen configuration of a plan. */
 gc_status gc_plan_config(const gc_plan *plan, uint32_t *tile_ints, uint32_t *blocks_per_cu,

@@ -7,7 +7,8 @@ namespace gcdev {
 
 constexpr int kThreads = 256;          // threads per workgroup (4 wave64)
 constexpr int kWaves = kThreads / 64;
-constexpr int kChunkWords = kThreads;  // control words per locate work item
+constexpr int kChunkWords = kThreads * 4;  // control words per locate work item
+constexpr int kClasses = 5;                 // decode kernel classes (codec families)
 
 // One list of a launch.  For a batch these live in a device table; for a
 // single list the runtime passes one by value.
@@ -20,7 +21,7 @@ struct ListDesc {
     uint32_t tile_base;       // first entry of this list in the tile arrays
     uint32_t chunk_base;      // first entry in the locate arrays (ntiles > 1)
     uint32_t nchunks;         // locate work items (0 when ntiles <= 1)
-    uint32_t pad;
+    uint32_t cls_base;        // first entry of this list in its decode class queue
 };
 
 // Where tile m of a list starts, written by the locate pass.

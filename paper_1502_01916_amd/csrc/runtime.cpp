@@ -1,10 +1,10 @@
 // runtime.cpp -- host runtime of libgc: device contexts, single-list decode,
-// batched decode plans (work-item tables, persistent launches, hipGraph
-// capture) and the autotuner that picks the tile size and occupancy.
+// batched decode plans (work-item tables per codec class, persistent launches,
+// hipGraph capture with one parallel branch per class), per-run kernel timing
+// and the autotuner that picks the tile size and occupancy.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -19,9 +19,10 @@
 #include "gc_format.h"
 
 namespace gcdev {
+int codec_class(uint32_t w0);
 int launch_locate(const LocateArgs &a, uint32_t grid, hipStream_t s);
-int launch_decode(int tile, const DecodeArgs &a, uint32_t grid, hipStream_t s);
-int decode_occupancy(int tile, int *blocks_per_cu);
+int launch_decode(int tile, int cls, const DecodeArgs &a, uint32_t grid, hipStream_t s);
+int decode_occupancy(int tile, int cls, int *blocks_per_cu);
 int locate_occupancy(int *blocks_per_cu);
 }  // namespace gcdev
 
@@ -29,7 +30,7 @@ using namespace gcdev;
 
 namespace {
 
-constexpr int kDefaultTile = 4096;
+constexpr int kDefaultTile = 2048;
 constexpr int kTiles[3] = {2048, 4096, 8192};
 
 #define HIP_OK(x)                         \
@@ -76,8 +77,9 @@ void dev_free(T *&p) {
     p = nullptr;
 }
 
+// Look-back and queue state of one launch sequence.
 struct Scratch {
-    RunState *state = nullptr;          // [0] locate, [1] decode
+    RunState *state = nullptr;          // [0] locate, [1 + class] decode
     TileInfo *tiles = nullptr;
     unsigned long long *tflags = nullptr;
     uint32_t *cflags = nullptr;
@@ -85,10 +87,10 @@ struct Scratch {
     size_t tiles_cap = 0, chunks_cap = 0;
 
     gc_status init_state() {
-        gc_status rc = dev_alloc(&state, 2);
+        gc_status rc = dev_alloc(&state, 1 + kClasses);
         if (rc) return rc;
-        RunState h[2] = {{0, 0, 1, 0}, {0, 0, 1, 0}};
-        HIP_OK(hipMemcpy(state, h, sizeof(h), hipMemcpyHostToDevice));
+        std::vector<RunState> h(1 + kClasses, RunState{0, 0, 1, 0});
+        HIP_OK(hipMemcpy(state, h.data(), h.size() * sizeof(RunState), hipMemcpyHostToDevice));
         return GC_OK;
     }
     gc_status reserve(size_t ntiles, size_t nchunks) {
@@ -142,27 +144,33 @@ struct gc_plan {
     gc_ctx *ctx = nullptr;
     size_t nlists = 0;
     int tile = kDefaultTile;
-    uint32_t bpc = 0;                 // decode workgroups per CU
-    uint32_t grid_a = 0, grid_b = 0;
-    uint32_t total_a = 0, total_b = 0;
+    uint32_t bpc = 0;                          // decode workgroups per CU (0 = max)
+    uint32_t grid_a = 0, grid_b[kClasses] = {};
+    uint32_t total_a = 0, total_b[kClasses] = {};
     bool use_graph = false;
-    std::vector<ListDesc> h_lists;    // pointers relative to base (offsets)
+    std::vector<ListDesc> h_lists;             // pointers filled at upload
+    std::vector<int> cls;                      // codec class per list
     std::vector<uint64_t> stream_off, out_off;
-    std::vector<uint32_t> item_a, item_b;
+    std::vector<uint32_t> item_a, item_b[kClasses];
     ListDesc *d_lists = nullptr;
-    uint32_t *d_item_a = nullptr, *d_item_b = nullptr;
+    uint32_t *d_item_a = nullptr, *d_item_b[kClasses] = {};
     Scratch sc;
     const uint32_t *bound_streams = nullptr;
     uint32_t *bound_out = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipGraph_t graph_a = nullptr, graph_b = nullptr;    // timing: one graph per kernel group
+    hipGraphExec_t exec_a = nullptr, exec_b = nullptr;
+    std::vector<hipEvent_t> ev;                // 3 per timing slot
+    uint32_t slots = 0;
+    uint64_t runs = 0;
 };
 
 namespace {
 
-int occupancy_decode(int tile) {
+int occupancy_decode(int tile, int cls) {
     int b = 0;
-    if (decode_occupancy(tile, &b) != 0 || b < 1) b = 1;
+    if (decode_occupancy(tile, cls, &b) != 0 || b < 1) b = 1;
     return b;
 }
 
@@ -191,7 +199,7 @@ LocateArgs make_locate_args(const ListDesc *lists, const uint32_t *item_list, co
 }
 
 DecodeArgs make_decode_args(const ListDesc *lists, const uint32_t *item_list, const ListDesc &single,
-                            uint32_t total, Scratch &sc, Status *st) {
+                            uint32_t total, int cls, Scratch &sc, Status *st) {
     DecodeArgs a;
     std::memset(&a, 0, sizeof(a));
     a.lists = lists;
@@ -200,16 +208,22 @@ DecodeArgs make_decode_args(const ListDesc *lists, const uint32_t *item_list, co
     a.total_items = total;
     a.tiles = sc.tiles;
     a.flags = sc.tflags;
-    a.state = sc.state + 1;
+    a.state = sc.state + 1 + cls;
     a.loc_state = sc.state;
     a.status = st;
     return a;
 }
 
+uint32_t list_chunks(const HeaderFields &h, uint32_t n, uint32_t C, uint32_t D) {
+    const uint32_t T = (n + (uint32_t)h.k - 1u) >> h.lk;
+    const uint32_t nw = locate_words_host(h, T, C, D);
+    return std::max(1u, (nw + kChunkWords - 1u) / kChunkWords);
+}
+
 // Builds the per-list work tables of a plan for one tile size.
 void build_tables(gc_plan *p, const uint32_t *h_headers) {
     p->item_a.clear();
-    p->item_b.clear();
+    for (auto &v : p->item_b) v.clear();
     uint32_t tb = 0, cb = 0;
     for (size_t i = 0; i < p->nlists; i++) {
         ListDesc &L = p->h_lists[i];
@@ -220,27 +234,30 @@ void build_tables(gc_plan *p, const uint32_t *h_headers) {
         if (L.ntiles > 1) {
             HeaderFields h;
             header_fields(h_headers[4 * i], h);
-            const uint32_t T = (L.n + (uint32_t)h.k - 1u) >> h.lk;
-            const uint32_t nw = locate_words_host(h, T, h_headers[4 * i + 2], h_headers[4 * i + 3]);
-            L.nchunks = std::max(1u, (nw + kChunkWords - 1u) / kChunkWords);
+            L.nchunks = list_chunks(h, L.n, h_headers[4 * i + 2], h_headers[4 * i + 3]);
         }
+        L.cls_base = (uint32_t)p->item_b[p->cls[i]].size();
         for (uint32_t c = 0; c < L.nchunks; c++) p->item_a.push_back((uint32_t)i);
-        for (uint32_t t = 0; t < L.ntiles; t++) p->item_b.push_back((uint32_t)i);
+        for (uint32_t t = 0; t < L.ntiles; t++) p->item_b[p->cls[i]].push_back((uint32_t)i);
         tb += L.ntiles;
         cb += L.nchunks;
     }
     p->total_a = (uint32_t)p->item_a.size();
-    p->total_b = (uint32_t)p->item_b.size();
+    for (int c = 0; c < kClasses; c++) p->total_b[c] = (uint32_t)p->item_b[c].size();
+}
+
+void plan_free_graphs(gc_plan *p) {
+    for (hipGraphExec_t *e : {&p->exec, &p->exec_a, &p->exec_b})
+        if (*e) (void)hipGraphExecDestroy(*e), *e = nullptr;
+    for (hipGraph_t *g : {&p->graph, &p->graph_a, &p->graph_b})
+        if (*g) (void)hipGraphDestroy(*g), *g = nullptr;
 }
 
 void plan_free_device(gc_plan *p) {
-    if (p->exec) (void)hipGraphExecDestroy(p->exec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
-    p->exec = nullptr;
-    p->graph = nullptr;
+    plan_free_graphs(p);
     dev_free(p->d_lists);
     dev_free(p->d_item_a);
-    dev_free(p->d_item_b);
+    for (auto &d : p->d_item_b) dev_free(d);
     p->sc.release();
 }
 
@@ -262,65 +279,115 @@ gc_status plan_materialize(gc_plan *p, const uint32_t *h_headers) {
     build_tables(p, h_headers);
     gc_status rc = dev_alloc(&p->d_lists, p->nlists);
     if (!rc) rc = dev_alloc(&p->d_item_a, p->total_a);
-    if (!rc) rc = dev_alloc(&p->d_item_b, p->total_b);
+    for (int c = 0; c < kClasses && !rc; c++) rc = dev_alloc(&p->d_item_b[c], p->total_b[c]);
     if (!rc) rc = p->sc.init_state();
-    if (!rc) rc = p->sc.reserve(p->total_b, p->total_a);
+    uint32_t tiles = 0;
+    for (int c = 0; c < kClasses; c++) tiles += p->total_b[c];
+    if (!rc) rc = p->sc.reserve(tiles, p->total_a);
     if (rc) return rc;
     if (p->total_a)
         HIP_OK(hipMemcpy(p->d_item_a, p->item_a.data(), p->total_a * 4, hipMemcpyHostToDevice));
-    if (p->total_b)
-        HIP_OK(hipMemcpy(p->d_item_b, p->item_b.data(), p->total_b * 4, hipMemcpyHostToDevice));
     const uint32_t cus = (uint32_t)p->ctx->num_cus;
-    const uint32_t occ_b = (uint32_t)occupancy_decode(p->tile);
-    const uint32_t bpc = p->bpc ? std::min(p->bpc, occ_b) : occ_b;
-    p->grid_b = std::max(1u, std::min(p->total_b, bpc * cus));
+    for (int c = 0; c < kClasses; c++) {
+        if (p->total_b[c])
+            HIP_OK(hipMemcpy(p->d_item_b[c], p->item_b[c].data(), p->total_b[c] * 4, hipMemcpyHostToDevice));
+        const uint32_t occ = (uint32_t)occupancy_decode(p->tile, c);
+        const uint32_t bpc = p->bpc ? std::min(p->bpc, occ) : occ;
+        p->grid_b[c] = std::max(1u, std::min(p->total_b[c], bpc * cus));
+    }
     p->grid_a = std::max(1u, std::min(p->total_a, (uint32_t)occupancy_locate() * cus));
     return GC_OK;
 }
 
-gc_status plan_launch(gc_plan *p, hipStream_t s) {
+// Launches the locate kernel (which & 1) and the decode kernels (which & 2)
+// on stream s; with `fork` streams the decode classes run as parallel
+// branches that s waits for.
+gc_status plan_launch(gc_plan *p, hipStream_t s, int which, hipStream_t *fork = nullptr,
+                      hipEvent_t *fev = nullptr) {
     ListDesc none;
     std::memset(&none, 0, sizeof(none));
-    if (p->total_a) {
+    if (p->total_a && (which & 1)) {
         LocateArgs a = make_locate_args(p->d_lists, p->d_item_a, none, p->total_a, p->tile, p->sc,
                                         p->ctx->status);
         if (launch_locate(a, p->grid_a, s)) return GC_EDEVICE;
     }
-    if (p->total_b) {
-        DecodeArgs d = make_decode_args(p->d_lists, p->d_item_b, none, p->total_b, p->sc, p->ctx->status);
-        if (launch_decode(p->tile, d, p->grid_b, s)) return GC_EDEVICE;
+    if (!(which & 2)) return GC_OK;
+    int nact = 0;
+    for (int c = 0; c < kClasses; c++) nact += p->total_b[c] ? 1 : 0;
+    const bool par = fork && nact > 1;
+    if (par) HIP_OK(hipEventRecord(fev[kClasses], s));
+    for (int c = 0; c < kClasses; c++) {
+        if (!p->total_b[c]) continue;
+        hipStream_t cs = s;
+        if (par) {
+            cs = fork[c];
+            HIP_OK(hipStreamWaitEvent(cs, fev[kClasses], 0));
+        }
+        DecodeArgs d = make_decode_args(p->d_lists, p->d_item_b[c], none, p->total_b[c], c, p->sc,
+                                        p->ctx->status);
+        if (launch_decode(p->tile, c, d, p->grid_b[c], cs)) return GC_EDEVICE;
+        if (par) {
+            HIP_OK(hipEventRecord(fev[c], cs));
+            HIP_OK(hipStreamWaitEvent(s, fev[c], 0));
+        }
     }
     return GC_OK;
 }
 
-gc_status plan_capture(gc_plan *p) {
-    hipStream_t s;
+gc_status capture_one(gc_plan *p, int which, hipGraph_t *graph, hipGraphExec_t *exec) {
+    hipStream_t s, fork[kClasses];
+    hipEvent_t fev[kClasses + 1];
     HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    for (int c = 0; c < kClasses; c++) HIP_OK(hipStreamCreateWithFlags(&fork[c], hipStreamNonBlocking));
+    for (int c = 0; c <= kClasses; c++) HIP_OK(hipEventCreateWithFlags(&fev[c], hipEventDisableTiming));
     gc_status rc = GC_OK;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         rc = GC_EDEVICE;
     } else {
-        rc = plan_launch(p, s);
+        rc = plan_launch(p, s, which, fork, fev);
         hipGraph_t g = nullptr;
         if (hipStreamEndCapture(s, &g) != hipSuccess || rc) {
             rc = GC_EDEVICE;
             if (g) (void)hipGraphDestroy(g);
         } else {
-            p->graph = g;
-            if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) rc = GC_EDEVICE;
+            *graph = g;
+            if (hipGraphInstantiate(exec, g, nullptr, nullptr, 0) != hipSuccess) rc = GC_EDEVICE;
         }
     }
+    for (int c = 0; c <= kClasses; c++) (void)hipEventDestroy(fev[c]);
+    for (int c = 0; c < kClasses; c++) (void)hipStreamDestroy(fork[c]);
     (void)hipStreamDestroy(s);
     (void)hipGetLastError();
     return rc;
 }
 
+gc_status plan_capture(gc_plan *p) {
+    plan_free_graphs(p);
+    if (p->slots) {
+        gc_status rc = capture_one(p, 1, &p->graph_a, &p->exec_a);
+        return rc ? rc : capture_one(p, 2, &p->graph_b, &p->exec_b);
+    }
+    return capture_one(p, 3, &p->graph, &p->exec);
+}
+
 gc_status plan_run(gc_plan *p, hipStream_t s) {
+    if (p->slots) {
+        const size_t k = (size_t)(p->runs % p->slots) * 3;
+        p->runs++;
+        HIP_OK(hipEventRecord(p->ev[k], s));
+        if (p->use_graph && p->exec_a) HIP_OK(hipGraphLaunch(p->exec_a, s));
+        else if (gc_status rc = plan_launch(p, s, 1)) return rc;
+        HIP_OK(hipEventRecord(p->ev[k + 1], s));
+        if (p->use_graph && p->exec_b) HIP_OK(hipGraphLaunch(p->exec_b, s));
+        else if (gc_status rc = plan_launch(p, s, 2)) return rc;
+        HIP_OK(hipEventRecord(p->ev[k + 2], s));
+        return GC_OK;
+    }
     if (p->use_graph && p->exec) {
         HIP_OK(hipGraphLaunch(p->exec, s));
         return GC_OK;
     }
-    return plan_launch(p, s);
+    return plan_launch(p, s, 3);
 }
 
 // ---- autotune cache: one JSON object {key: [tile, bpc], ...} -------------
@@ -361,7 +428,6 @@ void cache_store(const std::string &key, int tile, uint32_t bpc) {
         }
     }
     std::vector<std::string> entries;
-    // keep the other keys: entries look like "key": [a, b]
     size_t pos = 0;
     while ((pos = s.find('"', pos)) != std::string::npos) {
         const size_t e = s.find('"', pos + 1);
@@ -382,13 +448,12 @@ void cache_store(const std::string &key, int tile, uint32_t bpc) {
 }
 
 std::string plan_key(const gc_plan *p, const uint32_t *h_headers) {
-    // codec mix and size bucket of the batch
-    uint64_t total = 0, per_codec[4] = {0, 0, 0, 0};
+    uint64_t total = 0, per_cls[kClasses] = {};
     int lk = 2;
     for (size_t i = 0; i < p->nlists; i++) {
         HeaderFields h;
         header_fields(h_headers[4 * i], h);
-        per_codec[h.codec & 3] += p->h_lists[i].n;
+        per_cls[p->cls[i]] += p->h_lists[i].n;
         total += p->h_lists[i].n;
         lk = std::max(lk, h.lk);
     }
@@ -397,13 +462,11 @@ std::string plan_key(const gc_plan *p, const uint32_t *h_headers) {
     const uint64_t mean = p->nlists ? total / p->nlists : 0;
     int lm = 0;
     while ((1ull << lm) < mean) lm++;
-    char buf[160];
-    std::snprintf(buf, sizeof(buf), "gfx950:k%d:n2^%d:mean2^%d:mix%llu-%llu-%llu-%llu", 1 << lk, lg, lm,
-                  (unsigned long long)(total ? per_codec[0] * 8 / total : 0),
-                  (unsigned long long)(total ? per_codec[1] * 8 / total : 0),
-                  (unsigned long long)(total ? per_codec[2] * 8 / total : 0),
-                  (unsigned long long)(total ? per_codec[3] * 8 / total : 0));
-    return buf;
+    std::string key = "gfx950:k" + std::to_string(1 << lk) + ":n2^" + std::to_string(lg) + ":mean2^" +
+                      std::to_string(lm) + ":mix";
+    for (int c = 0; c < kClasses; c++)
+        key += (c ? "-" : "") + std::to_string(total ? per_cls[c] * 8 / total : 0);
+    return key;
 }
 
 gc_status autotune(gc_plan *p, const uint32_t *h_headers, const uint32_t *d_streams, uint32_t *d_out) {
@@ -421,17 +484,18 @@ gc_status autotune(gc_plan *p, const uint32_t *h_headers, const uint32_t *d_stre
     float best = 1e30f;
     gc_status rc = GC_OK;
     for (int tile : kTiles) {
-        p->tile = tile;
-        const int occ = occupancy_decode(tile);
-        for (int bpc = 1; bpc <= occ && !rc; bpc++) {
+        int occ = 1;
+        for (int c = 0; c < kClasses; c++) occ = std::max(occ, occupancy_decode(tile, c));
+        for (int bpc = occ; bpc >= 1 && !rc; bpc = bpc > 2 ? bpc - 2 : bpc - 1) {
+            p->tile = tile;
             p->bpc = (uint32_t)bpc;
             rc = plan_materialize(p, h_headers);
             if (!rc) rc = plan_upload(p, d_streams, d_out);
             if (rc) break;
-            for (int w = 0; w < 2 && !rc; w++) rc = plan_launch(p, nullptr);
+            for (int w = 0; w < 2 && !rc; w++) rc = plan_launch(p, nullptr, 3);
             if (rc) break;
             HIP_OK(hipEventRecord(e0, nullptr));
-            for (int r = 0; r < 5 && !rc; r++) rc = plan_launch(p, nullptr);
+            for (int r = 0; r < 5 && !rc; r++) rc = plan_launch(p, nullptr, 3);
             HIP_OK(hipEventRecord(e1, nullptr));
             HIP_OK(hipEventSynchronize(e1));
             float ms = 0;
@@ -458,6 +522,8 @@ gc_status validate_header(const uint32_t *hd, uint64_t n, uint64_t stream_words)
     if (!header_fields(hd[0], h)) return GC_ECORRUPT;
     if (hd[1] != n || (hd[2] & 3u) || (hd[3] & (uint32_t)(h.k - 1))) return GC_ECORRUPT;
     if (4ull + hd[2] + hd[3] > stream_words) return GC_ECORRUPT;
+    // unary Group-Scheme control positions are 32-bit bit offsets
+    if (h.codec == GC_SCHEME && h.ld != GC_LD_BINARY && hd[2] >= (1u << 27)) return GC_EUNSUPPORTED;
     return GC_OK;
 }
 
@@ -465,7 +531,7 @@ gc_status validate_header(const uint32_t *hd, uint64_t n, uint64_t stream_words)
 
 extern "C" {
 
-const char *gc_version(void) { return "libgc 0.1 (gfx950)"; }
+const char *gc_version(void) { return "libgc 0.2 (gfx950)"; }
 
 gc_status gc_ctx_create(int device, gc_ctx **ctx) {
     if (!ctx) return GC_EINVAL;
@@ -505,36 +571,41 @@ gc_status gc_ctx_destroy(gc_ctx *ctx) {
     return GC_OK;
 }
 
-gc_status gc_decode(gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words, size_t n, uint32_t *d_out,
-                    void *hip_stream) {
-    if (!ctx || !d_stream || stream_words < 4 || (n && !d_out)) return GC_EINVAL;
-    if ((reinterpret_cast<uintptr_t>(d_stream) & 15u) != 0u || n > 0xFFFFFFFFull) return GC_EINVAL;
+gc_status gc_decode(gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words, const uint32_t *h_header,
+                    uint32_t *d_out, void *hip_stream) {
+    if (!ctx || !d_stream || !h_header || stream_words < 4) return GC_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(d_stream) & 15u) != 0u) return GC_EINVAL;
+    const uint32_t n = h_header[1];
+    if (gc_status rc = validate_header(h_header, n, stream_words)) return rc;
     if (n == 0) return GC_OK;
+    if (!d_out) return GC_EINVAL;
     std::lock_guard<std::mutex> lk(ctx->mu);
     hipStream_t s = (hipStream_t)hip_stream;
     const int tile = ctx->tile;
+    const int cls = codec_class(h_header[0]);
     const uint32_t ntiles = (uint32_t)((n + (size_t)tile - 1) / (size_t)tile);
-    const uint32_t chunk_bound = (uint32_t)std::min<size_t>((stream_words + kChunkWords - 1) / kChunkWords,
-                                                            0xFFFFFFFFull);
-    gc_status rc = ctx->single.reserve(ntiles, ntiles > 1 ? chunk_bound : 0);
+    HeaderFields h;
+    header_fields(h_header[0], h);
+    const uint32_t nchunks = ntiles > 1 ? list_chunks(h, n, h_header[2], h_header[3]) : 0u;
+    gc_status rc = ctx->single.reserve(ntiles, nchunks);
     if (rc) return rc;
     ListDesc L;
     std::memset(&L, 0, sizeof(L));
     L.stream = d_stream;
     L.out = d_out;
     L.stream_words = stream_words;
-    L.n = (uint32_t)n;
+    L.n = n;
     L.ntiles = ntiles;
-    L.nchunks = ntiles > 1 ? chunk_bound : 0;
+    L.nchunks = nchunks;
     const uint32_t cus = (uint32_t)ctx->num_cus;
     if (ntiles > 1) {
         LocateArgs a = make_locate_args(nullptr, nullptr, L, 0, tile, ctx->single, ctx->status);
-        const uint32_t g = std::max(1u, std::min(chunk_bound, (uint32_t)occupancy_locate() * cus));
-        if (launch_locate(a, g, s)) return GC_EDEVICE;
+        if (launch_locate(a, std::max(1u, std::min(nchunks, (uint32_t)occupancy_locate() * cus)), s))
+            return GC_EDEVICE;
     }
-    DecodeArgs d = make_decode_args(nullptr, nullptr, L, 0, ctx->single, ctx->status);
-    const uint32_t g = std::max(1u, std::min(ntiles, (uint32_t)occupancy_decode(tile) * cus));
-    if (launch_decode(tile, d, g, s)) return GC_EDEVICE;
+    DecodeArgs d = make_decode_args(nullptr, nullptr, L, 0, cls, ctx->single, ctx->status);
+    const uint32_t g = std::max(1u, std::min(ntiles, (uint32_t)occupancy_decode(tile, cls) * cus));
+    if (launch_decode(tile, cls, d, g, s)) return GC_EDEVICE;
     return GC_OK;
 }
 
@@ -555,7 +626,9 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     p->tile = o.tile_ints ? (int)o.tile_ints : kDefaultTile;
     p->bpc = o.blocks_per_cu;
     p->use_graph = o.use_graph != 0;
+    p->slots = std::min<uint32_t>(o.timing_slots, 4096u);
     p->h_lists.resize(nlists);
+    p->cls.resize(nlists);
     p->stream_off.resize(nlists);
     p->out_off.resize(nlists);
     uint64_t tiles_total = 0;
@@ -570,6 +643,7 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
         std::memset(&L, 0, sizeof(L));
         L.stream_words = d.stream_words;
         L.n = d.n;
+        p->cls[i] = codec_class(h_headers[4 * i]);
         p->stream_off[i] = d.stream_off_words;
         p->out_off[i] = d.out_off;
         tiles_total += (d.n + 2047u) / 2048u;
@@ -581,11 +655,17 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     (void)hipSetDevice(ctx->device);
     gc_status rc = GC_OK;
     if (o.autotune && nlists && !o.tile_ints) rc = autotune(p, h_headers, d_streams, d_out);
+    for (uint32_t i = 0; i < 3 * p->slots && !rc; i++) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) rc = GC_EDEVICE;
+        else p->ev.push_back(e);
+    }
     if (!rc) rc = plan_materialize(p, h_headers);
     if (!rc && d_streams && d_out) rc = plan_upload(p, d_streams, d_out);
     if (!rc && p->use_graph) rc = plan_capture(p);
     if (rc) {
         plan_free_device(p);
+        for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
         delete p;
         return rc;
     }
@@ -598,6 +678,7 @@ gc_status gc_plan_destroy(gc_plan *plan) {
     (void)hipSetDevice(plan->ctx->device);
     (void)hipDeviceSynchronize();
     plan_free_device(plan);
+    for (hipEvent_t e : plan->ev) (void)hipEventDestroy(e);
     delete plan;
     return GC_OK;
 }
@@ -618,8 +699,9 @@ gc_status gc_decode_each(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_o
     if (!d_streams || !d_out || (reinterpret_cast<uintptr_t>(d_streams) & 15u)) return GC_EINVAL;
     hipStream_t s = (hipStream_t)hip_stream;
     const uint32_t cus = (uint32_t)plan->ctx->num_cus;
-    const uint32_t occ_b = (uint32_t)occupancy_decode(plan->tile);
     const uint32_t occ_a = (uint32_t)occupancy_locate();
+    uint32_t occ_b[kClasses];
+    for (int c = 0; c < kClasses; c++) occ_b[c] = (uint32_t)occupancy_decode(plan->tile, c);
     for (size_t i = 0; i < plan->nlists; i++) {
         ListDesc L = plan->h_lists[i];
         if (L.n == 0) continue;
@@ -629,17 +711,42 @@ gc_status gc_decode_each(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_o
             LocateArgs a = make_locate_args(nullptr, nullptr, L, 0, plan->tile, plan->sc, plan->ctx->status);
             if (launch_locate(a, std::max(1u, std::min(L.nchunks, occ_a * cus)), s)) return GC_EDEVICE;
         }
-        DecodeArgs d = make_decode_args(nullptr, nullptr, L, 0, plan->sc, plan->ctx->status);
-        if (launch_decode(plan->tile, d, std::max(1u, std::min(L.ntiles, occ_b * cus)), s)) return GC_EDEVICE;
+        const int c = plan->cls[i];
+        DecodeArgs d = make_decode_args(nullptr, nullptr, L, 0, c, plan->sc, plan->ctx->status);
+        if (launch_decode(plan->tile, c, d, std::max(1u, std::min(L.ntiles, occ_b[c] * cus)), s))
+            return GC_EDEVICE;
     }
+    return GC_OK;
+}
+
+gc_status gc_plan_timings(gc_plan *plan, uint32_t max_runs, float *locate_ms, float *decode_ms,
+                          uint32_t *nruns) {
+    if (!plan || !plan->slots || !locate_ms || !decode_ms || !nruns) return GC_EINVAL;
+    const uint64_t avail = std::min<uint64_t>(plan->runs, plan->slots);
+    const uint32_t n = (uint32_t)std::min<uint64_t>(avail, max_runs);
+    for (uint32_t i = 0; i < n; i++) {
+        const uint64_t run = plan->runs - n + i;
+        const size_t k = (size_t)(run % plan->slots) * 3;
+        HIP_OK(hipEventSynchronize(plan->ev[k + 2]));
+        HIP_OK(hipEventElapsedTime(&locate_ms[i], plan->ev[k], plan->ev[k + 1]));
+        HIP_OK(hipEventElapsedTime(&decode_ms[i], plan->ev[k + 1], plan->ev[k + 2]));
+    }
+    *nruns = n;
     return GC_OK;
 }
 
 gc_status gc_plan_config(const gc_plan *plan, uint32_t *tile_ints, uint32_t *blocks_per_cu, uint32_t *grid_blocks) {
     if (!plan) return GC_EINVAL;
+    uint32_t g = 0, b = 0;
+    for (int c = 0; c < kClasses; c++) {
+        if (!plan->total_b[c]) continue;
+        g += plan->grid_b[c];
+        b = std::max(b, plan->bpc ? std::min<uint32_t>(plan->bpc, (uint32_t)occupancy_decode(plan->tile, c))
+                                  : (uint32_t)occupancy_decode(plan->tile, c));
+    }
     if (tile_ints) *tile_ints = (uint32_t)plan->tile;
-    if (blocks_per_cu) *blocks_per_cu = plan->bpc ? plan->bpc : (uint32_t)occupancy_decode(plan->tile);
-    if (grid_blocks) *grid_blocks = plan->grid_b;
+    if (blocks_per_cu) *blocks_per_cu = b;
+    if (grid_blocks) *grid_blocks = g;
     return GC_OK;
 }
 

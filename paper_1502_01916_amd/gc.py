@@ -55,7 +55,7 @@ class ListDesc(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("tile_ints", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
                 ("use_graph", ctypes.c_uint32), ("autotune", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 4)]
+                ("timing_slots", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
 
 
 def params(k=4, cg=1, ld=LD_CU, pfd_pos=PFD_LINKED, zeta=(1, 10), delta=False):
@@ -86,13 +86,16 @@ def lib():
                                       i, u32p, sz, u64p, i]
         L.gc_ctx_create.argtypes = [i, ctypes.POINTER(vp)]
         L.gc_ctx_destroy.argtypes = [vp]
-        L.gc_decode.argtypes = [vp, vp, sz, sz, vp, vp]
+        L.gc_decode.argtypes = [vp, vp, sz, u32p, vp, vp]
         L.gc_plan_create.argtypes = [vp, ctypes.POINTER(ListDesc), sz, u32p, ctypes.POINTER(PlanOpts),
                                      vp, vp, ctypes.POINTER(vp)]
         L.gc_plan_destroy.argtypes = [vp]
         L.gc_decode_batch.argtypes = [vp, vp, vp, vp]
         L.gc_decode_each.argtypes = [vp, vp, vp, vp]
         L.gc_plan_config.argtypes = [vp, u32p, u32p, u32p]
+        f32p = ctypes.POINTER(ctypes.c_float)
+        L.gc_plan_timings.argtypes = [vp, ctypes.c_uint32, f32p, f32p, u32p]
+        L.gc_plan_timings.restype = ctypes.c_int
         L.gc_sync_status.argtypes = [vp, vp, u32p]
         for f in ("gc_encode", "gc_encode_lists", "gc_ctx_create", "gc_ctx_destroy", "gc_decode",
                   "gc_plan_create", "gc_plan_destroy", "gc_decode_batch", "gc_decode_each",
@@ -183,8 +186,10 @@ class Context:
         self._h = ctypes.c_void_p()
         _check("gc_ctx_create", lib().gc_ctx_create(int(device), ctypes.byref(self._h)))
 
-    def decode(self, d_stream, stream_words, n, d_out, stream=None):
-        _check("gc_decode", lib().gc_decode(self._h, _ptr(d_stream), int(stream_words), int(n),
+    def decode(self, d_stream, stream_words, header, d_out, stream=None):
+        """gc_decode: `header` is the host copy of the stream's first 4 words."""
+        hdr = np.ascontiguousarray(header, dtype=np.uint32)[:4]
+        _check("gc_decode", lib().gc_decode(self._h, _ptr(d_stream), int(stream_words), _u32(hdr),
                                             _ptr(d_out), _stream_handle(stream)))
 
     def sync_status(self, stream=None):
@@ -213,14 +218,15 @@ class Plan:
     """gc_plan_create / gc_decode_batch / gc_decode_each / gc_plan_destroy."""
 
     def __init__(self, ctx: Context, descs, headers, d_streams=None, d_out=None, tile_ints=0,
-                 blocks_per_cu=0, use_graph=False, autotune=False):
+                 blocks_per_cu=0, use_graph=False, autotune=False, timing_slots=0):
         self.ctx = ctx
         nl = len(descs)
         arr = (ListDesc * max(nl, 1))()
         for i, d in enumerate(descs):
             arr[i] = d
         hdr = np.ascontiguousarray(headers, dtype=np.uint32).reshape(-1)
-        opts = PlanOpts(int(tile_ints), int(blocks_per_cu), int(bool(use_graph)), int(bool(autotune)))
+        opts = PlanOpts(int(tile_ints), int(blocks_per_cu), int(bool(use_graph)), int(bool(autotune)),
+                        int(timing_slots))
         self._h = ctypes.c_void_p()
         rc = lib().gc_plan_create(ctx._h, arr, nl, _u32(hdr), ctypes.byref(opts),
                                   _ptr(d_streams) if d_streams is not None else None,
@@ -234,6 +240,14 @@ class Plan:
     def decode_each(self, d_streams, d_out, stream=None):
         _check("gc_decode_each", lib().gc_decode_each(self._h, _ptr(d_streams), _ptr(d_out),
                                                       _stream_handle(stream)))
+
+    def timings(self, max_runs):
+        """(locate_ms, decode_ms) arrays for the last runs, oldest first."""
+        a = (ctypes.c_float * max(max_runs, 1))()
+        b = (ctypes.c_float * max(max_runs, 1))()
+        n = ctypes.c_uint32()
+        _check("gc_plan_timings", lib().gc_plan_timings(self._h, int(max_runs), a, b, ctypes.byref(n)))
+        return np.array(a[:n.value]), np.array(b[:n.value])
 
     def config(self):
         t, b, g = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
@@ -253,18 +267,30 @@ class Plan:
             pass
 
 
-def batch_layout(streams_flat, stream_offs, lengths):
+def batch_layout(streams_flat, stream_offs, lengths, align=1):
     """List descriptors and headers for streams concatenated in `streams_flat`
-    (offsets from encode_lists) decoding into one output of sum(lengths)."""
+    (offsets from encode_lists).  List i decodes to out_offs[i] .. +lengths[i]
+    of one output buffer; with align > 1 every list starts on a multiple of
+    `align` integers.  Returns (descs, headers, out_offs) with out_offs[-1] the
+    buffer length."""
     lengths = np.asarray(lengths, dtype=np.int64)
+    padded = (lengths + align - 1) // align * align
     out_offs = np.zeros(lengths.size + 1, np.int64)
-    np.cumsum(lengths, out=out_offs[1:])
+    np.cumsum(padded, out=out_offs[1:])
     so = np.asarray(stream_offs, dtype=np.int64)
     descs = [ListDesc(int(so[i]), int(so[i + 1] - so[i]), int(out_offs[i]), int(lengths[i]), 0)
              for i in range(lengths.size)]
     idx = so[:-1, None] + np.arange(4)[None, :]
     headers = streams_flat[idx.reshape(-1)].reshape(-1, 4) if lengths.size else np.zeros((0, 4), np.uint32)
     return descs, np.ascontiguousarray(headers, dtype=np.uint32), out_offs
+
+
+def unpad(out, out_offs, lengths):
+    """Concatenates the decoded lists of a batch output laid out by batch_layout."""
+    lengths = np.asarray(lengths, dtype=np.int64)
+    if np.array_equal(np.diff(out_offs), lengths):
+        return out[:int(lengths.sum())]
+    return np.concatenate([out[int(o):int(o) + int(L)] for o, L in zip(out_offs[:-1], lengths)])
 
 
 def to_device(a_u32, device="cuda"):
