@@ -134,8 +134,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip per-list and per-codec runs")
-    ap.add_argument("--tile", type=int, default=0, help="force a tile size (0 = autotune)")
-    ap.add_argument("--bpc", type=int, default=0, help="force workgroups per CU (with --tile)")
+    ap.add_argument("--tile", type=int, default=0, help="force the wave-tile size (0 = autotune)")
+    ap.add_argument("--pfd-tile", type=int, default=0, help="force the Group-PFD tile size (with --tile)")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels directly, no hipGraph")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -162,8 +162,8 @@ def main():
     d_o = torch.empty(out_len, dtype=torch.int32, device="cuda")
     t = time.time()
     plan = gc.Plan(ctx, descs, headers, d_s, d_o, use_graph=not args.no_graph, tile_ints=args.tile,
-                   blocks_per_cu=args.bpc, autotune=args.tile == 0,
-                   timing_slots=args.steps + args.warmup)
+                   pfd_tile_ints=args.pfd_tile or (4096 if args.tile else 0),
+                   autotune=args.tile == 0, timing_slots=args.steps + args.warmup)
     cfg = plan.config()
     log("plan: %s (%.1fs)" % (cfg, time.time() - t))
 
@@ -209,7 +209,7 @@ def main():
             ds2 = gc.to_device(s2)
             do2 = torch.empty(int(oo2[-1]), dtype=torch.int32, device="cuda")
             p2 = gc.Plan(ctx, de2, h2, ds2, do2, use_graph=True, tile_ints=cfg["tile_ints"],
-                         blocks_per_cu=cfg["blocks_per_cu"], timing_slots=args.steps)
+                         pfd_tile_ints=cfg["pfd_tile_ints"], timing_slots=args.steps)
             el = timed(p2, ds2, do2, args.steps, 2, torch)
             _, dm = p2.timings(args.steps)
             n2 = int(l2.sum())
@@ -255,12 +255,15 @@ def main():
             "stream_bytes": stream_bytes,
             "bits_per_int": round(32.0 * streams.size / total, 3),
             "tile_ints": cfg["tile_ints"],
-            "blocks_per_cu": cfg["blocks_per_cu"],
+            "pfd_tile_ints": cfg["pfd_tile_ints"],
+            "tiles": cfg["tiles"],
+            "sum_tiles": cfg["sum_tiles"],
             "verified_bit_exact": verified,
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "gc_decode_kernel<%d>" % cfg["tile_ints"],
+            "kernel": "gc_decode_wave_kernel<%d,*> + gc_decode_kernel<%d,pfd> (concurrent)"
+                      % (cfg["tile_ints"], cfg["pfd_tile_ints"]),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -142,30 +142,36 @@ typedef struct {
 
 /* Plan options (zero-initialise for defaults). */
 typedef struct {
-    uint32_t tile_ints;      /* integers per decode tile: 0 = autotuned / default   */
-    uint32_t blocks_per_cu;  /* persistent workgroups per CU: 0 = autotuned/default */
+    uint32_t tile_ints;      /* integers per wave tile (Group-Simple, -Scheme, -AFOR):
+                                1024, 2048 or 4096, raised to 32*k for the widest
+                                layout in the batch; 0 = autotuned / default       */
+    uint32_t pfd_tile_ints;  /* integers per workgroup tile of Group-PFD: 2048, 4096
+                                or 8192; 0 = autotuned / default                   */
     uint32_t use_graph;      /* 1 = capture the launch sequence in a hipGraph       */
-    uint32_t autotune;       /* 1 = time candidate configurations at creation       */
+    uint32_t autotune;       /* 1 = time candidate tile sizes at creation           */
     uint32_t timing_slots;   /* > 0: record HIP events around the locate and decode
                                 launches of each gc_decode_batch, in this many
                                 rotating slots (see gc_plan_timings)               */
-    uint32_t reserved[3];
+    uint32_t reserved[3];    /* zero */
 } gc_plan_opts;
 
 /* Builds a batched decode plan for nlists lists.  h_headers holds the first
  * 4 words of every stream (4*nlists words, host memory).  The plan holds the
- * work queue, the per-tile locate table and look-back flags, and (optionally)
- * an instantiated hipGraph; it allocates everything here, never at execute.
- * With opts->autotune the plan times candidate tile sizes and occupancies on
- * the device buffers given (d_streams, d_out) and keeps the fastest; results
- * are cached in a JSON file named by $GC_AUTOTUNE_CACHE when set.          */
+ * tile tables (tile -> list, the per-tile locate entries and carries) and
+ * (optionally) an instantiated hipGraph; it allocates everything here, never
+ * at execute.  With opts->autotune the plan times candidate tile sizes on the
+ * device buffers given (d_streams, d_out) and keeps the fastest; results are
+ * cached in a JSON file named by $GC_AUTOTUNE_CACHE when set.  GC_EINVAL for
+ * a tile size not listed above or nonzero reserved words.                  */
 gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists,
                          const uint32_t *h_headers, const gc_plan_opts *opts,
                          const uint32_t *d_streams, uint32_t *d_out, gc_plan **plan);
 gc_status gc_plan_destroy(gc_plan *plan);
 
-/* Decodes every list of the plan in one persistent launch sequence
- * (captured in a hipGraph when the plan was created with use_graph).       */
+/* Decodes every list of the plan: the locate pass, then per codec class the
+ * tile-sum pass over its delta lists of more than one tile, the carry scan
+ * and the decode pass (one hipGraph branch per class when the plan was
+ * created with use_graph).                                                 */
 gc_status gc_decode_batch(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_out,
                           void *hip_stream);
 
@@ -177,15 +183,18 @@ gc_status gc_decode_each(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_o
 /* Kernel durations of the last runs of a plan created with timing_slots > 0:
  * synchronises the recorded HIP events and writes, oldest first, up to
  * max_runs pairs (locate_ms[i], decode_ms[i]) -- the time between the events
- * recorded on the launch stream before the locate kernel, between the two
- * kernels, and after the decode kernel.  *nruns receives the count written.
+ * recorded on the launch stream before the locate kernels, between the locate
+ * kernels and the decode kernels (tile sums, carry scans, decode passes), and
+ * after those.  *nruns receives the count written.
  * GC_EINVAL if the plan records no events.                                 */
 gc_status gc_plan_timings(gc_plan *plan, uint32_t max_runs, float *locate_ms, float *decode_ms,
                           uint32_t *nruns);
 
-/* Reports the chosen configuration of a plan. */
-gc_status gc_plan_config(const gc_plan *plan, uint32_t *tile_ints, uint32_t *blocks_per_cu,
-                         uint32_t *grid_blocks);
+/* Reports the chosen configuration of a plan: the wave-tile and Group-PFD
+ * tile sizes, the decode tiles of one run and, of those, the tiles the sum
+ * pass decodes as well.  Any pointer may be NULL.                          */
+gc_status gc_plan_config(const gc_plan *plan, uint32_t *tile_ints, uint32_t *pfd_tile_ints,
+                         uint64_t *tiles, uint64_t *sum_tiles);
 
 /* Synchronises hip_stream, then returns (and clears) the first device-side
  * error latched since the previous call: GC_OK or GC_ECORRUPT.  detail, if

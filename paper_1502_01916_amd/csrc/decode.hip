@@ -5,25 +5,28 @@
 //           per work item) and records where every decode tile starts: the
 //           control unit, the tuples of it that belong to the previous tile,
 //           the component data bit offset and (Group-PFD) the exception word
-//           offset.  The scan across work items uses decoupled look-back.
+//           offset.  Three kernels: chunk aggregates, their scan within each
+//           list, tile starts.
 //
-//   decode  One persistent kernel per codec class (Group-Simple, Group-Scheme
-//           unary, Group-Scheme binary, Group-AFOR, Group-PFD), so each keeps
-//           only its own registers and LDS.  A work item is one tile of TILE
-//           output integers.  The tile's control units are parsed into
-//           per-tuple records (component bit offset, width) in LDS; each
-//           thread then produces four consecutive integers per round from two
+//   decode  One kernel per codec class.  Group-Simple, Group-Scheme (unary
+//           and binary descriptors) and Group-AFOR decode one tile per wave64;
+//           Group-PFD one tile per workgroup, since its exception patching
+//           needs a tile-sized LDS buffer.  A tile's control units are parsed
+//           into per-tuple records (component bit offset, width) in LDS; each
+//           lane then produces four consecutive integers per round from two
 //           16-byte data rows read through the vector cache, with a 64-bit
 //           funnel shift (v_alignbit_b32) and a mask.  Group-PFD patches
 //           exceptions in LDS (linked chains, or bitmap ranks by ballot and
-//           mbcnt).  Delta lists are prefix-summed in-thread, across the wave
-//           with DPP, across the workgroup through LDS, and across tiles by a
-//           decoupled look-back that inspects 64 predecessors per probe.
+//           mbcnt).
 //
-// Work items are popped from an atomic counter in list/tile order, so every
-// look-back predecessor is owned by a running workgroup; each kernel resets
-// its counters when its last workgroup retires, so a run needs no memset and
-// can be replayed from a captured graph.
+//   carry   A delta list of more than one tile is prefix-summed across its
+//           tiles by reduce-then-scan: a sum pass decodes every tile and
+//           stores the sum of its gaps, one workgroup per list scans those
+//           sums into exclusive carries, and the decode pass adds the carry
+//           to its in-tile scan.  No tile ever waits for another, so every
+//           kernel is a plain grid with no work queue, no spinning and no
+//           atomics (the one exception: the first error is latched).  The sum
+//           pass costs a second read of the compressed data only.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -39,13 +42,11 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // Small helpers.
 
 constexpr uint32_t kEpochMask = 0x3FFFFFFFu;
-constexpr uint64_t kTimeoutTicks = 200000000ull;   // 2 s of the 100 MHz clock
 constexpr int kLocWords = kChunkWords / kThreads;  // control words per thread
 
 __device__ __forceinline__ uint32_t epoch_next(uint32_t e) {
     return ((e + 1u) & kEpochMask) ? ((e + 1u) & kEpochMask) : 1u;
 }
-__device__ __forceinline__ uint32_t epoch_prev(uint32_t e) { return e > 1u ? e - 1u : kEpochMask; }
 
 __device__ __forceinline__ uint32_t mask_of(uint32_t b) { return b >= 32u ? 0xFFFFFFFFu : ((1u << b) - 1u); }
 
@@ -107,19 +108,6 @@ __device__ __forceinline__ void latch(Status *st, uint32_t detail) {
         __hip_atomic_store(&st->detail, detail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ uint32_t load_acq(const uint32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long load_acq64(const unsigned long long *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void store_rel(uint32_t *p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void store_rel64(unsigned long long *p, unsigned long long v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Group-Simple selector -> (NUM, BW), Table III, packed as 5-bit fields
 // holding NUM-1 and BW-1.
 constexpr uint64_t kSimNumM1 = 31ull | 15ull << 5 | 9ull << 10 | 7ull << 15 | 5ull << 20 | 4ull << 25 |
@@ -170,60 +158,13 @@ __device__ __forceinline__ uint32_t pfd_exc_words(uint32_t desc, int k, int bitm
 
 __device__ __forceinline__ bool header_ok(const ListDesc &L, uint32_t w0, uint32_t n, uint32_t C,
                                           uint32_t D, HeaderFields &h) {
-    if (!header_fields(w0, h)) return false;
+    if (w0 != L.w0 || C != L.C || D != L.D || !header_fields(w0, h)) return false;
     if (n != L.n || (C & 3u) != 0u || (D & (uint32_t)(h.k - 1)) != 0u) return false;
     return 4ull + C + D <= L.stream_words;
 }
 
-__device__ __forceinline__ void finish_run(RunState *rs, uint32_t epoch) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t d = __hip_atomic_fetch_add(&rs->done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (d == gridDim.x - 1) {
-            __hip_atomic_store(&rs->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&rs->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&rs->epoch, epoch_next(epoch), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
-}
-
-// Decoupled look-back run by one whole wave: lane l inspects predecessor
-// gi-1-l; the nearest inclusive prefix and every aggregate after it are
-// summed into the probe.  `first` is the list's first entry, which always
-// publishes an inclusive prefix.
-template <typename Probe>
-__device__ __forceinline__ void wave_lookback(uint32_t gi, uint32_t first, Probe &probe, Status *st) {
-    const uint32_t lane = lane_id();
-    uint32_t base = gi;                       // this window covers base-1-lane
-    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-    for (;;) {
-        const bool in = base >= first + 1u + lane;
-        const uint32_t j = in ? base - 1u - lane : first;
-        const int state = in ? probe.state(j) : 2;   // 0 not ready, 1 aggregate, 2 inclusive
-        const uint64_t pmask = __ballot(state == 2);
-        const uint64_t nready = __ballot(state == 0);
-        if (pmask) {
-            const uint32_t p = (uint32_t)__builtin_ctzll(pmask);
-            const uint64_t need = (p == 63u) ? ~0ull : ((2ull << p) - 1ull);
-            if ((nready & need) == 0ull) {
-                probe.accumulate(in && lane <= p, j);
-                return;
-            }
-        } else if (nready == 0ull) {
-            probe.accumulate(true, j);
-            base -= 64u;
-            continue;
-        }
-        __builtin_amdgcn_s_sleep(1);
-        if (__builtin_amdgcn_s_memrealtime() - t0 > kTimeoutTicks) {
-            if (lane == 0) latch(st, kErrTimeout);
-            return;
-        }
-    }
-}
-
 // ===========================================================================
-// Locate kernel.
+// Locate kernels: reduce -> scan -> emit.
 
 __device__ __forceinline__ uint32_t locate_words(const HeaderFields &h, uint32_t T, uint32_t C, uint32_t D) {
     switch (h.codec) {
@@ -239,57 +180,40 @@ __device__ __forceinline__ uint32_t locate_words(const HeaderFields &h, uint32_t
     }
 }
 
-struct LocProbe {
-    const uint32_t *flags;
-    const LocVal *agg, *incl;
-    uint32_t epoch;
-    uint32_t tup, exc;
-    uint64_t data;
-    uint32_t st;
-    __device__ int state(uint32_t j) {
-        const uint32_t f = load_acq(&flags[j]);
-        st = ((f >> 2) == epoch) ? (f & 3u) : 0u;
-        return (int)st;
-    }
-    __device__ void accumulate(bool take, uint32_t j) {
-        LocVal v;
-        v.tup = 0;
-        v.exc = 0;
-        v.data = 0;
-        if (take) v = st == 2u ? incl[j] : agg[j];
-        tup += wave_sum(v.tup);
-        exc += wave_sum(v.exc);
-        data += wave_sum64(v.data);
-    }
+// One thread's view of a control chunk: its kLocWords words and their
+// aggregate (tuples, exception words, component data bits).
+struct LocThread {
+    HeaderFields h;
+    bool ok, bad;
+    uint32_t k, T, TT, D, nwords, wbase;
+    uint32_t word[kLocWords];
+    uint32_t vt, ve, vd;
 };
 
-__device__ void locate_chunk(const LocateArgs &a, const ListDesc &L, uint32_t chunk, uint32_t epoch,
-                             LocVal &s_pre, uint32_t *s_tmp, uint32_t &s_bad) {
-    const int tid = threadIdx.x;
+__device__ __forceinline__ void locate_thread(const ListDesc &L, uint32_t chunk, LocThread &t) {
     const uint32_t *S = L.stream;
     const uint32_t w0 = S[0], n = S[1], C = S[2], D = S[3];
-    HeaderFields h;
-    const bool ok = header_ok(L, w0, n, C, D, h);
-    const uint32_t k = (uint32_t)h.k;
-    const uint32_t T = ok ? (n + k - 1u) >> h.lk : 0u;
-    const uint32_t TT = a.tile_ints >> h.lk;
-    const uint32_t nwords = ok ? locate_words(h, T, C, D) : 0u;
+    t.ok = header_ok(L, w0, n, C, D, t.h);
+    t.k = (uint32_t)t.h.k;
+    t.T = t.ok ? (n + t.k - 1u) >> t.h.lk : 0u;
+    t.TT = L.tile_ints >> t.h.lk;
+    t.D = D;
+    t.nwords = t.ok ? locate_words(t.h, t.T, C, D) : 0u;
+    t.wbase = (chunk * (uint32_t)kThreads + threadIdx.x) * (uint32_t)kLocWords;
+    t.bad = !t.ok;
+    t.vt = t.ve = t.vd = 0;
     const uint32_t *ctrl = S + 4;
-    const uint32_t wbase = (chunk * (uint32_t)kThreads + (uint32_t)tid) * (uint32_t)kLocWords;
-    uint32_t word[kLocWords];
-    bool bad = !ok && tid == 0;
-
-    uint32_t vt = 0, ve = 0, vd = 0;
+    const HeaderFields &h = t.h;
 #pragma unroll
     for (int q = 0; q < kLocWords; q++) {
-        const uint32_t w = wbase + (uint32_t)q;
-        word[q] = w < nwords ? ctrl[w] : 0u;
+        const uint32_t w = t.wbase + (uint32_t)q;
+        t.word[q] = w < t.nwords ? ctrl[w] : 0u;
     }
 #pragma unroll
     for (int q = 0; q < kLocWords; q++) {
-        const uint32_t w = wbase + (uint32_t)q;
-        if (w >= nwords) continue;
-        const uint32_t wd = word[q];
+        const uint32_t w = t.wbase + (uint32_t)q;
+        if (w >= t.nwords) continue;
+        const uint32_t wd = t.word[q];
         switch (h.codec) {
         case 0: {
             const uint32_t S_total = D >> h.lk;
@@ -297,10 +221,10 @@ __device__ void locate_chunk(const LocateArgs &a, const ListDesc &L, uint32_t ch
                 if (8u * w + i >= S_total) break;
                 const uint32_t sel = (wd >> (4u * i)) & 15u;
                 if (sel >= 10u) {
-                    bad = true;
+                    t.bad = true;
                     continue;
                 }
-                vt += sim_num(sel);
+                t.vt += sim_num(sel);
             }
             break;
         }
@@ -308,15 +232,15 @@ __device__ void locate_chunk(const LocateArgs &a, const ListDesc &L, uint32_t ch
             if (h.ld == GC_LD_BINARY) {
                 const BinUnit u = bin_unit(h.cg);
                 for (uint32_t f = 0; f < u.fpw; f++) {
-                    const uint32_t t = w * u.fpw + f;
-                    if (t >= T) break;
-                    const uint32_t bit = bin_field_bit(t, u) & 31u;
-                    vt += 1u;
-                    vd += (uint32_t)h.cg * (((wd >> bit) & mask_of(u.fb)) + 1u);
+                    const uint32_t tt = w * u.fpw + f;
+                    if (tt >= t.T) break;
+                    const uint32_t bit = bin_field_bit(tt, u) & 31u;
+                    t.vt += 1u;
+                    t.vd += (uint32_t)h.cg * (((wd >> bit) & mask_of(u.fb)) + 1u);
                 }
             } else {
-                vt += (uint32_t)__builtin_popcount(~wd);
-                if (h.ld == GC_LD_IU) vd += (uint32_t)h.cg * iu_useful(wd);
+                t.vt += (uint32_t)__builtin_popcount(~wd);
+                if (h.ld == GC_LD_IU) t.vd += (uint32_t)h.cg * iu_useful(wd);
             }
             break;
         case 2:
@@ -324,224 +248,213 @@ __device__ void locate_chunk(const LocateArgs &a, const ListDesc &L, uint32_t ch
                 const uint32_t byte = (wd >> (8 * i)) & 0xFFu;
                 const uint32_t b = byte & 63u, cls = byte >> 6;
                 if (cls == 3u || b > 32u) {
-                    bad = true;
+                    t.bad = true;
                     continue;
                 }
                 const uint32_t F = 8u << cls;
-                vt += F;
-                vd += F * b;
+                t.vt += F;
+                t.vd += F * b;
             }
             break;
         default: {
             const uint32_t b = wd & 63u;
-            if (b > 32u) bad = true;
-            vt += 32u;
-            vd += 32u * min(b, 32u);
-            ve += pfd_exc_words(wd, (int)k, h.pfd_pos);
-            break;
-        }
-        }
-    }
-    if (bad) s_bad = 1u;
-
-    uint32_t tt, te, td;
-    const uint32_t xt = block_excl_scan(vt, s_tmp, tt);
-    const uint32_t xe = block_excl_scan(ve, s_tmp, te);
-    const uint32_t xd = block_excl_scan(vd, s_tmp, td);
-
-    if (tid < 64) {
-        const uint32_t gi = L.chunk_base + chunk;
-        LocProbe pr{a.flags, a.agg, a.incl, epoch, 0u, 0u, 0ull, 0u};
-        if (chunk > 0) {
-            if (tid == 0) {
-                LocVal agg;
-                agg.tup = tt;
-                agg.exc = te;
-                agg.data = td;
-                a.agg[gi] = agg;
-                store_rel(&a.flags[gi], (epoch << 2) | 1u);
-            }
-            wave_lookback(gi, L.chunk_base, pr, a.status);
-        }
-        if (tid == 0) {
-            LocVal pre;
-            pre.tup = pr.tup;
-            pre.exc = pr.exc;
-            pre.data = pr.data;
-            LocVal inc;
-            inc.tup = pre.tup + tt;
-            inc.exc = pre.exc + te;
-            inc.data = pre.data + td;
-            a.incl[gi] = inc;
-            store_rel(&a.flags[gi], (epoch << 2) | 2u);
-            s_pre = pre;
-        }
-    }
-    __syncthreads();
-    if (s_bad) {
-        if (tid == 0) latch(a.status, kErrLocate);
-        return;
-    }
-    const uint32_t ntiles = L.ntiles;
-    uint32_t base_t = s_pre.tup + xt;
-    uint64_t base_d = s_pre.data + xd;
-    uint32_t base_e = s_pre.exc + xe;
-    TileInfo *tiles = a.tiles + L.tile_base;
-
-    auto emit = [&](uint32_t m, uint32_t unit, uint32_t sub, uint64_t data, uint32_t exc) {
-        TileInfo ti;
-        ti.unit = unit;
-        ti.sub = sub;
-        ti.exc = exc;
-        ti.tag = epoch;
-        ti.data = data;
-        ti.pad = 0;
-        tiles[m] = ti;
-    };
-    // the tile boundary m*TT (m >= 1) that falls in tuples [t, t + cnt)
-    auto boundary = [&](uint32_t t, uint32_t cnt, uint32_t &m) -> bool {
-        m = (t + TT - 1u) / TT;
-        if (m == 0u) m = 1u;
-        return m < ntiles && (uint64_t)m * TT < (uint64_t)t + cnt;
-    };
-
-#pragma unroll
-    for (int q = 0; q < kLocWords; q++) {
-        const uint32_t w = wbase + (uint32_t)q;
-        if (w >= nwords) break;
-        const uint32_t wd = word[q];
-        switch (h.codec) {
-        case 0: {
-            const uint32_t S_total = D >> h.lk;
-            for (uint32_t i = 0; i < 8u; i++) {
-                const uint32_t s = 8u * w + i;
-                if (s >= S_total) break;
-                const uint32_t num = sim_num((wd >> (4u * i)) & 15u);
-                uint32_t m;
-                if (boundary(base_t, num, m)) emit(m, s, m * TT - base_t, 32ull * s, 0);
-                base_t += num;
-            }
-            break;
-        }
-        case 1:
-            if (h.ld == GC_LD_BINARY) {
-                const BinUnit u = bin_unit(h.cg);
-                for (uint32_t f = 0; f < u.fpw; f++) {
-                    const uint32_t t = w * u.fpw + f;
-                    if (t >= T) break;
-                    if (t > 0u && t % TT == 0u && t / TT < ntiles) emit(t / TT, t, 0, base_d, 0);
-                    const uint32_t bit = bin_field_bit(t, u) & 31u;
-                    base_d += (uint32_t)h.cg * (((wd >> bit) & mask_of(u.fb)) + 1u);
-                }
-            } else {
-                // terminators (0 bits) of ranks base_t .. base_t + cnt - 1 end in
-                // this word; the tile starting at tuple m*TT begins right after
-                // the terminator of rank m*TT - 1
-                const uint32_t z = ~wd;
-                const uint32_t cnt = (uint32_t)__builtin_popcount(z);
-                const uint32_t m = (base_t + TT) / TT;
-                if (cnt && m < ntiles && m * TT - 1u < base_t + cnt) {
-                    uint32_t zz = z;
-                    for (uint32_t i = 0; i < m * TT - 1u - base_t; i++) zz &= zz - 1u;
-                    const uint32_t bit = (uint32_t)__builtin_ctz(zz);
-                    const uint32_t pos = 32u * w + bit + 1u;
-                    uint64_t d;
-                    if (h.ld == GC_LD_CU) {
-                        d = (uint64_t)h.cg * pos;
-                    } else {
-                        // bits above `bit` read as padding: only bytes up to it count
-                        const uint32_t upto = bit == 31u ? wd : (wd | ~((2u << bit) - 1u));
-                        d = base_d + (uint64_t)h.cg * iu_useful(upto);
-                    }
-                    emit(m, pos, 0, d, 0);
-                }
-                base_t += cnt;
-                if (h.ld == GC_LD_IU) base_d += (uint32_t)h.cg * iu_useful(wd);
-            }
-            break;
-        case 2:
-            for (int i = 0; i < 4; i++) {
-                const uint32_t byte = (wd >> (8 * i)) & 0xFFu;
-                const uint32_t b = byte & 63u, F = 8u << (byte >> 6);
-                uint32_t m;
-                if (boundary(base_t, F, m)) emit(m, 4u * w + (uint32_t)i, m * TT - base_t, base_d, 0);
-                base_t += F;
-                base_d += (uint64_t)F * b;
-            }
-            break;
-        default: {
-            const uint32_t t = 32u * w;
-            if (t > 0u && t % TT == 0u && t / TT < ntiles) emit(t / TT, w, 0, base_d, base_e);
-            base_d += 32u * min(wd & 63u, 32u);
-            base_e += pfd_exc_words(wd, (int)k, h.pfd_pos);
+            if (b > 32u) t.bad = true;
+            t.vt += 32u;
+            t.vd += 32u * min(b, 32u);
+            t.ve += pfd_exc_words(wd, (int)t.k, h.pfd_pos);
             break;
         }
         }
     }
 }
 
-__global__ __launch_bounds__(kThreads) void gc_locate_kernel(LocateArgs a) {
-    __shared__ uint32_t s_item;
-    __shared__ LocVal s_pre;
+__device__ __forceinline__ bool locate_item(const LocateArgs &a, uint32_t item, ListDesc &L, uint32_t &chunk) {
+    if (item >= a.total_items) return false;
+    if (a.lists) {
+        L = a.lists[a.item_list[item]];
+        chunk = item - L.chunk_base;
+    } else {
+        L = a.single;
+        chunk = item;
+    }
+    return true;
+}
+
+// Aggregate of every control chunk.
+__global__ __launch_bounds__(kThreads) void gc_locate_reduce(LocateArgs a) {
     __shared__ uint32_t s_tmp[kWaves];
-    __shared__ uint32_t s_bad;
-    const uint32_t epoch = __hip_atomic_load(&a.state->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (;;) {
-        if (threadIdx.x == 0) {
-            s_item = atomicAdd(&a.state->counter, 1u);
-            s_bad = 0u;
-        }
-        __syncthreads();
-        const uint32_t item = s_item;
-        ListDesc L;
-        uint32_t chunk;
-        if (a.lists) {
-            if (item >= a.total_items) break;
-            L = a.lists[a.item_list[item]];
-            chunk = item - L.chunk_base;
-        } else {
-            L = a.single;
-            const uint32_t *S = L.stream;
-            HeaderFields h;
-            uint32_t nw = 0;
-            if (header_ok(L, S[0], S[1], S[2], S[3], h)) {
-                const uint32_t T = (S[1] + (uint32_t)h.k - 1u) >> h.lk;
-                nw = locate_words(h, T, S[2], S[3]);
-            }
-            const uint32_t nchunks = (nw + kChunkWords - 1u) / kChunkWords;
-            if (item >= (nchunks ? nchunks : 1u)) break;
-            chunk = item;
-        }
-        locate_chunk(a, L, chunk, epoch, s_pre, s_tmp, s_bad);
-        __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // a new locate run: later kernels of this launch sequence tag and
+        // check tile starts with the advanced epoch
+        const uint32_t e = __hip_atomic_load(&a.state->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.state->epoch, epoch_next(e), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    finish_run(a.state, epoch);
+    ListDesc L;
+    uint32_t chunk;
+    if (!locate_item(a, blockIdx.x, L, chunk)) return;
+    LocThread t;
+    locate_thread(L, chunk, t);
+    uint32_t tt, te, td;
+    (void)block_excl_scan(t.vt, s_tmp, tt);
+    (void)block_excl_scan(t.ve, s_tmp, te);
+    (void)block_excl_scan(t.vd, s_tmp, td);
+    if (t.bad) latch(a.status, kErrLocate);
+    if (threadIdx.x == 0) {
+        LocVal v;
+        v.tup = tt;
+        v.exc = te;
+        v.data = td;
+        a.agg[L.chunk_base + chunk] = v;
+    }
 }
 
+// Exclusive prefix of the chunk aggregates of one list per wave.
+__global__ __launch_bounds__(kThreads) void gc_locate_scan(LocateArgs a) {
+    const uint32_t item = blockIdx.x * (uint32_t)kWaves + (threadIdx.x >> 6);
+    if (item >= a.total_scan) return;
+    const ListDesc L = a.lists ? a.lists[a.scan_list[item]] : a.single;
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t ct = 0, ce = 0;
+    uint64_t cd = 0;
+    for (uint32_t c0 = 0; c0 < L.nchunks; c0 += 64u) {
+        const uint32_t c = c0 + lane;
+        LocVal v;
+        v.tup = 0;
+        v.exc = 0;
+        v.data = 0;
+        if (c < L.nchunks) v = a.agg[L.chunk_base + c];
+        const uint32_t d = (uint32_t)v.data;   // a chunk holds < 2^23 data bits
+        const uint32_t it = wave_incl_scan(v.tup), ie = wave_incl_scan(v.exc), id = wave_incl_scan(d);
+        if (c < L.nchunks) {
+            LocVal p;
+            p.tup = ct + it - v.tup;
+            p.exc = ce + ie - v.exc;
+            p.data = cd + (id - d);
+            a.pre[L.chunk_base + c] = p;
+        }
+        ct += (uint32_t)__builtin_amdgcn_readlane((int)it, 63);
+        ce += (uint32_t)__builtin_amdgcn_readlane((int)ie, 63);
+        cd += (uint32_t)__builtin_amdgcn_readlane((int)id, 63);
+    }
+}
+
+// Tile starts from the chunk prefixes, tagged with this run's epoch.
+__global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
+    __shared__ uint32_t s_tmp[kWaves];
+    const uint32_t epoch = __hip_atomic_load(&a.state->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ListDesc L;
+    uint32_t chunk;
+    if (locate_item(a, blockIdx.x, L, chunk)) {
+        LocThread t;
+        locate_thread(L, chunk, t);
+        uint32_t tt, te, td;
+        const uint32_t xt = block_excl_scan(t.vt, s_tmp, tt);
+        const uint32_t xe = block_excl_scan(t.ve, s_tmp, te);
+        const uint32_t xd = block_excl_scan(t.vd, s_tmp, td);
+        const LocVal pre = a.pre[L.chunk_base + chunk];
+        const uint32_t TT = t.TT, ntiles = L.ntiles, D = t.D;
+        const HeaderFields &h = t.h;
+        uint32_t base_t = pre.tup + xt;
+        uint64_t base_d = pre.data + xd;
+        uint32_t base_e = pre.exc + xe;
+        TileInfo *tiles = a.tiles + L.tile_base;
+        auto emit = [&](uint32_t m, uint32_t unit, uint32_t sub, uint64_t data, uint32_t exc) {
+            TileInfo ti;
+            ti.unit = unit;
+            ti.sub = sub;
+            ti.exc = exc;
+            ti.tag = epoch;
+            ti.data = data;
+            ti.pad = 0;
+            tiles[m] = ti;
+        };
+        // the tile boundary m*TT (m >= 1) that falls in tuples [t0, t0 + cnt)
+        auto boundary = [&](uint32_t t0, uint32_t cnt, uint32_t &m) -> bool {
+            m = (t0 + TT - 1u) / TT;
+            if (m == 0u) m = 1u;
+            return m < ntiles && (uint64_t)m * TT < (uint64_t)t0 + cnt;
+        };
+        if (!t.bad) {
+#pragma unroll
+            for (int q = 0; q < kLocWords; q++) {
+                const uint32_t w = t.wbase + (uint32_t)q;
+                if (w >= t.nwords) break;
+                const uint32_t wd = t.word[q];
+                switch (h.codec) {
+                case 0: {
+                    const uint32_t S_total = D >> h.lk;
+                    for (uint32_t i = 0; i < 8u; i++) {
+                        const uint32_t s = 8u * w + i;
+                        if (s >= S_total) break;
+                        const uint32_t num = sim_num((wd >> (4u * i)) & 15u);
+                        uint32_t m;
+                        if (boundary(base_t, num, m)) emit(m, s, m * TT - base_t, 32ull * s, 0);
+                        base_t += num;
+                    }
+                    break;
+                }
+                case 1:
+                    if (h.ld == GC_LD_BINARY) {
+                        const BinUnit u = bin_unit(h.cg);
+                        for (uint32_t f = 0; f < u.fpw; f++) {
+                            const uint32_t tt2 = w * u.fpw + f;
+                            if (tt2 >= t.T) break;
+                            if (tt2 > 0u && tt2 % TT == 0u && tt2 / TT < ntiles) emit(tt2 / TT, tt2, 0, base_d, 0);
+                            const uint32_t bit = bin_field_bit(tt2, u) & 31u;
+                            base_d += (uint32_t)h.cg * (((wd >> bit) & mask_of(u.fb)) + 1u);
+                        }
+                    } else {
+                        // terminators (0 bits) of ranks base_t .. base_t + cnt - 1 end
+                        // in this word; the tile starting at tuple m*TT begins right
+                        // after the terminator of rank m*TT - 1
+                        const uint32_t z = ~wd;
+                        const uint32_t cnt = (uint32_t)__builtin_popcount(z);
+                        const uint32_t m = (base_t + TT) / TT;
+                        if (cnt && m < ntiles && m * TT - 1u < base_t + cnt) {
+                            uint32_t zz = z;
+                            for (uint32_t i = 0; i < m * TT - 1u - base_t; i++) zz &= zz - 1u;
+                            const uint32_t bit = (uint32_t)__builtin_ctz(zz);
+                            const uint32_t pos = 32u * w + bit + 1u;
+                            uint64_t d;
+                            if (h.ld == GC_LD_CU) {
+                                d = (uint64_t)h.cg * pos;
+                            } else {
+                                // bits above `bit` read as padding: only bytes up to it count
+                                const uint32_t upto = bit == 31u ? wd : (wd | ~((2u << bit) - 1u));
+                                d = base_d + (uint64_t)h.cg * iu_useful(upto);
+                            }
+                            emit(m, pos, 0, d, 0);
+                        }
+                        base_t += cnt;
+                        if (h.ld == GC_LD_IU) base_d += (uint32_t)h.cg * iu_useful(wd);
+                    }
+                    break;
+                case 2:
+                    for (int i = 0; i < 4; i++) {
+                        const uint32_t byte = (wd >> (8 * i)) & 0xFFu;
+                        const uint32_t b = byte & 63u, F = 8u << (byte >> 6);
+                        uint32_t m;
+                        if (boundary(base_t, F, m)) emit(m, 4u * w + (uint32_t)i, m * TT - base_t, base_d, 0);
+                        base_t += F;
+                        base_d += (uint64_t)F * b;
+                    }
+                    break;
+                default: {
+                    const uint32_t t0 = 32u * w;
+                    if (t0 > 0u && t0 % TT == 0u && t0 / TT < ntiles) emit(t0 / TT, w, 0, base_d, base_e);
+                    base_d += 32u * min(wd & 63u, 32u);
+                    base_e += pfd_exc_words(wd, (int)t.k, h.pfd_pos);
+                    break;
+                }
+                }
+            }
+        }
+    }
+}
 // ===========================================================================
 // Decode kernels.
 
 enum : int { kClsSim = 0, kClsGscU = 1, kClsGscB = 2, kClsAfor = 3, kClsPfd = 4 };
-
-template <int TILE, int CLS>
-struct DecSmem {
-    static constexpr int TTM = TILE / 4;                    // tuples per tile at k = 4
-    static constexpr int R = TILE / (4 * kThreads);          // output rounds
-    static constexpr int NREC = CLS == kClsPfd ? 1 : TTM;
-    static constexpr int NCTRL = CLS == kClsSim ? TTM / 8 + 8 : CLS == kClsGscU ? TTM + 8 : 1;
-    static constexpr int NGAP = CLS == kClsPfd ? TILE : 1;
-    static constexpr int NEXC = CLS == kClsPfd ? TILE / 4 : 1;
-    static constexpr int NBLK = CLS == kClsPfd ? 64 : 1;
-    uint32_t rec[NREC];      // per tuple: component bit offset << 6 | width
-    uint32_t ctrl[NCTRL];
-    uint32_t gaps[NGAP];
-    uint32_t exc[NEXC];
-    uint32_t blk_off[NBLK], blk_exc[NBLK], blk_desc[NBLK];
-    uint32_t wtot[R * kWaves];
-    uint32_t wpre[R * kWaves];
-    uint32_t tmp[kWaves];
-    uint32_t item, bad, prefix, dbase, b0, excw, exc_staged;
-};
 
 struct TileCtx {
     const uint32_t *S;
@@ -555,240 +468,71 @@ struct TileCtx {
 
 __device__ __forceinline__ uint32_t rec_pack(uint32_t rel, uint32_t bw) { return (rel << 6) | bw; }
 
-// ---- Group-Simple: selector-stationary record scatter --------------------
-template <int TILE>
-__device__ void prologue_sim(const TileCtx &c, DecSmem<TILE, kClsSim> &sm) {
-    using SM = DecSmem<TILE, kClsSim>;
-    const int tid = threadIdx.x;
-    const uint32_t S_total = c.D >> c.lk;
-    const uint32_t s_first = c.st.unit, sub0 = c.st.sub;
-    const uint32_t s_end = c.has_en ? c.en.unit + (c.en.sub ? 1u : 0u) : S_total;
-    const uint32_t nsel = s_end - s_first;
-    const uint32_t cw0 = s_first >> 3, cw1 = (s_end + 7u) >> 3;
-    const bool rng_ok = s_end <= S_total && s_end > s_first && nsel <= c.TT + 1u && cw1 <= c.C &&
-                        cw1 - cw0 <= (uint32_t)SM::NCTRL;
-    if (!rng_ok) {
-        if (tid == 0) sm.bad = kErrRange;
-    } else {
-        for (uint32_t i = (uint32_t)tid; i < cw1 - cw0; i += kThreads) sm.ctrl[i] = c.ctrl[cw0 + i];
+// Fills the tile context of tile m (global tile gi) of list L from the
+// host's header words; false if the stream's header disagrees or the locate
+// pass did not reach the tile in this run.
+__device__ __forceinline__ bool tile_ctx(const DecodeArgs &a, const ListDesc &L, uint32_t m, uint32_t gi,
+                                         uint32_t tile, uint32_t loc_tag, TileCtx &c) {
+    c.S = L.stream;
+    c.n = L.n;
+    c.C = L.C;
+    c.D = L.D;
+    bool ok = header_ok(L, c.S[0], c.S[1], c.S[2], c.S[3], c.h);
+    if (!header_fields(L.w0, c.h)) ok = false;
+    c.k = (uint32_t)c.h.k;
+    c.lk = (uint32_t)c.h.lk;
+    c.T = (c.n + c.k - 1u) >> c.lk;
+    c.TT = tile >> c.lk;
+    c.t0 = m * c.TT;
+    c.i0 = m * tile;
+    ok = ok && c.i0 < c.n;
+    c.ntup = ok ? min(c.TT, c.T - c.t0) : 0u;
+    c.nint = ok ? min(tile, c.n - c.i0) : 0u;
+    c.ctrl = c.S + 4;
+    c.data = c.S + 4 + c.C;
+    c.has_en = m + 1u < L.ntiles;
+    c.st = TileInfo{};
+    c.en = TileInfo{};
+    if (m > 0u) {
+        c.st = a.tiles[gi];
+        ok = ok && c.st.tag == loc_tag;
     }
-    if (tid == 0) sm.dbase = s_first;
-    __syncthreads();
-    constexpr int SPT = (SM::TTM + 1 + kThreads - 1) / kThreads;
-    uint32_t sel[SPT];
-    uint32_t sum = 0;
-    const bool go = !sm.bad;
-#pragma unroll
-    for (int j = 0; j < SPT; j++) {
-        const uint32_t i = (uint32_t)tid * SPT + (uint32_t)j;
-        uint32_t s = 15u, cnt = 0;
-        if (go && i < nsel) {
-            const uint32_t g = s_first + i;
-            s = (sm.ctrl[(g >> 3) - cw0] >> ((g & 7u) * 4u)) & 15u;
-            const uint32_t j0 = i == 0u ? sub0 : 0u;
-            const uint32_t num = s < 10u ? sim_num(s) : 0u;
-            if (s >= 10u || num <= j0) {
-                sm.bad = kErrSelector;
-                s = 15u;
-            } else {
-                cnt = num - j0;
-            }
-        }
-        sel[j] = s;
-        sum += cnt;
+    if (c.has_en) {
+        c.en = a.tiles[gi + 1u];
+        ok = ok && c.en.tag == loc_tag;
     }
-    uint32_t total;
-    uint32_t run = block_excl_scan(sum, sm.tmp, total);
-    if (tid == 0 && go && total < c.ntup) sm.bad = kErrCount;
-#pragma unroll
-    for (int j = 0; j < SPT; j++) {
-        const uint32_t i = (uint32_t)tid * SPT + (uint32_t)j;
-        if (sel[j] < 10u) {
-            const uint32_t bw = sim_bw(sel[j]);
-            const uint32_t j0 = i == 0u ? sub0 : 0u;
-            const uint32_t cnt = sim_num(sel[j]) - j0;
-            const uint32_t lim = min(cnt, max(c.ntup, run) - run);   // 0 once run >= ntup
-            for (uint32_t jj = 0; jj < lim; jj++) sm.rec[run + jj] = rec_pack(32u * i + (j0 + jj) * bw, bw);
-            run += cnt;
-        }
-    }
+    return ok;
 }
 
-// ---- Group-Scheme with unary descriptors (complete or incomplete) --------
-template <int TILE>
-__device__ void prologue_gscu(const TileCtx &c, DecSmem<TILE, kClsGscU> &sm) {
-    using SM = DecSmem<TILE, kClsGscU>;
-    const int tid = threadIdx.x;
-    const uint32_t cg = (uint32_t)c.h.cg, umax = 32u / cg;
-    const bool iu = c.h.ld == GC_LD_IU;
-    const uint32_t p0 = c.st.unit;
-    const uint32_t p1 = c.has_en ? c.en.unit : 32u * c.C;
-    const uint32_t cw0 = p0 >> 5, cw1 = (p1 + 31u) >> 5;
-    const uint32_t nctrl = cw1 - cw0;
-    const bool rng_ok = p1 >= p0 && cw1 <= c.C && nctrl <= (uint32_t)SM::NCTRL;
-    if (!rng_ok) {
-        if (tid == 0) sm.bad = kErrRange;
-    } else {
-        for (uint32_t i = (uint32_t)tid; i < nctrl; i += kThreads) {
-            // only bits in [p0, p1) belong to the tile: the others read as 1
-            const uint32_t gw = cw0 + i;
-            uint32_t v = c.ctrl[gw];
-            if (gw == cw0 && (p0 & 31u)) v |= (1u << (p0 & 31u)) - 1u;
-            if (gw == (p1 >> 5) && (p1 & 31u)) v |= ~((1u << (p1 & 31u)) - 1u);
-            sm.ctrl[i] = v;
-        }
-    }
-    const uint64_t abs0 = iu ? c.st.data : (uint64_t)cg * p0;
-    const uint32_t dbase = (uint32_t)(abs0 >> 5);
-    if (tid == 0) sm.dbase = dbase;
-    __syncthreads();
-    const uint32_t nw = sm.bad ? 0u : nctrl;
-    const uint32_t wpt = (nw + kThreads - 1u) / kThreads;
-    const uint32_t wl0 = min((uint32_t)tid * wpt, nw), wl1 = min(wl0 + wpt, nw);
-    // where this thread's first code starts: after the last terminator of the
-    // tile's earlier words, else at p0
-    uint32_t start0 = p0;
-    if (wl0 < wl1)
-        for (uint32_t wl = wl0; wl-- > 0u;) {
-            const uint32_t z = ~sm.ctrl[wl];
-            if (z) {
-                start0 = 32u * (cw0 + wl) + 32u - (uint32_t)__builtin_clz(z);
-                break;
-            }
-        }
-    uint32_t cnt = 0, usum = 0;
-    {
-        uint32_t nxt = start0;
-        for (uint32_t wl = wl0; wl < wl1; wl++) {
-            uint32_t z = ~sm.ctrl[wl];
-            cnt += (uint32_t)__builtin_popcount(z);
-            while (z) {
-                const uint32_t zp = 32u * (cw0 + wl) + (uint32_t)__builtin_ctz(z);
-                z &= z - 1u;
-                const uint32_t start = iu ? max(nxt, zp & ~7u) : nxt;
-                const uint32_t u = zp - start + 1u;
-                if (u > umax) sm.bad = kErrUnary;
-                usum += u;
-                nxt = zp + 1u;
-            }
-        }
-    }
-    uint32_t tcnt, tus;
-    const uint32_t xc = block_excl_scan(cnt, sm.tmp, tcnt);
-    const uint32_t xu = block_excl_scan(iu ? usum : 0u, sm.tmp, tus);
-    if (tid == 0 && !sm.bad && tcnt < c.ntup) sm.bad = kErrCount;
-    uint32_t nxt = start0, t = xc, us = xu;
-    const uint32_t rel0 = (uint32_t)(abs0 & 31u);
-    for (uint32_t wl = wl0; wl < wl1 && t < c.ntup; wl++) {
-        uint32_t z = ~sm.ctrl[wl];
-        while (z && t < c.ntup) {
-            const uint32_t zp = 32u * (cw0 + wl) + (uint32_t)__builtin_ctz(z);
-            z &= z - 1u;
-            const uint32_t start = iu ? max(nxt, zp & ~7u) : nxt;
-            const uint32_t u = min(zp - start + 1u, umax);
-            const uint32_t rel = iu ? rel0 + cg * us : (uint32_t)((uint64_t)cg * start - 32ull * dbase);
-            sm.rec[t] = rec_pack(rel, cg * u);
-            t++;
-            us += u;
-            nxt = zp + 1u;
-        }
-    }
+// Wave-uniform value, so the compiler keeps what depends on it in scalar
+// registers.
+__device__ __forceinline__ uint32_t uniform(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+
+// The list of tile gi of a launch.
+__device__ __forceinline__ ListDesc tile_list(const DecodeArgs &a, uint32_t gi) {
+    return a.lists ? a.lists[a.tile_list[gi]] : a.single;
 }
 
-// ---- Group-Scheme with binary descriptors ---------------------------------
-template <int TILE>
-__device__ void prologue_gscb(const TileCtx &c, DecSmem<TILE, kClsGscB> &sm) {
-    using SM = DecSmem<TILE, kClsGscB>;
-    const int tid = threadIdx.x;
-    const uint32_t cg = (uint32_t)c.h.cg;
-    const BinUnit bu = bin_unit(c.h.cg);
-    constexpr int TPT = SM::TTM / kThreads;
-    uint32_t bw[TPT];
-    uint32_t sum = 0;
-    bool bad = false;
-#pragma unroll
-    for (int j = 0; j < TPT; j++) {
-        const uint32_t tt = (uint32_t)tid * TPT + (uint32_t)j;
-        uint32_t b = 0;
-        if (tt < c.ntup) {
-            const uint32_t bit = bin_field_bit(c.t0 + tt, bu);
-            if ((bit >> 5) >= c.C) bad = true;
-            else b = cg * (((c.ctrl[bit >> 5] >> (bit & 31u)) & mask_of(bu.fb)) + 1u);
-        }
-        bw[j] = b;
-        sum += b;
-    }
-    if (bad) sm.bad = kErrRange;
-    const uint64_t abs0 = c.st.data;
-    if (tid == 0) sm.dbase = (uint32_t)(abs0 >> 5);
-    uint32_t total;
-    uint32_t run = block_excl_scan(sum, sm.tmp, total) + (uint32_t)(abs0 & 31u);
-#pragma unroll
-    for (int j = 0; j < TPT; j++) {
-        const uint32_t tt = (uint32_t)tid * TPT + (uint32_t)j;
-        if (tt < c.ntup) sm.rec[tt] = rec_pack(run, bw[j]);
-        run += bw[j];
-    }
-}
+// ===========================================================================
+// Group-PFD: one workgroup per tile.
 
-// ---- Group-AFOR: frame-stationary record scatter ---------------------------
 template <int TILE>
-__device__ void prologue_afor(const TileCtx &c, DecSmem<TILE, kClsAfor> &sm) {
-    using SM = DecSmem<TILE, kClsAfor>;
-    const int tid = threadIdx.x;
-    const uint32_t f0 = c.st.unit, sub0 = c.st.sub;
-    const uint32_t nfr = min(c.TT / 8u + 2u, 4u * c.C > f0 ? 4u * c.C - f0 : 0u);
-    constexpr int FPT = (SM::TTM / 8 + 2 + kThreads - 1) / kThreads;
-    uint32_t cnt[FPT], bb[FPT];
-    uint32_t csum = 0, bsum = 0;
-#pragma unroll
-    for (int j = 0; j < FPT; j++) {
-        const uint32_t i = (uint32_t)tid * FPT + (uint32_t)j;
-        cnt[j] = bb[j] = 0u;
-        if (i < nfr) {
-            const uint32_t f = f0 + i;
-            const uint32_t byte = (c.ctrl[f >> 2] >> (8u * (f & 3u))) & 0xFFu;
-            uint32_t b = byte & 63u;
-            const uint32_t cls = byte >> 6;
-            if (cls == 3u || b > 32u) {
-                sm.bad = kErrFrame;
-                b = 0;
-            }
-            const uint32_t F = cls == 0u ? 8u : cls == 1u ? 16u : 32u;
-            const uint32_t j0 = i == 0u ? sub0 : 0u;
-            if (j0 >= F) sm.bad = kErrFrame;
-            else cnt[j] = F - j0;
-            bb[j] = b;
-            if (i == 0u) sm.b0 = b;
-            csum += cnt[j];
-            bsum += F * b;
-        }
-    }
-    uint32_t tc, tb;
-    uint32_t st_t = block_excl_scan(csum, sm.tmp, tc);
-    uint32_t off = block_excl_scan(bsum, sm.tmp, tb);
-    if (tid == 0 && !sm.bad && tc < c.ntup) sm.bad = kErrCount;
-    const uint64_t fdata0 = c.st.data;
-    const uint32_t dbase = (uint32_t)((fdata0 + (uint64_t)sub0 * sm.b0) >> 5);
-    if (tid == 0) sm.dbase = dbase;
-    const uint32_t frel0 = (uint32_t)(fdata0 - 32ull * dbase);
-#pragma unroll
-    for (int j = 0; j < FPT; j++) {
-        const uint32_t i = (uint32_t)tid * FPT + (uint32_t)j;
-        const uint32_t b = bb[j];
-        const uint32_t j0 = i == 0u ? sub0 : 0u;
-        const uint32_t frel = frel0 + off + j0 * b;
-        const uint32_t lim = min(cnt[j], max(c.ntup, st_t) - st_t);   // 0 once st_t >= ntup
-        for (uint32_t jj = 0; jj < lim; jj++) sm.rec[st_t + jj] = rec_pack(frel + jj * b, b);
-        st_t += cnt[j];
-        off += (cnt[j] ? cnt[j] + j0 : 0u) * b;
-    }
-}
+struct PfdSmem {
+    static constexpr int R = TILE / (4 * kThreads);          // output rounds
+    static constexpr int NEXC = TILE / 4;
+    uint32_t gaps[TILE];
+    uint32_t exc[NEXC];
+    uint32_t blk_off[64], blk_exc[64], blk_desc[64];
+    uint32_t wtot[R * kWaves];
+    uint32_t wpre[R * kWaves];
+    uint32_t tmp[kWaves];
+    uint32_t bad, dbase, excw, exc_staged;
+};
 
 // ---- Group-PFD: per-block descriptors, exceptions staged in LDS ------------
 template <int TILE>
-__device__ void prologue_pfd(const TileCtx &c, DecSmem<TILE, kClsPfd> &sm, uint64_t stream_words) {
-    using SM = DecSmem<TILE, kClsPfd>;
+__device__ void prologue_pfd(const TileCtx &c, PfdSmem<TILE> &sm, uint64_t stream_words) {
+    using SM = PfdSmem<TILE>;
     const int tid = threadIdx.x;
     const uint32_t k = c.k;
     const uint32_t nb = (c.ntup + 31u) >> 5;
@@ -839,7 +583,7 @@ __device__ void prologue_pfd(const TileCtx &c, DecSmem<TILE, kClsPfd> &sm, uint6
 }
 
 template <int TILE>
-__device__ void patch_pfd(const TileCtx &c, DecSmem<TILE, kClsPfd> &sm) {
+__device__ void patch_pfd(const TileCtx &c, PfdSmem<TILE> &sm) {
     const int tid = threadIdx.x;
     const uint32_t k = c.k, lk = c.lk;
     const uint32_t nb = (c.ntup + 31u) >> 5;
@@ -908,64 +652,23 @@ __device__ void patch_pfd(const TileCtx &c, DecSmem<TILE, kClsPfd> &sm) {
     }
 }
 
-struct DecProbe {
-    const unsigned long long *flags;
-    uint32_t epoch;
-    unsigned long long f;
-    uint32_t acc;
-    __device__ int state(uint32_t j) {
-        f = load_acq64(&flags[j]);
-        const uint32_t stt = (uint32_t)(f >> 32) & 3u;
-        return ((uint32_t)(f >> 34) == epoch) ? (int)stt : 0;
-    }
-    __device__ void accumulate(bool take, uint32_t) { acc += wave_sum(take ? (uint32_t)f : 0u); }
-};
 
-template <int TILE, int CLS>
-__device__ void decode_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, uint32_t epoch,
-                            uint32_t loc_tag, DecSmem<TILE, CLS> &sm) {
-    using SM = DecSmem<TILE, CLS>;
-    constexpr int R = SM::R;
+// Decodes tile m (global tile gi) of a Group-PFD list.  SUM: store only the
+// sum of the tile's gaps in carry[gi]; otherwise write the tile's output,
+// prefix-summed from carry[gi] for a delta list.
+template <int TILE, bool SUM>
+__device__ void pfd_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, uint32_t gi, uint32_t loc_tag,
+                         PfdSmem<TILE> &sm) {
+    constexpr int R = PfdSmem<TILE>::R;
     const int tid = threadIdx.x;
+    HeaderFields hl;
+    const bool delta = header_fields(L.w0, hl) && hl.delta;
+    const uint32_t carry0 = (!SUM && delta && L.ntiles > 1u) ? a.carry[gi] : 0u;
     TileCtx c;
-    c.S = L.stream;
-    const uint32_t w0 = c.S[0];
-    c.n = c.S[1];
-    c.C = c.S[2];
-    c.D = c.S[3];
-    bool ok = header_ok(L, w0, c.n, c.C, c.D, c.h);
-    c.k = (uint32_t)c.h.k;
-    c.lk = (uint32_t)c.h.lk;
-    c.T = (c.n + c.k - 1u) >> c.lk;
-    c.TT = (uint32_t)TILE >> c.lk;
-    c.t0 = m * c.TT;
-    c.i0 = m * (uint32_t)TILE;
-    ok = ok && c.i0 < c.n;
-    c.ntup = ok ? min(c.TT, c.T - c.t0) : 0u;
-    c.nint = ok ? min((uint32_t)TILE, c.n - c.i0) : 0u;
-    c.ctrl = c.S + 4;
-    c.data = c.S + 4 + c.C;
-    c.has_en = m + 1u < L.ntiles;
-    c.st = TileInfo{};
-    c.en = TileInfo{};
-    if (m > 0u) {
-        c.st = a.tiles[L.tile_base + m];
-        ok = ok && c.st.tag == loc_tag;
-    }
-    if (c.has_en) {
-        c.en = a.tiles[L.tile_base + m + 1u];
-        ok = ok && c.en.tag == loc_tag;
-    }
+    const bool ok = tile_ctx(a, L, m, gi, (uint32_t)TILE, loc_tag, c);
     if (tid == 0) sm.bad = ok ? 0u : kErrLocate;
     __syncthreads();
-
-    if (!sm.bad) {
-        if constexpr (CLS == kClsSim) prologue_sim<TILE>(c, sm);
-        else if constexpr (CLS == kClsGscU) prologue_gscu<TILE>(c, sm);
-        else if constexpr (CLS == kClsGscB) prologue_gscb<TILE>(c, sm);
-        else if constexpr (CLS == kClsAfor) prologue_afor<TILE>(c, sm);
-        else prologue_pfd<TILE>(c, sm, L.stream_words);
-    }
+    if (!sm.bad) prologue_pfd<TILE>(c, sm, L.stream_words);
     __syncthreads();
 
     // ---- unpack: four consecutive integers per thread and round ------------
@@ -975,61 +678,57 @@ __device__ void decode_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, 
     const uint32_t nrow = Dk > dbase ? Dk - dbase : 0u;   // data rows from dbase on
     const uint32_t kq = c.k >> 2;                          // 16-byte chunks per row
     const u32x4 *rows = reinterpret_cast<const u32x4 *>(c.data) + (size_t)dbase * kq;
-    uint32_t v[R][4];
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const uint32_t q = (uint32_t)(r * kThreads + tid);
-        v[r][0] = v[r][1] = v[r][2] = v[r][3] = 0u;
+        u32x4 v = {0u, 0u, 0u, 0u};
         if (!bad && 4u * q < c.nint) {
             const uint32_t t = q >> (c.lk - 2u);
             const uint32_t cq = q & (kq - 1u);
-            uint32_t O, bw;
-            if constexpr (CLS == kClsPfd) {
-                const uint32_t bi = t >> 5, desc = sm.blk_desc[bi];
-                bw = desc & 63u;
-                O = 32u * sm.blk_off[bi] + (t & 31u) * bw;
-            } else {
-                const uint32_t rc = sm.rec[t];
-                O = rc >> 6;
-                bw = rc & 63u;
-            }
+            const uint32_t bi = t >> 5, desc = sm.blk_desc[bi];
+            const uint32_t bw = desc & 63u;
+            const uint32_t O = 32u * sm.blk_off[bi] + (t & 31u) * bw;
             if (bw && nrow) {
                 const uint32_t wi = min(O >> 5, nrow - 1u), sh = O & 31u;
                 const uint32_t M = mask_of(bw);
                 const u32x4 lo = rows[(size_t)wi * kq + cq];
                 u32x4 hi = {0u, 0u, 0u, 0u};
                 if (sh + bw > 32u) hi = rows[(size_t)min(wi + 1u, nrow - 1u) * kq + cq];
-                v[r][0] = funnel(hi.x, lo.x, sh) & M;
-                v[r][1] = funnel(hi.y, lo.y, sh) & M;
-                v[r][2] = funnel(hi.z, lo.z, sh) & M;
-                v[r][3] = funnel(hi.w, lo.w, sh) & M;
+                v.x = funnel(hi.x, lo.x, sh) & M;
+                v.y = funnel(hi.y, lo.y, sh) & M;
+                v.z = funnel(hi.z, lo.z, sh) & M;
+                v.w = funnel(hi.w, lo.w, sh) & M;
             }
         }
+        *reinterpret_cast<u32x4 *>(&sm.gaps[4u * q]) = v;
     }
+    __syncthreads();
+    if (!bad) patch_pfd<TILE>(c, sm);
+    __syncthreads();
+    uint32_t v[R][4];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const uint32_t q = (uint32_t)(r * kThreads + tid);
+        const u32x4 g = *reinterpret_cast<const u32x4 *>(&sm.gaps[4u * q]);
+        v[r][0] = g.x;
+        v[r][1] = g.y;
+        v[r][2] = g.z;
+        v[r][3] = g.w;
+    }
+    if (tid == 0 && sm.bad) latch(a.status, sm.bad);
 
-    // ---- Group-PFD: exceptions replace their slots -------------------------
-    if constexpr (CLS == kClsPfd) {
+    const int wave = tid >> 6, lane = tid & 63;
+    if constexpr (SUM) {
+        uint32_t s = 0;
 #pragma unroll
-        for (int r = 0; r < R; r++) {
-            const uint32_t q = (uint32_t)(r * kThreads + tid);
-            *reinterpret_cast<u32x4 *>(&sm.gaps[4u * q]) = u32x4{v[r][0], v[r][1], v[r][2], v[r][3]};
-        }
-        __syncthreads();
-        if (!bad) patch_pfd<TILE>(c, sm);
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-            const uint32_t q = (uint32_t)(r * kThreads + tid);
-            const u32x4 g = *reinterpret_cast<const u32x4 *>(&sm.gaps[4u * q]);
-            v[r][0] = g.x;
-            v[r][1] = g.y;
-            v[r][2] = g.z;
-            v[r][3] = g.w;
-        }
+        for (int r = 0; r < R; r++) s += v[r][0] + v[r][1] + v[r][2] + v[r][3];
+        uint32_t total;
+        (void)block_excl_scan(s, sm.tmp, total);
+        if (tid == 0) a.carry[gi] = total;
+        return;
     }
 
     // ---- prefix sum (delta lists) -------------------------------------------
-    const int wave = tid >> 6, lane = tid & 63;
     uint32_t add[R];
 #pragma unroll
     for (int r = 0; r < R; r++) add[r] = 0u;
@@ -1048,24 +747,11 @@ __device__ void decode_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, 
             const uint32_t x = (uint32_t)tid < (uint32_t)(R * kWaves) ? sm.wtot[tid] : 0u;
             const uint32_t inc = wave_incl_scan(x);
             if ((uint32_t)tid < (uint32_t)(R * kWaves)) sm.wpre[tid] = inc - x;
-            const uint32_t tile_sum = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
-            const uint32_t gi = L.tile_base + m;
-            const unsigned long long tag = (unsigned long long)(epoch & kEpochMask) << 34;
-            DecProbe pr{a.flags, epoch & kEpochMask, 0ull, 0u};
-            if (m == 0u) {
-                if (tid == 0) store_rel64(&a.flags[gi], tag | (2ull << 32) | tile_sum);
-            } else {
-                if (tid == 0) store_rel64(&a.flags[gi], tag | (1ull << 32) | tile_sum);
-                wave_lookback(gi, L.tile_base, pr, a.status);
-                if (tid == 0) store_rel64(&a.flags[gi], tag | (2ull << 32) | (uint32_t)(pr.acc + tile_sum));
-            }
-            if (tid == 0) sm.prefix = pr.acc;
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < R; r++) add[r] += sm.prefix + sm.wpre[r * kWaves + wave];
+        for (int r = 0; r < R; r++) add[r] += carry0 + sm.wpre[r * kWaves + wave];
     }
-    if (tid == 0 && sm.bad) latch(a.status, sm.bad);
 
     // ---- store ---------------------------------------------------------------
     uint32_t *out = L.out + c.i0;
@@ -1087,31 +773,404 @@ __device__ void decode_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, 
     }
 }
 
-template <int TILE, int CLS>
-__global__ __launch_bounds__(kThreads) void gc_decode_kernel(DecodeArgs a) {
-    __shared__ DecSmem<TILE, CLS> sm;
-    const uint32_t epoch = __hip_atomic_load(&a.state->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t loc_tag =
-        epoch_prev(__hip_atomic_load(&a.loc_state->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    for (;;) {
-        if (threadIdx.x == 0) sm.item = atomicAdd(&a.state->counter, 1u);
-        __syncthreads();
-        const uint32_t item = sm.item;
-        __syncthreads();
-        ListDesc L;
-        uint32_t m;
-        if (a.lists) {
-            if (item >= a.total_items) break;
-            L = a.lists[a.item_list[item]];
-            m = item - L.cls_base;
-        } else {
-            L = a.single;
-            if (item >= L.ntiles) break;
-            m = item;
+template <int TILE, bool SUM>
+__global__ __launch_bounds__(kThreads) void gc_pfd_kernel(DecodeArgs a) {
+    __shared__ PfdSmem<TILE> sm;
+    const uint32_t loc_tag = __hip_atomic_load(&a.loc_state->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t gi = a.lo + blockIdx.x;
+    const ListDesc L = tile_list(a, gi);
+    pfd_tile<TILE, SUM>(a, L, gi - L.tile_base, gi, loc_tag, sm);
+}
+
+// ===========================================================================
+// Wave-tile decode kernels (Group-Simple, Group-Scheme, Group-AFOR).
+//
+// Every wave64 decodes its own tile of TW integers with no workgroup
+// barrier: a workgroup is only a container of four independent waves, each
+// with its own slice of LDS for its tuple records.
+
+template <int TW, int CLS>
+struct WaveSmem {
+    static constexpr int TTM = TW / 4;
+    static constexpr int NCTRL = CLS == kClsSim ? TTM / 8 + 8 : CLS == kClsGscU ? TTM + 8 : 1;
+    uint32_t rec[TTM];
+    uint32_t ctrl[NCTRL];
+};
+
+// Orders a wave's LDS writes before its later LDS reads by other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t wave_any(bool b) { return __ballot(b) != 0ull ? 1u : 0u; }
+
+// ---- Group-Simple ---------------------------------------------------------
+template <int TW>
+__device__ uint32_t wprologue_sim(const TileCtx &c, WaveSmem<TW, kClsSim> &sm, uint32_t lane, uint32_t &dbase) {
+    using SM = WaveSmem<TW, kClsSim>;
+    const uint32_t S_total = c.D >> c.lk;
+    const uint32_t s_first = c.st.unit, sub0 = c.st.sub;
+    const uint32_t s_end = c.has_en ? c.en.unit + (c.en.sub ? 1u : 0u) : S_total;
+    const uint32_t nsel = s_end - s_first;
+    const uint32_t cw0 = s_first >> 3, cw1 = (s_end + 7u) >> 3;
+    if (!(s_end <= S_total && s_end > s_first && nsel <= c.TT + 1u && cw1 <= c.C &&
+          cw1 - cw0 <= (uint32_t)SM::NCTRL))
+        return kErrRange;
+    for (uint32_t i = lane; i < cw1 - cw0; i += 64u) sm.ctrl[i] = c.ctrl[cw0 + i];
+    wave_lds_sync();
+    dbase = s_first;
+    constexpr int SPT = (SM::TTM + 1 + 63) / 64;
+    uint32_t sel[SPT];
+    uint32_t sum = 0;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < SPT; j++) {
+        const uint32_t i = lane * SPT + (uint32_t)j;
+        uint32_t s = 15u, cnt = 0;
+        if (i < nsel) {
+            const uint32_t g = s_first + i;
+            s = (sm.ctrl[(g >> 3) - cw0] >> ((g & 7u) * 4u)) & 15u;
+            const uint32_t j0 = i == 0u ? sub0 : 0u;
+            const uint32_t num = s < 10u ? sim_num(s) : 0u;
+            if (s >= 10u || num <= j0) {
+                bad = true;
+                s = 15u;
+            } else {
+                cnt = num - j0;
+            }
         }
-        decode_tile<TILE, CLS>(a, L, m, epoch, loc_tag, sm);
+        sel[j] = s;
+        sum += cnt;
     }
-    finish_run(a.state, epoch);
+    const uint32_t inc = wave_incl_scan(sum);
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+    if (wave_any(bad)) return kErrSelector;
+    if (total < c.ntup) return kErrCount;
+    uint32_t run = inc - sum;
+#pragma unroll
+    for (int j = 0; j < SPT; j++) {
+        const uint32_t i = lane * SPT + (uint32_t)j;
+        if (sel[j] < 10u) {
+            const uint32_t bw = sim_bw(sel[j]);
+            const uint32_t j0 = i == 0u ? sub0 : 0u;
+            const uint32_t cnt = sim_num(sel[j]) - j0;
+            const uint32_t lim = min(cnt, max(c.ntup, run) - run);   // 0 once run >= ntup
+            for (uint32_t jj = 0; jj < lim; jj++) sm.rec[run + jj] = rec_pack(32u * i + (j0 + jj) * bw, bw);
+            run += cnt;
+        }
+    }
+    wave_lds_sync();
+    return 0;
+}
+
+// ---- Group-Scheme, unary descriptors ----------------------------------------
+template <int TW>
+__device__ uint32_t wprologue_gscu(const TileCtx &c, WaveSmem<TW, kClsGscU> &sm, uint32_t lane, uint32_t &dbase) {
+    using SM = WaveSmem<TW, kClsGscU>;
+    const uint32_t cg = (uint32_t)c.h.cg, umax = 32u / cg;
+    const bool iu = c.h.ld == GC_LD_IU;
+    const uint32_t p0 = c.st.unit;
+    const uint32_t p1 = c.has_en ? c.en.unit : 32u * c.C;
+    const uint32_t cw0 = p0 >> 5, cw1 = (p1 + 31u) >> 5;
+    const uint32_t nctrl = cw1 - cw0;
+    if (!(p1 >= p0 && cw1 <= c.C && nctrl <= (uint32_t)SM::NCTRL)) return kErrRange;
+    for (uint32_t i = lane; i < nctrl; i += 64u) {
+        // only bits in [p0, p1) belong to the tile: the others read as 1
+        const uint32_t gw = cw0 + i;
+        uint32_t v = c.ctrl[gw];
+        if (gw == cw0 && (p0 & 31u)) v |= (1u << (p0 & 31u)) - 1u;
+        if (gw == (p1 >> 5) && (p1 & 31u)) v |= ~((1u << (p1 & 31u)) - 1u);
+        sm.ctrl[i] = v;
+    }
+    const uint64_t abs0 = iu ? c.st.data : (uint64_t)cg * p0;
+    dbase = (uint32_t)(abs0 >> 5);
+    wave_lds_sync();
+    const uint32_t wpt = (nctrl + 63u) / 64u;
+    const uint32_t wl0 = min(lane * wpt, nctrl), wl1 = min(wl0 + wpt, nctrl);
+    // where this lane's first code starts: after the last terminator of the
+    // tile's earlier words, else at p0
+    uint32_t start0 = p0;
+    if (wl0 < wl1)
+        for (uint32_t wl = wl0; wl-- > 0u;) {
+            const uint32_t z = ~sm.ctrl[wl];
+            if (z) {
+                start0 = 32u * (cw0 + wl) + 32u - (uint32_t)__builtin_clz(z);
+                break;
+            }
+        }
+    uint32_t cnt = 0, usum = 0;
+    bool bad = false;
+    {
+        uint32_t nxt = start0;
+        for (uint32_t wl = wl0; wl < wl1; wl++) {
+            uint32_t z = ~sm.ctrl[wl];
+            cnt += (uint32_t)__builtin_popcount(z);
+            while (z) {
+                const uint32_t zp = 32u * (cw0 + wl) + (uint32_t)__builtin_ctz(z);
+                z &= z - 1u;
+                const uint32_t start = iu ? max(nxt, zp & ~7u) : nxt;
+                const uint32_t u = zp - start + 1u;
+                bad |= u > umax;
+                usum += u;
+                nxt = zp + 1u;
+            }
+        }
+    }
+    const uint32_t ic = wave_incl_scan(cnt), iu_s = wave_incl_scan(usum);
+    const uint32_t tcnt = (uint32_t)__builtin_amdgcn_readlane((int)ic, 63);
+    if (wave_any(bad)) return kErrUnary;
+    if (tcnt < c.ntup) return kErrCount;
+    uint32_t nxt = start0, t = ic - cnt, us = iu_s - usum;
+    const uint32_t rel0 = (uint32_t)(abs0 & 31u);
+    for (uint32_t wl = wl0; wl < wl1 && t < c.ntup; wl++) {
+        uint32_t z = ~sm.ctrl[wl];
+        while (z && t < c.ntup) {
+            const uint32_t zp = 32u * (cw0 + wl) + (uint32_t)__builtin_ctz(z);
+            z &= z - 1u;
+            const uint32_t start = iu ? max(nxt, zp & ~7u) : nxt;
+            const uint32_t u = min(zp - start + 1u, umax);
+            const uint32_t rel = iu ? rel0 + cg * us : (uint32_t)((uint64_t)cg * start - 32ull * dbase);
+            sm.rec[t] = rec_pack(rel, cg * u);
+            t++;
+            us += u;
+            nxt = zp + 1u;
+        }
+    }
+    wave_lds_sync();
+    return 0;
+}
+
+// ---- Group-Scheme, binary descriptors ---------------------------------------
+template <int TW>
+__device__ uint32_t wprologue_gscb(const TileCtx &c, WaveSmem<TW, kClsGscB> &sm, uint32_t lane, uint32_t &dbase) {
+    using SM = WaveSmem<TW, kClsGscB>;
+    const uint32_t cg = (uint32_t)c.h.cg;
+    const BinUnit bu = bin_unit(c.h.cg);
+    constexpr int TPT = SM::TTM / 64;
+    uint32_t bw[TPT];
+    uint32_t sum = 0;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < TPT; j++) {
+        const uint32_t tt = lane * TPT + (uint32_t)j;
+        uint32_t b = 0;
+        if (tt < c.ntup) {
+            const uint32_t bit = bin_field_bit(c.t0 + tt, bu);
+            if ((bit >> 5) >= c.C) bad = true;
+            else b = cg * (((c.ctrl[bit >> 5] >> (bit & 31u)) & mask_of(bu.fb)) + 1u);
+        }
+        bw[j] = b;
+        sum += b;
+    }
+    if (wave_any(bad)) return kErrRange;
+    const uint64_t abs0 = c.st.data;
+    dbase = (uint32_t)(abs0 >> 5);
+    uint32_t run = wave_incl_scan(sum) - sum + (uint32_t)(abs0 & 31u);
+#pragma unroll
+    for (int j = 0; j < TPT; j++) {
+        const uint32_t tt = lane * TPT + (uint32_t)j;
+        if (tt < c.ntup) sm.rec[tt] = rec_pack(run, bw[j]);
+        run += bw[j];
+    }
+    wave_lds_sync();
+    return 0;
+}
+
+// ---- Group-AFOR ---------------------------------------------------------------
+template <int TW>
+__device__ uint32_t wprologue_afor(const TileCtx &c, WaveSmem<TW, kClsAfor> &sm, uint32_t lane, uint32_t &dbase) {
+    using SM = WaveSmem<TW, kClsAfor>;
+    const uint32_t f0 = c.st.unit, sub0 = c.st.sub;
+    const uint32_t nfr = min(c.TT / 8u + 2u, 4u * c.C > f0 ? 4u * c.C - f0 : 0u);
+    constexpr int FPT = (SM::TTM / 8 + 2 + 63) / 64;
+    uint32_t cnt[FPT], bb[FPT];
+    uint32_t csum = 0, bsum = 0;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < FPT; j++) {
+        const uint32_t i = lane * FPT + (uint32_t)j;
+        cnt[j] = bb[j] = 0u;
+        if (i < nfr) {
+            const uint32_t f = f0 + i;
+            const uint32_t byte = (c.ctrl[f >> 2] >> (8u * (f & 3u))) & 0xFFu;
+            uint32_t b = byte & 63u;
+            const uint32_t cls = byte >> 6;
+            if (cls == 3u || b > 32u) {
+                bad = true;
+                b = 0;
+            }
+            const uint32_t F = cls == 0u ? 8u : cls == 1u ? 16u : 32u;
+            const uint32_t j0 = i == 0u ? sub0 : 0u;
+            if (j0 >= F) bad = true;
+            else cnt[j] = F - j0;
+            bb[j] = b;
+            csum += cnt[j];
+            bsum += F * b;
+        }
+    }
+    const uint32_t ic = wave_incl_scan(csum), ib = wave_incl_scan(bsum);
+    const uint32_t tc = (uint32_t)__builtin_amdgcn_readlane((int)ic, 63);
+    if (wave_any(bad)) return kErrFrame;
+    if (tc < c.ntup) return kErrCount;
+    const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)bb[0]);   // frame f0 is lane 0's first
+    const uint64_t fdata0 = c.st.data;
+    dbase = (uint32_t)((fdata0 + (uint64_t)sub0 * b0) >> 5);
+    const uint32_t frel0 = (uint32_t)(fdata0 - 32ull * dbase);
+    uint32_t st_t = ic - csum, off = ib - bsum;
+#pragma unroll
+    for (int j = 0; j < FPT; j++) {
+        const uint32_t i = lane * FPT + (uint32_t)j;
+        const uint32_t b = bb[j];
+        const uint32_t j0 = i == 0u ? sub0 : 0u;
+        const uint32_t frel = frel0 + off + j0 * b;
+        const uint32_t lim = min(cnt[j], max(c.ntup, st_t) - st_t);   // 0 once st_t >= ntup
+        for (uint32_t jj = 0; jj < lim; jj++) sm.rec[st_t + jj] = rec_pack(frel + jj * b, b);
+        st_t += cnt[j];
+        off += (cnt[j] ? cnt[j] + j0 : 0u) * b;
+    }
+    wave_lds_sync();
+    return 0;
+}
+
+// Four consecutive integers of quad q from the tuple records and data rows.
+__device__ __forceinline__ u32x4 extract_quad(uint32_t rc, uint32_t q, uint32_t kq, const u32x4 *rows,
+                                             uint32_t nrow) {
+    const uint32_t O = rc >> 6, bw = rc & 63u;
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (bw && nrow) {
+        const uint32_t cq = q & (kq - 1u);
+        const uint32_t wi = min(O >> 5, nrow - 1u), sh = O & 31u;
+        const uint32_t M = mask_of(bw);
+        const u32x4 lo = rows[(size_t)wi * kq + cq];
+        u32x4 hi = {0u, 0u, 0u, 0u};
+        if (sh + bw > 32u) hi = rows[(size_t)min(wi + 1u, nrow - 1u) * kq + cq];
+        v.x = funnel(hi.x, lo.x, sh) & M;
+        v.y = funnel(hi.y, lo.y, sh) & M;
+        v.z = funnel(hi.z, lo.z, sh) & M;
+        v.w = funnel(hi.w, lo.w, sh) & M;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void store_quad(uint32_t *out, uint32_t ii, uint32_t nint, bool vec, u32x4 o) {
+    if (ii >= nint) return;
+    if (vec && ii + 4u <= nint) {
+        __builtin_nontemporal_store(o, reinterpret_cast<u32x4 *>(out + ii));
+    } else {
+        out[ii] = o.x;
+        if (ii + 1u < nint) out[ii + 1u] = o.y;
+        if (ii + 2u < nint) out[ii + 2u] = o.z;
+        if (ii + 3u < nint) out[ii + 3u] = o.w;
+    }
+}
+
+template <int TW, int CLS, bool SUM>
+__device__ void wave_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, uint32_t gi, uint32_t loc_tag,
+                          WaveSmem<TW, CLS> &sm, uint32_t lane) {
+    constexpr int R = TW / 256;
+    HeaderFields hl;
+    const bool delta = header_fields(L.w0, hl) && hl.delta;
+    const uint32_t carry0 = (!SUM && delta && L.ntiles > 1u) ? a.carry[gi] : 0u;
+    TileCtx c;
+    const bool ok = tile_ctx(a, L, m, gi, (uint32_t)TW, loc_tag, c);
+    uint32_t dbase = 0, err = ok ? 0u : kErrLocate;
+    if (!err) {
+        if constexpr (CLS == kClsSim) err = wprologue_sim<TW>(c, sm, lane, dbase);
+        else if constexpr (CLS == kClsGscU) err = wprologue_gscu<TW>(c, sm, lane, dbase);
+        else if constexpr (CLS == kClsGscB) err = wprologue_gscb<TW>(c, sm, lane, dbase);
+        else err = wprologue_afor<TW>(c, sm, lane, dbase);
+    }
+    const bool good = err == 0u;
+    if (!good && lane == 0) latch(a.status, err);
+    const uint32_t Dk = c.D >> c.lk;
+    const uint32_t nrow = Dk > dbase ? Dk - dbase : 0u;
+    const uint32_t kq = c.k >> 2;
+    const u32x4 *rows = reinterpret_cast<const u32x4 *>(c.data) + (size_t)dbase * kq;
+    const uint32_t tsh = c.lk - 2u;
+
+    if constexpr (SUM) {
+        uint32_t s = 0;
+        if (good) {
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const uint32_t q = (uint32_t)r * 64u + lane;
+                if (4u * q < c.nint) {
+                    const u32x4 v = extract_quad(sm.rec[q >> tsh], q, kq, rows, nrow);
+                    s += v.x + v.y + v.z + v.w;
+                }
+            }
+        }
+        s = wave_sum(s);
+        if (lane == 0) a.carry[gi] = s;
+        return;
+    }
+
+    uint32_t *out = L.out + c.i0;
+    const bool vec = (reinterpret_cast<uintptr_t>(out) & 15u) == 0u;
+    if (c.h.delta) {
+        uint32_t carry = carry0;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const uint32_t q = (uint32_t)r * 64u + lane;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (good && 4u * q < c.nint) v = extract_quad(sm.rec[q >> tsh], q, kq, rows, nrow);
+            v.y += v.x;
+            v.z += v.y;
+            v.w += v.z;
+            const uint32_t inc = wave_incl_scan(v.w);
+            const uint32_t add = carry + inc - v.w;
+            store_quad(out, 4u * q, c.nint, vec, u32x4{v.x + add, v.y + add, v.z + add, v.w + add});
+            carry += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const uint32_t q = (uint32_t)r * 64u + lane;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (good && 4u * q < c.nint) v = extract_quad(sm.rec[q >> tsh], q, kq, rows, nrow);
+            store_quad(out, 4u * q, c.nint, vec, v);
+        }
+    }
+}
+
+template <int TW, int CLS, bool SUM>
+__global__ __launch_bounds__(kThreads) void gc_wave_kernel(DecodeArgs a) {
+    __shared__ WaveSmem<TW, CLS> sm[kWaves];
+    const uint32_t wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63u;
+    const uint32_t w = blockIdx.x * (uint32_t)kWaves + wave;
+    if (w >= a.count) return;
+    const uint32_t loc_tag = __hip_atomic_load(&a.loc_state->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t gi = a.lo + w;
+    const ListDesc L = tile_list(a, gi);
+    wave_tile<TW, CLS, SUM>(a, L, gi - L.tile_base, gi, loc_tag, sm[wave], lane);
+}
+
+// ===========================================================================
+// Carry scan: the tile sums of one delta list become exclusive carries, in
+// place, 1024 tiles per round.
+
+__global__ __launch_bounds__(kThreads) void gc_carry_scan(CarryArgs a) {
+    __shared__ uint32_t s_tmp[kWaves];
+    if (blockIdx.x >= a.count) return;
+    const ListDesc L = a.lists ? a.lists[a.scan_list[blockIdx.x]] : a.single;
+    uint32_t *cy = a.carry + L.tile_base;
+    uint32_t run = 0;
+    for (uint32_t b = 0; b < L.ntiles; b += 4u * kThreads) {
+        const uint32_t i = b + 4u * threadIdx.x;
+        uint32_t v[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) v[j] = i + j < L.ntiles ? cy[i + j] : 0u;
+        uint32_t total;
+        uint32_t p = run + block_excl_scan(v[0] + v[1] + v[2] + v[3], s_tmp, total);
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (i + j < L.ntiles) cy[i + j] = p;
+            p += v[j];
+        }
+        run += total;
+    }
 }
 
 // ===========================================================================
@@ -1128,54 +1187,62 @@ int codec_class(uint32_t w0) {
     }
 }
 
-int launch_locate(const LocateArgs &a, uint32_t grid, hipStream_t s) {
-    hipLaunchKernelGGL(gc_locate_kernel, dim3(grid), dim3(kThreads), 0, s, a);
+int launch_locate(const LocateArgs &a, hipStream_t s) {
+    if (!a.total_items) return 0;
+    hipLaunchKernelGGL(gc_locate_reduce, dim3(a.total_items), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(gc_locate_scan, dim3((a.total_scan + kWaves - 1) / kWaves), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(gc_locate_emit, dim3(a.total_items), dim3(kThreads), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <int TILE>
-static const void *decode_fn(int cls) {
+int launch_carry_scan(const CarryArgs &a, hipStream_t s) {
+    if (!a.count) return 0;
+    hipLaunchKernelGGL(gc_carry_scan, dim3(a.count), dim3(kThreads), 0, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int TW, bool SUM>
+static const void *wave_fn(int cls) {
     switch (cls) {
-    case kClsSim: return reinterpret_cast<const void *>(gc_decode_kernel<TILE, kClsSim>);
-    case kClsGscU: return reinterpret_cast<const void *>(gc_decode_kernel<TILE, kClsGscU>);
-    case kClsGscB: return reinterpret_cast<const void *>(gc_decode_kernel<TILE, kClsGscB>);
-    case kClsAfor: return reinterpret_cast<const void *>(gc_decode_kernel<TILE, kClsAfor>);
-    case kClsPfd: return reinterpret_cast<const void *>(gc_decode_kernel<TILE, kClsPfd>);
+    case kClsSim: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsSim, SUM>);
+    case kClsGscU: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsGscU, SUM>);
+    case kClsGscB: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsGscB, SUM>);
+    case kClsAfor: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsAfor, SUM>);
     default: return nullptr;
     }
 }
 
+template <bool SUM>
 static const void *decode_fn(int tile, int cls) {
+    if (cls == kClsPfd) {
+        switch (tile) {
+        case 2048: return reinterpret_cast<const void *>(gc_pfd_kernel<2048, SUM>);
+        case 4096: return reinterpret_cast<const void *>(gc_pfd_kernel<4096, SUM>);
+        case 8192: return reinterpret_cast<const void *>(gc_pfd_kernel<8192, SUM>);
+        default: return nullptr;
+        }
+    }
     switch (tile) {
-    case 2048: return decode_fn<2048>(cls);
-    case 4096: return decode_fn<4096>(cls);
-    case 8192: return decode_fn<8192>(cls);
+    case 1024: return wave_fn<1024, SUM>(cls);
+    case 2048: return wave_fn<2048, SUM>(cls);
+    case 4096: return wave_fn<4096, SUM>(cls);
     default: return nullptr;
     }
 }
 
-int launch_decode(int tile, int cls, const DecodeArgs &a, uint32_t grid, hipStream_t s) {
-    const void *fn = decode_fn(tile, cls);
+// Launches the sum pass (sum != 0) or the decode pass over a.count tiles.
+int launch_decode(int tile, int cls, bool sum, const DecodeArgs &a, hipStream_t s) {
+    if (!a.count) return 0;
+    const void *fn = sum ? decode_fn<true>(tile, cls) : decode_fn<false>(tile, cls);
     if (!fn) return -2;
+    const uint32_t per = cls == kClsPfd ? 1u : (uint32_t)kWaves;
     DecodeArgs arg = a;
     void *params[] = {&arg};
-    if (hipLaunchKernel(fn, dim3(grid), dim3(kThreads), params, 0, s) != hipSuccess) {
+    if (hipLaunchKernel(fn, dim3((a.count + per - 1) / per), dim3(kThreads), params, 0, s) != hipSuccess) {
         (void)hipGetLastError();
         return -1;
     }
     return 0;
-}
-
-int decode_occupancy(int tile, int cls, int *blocks_per_cu) {
-    const void *fn = decode_fn(tile, cls);
-    if (!fn) return -2;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kThreads, 0) == hipSuccess ? 0 : -1;
-}
-
-int locate_occupancy(int *blocks_per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gc_locate_kernel, kThreads, 0) == hipSuccess
-               ? 0
-               : -1;
 }
 
 }  // namespace gcdev

@@ -11,7 +11,8 @@ constexpr int kChunkWords = kThreads * 4;  // control words per locate work item
 constexpr int kClasses = 5;                 // decode kernel classes (codec families)
 
 // One list of a launch.  For a batch these live in a device table; for a
-// single list the runtime passes one by value.
+// single list the runtime passes one by value.  The header words come from
+// the host's copy of the header; kernels check the stream against them.
 struct ListDesc {
     const uint32_t *stream;   // 16-byte aligned; header at stream[0..3]
     uint32_t *out;            // n outputs
@@ -21,7 +22,9 @@ struct ListDesc {
     uint32_t tile_base;       // first entry of this list in the tile arrays
     uint32_t chunk_base;      // first entry in the locate arrays (ntiles > 1)
     uint32_t nchunks;         // locate work items (0 when ntiles <= 1)
-    uint32_t cls_base;        // first entry of this list in its decode class queue
+    uint32_t tile_ints;       // integers per decode tile for this list's codec class
+    uint32_t w0, C, D;        // header words 0, 2 and 3
+    uint32_t pad;
 };
 
 // Where tile m of a list starts, written by the locate pass.
@@ -34,15 +37,14 @@ struct TileInfo {
     uint64_t pad;
 };
 
-// Self-resetting state of one persistent kernel: work counter, finished
-// workgroups, and the run epoch that tags look-back flags.  The last
-// workgroup to finish clears the counters and advances the epoch, so a run
-// needs no memset (and can sit in a captured graph).
+// Epoch of the locate pass: its first kernel advances it, its last tags
+// every tile start with it, and the decode kernels accept only tile starts
+// of the current epoch (a tile that the locate pass never reached is caught
+// instead of decoded from a stale entry).  No counter needs resetting, so a
+// run can be replayed from a captured graph without a memset.
 struct RunState {
-    uint32_t counter;
-    uint32_t done;
     uint32_t epoch;
-    uint32_t pad;
+    uint32_t pad[3];
 };
 
 // Device status: the first error latched, with a detail code.
@@ -58,31 +60,46 @@ struct LocVal {
     uint64_t data;     // component data bits
 };
 
+// Locate runs as three fence-free kernels: reduce (one aggregate per control
+// chunk), scan (exclusive prefix of the aggregates within each list) and emit
+// (tile starts from the prefixes).  Kernel boundaries order them.
 struct LocateArgs {
     const ListDesc *lists;      // batch table, or nullptr for `single`
-    const uint32_t *item_list;  // work item -> list (batch)
+    const uint32_t *item_list;  // chunk work item -> list (batch)
+    const uint32_t *scan_list;  // scan work item -> list (batch)
     ListDesc single;
-    uint32_t total_items;       // batch; single computes its own
-    uint32_t tile_ints;
+    uint32_t total_items;       // chunk items (batch or single)
+    uint32_t total_scan;        // lists with chunks (batch); 1 for single
     TileInfo *tiles;
-    uint32_t *flags;            // per chunk: epoch << 2 | state
     LocVal *agg;                // per chunk aggregate
-    LocVal *incl;               // per chunk inclusive prefix
-    RunState *state;
+    LocVal *pre;                // per chunk exclusive prefix within its list
+    RunState *state;            // emit kernel: epoch that tags tile starts
     Status *status;
 };
 
+// One decode launch covers the tiles [lo, lo + count) of the tile arrays:
+// a wave (Group-PFD: a workgroup) per tile.
 struct DecodeArgs {
-    const ListDesc *lists;
-    const uint32_t *item_list;
+    const ListDesc *lists;      // batch table, or nullptr for `single`
+    const uint32_t *tile_list;  // batch: tile -> list
     ListDesc single;
-    uint32_t total_items;
-    uint32_t pad;
+    uint32_t lo;
+    uint32_t count;
     const TileInfo *tiles;
-    unsigned long long *flags;  // per tile: epoch:30 | state:2 | sum:32
-    RunState *state;
-    const RunState *loc_state;  // the locate kernel's state (for the tile tags)
+    uint32_t *carry;            // per tile: sum of its gaps (sum pass), then the
+                                // exclusive prefix of those sums in its list
+    const RunState *loc_state;
     Status *status;
+};
+
+// Carry scan: one workgroup per delta list of more than one tile.
+struct CarryArgs {
+    const ListDesc *lists;      // batch table, or nullptr for `single`
+    const uint32_t *scan_list;  // batch: work item -> list
+    ListDesc single;
+    uint32_t count;
+    uint32_t pad;
+    uint32_t *carry;
 };
 
 // Detail codes of device-side errors.
@@ -96,7 +113,6 @@ enum : uint32_t {
     kErrRange = 7,
     kErrLocate = 8,
     kErrCount = 9,
-    kErrTimeout = 10,
     kErrBitmap = 11,
 };
 

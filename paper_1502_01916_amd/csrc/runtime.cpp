@@ -1,7 +1,7 @@
 // runtime.cpp -- host runtime of libgc: device contexts, single-list decode,
-// batched decode plans (work-item tables per codec class, persistent launches,
-// hipGraph capture with one parallel branch per class), per-run kernel timing
-// and the autotuner that picks the tile size and occupancy.
+// batched decode plans (tile tables grouped by codec class, one hipGraph
+// branch per class), per-run kernel timing and the autotuner that picks the
+// tile sizes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,18 +20,23 @@
 
 namespace gcdev {
 int codec_class(uint32_t w0);
-int launch_locate(const LocateArgs &a, uint32_t grid, hipStream_t s);
-int launch_decode(int tile, int cls, const DecodeArgs &a, uint32_t grid, hipStream_t s);
-int decode_occupancy(int tile, int cls, int *blocks_per_cu);
-int locate_occupancy(int *blocks_per_cu);
+int launch_locate(const LocateArgs &a, hipStream_t s);
+int launch_carry_scan(const CarryArgs &a, hipStream_t s);
+int launch_decode(int tile, int cls, bool sum, const DecodeArgs &a, hipStream_t s);
 }  // namespace gcdev
 
 using namespace gcdev;
 
 namespace {
 
-constexpr int kDefaultTile = 2048;
-constexpr int kTiles[3] = {2048, 4096, 8192};
+constexpr int kDefaultWaveTile = 2048;
+constexpr int kDefaultPfdTile = 4096;
+constexpr int kWaveTiles[3] = {1024, 2048, 4096};
+constexpr int kPfdTiles[3] = {2048, 4096, 8192};
+constexpr int kClsPfd = 4;
+
+bool valid_wave_tile(uint32_t t) { return t == 1024 || t == 2048 || t == 4096; }
+bool valid_pfd_tile(uint32_t t) { return t == 2048 || t == 4096 || t == 8192; }
 
 #define HIP_OK(x)                         \
     do {                                  \
@@ -77,42 +82,40 @@ void dev_free(T *&p) {
     p = nullptr;
 }
 
-// Look-back and queue state of one launch sequence.
+// Device scratch of one launch sequence: the locate epoch, the tile starts,
+// the tile carries and the locate chunk aggregates and prefixes.
 struct Scratch {
-    RunState *state = nullptr;          // [0] locate, [1 + class] decode
+    RunState *state = nullptr;
     TileInfo *tiles = nullptr;
-    unsigned long long *tflags = nullptr;
-    uint32_t *cflags = nullptr;
-    LocVal *agg = nullptr, *incl = nullptr;
+    uint32_t *carry = nullptr;
+    LocVal *agg = nullptr, *pre = nullptr;
     size_t tiles_cap = 0, chunks_cap = 0;
 
     gc_status init_state() {
-        gc_status rc = dev_alloc(&state, 1 + kClasses);
+        gc_status rc = dev_alloc(&state, 1);
         if (rc) return rc;
-        std::vector<RunState> h(1 + kClasses, RunState{0, 0, 1, 0});
-        HIP_OK(hipMemcpy(state, h.data(), h.size() * sizeof(RunState), hipMemcpyHostToDevice));
+        const RunState h = {1u, {0u, 0u, 0u}};
+        HIP_OK(hipMemcpy(state, &h, sizeof(h), hipMemcpyHostToDevice));
         return GC_OK;
     }
     gc_status reserve(size_t ntiles, size_t nchunks) {
         if (ntiles > tiles_cap) {
             HIP_OK(hipDeviceSynchronize());
             dev_free(tiles);
-            dev_free(tflags);
+            dev_free(carry);
             const size_t cap = std::max(ntiles, tiles_cap * 2);
             gc_status rc = dev_alloc(&tiles, cap);
-            if (!rc) rc = dev_alloc(&tflags, cap);
+            if (!rc) rc = dev_alloc(&carry, cap);
             if (rc) return rc;
             tiles_cap = cap;
         }
         if (nchunks > chunks_cap) {
             HIP_OK(hipDeviceSynchronize());
-            dev_free(cflags);
             dev_free(agg);
-            dev_free(incl);
+            dev_free(pre);
             const size_t cap = std::max(nchunks, chunks_cap * 2);
-            gc_status rc = dev_alloc(&cflags, cap);
-            if (!rc) rc = dev_alloc(&agg, cap);
-            if (!rc) rc = dev_alloc(&incl, cap);
+            gc_status rc = dev_alloc(&agg, cap);
+            if (!rc) rc = dev_alloc(&pre, cap);
             if (rc) return rc;
             chunks_cap = cap;
         }
@@ -121,10 +124,9 @@ struct Scratch {
     void release() {
         dev_free(state);
         dev_free(tiles);
-        dev_free(tflags);
-        dev_free(cflags);
+        dev_free(carry);
         dev_free(agg);
-        dev_free(incl);
+        dev_free(pre);
         tiles_cap = chunks_cap = 0;
     }
 };
@@ -136,24 +138,34 @@ struct gc_ctx {
     int num_cus = 0;
     Status *status = nullptr;
     Scratch single;
-    int tile = kDefaultTile;
+    int tile_w = kDefaultWaveTile, tile_p = kDefaultPfdTile;
     std::mutex mu;
+};
+
+// Tiles are numbered class by class; within a class the delta lists of more
+// than one tile come first, so one launch range covers each pass.
+struct ClassRange {
+    uint32_t lo = 0;        // first tile of the class
+    uint32_t count = 0;     // tiles of the class
+    uint32_t sum = 0;       // leading tiles that need a tile sum
+    uint32_t scan_lo = 0;   // first entry of the class in the scan list
+    uint32_t scans = 0;     // lists to scan
 };
 
 struct gc_plan {
     gc_ctx *ctx = nullptr;
     size_t nlists = 0;
-    int tile = kDefaultTile;
-    uint32_t bpc = 0;                          // decode workgroups per CU (0 = max)
-    uint32_t grid_a = 0, grid_b[kClasses] = {};
-    uint32_t total_a = 0, total_b[kClasses] = {};
+    int tile_w = kDefaultWaveTile, tile_p = kDefaultPfdTile;
+    ClassRange cr[kClasses];
+    uint32_t total_a = 0, total_s = 0, total_t = 0, total_scan = 0;
     bool use_graph = false;
     std::vector<ListDesc> h_lists;             // pointers filled at upload
     std::vector<int> cls;                      // codec class per list
     std::vector<uint64_t> stream_off, out_off;
-    std::vector<uint32_t> item_a, item_b[kClasses];
+    std::vector<uint32_t> item_a, item_s;      // locate: chunk -> list, scan -> list
+    std::vector<uint32_t> tile_list, scan_list;
     ListDesc *d_lists = nullptr;
-    uint32_t *d_item_a = nullptr, *d_item_b[kClasses] = {};
+    uint32_t *d_item_a = nullptr, *d_item_s = nullptr, *d_tile_list = nullptr, *d_scan_list = nullptr;
     Scratch sc;
     const uint32_t *bound_streams = nullptr;
     uint32_t *bound_out = nullptr;
@@ -168,49 +180,49 @@ struct gc_plan {
 
 namespace {
 
-int occupancy_decode(int tile, int cls) {
-    int b = 0;
-    if (decode_occupancy(tile, cls, &b) != 0 || b < 1) b = 1;
-    return b;
-}
-
-int occupancy_locate() {
-    int b = 0;
-    if (locate_occupancy(&b) != 0 || b < 1) b = 1;
-    return b;
-}
-
-LocateArgs make_locate_args(const ListDesc *lists, const uint32_t *item_list, const ListDesc &single,
-                            uint32_t total, int tile, Scratch &sc, Status *st) {
+LocateArgs make_locate_args(const ListDesc *lists, const uint32_t *item_list, const uint32_t *scan_list,
+                            const ListDesc &single, uint32_t total, uint32_t total_scan, Scratch &sc, Status *st) {
     LocateArgs a;
     std::memset(&a, 0, sizeof(a));
     a.lists = lists;
     a.item_list = item_list;
+    a.scan_list = scan_list;
     a.single = single;
     a.total_items = total;
-    a.tile_ints = (uint32_t)tile;
+    a.total_scan = total_scan;
     a.tiles = sc.tiles;
-    a.flags = sc.cflags;
     a.agg = sc.agg;
-    a.incl = sc.incl;
+    a.pre = sc.pre;
     a.state = sc.state;
     a.status = st;
     return a;
 }
 
-DecodeArgs make_decode_args(const ListDesc *lists, const uint32_t *item_list, const ListDesc &single,
-                            uint32_t total, int cls, Scratch &sc, Status *st) {
+DecodeArgs make_decode_args(const ListDesc *lists, const uint32_t *tile_list, const ListDesc &single, uint32_t lo,
+                            uint32_t count, Scratch &sc, Status *st) {
     DecodeArgs a;
     std::memset(&a, 0, sizeof(a));
     a.lists = lists;
-    a.item_list = item_list;
+    a.tile_list = tile_list;
     a.single = single;
-    a.total_items = total;
+    a.lo = lo;
+    a.count = count;
     a.tiles = sc.tiles;
-    a.flags = sc.tflags;
-    a.state = sc.state + 1 + cls;
+    a.carry = sc.carry;
     a.loc_state = sc.state;
     a.status = st;
+    return a;
+}
+
+CarryArgs make_carry_args(const ListDesc *lists, const uint32_t *scan_list, const ListDesc &single, uint32_t count,
+                          Scratch &sc) {
+    CarryArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.lists = lists;
+    a.scan_list = scan_list;
+    a.single = single;
+    a.count = count;
+    a.carry = sc.carry;
     return a;
 }
 
@@ -220,30 +232,97 @@ uint32_t list_chunks(const HeaderFields &h, uint32_t n, uint32_t C, uint32_t D) 
     return std::max(1u, (nw + kChunkWords - 1u) / kChunkWords);
 }
 
-// Builds the per-list work tables of a plan for one tile size.
-void build_tables(gc_plan *p, const uint32_t *h_headers) {
+bool is_delta(uint32_t w0) {
+    HeaderFields h;
+    return header_fields(w0, h) && h.delta;
+}
+
+// A tile must hold at least 32 tuples: every control unit (selector,
+// unary code word, frame, block) spans at most 32 tuples, so the locate pass
+// meets at most one tile boundary per unit.
+int min_wave_tile(const gc_plan *p) {
+    int t = 1024;
+    for (size_t i = 0; i < p->nlists; i++) {
+        if (p->cls[i] == kClsPfd) continue;
+        HeaderFields h;
+        header_fields(p->h_lists[i].w0, h);
+        t = std::max(t, 32 << h.lk);
+    }
+    return t;
+}
+
+// Single-list view of list L for the per-list paths: its own tile range.
+DecodeArgs single_args(const ListDesc &L, Scratch &sc, Status *st) {
+    return make_decode_args(nullptr, nullptr, L, L.tile_base, L.ntiles, sc, st);
+}
+
+// Launches every pass of one list on stream s (the per-list paths).
+gc_status launch_one(const ListDesc &L, int cls, Scratch &sc, Status *st, hipStream_t s) {
+    if (L.ntiles > 1) {
+        LocateArgs a = make_locate_args(nullptr, nullptr, nullptr, L, L.nchunks, 1, sc, st);
+        if (launch_locate(a, s)) return GC_EDEVICE;
+    }
+    const int tile = (int)L.tile_ints;
+    const DecodeArgs d = single_args(L, sc, st);
+    if (L.ntiles > 1 && is_delta(L.w0)) {
+        if (launch_decode(tile, cls, true, d, s)) return GC_EDEVICE;
+        if (launch_carry_scan(make_carry_args(nullptr, nullptr, L, 1, sc), s)) return GC_EDEVICE;
+    }
+    if (launch_decode(tile, cls, false, d, s)) return GC_EDEVICE;
+    return GC_OK;
+}
+
+// Builds the tile tables of a plan for its tile sizes.
+void build_tables(gc_plan *p) {
+    p->tile_w = std::max(p->tile_w, min_wave_tile(p));
     p->item_a.clear();
-    for (auto &v : p->item_b) v.clear();
-    uint32_t tb = 0, cb = 0;
+    p->item_s.clear();
+    p->tile_list.clear();
+    p->scan_list.clear();
+    uint32_t cb = 0;
     for (size_t i = 0; i < p->nlists; i++) {
         ListDesc &L = p->h_lists[i];
-        L.ntiles = (uint32_t)((L.n + (uint64_t)p->tile - 1) / (uint64_t)p->tile);
-        L.tile_base = tb;
+        L.tile_ints = (uint32_t)(p->cls[i] == kClsPfd ? p->tile_p : p->tile_w);
+        L.ntiles = (uint32_t)((L.n + (uint64_t)L.tile_ints - 1) / (uint64_t)L.tile_ints);
         L.chunk_base = cb;
         L.nchunks = 0;
         if (L.ntiles > 1) {
             HeaderFields h;
-            header_fields(h_headers[4 * i], h);
-            L.nchunks = list_chunks(h, L.n, h_headers[4 * i + 2], h_headers[4 * i + 3]);
+            header_fields(L.w0, h);
+            L.nchunks = list_chunks(h, L.n, L.C, L.D);
         }
-        L.cls_base = (uint32_t)p->item_b[p->cls[i]].size();
         for (uint32_t c = 0; c < L.nchunks; c++) p->item_a.push_back((uint32_t)i);
-        for (uint32_t t = 0; t < L.ntiles; t++) p->item_b[p->cls[i]].push_back((uint32_t)i);
-        tb += L.ntiles;
+        if (L.nchunks) p->item_s.push_back((uint32_t)i);
         cb += L.nchunks;
     }
+    uint32_t tb = 0;
+    for (int c = 0; c < kClasses; c++) {
+        ClassRange &r = p->cr[c];
+        r = ClassRange{};
+        r.lo = tb;
+        r.scan_lo = (uint32_t)p->scan_list.size();
+        for (int pass = 0; pass < 2; pass++) {
+            for (size_t i = 0; i < p->nlists; i++) {
+                ListDesc &L = p->h_lists[i];
+                if (p->cls[i] != c || L.ntiles == 0) continue;
+                const bool summed = L.ntiles > 1 && is_delta(L.w0);
+                if (summed != (pass == 0)) continue;
+                L.tile_base = tb;
+                for (uint32_t m = 0; m < L.ntiles; m++) p->tile_list.push_back((uint32_t)i);
+                tb += L.ntiles;
+                if (summed) {
+                    r.sum += L.ntiles;
+                    p->scan_list.push_back((uint32_t)i);
+                }
+            }
+        }
+        r.count = tb - r.lo;
+        r.scans = (uint32_t)p->scan_list.size() - r.scan_lo;
+    }
     p->total_a = (uint32_t)p->item_a.size();
-    for (int c = 0; c < kClasses; c++) p->total_b[c] = (uint32_t)p->item_b[c].size();
+    p->total_s = (uint32_t)p->item_s.size();
+    p->total_t = tb;
+    p->total_scan = (uint32_t)p->scan_list.size();
 }
 
 void plan_free_graphs(gc_plan *p) {
@@ -257,7 +336,9 @@ void plan_free_device(gc_plan *p) {
     plan_free_graphs(p);
     dev_free(p->d_lists);
     dev_free(p->d_item_a);
-    for (auto &d : p->d_item_b) dev_free(d);
+    dev_free(p->d_item_s);
+    dev_free(p->d_tile_list);
+    dev_free(p->d_scan_list);
     p->sc.release();
 }
 
@@ -273,59 +354,64 @@ gc_status plan_upload(gc_plan *p, const uint32_t *d_streams, uint32_t *d_out) {
     return GC_OK;
 }
 
-// Allocates the device side of a plan for its current tile size.
-gc_status plan_materialize(gc_plan *p, const uint32_t *h_headers) {
-    plan_free_device(p);
-    build_tables(p, h_headers);
-    gc_status rc = dev_alloc(&p->d_lists, p->nlists);
-    if (!rc) rc = dev_alloc(&p->d_item_a, p->total_a);
-    for (int c = 0; c < kClasses && !rc; c++) rc = dev_alloc(&p->d_item_b[c], p->total_b[c]);
-    if (!rc) rc = p->sc.init_state();
-    uint32_t tiles = 0;
-    for (int c = 0; c < kClasses; c++) tiles += p->total_b[c];
-    if (!rc) rc = p->sc.reserve(tiles, p->total_a);
+template <typename T>
+gc_status upload_vec(T **d, const std::vector<T> &h) {
+    dev_free(*d);
+    gc_status rc = dev_alloc(d, h.size());
     if (rc) return rc;
-    if (p->total_a)
-        HIP_OK(hipMemcpy(p->d_item_a, p->item_a.data(), p->total_a * 4, hipMemcpyHostToDevice));
-    const uint32_t cus = (uint32_t)p->ctx->num_cus;
-    for (int c = 0; c < kClasses; c++) {
-        if (p->total_b[c])
-            HIP_OK(hipMemcpy(p->d_item_b[c], p->item_b[c].data(), p->total_b[c] * 4, hipMemcpyHostToDevice));
-        const uint32_t occ = (uint32_t)occupancy_decode(p->tile, c);
-        const uint32_t bpc = p->bpc ? std::min(p->bpc, occ) : occ;
-        p->grid_b[c] = std::max(1u, std::min(p->total_b[c], bpc * cus));
-    }
-    p->grid_a = std::max(1u, std::min(p->total_a, (uint32_t)occupancy_locate() * cus));
+    if (!h.empty()) HIP_OK(hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
     return GC_OK;
 }
 
-// Launches the locate kernel (which & 1) and the decode kernels (which & 2)
-// on stream s; with `fork` streams the decode classes run as parallel
+// Allocates the device side of a plan for its current tile sizes.
+gc_status plan_materialize(gc_plan *p) {
+    plan_free_graphs(p);
+    build_tables(p);
+    gc_status rc = GC_OK;
+    if (!p->d_lists) rc = dev_alloc(&p->d_lists, p->nlists);
+    if (!rc && !p->sc.state) rc = p->sc.init_state();
+    if (!rc) rc = upload_vec(&p->d_item_a, p->item_a);
+    if (!rc) rc = upload_vec(&p->d_item_s, p->item_s);
+    if (!rc) rc = upload_vec(&p->d_tile_list, p->tile_list);
+    if (!rc) rc = upload_vec(&p->d_scan_list, p->scan_list);
+    if (!rc) rc = p->sc.reserve(p->total_t, p->total_a);
+    return rc;
+}
+
+// Launches the locate kernels (which & 1) and the per-class decode passes
+// (which & 2) on stream s; with `fork` streams the classes run as parallel
 // branches that s waits for.
 gc_status plan_launch(gc_plan *p, hipStream_t s, int which, hipStream_t *fork = nullptr,
                       hipEvent_t *fev = nullptr) {
     ListDesc none;
     std::memset(&none, 0, sizeof(none));
     if (p->total_a && (which & 1)) {
-        LocateArgs a = make_locate_args(p->d_lists, p->d_item_a, none, p->total_a, p->tile, p->sc,
-                                        p->ctx->status);
-        if (launch_locate(a, p->grid_a, s)) return GC_EDEVICE;
+        LocateArgs a = make_locate_args(p->d_lists, p->d_item_a, p->d_item_s, none, p->total_a, p->total_s,
+                                        p->sc, p->ctx->status);
+        if (launch_locate(a, s)) return GC_EDEVICE;
     }
     if (!(which & 2)) return GC_OK;
     int nact = 0;
-    for (int c = 0; c < kClasses; c++) nact += p->total_b[c] ? 1 : 0;
+    for (int c = 0; c < kClasses; c++) nact += p->cr[c].count ? 1 : 0;
     const bool par = fork && nact > 1;
     if (par) HIP_OK(hipEventRecord(fev[kClasses], s));
     for (int c = 0; c < kClasses; c++) {
-        if (!p->total_b[c]) continue;
+        const ClassRange &r = p->cr[c];
+        if (!r.count) continue;
         hipStream_t cs = s;
         if (par) {
             cs = fork[c];
             HIP_OK(hipStreamWaitEvent(cs, fev[kClasses], 0));
         }
-        DecodeArgs d = make_decode_args(p->d_lists, p->d_item_b[c], none, p->total_b[c], c, p->sc,
-                                        p->ctx->status);
-        if (launch_decode(p->tile, c, d, p->grid_b[c], cs)) return GC_EDEVICE;
+        const int tile = c == kClsPfd ? p->tile_p : p->tile_w;
+        if (r.sum) {
+            DecodeArgs d = make_decode_args(p->d_lists, p->d_tile_list, none, r.lo, r.sum, p->sc, p->ctx->status);
+            if (launch_decode(tile, c, true, d, cs)) return GC_EDEVICE;
+            CarryArgs ca = make_carry_args(p->d_lists, p->d_scan_list + r.scan_lo, none, r.scans, p->sc);
+            if (launch_carry_scan(ca, cs)) return GC_EDEVICE;
+        }
+        DecodeArgs d = make_decode_args(p->d_lists, p->d_tile_list, none, r.lo, r.count, p->sc, p->ctx->status);
+        if (launch_decode(tile, c, false, d, cs)) return GC_EDEVICE;
         if (par) {
             HIP_OK(hipEventRecord(fev[c], cs));
             HIP_OK(hipStreamWaitEvent(s, fev[c], 0));
@@ -333,7 +419,6 @@ gc_status plan_launch(gc_plan *p, hipStream_t s, int which, hipStream_t *fork = 
     }
     return GC_OK;
 }
-
 gc_status capture_one(gc_plan *p, int which, hipGraph_t *graph, hipGraphExec_t *exec) {
     hipStream_t s, fork[kClasses];
     hipEvent_t fev[kClasses + 1];
@@ -390,13 +475,13 @@ gc_status plan_run(gc_plan *p, hipStream_t s) {
     return plan_launch(p, s, 3);
 }
 
-// ---- autotune cache: one JSON object {key: [tile, bpc], ...} -------------
+// ---- autotune cache: one JSON object {key: [tile, pfd_tile], ...} --------
 std::string cache_path() {
     const char *e = std::getenv("GC_AUTOTUNE_CACHE");
     return e ? std::string(e) : std::string();
 }
 
-bool cache_lookup(const std::string &key, int &tile, uint32_t &bpc) {
+bool cache_lookup(const std::string &key, int &tile, int &ptile) {
     const std::string path = cache_path();
     if (path.empty()) return false;
     std::ifstream f(path);
@@ -407,15 +492,15 @@ bool cache_lookup(const std::string &key, int &tile, uint32_t &bpc) {
     const std::string pat = "\"" + key + "\": [";
     const size_t at = s.find(pat);
     if (at == std::string::npos) return false;
-    int t = 0, b = 0;
-    if (std::sscanf(s.c_str() + at + pat.size(), "%d, %d", &t, &b) != 2) return false;
-    if (t != 2048 && t != 4096 && t != 8192) return false;
+    int t = 0, pt = 0;
+    if (std::sscanf(s.c_str() + at + pat.size(), "%d, %d", &t, &pt) != 2) return false;
+    if (!valid_wave_tile((uint32_t)t) || !valid_pfd_tile((uint32_t)pt)) return false;
     tile = t;
-    bpc = (uint32_t)b;
+    ptile = pt;
     return true;
 }
 
-void cache_store(const std::string &key, int tile, uint32_t bpc) {
+void cache_store(const std::string &key, int tile, int ptile) {
     const std::string path = cache_path();
     if (path.empty()) return;
     std::string s;
@@ -439,7 +524,7 @@ void cache_store(const std::string &key, int tile, uint32_t bpc) {
         pos = rb + 1;
     }
     char buf[64];
-    std::snprintf(buf, sizeof(buf), "[%d, %u]", tile, bpc);
+    std::snprintf(buf, sizeof(buf), "[%d, %d]", tile, ptile);
     entries.push_back("\"" + key + "\": " + buf);
     std::ofstream f(path);
     f << "{\n";
@@ -447,12 +532,12 @@ void cache_store(const std::string &key, int tile, uint32_t bpc) {
     f << "}\n";
 }
 
-std::string plan_key(const gc_plan *p, const uint32_t *h_headers) {
+std::string plan_key(const gc_plan *p) {
     uint64_t total = 0, per_cls[kClasses] = {};
     int lk = 2;
     for (size_t i = 0; i < p->nlists; i++) {
         HeaderFields h;
-        header_fields(h_headers[4 * i], h);
+        header_fields(p->h_lists[i].w0, h);
         per_cls[p->cls[i]] += p->h_lists[i].n;
         total += p->h_lists[i].n;
         lk = std::max(lk, h.lk);
@@ -469,29 +554,30 @@ std::string plan_key(const gc_plan *p, const uint32_t *h_headers) {
     return key;
 }
 
-gc_status autotune(gc_plan *p, const uint32_t *h_headers, const uint32_t *d_streams, uint32_t *d_out) {
-    const std::string key = plan_key(p, h_headers);
-    int best_tile = p->tile;
-    uint32_t best_bpc = 0;
-    if (cache_lookup(key, best_tile, best_bpc)) {
-        p->tile = best_tile;
-        p->bpc = best_bpc;
+gc_status autotune(gc_plan *p, const uint32_t *d_streams, uint32_t *d_out) {
+    const std::string key = plan_key(p);
+    int best_w = p->tile_w, best_p = p->tile_p;
+    if (cache_lookup(key, best_w, best_p)) {
+        p->tile_w = best_w;
+        p->tile_p = best_p;
         return GC_OK;
     }
+    bool has_pfd = false, has_wave = false;
+    for (size_t i = 0; i < p->nlists; i++) (p->cls[i] == kClsPfd ? has_pfd : has_wave) = true;
     hipEvent_t e0, e1;
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
     float best = 1e30f;
     gc_status rc = GC_OK;
-    for (int tile : kTiles) {
-        int occ = 1;
-        for (int c = 0; c < kClasses; c++) occ = std::max(occ, occupancy_decode(tile, c));
-        for (int bpc = occ; bpc >= 1 && !rc; bpc = bpc > 2 ? bpc - 2 : bpc - 1) {
-            p->tile = tile;
-            p->bpc = (uint32_t)bpc;
-            rc = plan_materialize(p, h_headers);
+    const int tw_min = min_wave_tile(p);
+    for (int tw : kWaveTiles) {
+        if ((!has_wave && tw != kDefaultWaveTile) || tw < tw_min) continue;
+        for (int tp : kPfdTiles) {
+            if (!has_pfd && tp != kDefaultPfdTile) continue;
+            p->tile_w = tw;
+            p->tile_p = tp;
+            rc = plan_materialize(p);
             if (!rc) rc = plan_upload(p, d_streams, d_out);
-            if (rc) break;
             for (int w = 0; w < 2 && !rc; w++) rc = plan_launch(p, nullptr, 3);
             if (rc) break;
             HIP_OK(hipEventRecord(e0, nullptr));
@@ -502,17 +588,18 @@ gc_status autotune(gc_plan *p, const uint32_t *h_headers, const uint32_t *d_stre
             HIP_OK(hipEventElapsedTime(&ms, e0, e1));
             if (ms < best) {
                 best = ms;
-                best_tile = tile;
-                best_bpc = (uint32_t)bpc;
+                best_w = tw;
+                best_p = tp;
             }
         }
+        if (rc) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    p->tile = best_tile;
-    p->bpc = best_bpc;
-    cache_store(key, best_tile, best_bpc);
+    p->tile_w = best_w;
+    p->tile_p = best_p;
+    cache_store(key, best_w, best_p);
     return GC_OK;
 }
 
@@ -531,7 +618,7 @@ gc_status validate_header(const uint32_t *hd, uint64_t n, uint64_t stream_words)
 
 extern "C" {
 
-const char *gc_version(void) { return "libgc 0.2 (gfx950)"; }
+const char *gc_version(void) { return "libgc 0.3 (gfx950)"; }
 
 gc_status gc_ctx_create(int device, gc_ctx **ctx) {
     if (!ctx) return GC_EINVAL;
@@ -580,33 +667,24 @@ gc_status gc_decode(gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words, 
     if (n == 0) return GC_OK;
     if (!d_out) return GC_EINVAL;
     std::lock_guard<std::mutex> lk(ctx->mu);
-    hipStream_t s = (hipStream_t)hip_stream;
-    const int tile = ctx->tile;
     const int cls = codec_class(h_header[0]);
-    const uint32_t ntiles = (uint32_t)((n + (size_t)tile - 1) / (size_t)tile);
     HeaderFields h;
     header_fields(h_header[0], h);
-    const uint32_t nchunks = ntiles > 1 ? list_chunks(h, n, h_header[2], h_header[3]) : 0u;
-    gc_status rc = ctx->single.reserve(ntiles, nchunks);
-    if (rc) return rc;
+    const int tile = cls == kClsPfd ? ctx->tile_p : std::max(ctx->tile_w, 32 << h.lk);
     ListDesc L;
     std::memset(&L, 0, sizeof(L));
     L.stream = d_stream;
     L.out = d_out;
     L.stream_words = stream_words;
     L.n = n;
-    L.ntiles = ntiles;
-    L.nchunks = nchunks;
-    const uint32_t cus = (uint32_t)ctx->num_cus;
-    if (ntiles > 1) {
-        LocateArgs a = make_locate_args(nullptr, nullptr, L, 0, tile, ctx->single, ctx->status);
-        if (launch_locate(a, std::max(1u, std::min(nchunks, (uint32_t)occupancy_locate() * cus)), s))
-            return GC_EDEVICE;
-    }
-    DecodeArgs d = make_decode_args(nullptr, nullptr, L, 0, cls, ctx->single, ctx->status);
-    const uint32_t g = std::max(1u, std::min(ntiles, (uint32_t)occupancy_decode(tile, cls) * cus));
-    if (launch_decode(tile, cls, d, g, s)) return GC_EDEVICE;
-    return GC_OK;
+    L.ntiles = (uint32_t)((n + (size_t)tile - 1) / (size_t)tile);
+    L.nchunks = L.ntiles > 1 ? list_chunks(h, n, h_header[2], h_header[3]) : 0u;
+    L.tile_ints = (uint32_t)tile;
+    L.w0 = h_header[0];
+    L.C = h_header[2];
+    L.D = h_header[3];
+    if (gc_status rc = ctx->single.reserve(L.ntiles, L.nchunks)) return rc;
+    return launch_one(L, cls, ctx->single, ctx->status, (hipStream_t)hip_stream);
 }
 
 gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists, const uint32_t *h_headers,
@@ -617,14 +695,16 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     gc_plan_opts o;
     std::memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
-    if (o.tile_ints && o.tile_ints != 2048 && o.tile_ints != 4096 && o.tile_ints != 8192) return GC_EINVAL;
+    if (o.tile_ints && !valid_wave_tile(o.tile_ints)) return GC_EINVAL;
+    if (o.pfd_tile_ints && !valid_pfd_tile(o.pfd_tile_ints)) return GC_EINVAL;
+    if (o.reserved[0] || o.reserved[1] || o.reserved[2]) return GC_EINVAL;
     if ((o.autotune || o.use_graph) && nlists && (!d_streams || !d_out)) return GC_EINVAL;
     gc_plan *p = new (std::nothrow) gc_plan();
     if (!p) return GC_ENOMEM;
     p->ctx = ctx;
     p->nlists = nlists;
-    p->tile = o.tile_ints ? (int)o.tile_ints : kDefaultTile;
-    p->bpc = o.blocks_per_cu;
+    p->tile_w = o.tile_ints ? (int)o.tile_ints : kDefaultWaveTile;
+    p->tile_p = o.pfd_tile_ints ? (int)o.pfd_tile_ints : kDefaultPfdTile;
     p->use_graph = o.use_graph != 0;
     p->slots = std::min<uint32_t>(o.timing_slots, 4096u);
     p->h_lists.resize(nlists);
@@ -643,10 +723,13 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
         std::memset(&L, 0, sizeof(L));
         L.stream_words = d.stream_words;
         L.n = d.n;
-        p->cls[i] = codec_class(h_headers[4 * i]);
+        L.w0 = h_headers[4 * i];
+        L.C = h_headers[4 * i + 2];
+        L.D = h_headers[4 * i + 3];
+        p->cls[i] = codec_class(L.w0);
         p->stream_off[i] = d.stream_off_words;
         p->out_off[i] = d.out_off;
-        tiles_total += (d.n + 2047u) / 2048u;
+        tiles_total += (d.n + 1023u) / 1024u;
     }
     if (tiles_total > 0xFFFFFFF0ull) {
         delete p;
@@ -654,13 +737,13 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     }
     (void)hipSetDevice(ctx->device);
     gc_status rc = GC_OK;
-    if (o.autotune && nlists && !o.tile_ints) rc = autotune(p, h_headers, d_streams, d_out);
+    if (o.autotune && nlists && !o.tile_ints && !o.pfd_tile_ints) rc = autotune(p, d_streams, d_out);
     for (uint32_t i = 0; i < 3 * p->slots && !rc; i++) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) rc = GC_EDEVICE;
         else p->ev.push_back(e);
     }
-    if (!rc) rc = plan_materialize(p, h_headers);
+    if (!rc) rc = plan_materialize(p);
     if (!rc && d_streams && d_out) rc = plan_upload(p, d_streams, d_out);
     if (!rc && p->use_graph) rc = plan_capture(p);
     if (rc) {
@@ -698,23 +781,12 @@ gc_status gc_decode_each(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_o
     if (!plan) return GC_EINVAL;
     if (!d_streams || !d_out || (reinterpret_cast<uintptr_t>(d_streams) & 15u)) return GC_EINVAL;
     hipStream_t s = (hipStream_t)hip_stream;
-    const uint32_t cus = (uint32_t)plan->ctx->num_cus;
-    const uint32_t occ_a = (uint32_t)occupancy_locate();
-    uint32_t occ_b[kClasses];
-    for (int c = 0; c < kClasses; c++) occ_b[c] = (uint32_t)occupancy_decode(plan->tile, c);
     for (size_t i = 0; i < plan->nlists; i++) {
         ListDesc L = plan->h_lists[i];
         if (L.n == 0) continue;
         L.stream = d_streams + plan->stream_off[i];
         L.out = d_out + plan->out_off[i];
-        if (L.ntiles > 1) {
-            LocateArgs a = make_locate_args(nullptr, nullptr, L, 0, plan->tile, plan->sc, plan->ctx->status);
-            if (launch_locate(a, std::max(1u, std::min(L.nchunks, occ_a * cus)), s)) return GC_EDEVICE;
-        }
-        const int c = plan->cls[i];
-        DecodeArgs d = make_decode_args(nullptr, nullptr, L, 0, c, plan->sc, plan->ctx->status);
-        if (launch_decode(plan->tile, c, d, std::max(1u, std::min(L.ntiles, occ_b[c] * cus)), s))
-            return GC_EDEVICE;
+        if (gc_status rc = launch_one(L, plan->cls[i], plan->sc, plan->ctx->status, s)) return rc;
     }
     return GC_OK;
 }
@@ -735,18 +807,18 @@ gc_status gc_plan_timings(gc_plan *plan, uint32_t max_runs, float *locate_ms, fl
     return GC_OK;
 }
 
-gc_status gc_plan_config(const gc_plan *plan, uint32_t *tile_ints, uint32_t *blocks_per_cu, uint32_t *grid_blocks) {
+gc_status gc_plan_config(const gc_plan *plan, uint32_t *tile_ints, uint32_t *pfd_tile_ints, uint64_t *tiles,
+                         uint64_t *sum_tiles) {
     if (!plan) return GC_EINVAL;
-    uint32_t g = 0, b = 0;
+    uint64_t t = 0, st = 0;
     for (int c = 0; c < kClasses; c++) {
-        if (!plan->total_b[c]) continue;
-        g += plan->grid_b[c];
-        b = std::max(b, plan->bpc ? std::min<uint32_t>(plan->bpc, (uint32_t)occupancy_decode(plan->tile, c))
-                                  : (uint32_t)occupancy_decode(plan->tile, c));
+        t += plan->cr[c].count;
+        st += plan->cr[c].sum;
     }
-    if (tile_ints) *tile_ints = (uint32_t)plan->tile;
-    if (blocks_per_cu) *blocks_per_cu = b;
-    if (grid_blocks) *grid_blocks = g;
+    if (tile_ints) *tile_ints = (uint32_t)plan->tile_w;
+    if (pfd_tile_ints) *pfd_tile_ints = (uint32_t)plan->tile_p;
+    if (tiles) *tiles = t;
+    if (sum_tiles) *sum_tiles = st;
     return GC_OK;
 }
 

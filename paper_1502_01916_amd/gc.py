@@ -53,7 +53,7 @@ class ListDesc(ctypes.Structure):
 
 
 class PlanOpts(ctypes.Structure):
-    _fields_ = [("tile_ints", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
+    _fields_ = [("tile_ints", ctypes.c_uint32), ("pfd_tile_ints", ctypes.c_uint32),
                 ("use_graph", ctypes.c_uint32), ("autotune", ctypes.c_uint32),
                 ("timing_slots", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
 
@@ -92,7 +92,7 @@ def lib():
         L.gc_plan_destroy.argtypes = [vp]
         L.gc_decode_batch.argtypes = [vp, vp, vp, vp]
         L.gc_decode_each.argtypes = [vp, vp, vp, vp]
-        L.gc_plan_config.argtypes = [vp, u32p, u32p, u32p]
+        L.gc_plan_config.argtypes = [vp, u32p, u32p, u64p, u64p]
         f32p = ctypes.POINTER(ctypes.c_float)
         L.gc_plan_timings.argtypes = [vp, ctypes.c_uint32, f32p, f32p, u32p]
         L.gc_plan_timings.restype = ctypes.c_int
@@ -218,14 +218,14 @@ class Plan:
     """gc_plan_create / gc_decode_batch / gc_decode_each / gc_plan_destroy."""
 
     def __init__(self, ctx: Context, descs, headers, d_streams=None, d_out=None, tile_ints=0,
-                 blocks_per_cu=0, use_graph=False, autotune=False, timing_slots=0):
+                 pfd_tile_ints=0, use_graph=False, autotune=False, timing_slots=0):
         self.ctx = ctx
         nl = len(descs)
         arr = (ListDesc * max(nl, 1))()
         for i, d in enumerate(descs):
             arr[i] = d
         hdr = np.ascontiguousarray(headers, dtype=np.uint32).reshape(-1)
-        opts = PlanOpts(int(tile_ints), int(blocks_per_cu), int(bool(use_graph)), int(bool(autotune)),
+        opts = PlanOpts(int(tile_ints), int(pfd_tile_ints), int(bool(use_graph)), int(bool(autotune)),
                         int(timing_slots))
         self._h = ctypes.c_void_p()
         rc = lib().gc_plan_create(ctx._h, arr, nl, _u32(hdr), ctypes.byref(opts),
@@ -250,10 +250,13 @@ class Plan:
         return np.array(a[:n.value]), np.array(b[:n.value])
 
     def config(self):
-        t, b, g = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
-        _check("gc_plan_config", lib().gc_plan_config(self._h, ctypes.byref(t), ctypes.byref(b),
-                                                      ctypes.byref(g)))
-        return dict(tile_ints=t.value, blocks_per_cu=b.value, grid_blocks=g.value)
+        """Chosen tile sizes, decode tiles per run and the tiles of those the
+        sum pass decodes too."""
+        t, pt = ctypes.c_uint32(), ctypes.c_uint32()
+        n, ns = ctypes.c_uint64(), ctypes.c_uint64()
+        _check("gc_plan_config", lib().gc_plan_config(self._h, ctypes.byref(t), ctypes.byref(pt),
+                                                      ctypes.byref(n), ctypes.byref(ns)))
+        return dict(tile_ints=t.value, pfd_tile_ints=pt.value, tiles=n.value, sum_tiles=ns.value)
 
     def close(self):
         if self._h:

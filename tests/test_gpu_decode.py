@@ -131,10 +131,11 @@ def make_batch(rng, nlists, kmix=(4,), maxlen=40000):
     return flat, offs, lengths, lists
 
 
-@pytest.mark.parametrize("tile", [2048, 4096, 8192])
+@pytest.mark.parametrize("tiles", [(1024, 2048), (2048, 4096), (4096, 8192)])
 @pytest.mark.parametrize("graph", [False, True])
-def test_batch_parity(torch_cuda, ctx, tile, graph):
+def test_batch_parity(torch_cuda, ctx, tiles, graph):
     torch = torch_cuda
+    tile, pfd_tile = tiles
     rng = np.random.default_rng(50 + tile + int(graph))
     flat, offs, lengths, lists = make_batch(rng, 240, kmix=(4, 4, 8, 64))
     align = 4 if graph else 1        # 16-byte aligned lists take the vector-store path
@@ -143,7 +144,7 @@ def test_batch_parity(torch_cuda, ctx, tile, graph):
     total = int(out_offs[-1])
     d_o = torch.full((total + 64,), -1, dtype=torch.int32, device="cuda")
     say("batch tile", tile, "graph", graph, "lists", len(descs), "ints", total)
-    plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=tile, use_graph=graph)
+    plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=tile, pfd_tile_ints=pfd_tile, use_graph=graph)
     want = np.concatenate(lists)
     for rep in range(3):
         d_o.fill_(-1)
@@ -174,7 +175,8 @@ def test_autotuned_plan(torch_cuda, ctx, tmp_path, monkeypatch):
     say("autotune")
     plan = gc.Plan(ctx, descs, headers, d_s, d_o, autotune=True, use_graph=True)
     cfg = plan.config()
-    assert cfg["tile_ints"] in (2048, 4096, 8192) and cfg["blocks_per_cu"] >= 1
+    assert cfg["tile_ints"] in (1024, 2048, 4096) and cfg["pfd_tile_ints"] in (2048, 4096, 8192)
+    assert 1 <= cfg["tiles"] and cfg["sum_tiles"] <= cfg["tiles"]
     plan.decode_batch(d_s, d_o)
     assert ctx.sync_status()[0] == gc.OK
     assert np.array_equal(gc.to_host(d_o)[:int(out_offs[-1])], np.concatenate(lists))
@@ -234,8 +236,8 @@ def test_host_rejects_bad_headers(torch_cuda, ctx):
 
 def test_cfg2_full_size_batch(torch_cuda, ctx):
     """The benchmark workload at full size, in the launch configuration the
-    benchmark times: every cfg2 list (docIDs and TFs) through one persistent
-    hipGraph launch per codec; outputs equal the generator's lists (the
+    benchmark times: every cfg2 list (docIDs and TFs) through one hipGraph
+    launch per codec; outputs equal the generator's lists (the
     lossless-codec property at any size) and, on sampled lists, the oracle."""
     torch = torch_cuda
     lengths, docs, tfs = synth.cfg2()
