@@ -6,8 +6,9 @@ Workload: 10,000 synthetic posting lists (Zipf lengths clipped to
 and their TF lists, each coded with Group-Simple, Group-Scheme 1-CU,
 Group-Scheme 8-IU, Group-AFOR and Group-PFD (32-tuple blocks, zeta = 1/10) in
 the paper's 4-way layout: 100,000 streams, about 6.7e8 integers.  One step
-decodes every stream (docID lists prefix-summed) with one persistent launch
-sequence replayed from a hipGraph.
+decodes every stream (docID lists prefix-summed): the locate kernels, then per
+codec class the tile-sum pass, the carry scan and the decode pass, timed with
+HIP events between the kernels.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -43,6 +44,29 @@ def variants(gc):
             ("group-pfd", gc.PFD, dict(zeta=(1, 10)))]
 
 
+CLASS_NAMES = ["group-simple", "group-scheme-unary", "group-scheme-binary", "group-afor", "group-pfd"]
+KERNEL_NAMES = ["gc_wave_kernel<%d, 0, false>", "gc_wave_kernel<%d, 1, false>", "gc_wave_kernel<%d, 2, false>",
+                "gc_wave_kernel<%d, 3, false>", "gc_pfd_kernel<%d, false>"]
+
+
+def codec_class(gc, codec, kw):
+    if codec == gc.SIMPLE:
+        return 0
+    if codec == gc.SCHEME:
+        return 2 if kw.get("ld", gc.LD_CU) == gc.LD_BINARY else 1
+    return 3 if codec == gc.AFOR else 4
+
+
+def class_bytes(gc, parts, cls):
+    """Algorithmic bytes of one decode pass of a class: its streams read once
+    and its integers written once."""
+    b = 0
+    for p in parts:
+        if p["cls"] == cls:
+            b += 4 * int(p["streams"].size) + 4 * int(p["flat"].size)
+    return b
+
+
 def build_workload(gc, synth):
     t = time.time()
     lengths, docs, tfs = synth.cfg2()
@@ -53,7 +77,7 @@ def build_workload(gc, synth):
             t = time.time()
             s, offs = gc.encode_lists(flat, lengths, codec, gc.params(delta=delta, **kw))
             parts.append(dict(name=name, kind=kind, codec=codec, streams=s, offs=offs,
-                              lengths=lengths, flat=flat))
+                              lengths=lengths, flat=flat, cls=codec_class(gc, codec, kw)))
             log("encoded %-18s %-6s %.2f bits/int (%.1fs)" % (name, kind, 32.0 * s.size / flat.size,
                                                               time.time() - t))
     return parts
@@ -70,9 +94,10 @@ def concat(parts):
     return streams, np.concatenate(offs), lengths
 
 
-def read_traffic(units):
-    """HBM bytes per decode launch from the committed rocprofv3 counter
-    summary, if it was taken on the current decode kernel source."""
+def read_traffic(units, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current decode kernel source and this
+    workload."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -83,7 +108,8 @@ def read_traffic(units):
                 kv[k.strip()] = v.strip()
     with open(DECODE_SRC, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    if kv.get("decode_source_sha256") != sha or kv.get("workload_units") != str(units):
+    if (kv.get("decode_source_sha256") != sha or kv.get("workload_units") != str(units)
+            or kv.get("kernel") != kernel):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -136,7 +162,6 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip per-list and per-codec runs")
     ap.add_argument("--tile", type=int, default=0, help="force the wave-tile size (0 = autotune)")
     ap.add_argument("--pfd-tile", type=int, default=0, help="force the Group-PFD tile size (with --tile)")
-    ap.add_argument("--no-graph", action="store_true", help="launch kernels directly, no hipGraph")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the decode path is built and measured on a single "
@@ -161,14 +186,14 @@ def main():
     d_s = gc.to_device(streams)
     d_o = torch.empty(out_len, dtype=torch.int32, device="cuda")
     t = time.time()
-    plan = gc.Plan(ctx, descs, headers, d_s, d_o, use_graph=not args.no_graph, tile_ints=args.tile,
+    plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=args.tile,
                    pfd_tile_ints=args.pfd_tile or (4096 if args.tile else 0),
                    autotune=args.tile == 0, timing_slots=args.steps + args.warmup)
     cfg = plan.config()
     log("plan: %s (%.1fs)" % (cfg, time.time() - t))
 
     elapsed = timed(plan, d_s, d_o, args.steps, args.warmup, torch)
-    loc_ms, dec_ms = plan.timings(args.steps)
+    tm = plan.timings(args.steps)
     rc, detail = ctx.sync_status()
     if rc != gc.OK:
         raise SystemExit("device reported %d (detail %d)" % (rc, detail))
@@ -178,14 +203,19 @@ def main():
     del got, want
     ms_per_step = 1e3 * elapsed / args.steps
     value = total / (elapsed / args.steps) / 1e9
-    alg_bytes = stream_bytes + 4 * total
-    dec_avg = float(np.mean(dec_ms))
-    achieved = alg_bytes / (dec_avg * 1e-3) / 1e9
-    log("step %.3f ms  %.1f Gints/s  decode kernel %.3f ms (locate %.3f ms)  %.0f GB/s  verified=%s"
-        % (ms_per_step, value, dec_avg, float(np.mean(loc_ms)), achieved, verified))
+    # the dominant kernel: the decode pass of the class that takes longest
+    dec = tm["decode"].mean(axis=0)
+    cls = int(np.argmax(dec))
+    cls_bytes = class_bytes(gc, parts, cls)
+    dec_avg = float(dec[cls])
+    achieved = cls_bytes / (dec_avg * 1e-3) / 1e9
+    log("step %.3f ms  %.1f Gints/s  (GPU %.3f ms: locate %.3f, sum+carry %s, decode %s)  verified=%s"
+        % (ms_per_step, value, tm["total"].mean(), tm["locate"].mean(),
+           np.round(tm["sum"].mean(axis=0), 3), np.round(dec, 3), verified))
+    log("dominant kernel: %s decode pass %.3f ms, %.0f GB/s" % (CLASS_NAMES[cls], dec_avg, achieved))
     if not verified:
         raise SystemExit("decoded output differs from the generated lists")
-    traffic = read_traffic(len(descs))
+    traffic = read_traffic(len(descs), KERNEL_NAMES[cls] % cfg["tile_ints" if cls != 4 else "pfd_tile_ints"])
 
     extra = {}
     if not args.no_extra:
@@ -208,16 +238,19 @@ def main():
             de2, h2, oo2 = gc.batch_layout(s2, o2, l2, align=4)
             ds2 = gc.to_device(s2)
             do2 = torch.empty(int(oo2[-1]), dtype=torch.int32, device="cuda")
-            p2 = gc.Plan(ctx, de2, h2, ds2, do2, use_graph=True, tile_ints=cfg["tile_ints"],
+            p2 = gc.Plan(ctx, de2, h2, ds2, do2, tile_ints=cfg["tile_ints"],
                          pfd_tile_ints=cfg["pfd_tile_ints"], timing_slots=args.steps)
             el = timed(p2, ds2, do2, args.steps, 2, torch)
-            _, dm = p2.timings(args.steps)
+            t2 = p2.timings(args.steps)
+            c2 = sub[0]["cls"]
             n2 = int(l2.sum())
-            ab = 4 * int(s2.size) + 4 * n2
-            gbs = ab / (float(np.mean(dm)) * 1e-3) / 1e9
+            gbs = class_bytes(gc, sub, c2) / (float(t2["decode"][:, c2].mean()) * 1e-3) / 1e9
             per[sub[0]["name"]] = dict(gints_s=round(n2 / (el / args.steps) / 1e9, 2),
                                        bits_per_int_docids=round(32.0 * sub[0]["streams"].size / n2 * 2, 3),
                                        bits_per_int_tf=round(32.0 * sub[1]["streams"].size / n2 * 2, 3),
+                                       locate_ms=round(float(t2["locate"].mean()), 4),
+                                       sum_ms=round(float(t2["sum"][:, c2].mean()), 4),
+                                       decode_ms=round(float(t2["decode"][:, c2].mean()), 4),
                                        decode_kernel_gbs=round(gbs, 1),
                                        hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
             log("%-18s %s" % (sub[0]["name"], per[sub[0]["name"]]))
@@ -248,7 +281,7 @@ def main():
                         "2^25, 70% sparse / 30% clustered d-gaps) plus their TF lists (geometric "
                         "p=0.4), each coded with Group-Simple, Group-Scheme 1-CU, Group-Scheme "
                         "8-IU, Group-AFOR and Group-PFD (zeta 1/10), 4-way layout; all 100,000 "
-                        "streams decoded per step in one persistent hipGraph launch sequence, "
+                        "streams decoded per step (locate, tile sums, carry scans, decode passes), "
                         "docID lists prefix-summed; seed 2",
             "lists": len(descs),
             "ints_per_step": total,
@@ -262,16 +295,21 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "gc_decode_wave_kernel<%d,*> + gc_decode_kernel<%d,pfd> (concurrent)"
-                      % (cfg["tile_ints"], cfg["pfd_tile_ints"]),
+            "kernel": KERNEL_NAMES[cls] % (cfg["tile_ints"] if cls != 4 else cfg["pfd_tile_ints"]),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "algorithmic_bytes_per_launch": alg_bytes,
+            "algorithmic_bytes_per_launch": cls_bytes,
             "avg_kernel_ms": round(dec_avg, 4),
-            "avg_locate_kernel_ms": round(float(np.mean(loc_ms)), 4),
+        },
+        "phases_ms": {
+            "gpu_total": round(float(tm["total"].mean()), 4),
+            "locate": round(float(tm["locate"].mean()), 4),
+            "sum_and_carry": {CLASS_NAMES[c]: round(float(tm["sum"][:, c].mean()), 4)
+                              for c in range(5) if dec[c] > 0},
+            "decode": {CLASS_NAMES[c]: round(float(dec[c]), 4) for c in range(5) if dec[c] > 0},
         },
         "cpu_baseline": cpu,
     }

@@ -149,9 +149,9 @@ typedef struct {
                                 or 8192; 0 = autotuned / default                   */
     uint32_t use_graph;      /* 1 = capture the launch sequence in a hipGraph       */
     uint32_t autotune;       /* 1 = time candidate tile sizes at creation           */
-    uint32_t timing_slots;   /* > 0: record HIP events around the locate and decode
-                                launches of each gc_decode_batch, in this many
-                                rotating slots (see gc_plan_timings)               */
+    uint32_t timing_slots;   /* > 0: time the kernels of each gc_decode_batch with
+                                HIP events, in this many rotating slots (see
+                                gc_plan_timings); the run is then not graphed  */
     uint32_t reserved[3];    /* zero */
 } gc_plan_opts;
 
@@ -180,15 +180,22 @@ gc_status gc_decode_batch(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_
 gc_status gc_decode_each(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_out,
                          void *hip_stream);
 
-/* Kernel durations of the last runs of a plan created with timing_slots > 0:
- * synchronises the recorded HIP events and writes, oldest first, up to
- * max_runs pairs (locate_ms[i], decode_ms[i]) -- the time between the events
- * recorded on the launch stream before the locate kernels, between the locate
- * kernels and the decode kernels (tile sums, carry scans, decode passes), and
- * after those.  *nruns receives the count written.
+/* Kernel durations of the last runs of a plan created with timing_slots > 0.
+ * Such a plan launches its kernels directly (no graph), one codec class
+ * after another, with HIP events between them on the launch stream.  This
+ * synchronises those events and writes, oldest run first, up to max_runs rows
+ * of GC_TIMING_FIELDS floats (milliseconds) to ms:
+ *   [0]                     the whole run
+ *   [1]                     the locate kernels
+ *   [2 + c]                 the decode pass of codec class c
+ *   [2 + GC_CLASSES + c]    the tile-sum pass and carry scan of class c
+ * with classes c = 0 Group-Simple, 1 Group-Scheme with unary descriptors,
+ * 2 Group-Scheme with binary descriptors, 3 Group-AFOR, 4 Group-PFD (0 for a
+ * class the plan does not hold).  *nruns receives the rows written.
  * GC_EINVAL if the plan records no events.                                 */
-gc_status gc_plan_timings(gc_plan *plan, uint32_t max_runs, float *locate_ms, float *decode_ms,
-                          uint32_t *nruns);
+#define GC_CLASSES 5
+#define GC_TIMING_FIELDS (2 + 2 * GC_CLASSES)
+gc_status gc_plan_timings(gc_plan *plan, uint32_t max_runs, float *ms, uint32_t *nruns);
 
 /* Reports the chosen configuration of a plan: the wave-tile and Group-PFD
  * tile sizes, the decode tiles of one run and, of those, the tiles the sum

@@ -37,6 +37,10 @@
 namespace gcdev {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// Pointers into global memory, so accesses compile to global_* rather than
+// flat_* instructions.
+typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef __attribute__((address_space(1))) u32x4 gu32x4;
 
 // ---------------------------------------------------------------------------
 // Small helpers.
@@ -69,6 +73,20 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     x += dpp<0x143, 0xC, false>(x);   // row_bcast:31 into rows 2 and 3
     return x;
 }
+
+// Inclusive running maximum across a wave64 (same DPP pattern).
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
+    x = max(x, dpp<0x111, 0xF, true>(x));
+    x = max(x, dpp<0x112, 0xF, true>(x));
+    x = max(x, dpp<0x114, 0xF, true>(x));
+    x = max(x, dpp<0x118, 0xF, true>(x));
+    x = max(x, dpp<0x142, 0xA, false>(x));
+    x = max(x, dpp<0x143, 0xC, false>(x));
+    return x;
+}
+
+// The value of the previous lane (0 in lane 0): DPP wave_shr:1.
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t x) { return dpp<0x138, 0xF, true>(x); }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(x), 63);
@@ -114,8 +132,8 @@ constexpr uint64_t kSimNumM1 = 31ull | 15ull << 5 | 9ull << 10 | 7ull << 15 | 5u
                                3ull << 30 | 2ull << 35 | 1ull << 40 | 0ull << 45;
 constexpr uint64_t kSimBwM1 = 0ull | 1ull << 5 | 2ull << 10 | 3ull << 15 | 4ull << 20 | 5ull << 25 |
                               7ull << 30 | 9ull << 35 | 15ull << 40 | 31ull << 45;
-__device__ __forceinline__ uint32_t sim_num(uint32_t sel) { return (uint32_t)((kSimNumM1 >> (5 * sel)) & 31u) + 1u; }
-__device__ __forceinline__ uint32_t sim_bw(uint32_t sel) { return (uint32_t)((kSimBwM1 >> (5 * sel)) & 31u) + 1u; }
+__device__ __forceinline__ uint32_t sim_num(uint32_t sel) { return (uint32_t)((kSimNumM1 >> ((5 * sel) & 63u)) & 31u) + 1u; }
+__device__ __forceinline__ uint32_t sim_bw(uint32_t sel) { return (uint32_t)((kSimBwM1 >> ((5 * sel) & 63u)) & 31u) + 1u; }
 
 // Group-Scheme binary descriptor units (Table IV widths; 16-bit units of
 // three fields at 1-bit CG, 8-bit units otherwise).
@@ -793,8 +811,16 @@ template <int TW, int CLS>
 struct WaveSmem {
     static constexpr int TTM = TW / 4;
     static constexpr int NCTRL = CLS == kClsSim ? TTM / 8 + 8 : CLS == kClsGscU ? TTM + 8 : 1;
+    static constexpr int NDATA = TW / 8;   // 16-byte data chunks: 16 bits per integer
+    // + one row of 16 chunks that the second row read of a quad may touch
+    static constexpr int NB = (NDATA > (NCTRL + 3) / 4 ? NDATA : (NCTRL + 3) / 4) + 16;
+    // control words or per-unit record bases while the records are built,
+    // then the tile's data rows
+    union {
+        u32x4 data[NB];
+        uint32_t ctrl[4 * NB];
+    };
     uint32_t rec[TTM];
-    uint32_t ctrl[NCTRL];
 };
 
 // Orders a wave's LDS writes before its later LDS reads by other lanes.
@@ -806,62 +832,115 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 __device__ __forceinline__ uint32_t wave_any(bool b) { return __ballot(b) != 0ull ? 1u : 0u; }
 
+// Tuple records from unit starts.  A unit (selector, frame) u of the tile
+// covers the tuples from start_u on; info[u] = {base, bw} such that tuple t
+// of it has its component bit offset at base + t * bw.  The unit marks its
+// start with u + 1 in the zeroed record array; a running maximum over the
+// tuples (in-lane, then across the wave) names every tuple's unit.  Lane l
+// owns tuples [l * TPL, (l + 1) * TPL).
+template <int TTM>
+__device__ __forceinline__ void zero_markers(uint32_t *rec, uint32_t lane) {
+    constexpr int V = TTM / 256;
+    u32x4 *r4 = reinterpret_cast<u32x4 *>(rec) + lane * V;
+#pragma unroll
+    for (int v = 0; v < V; v++) r4[v] = u32x4{0u, 0u, 0u, 0u};
+}
+
+template <int TTM>
+__device__ __forceinline__ void expand_records(uint32_t *rec, const uint2 *info, uint32_t lane) {
+    constexpr int V = TTM / 256, TPL = 4 * V;
+    u32x4 *r4 = reinterpret_cast<u32x4 *>(rec) + lane * V;
+    uint32_t mk[TPL];
+#pragma unroll
+    for (int v = 0; v < V; v++) {
+        const u32x4 x = r4[v];
+        mk[4 * v] = x.x;
+        mk[4 * v + 1] = x.y;
+        mk[4 * v + 2] = x.z;
+        mk[4 * v + 3] = x.w;
+    }
+#pragma unroll
+    for (int u = 1; u < TPL; u++) mk[u] = max(mk[u], mk[u - 1]);
+    const uint32_t before = wave_shr1(wave_incl_max(mk[TPL - 1]));
+    const uint32_t t0 = lane * (uint32_t)TPL;
+#pragma unroll
+    for (int v = 0; v < V; v++) {
+        uint32_t o[4];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const uint32_t m = max(max(mk[4 * v + e], before), 1u) - 1u;
+            const uint2 in = info[m];
+            o[e] = ((in.x + (t0 + (uint32_t)(4 * v + e)) * in.y) << 6) | in.y;
+        }
+        r4[v] = u32x4{o[0], o[1], o[2], o[3]};
+    }
+    wave_lds_sync();
+}
+
 // ---- Group-Simple ---------------------------------------------------------
+// Lane l reads selectors l*SPT .. l*SPT + SPT - 1 of the tile straight from
+// the control words, scans their tuple counts across the wave, and scatters
+// unit markers and record bases for expand_records.
 template <int TW>
 __device__ uint32_t wprologue_sim(const TileCtx &c, WaveSmem<TW, kClsSim> &sm, uint32_t lane, uint32_t &dbase) {
     using SM = WaveSmem<TW, kClsSim>;
+    constexpr int SPT = (SM::TTM + 1 + 63) / 64;   // selectors per lane
+    constexpr int NW = (7 + SPT + 7) / 8;           // control words they can span
     const uint32_t S_total = c.D >> c.lk;
     const uint32_t s_first = c.st.unit, sub0 = c.st.sub;
     const uint32_t s_end = c.has_en ? c.en.unit + (c.en.sub ? 1u : 0u) : S_total;
     const uint32_t nsel = s_end - s_first;
-    const uint32_t cw0 = s_first >> 3, cw1 = (s_end + 7u) >> 3;
-    if (!(s_end <= S_total && s_end > s_first && nsel <= c.TT + 1u && cw1 <= c.C &&
-          cw1 - cw0 <= (uint32_t)SM::NCTRL))
-        return kErrRange;
-    for (uint32_t i = lane; i < cw1 - cw0; i += 64u) sm.ctrl[i] = c.ctrl[cw0 + i];
-    wave_lds_sync();
+    const uint32_t cw1 = (s_end + 7u) >> 3;
+    if (!(s_end <= S_total && s_end > s_first && nsel <= c.TT + 1u && cw1 <= c.C)) return kErrRange;
+    zero_markers<SM::TTM>(sm.rec, lane);
     dbase = s_first;
-    constexpr int SPT = (SM::TTM + 1 + 63) / 64;
-    uint32_t sel[SPT];
+    const uint32_t i0 = lane * (uint32_t)SPT;
+    const uint32_t g0 = s_first + i0;
+    const gu32 *ctrl = (const gu32 *)c.ctrl;
+    uint32_t w[NW + 1];
+#pragma unroll
+    for (int k = 0; k < NW; k++) {
+        const uint32_t gw = (g0 >> 3) + (uint32_t)k;
+        w[k] = (i0 < nsel && gw < cw1) ? ctrl[gw] : 0u;
+    }
+    w[NW] = 0u;
+    const uint32_t sh = 4u * (g0 & 7u);
+#pragma unroll
+    for (int k = 0; k < NW; k++) w[k] = funnel(w[k + 1], w[k], sh);
+    uint32_t cnt[SPT], bwv[SPT];
     uint32_t sum = 0;
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < SPT; j++) {
-        const uint32_t i = lane * SPT + (uint32_t)j;
-        uint32_t s = 15u, cnt = 0;
-        if (i < nsel) {
-            const uint32_t g = s_first + i;
-            s = (sm.ctrl[(g >> 3) - cw0] >> ((g & 7u) * 4u)) & 15u;
-            const uint32_t j0 = i == 0u ? sub0 : 0u;
-            const uint32_t num = s < 10u ? sim_num(s) : 0u;
-            if (s >= 10u || num <= j0) {
-                bad = true;
-                s = 15u;
-            } else {
-                cnt = num - j0;
-            }
-        }
-        sel[j] = s;
-        sum += cnt;
+        const uint32_t i = i0 + (uint32_t)j;
+        const uint32_t sel = (w[j >> 3] >> (4 * (j & 7))) & 15u;
+        const uint32_t j0 = i == 0u ? sub0 : 0u;
+        const uint32_t num = sim_num(sel);
+        const bool in = i < nsel, okj = sel < 10u && num > j0;
+        bad |= in && !okj;
+        cnt[j] = (in && okj) ? num - j0 : 0u;
+        bwv[j] = sim_bw(sel);
+        sum += cnt[j];
     }
     const uint32_t inc = wave_incl_scan(sum);
     const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
     if (wave_any(bad)) return kErrSelector;
     if (total < c.ntup) return kErrCount;
-    uint32_t run = inc - sum;
+    wave_lds_sync();   // markers zeroed before the scatter
+    uint2 *info = reinterpret_cast<uint2 *>(sm.data);
+    uint32_t start = inc - sum;
 #pragma unroll
     for (int j = 0; j < SPT; j++) {
-        const uint32_t i = lane * SPT + (uint32_t)j;
-        if (sel[j] < 10u) {
-            const uint32_t bw = sim_bw(sel[j]);
+        const uint32_t i = i0 + (uint32_t)j;
+        if (cnt[j]) {
             const uint32_t j0 = i == 0u ? sub0 : 0u;
-            const uint32_t cnt = sim_num(sel[j]) - j0;
-            const uint32_t lim = min(cnt, max(c.ntup, run) - run);   // 0 once run >= ntup
-            for (uint32_t jj = 0; jj < lim; jj++) sm.rec[run + jj] = rec_pack(32u * i + (j0 + jj) * bw, bw);
-            run += cnt;
+            info[i] = make_uint2(32u * i - (start - j0) * bwv[j], bwv[j]);
+            if (start < c.ntup) sm.rec[start] = i + 1u;
         }
+        start += cnt[j];
     }
     wave_lds_sync();
+    expand_records<SM::TTM>(sm.rec, info, lane);
     return 0;
 }
 
@@ -1034,9 +1113,10 @@ __device__ uint32_t wprologue_afor(const TileCtx &c, WaveSmem<TW, kClsAfor> &sm,
     return 0;
 }
 
-// Four consecutive integers of quad q from the tuple records and data rows.
-__device__ __forceinline__ u32x4 extract_quad(uint32_t rc, uint32_t q, uint32_t kq, const u32x4 *rows,
-                                             uint32_t nrow) {
+// Four consecutive integers of quad q from the tuple records and data rows
+// (in global memory, or staged in LDS).
+template <typename RowPtr>
+__device__ __forceinline__ u32x4 extract_quad(uint32_t rc, uint32_t q, uint32_t kq, RowPtr rows, uint32_t nrow) {
     const uint32_t O = rc >> 6, bw = rc & 63u;
     u32x4 v = {0u, 0u, 0u, 0u};
     if (bw && nrow) {
@@ -1054,6 +1134,26 @@ __device__ __forceinline__ u32x4 extract_quad(uint32_t rc, uint32_t q, uint32_t 
     return v;
 }
 
+// Copies n 16-byte chunks of data rows into the wave's LDS buffer: every
+// load is issued before the first LDS write, so the tile waits for memory
+// once.
+template <int N>
+__device__ __forceinline__ void stage_rows(u32x4 *dst, const gu32x4 *src, uint32_t n, uint32_t lane) {
+    constexpr int PL = N / 64;
+    u32x4 t[PL];
+#pragma unroll
+    for (int j = 0; j < PL; j++) {
+        const uint32_t i = (uint32_t)j * 64u + lane;
+        if (i < n) t[j] = src[i];
+    }
+#pragma unroll
+    for (int j = 0; j < PL; j++) {
+        const uint32_t i = (uint32_t)j * 64u + lane;
+        if (i < n) dst[i] = t[j];
+    }
+    wave_lds_sync();
+}
+
 __device__ __forceinline__ void store_quad(uint32_t *out, uint32_t ii, uint32_t nint, bool vec, u32x4 o) {
     if (ii >= nint) return;
     if (vec && ii + 4u <= nint) {
@@ -1064,6 +1164,80 @@ __device__ __forceinline__ void store_quad(uint32_t *out, uint32_t ii, uint32_t 
         if (ii + 2u < nint) out[ii + 2u] = o.z;
         if (ii + 3u < nint) out[ii + 3u] = o.w;
     }
+}
+
+// Sums (SUM) or writes the tile's integers: lane l handles quads l, l + 64,
+// ...; a delta tile is scanned in-lane, across the wave with DPP, and from
+// the carry of the previous rounds.
+template <int R, bool SUM, typename RowPtr>
+__device__ __forceinline__ uint32_t tile_quads(const uint32_t *rec, uint32_t tsh, uint32_t kq, RowPtr rows,
+                                               uint32_t nrow, uint32_t nint, uint32_t lane, bool delta,
+                                               uint32_t carry, uint32_t *out, bool vec) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const uint32_t q = (uint32_t)r * 64u + lane;
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (4u * q < nint) v = extract_quad(rec[q >> tsh], q, kq, rows, nrow);
+        if constexpr (SUM) {
+            s += v.x + v.y + v.z + v.w;
+        } else if (delta) {
+            v.y += v.x;
+            v.z += v.y;
+            v.w += v.z;
+            const uint32_t inc = wave_incl_scan(v.w);
+            const uint32_t add = carry + inc - v.w;
+            store_quad(out, 4u * q, nint, vec, u32x4{v.x + add, v.y + add, v.z + add, v.w + add});
+            carry += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+        } else {
+            store_quad(out, 4u * q, nint, vec, v);
+        }
+    }
+    return s;
+}
+
+// The tile's integers from records and LDS-staged rows, lane l taking quads
+// l, l + 64, ...: SUM returns the lane's sum of them; otherwise they are
+// written (a delta tile scanned in-lane, across the wave with DPP, and from
+// the carry of the earlier rounds).  FULL: a whole tile with a 16-byte
+// aligned output, so no quad needs a bounds check.  Rows are read without a
+// clamp: the row after the last holds padding, and its bits are masked off.
+template <int R, bool SUM, bool FULL, bool DELTA>
+__device__ __forceinline__ uint32_t quads_lds(const uint32_t *rec, const u32x4 *data, uint32_t tsh, uint32_t kq,
+                                              uint32_t nint, uint32_t lane, uint32_t carry, uint32_t *out,
+                                              bool vec) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const uint32_t q = (uint32_t)r * 64u + lane;
+        uint32_t rc = rec[q >> tsh];
+        if constexpr (!FULL) rc = 4u * q < nint ? rc : 0u;
+        const uint32_t O = rc >> 6, bw = rc & 63u, sh = O & 31u;
+        const uint32_t idx = (O >> 5) * kq + (q & (kq - 1u));
+        const u32x4 lo = data[idx], hi = data[idx + kq];
+        const uint32_t M = (uint32_t)(0xFFFFFFFFull >> (32u - bw));
+        u32x4 v;
+        v.x = funnel(hi.x, lo.x, sh) & M;
+        v.y = funnel(hi.y, lo.y, sh) & M;
+        v.z = funnel(hi.z, lo.z, sh) & M;
+        v.w = funnel(hi.w, lo.w, sh) & M;
+        if constexpr (SUM) {
+            s += v.x + v.y + v.z + v.w;
+        } else {
+            if constexpr (DELTA) {
+                v.y += v.x;
+                v.z += v.y;
+                v.w += v.z;
+                const uint32_t inc = wave_incl_scan(v.w);
+                const uint32_t add = carry + inc - v.w;
+                v += add;
+                carry += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+            }
+            if constexpr (FULL) __builtin_nontemporal_store(v, (gu32x4 *)out + q);
+            else store_quad(out, 4u * q, nint, vec, v);
+        }
+    }
+    return s;
 }
 
 template <int TW, int CLS, bool SUM>
@@ -1084,54 +1258,43 @@ __device__ void wave_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, ui
     }
     const bool good = err == 0u;
     if (!good && lane == 0) latch(a.status, err);
+    using SM = WaveSmem<TW, CLS>;
     const uint32_t Dk = c.D >> c.lk;
     const uint32_t nrow = Dk > dbase ? Dk - dbase : 0u;
     const uint32_t kq = c.k >> 2;
     const u32x4 *rows = reinterpret_cast<const u32x4 *>(c.data) + (size_t)dbase * kq;
     const uint32_t tsh = c.lk - 2u;
-
-    if constexpr (SUM) {
-        uint32_t s = 0;
-        if (good) {
-#pragma unroll
-            for (int r = 0; r < R; r++) {
-                const uint32_t q = (uint32_t)r * 64u + lane;
-                if (4u * q < c.nint) {
-                    const u32x4 v = extract_quad(sm.rec[q >> tsh], q, kq, rows, nrow);
-                    s += v.x + v.y + v.z + v.w;
-                }
-            }
-        }
-        s = wave_sum(s);
-        if (lane == 0) a.carry[gi] = s;
-        return;
+    const uint32_t nint = good ? c.nint : 0u;
+    // the tile's data rows end with its last record (offsets grow with the tuple)
+    uint32_t span = 0;
+    if (nint) {
+        const uint32_t lr = sm.rec[c.ntup - 1u];
+        span = min(nrow, ((lr >> 6) + (lr & 63u) + 31u) >> 5);
     }
-
+    const bool staged = span * kq <= (uint32_t)SM::NDATA;
     uint32_t *out = L.out + c.i0;
     const bool vec = (reinterpret_cast<uintptr_t>(out) & 15u) == 0u;
-    if (c.h.delta) {
-        uint32_t carry = carry0;
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-            const uint32_t q = (uint32_t)r * 64u + lane;
-            u32x4 v = {0u, 0u, 0u, 0u};
-            if (good && 4u * q < c.nint) v = extract_quad(sm.rec[q >> tsh], q, kq, rows, nrow);
-            v.y += v.x;
-            v.z += v.y;
-            v.w += v.z;
-            const uint32_t inc = wave_incl_scan(v.w);
-            const uint32_t add = carry + inc - v.w;
-            store_quad(out, 4u * q, c.nint, vec, u32x4{v.x + add, v.y + add, v.z + add, v.w + add});
-            carry += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+    uint32_t s = 0;
+    if (staged) {
+        if (span) stage_rows<SM::NDATA>(sm.data, (const gu32x4 *)rows, span * kq, lane);
+        const u32x4 *d = sm.data;
+        const bool full = nint == (uint32_t)TW && vec;
+        if constexpr (SUM) {
+            s = full ? quads_lds<R, true, true, true>(sm.rec, d, tsh, kq, nint, lane, 0u, out, vec)
+                     : quads_lds<R, true, false, true>(sm.rec, d, tsh, kq, nint, lane, 0u, out, vec);
+        } else if (c.h.delta) {
+            if (full) quads_lds<R, false, true, true>(sm.rec, d, tsh, kq, nint, lane, carry0, out, vec);
+            else quads_lds<R, false, false, true>(sm.rec, d, tsh, kq, nint, lane, carry0, out, vec);
+        } else {
+            if (full) quads_lds<R, false, true, false>(sm.rec, d, tsh, kq, nint, lane, 0u, out, vec);
+            else quads_lds<R, false, false, false>(sm.rec, d, tsh, kq, nint, lane, 0u, out, vec);
         }
     } else {
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-            const uint32_t q = (uint32_t)r * 64u + lane;
-            u32x4 v = {0u, 0u, 0u, 0u};
-            if (good && 4u * q < c.nint) v = extract_quad(sm.rec[q >> tsh], q, kq, rows, nrow);
-            store_quad(out, 4u * q, c.nint, vec, v);
-        }
+        s = tile_quads<R, SUM>(sm.rec, tsh, kq, rows, nrow, nint, lane, c.h.delta, carry0, out, vec);
+    }
+    if constexpr (SUM) {
+        const uint32_t t = wave_sum(s);
+        if (lane == 0) a.carry[gi] = t;
     }
 }
 

@@ -171,9 +171,7 @@ struct gc_plan {
     uint32_t *bound_out = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraph_t graph_a = nullptr, graph_b = nullptr;    // timing: one graph per kernel group
-    hipGraphExec_t exec_a = nullptr, exec_b = nullptr;
-    std::vector<hipEvent_t> ev;                // 3 per timing slot
+    std::vector<hipEvent_t> ev;                // kEvPerSlot per timing slot
     uint32_t slots = 0;
     uint64_t runs = 0;
 };
@@ -326,10 +324,8 @@ void build_tables(gc_plan *p) {
 }
 
 void plan_free_graphs(gc_plan *p) {
-    for (hipGraphExec_t *e : {&p->exec, &p->exec_a, &p->exec_b})
-        if (*e) (void)hipGraphExecDestroy(*e), *e = nullptr;
-    for (hipGraph_t *g : {&p->graph, &p->graph_a, &p->graph_b})
-        if (*g) (void)hipGraphDestroy(*g), *g = nullptr;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec), p->exec = nullptr;
+    if (p->graph) (void)hipGraphDestroy(p->graph), p->graph = nullptr;
 }
 
 void plan_free_device(gc_plan *p) {
@@ -378,40 +374,52 @@ gc_status plan_materialize(gc_plan *p) {
     return rc;
 }
 
-// Launches the locate kernels (which & 1) and the per-class decode passes
-// (which & 2) on stream s; with `fork` streams the classes run as parallel
-// branches that s waits for.
-gc_status plan_launch(gc_plan *p, hipStream_t s, int which, hipStream_t *fork = nullptr,
-                      hipEvent_t *fev = nullptr) {
+// Launches the locate kernels of every list on stream s.
+gc_status launch_locate_all(gc_plan *p, hipStream_t s) {
+    if (!p->total_a) return GC_OK;
     ListDesc none;
     std::memset(&none, 0, sizeof(none));
-    if (p->total_a && (which & 1)) {
-        LocateArgs a = make_locate_args(p->d_lists, p->d_item_a, p->d_item_s, none, p->total_a, p->total_s,
-                                        p->sc, p->ctx->status);
-        if (launch_locate(a, s)) return GC_EDEVICE;
+    LocateArgs a = make_locate_args(p->d_lists, p->d_item_a, p->d_item_s, none, p->total_a, p->total_s, p->sc,
+                                    p->ctx->status);
+    return launch_locate(a, s) ? GC_EDEVICE : GC_OK;
+}
+
+// Launches the passes of codec class c on stream s: tile sums and carry scan
+// (delta lists of more than one tile), then the decode pass.  `mid`, if
+// given, is recorded between the two.
+gc_status launch_class(gc_plan *p, int c, hipStream_t s, hipEvent_t mid = nullptr) {
+    const ClassRange &r = p->cr[c];
+    if (!r.count) return GC_OK;
+    ListDesc none;
+    std::memset(&none, 0, sizeof(none));
+    const int tile = c == kClsPfd ? p->tile_p : p->tile_w;
+    if (r.sum) {
+        DecodeArgs d = make_decode_args(p->d_lists, p->d_tile_list, none, r.lo, r.sum, p->sc, p->ctx->status);
+        if (launch_decode(tile, c, true, d, s)) return GC_EDEVICE;
+        CarryArgs ca = make_carry_args(p->d_lists, p->d_scan_list + r.scan_lo, none, r.scans, p->sc);
+        if (launch_carry_scan(ca, s)) return GC_EDEVICE;
     }
-    if (!(which & 2)) return GC_OK;
+    if (mid) HIP_OK(hipEventRecord(mid, s));
+    DecodeArgs d = make_decode_args(p->d_lists, p->d_tile_list, none, r.lo, r.count, p->sc, p->ctx->status);
+    return launch_decode(tile, c, false, d, s) ? GC_EDEVICE : GC_OK;
+}
+
+// Launches a whole run on stream s; with `fork` streams the classes run as
+// parallel branches that s waits for.
+gc_status plan_launch(gc_plan *p, hipStream_t s, hipStream_t *fork = nullptr, hipEvent_t *fev = nullptr) {
+    if (gc_status rc = launch_locate_all(p, s)) return rc;
     int nact = 0;
     for (int c = 0; c < kClasses; c++) nact += p->cr[c].count ? 1 : 0;
     const bool par = fork && nact > 1;
     if (par) HIP_OK(hipEventRecord(fev[kClasses], s));
     for (int c = 0; c < kClasses; c++) {
-        const ClassRange &r = p->cr[c];
-        if (!r.count) continue;
+        if (!p->cr[c].count) continue;
         hipStream_t cs = s;
         if (par) {
             cs = fork[c];
             HIP_OK(hipStreamWaitEvent(cs, fev[kClasses], 0));
         }
-        const int tile = c == kClsPfd ? p->tile_p : p->tile_w;
-        if (r.sum) {
-            DecodeArgs d = make_decode_args(p->d_lists, p->d_tile_list, none, r.lo, r.sum, p->sc, p->ctx->status);
-            if (launch_decode(tile, c, true, d, cs)) return GC_EDEVICE;
-            CarryArgs ca = make_carry_args(p->d_lists, p->d_scan_list + r.scan_lo, none, r.scans, p->sc);
-            if (launch_carry_scan(ca, cs)) return GC_EDEVICE;
-        }
-        DecodeArgs d = make_decode_args(p->d_lists, p->d_tile_list, none, r.lo, r.count, p->sc, p->ctx->status);
-        if (launch_decode(tile, c, false, d, cs)) return GC_EDEVICE;
+        if (gc_status rc = launch_class(p, c, cs)) return rc;
         if (par) {
             HIP_OK(hipEventRecord(fev[c], cs));
             HIP_OK(hipStreamWaitEvent(s, fev[c], 0));
@@ -419,7 +427,8 @@ gc_status plan_launch(gc_plan *p, hipStream_t s, int which, hipStream_t *fork = 
     }
     return GC_OK;
 }
-gc_status capture_one(gc_plan *p, int which, hipGraph_t *graph, hipGraphExec_t *exec) {
+
+gc_status capture_one(gc_plan *p, hipGraph_t *graph, hipGraphExec_t *exec) {
     hipStream_t s, fork[kClasses];
     hipEvent_t fev[kClasses + 1];
     HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -429,7 +438,7 @@ gc_status capture_one(gc_plan *p, int which, hipGraph_t *graph, hipGraphExec_t *
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         rc = GC_EDEVICE;
     } else {
-        rc = plan_launch(p, s, which, fork, fev);
+        rc = plan_launch(p, s, fork, fev);
         hipGraph_t g = nullptr;
         if (hipStreamEndCapture(s, &g) != hipSuccess || rc) {
             rc = GC_EDEVICE;
@@ -448,31 +457,33 @@ gc_status capture_one(gc_plan *p, int which, hipGraph_t *graph, hipGraphExec_t *
 
 gc_status plan_capture(gc_plan *p) {
     plan_free_graphs(p);
-    if (p->slots) {
-        gc_status rc = capture_one(p, 1, &p->graph_a, &p->exec_a);
-        return rc ? rc : capture_one(p, 2, &p->graph_b, &p->exec_b);
-    }
-    return capture_one(p, 3, &p->graph, &p->exec);
+    return capture_one(p, &p->graph, &p->exec);
 }
+
+// Events of one timing slot: run start, locate end, then per class: before
+// its sum pass, before its decode pass, after its decode pass.
+constexpr int kEvPerSlot = 2 + 3 * kClasses;
 
 gc_status plan_run(gc_plan *p, hipStream_t s) {
     if (p->slots) {
-        const size_t k = (size_t)(p->runs % p->slots) * 3;
+        hipEvent_t *e = &p->ev[(size_t)(p->runs % p->slots) * kEvPerSlot];
         p->runs++;
-        HIP_OK(hipEventRecord(p->ev[k], s));
-        if (p->use_graph && p->exec_a) HIP_OK(hipGraphLaunch(p->exec_a, s));
-        else if (gc_status rc = plan_launch(p, s, 1)) return rc;
-        HIP_OK(hipEventRecord(p->ev[k + 1], s));
-        if (p->use_graph && p->exec_b) HIP_OK(hipGraphLaunch(p->exec_b, s));
-        else if (gc_status rc = plan_launch(p, s, 2)) return rc;
-        HIP_OK(hipEventRecord(p->ev[k + 2], s));
+        HIP_OK(hipEventRecord(e[0], s));
+        if (gc_status rc = launch_locate_all(p, s)) return rc;
+        HIP_OK(hipEventRecord(e[1], s));
+        for (int c = 0; c < kClasses; c++) {
+            if (!p->cr[c].count) continue;
+            HIP_OK(hipEventRecord(e[2 + 3 * c], s));
+            if (gc_status rc = launch_class(p, c, s, e[3 + 3 * c])) return rc;
+            HIP_OK(hipEventRecord(e[4 + 3 * c], s));
+        }
         return GC_OK;
     }
     if (p->use_graph && p->exec) {
         HIP_OK(hipGraphLaunch(p->exec, s));
         return GC_OK;
     }
-    return plan_launch(p, s, 3);
+    return plan_launch(p, s);
 }
 
 // ---- autotune cache: one JSON object {key: [tile, pfd_tile], ...} --------
@@ -578,10 +589,10 @@ gc_status autotune(gc_plan *p, const uint32_t *d_streams, uint32_t *d_out) {
             p->tile_p = tp;
             rc = plan_materialize(p);
             if (!rc) rc = plan_upload(p, d_streams, d_out);
-            for (int w = 0; w < 2 && !rc; w++) rc = plan_launch(p, nullptr, 3);
+            for (int w = 0; w < 2 && !rc; w++) rc = plan_launch(p, nullptr);
             if (rc) break;
             HIP_OK(hipEventRecord(e0, nullptr));
-            for (int r = 0; r < 5 && !rc; r++) rc = plan_launch(p, nullptr, 3);
+            for (int r = 0; r < 5 && !rc; r++) rc = plan_launch(p, nullptr);
             HIP_OK(hipEventRecord(e1, nullptr));
             HIP_OK(hipEventSynchronize(e1));
             float ms = 0;
@@ -738,7 +749,7 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     (void)hipSetDevice(ctx->device);
     gc_status rc = GC_OK;
     if (o.autotune && nlists && !o.tile_ints && !o.pfd_tile_ints) rc = autotune(p, d_streams, d_out);
-    for (uint32_t i = 0; i < 3 * p->slots && !rc; i++) {
+    for (uint32_t i = 0; i < (uint32_t)kEvPerSlot * p->slots && !rc; i++) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) rc = GC_EDEVICE;
         else p->ev.push_back(e);
@@ -791,17 +802,26 @@ gc_status gc_decode_each(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_o
     return GC_OK;
 }
 
-gc_status gc_plan_timings(gc_plan *plan, uint32_t max_runs, float *locate_ms, float *decode_ms,
-                          uint32_t *nruns) {
-    if (!plan || !plan->slots || !locate_ms || !decode_ms || !nruns) return GC_EINVAL;
+gc_status gc_plan_timings(gc_plan *plan, uint32_t max_runs, float *ms, uint32_t *nruns) {
+    if (!plan || !plan->slots || !ms || !nruns) return GC_EINVAL;
     const uint64_t avail = std::min<uint64_t>(plan->runs, plan->slots);
     const uint32_t n = (uint32_t)std::min<uint64_t>(avail, max_runs);
     for (uint32_t i = 0; i < n; i++) {
         const uint64_t run = plan->runs - n + i;
-        const size_t k = (size_t)(run % plan->slots) * 3;
-        HIP_OK(hipEventSynchronize(plan->ev[k + 2]));
-        HIP_OK(hipEventElapsedTime(&locate_ms[i], plan->ev[k], plan->ev[k + 1]));
-        HIP_OK(hipEventElapsedTime(&decode_ms[i], plan->ev[k + 1], plan->ev[k + 2]));
+        hipEvent_t *e = &plan->ev[(size_t)(run % plan->slots) * kEvPerSlot];
+        float *row = ms + (size_t)i * GC_TIMING_FIELDS;
+        for (int f = 0; f < GC_TIMING_FIELDS; f++) row[f] = 0.0f;
+        hipEvent_t last = e[1];
+        for (int c = 0; c < kClasses; c++) {
+            if (!plan->cr[c].count) continue;
+            HIP_OK(hipEventSynchronize(e[4 + 3 * c]));
+            HIP_OK(hipEventElapsedTime(&row[2 + kClasses + c], e[2 + 3 * c], e[3 + 3 * c]));
+            HIP_OK(hipEventElapsedTime(&row[2 + c], e[3 + 3 * c], e[4 + 3 * c]));
+            last = e[4 + 3 * c];
+        }
+        HIP_OK(hipEventSynchronize(last));
+        HIP_OK(hipEventElapsedTime(&row[0], e[0], last));
+        HIP_OK(hipEventElapsedTime(&row[1], e[0], e[1]));
     }
     *nruns = n;
     return GC_OK;

@@ -21,6 +21,10 @@ SIMPLE, SCHEME, AFOR, PFD = 0, 1, 2, 3
 LD_BINARY, LD_CU, LD_IU = 0, 1, 2
 PFD_LINKED, PFD_BITMAP = 0, 1
 DELTA = 1
+# decode kernel classes (gc_plan_timings columns)
+CLS_SIMPLE, CLS_SCHEME_UNARY, CLS_SCHEME_BINARY, CLS_AFOR, CLS_PFD = range(5)
+CLASSES = 5
+TIMING_FIELDS = 2 + 2 * CLASSES
 OK, EINVAL, ENOSPC, ECORRUPT, EDEVICE, EUNSUPPORTED, ENOMEM = 0, -1, -2, -3, -4, -5, -6
 _NAMES = {0: "GC_OK", -1: "GC_EINVAL", -2: "GC_ENOSPC", -3: "GC_ECORRUPT", -4: "GC_EDEVICE",
           -5: "GC_EUNSUPPORTED", -6: "GC_ENOMEM"}
@@ -94,7 +98,7 @@ def lib():
         L.gc_decode_each.argtypes = [vp, vp, vp, vp]
         L.gc_plan_config.argtypes = [vp, u32p, u32p, u64p, u64p]
         f32p = ctypes.POINTER(ctypes.c_float)
-        L.gc_plan_timings.argtypes = [vp, ctypes.c_uint32, f32p, f32p, u32p]
+        L.gc_plan_timings.argtypes = [vp, ctypes.c_uint32, f32p, u32p]
         L.gc_plan_timings.restype = ctypes.c_int
         L.gc_sync_status.argtypes = [vp, vp, u32p]
         for f in ("gc_encode", "gc_encode_lists", "gc_ctx_create", "gc_ctx_destroy", "gc_decode",
@@ -242,12 +246,15 @@ class Plan:
                                                       _stream_handle(stream)))
 
     def timings(self, max_runs):
-        """(locate_ms, decode_ms) arrays for the last runs, oldest first."""
-        a = (ctypes.c_float * max(max_runs, 1))()
-        b = (ctypes.c_float * max(max_runs, 1))()
+        """Per-run kernel times (ms) of the last runs, oldest first: a dict of
+        arrays -- total, locate, decode[class], sum[class] (classes in the
+        order SIMPLE, SCHEME unary, SCHEME binary, AFOR, PFD)."""
+        a = (ctypes.c_float * (max(max_runs, 1) * TIMING_FIELDS))()
         n = ctypes.c_uint32()
-        _check("gc_plan_timings", lib().gc_plan_timings(self._h, int(max_runs), a, b, ctypes.byref(n)))
-        return np.array(a[:n.value]), np.array(b[:n.value])
+        _check("gc_plan_timings", lib().gc_plan_timings(self._h, int(max_runs), a, ctypes.byref(n)))
+        m = np.array(a[:n.value * TIMING_FIELDS], dtype=np.float64).reshape(n.value, TIMING_FIELDS)
+        return dict(total=m[:, 0], locate=m[:, 1], decode=m[:, 2:2 + CLASSES],
+                    sum=m[:, 2 + CLASSES:2 + 2 * CLASSES])
 
     def config(self):
         """Chosen tile sizes, decode tiles per run and the tiles of those the
