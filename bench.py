@@ -162,6 +162,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip per-list and per-codec runs")
     ap.add_argument("--tile", type=int, default=0, help="force the wave-tile size (0 = autotune)")
     ap.add_argument("--pfd-tile", type=int, default=0, help="force the Group-PFD tile size (with --tile)")
+    ap.add_argument("--locate-stream", action="store_true",
+                    help="run the locate kernels on a second stream, ahead of the other kernels")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the decode path is built and measured on a single "
@@ -186,7 +188,7 @@ def main():
     d_s = gc.to_device(streams)
     d_o = torch.empty(out_len, dtype=torch.int32, device="cuda")
     t = time.time()
-    plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=args.tile,
+    plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=args.tile, locate_stream=args.locate_stream,
                    pfd_tile_ints=args.pfd_tile or (4096 if args.tile else 0),
                    autotune=args.tile == 0, timing_slots=args.steps + args.warmup)
     cfg = plan.config()
@@ -209,8 +211,8 @@ def main():
     cls_bytes = class_bytes(gc, parts, cls)
     dec_avg = float(dec[cls])
     achieved = cls_bytes / (dec_avg * 1e-3) / 1e9
-    log("step %.3f ms  %.1f Gints/s  (GPU %.3f ms: locate %.3f, sum+carry %s, decode %s)  verified=%s"
-        % (ms_per_step, value, tm["total"].mean(), tm["locate"].mean(),
+    log("step %.3f ms  %.1f Gints/s  (GPU %.3f ms; per class locate %s, sum+carry %s, decode %s)  verified=%s"
+        % (ms_per_step, value, tm["total"].mean(), np.round(tm["locate"].mean(axis=0), 3),
            np.round(tm["sum"].mean(axis=0), 3), np.round(dec, 3), verified))
     log("dominant kernel: %s decode pass %.3f ms, %.0f GB/s" % (CLASS_NAMES[cls], dec_avg, achieved))
     if not verified:
@@ -248,7 +250,7 @@ def main():
             per[sub[0]["name"]] = dict(gints_s=round(n2 / (el / args.steps) / 1e9, 2),
                                        bits_per_int_docids=round(32.0 * sub[0]["streams"].size / n2 * 2, 3),
                                        bits_per_int_tf=round(32.0 * sub[1]["streams"].size / n2 * 2, 3),
-                                       locate_ms=round(float(t2["locate"].mean()), 4),
+                                       locate_ms=round(float(t2["locate"][:, c2].mean()), 4),
                                        sum_ms=round(float(t2["sum"][:, c2].mean()), 4),
                                        decode_ms=round(float(t2["decode"][:, c2].mean()), 4),
                                        decode_kernel_gbs=round(gbs, 1),
@@ -306,7 +308,8 @@ def main():
         },
         "phases_ms": {
             "gpu_total": round(float(tm["total"].mean()), 4),
-            "locate": round(float(tm["locate"].mean()), 4),
+            "locate": {CLASS_NAMES[c]: round(float(tm["locate"][:, c].mean()), 4)
+                       for c in range(5) if dec[c] > 0},
             "sum_and_carry": {CLASS_NAMES[c]: round(float(tm["sum"][:, c].mean()), 4)
                               for c in range(5) if dec[c] > 0},
             "decode": {CLASS_NAMES[c]: round(float(dec[c]), 4) for c in range(5) if dec[c] > 0},

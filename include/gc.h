@@ -152,7 +152,10 @@ typedef struct {
     uint32_t timing_slots;   /* > 0: time the kernels of each gc_decode_batch with
                                 HIP events, in this many rotating slots (see
                                 gc_plan_timings); the run is then not graphed  */
-    uint32_t reserved[3];    /* zero */
+    uint32_t schedule;       /* 0: every kernel on the launch stream, class by
+                                class; 1: the locate kernels of every class on a
+                                second stream, ahead of the other kernels      */
+    uint32_t reserved[2];    /* zero */
 } gc_plan_opts;
 
 /* Builds a batched decode plan for nlists lists.  h_headers holds the first
@@ -181,20 +184,22 @@ gc_status gc_decode_each(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_o
                          void *hip_stream);
 
 /* Kernel durations of the last runs of a plan created with timing_slots > 0.
- * Such a plan launches its kernels directly (no graph), one codec class
- * after another, with HIP events between them on the launch stream.  This
- * synchronises those events and writes, oldest run first, up to max_runs rows
- * of GC_TIMING_FIELDS floats (milliseconds) to ms:
- *   [0]                     the whole run
- *   [1]                     the locate kernels
- *   [2 + c]                 the decode pass of codec class c
- *   [2 + GC_CLASSES + c]    the tile-sum pass and carry scan of class c
+ * Such a plan launches its kernels directly (no graph), with HIP events
+ * around each phase on the stream that runs it (the locate kernels on the
+ * plan's second stream when opts->schedule is 1).  This synchronises those
+ * events and writes, oldest run first, up to max_runs rows of
+ * GC_TIMING_FIELDS floats (milliseconds) to ms:
+ *   [0]                         the whole run, on the launch stream
+ *   [1 + c]                     the locate kernels of codec class c
+ *   [1 + GC_CLASSES + c]        its tile-sum pass and carry scan
+ *   [1 + 2 * GC_CLASSES + c]    its decode pass
  * with classes c = 0 Group-Simple, 1 Group-Scheme with unary descriptors,
  * 2 Group-Scheme with binary descriptors, 3 Group-AFOR, 4 Group-PFD (0 for a
- * class the plan does not hold).  *nruns receives the rows written.
- * GC_EINVAL if the plan records no events.                                 */
+ * class the plan does not hold).  Locate kernels overlap the other phases,
+ * so the phases need not add up to the whole run.  *nruns receives the rows
+ * written.  GC_EINVAL if the plan records no events.                       */
 #define GC_CLASSES 5
-#define GC_TIMING_FIELDS (2 + 2 * GC_CLASSES)
+#define GC_TIMING_FIELDS (1 + 3 * GC_CLASSES)
 gc_status gc_plan_timings(gc_plan *plan, uint32_t max_runs, float *ms, uint32_t *nruns);
 
 /* Reports the chosen configuration of a plan: the wave-tile and Group-PFD

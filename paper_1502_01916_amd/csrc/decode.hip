@@ -289,8 +289,8 @@ __device__ __forceinline__ void locate_thread(const ListDesc &L, uint32_t chunk,
 __device__ __forceinline__ bool locate_item(const LocateArgs &a, uint32_t item, ListDesc &L, uint32_t &chunk) {
     if (item >= a.total_items) return false;
     if (a.lists) {
-        L = a.lists[a.item_list[item]];
-        chunk = item - L.chunk_base;
+        L = a.lists[a.item_list[a.item_lo + item]];
+        chunk = a.item_lo + item - L.chunk_base;
     } else {
         L = a.single;
         chunk = item;
@@ -820,7 +820,7 @@ struct WaveSmem {
         u32x4 data[NB];
         uint32_t ctrl[4 * NB];
     };
-    uint32_t rec[TTM];
+    uint32_t rec[TTM + 4];   // + room for one more entry while the records are built
 };
 
 // Orders a wave's LDS writes before its later LDS reads by other lanes.
@@ -945,9 +945,19 @@ __device__ uint32_t wprologue_sim(const TileCtx &c, WaveSmem<TW, kClsSim> &sm, u
 }
 
 // ---- Group-Scheme, unary descriptors ----------------------------------------
+// Every 0 bit of the control area ends one tuple's code (bits outside the
+// tile's [p0, p1) read as 1).  The control bits are split into 64 ranges of
+// equal length; each lane counts the terminators in its range and, after a
+// wave scan of the counts, writes their positions in rank order to Z (a
+// compaction with Z[0] = the position just before the tile).  Lane l then
+// turns Z[l*TPL .. l*TPL + TPL] into the records of its TPL tuples: a code
+// spans the bits after the previous terminator up to its own (incomplete
+// units: not across a byte, so it starts at the byte boundary at the
+// latest), and its data follow the data of the codes before it.
 template <int TW>
 __device__ uint32_t wprologue_gscu(const TileCtx &c, WaveSmem<TW, kClsGscU> &sm, uint32_t lane, uint32_t &dbase) {
     using SM = WaveSmem<TW, kClsGscU>;
+    constexpr int TPL = SM::TTM / 64;
     const uint32_t cg = (uint32_t)c.h.cg, umax = 32u / cg;
     const bool iu = c.h.ld == GC_LD_IU;
     const uint32_t p0 = c.st.unit;
@@ -955,67 +965,78 @@ __device__ uint32_t wprologue_gscu(const TileCtx &c, WaveSmem<TW, kClsGscU> &sm,
     const uint32_t cw0 = p0 >> 5, cw1 = (p1 + 31u) >> 5;
     const uint32_t nctrl = cw1 - cw0;
     if (!(p1 >= p0 && cw1 <= c.C && nctrl <= (uint32_t)SM::NCTRL)) return kErrRange;
+    const gu32 *ctrl = (const gu32 *)c.ctrl;
     for (uint32_t i = lane; i < nctrl; i += 64u) {
-        // only bits in [p0, p1) belong to the tile: the others read as 1
         const uint32_t gw = cw0 + i;
-        uint32_t v = c.ctrl[gw];
+        uint32_t v = ctrl[gw];
         if (gw == cw0 && (p0 & 31u)) v |= (1u << (p0 & 31u)) - 1u;
         if (gw == (p1 >> 5) && (p1 & 31u)) v |= ~((1u << (p1 & 31u)) - 1u);
         sm.ctrl[i] = v;
     }
     const uint64_t abs0 = iu ? c.st.data : (uint64_t)cg * p0;
     dbase = (uint32_t)(abs0 >> 5);
+    const uint32_t p0r = p0 & 31u;   // bit positions count from 32 * cw0
     wave_lds_sync();
-    const uint32_t wpt = (nctrl + 63u) / 64u;
-    const uint32_t wl0 = min(lane * wpt, nctrl), wl1 = min(wl0 + wpt, nctrl);
-    // where this lane's first code starts: after the last terminator of the
-    // tile's earlier words, else at p0
-    uint32_t start0 = p0;
-    if (wl0 < wl1)
-        for (uint32_t wl = wl0; wl-- > 0u;) {
-            const uint32_t z = ~sm.ctrl[wl];
-            if (z) {
-                start0 = 32u * (cw0 + wl) + 32u - (uint32_t)__builtin_clz(z);
-                break;
-            }
-        }
-    uint32_t cnt = 0, usum = 0;
-    bool bad = false;
-    {
-        uint32_t nxt = start0;
-        for (uint32_t wl = wl0; wl < wl1; wl++) {
-            uint32_t z = ~sm.ctrl[wl];
-            cnt += (uint32_t)__builtin_popcount(z);
-            while (z) {
-                const uint32_t zp = 32u * (cw0 + wl) + (uint32_t)__builtin_ctz(z);
-                z &= z - 1u;
-                const uint32_t start = iu ? max(nxt, zp & ~7u) : nxt;
-                const uint32_t u = zp - start + 1u;
-                bad |= u > umax;
-                usum += u;
-                nxt = zp + 1u;
-            }
+    const uint32_t nbits = 32u * nctrl;
+    const uint32_t B = (nbits + 63u) >> 6;
+    const uint32_t ra = min(lane * B, nbits), rb = min(ra + B, nbits);
+    const uint32_t wa = ra >> 5, wb = (rb + 31u) >> 5;
+    auto zeros = [&](uint32_t w) -> uint32_t {   // terminators of word w inside [ra, rb)
+        uint32_t z = ~sm.ctrl[w];
+        const uint32_t lo = 32u * w;
+        if (ra > lo) z &= ~0u << (ra - lo);
+        if (rb < lo + 32u) z &= (1u << (rb - lo)) - 1u;
+        return z;
+    };
+    uint32_t cnt = 0;
+    for (uint32_t w = wa; w < wb; w++) cnt += (uint32_t)__builtin_popcount(zeros(w));
+    const uint32_t ic = wave_incl_scan(cnt);
+    const uint32_t tcnt = (uint32_t)__builtin_amdgcn_readlane((int)ic, 63);
+    if (tcnt < c.ntup) return kErrCount;
+    uint32_t *Z = sm.rec;   // Z[r + 1] = position of terminator r; read before the records overwrite it
+    if (lane == 0) Z[0] = p0r - 1u;
+    uint32_t r = ic - cnt;
+    for (uint32_t w = wa; w < wb && r < c.ntup; w++) {
+        uint32_t z = zeros(w);
+        while (z && r < c.ntup) {
+            Z[++r] = 32u * w + (uint32_t)__builtin_ctz(z);
+            z &= z - 1u;
         }
     }
-    const uint32_t ic = wave_incl_scan(cnt), iu_s = wave_incl_scan(usum);
-    const uint32_t tcnt = (uint32_t)__builtin_amdgcn_readlane((int)ic, 63);
+    wave_lds_sync();
+    const uint32_t t0 = lane * (uint32_t)TPL;
+    uint32_t zr[TPL + 1];
+#pragma unroll
+    for (int i = 0; i <= TPL; i++) zr[i] = Z[min(t0 + (uint32_t)i, c.ntup)];
+    uint32_t st[TPL], un[TPL];
+    uint32_t usum = 0;
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < TPL; i++) {
+        const bool in = t0 + (uint32_t)i < c.ntup;
+        const uint32_t zp = zr[i + 1];
+        const uint32_t start = iu ? max(zr[i] + 1u, zp & ~7u) : zr[i] + 1u;
+        const uint32_t u = zp - start + 1u;
+        bad |= in && (u > umax || zp < start);
+        st[i] = start;
+        un[i] = in ? min(u, umax) : 0u;
+        usum += un[i];
+    }
     if (wave_any(bad)) return kErrUnary;
-    if (tcnt < c.ntup) return kErrCount;
-    uint32_t nxt = start0, t = ic - cnt, us = iu_s - usum;
+    uint32_t us = iu ? wave_incl_scan(usum) - usum : 0u;
     const uint32_t rel0 = (uint32_t)(abs0 & 31u);
-    for (uint32_t wl = wl0; wl < wl1 && t < c.ntup; wl++) {
-        uint32_t z = ~sm.ctrl[wl];
-        while (z && t < c.ntup) {
-            const uint32_t zp = 32u * (cw0 + wl) + (uint32_t)__builtin_ctz(z);
-            z &= z - 1u;
-            const uint32_t start = iu ? max(nxt, zp & ~7u) : nxt;
-            const uint32_t u = min(zp - start + 1u, umax);
-            const uint32_t rel = iu ? rel0 + cg * us : (uint32_t)((uint64_t)cg * start - 32ull * dbase);
-            sm.rec[t] = rec_pack(rel, cg * u);
-            t++;
-            us += u;
-            nxt = zp + 1u;
+    u32x4 *r4 = reinterpret_cast<u32x4 *>(sm.rec) + lane * (uint32_t)(TPL / 4);
+#pragma unroll
+    for (int v = 0; v < TPL / 4; v++) {
+        uint32_t o[4];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int i = 4 * v + e;
+            const uint32_t rel = iu ? rel0 + cg * us : rel0 + cg * (st[i] - p0r);
+            o[e] = rec_pack(rel, cg * un[i]);
+            us += un[i];
         }
+        r4[v] = u32x4{o[0], o[1], o[2], o[3]};
     }
     wave_lds_sync();
     return 0;

@@ -68,8 +68,10 @@ struct LocateArgs {
     const uint32_t *item_list;  // chunk work item -> list (batch)
     const uint32_t *scan_list;  // scan work item -> list (batch)
     ListDesc single;
-    uint32_t total_items;       // chunk items (batch or single)
+    uint32_t total_items;       // chunk items of this launch (batch or single)
     uint32_t total_scan;        // lists with chunks (batch); 1 for single
+    uint32_t item_lo;           // batch: first chunk item of this launch
+    uint32_t pad;
     TileInfo *tiles;
     LocVal *agg;                // per chunk aggregate
     LocVal *pre;                // per chunk exclusive prefix within its list

@@ -82,20 +82,21 @@ void dev_free(T *&p) {
     p = nullptr;
 }
 
-// Device scratch of one launch sequence: the locate epoch, the tile starts,
-// the tile carries and the locate chunk aggregates and prefixes.
+// Device scratch of one launch sequence: the locate epoch of every codec
+// class, the tile starts, the tile carries and the locate chunk aggregates
+// and prefixes.
 struct Scratch {
-    RunState *state = nullptr;
+    RunState *state = nullptr;          // [class]
     TileInfo *tiles = nullptr;
     uint32_t *carry = nullptr;
     LocVal *agg = nullptr, *pre = nullptr;
     size_t tiles_cap = 0, chunks_cap = 0;
 
     gc_status init_state() {
-        gc_status rc = dev_alloc(&state, 1);
+        gc_status rc = dev_alloc(&state, kClasses);
         if (rc) return rc;
-        const RunState h = {1u, {0u, 0u, 0u}};
-        HIP_OK(hipMemcpy(state, &h, sizeof(h), hipMemcpyHostToDevice));
+        std::vector<RunState> h(kClasses, RunState{1u, {0u, 0u, 0u}});
+        HIP_OK(hipMemcpy(state, h.data(), h.size() * sizeof(RunState), hipMemcpyHostToDevice));
         return GC_OK;
     }
     gc_status reserve(size_t ntiles, size_t nchunks) {
@@ -145,6 +146,10 @@ struct gc_ctx {
 // Tiles are numbered class by class; within a class the delta lists of more
 // than one tile come first, so one launch range covers each pass.
 struct ClassRange {
+    uint32_t loc_lo = 0;    // first locate chunk item of the class
+    uint32_t loc_count = 0; // its locate chunk items
+    uint32_t lsc_lo = 0;    // first locate scan item (a list with chunks)
+    uint32_t lsc_count = 0;
     uint32_t lo = 0;        // first tile of the class
     uint32_t count = 0;     // tiles of the class
     uint32_t sum = 0;       // leading tiles that need a tile sum
@@ -172,6 +177,8 @@ struct gc_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<hipEvent_t> ev;                // kEvPerSlot per timing slot
+    hipStream_t aux = nullptr;                 // timing: the locate stream
+    bool serial = true;                        // no locate stream
     uint32_t slots = 0;
     uint64_t runs = 0;
 };
@@ -179,7 +186,8 @@ struct gc_plan {
 namespace {
 
 LocateArgs make_locate_args(const ListDesc *lists, const uint32_t *item_list, const uint32_t *scan_list,
-                            const ListDesc &single, uint32_t total, uint32_t total_scan, Scratch &sc, Status *st) {
+                            const ListDesc &single, uint32_t total, uint32_t total_scan, int cls, Scratch &sc,
+                            Status *st) {
     LocateArgs a;
     std::memset(&a, 0, sizeof(a));
     a.lists = lists;
@@ -191,13 +199,13 @@ LocateArgs make_locate_args(const ListDesc *lists, const uint32_t *item_list, co
     a.tiles = sc.tiles;
     a.agg = sc.agg;
     a.pre = sc.pre;
-    a.state = sc.state;
+    a.state = sc.state + cls;
     a.status = st;
     return a;
 }
 
 DecodeArgs make_decode_args(const ListDesc *lists, const uint32_t *tile_list, const ListDesc &single, uint32_t lo,
-                            uint32_t count, Scratch &sc, Status *st) {
+                            uint32_t count, int cls, Scratch &sc, Status *st) {
     DecodeArgs a;
     std::memset(&a, 0, sizeof(a));
     a.lists = lists;
@@ -207,7 +215,7 @@ DecodeArgs make_decode_args(const ListDesc *lists, const uint32_t *tile_list, co
     a.count = count;
     a.tiles = sc.tiles;
     a.carry = sc.carry;
-    a.loc_state = sc.state;
+    a.loc_state = sc.state + cls;
     a.status = st;
     return a;
 }
@@ -250,18 +258,18 @@ int min_wave_tile(const gc_plan *p) {
 }
 
 // Single-list view of list L for the per-list paths: its own tile range.
-DecodeArgs single_args(const ListDesc &L, Scratch &sc, Status *st) {
-    return make_decode_args(nullptr, nullptr, L, L.tile_base, L.ntiles, sc, st);
+DecodeArgs single_args(const ListDesc &L, int cls, Scratch &sc, Status *st) {
+    return make_decode_args(nullptr, nullptr, L, L.tile_base, L.ntiles, cls, sc, st);
 }
 
 // Launches every pass of one list on stream s (the per-list paths).
 gc_status launch_one(const ListDesc &L, int cls, Scratch &sc, Status *st, hipStream_t s) {
     if (L.ntiles > 1) {
-        LocateArgs a = make_locate_args(nullptr, nullptr, nullptr, L, L.nchunks, 1, sc, st);
+        LocateArgs a = make_locate_args(nullptr, nullptr, nullptr, L, L.nchunks, 1, cls, sc, st);
         if (launch_locate(a, s)) return GC_EDEVICE;
     }
     const int tile = (int)L.tile_ints;
-    const DecodeArgs d = single_args(L, sc, st);
+    const DecodeArgs d = single_args(L, cls, sc, st);
     if (L.ntiles > 1 && is_delta(L.w0)) {
         if (launch_decode(tile, cls, true, d, s)) return GC_EDEVICE;
         if (launch_carry_scan(make_carry_args(nullptr, nullptr, L, 1, sc), s)) return GC_EDEVICE;
@@ -277,26 +285,36 @@ void build_tables(gc_plan *p) {
     p->item_s.clear();
     p->tile_list.clear();
     p->scan_list.clear();
-    uint32_t cb = 0;
     for (size_t i = 0; i < p->nlists; i++) {
         ListDesc &L = p->h_lists[i];
         L.tile_ints = (uint32_t)(p->cls[i] == kClsPfd ? p->tile_p : p->tile_w);
         L.ntiles = (uint32_t)((L.n + (uint64_t)L.tile_ints - 1) / (uint64_t)L.tile_ints);
-        L.chunk_base = cb;
         L.nchunks = 0;
         if (L.ntiles > 1) {
             HeaderFields h;
             header_fields(L.w0, h);
             L.nchunks = list_chunks(h, L.n, L.C, L.D);
         }
-        for (uint32_t c = 0; c < L.nchunks; c++) p->item_a.push_back((uint32_t)i);
-        if (L.nchunks) p->item_s.push_back((uint32_t)i);
-        cb += L.nchunks;
     }
-    uint32_t tb = 0;
+    // Locate items, tiles and carry scans are numbered class by class, so
+    // each class's kernels cover one range of each table.  Within a class
+    // the delta lists of more than one tile come first.
+    uint32_t cb = 0, tb = 0;
     for (int c = 0; c < kClasses; c++) {
         ClassRange &r = p->cr[c];
         r = ClassRange{};
+        r.loc_lo = cb;
+        r.lsc_lo = (uint32_t)p->item_s.size();
+        for (size_t i = 0; i < p->nlists; i++) {
+            ListDesc &L = p->h_lists[i];
+            if (p->cls[i] != c || !L.nchunks) continue;
+            L.chunk_base = cb;
+            for (uint32_t k = 0; k < L.nchunks; k++) p->item_a.push_back((uint32_t)i);
+            p->item_s.push_back((uint32_t)i);
+            cb += L.nchunks;
+        }
+        r.loc_count = cb - r.loc_lo;
+        r.lsc_count = (uint32_t)p->item_s.size() - r.lsc_lo;
         r.lo = tb;
         r.scan_lo = (uint32_t)p->scan_list.size();
         for (int pass = 0; pass < 2; pass++) {
@@ -374,71 +392,85 @@ gc_status plan_materialize(gc_plan *p) {
     return rc;
 }
 
-// Launches the locate kernels of every list on stream s.
-gc_status launch_locate_all(gc_plan *p, hipStream_t s) {
-    if (!p->total_a) return GC_OK;
+// Launches the locate kernels of codec class c on stream s.
+gc_status launch_class_locate(gc_plan *p, int c, hipStream_t s) {
+    const ClassRange &r = p->cr[c];
+    if (!r.loc_count) return GC_OK;
     ListDesc none;
     std::memset(&none, 0, sizeof(none));
-    LocateArgs a = make_locate_args(p->d_lists, p->d_item_a, p->d_item_s, none, p->total_a, p->total_s, p->sc,
-                                    p->ctx->status);
+    LocateArgs a = make_locate_args(p->d_lists, p->d_item_a, p->d_item_s + r.lsc_lo, none, r.loc_count,
+                                    r.lsc_count, c, p->sc, p->ctx->status);
+    a.item_lo = r.loc_lo;
     return launch_locate(a, s) ? GC_EDEVICE : GC_OK;
 }
 
-// Launches the passes of codec class c on stream s: tile sums and carry scan
-// (delta lists of more than one tile), then the decode pass.  `mid`, if
-// given, is recorded between the two.
-gc_status launch_class(gc_plan *p, int c, hipStream_t s, hipEvent_t mid = nullptr) {
+// Launches the tile sums and carry scan (delta lists of more than one tile)
+// and the decode pass of codec class c on stream s; `mid`, if given, is
+// recorded between the two.
+gc_status launch_class_work(gc_plan *p, int c, hipStream_t s, hipEvent_t mid = nullptr) {
     const ClassRange &r = p->cr[c];
-    if (!r.count) return GC_OK;
     ListDesc none;
     std::memset(&none, 0, sizeof(none));
     const int tile = c == kClsPfd ? p->tile_p : p->tile_w;
     if (r.sum) {
-        DecodeArgs d = make_decode_args(p->d_lists, p->d_tile_list, none, r.lo, r.sum, p->sc, p->ctx->status);
+        DecodeArgs d = make_decode_args(p->d_lists, p->d_tile_list, none, r.lo, r.sum, c, p->sc, p->ctx->status);
         if (launch_decode(tile, c, true, d, s)) return GC_EDEVICE;
         CarryArgs ca = make_carry_args(p->d_lists, p->d_scan_list + r.scan_lo, none, r.scans, p->sc);
         if (launch_carry_scan(ca, s)) return GC_EDEVICE;
     }
     if (mid) HIP_OK(hipEventRecord(mid, s));
-    DecodeArgs d = make_decode_args(p->d_lists, p->d_tile_list, none, r.lo, r.count, p->sc, p->ctx->status);
+    DecodeArgs d = make_decode_args(p->d_lists, p->d_tile_list, none, r.lo, r.count, c, p->sc, p->ctx->status);
     return launch_decode(tile, c, false, d, s) ? GC_EDEVICE : GC_OK;
 }
 
-// Launches a whole run on stream s; with `fork` streams the classes run as
-// parallel branches that s waits for.
-gc_status plan_launch(gc_plan *p, hipStream_t s, hipStream_t *fork = nullptr, hipEvent_t *fev = nullptr) {
-    if (gc_status rc = launch_locate_all(p, s)) return rc;
-    int nact = 0;
-    for (int c = 0; c < kClasses; c++) nact += p->cr[c].count ? 1 : 0;
-    const bool par = fork && nact > 1;
-    if (par) HIP_OK(hipEventRecord(fev[kClasses], s));
+// Launches a whole run on stream s, class after class.  With an auxiliary
+// stream `aux`, the locate kernels of every class run there in class order
+// and the rest of class c waits only for its own locate, so the locate of
+// the next class overlaps the passes of this one.  sync[c] signals the end
+// of class c's locate; with `tev` (timing), class c records tev[5c .. 5c+4]:
+// before and after its locate, before its tile sums, before and after its
+// decode pass.
+gc_status plan_launch(gc_plan *p, hipStream_t s, hipStream_t aux = nullptr, hipEvent_t start = nullptr,
+                      hipEvent_t *sync = nullptr, hipEvent_t *tev = nullptr) {
+    if (aux) {
+        HIP_OK(hipEventRecord(start, s));
+        HIP_OK(hipStreamWaitEvent(aux, start, 0));
+    }
+    hipStream_t ls = aux ? aux : s;
+    for (int c = 0; c < kClasses && aux; c++) {
+        if (!p->cr[c].count) continue;
+        if (tev) HIP_OK(hipEventRecord(tev[5 * c], ls));
+        if (gc_status rc = launch_class_locate(p, c, ls)) return rc;
+        HIP_OK(hipEventRecord(tev ? tev[5 * c + 1] : sync[c], ls));
+    }
     for (int c = 0; c < kClasses; c++) {
         if (!p->cr[c].count) continue;
-        hipStream_t cs = s;
-        if (par) {
-            cs = fork[c];
-            HIP_OK(hipStreamWaitEvent(cs, fev[kClasses], 0));
+        if (aux) {
+            HIP_OK(hipStreamWaitEvent(s, tev ? tev[5 * c + 1] : sync[c], 0));
+        } else {
+            if (tev) HIP_OK(hipEventRecord(tev[5 * c], s));
+            if (gc_status rc = launch_class_locate(p, c, s)) return rc;
+            if (tev) HIP_OK(hipEventRecord(tev[5 * c + 1], s));
         }
-        if (gc_status rc = launch_class(p, c, cs)) return rc;
-        if (par) {
-            HIP_OK(hipEventRecord(fev[c], cs));
-            HIP_OK(hipStreamWaitEvent(s, fev[c], 0));
-        }
+        if (tev) HIP_OK(hipEventRecord(tev[5 * c + 2], s));
+        if (gc_status rc = launch_class_work(p, c, s, tev ? tev[5 * c + 3] : nullptr)) return rc;
+        if (tev) HIP_OK(hipEventRecord(tev[5 * c + 4], s));
     }
     return GC_OK;
 }
 
 gc_status capture_one(gc_plan *p, hipGraph_t *graph, hipGraphExec_t *exec) {
-    hipStream_t s, fork[kClasses];
-    hipEvent_t fev[kClasses + 1];
+    hipStream_t s, aux;
+    hipEvent_t start, sync[kClasses];
     HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    for (int c = 0; c < kClasses; c++) HIP_OK(hipStreamCreateWithFlags(&fork[c], hipStreamNonBlocking));
-    for (int c = 0; c <= kClasses; c++) HIP_OK(hipEventCreateWithFlags(&fev[c], hipEventDisableTiming));
+    HIP_OK(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
+    HIP_OK(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    for (int c = 0; c < kClasses; c++) HIP_OK(hipEventCreateWithFlags(&sync[c], hipEventDisableTiming));
     gc_status rc = GC_OK;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         rc = GC_EDEVICE;
     } else {
-        rc = plan_launch(p, s, fork, fev);
+        rc = plan_launch(p, s, p->serial ? nullptr : aux, start, sync);
         hipGraph_t g = nullptr;
         if (hipStreamEndCapture(s, &g) != hipSuccess || rc) {
             rc = GC_EDEVICE;
@@ -448,8 +480,9 @@ gc_status capture_one(gc_plan *p, hipGraph_t *graph, hipGraphExec_t *exec) {
             if (hipGraphInstantiate(exec, g, nullptr, nullptr, 0) != hipSuccess) rc = GC_EDEVICE;
         }
     }
-    for (int c = 0; c <= kClasses; c++) (void)hipEventDestroy(fev[c]);
-    for (int c = 0; c < kClasses; c++) (void)hipStreamDestroy(fork[c]);
+    for (int c = 0; c < kClasses; c++) (void)hipEventDestroy(sync[c]);
+    (void)hipEventDestroy(start);
+    (void)hipStreamDestroy(aux);
     (void)hipStreamDestroy(s);
     (void)hipGetLastError();
     return rc;
@@ -460,23 +493,17 @@ gc_status plan_capture(gc_plan *p) {
     return capture_one(p, &p->graph, &p->exec);
 }
 
-// Events of one timing slot: run start, locate end, then per class: before
-// its sum pass, before its decode pass, after its decode pass.
-constexpr int kEvPerSlot = 2 + 3 * kClasses;
+// Events of one timing slot: run start and end on the launch stream, then
+// five per class (see plan_launch).
+constexpr int kEvPerSlot = 2 + 5 * kClasses;
 
 gc_status plan_run(gc_plan *p, hipStream_t s) {
     if (p->slots) {
         hipEvent_t *e = &p->ev[(size_t)(p->runs % p->slots) * kEvPerSlot];
         p->runs++;
         HIP_OK(hipEventRecord(e[0], s));
-        if (gc_status rc = launch_locate_all(p, s)) return rc;
+        if (gc_status rc = plan_launch(p, s, p->serial ? nullptr : p->aux, e[0], nullptr, e + 2)) return rc;
         HIP_OK(hipEventRecord(e[1], s));
-        for (int c = 0; c < kClasses; c++) {
-            if (!p->cr[c].count) continue;
-            HIP_OK(hipEventRecord(e[2 + 3 * c], s));
-            if (gc_status rc = launch_class(p, c, s, e[3 + 3 * c])) return rc;
-            HIP_OK(hipEventRecord(e[4 + 3 * c], s));
-        }
         return GC_OK;
     }
     if (p->use_graph && p->exec) {
@@ -708,7 +735,7 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     if (opts) o = *opts;
     if (o.tile_ints && !valid_wave_tile(o.tile_ints)) return GC_EINVAL;
     if (o.pfd_tile_ints && !valid_pfd_tile(o.pfd_tile_ints)) return GC_EINVAL;
-    if (o.reserved[0] || o.reserved[1] || o.reserved[2]) return GC_EINVAL;
+    if (o.schedule > 1u || o.reserved[0] || o.reserved[1]) return GC_EINVAL;
     if ((o.autotune || o.use_graph) && nlists && (!d_streams || !d_out)) return GC_EINVAL;
     gc_plan *p = new (std::nothrow) gc_plan();
     if (!p) return GC_ENOMEM;
@@ -717,6 +744,7 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     p->tile_w = o.tile_ints ? (int)o.tile_ints : kDefaultWaveTile;
     p->tile_p = o.pfd_tile_ints ? (int)o.pfd_tile_ints : kDefaultPfdTile;
     p->use_graph = o.use_graph != 0;
+    p->serial = o.schedule == 0u;
     p->slots = std::min<uint32_t>(o.timing_slots, 4096u);
     p->h_lists.resize(nlists);
     p->cls.resize(nlists);
@@ -754,12 +782,14 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
         if (hipEventCreate(&e) != hipSuccess) rc = GC_EDEVICE;
         else p->ev.push_back(e);
     }
+    if (p->slots && !rc && hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking) != hipSuccess) rc = GC_EDEVICE;
     if (!rc) rc = plan_materialize(p);
     if (!rc && d_streams && d_out) rc = plan_upload(p, d_streams, d_out);
     if (!rc && p->use_graph) rc = plan_capture(p);
     if (rc) {
         plan_free_device(p);
         for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+        if (p->aux) (void)hipStreamDestroy(p->aux);
         delete p;
         return rc;
     }
@@ -773,6 +803,7 @@ gc_status gc_plan_destroy(gc_plan *plan) {
     (void)hipDeviceSynchronize();
     plan_free_device(plan);
     for (hipEvent_t e : plan->ev) (void)hipEventDestroy(e);
+    if (plan->aux) (void)hipStreamDestroy(plan->aux);
     delete plan;
     return GC_OK;
 }
@@ -811,17 +842,15 @@ gc_status gc_plan_timings(gc_plan *plan, uint32_t max_runs, float *ms, uint32_t 
         hipEvent_t *e = &plan->ev[(size_t)(run % plan->slots) * kEvPerSlot];
         float *row = ms + (size_t)i * GC_TIMING_FIELDS;
         for (int f = 0; f < GC_TIMING_FIELDS; f++) row[f] = 0.0f;
-        hipEvent_t last = e[1];
+        HIP_OK(hipEventSynchronize(e[1]));
+        HIP_OK(hipEventElapsedTime(&row[0], e[0], e[1]));
         for (int c = 0; c < kClasses; c++) {
             if (!plan->cr[c].count) continue;
-            HIP_OK(hipEventSynchronize(e[4 + 3 * c]));
-            HIP_OK(hipEventElapsedTime(&row[2 + kClasses + c], e[2 + 3 * c], e[3 + 3 * c]));
-            HIP_OK(hipEventElapsedTime(&row[2 + c], e[3 + 3 * c], e[4 + 3 * c]));
-            last = e[4 + 3 * c];
+            hipEvent_t *ce = e + 2 + 5 * c;
+            HIP_OK(hipEventElapsedTime(&row[1 + c], ce[0], ce[1]));
+            HIP_OK(hipEventElapsedTime(&row[1 + kClasses + c], ce[2], ce[3]));
+            HIP_OK(hipEventElapsedTime(&row[1 + 2 * kClasses + c], ce[3], ce[4]));
         }
-        HIP_OK(hipEventSynchronize(last));
-        HIP_OK(hipEventElapsedTime(&row[0], e[0], last));
-        HIP_OK(hipEventElapsedTime(&row[1], e[0], e[1]));
     }
     *nruns = n;
     return GC_OK;

@@ -24,7 +24,7 @@ DELTA = 1
 # decode kernel classes (gc_plan_timings columns)
 CLS_SIMPLE, CLS_SCHEME_UNARY, CLS_SCHEME_BINARY, CLS_AFOR, CLS_PFD = range(5)
 CLASSES = 5
-TIMING_FIELDS = 2 + 2 * CLASSES
+TIMING_FIELDS = 1 + 3 * CLASSES
 OK, EINVAL, ENOSPC, ECORRUPT, EDEVICE, EUNSUPPORTED, ENOMEM = 0, -1, -2, -3, -4, -5, -6
 _NAMES = {0: "GC_OK", -1: "GC_EINVAL", -2: "GC_ENOSPC", -3: "GC_ECORRUPT", -4: "GC_EDEVICE",
           -5: "GC_EUNSUPPORTED", -6: "GC_ENOMEM"}
@@ -59,7 +59,8 @@ class ListDesc(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("tile_ints", ctypes.c_uint32), ("pfd_tile_ints", ctypes.c_uint32),
                 ("use_graph", ctypes.c_uint32), ("autotune", ctypes.c_uint32),
-                ("timing_slots", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+                ("timing_slots", ctypes.c_uint32), ("schedule", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 def params(k=4, cg=1, ld=LD_CU, pfd_pos=PFD_LINKED, zeta=(1, 10), delta=False):
@@ -222,7 +223,7 @@ class Plan:
     """gc_plan_create / gc_decode_batch / gc_decode_each / gc_plan_destroy."""
 
     def __init__(self, ctx: Context, descs, headers, d_streams=None, d_out=None, tile_ints=0,
-                 pfd_tile_ints=0, use_graph=False, autotune=False, timing_slots=0):
+                 pfd_tile_ints=0, use_graph=False, autotune=False, timing_slots=0, locate_stream=False):
         self.ctx = ctx
         nl = len(descs)
         arr = (ListDesc * max(nl, 1))()
@@ -230,7 +231,7 @@ class Plan:
             arr[i] = d
         hdr = np.ascontiguousarray(headers, dtype=np.uint32).reshape(-1)
         opts = PlanOpts(int(tile_ints), int(pfd_tile_ints), int(bool(use_graph)), int(bool(autotune)),
-                        int(timing_slots))
+                        int(timing_slots), int(bool(locate_stream)))
         self._h = ctypes.c_void_p()
         rc = lib().gc_plan_create(ctx._h, arr, nl, _u32(hdr), ctypes.byref(opts),
                                   _ptr(d_streams) if d_streams is not None else None,
@@ -247,14 +248,14 @@ class Plan:
 
     def timings(self, max_runs):
         """Per-run kernel times (ms) of the last runs, oldest first: a dict of
-        arrays -- total, locate, decode[class], sum[class] (classes in the
-        order SIMPLE, SCHEME unary, SCHEME binary, AFOR, PFD)."""
+        arrays -- total (runs,), and locate, sum, decode (runs, CLASSES) with
+        classes in the order SIMPLE, SCHEME unary, SCHEME binary, AFOR, PFD."""
         a = (ctypes.c_float * (max(max_runs, 1) * TIMING_FIELDS))()
         n = ctypes.c_uint32()
         _check("gc_plan_timings", lib().gc_plan_timings(self._h, int(max_runs), a, ctypes.byref(n)))
         m = np.array(a[:n.value * TIMING_FIELDS], dtype=np.float64).reshape(n.value, TIMING_FIELDS)
-        return dict(total=m[:, 0], locate=m[:, 1], decode=m[:, 2:2 + CLASSES],
-                    sum=m[:, 2 + CLASSES:2 + 2 * CLASSES])
+        return dict(total=m[:, 0], locate=m[:, 1:1 + CLASSES], sum=m[:, 1 + CLASSES:1 + 2 * CLASSES],
+                    decode=m[:, 1 + 2 * CLASSES:1 + 3 * CLASSES])
 
     def config(self):
         """Chosen tile sizes, decode tiles per run and the tiles of those the

@@ -185,6 +185,37 @@ def test_autotuned_plan(torch_cuda, ctx, tmp_path, monkeypatch):
     assert plan2.config()["tile_ints"] == cfg["tile_ints"]
 
 
+@pytest.mark.parametrize("locate_stream", [False, True])
+def test_timed_plan(torch_cuda, ctx, locate_stream):
+    """A plan with timing slots launches its kernels directly (the locate
+    kernels on a second stream with locate_stream); its output equals the
+    oracle's, and every class present reports positive phase times on every
+    run."""
+    torch = torch_cuda
+    rng = np.random.default_rng(31)
+    flat, offs, lengths, lists = make_batch(rng, 160, kmix=(4, 4, 8))
+    descs, headers, out_offs = gc.batch_layout(flat, offs, lengths, align=4)
+    d_s = gc.to_device(flat)
+    d_o = torch.full((int(out_offs[-1]) + 16,), -1, dtype=torch.int32, device="cuda")
+    say("timed plan locate_stream", locate_stream)
+    plan = gc.Plan(ctx, descs, headers, d_s, d_o, timing_slots=4, locate_stream=locate_stream)
+    want = np.concatenate(lists)
+    for rep in range(6):
+        plan.decode_batch(d_s, d_o)
+    rc, det = ctx.sync_status()
+    assert rc == gc.OK, det
+    assert np.array_equal(gc.unpad(gc.to_host(d_o), out_offs, lengths), want)
+    tm = plan.timings(10)
+    assert tm["total"].shape == (4,) and tm["decode"].shape == (4, gc.CLASSES)
+    present = {gc.CLS_SIMPLE, gc.CLS_SCHEME_UNARY, gc.CLS_SCHEME_BINARY, gc.CLS_AFOR, gc.CLS_PFD}
+    assert np.all(tm["total"] > 0)
+    for c in present:
+        assert np.all(tm["decode"][:, c] > 0), c
+        assert np.all(tm["sum"][:, c] > 0), c
+        assert np.all(tm["decode"][:, c] <= tm["total"] + 1e-3)
+    plan.close()
+
+
 def test_corrupt_streams_latch_status(torch_cuda, ctx):
     torch = torch_cuda
     rng = np.random.default_rng(9)
