@@ -286,14 +286,17 @@ __device__ __forceinline__ void locate_thread(const ListDesc &L, uint32_t chunk,
     }
 }
 
-__device__ __forceinline__ bool locate_item(const LocateArgs &a, uint32_t item, ListDesc &L, uint32_t &chunk) {
+__device__ __forceinline__ bool locate_item(const LocateArgs &a, uint32_t item, ListDesc &L, uint32_t &chunk,
+                                            uint32_t &list) {
     if (item >= a.total_items) return false;
     if (a.lists) {
-        L = a.lists[a.item_list[a.item_lo + item]];
+        list = a.item_list[a.item_lo + item];
+        L = a.lists[list];
         chunk = a.item_lo + item - L.chunk_base;
     } else {
         L = a.single;
         chunk = item;
+        list = 0;
     }
     return true;
 }
@@ -308,8 +311,8 @@ __global__ __launch_bounds__(kThreads) void gc_locate_reduce(LocateArgs a) {
         __hip_atomic_store(&a.state->epoch, epoch_next(e), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     ListDesc L;
-    uint32_t chunk;
-    if (!locate_item(a, blockIdx.x, L, chunk)) return;
+    uint32_t chunk, list;
+    if (!locate_item(a, blockIdx.x, L, chunk, list)) return;
     LocThread t;
     locate_thread(L, chunk, t);
     uint32_t tt, te, td;
@@ -361,8 +364,8 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
     __shared__ uint32_t s_tmp[kWaves];
     const uint32_t epoch = __hip_atomic_load(&a.state->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     ListDesc L;
-    uint32_t chunk;
-    if (locate_item(a, blockIdx.x, L, chunk)) {
+    uint32_t chunk, list;
+    if (locate_item(a, blockIdx.x, L, chunk, list)) {
         LocThread t;
         locate_thread(L, chunk, t);
         uint32_t tt, te, td;
@@ -383,6 +386,7 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
             ti.exc = exc;
             ti.tag = epoch;
             ti.data = data;
+            ti.list = list;
             ti.pad = 0;
             tiles[m] = ti;
         };
@@ -489,7 +493,7 @@ __device__ __forceinline__ uint32_t rec_pack(uint32_t rel, uint32_t bw) { return
 // Fills the tile context of tile m (global tile gi) of list L from the
 // host's header words; false if the stream's header disagrees or the locate
 // pass did not reach the tile in this run.
-__device__ __forceinline__ bool tile_ctx(const DecodeArgs &a, const ListDesc &L, uint32_t m, uint32_t gi,
+__device__ __forceinline__ bool tile_ctx(const ListDesc &L, uint32_t m, const TileInfo &s0, const TileInfo &s1,
                                          uint32_t tile, uint32_t loc_tag, TileCtx &c) {
     c.S = L.stream;
     c.n = L.n;
@@ -512,23 +516,60 @@ __device__ __forceinline__ bool tile_ctx(const DecodeArgs &a, const ListDesc &L,
     c.st = TileInfo{};
     c.en = TileInfo{};
     if (m > 0u) {
-        c.st = a.tiles[gi];
+        c.st = s0;
         ok = ok && c.st.tag == loc_tag;
     }
     if (c.has_en) {
-        c.en = a.tiles[gi + 1u];
+        c.en = s1;
         ok = ok && c.en.tag == loc_tag;
     }
     return ok;
+}
+
+// The tile starts of tile gi and gi + 1 and the carry of tile gi, loaded
+// before the list descriptor (the tile arrays hold one spare entry).
+struct TilePre {
+    TileInfo s0, s1;
+    uint32_t carry;
+};
+
+__device__ __forceinline__ TilePre tile_pre(const DecodeArgs &a, uint32_t gi) {
+    typedef __attribute__((address_space(1))) const TileInfo gTileInfo;
+    const gTileInfo *t = (const gTileInfo *)a.tiles;
+    TilePre p;
+    p.s0.unit = t[gi].unit;
+    p.s0.sub = t[gi].sub;
+    p.s0.exc = t[gi].exc;
+    p.s0.tag = t[gi].tag;
+    p.s0.data = t[gi].data;
+    p.s0.list = t[gi].list;
+    p.s1.unit = t[gi + 1u].unit;
+    p.s1.sub = t[gi + 1u].sub;
+    p.s1.exc = t[gi + 1u].exc;
+    p.s1.tag = t[gi + 1u].tag;
+    p.s1.data = t[gi + 1u].data;
+    p.carry = ((const gu32 *)a.carry)[gi];
+    return p;
 }
 
 // Wave-uniform value, so the compiler keeps what depends on it in scalar
 // registers.
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
 
-// The list of tile gi of a launch.
-__device__ __forceinline__ ListDesc tile_list(const DecodeArgs &a, uint32_t gi) {
-    return a.lists ? a.lists[a.tile_list[gi]] : a.single;
+// The list of a tile, named by its start entry (from global memory in a
+// batch, so the wave-uniform loads stay scalar).
+__device__ __forceinline__ ListDesc tile_list(const DecodeArgs &a, const TilePre &pre) {
+    if (!a.lists) return a.single;
+    const gu32x4 *g = (const gu32x4 *)(a.lists + pre.s0.list);
+    union {
+        u32x4 v[4];
+        ListDesc d;
+    } u;
+    u.v[0] = g[0];
+    u.v[1] = g[1];
+    u.v[2] = g[2];
+    u.v[3] = g[3];
+    return u.d;
 }
 
 // ===========================================================================
@@ -675,15 +716,15 @@ __device__ void patch_pfd(const TileCtx &c, PfdSmem<TILE> &sm) {
 // sum of the tile's gaps in carry[gi]; otherwise write the tile's output,
 // prefix-summed from carry[gi] for a delta list.
 template <int TILE, bool SUM>
-__device__ void pfd_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, uint32_t gi, uint32_t loc_tag,
-                         PfdSmem<TILE> &sm) {
+__device__ void pfd_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, uint32_t gi, const TilePre &pre,
+                         uint32_t loc_tag, PfdSmem<TILE> &sm) {
     constexpr int R = PfdSmem<TILE>::R;
     const int tid = threadIdx.x;
     HeaderFields hl;
     const bool delta = header_fields(L.w0, hl) && hl.delta;
-    const uint32_t carry0 = (!SUM && delta && L.ntiles > 1u) ? a.carry[gi] : 0u;
+    const uint32_t carry0 = (!SUM && delta && L.ntiles > 1u) ? pre.carry : 0u;
     TileCtx c;
-    const bool ok = tile_ctx(a, L, m, gi, (uint32_t)TILE, loc_tag, c);
+    const bool ok = tile_ctx(L, m, pre.s0, pre.s1, (uint32_t)TILE, loc_tag, c);
     if (tid == 0) sm.bad = ok ? 0u : kErrLocate;
     __syncthreads();
     if (!sm.bad) prologue_pfd<TILE>(c, sm, L.stream_words);
@@ -794,10 +835,11 @@ __device__ void pfd_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, uin
 template <int TILE, bool SUM>
 __global__ __launch_bounds__(kThreads) void gc_pfd_kernel(DecodeArgs a) {
     __shared__ PfdSmem<TILE> sm;
-    const uint32_t loc_tag = __hip_atomic_load(&a.loc_state->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t gi = a.lo + blockIdx.x;
-    const ListDesc L = tile_list(a, gi);
-    pfd_tile<TILE, SUM>(a, L, gi - L.tile_base, gi, loc_tag, sm);
+    const uint32_t loc_tag = *(const gu32 *)&a.loc_state->epoch;   // written by an earlier kernel
+    const TilePre pre = tile_pre(a, gi);
+    const ListDesc L = tile_list(a, pre);
+    pfd_tile<TILE, SUM>(a, L, gi - L.tile_base, gi, pre, loc_tag, sm);
 }
 
 // ===========================================================================
@@ -1262,14 +1304,14 @@ __device__ __forceinline__ uint32_t quads_lds(const uint32_t *rec, const u32x4 *
 }
 
 template <int TW, int CLS, bool SUM>
-__device__ void wave_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, uint32_t gi, uint32_t loc_tag,
-                          WaveSmem<TW, CLS> &sm, uint32_t lane) {
+__device__ void wave_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, uint32_t gi, const TilePre &pre,
+                          uint32_t loc_tag, WaveSmem<TW, CLS> &sm, uint32_t lane) {
     constexpr int R = TW / 256;
     HeaderFields hl;
     const bool delta = header_fields(L.w0, hl) && hl.delta;
-    const uint32_t carry0 = (!SUM && delta && L.ntiles > 1u) ? a.carry[gi] : 0u;
+    const uint32_t carry0 = (!SUM && delta && L.ntiles > 1u) ? pre.carry : 0u;
     TileCtx c;
-    const bool ok = tile_ctx(a, L, m, gi, (uint32_t)TW, loc_tag, c);
+    const bool ok = tile_ctx(L, m, pre.s0, pre.s1, (uint32_t)TW, loc_tag, c);
     uint32_t dbase = 0, err = ok ? 0u : kErrLocate;
     if (!err) {
         if constexpr (CLS == kClsSim) err = wprologue_sim<TW>(c, sm, lane, dbase);
@@ -1325,10 +1367,11 @@ __global__ __launch_bounds__(kThreads) void gc_wave_kernel(DecodeArgs a) {
     const uint32_t wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63u;
     const uint32_t w = blockIdx.x * (uint32_t)kWaves + wave;
     if (w >= a.count) return;
-    const uint32_t loc_tag = __hip_atomic_load(&a.loc_state->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t gi = a.lo + w;
-    const ListDesc L = tile_list(a, gi);
-    wave_tile<TW, CLS, SUM>(a, L, gi - L.tile_base, gi, loc_tag, sm[wave], lane);
+    const uint32_t loc_tag = *(const gu32 *)&a.loc_state->epoch;   // written by an earlier kernel
+    const TilePre pre = tile_pre(a, gi);
+    const ListDesc L = tile_list(a, pre);
+    wave_tile<TW, CLS, SUM>(a, L, gi - L.tile_base, gi, pre, loc_tag, sm[wave], lane);
 }
 
 // ===========================================================================

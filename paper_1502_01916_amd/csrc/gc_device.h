@@ -7,7 +7,7 @@ namespace gcdev {
 
 constexpr int kThreads = 256;          // threads per workgroup (4 wave64)
 constexpr int kWaves = kThreads / 64;
-constexpr int kChunkWords = kThreads * 4;  // control words per locate work item
+constexpr int kChunkWords = kThreads * 2;  // control words per locate work item
 constexpr int kClasses = 5;                 // decode kernel classes (codec families)
 
 // One list of a launch.  For a batch these live in a device table; for a
@@ -34,7 +34,8 @@ struct TileInfo {
     uint32_t exc;     // Group-PFD: exception-area word offset of the unit
     uint32_t tag;     // epoch of the locate run that wrote this entry
     uint64_t data;    // component bit offset of the unit (Group-Scheme: of the tuple)
-    uint64_t pad;
+    uint32_t list;    // batch: the tile's list (tile 0 of a list: set by the host)
+    uint32_t pad;
 };
 
 // Epoch of the locate pass: its first kernel advances it, its last tags
@@ -83,7 +84,6 @@ struct LocateArgs {
 // a wave (Group-PFD: a workgroup) per tile.
 struct DecodeArgs {
     const ListDesc *lists;      // batch table, or nullptr for `single`
-    const uint32_t *tile_list;  // batch: tile -> list
     ListDesc single;
     uint32_t lo;
     uint32_t count;

@@ -170,7 +170,7 @@ struct gc_plan {
     std::vector<uint32_t> item_a, item_s;      // locate: chunk -> list, scan -> list
     std::vector<uint32_t> tile_list, scan_list;
     ListDesc *d_lists = nullptr;
-    uint32_t *d_item_a = nullptr, *d_item_s = nullptr, *d_tile_list = nullptr, *d_scan_list = nullptr;
+    uint32_t *d_item_a = nullptr, *d_item_s = nullptr, *d_scan_list = nullptr;
     Scratch sc;
     const uint32_t *bound_streams = nullptr;
     uint32_t *bound_out = nullptr;
@@ -204,12 +204,11 @@ LocateArgs make_locate_args(const ListDesc *lists, const uint32_t *item_list, co
     return a;
 }
 
-DecodeArgs make_decode_args(const ListDesc *lists, const uint32_t *tile_list, const ListDesc &single, uint32_t lo,
-                            uint32_t count, int cls, Scratch &sc, Status *st) {
+DecodeArgs make_decode_args(const ListDesc *lists, const ListDesc &single, uint32_t lo, uint32_t count, int cls,
+                            Scratch &sc, Status *st) {
     DecodeArgs a;
     std::memset(&a, 0, sizeof(a));
     a.lists = lists;
-    a.tile_list = tile_list;
     a.single = single;
     a.lo = lo;
     a.count = count;
@@ -259,7 +258,7 @@ int min_wave_tile(const gc_plan *p) {
 
 // Single-list view of list L for the per-list paths: its own tile range.
 DecodeArgs single_args(const ListDesc &L, int cls, Scratch &sc, Status *st) {
-    return make_decode_args(nullptr, nullptr, L, L.tile_base, L.ntiles, cls, sc, st);
+    return make_decode_args(nullptr, L, L.tile_base, L.ntiles, cls, sc, st);
 }
 
 // Launches every pass of one list on stream s (the per-list paths).
@@ -351,7 +350,6 @@ void plan_free_device(gc_plan *p) {
     dev_free(p->d_lists);
     dev_free(p->d_item_a);
     dev_free(p->d_item_s);
-    dev_free(p->d_tile_list);
     dev_free(p->d_scan_list);
     p->sc.release();
 }
@@ -386,9 +384,19 @@ gc_status plan_materialize(gc_plan *p) {
     if (!rc && !p->sc.state) rc = p->sc.init_state();
     if (!rc) rc = upload_vec(&p->d_item_a, p->item_a);
     if (!rc) rc = upload_vec(&p->d_item_s, p->item_s);
-    if (!rc) rc = upload_vec(&p->d_tile_list, p->tile_list);
+
     if (!rc) rc = upload_vec(&p->d_scan_list, p->scan_list);
-    if (!rc) rc = p->sc.reserve(p->total_t, p->total_a);
+    if (!rc) rc = p->sc.reserve(p->total_t + 1, p->total_a);
+    if (!rc && p->total_t) {
+        // every tile names its list; the locate pass rewrites the entries of
+        // tiles m >= 1 on each run, tile 0 of a list starts at zero
+        std::vector<TileInfo> init(p->total_t);
+        for (uint32_t t = 0; t < p->total_t; t++) {
+            std::memset(&init[t], 0, sizeof(TileInfo));
+            init[t].list = p->tile_list[t];
+        }
+        HIP_OK(hipMemcpy(p->sc.tiles, init.data(), init.size() * sizeof(TileInfo), hipMemcpyHostToDevice));
+    }
     return rc;
 }
 
@@ -413,13 +421,13 @@ gc_status launch_class_work(gc_plan *p, int c, hipStream_t s, hipEvent_t mid = n
     std::memset(&none, 0, sizeof(none));
     const int tile = c == kClsPfd ? p->tile_p : p->tile_w;
     if (r.sum) {
-        DecodeArgs d = make_decode_args(p->d_lists, p->d_tile_list, none, r.lo, r.sum, c, p->sc, p->ctx->status);
+        DecodeArgs d = make_decode_args(p->d_lists, none, r.lo, r.sum, c, p->sc, p->ctx->status);
         if (launch_decode(tile, c, true, d, s)) return GC_EDEVICE;
         CarryArgs ca = make_carry_args(p->d_lists, p->d_scan_list + r.scan_lo, none, r.scans, p->sc);
         if (launch_carry_scan(ca, s)) return GC_EDEVICE;
     }
     if (mid) HIP_OK(hipEventRecord(mid, s));
-    DecodeArgs d = make_decode_args(p->d_lists, p->d_tile_list, none, r.lo, r.count, c, p->sc, p->ctx->status);
+    DecodeArgs d = make_decode_args(p->d_lists, none, r.lo, r.count, c, p->sc, p->ctx->status);
     return launch_decode(tile, c, false, d, s) ? GC_EDEVICE : GC_OK;
 }
 
@@ -721,7 +729,7 @@ gc_status gc_decode(gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words, 
     L.w0 = h_header[0];
     L.C = h_header[2];
     L.D = h_header[3];
-    if (gc_status rc = ctx->single.reserve(L.ntiles, L.nchunks)) return rc;
+    if (gc_status rc = ctx->single.reserve(L.ntiles + 1, L.nchunks)) return rc;
     return launch_one(L, cls, ctx->single, ctx->status, (hipStream_t)hip_stream);
 }
 
