@@ -213,6 +213,57 @@ gc_status gc_plan_config(const gc_plan *plan, uint32_t *tile_ints, uint32_t *pfd
  * not NULL, receives an implementation-specific code of the failed check.  */
 gc_status gc_sync_status(gc_ctx *ctx, void *hip_stream, uint32_t *detail);
 
+/* ---- per-block container of the learned codec selector -----------------
+ * Not part of the paper: a container in which every block of
+ * GC_BLOCK_INTS integers (32 tuples of the 4-way layout) is coded on its own
+ * with one of GC_BLOCK_CLASSES codec classes, each the whole-list rule of
+ * its section applied to the block's 32 tuples:
+ *   0 Group-Simple (Algorithm 1, Table III)
+ *   1..4 Group-Scheme with binary descriptors, CG = 1, 2, 4, 8 (Section 5.2)
+ *   5..8 Group-Scheme with complete unary descriptors, CG = 1, 2, 4, 8
+ *   9, 10 Group-Scheme with incomplete unary descriptors, CG = 4, 8
+ *   11 Group-AFOR (Section 6.1)
+ *   12..15 Group-PFD with linked exceptions, zeta = 1/64, 1/10, 2/10, 3/10
+ *        (Section 6.2; zeta below 1/32 is BP128, Section 6.3)
+ * Layout: header {version 1 | codec 4 << 8 | log2 4 << 12, n, blocks,
+ * payload words}; one word per block, class:5 | control words:9 | data
+ * words:9 | exception words:9; then the block payloads back to back, each
+ * its unpadded control words, its data words and its exception words.  A
+ * block's size is 1 + its payload words.  Integers are coded as they are
+ * (no d-gaps).                                                              */
+#define GC_BLOCK_INTS 128
+#define GC_BLOCK_CLASSES 16
+#define GC_BLOCK_FEATURES 40
+
+/* Device memory d_in holds nblocks * GC_BLOCK_INTS integers.  Writes the 40
+ * features of every block to d_feat (nblocks x 40 floats, row-major): the
+ * largest bit width / 32; the count of integers of bit width 0..32 / 128;
+ * the count of integers wider than (largest width - t), t = 1..6, / 128
+ * (all integers when that is negative).  Asynchronous on hip_stream.       */
+gc_status gc_block_features(gc_ctx *ctx, const uint32_t *d_in, size_t nblocks, float *d_feat,
+                            void *hip_stream);
+
+/* The coded size in words (block word included) of every block in every
+ * class to d_sizes (nblocks x GC_BLOCK_CLASSES, row-major) and the least
+ * one's class (the smaller class on ties: the exhaustive choice) to
+ * d_best.  Either output may be NULL.  Asynchronous on hip_stream.         */
+gc_status gc_block_sizes(gc_ctx *ctx, const uint32_t *d_in, size_t nblocks, uint32_t *d_sizes,
+                         uint8_t *d_best, void *hip_stream);
+
+/* Words a container of n integers can take at most. */
+size_t gc_blockmix_bound_words(size_t n);
+
+/* Codes the n integers of d_in (device memory holding ceil(n/128) * 128
+ * integers, the tail zero-padded) into a container at d_out, block b in
+ * class d_class[b] (device memory, one byte per block).  *out_words
+ * receives the container's length; the call reads that total back from the
+ * device (so it returns after the sizing kernels finished) and queues the
+ * writing kernels on hip_stream.  GC_ENOSPC if out_cap_words is too small,
+ * GC_EINVAL for a class >= GC_BLOCK_CLASSES or when
+ * gc_blockmix_bound_words(n) exceeds 2^32 - 1.                              */
+gc_status gc_blockmix_encode(gc_ctx *ctx, const uint32_t *d_in, size_t n, const uint8_t *d_class,
+                             uint32_t *d_out, size_t out_cap_words, size_t *out_words, void *hip_stream);
+
 /* Library version string. */
 const char *gc_version(void);
 

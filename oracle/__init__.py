@@ -20,7 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRCS = [os.path.join(_HERE, f) for f in ("gc_oracle.c", "gc_blocks.c")]
+_SRCS = [os.path.join(_HERE, "gc_oracle.c")]
 _lock = threading.Lock()
 _lib = None
 
@@ -80,8 +80,7 @@ def lib():
             L.or_afor_encode_with.restype = ctypes.c_long
             L.or_decode.argtypes = [u32p, sz, u32p, sz]
             L.or_decode.restype = ctypes.c_long
-            if hasattr(L, "or_block_sizes"):
-                _bind_blocks(L)
+            _bind_blocks(L)
             _lib = L
     return _lib
 
@@ -90,12 +89,15 @@ def _bind_blocks(L):
     u32p = ctypes.POINTER(ctypes.c_uint32)
     u8p = ctypes.POINTER(ctypes.c_uint8)
     sz = ctypes.c_size_t
-    f32p = ctypes.POINTER(ctypes.c_float)
-    L.or_block_nclasses.restype = ctypes.c_int
-    L.or_block_sizes.argtypes = [u32p, sz, u32p]
-    L.or_block_sizes.restype = ctypes.c_int
-    L.or_block_features.argtypes = [u32p, sz, f32p]
-    L.or_blockmix_encode.argtypes = [u32p, sz, ctypes.c_int, u8p, u32p, sz]
+    L.or_block_class_params.argtypes = [ctypes.c_int, ctypes.POINTER(Params)]
+    L.or_block_encode.argtypes = [u32p, ctypes.c_int, u32p, sz, u32p]
+    L.or_block_encode.restype = ctypes.c_long
+    L.or_block_size.argtypes = [u32p, ctypes.c_int]
+    L.or_block_size.restype = ctypes.c_long
+    L.or_block_best.argtypes = [u32p, ctypes.POINTER(ctypes.c_long)]
+    L.or_block_decode.argtypes = [ctypes.c_uint32, u32p, sz, u32p]
+    L.or_block_features.argtypes = [u32p, ctypes.POINTER(ctypes.c_double)]
+    L.or_blockmix_encode.argtypes = [u32p, sz, u8p, u32p, sz, u8p]
     L.or_blockmix_encode.restype = ctypes.c_long
     L.or_blockmix_decode.argtypes = [u32p, sz, u32p, sz]
     L.or_blockmix_decode.restype = ctypes.c_long
@@ -238,3 +240,88 @@ def parse_header(w0: int):
 
 class CorruptStream(ValueError):
     pass
+
+
+# ---------------------------------------------------------------------------
+# Per-block container of the learned selector.
+
+BLOCK_INTS = 128
+NCLASS = 16
+
+
+def block_class_params(kappa: int) -> Params:
+    p = Params()
+    if not lib().or_block_class_params(int(kappa), ctypes.byref(p)):
+        raise ValueError(kappa)
+    return p
+
+
+def _block(x):
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    assert x.size == BLOCK_INTS
+    return x
+
+
+def block_encode(x, kappa: int):
+    """(block word, payload words) of one 128-integer block coded with class kappa."""
+    x = _block(x)
+    buf = np.zeros(4 * BLOCK_INTS + 64, np.uint32)
+    bw = ctypes.c_uint32()
+    w = lib().or_block_encode(_u32(x), int(kappa), _u32(buf), buf.size, ctypes.byref(bw))
+    if w <= 0:
+        raise ValueError("block encode failed")
+    return int(bw.value), buf[:w].copy()
+
+
+def block_size(x, kappa: int) -> int:
+    return int(lib().or_block_size(_u32(_block(x)), int(kappa)))
+
+
+def block_best(x):
+    """(exhaustive class, sizes of all classes in words)."""
+    sizes = (ctypes.c_long * NCLASS)()
+    best = lib().or_block_best(_u32(_block(x)), sizes)
+    return int(best), np.array(sizes[:], dtype=np.int64)
+
+
+def block_decode(blockword: int, payload):
+    payload = np.ascontiguousarray(payload, dtype=np.uint32)
+    out = np.zeros(BLOCK_INTS, np.uint32)
+    rc = lib().or_block_decode(ctypes.c_uint32(int(blockword)), _u32(payload), payload.size, _u32(out))
+    if rc != OK:
+        raise CorruptStream(rc)
+    return out
+
+
+def block_features(x):
+    f = (ctypes.c_double * 40)()
+    lib().or_block_features(_u32(_block(x)), f)
+    return np.array(f[:], dtype=np.float64)
+
+
+def blockmix_encode(x, kappas=None):
+    """(container words, classes used); kappas None = exhaustive choice."""
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    nb = (x.size + BLOCK_INTS - 1) // BLOCK_INTS
+    cap = 4 + nb * (4 * BLOCK_INTS + 64) + 64
+    out = np.zeros(cap, np.uint32)
+    used = np.zeros(max(nb, 1), np.uint8)
+    kp = None
+    if kappas is not None:
+        kappas = np.ascontiguousarray(kappas, dtype=np.uint8)
+        assert kappas.size == nb
+        kp = _u8(kappas)
+    w = lib().or_blockmix_encode(_u32(x), x.size, kp, _u32(out), cap, _u8(used))
+    if w < 0:
+        raise ValueError("blockmix encode failed: %d" % w)
+    return out[:w].copy(), used[:nb].copy()
+
+
+def blockmix_decode(s):
+    s = np.ascontiguousarray(s, dtype=np.uint32)
+    n = int(s[1]) if s.size >= 2 else 0
+    out = np.zeros(max(n, 1), np.uint32)
+    r = lib().or_blockmix_decode(_u32(s), s.size, _u32(out), n)
+    if r < 0:
+        raise CorruptStream(r)
+    return out[:n]

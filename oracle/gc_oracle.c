@@ -1036,3 +1036,233 @@ long or_decode(const uint32_t *s, size_t words, uint32_t *out, size_t cap)
     free(x);
     return rc == OR_OK ? (long)n : rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Per-block container for the learned selector (not part of the paper):
+ * every block of OR_BLOCK_INTS integers (32 tuples at k = 4) is coded on its
+ * own with one of OR_NCLASS codec/parameter classes, by the rules above.
+ * Container: header {version | codec 4 << 8 | log2k << 12, n, blocks,
+ * payload words}, then one word per block -- class:5 | control words:9 |
+ * data words:9 | exception words:9 -- then the block payloads back to back
+ * (each: its control words unpadded, its data words, its exception words).
+ * A block's size is 1 + its three word counts; the exhaustive choice is the
+ * class of least size, the smaller class on ties.                          */
+
+#define OR_BLOCK_INTS 128
+#define OR_NCLASS 16
+#define OR_CODEC_BLOCKMIX 4
+
+static const int BLOCK_CLASS[OR_NCLASS][5] = {
+    /* codec, cg, ld, zeta num, zeta den */
+    {OR_SIMPLE, 1, 0, 1, 10},
+    {OR_SCHEME, 1, OR_LD_BINARY, 1, 10}, {OR_SCHEME, 2, OR_LD_BINARY, 1, 10},
+    {OR_SCHEME, 4, OR_LD_BINARY, 1, 10}, {OR_SCHEME, 8, OR_LD_BINARY, 1, 10},
+    {OR_SCHEME, 1, OR_LD_CU, 1, 10}, {OR_SCHEME, 2, OR_LD_CU, 1, 10},
+    {OR_SCHEME, 4, OR_LD_CU, 1, 10}, {OR_SCHEME, 8, OR_LD_CU, 1, 10},
+    {OR_SCHEME, 4, OR_LD_IU, 1, 10}, {OR_SCHEME, 8, OR_LD_IU, 1, 10},
+    {OR_AFOR, 1, 0, 1, 10},
+    {OR_PFD, 1, 0, 1, 64}, {OR_PFD, 1, 0, 1, 10}, {OR_PFD, 1, 0, 2, 10}, {OR_PFD, 1, 0, 3, 10},
+};
+
+int or_block_class_params(int kappa, or_params *p)
+{
+    if (kappa < 0 || kappa >= OR_NCLASS)
+        return 0;
+    memset(p, 0, sizeof(*p));
+    p->codec = BLOCK_CLASS[kappa][0];
+    p->k = 4;
+    p->cg = BLOCK_CLASS[kappa][1];
+    p->ld = BLOCK_CLASS[kappa][2];
+    p->delta = 0;
+    p->pfd_pos = OR_PFD_LINKED;
+    p->zeta_num = BLOCK_CLASS[kappa][3];
+    p->zeta_den = BLOCK_CLASS[kappa][4];
+    return 1;
+}
+
+/* Codes one block into its areas (32 tuples; no codec needs padding). */
+static int block_areas(const uint32_t *x, int kappa, areas *a)
+{
+    or_params p;
+    if (!or_block_class_params(kappa, &p))
+        return 0;
+    const size_t T = OR_BLOCK_INTS / 4;
+    if (!areas_alloc(a, T, 4)) {
+        areas_free(a);
+        return 0;
+    }
+    if (p.codec == OR_SIMPLE) {
+        gsim_encode(x, T, 4, a, NULL, 0);
+    } else if (p.codec == OR_SCHEME) {
+        gsc_encode(x, T, 4, p.cg, p.ld, a);
+    } else if (p.codec == OR_AFOR) {
+        uint32_t qmax[32];
+        uint8_t F[4];
+        or_tuple_max(x, T, 4, qmax);
+        size_t nf = or_afor_partition(qmax, T, 4, F);
+        afor_encode_frames(x, T, 4, F, nf, a);
+    } else {
+        pfd_encode(x, T, 4, p.zeta_num, p.zeta_den, p.pfd_pos, a);
+    }
+    if (a->err) {
+        areas_free(a);
+        return 0;
+    }
+    return 1;
+}
+
+/* Block word and payload of one block; returns the payload words written
+ * (0 on error). */
+long or_block_encode(const uint32_t *x, int kappa, uint32_t *payload, size_t cap, uint32_t *blockword)
+{
+    areas a;
+    if (!block_areas(x, kappa, &a))
+        return 0;
+    size_t Cw = ceil_div((size_t)a.ctrl_bits, 32), Dw = a.D, Ew = a.E;
+    long r = 0;
+    if (Cw < 512 && Dw < 512 && Ew < 512 && Cw + Dw + Ew <= cap) {
+        memcpy(payload, a.ctrl, Cw * 4);
+        memcpy(payload + Cw, a.data, Dw * 4);
+        memcpy(payload + Cw + Dw, a.exc, Ew * 4);
+        *blockword = (uint32_t)kappa | (uint32_t)(Cw << 5) | (uint32_t)(Dw << 14) | (uint32_t)(Ew << 23);
+        r = (long)(Cw + Dw + Ew);
+    }
+    areas_free(&a);
+    return r;
+}
+
+/* Size of one block coded with class kappa, in words (block word included). */
+long or_block_size(const uint32_t *x, int kappa)
+{
+    uint32_t buf[4 * OR_BLOCK_INTS + 64], bw;
+    long w = or_block_encode(x, kappa, buf, sizeof(buf) / 4, &bw);
+    return w > 0 ? 1 + w : OR_EINVAL;
+}
+
+/* Exhaustive selection: sizes of every class, the least one (smaller class
+ * on ties). */
+int or_block_best(const uint32_t *x, long *sizes)
+{
+    int best = -1;
+    for (int kappa = 0; kappa < OR_NCLASS; kappa++) {
+        sizes[kappa] = or_block_size(x, kappa);
+        if (sizes[kappa] > 0 && (best < 0 || sizes[kappa] < sizes[best]))
+            best = kappa;
+    }
+    return best;
+}
+
+/* Decodes one block payload by rebuilding the equivalent whole stream. */
+int or_block_decode(uint32_t blockword, const uint32_t *payload, size_t words, uint32_t *x)
+{
+    int kappa = (int)(blockword & 31u);
+    size_t Cw = (blockword >> 5) & 511u, Dw = (blockword >> 14) & 511u, Ew = (blockword >> 23) & 511u;
+    or_params p;
+    if (!or_block_class_params(kappa, &p) || Cw + Dw + Ew > words)
+        return OR_ECORRUPT;
+    size_t C = round_up(Cw, 4);
+    size_t total = 4 + C + Dw + round_up(Ew, 4);
+    uint32_t *s = (uint32_t *)calloc(total, 4);
+    if (!s)
+        return OR_ENOMEM;
+    s[0] = header_word0(&p);
+    s[1] = OR_BLOCK_INTS;
+    s[2] = (uint32_t)C;
+    s[3] = (uint32_t)Dw;
+    memcpy(s + 4, payload, Cw * 4);
+    /* padding control words read as 1 bits (unary codes end before them) */
+    for (size_t i = Cw; i < C; i++)
+        s[4 + i] = 0xFFFFFFFFu;
+    memcpy(s + 4 + C, payload + Cw, Dw * 4);
+    memcpy(s + 4 + C + Dw, payload + Cw + Dw, Ew * 4);
+    long r = or_decode(s, total, x, OR_BLOCK_INTS);
+    free(s);
+    return r == OR_BLOCK_INTS ? OR_OK : OR_ECORRUPT;
+}
+
+/* The 40 block features (a reading of the selector's inputs): the maximum
+ * bit width / 32; the histogram of per-integer widths 0..32 / 128; the
+ * number of integers wider than maxW - t, t = 1..6, / 128 (all of them when
+ * maxW - t < 0). */
+void or_block_features(const uint32_t *x, double *f)
+{
+    int hist[33] = {0}, maxw = 0;
+    for (int i = 0; i < OR_BLOCK_INTS; i++) {
+        int w = or_bw(x[i]);
+        hist[w]++;
+        if (w > maxw)
+            maxw = w;
+    }
+    f[0] = maxw / 32.0;
+    for (int w = 0; w <= 32; w++)
+        f[1 + w] = hist[w] / (double)OR_BLOCK_INTS;
+    for (int t = 1; t <= 6; t++) {
+        int b = maxw - t, cnt = 0;
+        for (int i = 0; i < OR_BLOCK_INTS; i++)
+            if (b < 0 || or_bw(x[i]) > b)
+                cnt++;
+        f[33 + t] = cnt / (double)OR_BLOCK_INTS;
+    }
+}
+
+/* Codes n integers (zero-padded to whole blocks) block by block with the
+ * given classes, or the exhaustive choice when kappas is NULL; the classes
+ * used are written to kappa_out when it is not NULL.  Returns the words
+ * written. */
+long or_blockmix_encode(const uint32_t *in, size_t n, const uint8_t *kappas, uint32_t *out, size_t cap,
+                        uint8_t *kappa_out)
+{
+    size_t nb = ceil_div(n, OR_BLOCK_INTS);
+    if (n > 0xFFFFFFFFu || cap < 4 + nb)
+        return cap < 4 + nb ? OR_ENOSPC : OR_EINVAL;
+    size_t pos = 4 + nb;
+    uint32_t x[OR_BLOCK_INTS];
+    for (size_t b = 0; b < nb; b++) {
+        size_t m = n - b * OR_BLOCK_INTS < OR_BLOCK_INTS ? n - b * OR_BLOCK_INTS : OR_BLOCK_INTS;
+        memset(x, 0, sizeof(x));
+        memcpy(x, in + b * OR_BLOCK_INTS, m * 4);
+        int kappa;
+        if (kappas) {
+            kappa = kappas[b];
+        } else {
+            long sizes[OR_NCLASS];
+            kappa = or_block_best(x, sizes);
+        }
+        if (kappa_out)
+            kappa_out[b] = (uint8_t)kappa;
+        uint32_t bw;
+        long w = or_block_encode(x, kappa, out + pos, cap - pos, &bw);
+        if (w <= 0)
+            return cap - pos < 4 * OR_BLOCK_INTS + 64 ? OR_ENOSPC : OR_EINVAL;
+        out[4 + b] = bw;
+        pos += (size_t)w;
+    }
+    out[0] = (uint32_t)OR_VERSION | ((uint32_t)OR_CODEC_BLOCKMIX << 8) | (2u << 12);
+    out[1] = (uint32_t)n;
+    out[2] = (uint32_t)nb;
+    out[3] = (uint32_t)(pos - 4 - nb);
+    return (long)pos;
+}
+
+long or_blockmix_decode(const uint32_t *s, size_t words, uint32_t *out, size_t cap)
+{
+    if (words < 4 || s[0] != ((uint32_t)OR_VERSION | ((uint32_t)OR_CODEC_BLOCKMIX << 8) | (2u << 12)))
+        return OR_ECORRUPT;
+    size_t n = s[1], nb = s[2], pw = s[3];
+    if (nb != ceil_div(n, OR_BLOCK_INTS) || 4 + nb + pw > words)
+        return OR_ECORRUPT;
+    if (n > cap)
+        return OR_ENOSPC;
+    size_t pos = 4 + nb, end = 4 + nb + pw;
+    uint32_t x[OR_BLOCK_INTS];
+    for (size_t b = 0; b < nb; b++) {
+        uint32_t bw = s[4 + b];
+        size_t len = ((bw >> 5) & 511u) + ((bw >> 14) & 511u) + ((bw >> 23) & 511u);
+        if (pos + len > end || or_block_decode(bw, s + pos, len, x) != OR_OK)
+            return OR_ECORRUPT;
+        size_t m = n - b * OR_BLOCK_INTS < OR_BLOCK_INTS ? n - b * OR_BLOCK_INTS : OR_BLOCK_INTS;
+        memcpy(out + b * OR_BLOCK_INTS, x, m * 4);
+        pos += len;
+    }
+    return pos == end ? (long)n : OR_ECORRUPT;
+}

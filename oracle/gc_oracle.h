@@ -47,4 +47,17 @@ long or_afor_encode_with(const uint32_t *in, size_t n, const or_params *p, const
                          size_t nf, uint32_t *out, size_t cap);
 long or_decode(const uint32_t *s, size_t words, uint32_t *out, size_t cap);
 
+/* per-block container of the learned selector (see gc_oracle.c) */
+#define OR_BLOCK_INTS 128
+#define OR_NCLASS 16
+int or_block_class_params(int kappa, or_params *p);
+long or_block_encode(const uint32_t *x, int kappa, uint32_t *payload, size_t cap, uint32_t *blockword);
+long or_block_size(const uint32_t *x, int kappa);
+int or_block_best(const uint32_t *x, long *sizes);
+int or_block_decode(uint32_t blockword, const uint32_t *payload, size_t words, uint32_t *x);
+void or_block_features(const uint32_t *x, double *f);
+long or_blockmix_encode(const uint32_t *in, size_t n, const uint8_t *kappas, uint32_t *out, size_t cap,
+                        uint8_t *kappa_out);
+long or_blockmix_decode(const uint32_t *s, size_t words, uint32_t *out, size_t cap);
+
 #endif

@@ -33,6 +33,7 @@
 #include "gc.h"
 #include "gc_device.h"
 #include "gc_format.h"
+#include "gc_wave.h"
 
 namespace gcdev {
 
@@ -50,57 +51,6 @@ constexpr int kLocWords = kChunkWords / kThreads;  // control words per thread
 
 __device__ __forceinline__ uint32_t epoch_next(uint32_t e) {
     return ((e + 1u) & kEpochMask) ? ((e + 1u) & kEpochMask) : 1u;
-}
-
-__device__ __forceinline__ uint32_t mask_of(uint32_t b) { return b >= 32u ? 0xFFFFFFFFu : ((1u << b) - 1u); }
-
-__device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh) {
-    return __builtin_amdgcn_alignbit(hi, lo, sh);
-}
-
-template <int CTRL, int ROWS, bool BC>
-__device__ __forceinline__ uint32_t dpp(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, BC);
-}
-
-// Inclusive scan across a wave64 with DPP row shifts and row broadcasts.
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
-    x += dpp<0x111, 0xF, true>(x);    // row_shr:1
-    x += dpp<0x112, 0xF, true>(x);    // row_shr:2
-    x += dpp<0x114, 0xF, true>(x);    // row_shr:4
-    x += dpp<0x118, 0xF, true>(x);    // row_shr:8
-    x += dpp<0x142, 0xA, false>(x);   // row_bcast:15 into rows 1 and 3
-    x += dpp<0x143, 0xC, false>(x);   // row_bcast:31 into rows 2 and 3
-    return x;
-}
-
-// Inclusive running maximum across a wave64 (same DPP pattern).
-__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
-    x = max(x, dpp<0x111, 0xF, true>(x));
-    x = max(x, dpp<0x112, 0xF, true>(x));
-    x = max(x, dpp<0x114, 0xF, true>(x));
-    x = max(x, dpp<0x118, 0xF, true>(x));
-    x = max(x, dpp<0x142, 0xA, false>(x));
-    x = max(x, dpp<0x143, 0xC, false>(x));
-    return x;
-}
-
-// The value of the previous lane (0 in lane 0): DPP wave_shr:1.
-__device__ __forceinline__ uint32_t wave_shr1(uint32_t x) { return dpp<0x138, 0xF, true>(x); }
-
-__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
-    return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(x), 63);
-}
-
-// 64-bit wave sum from 32-bit scans (16-bit halves of the low word cannot
-// overflow across 64 lanes).
-__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
-    const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
-    return (uint64_t)wave_sum(lo & 0xFFFFu) + ((uint64_t)wave_sum(lo >> 16) << 16) + ((uint64_t)wave_sum(hi) << 32);
-}
-
-__device__ __forceinline__ uint32_t lane_id() {
-    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
 
 // Exclusive scan over the workgroup; `tmp` holds kWaves words of LDS.
@@ -865,14 +815,6 @@ struct WaveSmem {
     uint32_t rec[TTM + 4];   // + room for one more entry while the records are built
 };
 
-// Orders a wave's LDS writes before its later LDS reads by other lanes.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ uint32_t wave_any(bool b) { return __ballot(b) != 0ull ? 1u : 0u; }
 
 // Tuple records from unit starts.  A unit (selector, frame) u of the tile
 // covers the tuples from start_u on; info[u] = {base, bw} such that tuple t

@@ -17,6 +17,7 @@
 #include "gc.h"
 #include "gc_device.h"
 #include "gc_format.h"
+#include "gc_blocks.h"
 
 namespace gcdev {
 int codec_class(uint32_t w0);
@@ -134,11 +135,38 @@ struct Scratch {
 
 }  // namespace
 
+// Device scratch of the block container encoder: per-block payload words
+// and offsets, the scan's chunk sums, and {total words, bad class flag}.
+struct BlockScratch {
+    uint32_t *words = nullptr, *offs = nullptr, *csum = nullptr, *result = nullptr;
+    size_t cap = 0;
+    gc_status reserve(size_t nblocks) {
+        if (nblocks <= cap && result) return GC_OK;
+        HIP_OK(hipDeviceSynchronize());
+        release();
+        const size_t c = std::max(nblocks, (size_t)1024);
+        gc_status rc = dev_alloc(&words, c);
+        if (!rc) rc = dev_alloc(&offs, c);
+        if (!rc) rc = dev_alloc(&csum, gcblk::scan_chunks(c) + 1);
+        if (!rc) rc = dev_alloc(&result, 2);
+        if (!rc) cap = c;
+        return rc;
+    }
+    void release() {
+        dev_free(words);
+        dev_free(offs);
+        dev_free(csum);
+        dev_free(result);
+        cap = 0;
+    }
+};
+
 struct gc_ctx {
     int device = 0;
     int num_cus = 0;
     Status *status = nullptr;
     Scratch single;
+    BlockScratch blk;
     int tile_w = kDefaultWaveTile, tile_p = kDefaultPfdTile;
     std::mutex mu;
 };
@@ -700,6 +728,7 @@ gc_status gc_ctx_destroy(gc_ctx *ctx) {
     (void)hipDeviceSynchronize();
     dev_free(ctx->status);
     ctx->single.release();
+    ctx->blk.release();
     delete ctx;
     return GC_OK;
 }
@@ -876,6 +905,66 @@ gc_status gc_plan_config(const gc_plan *plan, uint32_t *tile_ints, uint32_t *pfd
     if (pfd_tile_ints) *pfd_tile_ints = (uint32_t)plan->tile_p;
     if (tiles) *tiles = t;
     if (sum_tiles) *sum_tiles = st;
+    return GC_OK;
+}
+
+gc_status gc_block_features(gc_ctx *ctx, const uint32_t *d_in, size_t nblocks, float *d_feat, void *hip_stream) {
+    if (!ctx || (nblocks && (!d_in || !d_feat))) return GC_EINVAL;
+    if (nblocks > 0xFFFFFFFFull) return GC_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    return gcblk::launch_block_features(d_in, nblocks, d_feat, (hipStream_t)hip_stream) ? GC_EDEVICE : GC_OK;
+}
+
+gc_status gc_block_sizes(gc_ctx *ctx, const uint32_t *d_in, size_t nblocks, uint32_t *d_sizes, uint8_t *d_best,
+                         void *hip_stream) {
+    if (!ctx || (nblocks && !d_in)) return GC_EINVAL;
+    if (nblocks > 0xFFFFFFFFull) return GC_EINVAL;
+    if (!d_sizes && !d_best) return GC_OK;
+    (void)hipSetDevice(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    uint32_t *sz = d_sizes;
+    uint8_t *best = d_best;
+    // both outputs are written by one kernel; a NULL one goes to scratch
+    if (!sz || !best) {
+        if (gc_status rc = ctx->blk.reserve(nblocks * (size_t)gcblk::kClasses)) return rc;
+        if (!sz) sz = ctx->blk.words;
+        if (!best) best = reinterpret_cast<uint8_t *>(ctx->blk.offs);
+    }
+    return gcblk::launch_block_sizes(d_in, nblocks, sz, best, (hipStream_t)hip_stream) ? GC_EDEVICE : GC_OK;
+}
+
+size_t gc_blockmix_bound_words(size_t n) {
+    const size_t nb = (n + gcblk::kBlockInts - 1) / gcblk::kBlockInts;
+    return 4 + nb * (1 + (size_t)gcblk::kMaxPayloadWords);
+}
+
+gc_status gc_blockmix_encode(gc_ctx *ctx, const uint32_t *d_in, size_t n, const uint8_t *d_class, uint32_t *d_out,
+                             size_t out_cap_words, size_t *out_words, void *hip_stream) {
+    if (!ctx || !out_words || !d_out || (n && (!d_in || !d_class))) return GC_EINVAL;
+    // offsets and the total are 32-bit words
+    if (gc_blockmix_bound_words(n) > 0xFFFFFFFFull) return GC_EINVAL;
+    const size_t nb = (n + gcblk::kBlockInts - 1) / gcblk::kBlockInts;
+    if (out_cap_words < 4 + nb) return GC_ENOSPC;
+    (void)hipSetDevice(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t s = (hipStream_t)hip_stream;
+    uint32_t res[2] = {0u, 0u};
+    if (nb) {
+        if (gc_status rc = ctx->blk.reserve(nb)) return rc;
+        if (gcblk::launch_blockmix_plan(d_in, nb, d_class, ctx->blk.words, ctx->blk.offs, ctx->blk.csum,
+                                        ctx->blk.result, s))
+            return GC_EDEVICE;
+        HIP_OK(hipMemcpyAsync(res, ctx->blk.result, sizeof(res), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if (res[1]) return GC_EINVAL;
+    }
+    const size_t total = 4 + nb + (size_t)res[0];
+    if (total > out_cap_words) return GC_ENOSPC;
+    const uint32_t hdr[4] = {GC_FMT_VERSION | (4u << 8) | (2u << 12), (uint32_t)n, (uint32_t)nb, res[0]};
+    HIP_OK(hipMemcpyAsync(d_out, hdr, sizeof(hdr), hipMemcpyHostToDevice, s));
+    if (nb && gcblk::launch_blockmix_emit(d_in, nb, d_class, ctx->blk.offs, d_out, s)) return GC_EDEVICE;
+    HIP_OK(hipStreamSynchronize(s));
+    *out_words = total;
     return GC_OK;
 }
 

@@ -102,9 +102,15 @@ def lib():
         L.gc_plan_timings.argtypes = [vp, ctypes.c_uint32, f32p, u32p]
         L.gc_plan_timings.restype = ctypes.c_int
         L.gc_sync_status.argtypes = [vp, vp, u32p]
+        L.gc_block_features.argtypes = [vp, vp, sz, vp, vp]
+        L.gc_block_sizes.argtypes = [vp, vp, sz, vp, vp, vp]
+        L.gc_blockmix_bound_words.argtypes = [sz]
+        L.gc_blockmix_bound_words.restype = sz
+        L.gc_blockmix_encode.argtypes = [vp, vp, sz, vp, vp, sz, ctypes.POINTER(sz), vp]
         for f in ("gc_encode", "gc_encode_lists", "gc_ctx_create", "gc_ctx_destroy", "gc_decode",
                   "gc_plan_create", "gc_plan_destroy", "gc_decode_batch", "gc_decode_each",
-                  "gc_plan_config", "gc_sync_status"):
+                  "gc_plan_config", "gc_sync_status", "gc_block_features", "gc_block_sizes",
+                  "gc_blockmix_encode"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
         return L
@@ -207,6 +213,26 @@ class Context:
         rc, d = self.sync_status(stream)
         _check("gc_sync_status", rc, d)
 
+    # ---- per-block container (learned codec selector) ----
+    def block_features(self, d_in, nblocks, d_feat, stream=None):
+        """gc_block_features: d_in int32 [nblocks*128], d_feat float32 [nblocks, 40]."""
+        _check("gc_block_features", lib().gc_block_features(self._h, _ptr(d_in), int(nblocks), _ptr(d_feat),
+                                                              _stream_handle(stream)))
+
+    def block_sizes(self, d_in, nblocks, d_sizes=None, d_best=None, stream=None):
+        """gc_block_sizes: d_sizes int32 [nblocks, 16], d_best uint8 [nblocks]; either may be None."""
+        _check("gc_block_sizes", lib().gc_block_sizes(
+            self._h, _ptr(d_in), int(nblocks), None if d_sizes is None else _ptr(d_sizes),
+            None if d_best is None else _ptr(d_best), _stream_handle(stream)))
+
+    def blockmix_encode(self, d_in, n, d_class, d_out, stream=None):
+        """gc_blockmix_encode: returns the container's length in words."""
+        used = ctypes.c_size_t()
+        _check("gc_blockmix_encode", lib().gc_blockmix_encode(
+            self._h, _ptr(d_in), int(n), _ptr(d_class), _ptr(d_out), int(d_out.numel()), ctypes.byref(used),
+            _stream_handle(stream)))
+        return used.value
+
     def close(self):
         if self._h:
             lib().gc_ctx_destroy(self._h)
@@ -302,6 +328,15 @@ def unpad(out, out_offs, lengths):
     if np.array_equal(np.diff(out_offs), lengths):
         return out[:int(lengths.sum())]
     return np.concatenate([out[int(o):int(o) + int(L)] for o, L in zip(out_offs[:-1], lengths)])
+
+
+BLOCK_INTS = 128
+BLOCK_CLASSES = 16
+BLOCK_FEATURES = 40
+
+
+def blockmix_bound_words(n):
+    return int(lib().gc_blockmix_bound_words(int(n)))
 
 
 def to_device(a_u32, device="cuda"):
