@@ -264,6 +264,76 @@ size_t gc_blockmix_bound_words(size_t n);
 gc_status gc_blockmix_encode(gc_ctx *ctx, const uint32_t *d_in, size_t n, const uint8_t *d_class,
                              uint32_t *d_out, size_t out_cap_words, size_t *out_words, void *hip_stream);
 
+/* ---- learned codec selector -------------------------------------------------
+ * Not part of the paper.  A network maps the 40 features of a block
+ * (gc_block_features) to scores of the GC_BLOCK_CLASSES classes:
+ * 40 -> 64 -> 64 -> 16, ReLU after the two hidden layers, softmax.  Matrix
+ * products take bf16 operands (the weights and activations rounded to
+ * nearest even) and accumulate in fp32 on the matrix cores; parameters and
+ * Adam moments are fp32.  Parameters form one flat fp32 vector of
+ * gc_mlp_param_count() values: W1[40][64], b1[64], W2[64][64], b2[64],
+ * W3[64][16], b3[16], row-major, the first index the layer input.
+ * Training minimises the mean over a batch of -log P[label] + lam *
+ * sum_k P_k cost_k, where cost_k >= 0 is class k's relative size excess
+ * over the block's least size (so the second term is the expected excess).
+ * Calls on one model must not overlap.                                      */
+typedef struct gc_mlp gc_mlp;
+
+typedef struct {
+    float lr, beta1, beta2, eps; /* Adam */
+    float lam;                   /* weight of the expected-excess term */
+    uint32_t batch;              /* samples per step, at most the model's max_batch */
+    uint32_t reserved[2];
+} gc_adam_opts;
+
+size_t gc_mlp_param_count(void);
+
+/* A model on ctx's device with zero parameters; max_batch bounds the batch
+ * of gc_mlp_grad and gc_mlp_train.  Device memory is allocated here only. */
+gc_status gc_mlp_create(gc_ctx *ctx, uint32_t max_batch, gc_mlp **out);
+gc_status gc_mlp_destroy(gc_mlp *model);
+
+/* Host parameter vector in/out (count must be gc_mlp_param_count()); set
+ * also clears the Adam moments and step.  Both return when the copy is done. */
+gc_status gc_mlp_set_params(gc_mlp *model, const float *h_params, size_t count, void *hip_stream);
+gc_status gc_mlp_get_params(gc_mlp *model, float *h_params, size_t count, void *hip_stream);
+
+/* Scores of n feature rows (device, n x 40): logits to d_logits (n x 16,
+ * may be NULL) and the class of the largest logit (the smaller class on
+ * ties) to d_class (may be NULL).  Asynchronous.                            */
+gc_status gc_mlp_forward(gc_mlp *model, const float *d_feat, size_t n, float *d_logits, uint8_t *d_class,
+                         void *hip_stream);
+
+/* Gradient of the mean loss over `batch` samples: sample r is feature row
+ * d_index[r] (row r when d_index is NULL) with label d_label[row] and costs
+ * d_cost[row * 16 ..] (only read when lam != 0).  Writes the flat gradient
+ * to d_grad and the mean loss to d_loss (either may be NULL).  Asynchronous. */
+gc_status gc_mlp_grad(gc_mlp *model, const float *d_feat, const uint8_t *d_label, const float *d_cost,
+                      const uint32_t *d_index, uint32_t batch, float lam, float *d_grad, float *d_loss,
+                      void *hip_stream);
+
+/* One pass of Adam steps over the samples d_index[0 .. nindex) (rows
+ * 0 .. nindex when NULL), opt->batch at a time, the last batch possibly
+ * smaller; the mean loss of step s goes to d_loss[s] (may be NULL).
+ * Asynchronous.                                                              */
+gc_status gc_mlp_train(gc_mlp *model, const float *d_feat, const uint8_t *d_label, const float *d_cost,
+                       const uint32_t *d_index, size_t nindex, const gc_adam_opts *opt, float *d_loss,
+                       void *hip_stream);
+
+/* Block-container encoder with the class of every block chosen by
+ *   GC_SELECT_EXHAUSTIVE  the least coded size (gc_block_sizes),
+ *   GC_SELECT_LEARNED     the model's class for the block's features,
+ *   GC_SELECT_FIXED       fixed_class for every block.
+ * Same input, output and errors as gc_blockmix_encode; the classes also go
+ * to d_class_out when it is not NULL (one byte per block).  Returns when
+ * the container is written.                                                 */
+#define GC_SELECT_EXHAUSTIVE 0
+#define GC_SELECT_LEARNED 1
+#define GC_SELECT_FIXED 2
+gc_status gc_encode_blocks(gc_ctx *ctx, const uint32_t *d_in, size_t n, int mode, gc_mlp *model,
+                           uint32_t fixed_class, uint32_t *d_out, size_t out_cap_words, size_t *out_words,
+                           uint8_t *d_class_out, void *hip_stream);
+
 /* Library version string. */
 const char *gc_version(void);
 

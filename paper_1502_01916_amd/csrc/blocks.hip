@@ -368,8 +368,8 @@ __global__ __launch_bounds__(kThreads) void gc_block_sizes_kernel(const uint32_t
             bk = kappa;
         }
     }
-    if (lane < (uint32_t)kClasses) sizes[blk * (size_t)kClasses + lane] = mine;
-    if (lane == 0u) best[blk] = (uint8_t)bk;
+    if (sizes && lane < (uint32_t)kClasses) sizes[blk * (size_t)kClasses + lane] = mine;
+    if (best && lane == 0u) best[blk] = (uint8_t)bk;
 }
 
 // ---- container encode ----------------------------------------------------------

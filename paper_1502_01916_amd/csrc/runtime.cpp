@@ -5,11 +5,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <mutex>
+#include <new>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -18,6 +20,7 @@
 #include "gc_device.h"
 #include "gc_format.h"
 #include "gc_blocks.h"
+#include "gc_mlp.h"
 
 namespace gcdev {
 int codec_class(uint32_t w0);
@@ -139,6 +142,8 @@ struct Scratch {
 // and offsets, the scan's chunk sums, and {total words, bad class flag}.
 struct BlockScratch {
     uint32_t *words = nullptr, *offs = nullptr, *csum = nullptr, *result = nullptr;
+    float *feat = nullptr;   // features of every block (selector input)
+    uint8_t *cls = nullptr;  // class of every block
     size_t cap = 0;
     gc_status reserve(size_t nblocks) {
         if (nblocks <= cap && result) return GC_OK;
@@ -149,6 +154,8 @@ struct BlockScratch {
         if (!rc) rc = dev_alloc(&offs, c);
         if (!rc) rc = dev_alloc(&csum, gcblk::scan_chunks(c) + 1);
         if (!rc) rc = dev_alloc(&result, 2);
+        if (!rc) rc = dev_alloc(&feat, c * gcblk::kFeatures);
+        if (!rc) rc = dev_alloc(&cls, c);
         if (!rc) cap = c;
         return rc;
     }
@@ -157,6 +164,8 @@ struct BlockScratch {
         dev_free(offs);
         dev_free(csum);
         dev_free(result);
+        dev_free(feat);
+        dev_free(cls);
         cap = 0;
     }
 };
@@ -921,21 +930,34 @@ gc_status gc_block_sizes(gc_ctx *ctx, const uint32_t *d_in, size_t nblocks, uint
     if (nblocks > 0xFFFFFFFFull) return GC_EINVAL;
     if (!d_sizes && !d_best) return GC_OK;
     (void)hipSetDevice(ctx->device);
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    uint32_t *sz = d_sizes;
-    uint8_t *best = d_best;
-    // both outputs are written by one kernel; a NULL one goes to scratch
-    if (!sz || !best) {
-        if (gc_status rc = ctx->blk.reserve(nblocks * (size_t)gcblk::kClasses)) return rc;
-        if (!sz) sz = ctx->blk.words;
-        if (!best) best = reinterpret_cast<uint8_t *>(ctx->blk.offs);
-    }
-    return gcblk::launch_block_sizes(d_in, nblocks, sz, best, (hipStream_t)hip_stream) ? GC_EDEVICE : GC_OK;
+    return gcblk::launch_block_sizes(d_in, nblocks, d_sizes, d_best, (hipStream_t)hip_stream) ? GC_EDEVICE : GC_OK;
 }
 
 size_t gc_blockmix_bound_words(size_t n) {
     const size_t nb = (n + gcblk::kBlockInts - 1) / gcblk::kBlockInts;
     return 4 + nb * (1 + (size_t)gcblk::kMaxPayloadWords);
+}
+
+// The container of d_in with block b in class cls[b]; ctx->mu held.
+static gc_status blockmix_encode_locked(gc_ctx *ctx, const uint32_t *d_in, size_t n, size_t nb, const uint8_t *cls,
+                                        uint32_t *d_out, size_t out_cap_words, size_t *out_words, hipStream_t s) {
+    uint32_t res[2] = {0u, 0u};
+    if (nb) {
+        if (gcblk::launch_blockmix_plan(d_in, nb, cls, ctx->blk.words, ctx->blk.offs, ctx->blk.csum, ctx->blk.result,
+                                        s))
+            return GC_EDEVICE;
+        HIP_OK(hipMemcpyAsync(res, ctx->blk.result, sizeof(res), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if (res[1]) return GC_EINVAL;
+    }
+    const size_t total = 4 + nb + (size_t)res[0];
+    if (total > out_cap_words) return GC_ENOSPC;
+    const uint32_t hdr[4] = {GC_FMT_VERSION | (4u << 8) | (2u << 12), (uint32_t)n, (uint32_t)nb, res[0]};
+    HIP_OK(hipMemcpyAsync(d_out, hdr, sizeof(hdr), hipMemcpyHostToDevice, s));
+    if (nb && gcblk::launch_blockmix_emit(d_in, nb, cls, ctx->blk.offs, d_out, s)) return GC_EDEVICE;
+    HIP_OK(hipStreamSynchronize(s));
+    *out_words = total;
+    return GC_OK;
 }
 
 gc_status gc_blockmix_encode(gc_ctx *ctx, const uint32_t *d_in, size_t n, const uint8_t *d_class, uint32_t *d_out,
@@ -947,25 +969,178 @@ gc_status gc_blockmix_encode(gc_ctx *ctx, const uint32_t *d_in, size_t n, const 
     if (out_cap_words < 4 + nb) return GC_ENOSPC;
     (void)hipSetDevice(ctx->device);
     std::lock_guard<std::mutex> lk(ctx->mu);
+    if (nb)
+        if (gc_status rc = ctx->blk.reserve(nb)) return rc;
+    return blockmix_encode_locked(ctx, d_in, n, nb, d_class, d_out, out_cap_words, out_words,
+                                  (hipStream_t)hip_stream);
+}
+
+// ---- selector network ----------------------------------------------------------
+
+struct gc_mlp {
+    int device = 0;
+    float *theta = nullptr, *m = nullptr, *v = nullptr, *partial = nullptr;
+    uint16_t *wbuf = nullptr;
+    gcmlp::Packed w{};
+    uint32_t max_batch = 0;
+    uint64_t step = 0;
+    std::mutex mu;
+};
+
+static constexpr size_t kPackedHalves = 64 * 48 + 64 * 64 * 2 + 16 * 64 * 2;
+
+gc_status gc_mlp_create(gc_ctx *ctx, uint32_t max_batch, gc_mlp **out) {
+    if (!ctx || !out || !max_batch) return GC_EINVAL;
+    *out = nullptr;
+    (void)hipSetDevice(ctx->device);
+    gc_mlp *m = new (std::nothrow) gc_mlp();
+    if (!m) return GC_ENOMEM;
+    m->device = ctx->device;
+    m->max_batch = max_batch;
+    const size_t groups = ((size_t)max_batch + gcmlp::kRows - 1) / gcmlp::kRows;
+    gc_status rc = dev_alloc(&m->theta, gcmlp::kParams);
+    if (!rc) rc = dev_alloc(&m->m, gcmlp::kParams);
+    if (!rc) rc = dev_alloc(&m->v, gcmlp::kParams);
+    if (!rc) rc = dev_alloc(&m->partial, groups * gcmlp::kPartialStride);
+    if (!rc) rc = dev_alloc(&m->wbuf, kPackedHalves);
+    if (!rc && (hipMemset(m->theta, 0, gcmlp::kParams * 4) != hipSuccess ||
+                hipMemset(m->m, 0, gcmlp::kParams * 4) != hipSuccess ||
+                hipMemset(m->v, 0, gcmlp::kParams * 4) != hipSuccess ||
+                hipMemset(m->wbuf, 0, kPackedHalves * 2) != hipSuccess || hipDeviceSynchronize() != hipSuccess))
+        rc = GC_EDEVICE;
+    if (rc) {
+        gc_mlp_destroy(m);
+        return rc;
+    }
+    m->w.w1t = m->wbuf;
+    m->w.w2t = m->w.w1t + 64 * 48;
+    m->w.w2 = m->w.w2t + 64 * 64;
+    m->w.w3t = m->w.w2 + 64 * 64;
+    m->w.w3 = m->w.w3t + 16 * 64;
+    *out = m;
+    return GC_OK;
+}
+
+gc_status gc_mlp_destroy(gc_mlp *m) {
+    if (!m) return GC_EINVAL;
+    (void)hipSetDevice(m->device);
+    (void)hipDeviceSynchronize();
+    dev_free(m->theta);
+    dev_free(m->m);
+    dev_free(m->v);
+    dev_free(m->partial);
+    dev_free(m->wbuf);
+    delete m;
+    return GC_OK;
+}
+
+size_t gc_mlp_param_count(void) { return gcmlp::kParams; }
+
+gc_status gc_mlp_set_params(gc_mlp *m, const float *h_theta, size_t count, void *hip_stream) {
+    if (!m || !h_theta || count != (size_t)gcmlp::kParams) return GC_EINVAL;
+    (void)hipSetDevice(m->device);
+    std::lock_guard<std::mutex> lk(m->mu);
     hipStream_t s = (hipStream_t)hip_stream;
-    uint32_t res[2] = {0u, 0u};
+    HIP_OK(hipMemcpyAsync(m->theta, h_theta, count * 4, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemsetAsync(m->m, 0, count * 4, s));
+    HIP_OK(hipMemsetAsync(m->v, 0, count * 4, s));
+    if (gcmlp::launch_pack(m->theta, m->w, s)) return GC_EDEVICE;
+    HIP_OK(hipStreamSynchronize(s));
+    m->step = 0;
+    return GC_OK;
+}
+
+gc_status gc_mlp_get_params(gc_mlp *m, float *h_theta, size_t count, void *hip_stream) {
+    if (!m || !h_theta || count != (size_t)gcmlp::kParams) return GC_EINVAL;
+    (void)hipSetDevice(m->device);
+    std::lock_guard<std::mutex> lk(m->mu);
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIP_OK(hipMemcpyAsync(h_theta, m->theta, count * 4, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return GC_OK;
+}
+
+gc_status gc_mlp_forward(gc_mlp *m, const float *d_feat, size_t n, float *d_logits, uint8_t *d_class,
+                         void *hip_stream) {
+    if (!m || (n && !d_feat) || n > 0xFFFFFFFFull) return GC_EINVAL;
+    (void)hipSetDevice(m->device);
+    return gcmlp::launch_forward(d_feat, n, m->theta, m->w, d_logits, d_class, (hipStream_t)hip_stream) ? GC_EDEVICE
+                                                                                                         : GC_OK;
+}
+
+gc_status gc_mlp_grad(gc_mlp *m, const float *d_feat, const uint8_t *d_label, const float *d_cost,
+                      const uint32_t *d_index, uint32_t batch, float lam, float *d_grad, float *d_loss,
+                      void *hip_stream) {
+    if (!m || !batch || batch > m->max_batch || !d_feat || !d_label || (lam != 0.f && !d_cost)) return GC_EINVAL;
+    (void)hipSetDevice(m->device);
+    std::lock_guard<std::mutex> lk(m->mu);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const gcmlp::Batch b = {d_feat, d_index, d_label, lam != 0.f ? d_cost : nullptr, 0, batch, lam};
+    const uint32_t parts = (batch + gcmlp::kRows - 1) / gcmlp::kRows;
+    if (gcmlp::launch_grad_partials(b, m->theta, m->w, m->partial, s)) return GC_EDEVICE;
+    if (gcmlp::launch_reduce_adam(m->partial, parts, d_grad, d_loss, m->theta, m->m, m->v, m->w, false, 0.f, 0.f,
+                                  0.f, 0.f, 0.f, 0.f, s))
+        return GC_EDEVICE;
+    return GC_OK;
+}
+
+gc_status gc_mlp_train(gc_mlp *m, const float *d_feat, const uint8_t *d_label, const float *d_cost,
+                       const uint32_t *d_index, size_t nindex, const gc_adam_opts *opt, float *d_loss,
+                       void *hip_stream) {
+    if (!m || !opt || !d_feat || !d_label || !opt->batch || opt->batch > m->max_batch) return GC_EINVAL;
+    if (opt->lam != 0.f && !d_cost) return GC_EINVAL;
+    if (!(opt->lr > 0.f) || !(opt->beta1 >= 0.f && opt->beta1 < 1.f) || !(opt->beta2 >= 0.f && opt->beta2 < 1.f) ||
+        !(opt->eps > 0.f))
+        return GC_EINVAL;
+    (void)hipSetDevice(m->device);
+    std::lock_guard<std::mutex> lk(m->mu);
+    hipStream_t s = (hipStream_t)hip_stream;
+    size_t k = 0;
+    for (size_t row0 = 0; row0 < nindex; row0 += opt->batch, k++) {
+        const uint32_t count = (uint32_t)std::min<size_t>(opt->batch, nindex - row0);
+        const gcmlp::Batch b = {d_feat, d_index, d_label, opt->lam != 0.f ? d_cost : nullptr, row0, count, opt->lam};
+        const uint64_t t = ++m->step;
+        const float c1 = (float)(1.0 / (1.0 - std::pow((double)opt->beta1, (double)t)));
+        const float c2 = (float)(1.0 / (1.0 - std::pow((double)opt->beta2, (double)t)));
+        if (gcmlp::launch_grad_partials(b, m->theta, m->w, m->partial, s)) return GC_EDEVICE;
+        if (gcmlp::launch_reduce_adam(m->partial, (count + gcmlp::kRows - 1) / gcmlp::kRows, nullptr,
+                                      d_loss ? d_loss + k : nullptr, m->theta, m->m, m->v, m->w, true, opt->lr,
+                                      opt->beta1, opt->beta2, opt->eps, c1, c2, s))
+            return GC_EDEVICE;
+    }
+    return GC_OK;
+}
+
+gc_status gc_encode_blocks(gc_ctx *ctx, const uint32_t *d_in, size_t n, int mode, gc_mlp *model,
+                           uint32_t fixed_class, uint32_t *d_out, size_t out_cap_words, size_t *out_words,
+                           uint8_t *d_class_out, void *hip_stream) {
+    if (!ctx || !out_words || !d_out || (n && !d_in)) return GC_EINVAL;
+    if (mode == GC_SELECT_LEARNED && (!model || model->device != ctx->device)) return GC_EINVAL;
+    if (mode == GC_SELECT_FIXED && fixed_class >= (uint32_t)gcblk::kClasses) return GC_EINVAL;
+    if (mode != GC_SELECT_EXHAUSTIVE && mode != GC_SELECT_LEARNED && mode != GC_SELECT_FIXED) return GC_EINVAL;
+    if (gc_blockmix_bound_words(n) > 0xFFFFFFFFull) return GC_EINVAL;
+    const size_t nb = (n + gcblk::kBlockInts - 1) / gcblk::kBlockInts;
+    if (out_cap_words < 4 + nb) return GC_ENOSPC;
+    (void)hipSetDevice(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t s = (hipStream_t)hip_stream;
+    uint8_t *cls = d_class_out;
     if (nb) {
         if (gc_status rc = ctx->blk.reserve(nb)) return rc;
-        if (gcblk::launch_blockmix_plan(d_in, nb, d_class, ctx->blk.words, ctx->blk.offs, ctx->blk.csum,
-                                        ctx->blk.result, s))
-            return GC_EDEVICE;
-        HIP_OK(hipMemcpyAsync(res, ctx->blk.result, sizeof(res), hipMemcpyDeviceToHost, s));
-        HIP_OK(hipStreamSynchronize(s));
-        if (res[1]) return GC_EINVAL;
+        if (!cls) cls = ctx->blk.cls;
+        int err = 0;
+        if (mode == GC_SELECT_EXHAUSTIVE) {
+            err = gcblk::launch_block_sizes(d_in, nb, nullptr, cls, s);
+        } else if (mode == GC_SELECT_LEARNED) {
+            std::lock_guard<std::mutex> lm(model->mu);
+            err = gcblk::launch_block_features(d_in, nb, ctx->blk.feat, s);
+            if (!err) err = gcmlp::launch_forward(ctx->blk.feat, nb, model->theta, model->w, nullptr, cls, s);
+        } else {
+            err = hipMemsetAsync(cls, (int)fixed_class, nb, s) != hipSuccess;
+        }
+        if (err) return GC_EDEVICE;
     }
-    const size_t total = 4 + nb + (size_t)res[0];
-    if (total > out_cap_words) return GC_ENOSPC;
-    const uint32_t hdr[4] = {GC_FMT_VERSION | (4u << 8) | (2u << 12), (uint32_t)n, (uint32_t)nb, res[0]};
-    HIP_OK(hipMemcpyAsync(d_out, hdr, sizeof(hdr), hipMemcpyHostToDevice, s));
-    if (nb && gcblk::launch_blockmix_emit(d_in, nb, d_class, ctx->blk.offs, d_out, s)) return GC_EDEVICE;
-    HIP_OK(hipStreamSynchronize(s));
-    *out_words = total;
-    return GC_OK;
+    return blockmix_encode_locked(ctx, d_in, n, nb, cls, d_out, out_cap_words, out_words, s);
 }
 
 gc_status gc_sync_status(gc_ctx *ctx, void *hip_stream, uint32_t *detail) {

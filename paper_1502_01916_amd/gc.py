@@ -63,6 +63,16 @@ class PlanOpts(ctypes.Structure):
                 ("reserved", ctypes.c_uint32 * 2)]
 
 
+class AdamOpts(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("lam", ctypes.c_float), ("batch", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
+
+
+def adam_opts(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, lam=0.0, batch=4096):
+    return AdamOpts(lr, beta1, beta2, eps, lam, batch)
+
+
 def params(k=4, cg=1, ld=LD_CU, pfd_pos=PFD_LINKED, zeta=(1, 10), delta=False):
     return Params(int(k), int(cg), int(ld), int(pfd_pos), 0, int(zeta[0]), int(zeta[1]),
                   DELTA if delta else 0)
@@ -80,6 +90,7 @@ def lib():
         vp, sz, u32p = ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint32)
         u64p = ctypes.POINTER(ctypes.c_uint64)
         i = ctypes.c_int
+        f32p = ctypes.POINTER(ctypes.c_float)
         L.gc_version.restype = ctypes.c_char_p
         L.gc_encoded_bound_words.argtypes = [sz, i, ctypes.POINTER(Params)]
         L.gc_encoded_bound_words.restype = sz
@@ -98,7 +109,6 @@ def lib():
         L.gc_decode_batch.argtypes = [vp, vp, vp, vp]
         L.gc_decode_each.argtypes = [vp, vp, vp, vp]
         L.gc_plan_config.argtypes = [vp, u32p, u32p, u64p, u64p]
-        f32p = ctypes.POINTER(ctypes.c_float)
         L.gc_plan_timings.argtypes = [vp, ctypes.c_uint32, f32p, u32p]
         L.gc_plan_timings.restype = ctypes.c_int
         L.gc_sync_status.argtypes = [vp, vp, u32p]
@@ -107,10 +117,20 @@ def lib():
         L.gc_blockmix_bound_words.argtypes = [sz]
         L.gc_blockmix_bound_words.restype = sz
         L.gc_blockmix_encode.argtypes = [vp, vp, sz, vp, vp, sz, ctypes.POINTER(sz), vp]
+        L.gc_mlp_param_count.restype = sz
+        L.gc_mlp_create.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(vp)]
+        L.gc_mlp_destroy.argtypes = [vp]
+        L.gc_mlp_set_params.argtypes = [vp, f32p, sz, vp]
+        L.gc_mlp_get_params.argtypes = [vp, f32p, sz, vp]
+        L.gc_mlp_forward.argtypes = [vp, vp, sz, vp, vp, vp]
+        L.gc_mlp_grad.argtypes = [vp, vp, vp, vp, vp, ctypes.c_uint32, ctypes.c_float, vp, vp, vp]
+        L.gc_mlp_train.argtypes = [vp, vp, vp, vp, vp, sz, ctypes.POINTER(AdamOpts), vp, vp]
+        L.gc_encode_blocks.argtypes = [vp, vp, sz, i, vp, ctypes.c_uint32, vp, sz, ctypes.POINTER(sz), vp, vp]
         for f in ("gc_encode", "gc_encode_lists", "gc_ctx_create", "gc_ctx_destroy", "gc_decode",
                   "gc_plan_create", "gc_plan_destroy", "gc_decode_batch", "gc_decode_each",
                   "gc_plan_config", "gc_sync_status", "gc_block_features", "gc_block_sizes",
-                  "gc_blockmix_encode"):
+                  "gc_blockmix_encode", "gc_mlp_create", "gc_mlp_destroy", "gc_mlp_set_params",
+                  "gc_mlp_get_params", "gc_mlp_forward", "gc_mlp_grad", "gc_mlp_train", "gc_encode_blocks"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
         return L
@@ -233,6 +253,15 @@ class Context:
             _stream_handle(stream)))
         return used.value
 
+    def encode_blocks(self, d_in, n, mode, d_out, model=None, fixed_class=0, d_class_out=None, stream=None):
+        """gc_encode_blocks: returns the container's length in words."""
+        used = ctypes.c_size_t()
+        _check("gc_encode_blocks", lib().gc_encode_blocks(
+            self._h, _ptr(d_in), int(n), int(mode), None if model is None else model._h, int(fixed_class),
+            _ptr(d_out), int(d_out.numel()), ctypes.byref(used),
+            None if d_class_out is None else _ptr(d_class_out), _stream_handle(stream)))
+        return used.value
+
     def close(self):
         if self._h:
             lib().gc_ctx_destroy(self._h)
@@ -328,6 +357,64 @@ def unpad(out, out_offs, lengths):
     if np.array_equal(np.diff(out_offs), lengths):
         return out[:int(lengths.sum())]
     return np.concatenate([out[int(o):int(o) + int(L)] for o, L in zip(out_offs[:-1], lengths)])
+
+
+SELECT_EXHAUSTIVE, SELECT_LEARNED, SELECT_FIXED = 0, 1, 2
+
+
+def _opt(t):
+    return None if t is None else _ptr(t)
+
+
+class Mlp:
+    """The selector network: gc_mlp_create / set/get_params / forward / grad /
+    train / destroy.  Device tensors in, device tensors out."""
+
+    def __init__(self, ctx: Context, max_batch=4096):
+        self.ctx = ctx
+        self._h = ctypes.c_void_p()
+        _check("gc_mlp_create", lib().gc_mlp_create(ctx._h, int(max_batch), ctypes.byref(self._h)))
+
+    @staticmethod
+    def param_count():
+        return int(lib().gc_mlp_param_count())
+
+    def set_params(self, theta, stream=None):
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        _check("gc_mlp_set_params", lib().gc_mlp_set_params(
+            self._h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), t.size, _stream_handle(stream)))
+
+    def get_params(self, stream=None):
+        t = np.zeros(self.param_count(), np.float32)
+        _check("gc_mlp_get_params", lib().gc_mlp_get_params(
+            self._h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), t.size, _stream_handle(stream)))
+        return t
+
+    def forward(self, d_feat, n, d_logits=None, d_class=None, stream=None):
+        _check("gc_mlp_forward", lib().gc_mlp_forward(self._h, _ptr(d_feat), int(n), _opt(d_logits),
+                                                      _opt(d_class), _stream_handle(stream)))
+
+    def grad(self, d_feat, d_label, batch, d_cost=None, d_index=None, lam=0.0, d_grad=None, d_loss=None,
+             stream=None):
+        _check("gc_mlp_grad", lib().gc_mlp_grad(self._h, _ptr(d_feat), _ptr(d_label), _opt(d_cost), _opt(d_index),
+                                                int(batch), float(lam), _opt(d_grad), _opt(d_loss),
+                                                _stream_handle(stream)))
+
+    def train(self, d_feat, d_label, nindex, opts: AdamOpts, d_cost=None, d_index=None, d_loss=None, stream=None):
+        _check("gc_mlp_train", lib().gc_mlp_train(self._h, _ptr(d_feat), _ptr(d_label), _opt(d_cost),
+                                                  _opt(d_index), int(nindex), ctypes.byref(opts), _opt(d_loss),
+                                                  _stream_handle(stream)))
+
+    def close(self):
+        if self._h:
+            lib().gc_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 BLOCK_INTS = 128
