@@ -237,18 +237,21 @@ gc_status gc_sync_status(gc_ctx *ctx, void *hip_stream, uint32_t *detail);
 
 /* Device memory d_in holds nblocks * GC_BLOCK_INTS integers.  Writes the 40
  * features of every block to d_feat (nblocks x 40 floats, row-major): the
- * largest bit width / 32; the count of integers of bit width 0..32 / 128;
- * the count of integers wider than (largest width - t), t = 1..6, / 128
- * (all integers when that is negative).  Asynchronous on hip_stream.       */
+ * largest bit width / 32; the count of tuples (4 consecutive integers, the
+ * width of the widest) of width 0..32 / 32; the count of integers wider
+ * than (largest width - t), t = 1..6, / 128 (all integers when that is
+ * negative).  Asynchronous on hip_stream.                                  */
 gc_status gc_block_features(gc_ctx *ctx, const uint32_t *d_in, size_t nblocks, float *d_feat,
                             void *hip_stream);
 
 /* The coded size in words (block word included) of every block in every
- * class to d_sizes (nblocks x GC_BLOCK_CLASSES, row-major) and the least
+ * class to d_sizes (nblocks x GC_BLOCK_CLASSES, row-major), the least
  * one's class (the smaller class on ties: the exhaustive choice) to
- * d_best.  Either output may be NULL.  Asynchronous on hip_stream.         */
+ * d_best, and every class's relative excess (size - least) / least, in
+ * fp32, to d_cost (nblocks x GC_BLOCK_CLASSES).  Any output may be NULL.
+ * Asynchronous on hip_stream.                                               */
 gc_status gc_block_sizes(gc_ctx *ctx, const uint32_t *d_in, size_t nblocks, uint32_t *d_sizes,
-                         uint8_t *d_best, void *hip_stream);
+                         uint8_t *d_best, float *d_cost, void *hip_stream);
 
 /* Words a container of n integers can take at most. */
 size_t gc_blockmix_bound_words(size_t n);

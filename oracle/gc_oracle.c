@@ -1186,16 +1186,21 @@ int or_block_decode(uint32_t blockword, const uint32_t *payload, size_t words, u
  * maxW - t < 0). */
 void or_block_features(const uint32_t *x, double *f)
 {
+    /* the width of a tuple is the width of its widest integer (the width
+     * every codec of the 4-way layout sizes a tuple by) */
     int hist[33] = {0}, maxw = 0;
-    for (int i = 0; i < OR_BLOCK_INTS; i++) {
-        int w = or_bw(x[i]);
+    for (int t = 0; t < OR_BLOCK_INTS / 4; t++) {
+        int w = 0;
+        for (int c = 0; c < 4; c++)
+            if (or_bw(x[4 * t + c]) > w)
+                w = or_bw(x[4 * t + c]);
         hist[w]++;
         if (w > maxw)
             maxw = w;
     }
     f[0] = maxw / 32.0;
     for (int w = 0; w <= 32; w++)
-        f[1 + w] = hist[w] / (double)OR_BLOCK_INTS;
+        f[1 + w] = hist[w] / (double)(OR_BLOCK_INTS / 4);
     for (int t = 1; t <= 6; t++) {
         int b = maxw - t, cnt = 0;
         for (int i = 0; i < OR_BLOCK_INTS; i++)

@@ -322,34 +322,45 @@ __device__ __forceinline__ void load_block(const uint32_t *in, size_t blk, uint3
 }
 
 // ---- features ---------------------------------------------------------------
-// The maximum bit width / 32, the histogram of the 128 widths (0..32) / 128,
-// and the integers wider than maxw - t for t = 1..6 (all of them when
-// maxw - t < 0) / 128.
+// The largest bit width / 32; the histogram of the 32 tuple widths (0..32)
+// / 32, a tuple's width being that of its widest integer; and the integers
+// wider than maxw - t for t = 1..6 (all of them when maxw - t < 0) / 128.
 __global__ __launch_bounds__(kThreads) void gc_block_features_kernel(const uint32_t *in, size_t nblocks,
                                                                      float *feat) {
     const uint32_t lane = threadIdx.x & 63u;
     const size_t blk = (size_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
     if (blk >= nblocks) return;
-    const gu32 *src = (const gu32 *)(in + blk * (size_t)kBlockInts);
-    const uint32_t w0 = bitw(src[lane]), w1 = bitw(src[lane + 64u]);
-    const uint32_t maxw = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(max(w0, w1)), 63);
-    uint32_t hist = 0, wider = 0;   // lane j: bin j-1 (j = 1..33); lane 33+t: wider than maxw - t
-    const int tt = lane >= 34u && lane < 40u ? (int)lane - 33 : 0;
-    for (uint32_t w = 0; w <= 32u; w++) {
-        const uint32_t c = (uint32_t)(__builtin_popcountll(__ballot(w0 == w)) + __builtin_popcountll(__ballot(w1 == w)));
-        if (lane == w + 1u) hist = c;
-        if (tt && (int)w > (int)maxw - tt) wider += c;
+    const gu32x4 *src = (const gu32x4 *)(in + blk * (size_t)kBlockInts);
+    const bool valid = lane < (uint32_t)kTuples;
+    u32x4 q = {0u, 0u, 0u, 0u};
+    if (valid) q = src[lane];
+    const uint32_t w[4] = {bitw(q.x), bitw(q.y), bitw(q.z), bitw(q.w)};
+    const uint32_t tw = bitw(q.x | q.y | q.z | q.w);
+    const uint32_t maxw = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(tw), 63);
+    uint32_t hist = 0;   // lane j = 1..33: tuples of width j - 1
+    for (uint32_t b = 0; b <= 32u; b++) {
+        const uint32_t c = (uint32_t)__builtin_popcountll(__ballot(valid && tw == b));
+        if (lane == b + 1u) hist = c;
+    }
+    uint32_t wider = 0;  // lane 33 + t: integers wider than maxw - t
+    for (int t = 1; t <= 6; t++) {
+        const int thr = (int)maxw - t;
+        uint32_t c = 0;
+        if (valid)
+            for (int j = 0; j < 4; j++) c += (int)w[j] > thr ? 1u : 0u;
+        c = wave_sum(c);
+        if (lane == 33u + (uint32_t)t) wider = c;
     }
     float f = 0.0f;
     if (lane == 0u) f = (float)maxw / 32.0f;
-    else if (lane <= 33u) f = (float)hist / 128.0f;
-    else if (tt) f = (float)wider / 128.0f;
+    else if (lane <= 33u) f = (float)hist / 32.0f;
+    else f = (float)wider / 128.0f;
     if (lane < (uint32_t)kFeatures) feat[blk * (size_t)kFeatures + lane] = f;
 }
 
 // ---- sizes of every class, exhaustive choice -----------------------------------
 __global__ __launch_bounds__(kThreads) void gc_block_sizes_kernel(const uint32_t *in, size_t nblocks,
-                                                                  uint32_t *sizes, uint8_t *best) {
+                                                                  uint32_t *sizes, uint8_t *best, float *cost) {
     __shared__ BlockSmem smem[kWaves];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -370,6 +381,8 @@ __global__ __launch_bounds__(kThreads) void gc_block_sizes_kernel(const uint32_t
     }
     if (sizes && lane < (uint32_t)kClasses) sizes[blk * (size_t)kClasses + lane] = mine;
     if (best && lane == 0u) best[blk] = (uint8_t)bk;
+    // relative size excess over the least size: the selector's training cost
+    if (cost && lane < (uint32_t)kClasses) cost[blk * (size_t)kClasses + lane] = (float)(mine - bsize) / (float)bsize;
 }
 
 // ---- container encode ----------------------------------------------------------
@@ -493,9 +506,11 @@ int launch_block_features(const uint32_t *in, size_t nblocks, float *feat, hipSt
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_block_sizes(const uint32_t *in, size_t nblocks, uint32_t *sizes, uint8_t *best, hipStream_t s) {
+int launch_block_sizes(const uint32_t *in, size_t nblocks, uint32_t *sizes, uint8_t *best, float *cost,
+                       hipStream_t s) {
     if (!nblocks) return 0;
-    hipLaunchKernelGGL(gc_block_sizes_kernel, grid_for(nblocks), dim3(kThreads), 0, s, in, nblocks, sizes, best);
+    hipLaunchKernelGGL(gc_block_sizes_kernel, grid_for(nblocks), dim3(kThreads), 0, s, in, nblocks, sizes, best,
+                       cost);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -18,7 +18,8 @@ constexpr int kMaxExcWords = 132;
 constexpr int kMaxPayloadWords = kMaxCtrlWords + kMaxDataWords + kMaxExcWords;
 
 int launch_block_features(const uint32_t *in, size_t nblocks, float *feat, hipStream_t s);
-int launch_block_sizes(const uint32_t *in, size_t nblocks, uint32_t *sizes, uint8_t *best, hipStream_t s);
+int launch_block_sizes(const uint32_t *in, size_t nblocks, uint32_t *sizes, uint8_t *best, float *cost,
+                       hipStream_t s);
 size_t scan_chunks(size_t n);
 int launch_blockmix_plan(const uint32_t *in, size_t nblocks, const uint8_t *cls, uint32_t *words, uint32_t *offs,
                          uint32_t *csum, uint32_t *result, hipStream_t s);

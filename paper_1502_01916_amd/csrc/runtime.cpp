@@ -925,12 +925,13 @@ gc_status gc_block_features(gc_ctx *ctx, const uint32_t *d_in, size_t nblocks, f
 }
 
 gc_status gc_block_sizes(gc_ctx *ctx, const uint32_t *d_in, size_t nblocks, uint32_t *d_sizes, uint8_t *d_best,
+                         float *d_cost,
                          void *hip_stream) {
     if (!ctx || (nblocks && !d_in)) return GC_EINVAL;
     if (nblocks > 0xFFFFFFFFull) return GC_EINVAL;
-    if (!d_sizes && !d_best) return GC_OK;
+    if (!d_sizes && !d_best && !d_cost) return GC_OK;
     (void)hipSetDevice(ctx->device);
-    return gcblk::launch_block_sizes(d_in, nblocks, d_sizes, d_best, (hipStream_t)hip_stream) ? GC_EDEVICE : GC_OK;
+    return gcblk::launch_block_sizes(d_in, nblocks, d_sizes, d_best, d_cost, (hipStream_t)hip_stream) ? GC_EDEVICE : GC_OK;
 }
 
 size_t gc_blockmix_bound_words(size_t n) {
@@ -1130,7 +1131,7 @@ gc_status gc_encode_blocks(gc_ctx *ctx, const uint32_t *d_in, size_t n, int mode
         if (!cls) cls = ctx->blk.cls;
         int err = 0;
         if (mode == GC_SELECT_EXHAUSTIVE) {
-            err = gcblk::launch_block_sizes(d_in, nb, nullptr, cls, s);
+            err = gcblk::launch_block_sizes(d_in, nb, nullptr, cls, nullptr, s);
         } else if (mode == GC_SELECT_LEARNED) {
             std::lock_guard<std::mutex> lm(model->mu);
             err = gcblk::launch_block_features(d_in, nb, ctx->blk.feat, s);

@@ -113,7 +113,7 @@ def lib():
         L.gc_plan_timings.restype = ctypes.c_int
         L.gc_sync_status.argtypes = [vp, vp, u32p]
         L.gc_block_features.argtypes = [vp, vp, sz, vp, vp]
-        L.gc_block_sizes.argtypes = [vp, vp, sz, vp, vp, vp]
+        L.gc_block_sizes.argtypes = [vp, vp, sz, vp, vp, vp, vp]
         L.gc_blockmix_bound_words.argtypes = [sz]
         L.gc_blockmix_bound_words.restype = sz
         L.gc_blockmix_encode.argtypes = [vp, vp, sz, vp, vp, sz, ctypes.POINTER(sz), vp]
@@ -239,11 +239,13 @@ class Context:
         _check("gc_block_features", lib().gc_block_features(self._h, _ptr(d_in), int(nblocks), _ptr(d_feat),
                                                               _stream_handle(stream)))
 
-    def block_sizes(self, d_in, nblocks, d_sizes=None, d_best=None, stream=None):
-        """gc_block_sizes: d_sizes int32 [nblocks, 16], d_best uint8 [nblocks]; either may be None."""
+    def block_sizes(self, d_in, nblocks, d_sizes=None, d_best=None, d_cost=None, stream=None):
+        """gc_block_sizes: d_sizes int32 [nblocks, 16], d_best uint8 [nblocks], d_cost float32
+        [nblocks, 16]; any may be None."""
         _check("gc_block_sizes", lib().gc_block_sizes(
             self._h, _ptr(d_in), int(nblocks), None if d_sizes is None else _ptr(d_sizes),
-            None if d_best is None else _ptr(d_best), _stream_handle(stream)))
+            None if d_best is None else _ptr(d_best), None if d_cost is None else _ptr(d_cost),
+            _stream_handle(stream)))
 
     def blockmix_encode(self, d_in, n, d_class, d_out, stream=None):
         """gc_blockmix_encode: returns the container's length in words."""

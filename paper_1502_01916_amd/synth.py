@@ -155,6 +155,8 @@ def block_corpus(seed, total_ints, nlists_hint=10_000):
     rng = np.random.default_rng(seed)
     per = total_ints // 2
     L = zipf_lengths(nlists_hint, per, 128, MAX_LIST, rng)
+    if L.sum() < per:                 # the Zipf fit lands a few values short
+        L[np.argmin(L)] += per - L.sum()
     g = mixed_gaps(rng, L)
     tf = rng.geometric(0.4, int(L.sum())).astype(np.uint32)
     lengths = np.concatenate([L, L])

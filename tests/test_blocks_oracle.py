@@ -98,9 +98,10 @@ def test_block_features_brute_force():
         f = O.block_features(x)
         w = bit_width(x)
         W = int(w.max())
+        tw = w.reshape(32, 4).max(axis=1)     # tuple widths
         assert f[0] == W / 32
         for b in range(33):
-            assert f[1 + b] == np.count_nonzero(w == b) / 128
+            assert f[1 + b] == np.count_nonzero(tw == b) / 32
         for t in range(1, 7):
             assert f[33 + t] == np.count_nonzero(w > W - t) / 128
         assert f[1:34].sum() == pytest.approx(1.0)

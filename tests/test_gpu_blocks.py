@@ -60,15 +60,20 @@ def test_block_features_sizes(torch_cuda, ctx, nb):
     d_feat = torch.full((nb, 40), -1.0, dtype=torch.float32, device="cuda")
     d_sizes = torch.full((nb, 16), -1, dtype=torch.int32, device="cuda")
     d_best = torch.full((nb,), 255, dtype=torch.uint8, device="cuda")
+    d_cost = torch.full((nb, 16), -1.0, dtype=torch.float32, device="cuda")
     ctx.block_features(d_in, nb, d_feat)
-    ctx.block_sizes(d_in, nb, d_sizes, d_best)
+    ctx.block_sizes(d_in, nb, d_sizes, d_best, d_cost)
     torch.cuda.synchronize()
     g_feat = d_feat.cpu().numpy().astype(np.float64)
     # every feature is a multiple of 1/128 or 1/32: exact in fp32
     assert np.array_equal(g_feat, feat)
     assert np.array_equal(d_sizes.cpu().numpy().astype(np.int64), sizes)
     assert np.array_equal(d_best.cpu().numpy().astype(np.int64), best)
-    # best alone (sizes to scratch)
+    # relative excess: an exact integer difference over the least size, one fp32 rounding
+    smin = sizes.min(axis=1, keepdims=True)
+    want = (sizes - smin).astype(np.float32) / smin.astype(np.float32)
+    assert np.array_equal(d_cost.cpu().numpy(), want)
+    # best alone
     d_best2 = torch.full((nb,), 255, dtype=torch.uint8, device="cuda")
     ctx.block_sizes(d_in, nb, None, d_best2)
     torch.cuda.synchronize()

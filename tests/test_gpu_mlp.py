@@ -169,10 +169,9 @@ def test_training_lowers_loss(torch_cuda, ctx):
     d_f = torch.zeros((nb, 40), dtype=torch.float32, device="cuda")
     d_s = torch.zeros((nb, 16), dtype=torch.int32, device="cuda")
     d_b = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+    d_c = torch.zeros((nb, 16), dtype=torch.float32, device="cuda")
     ctx.block_features(d_in, nb, d_f)
-    ctx.block_sizes(d_in, nb, d_s, d_b)
-    s = d_s.float()
-    d_c = (s / s.min(dim=1, keepdim=True).values - 1.0).contiguous()
+    ctx.block_sizes(d_in, nb, d_s, d_b, d_c)
     net = gc.Mlp(ctx, 512)
     net.set_params(M.init_params(3))
     steps = nb // 512
