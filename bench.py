@@ -7,8 +7,10 @@ and their TF lists, each coded with Group-Simple, Group-Scheme 1-CU,
 Group-Scheme 8-IU, Group-AFOR and Group-PFD (32-tuple blocks, zeta = 1/10) in
 the paper's 4-way layout: 100,000 streams, about 6.7e8 integers.  One step
 decodes every stream (docID lists prefix-summed): the locate kernels, then per
-codec class the tile-sum pass, the carry scan and the decode pass, timed with
-HIP events between the kernels.
+codec class the tile-sum pass, the carry scan and the decode pass, all captured
+in one hipGraph; `value` times the graph replays.  A second plan with the same
+tiles launches the kernels directly with HIP events between the phases; it
+gives the per-phase times and the dominant kernel's average duration.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -117,28 +119,63 @@ def read_traffic(units, kernel):
         return None
 
 
+def cpu_threads():
+    """Host threads for the CPU baseline: the cores this process may use,
+    at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def cpu_baseline(parts, seconds):
     """The plain C oracle decoding (and prefix-summing) a random sample of the
-    same streams on one host core, for about `seconds` seconds."""
+    same streams: first on one host thread, then on every host thread, lists
+    handed out one at a time (the oracle call releases the GIL), each for
+    about `seconds` seconds."""
+    import threading
     import oracle as O
     rng = np.random.default_rng(123)
     order = [(pi, li) for pi in range(len(parts)) for li in range(parts[pi]["lengths"].size)]
     rng.shuffle(order)
-    done_ints = done_lists = 0
-    t0 = time.perf_counter()
-    for pi, li in order:
-        p = parts[pi]
-        s = p["streams"][int(p["offs"][li]):int(p["offs"][li + 1])]
-        out = O.decode(s)
-        done_ints += out.size
-        done_lists += 1
-        if time.perf_counter() - t0 > seconds:
-            break
-    dt = time.perf_counter() - t0
-    return dict(value=done_ints / dt / 1e9, unit="Gints/s", cores=1, kind="oracle",
-                sample="%d lists (%d integers) drawn at random from the same 100,000 streams, each "
-                       "decoded and prefix-summed once by the single-threaded C oracle in %.1f s"
-                       % (done_lists, done_ints, dt))
+
+    def run(nthreads):
+        lock = threading.Lock()
+        state = dict(next=0, ints=0, lists=0)
+        t0 = time.perf_counter()
+
+        def worker():
+            while True:
+                with lock:
+                    k = state["next"]
+                    if k >= len(order) or time.perf_counter() - t0 > seconds:
+                        return
+                    state["next"] = k + 1
+                pi, li = order[k]
+                p = parts[pi]
+                out = O.decode(p["streams"][int(p["offs"][li]):int(p["offs"][li + 1])])
+                with lock:
+                    state["ints"] += out.size
+                    state["lists"] += 1
+
+        threads = [threading.Thread(target=worker) for _ in range(nthreads)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        dt = time.perf_counter() - t0
+        return state["ints"] / dt / 1e9, state["lists"], state["ints"], dt
+
+    one = run(1)
+    nt = cpu_threads()
+    many = run(nt)
+    return dict(value=round(many[0], 4), unit="Gints/s", cores=nt, kind="oracle",
+                per_core_value=round(one[0], 4),
+                sample="lists drawn at random from the same 100,000 streams, each decoded and "
+                       "prefix-summed by the plain C oracle: %d lists (%d integers) in %.1f s on %d host "
+                       "threads; single-threaded: %d lists (%d integers) in %.1f s"
+                       % (many[1], many[2], many[3], nt, one[1], one[2], one[3]))
 
 
 def timed(plan, d_s, d_o, steps, warmup, torch):
@@ -157,7 +194,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip per-list and per-codec runs")
     ap.add_argument("--tile", type=int, default=0, help="force the wave-tile size (0 = autotune)")
@@ -188,14 +225,20 @@ def main():
     d_s = gc.to_device(streams)
     d_o = torch.empty(out_len, dtype=torch.int32, device="cuda")
     t = time.time()
+    # the timed plan: autotuned tiles, the whole run captured in one hipGraph
     plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=args.tile, locate_stream=args.locate_stream,
                    pfd_tile_ints=args.pfd_tile or (4096 if args.tile else 0),
-                   autotune=args.tile == 0, timing_slots=args.steps + args.warmup)
+                   autotune=args.tile == 0, use_graph=True)
     cfg = plan.config()
     log("plan: %s (%.1fs)" % (cfg, time.time() - t))
+    # the same tiles with HIP events between the phases (direct launches), for
+    # the per-phase times and the dominant kernel's duration
+    tplan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=cfg["tile_ints"], pfd_tile_ints=cfg["pfd_tile_ints"],
+                    locate_stream=args.locate_stream, timing_slots=args.steps + args.warmup)
 
     elapsed = timed(plan, d_s, d_o, args.steps, args.warmup, torch)
-    tm = plan.timings(args.steps)
+    t_events = timed(tplan, d_s, d_o, args.steps, args.warmup, torch)
+    tm = tplan.timings(args.steps)
     rc, detail = ctx.sync_status()
     if rc != gc.OK:
         raise SystemExit("device reported %d (detail %d)" % (rc, detail))
@@ -211,8 +254,9 @@ def main():
     cls_bytes = class_bytes(gc, parts, cls)
     dec_avg = float(dec[cls])
     achieved = cls_bytes / (dec_avg * 1e-3) / 1e9
-    log("step %.3f ms  %.1f Gints/s  (GPU %.3f ms; per class locate %s, sum+carry %s, decode %s)  verified=%s"
-        % (ms_per_step, value, tm["total"].mean(), np.round(tm["locate"].mean(axis=0), 3),
+    log("step %.3f ms  %.1f Gints/s  (with events between phases %.3f ms, GPU %.3f ms; per class locate %s, "
+        "sum+carry %s, decode %s)  verified=%s"
+        % (ms_per_step, value, 1e3 * t_events / args.steps, tm["total"].mean(), np.round(tm["locate"].mean(axis=0), 3),
            np.round(tm["sum"].mean(axis=0), 3), np.round(dec, 3), verified))
     log("dominant kernel: %s decode pass %.3f ms, %.0f GB/s" % (CLASS_NAMES[cls], dec_avg, achieved))
     if not verified:
@@ -263,7 +307,8 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(parts, args.cpu_seconds)
-        log("cpu oracle: %.4f Gints/s (%s)" % (cpu["value"], cpu["sample"]))
+        log("cpu oracle: %.4f Gints/s on %d threads, %.4f on one (%s)"
+            % (cpu["value"], cpu["cores"], cpu["per_core_value"], cpu["sample"]))
 
     line = {
         "metric": METRIC,
@@ -307,6 +352,7 @@ def main():
             "avg_kernel_ms": round(dec_avg, 4),
         },
         "phases_ms": {
+            "note": "from a second plan with the same tiles and HIP events between the phases",
             "gpu_total": round(float(tm["total"].mean()), 4),
             "locate": {CLASS_NAMES[c]: round(float(tm["locate"][:, c].mean()), 4)
                        for c in range(5) if dec[c] > 0},
@@ -324,6 +370,7 @@ def main():
     dst.copy_(src)
     torch.cuda.synchronize()
     plan.close()
+    tplan.close()
     ctx.close()
     print(json.dumps(line), flush=True)
 
