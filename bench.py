@@ -48,7 +48,7 @@ def variants(gc):
 
 CLASS_NAMES = ["group-simple", "group-scheme-unary", "group-scheme-binary", "group-afor", "group-pfd"]
 KERNEL_NAMES = ["gc_wave_kernel<%d, 0, false>", "gc_wave_kernel<%d, 1, false>", "gc_wave_kernel<%d, 2, false>",
-                "gc_wave_kernel<%d, 3, false>", "gc_pfd_kernel<%d, false>"]
+                "gc_wave_kernel<%d, 3, false>", "gc_wave_kernel<%d, 4, false>"]
 
 
 def codec_class(gc, codec, kw):

@@ -523,277 +523,7 @@ __device__ __forceinline__ ListDesc tile_list(const DecodeArgs &a, const TilePre
 }
 
 // ===========================================================================
-// Group-PFD: one workgroup per tile.
-
-template <int TILE>
-struct PfdSmem {
-    static constexpr int R = TILE / (4 * kThreads);          // output rounds
-    static constexpr int NEXC = TILE / 4;
-    uint32_t gaps[TILE];
-    uint32_t exc[NEXC];
-    uint32_t blk_off[64], blk_exc[64], blk_desc[64];
-    uint32_t wtot[R * kWaves];
-    uint32_t wpre[R * kWaves];
-    uint32_t tmp[kWaves];
-    uint32_t bad, dbase, excw, exc_staged;
-};
-
-// ---- Group-PFD: per-block descriptors, exceptions staged in LDS ------------
-template <int TILE>
-__device__ void prologue_pfd(const TileCtx &c, PfdSmem<TILE> &sm, uint64_t stream_words) {
-    using SM = PfdSmem<TILE>;
-    const int tid = threadIdx.x;
-    const uint32_t k = c.k;
-    const uint32_t nb = (c.ntup + 31u) >> 5;
-    const uint32_t beta0 = c.t0 >> 5;
-    const int bitmap = c.h.pfd_pos;
-    if (tid < 64) {
-        uint32_t desc = 0, b = 0, ew = 0;
-        if ((uint32_t)tid < nb) {
-            if (beta0 + (uint32_t)tid >= c.C) {
-                sm.bad = kErrRange;
-            } else {
-                desc = c.ctrl[beta0 + (uint32_t)tid];
-                b = desc & 63u;
-                const uint32_t nexc = desc >> 20, wcode = (desc >> 6) & 3u;
-                const uint32_t first = (desc >> 8) & 0xFFFu;
-                if (b > 32u || nexc > 32u * k || (nexc && !wcode) || (bitmap && first > 32u)) {
-                    sm.bad = kErrPfdDesc;
-                    b = 0;
-                    desc = 0;
-                }
-                ew = pfd_exc_words(desc, (int)k, bitmap);
-            }
-        }
-        const uint32_t ib = wave_incl_scan(b), ie = wave_incl_scan(ew);
-        if ((uint32_t)tid < nb) {
-            sm.blk_off[tid] = ib - b;
-            sm.blk_exc[tid] = ie - ew;
-            sm.blk_desc[tid] = desc;
-        }
-        if (tid == 63) {
-            sm.dbase = (uint32_t)(c.st.data >> 5);
-            sm.excw = ie;
-        }
-    }
-    __syncthreads();
-    // exception words of the tile's blocks
-    const uint64_t ex0 = 4ull + c.C + c.D + c.st.exc;
-    const uint32_t excw = sm.excw;
-    const bool fits = excw <= (uint32_t)SM::NEXC;
-    if (!sm.bad) {
-        if (ex0 + excw > stream_words) {
-            if (tid == 0) sm.bad = kErrRange;
-        } else if (fits) {
-            for (uint32_t q = (uint32_t)tid; q < excw; q += kThreads) sm.exc[q] = c.S[ex0 + q];
-        }
-    }
-    if (tid == 0) sm.exc_staged = fits ? 1u : 0u;
-}
-
-template <int TILE>
-__device__ void patch_pfd(const TileCtx &c, PfdSmem<TILE> &sm) {
-    const int tid = threadIdx.x;
-    const uint32_t k = c.k, lk = c.lk;
-    const uint32_t nb = (c.ntup + 31u) >> 5;
-    const uint32_t BI = 32u * k;
-    const uint64_t ex0 = 4ull + c.C + c.D + c.st.exc;
-    const bool staged = sm.exc_staged != 0u;
-    auto exw = [&](uint32_t idx) -> uint32_t { return staged ? sm.exc[idx] : c.S[ex0 + idx]; };
-    if (c.h.pfd_pos == GC_PFD_LINKED) {
-        for (uint32_t bi = (uint32_t)tid; bi < nb; bi += kThreads) {
-            const uint32_t desc = sm.blk_desc[bi];
-            const uint32_t nexc = desc >> 20;
-            if (!nexc) continue;
-            const uint32_t w = 4u << ((desc >> 6) & 3u), wm = mask_of(w);
-            const uint32_t xb = sm.blk_exc[bi];
-            uint32_t p = (desc >> 8) & 0xFFFu;
-            uint32_t *g = &sm.gaps[bi * BI];
-            for (uint32_t e = 0; e < nexc; e++) {
-                if (p >= BI) {
-                    sm.bad = kErrPfdChain;
-                    break;
-                }
-                const uint32_t slot = g[p];
-                const uint32_t bit = e * w;
-                g[p] = (exw(xb + (bit >> 5)) >> (bit & 31u)) & wm;
-                p = slot < BI ? p + slot + 1u : BI;
-            }
-        }
-    } else {
-        const int wave = tid >> 6;
-        const uint32_t lane = (uint32_t)(tid & 63);
-        for (uint32_t bi = (uint32_t)wave; bi < nb; bi += kWaves) {
-            const uint32_t desc = sm.blk_desc[bi];
-            const uint32_t nexc = desc >> 20;
-            if (!nexc) continue;
-            const uint32_t w = 4u << ((desc >> 6) & 3u), wm = mask_of(w);
-            const uint32_t nt = (desc >> 8) & 0xFFFu;
-            const uint32_t xb = sm.blk_exc[bi];
-            const uint32_t tm = exw(xb);
-            if ((uint32_t)__builtin_popcount(tm) != nt) {
-                if (lane == 0) sm.bad = kErrBitmap;
-                continue;
-            }
-            const uint32_t vbase = xb + 1u + ((nt * k + 31u) >> 5);
-            uint32_t run = 0;
-            for (uint32_t p0 = 0; p0 < BI; p0 += 64u) {
-                const uint32_t p = p0 + lane;
-                const uint32_t t = p >> lk, cc = p & (k - 1u);
-                bool isx = false;
-                if ((tm >> t) & 1u) {
-                    const uint32_t rank = (uint32_t)__builtin_popcount(tm & ((1u << t) - 1u));
-                    const uint32_t bit = rank * k + cc;
-                    isx = (exw(xb + 1u + (bit >> 5)) >> (bit & 31u)) & 1u;
-                }
-                const uint64_t bal = __ballot(isx);
-                const uint32_t before =
-                    __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                const uint32_t e = run + before;
-                if (isx && e < nexc) {
-                    const uint32_t bitv = e * w;
-                    sm.gaps[bi * BI + p] = (exw(vbase + (bitv >> 5)) >> (bitv & 31u)) & wm;
-                }
-                run += (uint32_t)__builtin_popcountll(bal);
-            }
-            if (lane == 0 && run != nexc) sm.bad = kErrBitmap;
-        }
-    }
-}
-
-
-// Decodes tile m (global tile gi) of a Group-PFD list.  SUM: store only the
-// sum of the tile's gaps in carry[gi]; otherwise write the tile's output,
-// prefix-summed from carry[gi] for a delta list.
-template <int TILE, bool SUM>
-__device__ void pfd_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, uint32_t gi, const TilePre &pre,
-                         uint32_t loc_tag, PfdSmem<TILE> &sm) {
-    constexpr int R = PfdSmem<TILE>::R;
-    const int tid = threadIdx.x;
-    HeaderFields hl;
-    const bool delta = header_fields(L.w0, hl) && hl.delta;
-    const uint32_t carry0 = (!SUM && delta && L.ntiles > 1u) ? pre.carry : 0u;
-    TileCtx c;
-    const bool ok = tile_ctx(L, m, pre.s0, pre.s1, (uint32_t)TILE, loc_tag, c);
-    if (tid == 0) sm.bad = ok ? 0u : kErrLocate;
-    __syncthreads();
-    if (!sm.bad) prologue_pfd<TILE>(c, sm, L.stream_words);
-    __syncthreads();
-
-    // ---- unpack: four consecutive integers per thread and round ------------
-    const bool bad = sm.bad != 0u;
-    const uint32_t Dk = c.D >> c.lk;
-    const uint32_t dbase = sm.dbase;
-    const uint32_t nrow = Dk > dbase ? Dk - dbase : 0u;   // data rows from dbase on
-    const uint32_t kq = c.k >> 2;                          // 16-byte chunks per row
-    const u32x4 *rows = reinterpret_cast<const u32x4 *>(c.data) + (size_t)dbase * kq;
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const uint32_t q = (uint32_t)(r * kThreads + tid);
-        u32x4 v = {0u, 0u, 0u, 0u};
-        if (!bad && 4u * q < c.nint) {
-            const uint32_t t = q >> (c.lk - 2u);
-            const uint32_t cq = q & (kq - 1u);
-            const uint32_t bi = t >> 5, desc = sm.blk_desc[bi];
-            const uint32_t bw = desc & 63u;
-            const uint32_t O = 32u * sm.blk_off[bi] + (t & 31u) * bw;
-            if (bw && nrow) {
-                const uint32_t wi = min(O >> 5, nrow - 1u), sh = O & 31u;
-                const uint32_t M = mask_of(bw);
-                const u32x4 lo = rows[(size_t)wi * kq + cq];
-                u32x4 hi = {0u, 0u, 0u, 0u};
-                if (sh + bw > 32u) hi = rows[(size_t)min(wi + 1u, nrow - 1u) * kq + cq];
-                v.x = funnel(hi.x, lo.x, sh) & M;
-                v.y = funnel(hi.y, lo.y, sh) & M;
-                v.z = funnel(hi.z, lo.z, sh) & M;
-                v.w = funnel(hi.w, lo.w, sh) & M;
-            }
-        }
-        *reinterpret_cast<u32x4 *>(&sm.gaps[4u * q]) = v;
-    }
-    __syncthreads();
-    if (!bad) patch_pfd<TILE>(c, sm);
-    __syncthreads();
-    uint32_t v[R][4];
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const uint32_t q = (uint32_t)(r * kThreads + tid);
-        const u32x4 g = *reinterpret_cast<const u32x4 *>(&sm.gaps[4u * q]);
-        v[r][0] = g.x;
-        v[r][1] = g.y;
-        v[r][2] = g.z;
-        v[r][3] = g.w;
-    }
-    if (tid == 0 && sm.bad) latch(a.status, sm.bad);
-
-    const int wave = tid >> 6, lane = tid & 63;
-    if constexpr (SUM) {
-        uint32_t s = 0;
-#pragma unroll
-        for (int r = 0; r < R; r++) s += v[r][0] + v[r][1] + v[r][2] + v[r][3];
-        uint32_t total;
-        (void)block_excl_scan(s, sm.tmp, total);
-        if (tid == 0) a.carry[gi] = total;
-        return;
-    }
-
-    // ---- prefix sum (delta lists) -------------------------------------------
-    uint32_t add[R];
-#pragma unroll
-    for (int r = 0; r < R; r++) add[r] = 0u;
-    if (c.h.delta) {
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-            v[r][1] += v[r][0];
-            v[r][2] += v[r][1];
-            v[r][3] += v[r][2];
-            const uint32_t inc = wave_incl_scan(v[r][3]);
-            add[r] = inc - v[r][3];
-            if (lane == 63) sm.wtot[r * kWaves + wave] = inc;
-        }
-        __syncthreads();
-        if (tid < 64) {
-            const uint32_t x = (uint32_t)tid < (uint32_t)(R * kWaves) ? sm.wtot[tid] : 0u;
-            const uint32_t inc = wave_incl_scan(x);
-            if ((uint32_t)tid < (uint32_t)(R * kWaves)) sm.wpre[tid] = inc - x;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < R; r++) add[r] += carry0 + sm.wpre[r * kWaves + wave];
-    }
-
-    // ---- store ---------------------------------------------------------------
-    uint32_t *out = L.out + c.i0;
-    const bool vec = (reinterpret_cast<uintptr_t>(out) & 15u) == 0u;
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const uint32_t q = (uint32_t)(r * kThreads + tid);
-        const uint32_t ii = 4u * q;
-        if (ii >= c.nint) continue;
-        const u32x4 o = {v[r][0] + add[r], v[r][1] + add[r], v[r][2] + add[r], v[r][3] + add[r]};
-        if (vec && ii + 4u <= c.nint) {
-            __builtin_nontemporal_store(o, reinterpret_cast<u32x4 *>(out + ii));
-        } else {
-            out[ii] = o.x;
-            if (ii + 1u < c.nint) out[ii + 1u] = o.y;
-            if (ii + 2u < c.nint) out[ii + 2u] = o.z;
-            if (ii + 3u < c.nint) out[ii + 3u] = o.w;
-        }
-    }
-}
-
-template <int TILE, bool SUM>
-__global__ __launch_bounds__(kThreads) void gc_pfd_kernel(DecodeArgs a) {
-    __shared__ PfdSmem<TILE> sm;
-    const uint32_t gi = a.lo + blockIdx.x;
-    const uint32_t loc_tag = *(const gu32 *)&a.loc_state->epoch;   // written by an earlier kernel
-    const TilePre pre = tile_pre(a, gi);
-    const ListDesc L = tile_list(a, pre);
-    pfd_tile<TILE, SUM>(a, L, gi - L.tile_base, gi, pre, loc_tag, sm);
-}
-
-// ===========================================================================
-// Wave-tile decode kernels (Group-Simple, Group-Scheme, Group-AFOR).
+// Wave-tile decode kernels (Group-Simple, Group-Scheme, Group-AFOR, Group-PFD).
 //
 // Every wave64 decodes its own tile of TW integers with no workgroup
 // barrier: a workgroup is only a container of four independent waves, each
@@ -813,6 +543,18 @@ struct WaveSmem {
         uint32_t ctrl[4 * NB];
     };
     uint32_t rec[TTM + 4];   // + room for one more entry while the records are built
+    // Group-PFD only: block descriptors, data row and exception word offsets
+    // of the tile's blocks; the exception bitmap of the tile's integers, per
+    // bitmap word the exceptions before it (tile-wide) and the bit offset |
+    // width code of its first exception value; staged exception words
+    static constexpr int NBLK = CLS == kClsPfd ? TW / 128 : 1;
+    static constexpr int NBM = CLS == kClsPfd ? TW / 32 : 1;
+    static constexpr int NX = CLS == kClsPfd ? TW / 8 : 1;
+    static constexpr int NXV = CLS == kClsPfd ? TW / 8 : 1;
+    uint32_t bdesc[NBLK], brow[NBLK], bxw[NBLK];
+    uint32_t bmap[NBM], xcnt[NBM], vbit[NBM];
+    uint32_t xw[NX];
+    uint32_t xv[NXV];   // exception values in tile order, when they fit
 };
 
 
@@ -1118,6 +860,240 @@ __device__ uint32_t wprologue_afor(const TileCtx &c, WaveSmem<TW, kClsAfor> &sm,
     return 0;
 }
 
+// ---- Group-PFD (Section 6.2) --------------------------------------------------
+// A tile is a whole number of blocks of 32 tuples.  The prologue reads the
+// tile's block descriptors, scans their data rows and exception words, stages
+// the tile's exception words in LDS when they fit, and makes the tuple
+// records: tuple t of block j has width b_j, at row offset 32 * (the rows of
+// the blocks before j) + (t mod 32) * b_j.  Once the data rows are staged,
+// pfd_marks sets a bitmap of the tile's exception positions -- from the
+// linked chain (the slot of an exception holds the distance to the next
+// one) or from the tuple and component masks -- and the unpack replaces the
+// values at marked positions with their exception values.
+
+// Exception words of a tile: staged in LDS, or read from the stream.
+struct ExcSrc {
+    const uint32_t *lds;
+    const gu32 *g;
+    uint32_t n;
+    bool staged;
+    __device__ __forceinline__ uint32_t at(uint32_t i) const {
+        if (i >= n) return 0u;
+        return staged ? lds[i] : g[i];
+    }
+};
+
+template <int TW>
+__device__ uint32_t wprologue_pfd(const TileCtx &c, WaveSmem<TW, kClsPfd> &sm, uint32_t lane, uint32_t &dbase,
+                                  uint64_t stream_words, ExcSrc &xs) {
+    using SM = WaveSmem<TW, kClsPfd>;
+    const uint32_t k = c.k;
+    const uint32_t nb = (c.ntup + 31u) >> 5;   // <= NBLK <= 32
+    const uint32_t beta0 = c.t0 >> 5;
+    const int bitmap = c.h.pfd_pos;
+    uint32_t desc = 0, b = 0, ew = 0;
+    bool bad_range = false, bad_desc = false;
+    if (lane < nb) {
+        if (beta0 + lane >= c.C) {
+            bad_range = true;
+        } else {
+            desc = ((const gu32 *)c.ctrl)[beta0 + lane];
+            b = desc & 63u;
+            const uint32_t nexc = desc >> 20, wcode = (desc >> 6) & 3u;
+            const uint32_t first = (desc >> 8) & 0xFFFu;
+            if (b > 32u || nexc > 32u * k || (nexc && !wcode) || (bitmap && first > 32u)) {
+                bad_desc = true;
+                b = 0;
+                desc = 0;
+            }
+            ew = pfd_exc_words(desc, (int)k, bitmap);
+        }
+    }
+    if (wave_any(bad_range)) return kErrRange;
+    if (wave_any(bad_desc)) return kErrPfdDesc;
+    const uint32_t ib = wave_incl_scan(b), ie = wave_incl_scan(ew);
+    const uint32_t xwords = (uint32_t)__builtin_amdgcn_readlane((int)ie, 63);
+    if (lane < nb) {
+        sm.bdesc[lane] = desc;
+        sm.brow[lane] = ib - b;
+        sm.bxw[lane] = ie - ew;
+    }
+    dbase = (uint32_t)(c.st.data >> 5);
+    const uint64_t ex0 = 4ull + c.C + c.D + c.st.exc;
+    if (ex0 + xwords > stream_words) return kErrRange;
+    xs.lds = sm.xw;
+    xs.g = (const gu32 *)c.S + ex0;
+    xs.n = xwords;
+    xs.staged = xwords <= (uint32_t)SM::NX;
+    if (xs.staged)
+        for (uint32_t i = lane; i < xwords; i += 64u) sm.xw[i] = xs.g[i];
+    wave_lds_sync();
+    for (uint32_t t = lane; t < c.ntup; t += 64u) {
+        const uint32_t j = t >> 5, bj = sm.bdesc[j] & 63u;
+        sm.rec[t] = rec_pack(32u * sm.brow[j] + (t & 31u) * bj, bj);
+    }
+    wave_lds_sync();
+    return 0;
+}
+
+template <int TW, typename W>
+__device__ uint32_t pfd_marks(const TileCtx &c, WaveSmem<TW, kClsPfd> &sm, uint32_t lane, W rows, uint32_t nrow,
+                              const ExcSrc &xs, uint32_t &nexc_tile) {
+    const uint32_t k = c.k, lk = c.lk;
+    const uint32_t nb = (c.ntup + 31u) >> 5;
+    const uint32_t BI = 32u * k;        // positions per block
+    const uint32_t nbw = nb * k;        // bitmap words of the tile's blocks (k per block)
+    const bool linked = c.h.pfd_pos == GC_PFD_LINKED;
+    for (uint32_t w = lane; w < nbw; w += 64u) sm.bmap[w] = 0u;
+    wave_lds_sync();
+    bool bad = false;
+    if (linked) {
+        // one lane walks the chain of one block; position p is component
+        // p mod k of the block's tuple p / k, at bit (p / k) * b of its rows.
+        // At k = 4 the block's four bitmap words stay in registers.
+        for (uint32_t j = lane; j < nb; j += 64u) {
+            const uint32_t desc = sm.bdesc[j], nexc = desc >> 20, b = desc & 63u, M = mask_of(b);
+            const uint32_t o0 = 32u * sm.brow[j];
+            const uint32_t rlast = nrow ? nrow - 1u : 0u;
+            uint32_t p = (desc >> 8) & 0xFFFu;
+            uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+            for (uint32_t e = 0; e < nexc; e++) {
+                if (p >= BI) {
+                    bad = true;
+                    break;
+                }
+                uint32_t slot = 0;
+                if (b && nrow) {
+                    const uint32_t O = o0 + (p >> lk) * b;
+                    const uint32_t row = min(O >> 5, rlast), sh = O & 31u;
+                    const uint32_t at = row * k + (p & (k - 1u));
+                    const uint32_t lo = rows[at];
+                    const uint32_t hi = row < rlast ? rows[at + k] : 0u;
+                    slot = funnel(hi, lo, sh) & M;
+                }
+                const uint32_t bit = 1u << (p & 31u);
+                if (k == 4u) {
+                    const uint32_t wq = p >> 5;
+                    m0 |= wq == 0u ? bit : 0u;
+                    m1 |= wq == 1u ? bit : 0u;
+                    m2 |= wq == 2u ? bit : 0u;
+                    m3 |= wq == 3u ? bit : 0u;
+                } else {
+                    atomicOr(&sm.bmap[(j * BI + p) >> 5], bit);
+                }
+                p = slot < BI ? p + slot + 1u : BI;
+            }
+            if (k == 4u) {
+                sm.bmap[4u * j] = m0;
+                sm.bmap[4u * j + 1u] = m1;
+                sm.bmap[4u * j + 2u] = m2;
+                sm.bmap[4u * j + 3u] = m3;
+            }
+        }
+    } else {
+        // one lane per tuple: its component mask, if the tuple mask names it
+        for (uint32_t x = lane; x < 32u * nb; x += 64u) {
+            const uint32_t j = x >> 5, t = x & 31u;
+            if (!(sm.bdesc[j] >> 20)) continue;
+            const uint32_t xb = sm.bxw[j];
+            const uint32_t tm = xs.at(xb);
+            if (!((tm >> t) & 1u)) continue;
+            const uint32_t r = (uint32_t)__builtin_popcount(tm & ((1u << t) - 1u));
+            const uint32_t base = j * BI + t * k;
+            if (k < 32u) {
+                const uint32_t bit = r * k;
+                const uint32_t m = (xs.at(xb + 1u + (bit >> 5)) >> (bit & 31u)) & mask_of(k);
+                atomicOr(&sm.bmap[base >> 5], m << (base & 31u));
+            } else {
+                for (uint32_t h = 0; h < (k >> 5); h++) sm.bmap[(base >> 5) + h] = xs.at(xb + 1u + r * (k >> 5) + h);
+            }
+        }
+    }
+    if (wave_any(bad)) return kErrPfdChain;
+    wave_lds_sync();
+    // exceptions before every bitmap word, tile-wide
+    uint32_t run = 0;
+    for (uint32_t w0 = 0; w0 < nbw; w0 += 64u) {
+        const uint32_t w = w0 + lane;
+        const uint32_t cnt = w < nbw ? (uint32_t)__builtin_popcount(sm.bmap[w]) : 0u;
+        const uint32_t inc = wave_incl_scan(cnt);
+        if (w < nbw) sm.xcnt[w] = run + inc - cnt;
+        run += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+    }
+    wave_lds_sync();
+    // per word: bit offset of its first value in the tile's exception words
+    // | width code; every block must mark exactly its exception count
+    for (uint32_t w = lane; w < nbw; w += 64u) {
+        const uint32_t j = w >> lk, desc = sm.bdesc[j], nexc = desc >> 20, wcode = (desc >> 6) & 3u;
+        const uint32_t first_w = j << lk, last_w = first_w + k - 1u;
+        const uint32_t before = sm.xcnt[w] - sm.xcnt[first_w];
+        const uint32_t xb = sm.bxw[j];
+        uint32_t vb = xb;
+        if (!linked) {
+            const uint32_t nt = (desc >> 8) & 0xFFFu;
+            vb = xb + 1u + ((nt * k + 31u) >> 5);
+            if (w == first_w && nexc && (uint32_t)__builtin_popcount(xs.at(xb)) != nt) bad = true;
+        }
+        if (w == last_w) {
+            const uint32_t total = sm.xcnt[w] + (uint32_t)__builtin_popcount(sm.bmap[w]) - sm.xcnt[first_w];
+            if (total != nexc) bad = true;
+        }
+        const uint32_t ewb = 4u << wcode;
+        sm.vbit[w] = ((32u * vb + before * ewb) << 2) | wcode;
+        // the word's exception values, in order, to xv when the tile's fit
+        if (run <= (uint32_t)WaveSmem<TW, kClsPfd>::NXV) {
+            uint32_t bm = sm.bmap[w], r = sm.xcnt[w], bit = 32u * vb + before * ewb;
+            const uint32_t M = mask_of(ewb);
+            while (bm) {
+                sm.xv[r++] = (xs.at(bit >> 5) >> (bit & 31u)) & M;
+                bit += ewb;
+                bm &= bm - 1u;
+            }
+        }
+    }
+    if (wave_any(bad)) return linked ? kErrPfdChain : kErrBitmap;
+    nexc_tile = run;
+    wave_lds_sync();
+    return 0;
+}
+
+// Replaces the marked integers of quad q (tile integers 4q .. 4q + 3): from
+// the values in tile order (xv) when the tile's exceptions fit there,
+// otherwise from the exception words.
+struct PatchSrc {
+    const uint32_t *bmap, *vbit, *xcnt, *xv;
+    ExcSrc xs;
+    bool in_lds;
+};
+
+__device__ __forceinline__ void pfd_patch(u32x4 &v, uint32_t q, const PatchSrc &ps) {
+    const uint32_t wi = q >> 3, sh4 = (q & 7u) << 2;
+    const uint32_t bm = ps.bmap[wi];
+    const uint32_t nib = (bm >> sh4) & 15u;
+    if (nib) {
+        const uint32_t below = (uint32_t)__builtin_popcount(bm & ((1u << sh4) - 1u));
+        uint32_t o[4] = {v.x, v.y, v.z, v.w};
+        if (ps.in_lds) {
+            uint32_t r = ps.xcnt[wi] + below;
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                if ((nib >> j) & 1u) o[j] = ps.xv[r++];
+        } else {
+            const uint32_t code = ps.vbit[wi];
+            const uint32_t ew = 4u << (code & 3u), M = mask_of(ew);
+            uint32_t bit = (code >> 2) + below * ew;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                if ((nib >> j) & 1u) {
+                    o[j] = (ps.xs.at(bit >> 5) >> (bit & 31u)) & M;
+                    bit += ew;
+                }
+            }
+        }
+        v = u32x4{o[0], o[1], o[2], o[3]};
+    }
+}
+
 // Four consecutive integers of quad q from the tuple records and data rows
 // (in global memory, or staged in LDS).
 template <typename RowPtr>
@@ -1174,16 +1150,19 @@ __device__ __forceinline__ void store_quad(uint32_t *out, uint32_t ii, uint32_t 
 // Sums (SUM) or writes the tile's integers: lane l handles quads l, l + 64,
 // ...; a delta tile is scanned in-lane, across the wave with DPP, and from
 // the carry of the previous rounds.
-template <int R, bool SUM, typename RowPtr>
+template <int R, bool SUM, bool PATCH, typename RowPtr>
 __device__ __forceinline__ uint32_t tile_quads(const uint32_t *rec, uint32_t tsh, uint32_t kq, RowPtr rows,
                                                uint32_t nrow, uint32_t nint, uint32_t lane, bool delta,
-                                               uint32_t carry, uint32_t *out, bool vec) {
+                                               uint32_t carry, uint32_t *out, bool vec, const PatchSrc &ps) {
     uint32_t s = 0;
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const uint32_t q = (uint32_t)r * 64u + lane;
         u32x4 v = {0u, 0u, 0u, 0u};
-        if (4u * q < nint) v = extract_quad(rec[q >> tsh], q, kq, rows, nrow);
+        if (4u * q < nint) {
+            v = extract_quad(rec[q >> tsh], q, kq, rows, nrow);
+            if constexpr (PATCH) pfd_patch(v, q, ps);
+        }
         if constexpr (SUM) {
             s += v.x + v.y + v.z + v.w;
         } else if (delta) {
@@ -1207,12 +1186,13 @@ __device__ __forceinline__ uint32_t tile_quads(const uint32_t *rec, uint32_t tsh
 // the carry of the earlier rounds).  FULL: a whole tile with a 16-byte
 // aligned output, so no quad needs a bounds check.  Rows are read without a
 // clamp: the row after the last holds padding, and its bits are masked off.
-template <int R, bool SUM, bool FULL, bool DELTA>
+template <int R, bool SUM, bool FULL, bool DELTA, bool PATCH>
 __device__ __forceinline__ uint32_t quads_lds(const uint32_t *rec, const u32x4 *data, uint32_t tsh, uint32_t kq,
                                               uint32_t nint, uint32_t lane, uint32_t carry, uint32_t *out,
-                                              bool vec) {
+                                              bool vec, const PatchSrc &ps) {
     uint32_t s = 0;
-#pragma unroll
+    constexpr int U = PATCH ? 2 : R;   // the patch branch needs registers of its own
+#pragma unroll U
     for (int r = 0; r < R; r++) {
         const uint32_t q = (uint32_t)r * 64u + lane;
         uint32_t rc = rec[q >> tsh];
@@ -1226,6 +1206,9 @@ __device__ __forceinline__ uint32_t quads_lds(const uint32_t *rec, const u32x4 *
         v.y = funnel(hi.y, lo.y, sh) & M;
         v.z = funnel(hi.z, lo.z, sh) & M;
         v.w = funnel(hi.w, lo.w, sh) & M;
+        if constexpr (PATCH) {
+            if (FULL || 4u * q < nint) pfd_patch(v, q, ps);
+        }
         if constexpr (SUM) {
             s += v.x + v.y + v.z + v.w;
         } else {
@@ -1249,27 +1232,28 @@ template <int TW, int CLS, bool SUM>
 __device__ void wave_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, uint32_t gi, const TilePre &pre,
                           uint32_t loc_tag, WaveSmem<TW, CLS> &sm, uint32_t lane) {
     constexpr int R = TW / 256;
+    constexpr bool PATCH = CLS == kClsPfd;
     HeaderFields hl;
     const bool delta = header_fields(L.w0, hl) && hl.delta;
     const uint32_t carry0 = (!SUM && delta && L.ntiles > 1u) ? pre.carry : 0u;
     TileCtx c;
     const bool ok = tile_ctx(L, m, pre.s0, pre.s1, (uint32_t)TW, loc_tag, c);
     uint32_t dbase = 0, err = ok ? 0u : kErrLocate;
+    PatchSrc ps = {sm.bmap, sm.vbit, sm.xcnt, sm.xv, ExcSrc{nullptr, nullptr, 0u, false}, false};
     if (!err) {
         if constexpr (CLS == kClsSim) err = wprologue_sim<TW>(c, sm, lane, dbase);
         else if constexpr (CLS == kClsGscU) err = wprologue_gscu<TW>(c, sm, lane, dbase);
         else if constexpr (CLS == kClsGscB) err = wprologue_gscb<TW>(c, sm, lane, dbase);
-        else err = wprologue_afor<TW>(c, sm, lane, dbase);
+        else if constexpr (CLS == kClsAfor) err = wprologue_afor<TW>(c, sm, lane, dbase);
+        else err = wprologue_pfd<TW>(c, sm, lane, dbase, L.stream_words, ps.xs);
     }
-    const bool good = err == 0u;
-    if (!good && lane == 0) latch(a.status, err);
     using SM = WaveSmem<TW, CLS>;
     const uint32_t Dk = c.D >> c.lk;
     const uint32_t nrow = Dk > dbase ? Dk - dbase : 0u;
     const uint32_t kq = c.k >> 2;
     const u32x4 *rows = reinterpret_cast<const u32x4 *>(c.data) + (size_t)dbase * kq;
     const uint32_t tsh = c.lk - 2u;
-    const uint32_t nint = good ? c.nint : 0u;
+    uint32_t nint = err ? 0u : c.nint;
     // the tile's data rows end with its last record (offsets grow with the tuple)
     uint32_t span = 0;
     if (nint) {
@@ -1277,25 +1261,35 @@ __device__ void wave_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, ui
         span = min(nrow, ((lr >> 6) + (lr & 63u) + 31u) >> 5);
     }
     const bool staged = span * kq <= (uint32_t)SM::NDATA;
+    if (staged && span) stage_rows<SM::NDATA>(sm.data, (const gu32x4 *)rows, span * kq, lane);
+    if constexpr (PATCH) {
+        if (!err) {
+            uint32_t nx = 0;
+            err = staged ? pfd_marks<TW>(c, sm, lane, reinterpret_cast<const uint32_t *>(sm.data), span, ps.xs, nx)
+                         : pfd_marks<TW>(c, sm, lane, (const gu32 *)rows, nrow, ps.xs, nx);
+            ps.in_lds = nx <= (uint32_t)SM::NXV;
+            if (err) nint = 0u;
+        }
+    }
+    if (err && lane == 0) latch(a.status, err);
     uint32_t *out = L.out + c.i0;
     const bool vec = (reinterpret_cast<uintptr_t>(out) & 15u) == 0u;
     uint32_t s = 0;
     if (staged) {
-        if (span) stage_rows<SM::NDATA>(sm.data, (const gu32x4 *)rows, span * kq, lane);
         const u32x4 *d = sm.data;
         const bool full = nint == (uint32_t)TW && vec;
         if constexpr (SUM) {
-            s = full ? quads_lds<R, true, true, true>(sm.rec, d, tsh, kq, nint, lane, 0u, out, vec)
-                     : quads_lds<R, true, false, true>(sm.rec, d, tsh, kq, nint, lane, 0u, out, vec);
+            s = full ? quads_lds<R, true, true, true, PATCH>(sm.rec, d, tsh, kq, nint, lane, 0u, out, vec, ps)
+                     : quads_lds<R, true, false, true, PATCH>(sm.rec, d, tsh, kq, nint, lane, 0u, out, vec, ps);
         } else if (c.h.delta) {
-            if (full) quads_lds<R, false, true, true>(sm.rec, d, tsh, kq, nint, lane, carry0, out, vec);
-            else quads_lds<R, false, false, true>(sm.rec, d, tsh, kq, nint, lane, carry0, out, vec);
+            if (full) quads_lds<R, false, true, true, PATCH>(sm.rec, d, tsh, kq, nint, lane, carry0, out, vec, ps);
+            else quads_lds<R, false, false, true, PATCH>(sm.rec, d, tsh, kq, nint, lane, carry0, out, vec, ps);
         } else {
-            if (full) quads_lds<R, false, true, false>(sm.rec, d, tsh, kq, nint, lane, 0u, out, vec);
-            else quads_lds<R, false, false, false>(sm.rec, d, tsh, kq, nint, lane, 0u, out, vec);
+            if (full) quads_lds<R, false, true, false, PATCH>(sm.rec, d, tsh, kq, nint, lane, 0u, out, vec, ps);
+            else quads_lds<R, false, false, false, PATCH>(sm.rec, d, tsh, kq, nint, lane, 0u, out, vec, ps);
         }
     } else {
-        s = tile_quads<R, SUM>(sm.rec, tsh, kq, rows, nrow, nint, lane, c.h.delta, carry0, out, vec);
+        s = tile_quads<R, SUM, PATCH>(sm.rec, tsh, kq, rows, nrow, nint, lane, c.h.delta, carry0, out, vec, ps);
     }
     if constexpr (SUM) {
         const uint32_t t = wave_sum(s);
@@ -1377,20 +1371,16 @@ static const void *wave_fn(int cls) {
     case kClsGscU: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsGscU, SUM>);
     case kClsGscB: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsGscB, SUM>);
     case kClsAfor: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsAfor, SUM>);
+    case kClsPfd:
+        // a Group-PFD tile holds whole 32-tuple blocks, up to 2048 integers at k = 64
+        if constexpr (TW >= 2048) return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsPfd, SUM>);
+        return nullptr;
     default: return nullptr;
     }
 }
 
 template <bool SUM>
 static const void *decode_fn(int tile, int cls) {
-    if (cls == kClsPfd) {
-        switch (tile) {
-        case 2048: return reinterpret_cast<const void *>(gc_pfd_kernel<2048, SUM>);
-        case 4096: return reinterpret_cast<const void *>(gc_pfd_kernel<4096, SUM>);
-        case 8192: return reinterpret_cast<const void *>(gc_pfd_kernel<8192, SUM>);
-        default: return nullptr;
-        }
-    }
     switch (tile) {
     case 1024: return wave_fn<1024, SUM>(cls);
     case 2048: return wave_fn<2048, SUM>(cls);
@@ -1404,7 +1394,7 @@ int launch_decode(int tile, int cls, bool sum, const DecodeArgs &a, hipStream_t 
     if (!a.count) return 0;
     const void *fn = sum ? decode_fn<true>(tile, cls) : decode_fn<false>(tile, cls);
     if (!fn) return -2;
-    const uint32_t per = cls == kClsPfd ? 1u : (uint32_t)kWaves;
+    const uint32_t per = (uint32_t)kWaves;
     DecodeArgs arg = a;
     void *params[] = {&arg};
     if (hipLaunchKernel(fn, dim3((a.count + per - 1) / per), dim3(kThreads), params, 0, s) != hipSuccess) {

@@ -36,11 +36,11 @@ namespace {
 constexpr int kDefaultWaveTile = 2048;
 constexpr int kDefaultPfdTile = 4096;
 constexpr int kWaveTiles[3] = {1024, 2048, 4096};
-constexpr int kPfdTiles[3] = {2048, 4096, 8192};
+constexpr int kPfdTiles[2] = {2048, 4096};
 constexpr int kClsPfd = 4;
 
 bool valid_wave_tile(uint32_t t) { return t == 1024 || t == 2048 || t == 4096; }
-bool valid_pfd_tile(uint32_t t) { return t == 2048 || t == 4096 || t == 8192; }
+bool valid_pfd_tile(uint32_t t) { return t == 2048 || t == 4096; }
 
 #define HIP_OK(x)                         \
     do {                                  \
