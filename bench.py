@@ -354,8 +354,9 @@ def main():
         "phases_ms": {
             "note": "from a second plan with the same tiles and HIP events between the phases",
             "gpu_total": round(float(tm["total"].mean()), 4),
-            "locate": {CLASS_NAMES[c]: round(float(tm["locate"][:, c].mean()), 4)
-                       for c in range(5) if dec[c] > 0},
+            "locate": ({CLASS_NAMES[c]: round(float(tm["locate"][:, c].mean()), 4)
+                        for c in range(5) if dec[c] > 0} if args.locate_stream
+                       else {"all classes": round(float(tm["locate"].sum(axis=1).mean()), 4)}),
             "sum_and_carry": {CLASS_NAMES[c]: round(float(tm["sum"][:, c].mean()), 4)
                               for c in range(5) if dec[c] > 0},
             "decode": {CLASS_NAMES[c]: round(float(dec[c]), 4) for c in range(5) if dec[c] > 0},

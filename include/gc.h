@@ -152,8 +152,9 @@ typedef struct {
     uint32_t timing_slots;   /* > 0: time the kernels of each gc_decode_batch with
                                 HIP events, in this many rotating slots (see
                                 gc_plan_timings); the run is then not graphed  */
-    uint32_t schedule;       /* 0: every kernel on the launch stream, class by
-                                class; 1: the locate kernels of every class on a
+    uint32_t schedule;       /* 0: every kernel on the launch stream: one locate
+                                pass over every class, then class by class the
+                                other passes; 1: per-class locate kernels on a
                                 second stream, ahead of the other kernels      */
     uint32_t reserved[2];    /* zero */
 } gc_plan_opts;
@@ -190,13 +191,16 @@ gc_status gc_decode_each(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_o
  * events and writes, oldest run first, up to max_runs rows of
  * GC_TIMING_FIELDS floats (milliseconds) to ms:
  *   [0]                         the whole run, on the launch stream
- *   [1 + c]                     the locate kernels of codec class c
+ *   [1 + c]                     the locate kernels of codec class c (with
+ *                               schedule 0 the one locate pass, in the column
+ *                               of the first class the plan holds; 0 in the
+ *                               others)
  *   [1 + GC_CLASSES + c]        its tile-sum pass and carry scan
  *   [1 + 2 * GC_CLASSES + c]    its decode pass
  * with classes c = 0 Group-Simple, 1 Group-Scheme with unary descriptors,
  * 2 Group-Scheme with binary descriptors, 3 Group-AFOR, 4 Group-PFD (0 for a
- * class the plan does not hold).  Locate kernels overlap the other phases,
- * so the phases need not add up to the whole run.  *nruns receives the rows
+ * class the plan does not hold).  With schedule 1 locate kernels overlap the
+ * other phases, so the phases need not add up to the whole run.  *nruns receives the rows
  * written.  GC_EINVAL if the plan records no events.                       */
 #define GC_CLASSES 5
 #define GC_TIMING_FIELDS (1 + 3 * GC_CLASSES)

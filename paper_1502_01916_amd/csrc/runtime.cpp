@@ -438,6 +438,26 @@ gc_status plan_materialize(gc_plan *p) {
 }
 
 // Launches the locate kernels of codec class c on stream s.
+// Launches the locate kernels of every class at once on stream s, with the
+// epoch of class 0 (the serial schedule: every class's passes follow it).
+gc_status launch_all_locate(gc_plan *p, hipStream_t s) {
+    if (!p->total_a) return GC_OK;
+    ListDesc none;
+    std::memset(&none, 0, sizeof(none));
+    LocateArgs a = make_locate_args(p->d_lists, p->d_item_a, p->d_item_s, none, p->total_a, p->total_s, 0, p->sc,
+                                    p->ctx->status);
+    a.item_lo = 0;
+    return launch_locate(a, s) ? GC_EDEVICE : GC_OK;
+}
+
+// The class that reports the locate time: with the serial schedule the
+// single locate pass is timed in the column of the first class with tiles.
+int first_class(const gc_plan *p) {
+    for (int c = 0; c < kClasses; c++)
+        if (p->cr[c].count) return c;
+    return 0;
+}
+
 gc_status launch_class_locate(gc_plan *p, int c, hipStream_t s) {
     const ClassRange &r = p->cr[c];
     if (!r.loc_count) return GC_OK;
@@ -457,21 +477,24 @@ gc_status launch_class_work(gc_plan *p, int c, hipStream_t s, hipEvent_t mid = n
     ListDesc none;
     std::memset(&none, 0, sizeof(none));
     const int tile = c == kClsPfd ? p->tile_p : p->tile_w;
+    const int epoch_cls = p->serial ? 0 : c;   // whose locate epoch tags the tile starts
     if (r.sum) {
-        DecodeArgs d = make_decode_args(p->d_lists, none, r.lo, r.sum, c, p->sc, p->ctx->status);
+        DecodeArgs d = make_decode_args(p->d_lists, none, r.lo, r.sum, epoch_cls, p->sc, p->ctx->status);
         if (launch_decode(tile, c, true, d, s)) return GC_EDEVICE;
         CarryArgs ca = make_carry_args(p->d_lists, p->d_scan_list + r.scan_lo, none, r.scans, p->sc);
         if (launch_carry_scan(ca, s)) return GC_EDEVICE;
     }
     if (mid) HIP_OK(hipEventRecord(mid, s));
-    DecodeArgs d = make_decode_args(p->d_lists, none, r.lo, r.count, c, p->sc, p->ctx->status);
+    DecodeArgs d = make_decode_args(p->d_lists, none, r.lo, r.count, epoch_cls, p->sc, p->ctx->status);
     return launch_decode(tile, c, false, d, s) ? GC_EDEVICE : GC_OK;
 }
 
-// Launches a whole run on stream s, class after class.  With an auxiliary
-// stream `aux`, the locate kernels of every class run there in class order
-// and the rest of class c waits only for its own locate, so the locate of
-// the next class overlaps the passes of this one.  sync[c] signals the end
+// Launches a whole run on stream s: without an auxiliary stream, one locate
+// pass over every class, then class after class the tile sums, carry scans
+// and decode pass.  With an auxiliary stream `aux`, the locate kernels of
+// every class run there in class order and the rest of class c waits only
+// for its own locate, so the locate of the next class overlaps the passes of
+// this one.  sync[c] signals the end
 // of class c's locate; with `tev` (timing), class c records tev[5c .. 5c+4]:
 // before and after its locate, before its tile sums, before and after its
 // decode pass.
@@ -482,6 +505,12 @@ gc_status plan_launch(gc_plan *p, hipStream_t s, hipStream_t aux = nullptr, hipE
         HIP_OK(hipStreamWaitEvent(aux, start, 0));
     }
     hipStream_t ls = aux ? aux : s;
+    if (!aux) {
+        const int c0 = first_class(p);
+        if (tev) HIP_OK(hipEventRecord(tev[5 * c0], s));
+        if (gc_status rc = launch_all_locate(p, s)) return rc;
+        if (tev) HIP_OK(hipEventRecord(tev[5 * c0 + 1], s));
+    }
     for (int c = 0; c < kClasses && aux; c++) {
         if (!p->cr[c].count) continue;
         if (tev) HIP_OK(hipEventRecord(tev[5 * c], ls));
@@ -490,13 +519,7 @@ gc_status plan_launch(gc_plan *p, hipStream_t s, hipStream_t aux = nullptr, hipE
     }
     for (int c = 0; c < kClasses; c++) {
         if (!p->cr[c].count) continue;
-        if (aux) {
-            HIP_OK(hipStreamWaitEvent(s, tev ? tev[5 * c + 1] : sync[c], 0));
-        } else {
-            if (tev) HIP_OK(hipEventRecord(tev[5 * c], s));
-            if (gc_status rc = launch_class_locate(p, c, s)) return rc;
-            if (tev) HIP_OK(hipEventRecord(tev[5 * c + 1], s));
-        }
+        if (aux) HIP_OK(hipStreamWaitEvent(s, tev ? tev[5 * c + 1] : sync[c], 0));
         if (tev) HIP_OK(hipEventRecord(tev[5 * c + 2], s));
         if (gc_status rc = launch_class_work(p, c, s, tev ? tev[5 * c + 3] : nullptr)) return rc;
         if (tev) HIP_OK(hipEventRecord(tev[5 * c + 4], s));
@@ -890,10 +913,11 @@ gc_status gc_plan_timings(gc_plan *plan, uint32_t max_runs, float *ms, uint32_t 
         for (int f = 0; f < GC_TIMING_FIELDS; f++) row[f] = 0.0f;
         HIP_OK(hipEventSynchronize(e[1]));
         HIP_OK(hipEventElapsedTime(&row[0], e[0], e[1]));
+        const int c0 = first_class(plan);
         for (int c = 0; c < kClasses; c++) {
             if (!plan->cr[c].count) continue;
             hipEvent_t *ce = e + 2 + 5 * c;
-            HIP_OK(hipEventElapsedTime(&row[1 + c], ce[0], ce[1]));
+            if (!plan->serial || c == c0) HIP_OK(hipEventElapsedTime(&row[1 + c], ce[0], ce[1]));
             HIP_OK(hipEventElapsedTime(&row[1 + kClasses + c], ce[2], ce[3]));
             HIP_OK(hipEventElapsedTime(&row[1 + 2 * kClasses + c], ce[3], ce[4]));
         }

@@ -213,6 +213,13 @@ def test_timed_plan(torch_cuda, ctx, locate_stream):
         assert np.all(tm["decode"][:, c] > 0), c
         assert np.all(tm["sum"][:, c] > 0), c
         assert np.all(tm["decode"][:, c] <= tm["total"] + 1e-3)
+    if locate_stream:
+        for c in present:
+            assert np.all(tm["locate"][:, c] > 0), c
+    else:
+        # one locate pass for every class, timed in the first class's column
+        assert np.all(tm["locate"][:, gc.CLS_SIMPLE] > 0)
+        assert not np.any(tm["locate"][:, 1:])
     plan.close()
 
 
