@@ -47,8 +47,9 @@ def variants(gc):
 
 
 CLASS_NAMES = ["group-simple", "group-scheme-unary", "group-scheme-binary", "group-afor", "group-pfd"]
-KERNEL_NAMES = ["gc_wave_kernel<%d, 0, false>", "gc_wave_kernel<%d, 1, false>", "gc_wave_kernel<%d, 2, false>",
-                "gc_wave_kernel<%d, 3, false>", "gc_wave_kernel<%d, 4, false>"]
+# the decode pass of each class (third template argument: 0 decode, 1 tile sums)
+KERNEL_NAMES = ["gc_wave_kernel<%d, 0, 0>", "gc_wave_kernel<%d, 1, 0>", "gc_wave_kernel<%d, 2, 0>",
+                "gc_wave_kernel<%d, 3, 0>", "gc_wave_kernel<%d, 4, 0>"]
 
 
 def codec_class(gc, codec, kw):

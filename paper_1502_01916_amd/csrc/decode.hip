@@ -1228,76 +1228,117 @@ __device__ __forceinline__ uint32_t quads_lds(const uint32_t *rec, const u32x4 *
     return s;
 }
 
-template <int TW, int CLS, bool SUM>
-__device__ void wave_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, uint32_t gi, const TilePre &pre,
-                          uint32_t loc_tag, WaveSmem<TW, CLS> &sm, uint32_t lane) {
-    constexpr int R = TW / 256;
-    constexpr bool PATCH = CLS == kClsPfd;
-    HeaderFields hl;
-    const bool delta = header_fields(L.w0, hl) && hl.delta;
-    const uint32_t carry0 = (!SUM && delta && L.ntiles > 1u) ? pre.carry : 0u;
+// Everything of one tile up to its unpack: context, prologue, staged rows
+// and (Group-PFD) exception marks.
+template <int TW, int CLS>
+struct TileRun {
     TileCtx c;
+    PatchSrc ps;
+    const u32x4 *rows;
+    uint32_t *out;
+    uint32_t nint, nrow, kq, tsh;
+    bool staged, vec;
+};
+
+template <int TW, int CLS>
+__device__ __forceinline__ void tile_setup(const DecodeArgs &a, const ListDesc &L, uint32_t m, const TilePre &pre,
+                                           uint32_t loc_tag, WaveSmem<TW, CLS> &sm, uint32_t lane,
+                                           TileRun<TW, CLS> &t) {
+    TileCtx &c = t.c;
     const bool ok = tile_ctx(L, m, pre.s0, pre.s1, (uint32_t)TW, loc_tag, c);
     uint32_t dbase = 0, err = ok ? 0u : kErrLocate;
-    PatchSrc ps = {sm.bmap, sm.vbit, sm.xcnt, sm.xv, ExcSrc{nullptr, nullptr, 0u, false}, false};
+    t.ps = PatchSrc{sm.bmap, sm.vbit, sm.xcnt, sm.xv, ExcSrc{nullptr, nullptr, 0u, false}, false};
     if (!err) {
         if constexpr (CLS == kClsSim) err = wprologue_sim<TW>(c, sm, lane, dbase);
         else if constexpr (CLS == kClsGscU) err = wprologue_gscu<TW>(c, sm, lane, dbase);
         else if constexpr (CLS == kClsGscB) err = wprologue_gscb<TW>(c, sm, lane, dbase);
         else if constexpr (CLS == kClsAfor) err = wprologue_afor<TW>(c, sm, lane, dbase);
-        else err = wprologue_pfd<TW>(c, sm, lane, dbase, L.stream_words, ps.xs);
+        else err = wprologue_pfd<TW>(c, sm, lane, dbase, L.stream_words, t.ps.xs);
     }
     using SM = WaveSmem<TW, CLS>;
     const uint32_t Dk = c.D >> c.lk;
-    const uint32_t nrow = Dk > dbase ? Dk - dbase : 0u;
-    const uint32_t kq = c.k >> 2;
-    const u32x4 *rows = reinterpret_cast<const u32x4 *>(c.data) + (size_t)dbase * kq;
-    const uint32_t tsh = c.lk - 2u;
-    uint32_t nint = err ? 0u : c.nint;
+    t.nrow = Dk > dbase ? Dk - dbase : 0u;
+    t.kq = c.k >> 2;
+    t.rows = reinterpret_cast<const u32x4 *>(c.data) + (size_t)dbase * t.kq;
+    t.tsh = c.lk - 2u;
+    t.nint = err ? 0u : c.nint;
     // the tile's data rows end with its last record (offsets grow with the tuple)
     uint32_t span = 0;
-    if (nint) {
+    if (t.nint) {
         const uint32_t lr = sm.rec[c.ntup - 1u];
-        span = min(nrow, ((lr >> 6) + (lr & 63u) + 31u) >> 5);
+        span = min(t.nrow, ((lr >> 6) + (lr & 63u) + 31u) >> 5);
     }
-    const bool staged = span * kq <= (uint32_t)SM::NDATA;
-    if (staged && span) stage_rows<SM::NDATA>(sm.data, (const gu32x4 *)rows, span * kq, lane);
-    if constexpr (PATCH) {
+    t.staged = span * t.kq <= (uint32_t)SM::NDATA;
+    if (t.staged && span) stage_rows<SM::NDATA>(sm.data, (const gu32x4 *)t.rows, span * t.kq, lane);
+    if constexpr (CLS == kClsPfd) {
         if (!err) {
             uint32_t nx = 0;
-            err = staged ? pfd_marks<TW>(c, sm, lane, reinterpret_cast<const uint32_t *>(sm.data), span, ps.xs, nx)
-                         : pfd_marks<TW>(c, sm, lane, (const gu32 *)rows, nrow, ps.xs, nx);
-            ps.in_lds = nx <= (uint32_t)SM::NXV;
-            if (err) nint = 0u;
+            err = t.staged ? pfd_marks<TW>(c, sm, lane, reinterpret_cast<const uint32_t *>(sm.data), span, t.ps.xs, nx)
+                           : pfd_marks<TW>(c, sm, lane, (const gu32 *)t.rows, t.nrow, t.ps.xs, nx);
+            t.ps.in_lds = nx <= (uint32_t)SM::NXV;
+            if (err) t.nint = 0u;
         }
     }
     if (err && lane == 0) latch(a.status, err);
-    uint32_t *out = L.out + c.i0;
-    const bool vec = (reinterpret_cast<uintptr_t>(out) & 15u) == 0u;
-    uint32_t s = 0;
-    if (staged) {
+    t.out = L.out + c.i0;
+    t.vec = (reinterpret_cast<uintptr_t>(t.out) & 15u) == 0u;
+}
+
+// The sum of a set-up tile's integers (wave-uniform).
+template <int TW, int CLS>
+__device__ __forceinline__ uint32_t tile_total(const TileRun<TW, CLS> &t, WaveSmem<TW, CLS> &sm, uint32_t lane) {
+    constexpr int R = TW / 256;
+    constexpr bool PATCH = CLS == kClsPfd;
+    uint32_t s;
+    if (t.staged) {
+        s = (t.nint == (uint32_t)TW && t.vec)
+                ? quads_lds<R, true, true, true, PATCH>(sm.rec, sm.data, t.tsh, t.kq, t.nint, lane, 0u, t.out, t.vec, t.ps)
+                : quads_lds<R, true, false, true, PATCH>(sm.rec, sm.data, t.tsh, t.kq, t.nint, lane, 0u, t.out, t.vec,
+                                                         t.ps);
+    } else {
+        s = tile_quads<R, true, PATCH>(sm.rec, t.tsh, t.kq, t.rows, t.nrow, t.nint, lane, false, 0u, t.out, t.vec,
+                                       t.ps);
+    }
+    return wave_sum(s);
+}
+
+// MODE: 0 decode (a delta tile adds carry[gi], the exclusive prefix of the
+// tile sums of its list), 1 the tile's sum to carry[gi].
+enum : int { kModeDecode = 0, kModeSum = 1 };
+
+template <int TW, int CLS, int MODE>
+__device__ void wave_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, uint32_t gi, const TilePre &pre,
+                          uint32_t loc_tag, WaveSmem<TW, CLS> &sm, uint32_t lane) {
+    constexpr int R = TW / 256;
+    constexpr bool PATCH = CLS == kClsPfd;
+    TileRun<TW, CLS> t;
+    tile_setup<TW, CLS>(a, L, m, pre, loc_tag, sm, lane, t);
+    if constexpr (MODE == kModeSum) {
+        const uint32_t s = tile_total<TW, CLS>(t, sm, lane);
+        if (lane == 0) a.carry[gi] = s;
+        return;
+    }
+    HeaderFields hl;
+    const bool delta = header_fields(L.w0, hl) && hl.delta;
+    const uint32_t carry0 = (delta && L.ntiles > 1u) ? pre.carry : 0u;
+    const uint32_t nint = t.nint;
+    if (t.staged) {
         const u32x4 *d = sm.data;
-        const bool full = nint == (uint32_t)TW && vec;
-        if constexpr (SUM) {
-            s = full ? quads_lds<R, true, true, true, PATCH>(sm.rec, d, tsh, kq, nint, lane, 0u, out, vec, ps)
-                     : quads_lds<R, true, false, true, PATCH>(sm.rec, d, tsh, kq, nint, lane, 0u, out, vec, ps);
-        } else if (c.h.delta) {
-            if (full) quads_lds<R, false, true, true, PATCH>(sm.rec, d, tsh, kq, nint, lane, carry0, out, vec, ps);
-            else quads_lds<R, false, false, true, PATCH>(sm.rec, d, tsh, kq, nint, lane, carry0, out, vec, ps);
+        const bool full = nint == (uint32_t)TW && t.vec;
+        if (t.c.h.delta) {
+            if (full) quads_lds<R, false, true, true, PATCH>(sm.rec, d, t.tsh, t.kq, nint, lane, carry0, t.out, t.vec, t.ps);
+            else quads_lds<R, false, false, true, PATCH>(sm.rec, d, t.tsh, t.kq, nint, lane, carry0, t.out, t.vec, t.ps);
         } else {
-            if (full) quads_lds<R, false, true, false, PATCH>(sm.rec, d, tsh, kq, nint, lane, 0u, out, vec, ps);
-            else quads_lds<R, false, false, false, PATCH>(sm.rec, d, tsh, kq, nint, lane, 0u, out, vec, ps);
+            if (full) quads_lds<R, false, true, false, PATCH>(sm.rec, d, t.tsh, t.kq, nint, lane, 0u, t.out, t.vec, t.ps);
+            else quads_lds<R, false, false, false, PATCH>(sm.rec, d, t.tsh, t.kq, nint, lane, 0u, t.out, t.vec, t.ps);
         }
     } else {
-        s = tile_quads<R, SUM, PATCH>(sm.rec, tsh, kq, rows, nrow, nint, lane, c.h.delta, carry0, out, vec, ps);
-    }
-    if constexpr (SUM) {
-        const uint32_t t = wave_sum(s);
-        if (lane == 0) a.carry[gi] = t;
+        (void)tile_quads<R, false, PATCH>(sm.rec, t.tsh, t.kq, t.rows, t.nrow, nint, lane, t.c.h.delta, carry0, t.out,
+                                          t.vec, t.ps);
     }
 }
 
-template <int TW, int CLS, bool SUM>
+template <int TW, int CLS, int MODE>
 __global__ __launch_bounds__(kThreads) void gc_wave_kernel(DecodeArgs a) {
     __shared__ WaveSmem<TW, CLS> sm[kWaves];
     const uint32_t wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63u;
@@ -1307,7 +1348,7 @@ __global__ __launch_bounds__(kThreads) void gc_wave_kernel(DecodeArgs a) {
     const uint32_t loc_tag = *(const gu32 *)&a.loc_state->epoch;   // written by an earlier kernel
     const TilePre pre = tile_pre(a, gi);
     const ListDesc L = tile_list(a, pre);
-    wave_tile<TW, CLS, SUM>(a, L, gi - L.tile_base, gi, pre, loc_tag, sm[wave], lane);
+    wave_tile<TW, CLS, MODE>(a, L, gi - L.tile_base, gi, pre, loc_tag, sm[wave], lane);
 }
 
 // ===========================================================================
@@ -1364,35 +1405,35 @@ int launch_carry_scan(const CarryArgs &a, hipStream_t s) {
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <int TW, bool SUM>
+template <int TW, int MODE>
 static const void *wave_fn(int cls) {
     switch (cls) {
-    case kClsSim: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsSim, SUM>);
-    case kClsGscU: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsGscU, SUM>);
-    case kClsGscB: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsGscB, SUM>);
-    case kClsAfor: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsAfor, SUM>);
+    case kClsSim: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsSim, MODE>);
+    case kClsGscU: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsGscU, MODE>);
+    case kClsGscB: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsGscB, MODE>);
+    case kClsAfor: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsAfor, MODE>);
     case kClsPfd:
         // a Group-PFD tile holds whole 32-tuple blocks, up to 2048 integers at k = 64
-        if constexpr (TW >= 2048) return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsPfd, SUM>);
+        if constexpr (TW >= 2048) return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsPfd, MODE>);
         return nullptr;
     default: return nullptr;
     }
 }
 
-template <bool SUM>
+template <int MODE>
 static const void *decode_fn(int tile, int cls) {
     switch (tile) {
-    case 1024: return wave_fn<1024, SUM>(cls);
-    case 2048: return wave_fn<2048, SUM>(cls);
-    case 4096: return wave_fn<4096, SUM>(cls);
+    case 1024: return wave_fn<1024, MODE>(cls);
+    case 2048: return wave_fn<2048, MODE>(cls);
+    case 4096: return wave_fn<4096, MODE>(cls);
     default: return nullptr;
     }
 }
 
-// Launches the sum pass (sum != 0) or the decode pass over a.count tiles.
-int launch_decode(int tile, int cls, bool sum, const DecodeArgs &a, hipStream_t s) {
+// Launches a pass over a.count tiles: mode 0 decode, 1 tile sums.
+int launch_decode(int tile, int cls, int mode, const DecodeArgs &a, hipStream_t s) {
     if (!a.count) return 0;
-    const void *fn = sum ? decode_fn<true>(tile, cls) : decode_fn<false>(tile, cls);
+    const void *fn = mode == 1 ? decode_fn<kModeSum>(tile, cls) : decode_fn<kModeDecode>(tile, cls);
     if (!fn) return -2;
     const uint32_t per = (uint32_t)kWaves;
     DecodeArgs arg = a;

@@ -26,7 +26,7 @@ namespace gcdev {
 int codec_class(uint32_t w0);
 int launch_locate(const LocateArgs &a, hipStream_t s);
 int launch_carry_scan(const CarryArgs &a, hipStream_t s);
-int launch_decode(int tile, int cls, bool sum, const DecodeArgs &a, hipStream_t s);
+int launch_decode(int tile, int cls, int mode, const DecodeArgs &a, hipStream_t s);
 }  // namespace gcdev
 
 using namespace gcdev;
@@ -307,10 +307,10 @@ gc_status launch_one(const ListDesc &L, int cls, Scratch &sc, Status *st, hipStr
     const int tile = (int)L.tile_ints;
     const DecodeArgs d = single_args(L, cls, sc, st);
     if (L.ntiles > 1 && is_delta(L.w0)) {
-        if (launch_decode(tile, cls, true, d, s)) return GC_EDEVICE;
+        if (launch_decode(tile, cls, 1, d, s)) return GC_EDEVICE;
         if (launch_carry_scan(make_carry_args(nullptr, nullptr, L, 1, sc), s)) return GC_EDEVICE;
     }
-    if (launch_decode(tile, cls, false, d, s)) return GC_EDEVICE;
+    if (launch_decode(tile, cls, 0, d, s)) return GC_EDEVICE;
     return GC_OK;
 }
 
@@ -480,13 +480,13 @@ gc_status launch_class_work(gc_plan *p, int c, hipStream_t s, hipEvent_t mid = n
     const int epoch_cls = p->serial ? 0 : c;   // whose locate epoch tags the tile starts
     if (r.sum) {
         DecodeArgs d = make_decode_args(p->d_lists, none, r.lo, r.sum, epoch_cls, p->sc, p->ctx->status);
-        if (launch_decode(tile, c, true, d, s)) return GC_EDEVICE;
+        if (launch_decode(tile, c, 1, d, s)) return GC_EDEVICE;
         CarryArgs ca = make_carry_args(p->d_lists, p->d_scan_list + r.scan_lo, none, r.scans, p->sc);
         if (launch_carry_scan(ca, s)) return GC_EDEVICE;
     }
     if (mid) HIP_OK(hipEventRecord(mid, s));
     DecodeArgs d = make_decode_args(p->d_lists, none, r.lo, r.count, epoch_cls, p->sc, p->ctx->status);
-    return launch_decode(tile, c, false, d, s) ? GC_EDEVICE : GC_OK;
+    return launch_decode(tile, c, 0, d, s) ? GC_EDEVICE : GC_OK;
 }
 
 // Launches a whole run on stream s: without an auxiliary stream, one locate
