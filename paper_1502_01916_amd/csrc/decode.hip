@@ -251,9 +251,28 @@ __device__ __forceinline__ bool locate_item(const LocateArgs &a, uint32_t item, 
     return true;
 }
 
+// Workgroup totals of three values (one barrier).
+__device__ __forceinline__ void block_sum3(uint32_t &x, uint32_t &y, uint32_t &z, uint32_t (*tmp)[kWaves]) {
+    const uint32_t a = wave_sum(x), b = wave_sum(y), c = wave_sum(z);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        tmp[0][w] = a;
+        tmp[1][w] = b;
+        tmp[2][w] = c;
+    }
+    __syncthreads();
+    x = y = z = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; i++) {
+        x += tmp[0][i];
+        y += tmp[1][i];
+        z += tmp[2][i];
+    }
+}
+
 // Aggregate of every control chunk.
 __global__ __launch_bounds__(kThreads) void gc_locate_reduce(LocateArgs a) {
-    __shared__ uint32_t s_tmp[kWaves];
+    __shared__ uint32_t s_tmp[3][kWaves];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         // a new locate run: later kernels of this launch sequence tag and
         // check tile starts with the advanced epoch
@@ -265,10 +284,8 @@ __global__ __launch_bounds__(kThreads) void gc_locate_reduce(LocateArgs a) {
     if (!locate_item(a, blockIdx.x, L, chunk, list)) return;
     LocThread t;
     locate_thread(L, chunk, t);
-    uint32_t tt, te, td;
-    (void)block_excl_scan(t.vt, s_tmp, tt);
-    (void)block_excl_scan(t.ve, s_tmp, te);
-    (void)block_excl_scan(t.vd, s_tmp, td);
+    uint32_t tt = t.vt, te = t.ve, td = t.vd;
+    block_sum3(tt, te, td, s_tmp);
     if (t.bad) latch(a.status, kErrLocate);
     if (threadIdx.x == 0) {
         LocVal v;
