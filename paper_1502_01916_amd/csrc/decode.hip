@@ -861,19 +861,26 @@ __device__ uint32_t wprologue_afor(const TileCtx &c, WaveSmem<TW, kClsAfor> &sm,
     const uint64_t fdata0 = c.st.data;
     dbase = (uint32_t)((fdata0 + (uint64_t)sub0 * b0) >> 5);
     const uint32_t frel0 = (uint32_t)(fdata0 - 32ull * dbase);
+    // frame i of the tile marks its first tuple with i + 1 and records
+    // {base, b} with base + t * b the bit offset of tile tuple t of it
+    zero_markers<SM::TTM>(sm.rec, lane);
+    wave_lds_sync();
+    uint2 *info = reinterpret_cast<uint2 *>(sm.data);
     uint32_t st_t = ic - csum, off = ib - bsum;
 #pragma unroll
     for (int j = 0; j < FPT; j++) {
         const uint32_t i = lane * FPT + (uint32_t)j;
         const uint32_t b = bb[j];
         const uint32_t j0 = i == 0u ? sub0 : 0u;
-        const uint32_t frel = frel0 + off + j0 * b;
-        const uint32_t lim = min(cnt[j], max(c.ntup, st_t) - st_t);   // 0 once st_t >= ntup
-        for (uint32_t jj = 0; jj < lim; jj++) sm.rec[st_t + jj] = rec_pack(frel + jj * b, b);
+        if (cnt[j]) {
+            info[i] = make_uint2(frel0 + off + j0 * b - st_t * b, b);
+            if (st_t < c.ntup) sm.rec[st_t] = i + 1u;
+        }
         st_t += cnt[j];
         off += (cnt[j] ? cnt[j] + j0 : 0u) * b;
     }
     wave_lds_sync();
+    expand_records<SM::TTM>(sm.rec, info, lane);
     return 0;
 }
 
