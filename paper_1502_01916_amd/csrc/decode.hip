@@ -458,16 +458,16 @@ struct TileCtx {
 __device__ __forceinline__ uint32_t rec_pack(uint32_t rel, uint32_t bw) { return (rel << 6) | bw; }
 
 // Fills the tile context of tile m (global tile gi) of list L from the
-// host's header words; false if the stream's header disagrees or the locate
-// pass did not reach the tile in this run.
+// host's copy of the header (validated when the plan was made; the stream's
+// own header is compared with it at the end of the tile's set-up); false if
+// the locate pass did not reach the tile in this run.
 __device__ __forceinline__ bool tile_ctx(const ListDesc &L, uint32_t m, const TileInfo &s0, const TileInfo &s1,
                                          uint32_t tile, uint32_t loc_tag, TileCtx &c) {
     c.S = L.stream;
     c.n = L.n;
     c.C = L.C;
     c.D = L.D;
-    bool ok = header_ok(L, c.S[0], c.S[1], c.S[2], c.S[3], c.h);
-    if (!header_fields(L.w0, c.h)) ok = false;
+    bool ok = header_fields(L.w0, c.h);
     c.k = (uint32_t)c.h.k;
     c.lk = (uint32_t)c.h.lk;
     c.T = (c.n + c.k - 1u) >> c.lk;
@@ -621,14 +621,13 @@ __device__ __forceinline__ void expand_records(uint32_t *rec, const uint2 *info,
 }
 
 // ---- Group-Simple ---------------------------------------------------------
-// Lane l reads selectors l*SPT .. l*SPT + SPT - 1 of the tile straight from
-// the control words, scans their tuple counts across the wave, and scatters
-// unit markers and record bases for expand_records.
+// Selectors are dealt to the lanes 64 at a time (selector i to lane i mod
+// 64), read straight from the control words; a wave scan of their tuple
+// counts per round places them, and each scatters its unit marker and record
+// base for expand_records.
 template <int TW>
 __device__ uint32_t wprologue_sim(const TileCtx &c, WaveSmem<TW, kClsSim> &sm, uint32_t lane, uint32_t &dbase) {
     using SM = WaveSmem<TW, kClsSim>;
-    constexpr int SPT = (SM::TTM + 1 + 63) / 64;   // selectors per lane
-    constexpr int NW = (7 + SPT + 7) / 8;           // control words they can span
     const uint32_t S_total = c.D >> c.lk;
     const uint32_t s_first = c.st.unit, sub0 = c.st.sub;
     const uint32_t s_end = c.has_en ? c.en.unit + (c.en.sub ? 1u : 0u) : S_total;
@@ -637,51 +636,32 @@ __device__ uint32_t wprologue_sim(const TileCtx &c, WaveSmem<TW, kClsSim> &sm, u
     if (!(s_end <= S_total && s_end > s_first && nsel <= c.TT + 1u && cw1 <= c.C)) return kErrRange;
     zero_markers<SM::TTM>(sm.rec, lane);
     dbase = s_first;
-    const uint32_t i0 = lane * (uint32_t)SPT;
-    const uint32_t g0 = s_first + i0;
     const gu32 *ctrl = (const gu32 *)c.ctrl;
-    uint32_t w[NW + 1];
-#pragma unroll
-    for (int k = 0; k < NW; k++) {
-        const uint32_t gw = (g0 >> 3) + (uint32_t)k;
-        w[k] = (i0 < nsel && gw < cw1) ? ctrl[gw] : 0u;
-    }
-    w[NW] = 0u;
-    const uint32_t sh = 4u * (g0 & 7u);
-#pragma unroll
-    for (int k = 0; k < NW; k++) w[k] = funnel(w[k + 1], w[k], sh);
-    uint32_t cnt[SPT], bwv[SPT];
-    uint32_t sum = 0;
+    uint2 *info = reinterpret_cast<uint2 *>(sm.data);
     bool bad = false;
-#pragma unroll
-    for (int j = 0; j < SPT; j++) {
-        const uint32_t i = i0 + (uint32_t)j;
-        const uint32_t sel = (w[j >> 3] >> (4 * (j & 7))) & 15u;
+    uint32_t base = 0;   // tuples of the tile before this round's selectors
+    wave_lds_sync();     // markers zeroed before the scatter
+    for (uint32_t i0 = 0; i0 < nsel; i0 += 64u) {
+        const uint32_t i = i0 + lane;
+        const bool in = i < nsel;
+        const uint32_t g = s_first + i;
+        const uint32_t sel = in ? (ctrl[g >> 3] >> (4u * (g & 7u))) & 15u : 0u;
         const uint32_t j0 = i == 0u ? sub0 : 0u;
         const uint32_t num = sim_num(sel);
-        const bool in = i < nsel, okj = sel < 10u && num > j0;
+        const bool okj = sel < 10u && num > j0;
         bad |= in && !okj;
-        cnt[j] = (in && okj) ? num - j0 : 0u;
-        bwv[j] = sim_bw(sel);
-        sum += cnt[j];
-    }
-    const uint32_t inc = wave_incl_scan(sum);
-    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
-    if (wave_any(bad)) return kErrSelector;
-    if (total < c.ntup) return kErrCount;
-    wave_lds_sync();   // markers zeroed before the scatter
-    uint2 *info = reinterpret_cast<uint2 *>(sm.data);
-    uint32_t start = inc - sum;
-#pragma unroll
-    for (int j = 0; j < SPT; j++) {
-        const uint32_t i = i0 + (uint32_t)j;
-        if (cnt[j]) {
-            const uint32_t j0 = i == 0u ? sub0 : 0u;
-            info[i] = make_uint2(32u * i - (start - j0) * bwv[j], bwv[j]);
+        const uint32_t cnt = (in && okj) ? num - j0 : 0u;
+        const uint32_t bw = sim_bw(sel);
+        const uint32_t inc = wave_incl_scan(cnt);
+        const uint32_t start = base + inc - cnt;
+        if (cnt) {
+            info[i] = make_uint2(32u * i - (start - j0) * bw, bw);
             if (start < c.ntup) sm.rec[start] = i + 1u;
         }
-        start += cnt[j];
+        base += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
     }
+    if (wave_any(bad)) return kErrSelector;
+    if (base < c.ntup) return kErrCount;
     wave_lds_sync();
     expand_records<SM::TTM>(sm.rec, info, lane);
     return 0;
@@ -1269,6 +1249,9 @@ __device__ __forceinline__ void tile_setup(const DecodeArgs &a, const ListDesc &
                                            uint32_t loc_tag, WaveSmem<TW, CLS> &sm, uint32_t lane,
                                            TileRun<TW, CLS> &t) {
     TileCtx &c = t.c;
+    // the stream's header, loaded now and compared once the prologue's own
+    // loads are under way
+    const u32x4 hd = *(const gu32x4 *)L.stream;
     const bool ok = tile_ctx(L, m, pre.s0, pre.s1, (uint32_t)TW, loc_tag, c);
     uint32_t dbase = 0, err = ok ? 0u : kErrLocate;
     t.ps = PatchSrc{sm.bmap, sm.vbit, sm.xcnt, sm.xv, ExcSrc{nullptr, nullptr, 0u, false}, false};
@@ -1302,6 +1285,10 @@ __device__ __forceinline__ void tile_setup(const DecodeArgs &a, const ListDesc &
             t.ps.in_lds = nx <= (uint32_t)SM::NXV;
             if (err) t.nint = 0u;
         }
+    }
+    if (!err && (hd.x != L.w0 || hd.y != L.n || hd.z != L.C || hd.w != L.D)) {
+        err = kErrHeader;
+        t.nint = 0u;
     }
     if (err && lane == 0) latch(a.status, err);
     t.out = L.out + c.i0;
