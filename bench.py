@@ -185,6 +185,30 @@ def cpu_baseline(parts, seconds):
                        % (lists, ints, nt, wall, one[0], one[1], one[2]))
 
 
+def cfg1_latency(gc, synth, ctx, torch, reps=30):
+    """One list of 2^20 docIDs (mean gap 16) in Group-Simple, decoded and
+    prefix-summed by gc_decode (locate, tile sums, carry scan, decode):
+    the single-list latency, timed with HIP events around each call."""
+    docs = synth.cfg1()
+    s = gc.encode(docs, gc.SIMPLE, gc.params(delta=True))
+    d_s = gc.to_device(s)
+    d_o = torch.empty(docs.size, dtype=torch.int32, device="cuda")
+    for _ in range(3):
+        ctx.decode(d_s, s.size, s[:4], d_o)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record()
+        ctx.decode(d_s, s.size, s[:4], d_o)
+        e1.record()
+    torch.cuda.synchronize()
+    us = sorted(1e3 * e0.elapsed_time(e1) for e0, e1 in ev)
+    rc, det = ctx.sync_status()
+    ok = rc == gc.OK and np.array_equal(gc.to_host(d_o), docs)
+    med = us[len(us) // 2]
+    return dict(ints=int(docs.size), bits_per_int=round(32.0 * s.size / docs.size, 3), median_us=round(med, 2),
+                min_us=round(us[0], 2), gints_s=round(docs.size / med / 1e3, 2), verified_bit_exact=bool(ok))
+
+
 def timed(plan, d_s, d_o, steps, warmup, torch):
     for _ in range(warmup):
         plan.decode_batch(d_s, d_o)
@@ -310,6 +334,8 @@ def main():
             p2.close()
             del ds2, do2
         extra["per_codec"] = per
+        extra["cfg1_latency"] = cfg1_latency(gc, synth, ctx, torch)
+        log("cfg1 single list: %s" % extra["cfg1_latency"])
 
     cpu = None
     if not args.no_cpu:

@@ -1119,22 +1119,26 @@ __device__ __forceinline__ u32x4 extract_quad(uint32_t rc, uint32_t q, uint32_t 
     return v;
 }
 
-// Copies n 16-byte chunks of data rows into the wave's LDS buffer: every
-// load is issued before the first LDS write, so the tile waits for memory
-// once.
+// Copies n 16-byte chunks of data rows into the wave's LDS buffer, four
+// loads per lane in flight at a time (all of them at 2048-integer tiles):
+// more raised the register count of the larger tiles.
 template <int N>
 __device__ __forceinline__ void stage_rows(u32x4 *dst, const gu32x4 *src, uint32_t n, uint32_t lane) {
     constexpr int PL = N / 64;
-    u32x4 t[PL];
+    constexpr int BATCH = PL < 4 ? PL : 4;   // four 16-byte loads in flight per lane
 #pragma unroll
-    for (int j = 0; j < PL; j++) {
-        const uint32_t i = (uint32_t)j * 64u + lane;
-        if (i < n) t[j] = src[i];
-    }
+    for (int j0 = 0; j0 < PL; j0 += BATCH) {
+        u32x4 t[BATCH];
 #pragma unroll
-    for (int j = 0; j < PL; j++) {
-        const uint32_t i = (uint32_t)j * 64u + lane;
-        if (i < n) dst[i] = t[j];
+        for (int j = 0; j < BATCH; j++) {
+            const uint32_t i = (uint32_t)(j0 + j) * 64u + lane;
+            if (i < n) t[j] = src[i];
+        }
+#pragma unroll
+        for (int j = 0; j < BATCH; j++) {
+            const uint32_t i = (uint32_t)(j0 + j) * 64u + lane;
+            if (i < n) dst[i] = t[j];
+        }
     }
     wave_lds_sync();
 }
@@ -1159,7 +1163,7 @@ __device__ __forceinline__ uint32_t tile_quads(const uint32_t *rec, uint32_t tsh
                                                uint32_t nrow, uint32_t nint, uint32_t lane, bool delta,
                                                uint32_t carry, uint32_t *out, bool vec, const PatchSrc &ps) {
     uint32_t s = 0;
-#pragma unroll
+#pragma unroll 4
     for (int r = 0; r < R; r++) {
         const uint32_t q = (uint32_t)r * 64u + lane;
         u32x4 v = {0u, 0u, 0u, 0u};
@@ -1195,7 +1199,7 @@ __device__ __forceinline__ uint32_t quads_lds(const uint32_t *rec, const u32x4 *
                                               uint32_t nint, uint32_t lane, uint32_t carry, uint32_t *out,
                                               bool vec, const PatchSrc &ps) {
     uint32_t s = 0;
-    constexpr int U = PATCH ? 2 : R;   // the patch branch needs registers of its own
+    constexpr int U = PATCH ? 2 : (R < 4 ? R : 4);   // deeper unrolling only raised register use
 #pragma unroll U
     for (int r = 0; r < R; r++) {
         const uint32_t q = (uint32_t)r * 64u + lane;
