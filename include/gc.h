@@ -305,6 +305,14 @@ gc_status gc_mlp_destroy(gc_mlp *model);
 gc_status gc_mlp_set_params(gc_mlp *model, const float *h_params, size_t count, void *hip_stream);
 gc_status gc_mlp_get_params(gc_mlp *model, float *h_params, size_t count, void *hip_stream);
 
+/* The whole training state, for checkpoints: h_state holds 3 *
+ * gc_mlp_param_count() floats -- the parameters, then Adam's first and
+ * second moments, in the parameter layout -- and the Adam step count goes
+ * with it.  set restores a state written by get (training then continues
+ * exactly as it would have).  Both return when the copies are done.        */
+gc_status gc_mlp_get_state(gc_mlp *model, float *h_state, size_t count, uint64_t *h_step, void *hip_stream);
+gc_status gc_mlp_set_state(gc_mlp *model, const float *h_state, size_t count, uint64_t step, void *hip_stream);
+
 /* Scores of n feature rows (device, n x 40): logits to d_logits (n x 16,
  * may be NULL) and the class of the largest logit (the smaller class on
  * ties) to d_class (may be NULL).  Asynchronous.                            */

@@ -1085,6 +1085,35 @@ gc_status gc_mlp_get_params(gc_mlp *m, float *h_theta, size_t count, void *hip_s
     return GC_OK;
 }
 
+gc_status gc_mlp_get_state(gc_mlp *m, float *h_state, size_t count, uint64_t *h_step, void *hip_stream) {
+    const size_t P = gcmlp::kParams;
+    if (!m || !h_state || !h_step || count != 3 * P) return GC_EINVAL;
+    (void)hipSetDevice(m->device);
+    std::lock_guard<std::mutex> lk(m->mu);
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIP_OK(hipMemcpyAsync(h_state, m->theta, P * 4, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(h_state + P, m->m, P * 4, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(h_state + 2 * P, m->v, P * 4, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    *h_step = m->step;
+    return GC_OK;
+}
+
+gc_status gc_mlp_set_state(gc_mlp *m, const float *h_state, size_t count, uint64_t step, void *hip_stream) {
+    const size_t P = gcmlp::kParams;
+    if (!m || !h_state || count != 3 * P) return GC_EINVAL;
+    (void)hipSetDevice(m->device);
+    std::lock_guard<std::mutex> lk(m->mu);
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIP_OK(hipMemcpyAsync(m->theta, h_state, P * 4, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(m->m, h_state + P, P * 4, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(m->v, h_state + 2 * P, P * 4, hipMemcpyHostToDevice, s));
+    if (gcmlp::launch_pack(m->theta, m->w, s)) return GC_EDEVICE;
+    HIP_OK(hipStreamSynchronize(s));
+    m->step = step;
+    return GC_OK;
+}
+
 gc_status gc_mlp_forward(gc_mlp *m, const float *d_feat, size_t n, float *d_logits, uint8_t *d_class,
                          void *hip_stream) {
     if (!m || (n && !d_feat) || n > 0xFFFFFFFFull) return GC_EINVAL;

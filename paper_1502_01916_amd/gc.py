@@ -123,6 +123,8 @@ def lib():
         L.gc_mlp_set_params.argtypes = [vp, f32p, sz, vp]
         L.gc_mlp_get_params.argtypes = [vp, f32p, sz, vp]
         L.gc_mlp_forward.argtypes = [vp, vp, sz, vp, vp, vp]
+        L.gc_mlp_get_state.argtypes = [vp, f32p, sz, ctypes.POINTER(ctypes.c_uint64), vp]
+        L.gc_mlp_set_state.argtypes = [vp, f32p, sz, ctypes.c_uint64, vp]
         L.gc_mlp_grad.argtypes = [vp, vp, vp, vp, vp, ctypes.c_uint32, ctypes.c_float, vp, vp, vp]
         L.gc_mlp_train.argtypes = [vp, vp, vp, vp, vp, sz, ctypes.POINTER(AdamOpts), vp, vp]
         L.gc_encode_blocks.argtypes = [vp, vp, sz, i, vp, ctypes.c_uint32, vp, sz, ctypes.POINTER(sz), vp, vp]
@@ -130,7 +132,8 @@ def lib():
                   "gc_plan_create", "gc_plan_destroy", "gc_decode_batch", "gc_decode_each",
                   "gc_plan_config", "gc_sync_status", "gc_block_features", "gc_block_sizes",
                   "gc_blockmix_encode", "gc_mlp_create", "gc_mlp_destroy", "gc_mlp_set_params",
-                  "gc_mlp_get_params", "gc_mlp_forward", "gc_mlp_grad", "gc_mlp_train", "gc_encode_blocks"):
+                  "gc_mlp_get_params", "gc_mlp_forward", "gc_mlp_grad", "gc_mlp_train", "gc_encode_blocks",
+                  "gc_mlp_get_state", "gc_mlp_set_state"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
         return L
@@ -391,6 +394,20 @@ class Mlp:
         _check("gc_mlp_get_params", lib().gc_mlp_get_params(
             self._h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), t.size, _stream_handle(stream)))
         return t
+
+    def get_state(self, stream=None):
+        """(state floats [3 * params]: parameters, Adam m, Adam v; step)."""
+        st = np.zeros(3 * self.param_count(), np.float32)
+        step = ctypes.c_uint64()
+        _check("gc_mlp_get_state", lib().gc_mlp_get_state(
+            self._h, st.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), st.size, ctypes.byref(step),
+            _stream_handle(stream)))
+        return st, int(step.value)
+
+    def set_state(self, state, step, stream=None):
+        st = np.ascontiguousarray(state, dtype=np.float32)
+        _check("gc_mlp_set_state", lib().gc_mlp_set_state(
+            self._h, st.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), st.size, int(step), _stream_handle(stream)))
 
     def forward(self, d_feat, n, d_logits=None, d_class=None, stream=None):
         _check("gc_mlp_forward", lib().gc_mlp_forward(self._h, _ptr(d_feat), int(n), _opt(d_logits),

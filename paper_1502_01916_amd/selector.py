@@ -65,6 +65,23 @@ def train(ctx: gc.Context, t: Targets, epochs=30, batch=4096, lr=3e-3, lr_final=
     return model, per_epoch, secs
 
 
+def save(model: gc.Mlp, path: str):
+    """Checkpoint of the network and its Adam state (numpy .npz, no pickles)."""
+    state, step = model.get_state()
+    np.savez(path, state=state, step=np.uint64(step), params=np.uint64(gc.Mlp.param_count()),
+             layout=np.array([40, 64, 64, 16], np.int32))
+
+
+def load(ctx: gc.Context, path: str, max_batch=4096) -> gc.Mlp:
+    """A network restored from save(); training continues where it stopped."""
+    with np.load(path, allow_pickle=False) as z:
+        if int(z["params"]) != gc.Mlp.param_count() or list(z["layout"]) != [40, 64, 64, 16]:
+            raise ValueError("checkpoint of another network layout")
+        model = gc.Mlp(ctx, max_batch)
+        model.set_state(z["state"], int(z["step"]))
+    return model
+
+
 def encode(ctx: gc.Context, d_in, n: int, mode: int, model: gc.Mlp | None = None, fixed_class=0,
            with_classes=False):
     """The container of the first n integers of d_in (padded to whole

@@ -184,3 +184,33 @@ def test_training_lowers_loss(torch_cuda, ctx):
     l = d_l.cpu().numpy()
     assert np.all(np.isfinite(l))
     assert l[-steps:].mean() < 0.6 * l[:steps].mean(), (l[:steps].mean(), l[-steps:].mean())
+
+
+def test_checkpoint_resume(torch_cuda, ctx, tmp_path):
+    """Training resumed from a checkpoint continues exactly as uninterrupted
+    training (the kernels are deterministic)."""
+    torch = torch_cuda
+    from paper_1502_01916_amd import selector
+    say("mlp checkpoint resume")
+    nb = 2048
+    x = blocks(23, nb)
+    d_in = gc.to_device(x.reshape(-1))
+    T = selector.Targets(ctx, d_in, nb)
+    perms = [torch.from_numpy(np.random.default_rng(e).permutation(nb).astype(np.int32)).cuda() for e in range(4)]
+    opts = gc.adam_opts(lr=3e-3, lam=4.0, batch=256)
+    a = gc.Mlp(ctx, 256)
+    a.set_params(M.init_params(5))
+    for e in range(2):
+        a.train(T.feat, T.best, nb, opts, d_cost=T.cost, d_index=perms[e])
+    path = str(tmp_path / "ckpt.npz")
+    selector.save(a, path)
+    b = selector.load(ctx, path, 256)
+    assert b.get_state()[1] == a.get_state()[1] == 2 * (nb // 256)
+    for e in range(2, 4):
+        a.train(T.feat, T.best, nb, opts, d_cost=T.cost, d_index=perms[e])
+        b.train(T.feat, T.best, nb, opts, d_cost=T.cost, d_index=perms[e])
+    sa, sb = a.get_state(), b.get_state()
+    assert sa[1] == sb[1]
+    assert np.array_equal(sa[0], sb[0])
+    a.close()
+    b.close()
