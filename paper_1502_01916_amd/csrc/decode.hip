@@ -124,12 +124,6 @@ __device__ __forceinline__ uint32_t pfd_exc_words(uint32_t desc, int k, int bitm
     return bitmap ? 1u + ((first * (uint32_t)k + 31u) >> 5) + vals : vals;
 }
 
-__device__ __forceinline__ bool header_ok(const ListDesc &L, uint32_t w0, uint32_t n, uint32_t C,
-                                          uint32_t D, HeaderFields &h) {
-    if (w0 != L.w0 || C != L.C || D != L.D || !header_fields(w0, h)) return false;
-    if (n != L.n || (C & 3u) != 0u || (D & (uint32_t)(h.k - 1)) != 0u) return false;
-    return 4ull + C + D <= L.stream_words;
-}
 
 // ===========================================================================
 // Locate kernels: reduce -> scan -> emit.
@@ -158,10 +152,13 @@ struct LocThread {
     uint32_t vt, ve, vd;
 };
 
+// The header comes from the host's copy in the list descriptor (validated
+// when the plan was made): the decode tiles compare the stream's own header
+// with it, so the locate pass does not wait for that load.
 __device__ __forceinline__ void locate_thread(const ListDesc &L, uint32_t chunk, LocThread &t) {
     const uint32_t *S = L.stream;
-    const uint32_t w0 = S[0], n = S[1], C = S[2], D = S[3];
-    t.ok = header_ok(L, w0, n, C, D, t.h);
+    const uint32_t n = L.n, C = L.C, D = L.D;
+    t.ok = header_fields(L.w0, t.h);
     t.k = (uint32_t)t.h.k;
     t.T = t.ok ? (n + t.k - 1u) >> t.h.lk : 0u;
     t.TT = L.tile_ints >> t.h.lk;
