@@ -233,12 +233,24 @@ __device__ __forceinline__ void locate_thread(const ListDesc &L, uint32_t chunk,
     }
 }
 
+// The list and chunk of a locate work item.  Loaded through global-address
+// pointers before the kernel stores anything, so the wave-uniform loads
+// stay scalar.
 __device__ __forceinline__ bool locate_item(const LocateArgs &a, uint32_t item, ListDesc &L, uint32_t &chunk,
                                             uint32_t &list) {
     if (item >= a.total_items) return false;
     if (a.lists) {
-        list = a.item_list[a.item_lo + item];
-        L = a.lists[list];
+        list = ((const gu32 *)a.item_list)[a.item_lo + item];
+        const gu32x4 *g = (const gu32x4 *)(a.lists + list);
+        union {
+            u32x4 v[4];
+            ListDesc d;
+        } u;
+        u.v[0] = g[0];
+        u.v[1] = g[1];
+        u.v[2] = g[2];
+        u.v[3] = g[3];
+        L = u.d;
         chunk = a.item_lo + item - L.chunk_base;
     } else {
         L = a.single;
@@ -270,26 +282,28 @@ __device__ __forceinline__ void block_sum3(uint32_t &x, uint32_t &y, uint32_t &z
 // Aggregate of every control chunk.
 __global__ __launch_bounds__(kThreads) void gc_locate_reduce(LocateArgs a) {
     __shared__ uint32_t s_tmp[3][kWaves];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        // a new locate run: later kernels of this launch sequence tag and
-        // check tile starts with the advanced epoch
-        const uint32_t e = __hip_atomic_load(&a.state->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&a.state->epoch, epoch_next(e), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
     ListDesc L;
     uint32_t chunk, list;
-    if (!locate_item(a, blockIdx.x, L, chunk, list)) return;
-    LocThread t;
-    locate_thread(L, chunk, t);
-    uint32_t tt = t.vt, te = t.ve, td = t.vd;
-    block_sum3(tt, te, td, s_tmp);
-    if (t.bad) latch(a.status, kErrLocate);
-    if (threadIdx.x == 0) {
-        LocVal v;
-        v.tup = tt;
-        v.exc = te;
-        v.data = td;
-        a.agg[L.chunk_base + chunk] = v;
+    if (locate_item(a, blockIdx.x, L, chunk, list)) {
+        LocThread t;
+        locate_thread(L, chunk, t);
+        uint32_t tt = t.vt, te = t.ve, td = t.vd;
+        block_sum3(tt, te, td, s_tmp);
+        if (t.bad) latch(a.status, kErrLocate);
+        if (threadIdx.x == 0) {
+            LocVal v;
+            v.tup = tt;
+            v.exc = te;
+            v.data = td;
+            a.agg[L.chunk_base + chunk] = v;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // a new locate run: later kernels of this launch sequence tag and
+        // check tile starts with the advanced epoch (stored last, so the
+        // loads above stay scalar)
+        const uint32_t e = __hip_atomic_load(&a.state->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.state->epoch, epoch_next(e), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -326,10 +340,10 @@ __global__ __launch_bounds__(kThreads) void gc_locate_scan(LocateArgs a) {
 // Tile starts from the chunk prefixes, tagged with this run's epoch.
 __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
     __shared__ uint32_t s_tmp[kWaves];
-    const uint32_t epoch = __hip_atomic_load(&a.state->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     ListDesc L;
     uint32_t chunk, list;
     if (locate_item(a, blockIdx.x, L, chunk, list)) {
+        const uint32_t epoch = *(const gu32 *)&a.state->epoch;   // advanced by the reduce kernel
         LocThread t;
         locate_thread(L, chunk, t);
         uint32_t tt, te, td;
