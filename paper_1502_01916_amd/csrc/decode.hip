@@ -1337,6 +1337,9 @@ __device__ void wave_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, ui
                           uint32_t loc_tag, WaveSmem<TW, CLS> &sm, uint32_t lane) {
     constexpr int R = TW / 256;
     constexpr bool PATCH = CLS == kClsPfd;
+    // no carry needs the sum of a list's last tile
+    if constexpr (MODE == kModeSum)
+        if (m + 1u >= L.ntiles) return;
     TileRun<TW, CLS> t;
     tile_setup<TW, CLS>(a, L, m, pre, loc_tag, sm, lane, t);
     if constexpr (MODE == kModeSum) {
@@ -1379,7 +1382,8 @@ __global__ __launch_bounds__(kThreads) void gc_wave_kernel(DecodeArgs a) {
 
 // ===========================================================================
 // Carry scan: the tile sums of one delta list become exclusive carries, in
-// place, 1024 tiles per round.
+// place, 1024 tiles per round (the last tile's sum is never read: the sum
+// pass skips it).
 
 __global__ __launch_bounds__(kThreads) void gc_carry_scan(CarryArgs a) {
     __shared__ uint32_t s_tmp[kWaves];
@@ -1391,7 +1395,7 @@ __global__ __launch_bounds__(kThreads) void gc_carry_scan(CarryArgs a) {
         const uint32_t i = b + 4u * threadIdx.x;
         uint32_t v[4];
 #pragma unroll
-        for (int j = 0; j < 4; j++) v[j] = i + j < L.ntiles ? cy[i + j] : 0u;
+        for (int j = 0; j < 4; j++) v[j] = i + j + 1u < L.ntiles ? cy[i + j] : 0u;   // no tile follows the last
         uint32_t total;
         uint32_t p = run + block_excl_scan(v[0] + v[1] + v[2] + v[3], s_tmp, total);
 #pragma unroll
