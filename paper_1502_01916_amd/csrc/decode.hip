@@ -434,7 +434,10 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
                         const uint32_t byte = (wd >> (8 * i)) & 0xFFu;
                         const uint32_t b = byte & 63u, F = 8u << (byte >> 6);
                         uint32_t m;
-                        if (boundary(base_t, F, m)) emit(m, 4u * w + (uint32_t)i, m * TT - base_t, base_d, 0);
+                        if (boundary(base_t, F, m)) {
+                            const uint32_t sub = m * TT - base_t;
+                            emit(m, 4u * w + (uint32_t)i, sub, base_d + (uint64_t)sub * b, 0);
+                        }
                         base_t += F;
                         base_d += (uint64_t)F * b;
                     }
@@ -849,8 +852,10 @@ __device__ uint32_t wprologue_afor(const TileCtx &c, WaveSmem<TW, kClsAfor> &sm,
     if (wave_any(bad)) return kErrFrame;
     if (tc < c.ntup) return kErrCount;
     const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)bb[0]);   // frame f0 is lane 0's first
-    const uint64_t fdata0 = c.st.data;
-    dbase = (uint32_t)((fdata0 + (uint64_t)sub0 * b0) >> 5);
+    // the tile start holds the bit offset of its first tuple, sub0 tuples into frame f0
+    if ((uint64_t)sub0 * b0 > c.st.data) return kErrFrame;
+    const uint64_t fdata0 = c.st.data - (uint64_t)sub0 * b0;
+    dbase = (uint32_t)(c.st.data >> 5);
     const uint32_t frel0 = (uint32_t)(fdata0 - 32ull * dbase);
     // frame i of the tile marks its first tuple with i + 1 and records
     // {base, b} with base + t * b the bit offset of tile tuple t of it
@@ -1259,15 +1264,54 @@ struct TileRun {
     bool staged, vec;
 };
 
+// Data rows [r0, r1) of a tile, from the tile starts at its two ends (a
+// list's last tile runs to the end of the data area).
+template <int CLS>
+__device__ __forceinline__ void tile_rows(const TileCtx &c, uint32_t Dk, uint32_t &r0, uint32_t &r1) {
+    if constexpr (CLS == kClsSim) {   // one row per selector
+        r0 = c.st.unit;
+        r1 = c.has_en ? c.en.unit + (c.en.sub ? 1u : 0u) : Dk;
+    } else {
+        r0 = (uint32_t)min(c.st.data >> 5, (uint64_t)Dk);
+        r1 = c.has_en ? (uint32_t)min((c.en.data + 31u) >> 5, (uint64_t)Dk) : Dk;
+    }
+    r1 = min(r1, Dk);
+}
+
 template <int TW, int CLS>
 __device__ __forceinline__ void tile_setup(const DecodeArgs &a, const ListDesc &L, uint32_t m, const TilePre &pre,
                                            uint32_t loc_tag, WaveSmem<TW, CLS> &sm, uint32_t lane,
                                            TileRun<TW, CLS> &t) {
+    using SM = WaveSmem<TW, CLS>;
     TileCtx &c = t.c;
     // the stream's header, loaded now and compared once the prologue's own
     // loads are under way
     const u32x4 hd = *(const gu32x4 *)L.stream;
     const bool ok = tile_ctx(L, m, pre.s0, pre.s1, (uint32_t)TW, loc_tag, c);
+    // The data rows are loaded into registers before the prologue reads the
+    // control words, so that the two loads wait together; they go to LDS
+    // once the prologue no longer needs it.  Tiles whose rows do not fit
+    // the registers (or whose records end past them) stage after the
+    // prologue instead.
+    constexpr int EV = SM::NDATA / 64;
+    constexpr bool EARLY = EV <= 4;
+    const uint32_t Dk = c.D >> c.lk;
+    uint32_t r0 = 0, r1 = 0;
+    tile_rows<CLS>(c, Dk, r0, r1);
+    const uint32_t nch = r1 >= r0 ? (r1 - r0) * (c.k >> 2) : 0u;
+    const bool early = EARLY && ok && r1 >= r0 && nch <= (uint32_t)SM::NDATA;
+    u32x4 ev[EARLY ? EV : 1];
+    if constexpr (EARLY) {
+        // unconditional loads (no branch between them and their wait):
+        // lanes past the rows, and every lane of a tile that does not load
+        // early, read the stream's header instead
+        const gu32x4 *g = early ? (const gu32x4 *)c.data + (size_t)r0 * (c.k >> 2) : (const gu32x4 *)L.stream;
+#pragma unroll
+        for (int v = 0; v < EV; v++) {
+            const uint32_t i = (uint32_t)v * 64u + lane;
+            ev[v] = g[early && i < nch ? i : 0u];
+        }
+    }
     uint32_t dbase = 0, err = ok ? 0u : kErrLocate;
     t.ps = PatchSrc{sm.bmap, sm.vbit, sm.xcnt, sm.xv, ExcSrc{nullptr, nullptr, 0u, false}, false};
     if (!err) {
@@ -1277,8 +1321,6 @@ __device__ __forceinline__ void tile_setup(const DecodeArgs &a, const ListDesc &
         else if constexpr (CLS == kClsAfor) err = wprologue_afor<TW>(c, sm, lane, dbase);
         else err = wprologue_pfd<TW>(c, sm, lane, dbase, L.stream_words, t.ps.xs);
     }
-    using SM = WaveSmem<TW, CLS>;
-    const uint32_t Dk = c.D >> c.lk;
     t.nrow = Dk > dbase ? Dk - dbase : 0u;
     t.kq = c.k >> 2;
     t.rows = reinterpret_cast<const u32x4 *>(c.data) + (size_t)dbase * t.kq;
@@ -1291,7 +1333,18 @@ __device__ __forceinline__ void tile_setup(const DecodeArgs &a, const ListDesc &
         span = min(t.nrow, ((lr >> 6) + (lr & 63u) + 31u) >> 5);
     }
     t.staged = span * t.kq <= (uint32_t)SM::NDATA;
-    if (t.staged && span) stage_rows<SM::NDATA>(sm.data, (const gu32x4 *)t.rows, span * t.kq, lane);
+    if (t.staged && span) {
+        if (EARLY && early && dbase == r0 && span * t.kq <= nch) {
+#pragma unroll
+            for (int v = 0; v < (EARLY ? EV : 1); v++) {
+                const uint32_t i = (uint32_t)v * 64u + lane;
+                if (i < nch) sm.data[i] = ev[v];
+            }
+            wave_lds_sync();
+        } else {
+            stage_rows<SM::NDATA>(sm.data, (const gu32x4 *)t.rows, span * t.kq, lane);
+        }
+    }
     if constexpr (CLS == kClsPfd) {
         if (!err) {
             uint32_t nx = 0;

@@ -33,7 +33,7 @@ struct TileInfo {
     uint32_t sub;     // tuples of that unit that belong to the previous tile
     uint32_t exc;     // Group-PFD: exception-area word offset of the unit
     uint32_t tag;     // epoch of the locate run that wrote this entry
-    uint64_t data;    // component bit offset of the unit (Group-Scheme: of the tuple)
+    uint64_t data;    // component bit offset of the unit (Group-Scheme, Group-AFOR: of the tile's first tuple)
     uint32_t list;    // batch: the tile's list (tile 0 of a list: set by the host)
     uint32_t pad;
 };
