@@ -573,19 +573,33 @@ struct WaveSmem {
         u32x4 data[NB];
         uint32_t ctrl[4 * NB];
     };
-    uint32_t rec[TTM + 4];   // + room for one more entry while the records are built
+    // tuple records (Group-PFD computes them from its block words instead)
+    uint32_t rec[CLS == kClsPfd ? 4 : TTM + 4];   // + room for one more entry while the records are built
     // Group-PFD only: block descriptors, data row and exception word offsets
-    // of the tile's blocks; the exception bitmap of the tile's integers, per
-    // bitmap word the exceptions before it (tile-wide) and the bit offset |
-    // width code of its first exception value; staged exception words
+    // of the tile's blocks and their record words (row offset | width); the
+    // exception bitmap of the tile's integers, per bitmap word the
+    // exceptions before it (tile-wide) and the bit offset | width code of
+    // its first exception value.  The tile's exception words and its
+    // exception values in tile order go to the data buffer after the rows,
+    // when they fit there.
     static constexpr int NBLK = CLS == kClsPfd ? TW / 128 : 1;
     static constexpr int NBM = CLS == kClsPfd ? TW / 32 : 1;
-    static constexpr int NX = CLS == kClsPfd ? TW / 8 : 1;
-    static constexpr int NXV = CLS == kClsPfd ? TW / 8 : 1;
-    uint32_t bdesc[NBLK], brow[NBLK], bxw[NBLK];
+    uint32_t bdesc[NBLK], brow[NBLK], bxw[NBLK], brec[NBLK];
     uint32_t bmap[NBM], xcnt[NBM], vbit[NBM];
-    uint32_t xw[NX];
-    uint32_t xv[NXV];   // exception values in tile order, when they fit
+};
+
+// Record of tuple t (bit offset << 6 | width): from the record array, or,
+// for a Group-PFD tile, from the record word of its 32-tuple block.
+struct RecArr {
+    const uint32_t *rec;
+    __device__ __forceinline__ uint32_t operator()(uint32_t t) const { return rec[t]; }
+};
+struct RecBlk {
+    const uint32_t *brec;
+    __device__ __forceinline__ uint32_t operator()(uint32_t t) const {
+        const uint32_t w = brec[t >> 5], b = w & 63u;
+        return (((w >> 6) << 11) + (((t & 31u) * b) << 6)) | b;
+    }
 };
 
 
@@ -906,7 +920,6 @@ struct ExcSrc {
 template <int TW>
 __device__ uint32_t wprologue_pfd(const TileCtx &c, WaveSmem<TW, kClsPfd> &sm, uint32_t lane, uint32_t &dbase,
                                   uint64_t stream_words, ExcSrc &xs) {
-    using SM = WaveSmem<TW, kClsPfd>;
     const uint32_t k = c.k;
     const uint32_t nb = (c.ntup + 31u) >> 5;   // <= NBLK <= 32
     const uint32_t beta0 = c.t0 >> 5;
@@ -937,28 +950,22 @@ __device__ uint32_t wprologue_pfd(const TileCtx &c, WaveSmem<TW, kClsPfd> &sm, u
         sm.bdesc[lane] = desc;
         sm.brow[lane] = ib - b;
         sm.bxw[lane] = ie - ew;
+        sm.brec[lane] = ((ib - b) << 6) | b;
     }
     dbase = (uint32_t)(c.st.data >> 5);
     const uint64_t ex0 = 4ull + c.C + c.D + c.st.exc;
     if (ex0 + xwords > stream_words) return kErrRange;
-    xs.lds = sm.xw;
+    xs.lds = nullptr;   // staged by the tile set-up when they fit
     xs.g = (const gu32 *)c.S + ex0;
     xs.n = xwords;
-    xs.staged = xwords <= (uint32_t)SM::NX;
-    if (xs.staged)
-        for (uint32_t i = lane; i < xwords; i += 64u) sm.xw[i] = xs.g[i];
-    wave_lds_sync();
-    for (uint32_t t = lane; t < c.ntup; t += 64u) {
-        const uint32_t j = t >> 5, bj = sm.bdesc[j] & 63u;
-        sm.rec[t] = rec_pack(32u * sm.brow[j] + (t & 31u) * bj, bj);
-    }
+    xs.staged = false;
     wave_lds_sync();
     return 0;
 }
 
 template <int TW, typename W>
 __device__ uint32_t pfd_marks(const TileCtx &c, WaveSmem<TW, kClsPfd> &sm, uint32_t lane, W rows, uint32_t nrow,
-                              const ExcSrc &xs, uint32_t &nexc_tile) {
+                              const ExcSrc &xs, uint32_t *xv, uint32_t xv_cap, uint32_t &nexc_tile) {
     const uint32_t k = c.k, lk = c.lk;
     const uint32_t nb = (c.ntup + 31u) >> 5;
     const uint32_t BI = 32u * k;        // positions per block
@@ -1061,11 +1068,11 @@ __device__ uint32_t pfd_marks(const TileCtx &c, WaveSmem<TW, kClsPfd> &sm, uint3
         const uint32_t ewb = 4u << wcode;
         sm.vbit[w] = ((32u * vb + before * ewb) << 2) | wcode;
         // the word's exception values, in order, to xv when the tile's fit
-        if (run <= (uint32_t)WaveSmem<TW, kClsPfd>::NXV) {
+        if (run <= xv_cap) {
             uint32_t bm = sm.bmap[w], r = sm.xcnt[w], bit = 32u * vb + before * ewb;
             const uint32_t M = mask_of(ewb);
             while (bm) {
-                sm.xv[r++] = (xs.at(bit >> 5) >> (bit & 31u)) & M;
+                xv[r++] = (xs.at(bit >> 5) >> (bit & 31u)) & M;
                 bit += ewb;
                 bm &= bm - 1u;
             }
@@ -1174,8 +1181,8 @@ __device__ __forceinline__ void store_quad(uint32_t *out, uint32_t ii, uint32_t 
 // Sums (SUM) or writes the tile's integers: lane l handles quads l, l + 64,
 // ...; a delta tile is scanned in-lane, across the wave with DPP, and from
 // the carry of the previous rounds.
-template <int R, bool SUM, bool PATCH, typename RowPtr>
-__device__ __forceinline__ uint32_t tile_quads(const uint32_t *rec, uint32_t tsh, uint32_t kq, RowPtr rows,
+template <int R, bool SUM, bool PATCH, typename Rec, typename RowPtr>
+__device__ __forceinline__ uint32_t tile_quads(Rec rec, uint32_t tsh, uint32_t kq, RowPtr rows,
                                                uint32_t nrow, uint32_t nint, uint32_t lane, bool delta,
                                                uint32_t carry, uint32_t *out, bool vec, const PatchSrc &ps) {
     uint32_t s = 0;
@@ -1184,7 +1191,7 @@ __device__ __forceinline__ uint32_t tile_quads(const uint32_t *rec, uint32_t tsh
         const uint32_t q = (uint32_t)r * 64u + lane;
         u32x4 v = {0u, 0u, 0u, 0u};
         if (4u * q < nint) {
-            v = extract_quad(rec[q >> tsh], q, kq, rows, nrow);
+            v = extract_quad(rec(q >> tsh), q, kq, rows, nrow);
             if constexpr (PATCH) pfd_patch(v, q, ps);
         }
         if constexpr (SUM) {
@@ -1210,8 +1217,8 @@ __device__ __forceinline__ uint32_t tile_quads(const uint32_t *rec, uint32_t tsh
 // the carry of the earlier rounds).  FULL: a whole tile with a 16-byte
 // aligned output, so no quad needs a bounds check.  Rows are read without a
 // clamp: the row after the last holds padding, and its bits are masked off.
-template <int R, bool SUM, bool FULL, bool DELTA, bool PATCH>
-__device__ __forceinline__ uint32_t quads_lds(const uint32_t *rec, const u32x4 *data, uint32_t tsh, uint32_t kq,
+template <int R, bool SUM, bool FULL, bool DELTA, bool PATCH, typename Rec>
+__device__ __forceinline__ uint32_t quads_lds(Rec rec, const u32x4 *data, uint32_t tsh, uint32_t kq,
                                               uint32_t nint, uint32_t lane, uint32_t carry, uint32_t *out,
                                               bool vec, const PatchSrc &ps) {
     uint32_t s = 0;
@@ -1219,7 +1226,7 @@ __device__ __forceinline__ uint32_t quads_lds(const uint32_t *rec, const u32x4 *
 #pragma unroll U
     for (int r = 0; r < R; r++) {
         const uint32_t q = (uint32_t)r * 64u + lane;
-        uint32_t rc = rec[q >> tsh];
+        uint32_t rc = rec(q >> tsh);
         if constexpr (!FULL) rc = 4u * q < nint ? rc : 0u;
         const uint32_t O = rc >> 6, bw = rc & 63u, sh = O & 31u;
         const uint32_t idx = (O >> 5) * kq + (q & (kq - 1u));
@@ -1263,6 +1270,12 @@ struct TileRun {
     uint32_t nint, nrow, kq, tsh;
     bool staged, vec;
 };
+
+template <int TW, int CLS>
+__device__ __forceinline__ auto tile_recs(const WaveSmem<TW, CLS> &sm) {
+    if constexpr (CLS == kClsPfd) return RecBlk{sm.brec};
+    else return RecArr{sm.rec};
+}
 
 // Data rows [r0, r1) of a tile, from the tile starts at its two ends (a
 // list's last tile runs to the end of the data area).
@@ -1312,8 +1325,25 @@ __device__ __forceinline__ void tile_setup(const DecodeArgs &a, const ListDesc &
             ev[v] = g[early && i < nch ? i : 0u];
         }
     }
+    // Group-PFD: the tile's exception words likewise (the tile starts give
+    // their range; the last tile's run to the end of the stream)
+    constexpr int XE = CLS == kClsPfd ? 4 : 1;   // words per lane
+    uint32_t xe[XE];
+    uint32_t xn = 0;
+    if constexpr (CLS == kClsPfd) {
+        const uint64_t ex0 = 4ull + c.C + c.D + c.st.exc;
+        const uint64_t ex1 = c.has_en ? 4ull + c.C + c.D + c.en.exc : L.stream_words;
+        const bool xok = ok && ex0 <= ex1 && ex1 <= L.stream_words && ex1 - ex0 <= 64ull * XE;
+        xn = xok ? (uint32_t)(ex1 - ex0) : 0u;
+        const gu32 *g = xok ? (const gu32 *)c.S + ex0 : (const gu32 *)L.stream;
+#pragma unroll
+        for (int v = 0; v < XE; v++) {
+            const uint32_t i = (uint32_t)v * 64u + lane;
+            xe[v] = g[i < xn ? i : 0u];
+        }
+    }
     uint32_t dbase = 0, err = ok ? 0u : kErrLocate;
-    t.ps = PatchSrc{sm.bmap, sm.vbit, sm.xcnt, sm.xv, ExcSrc{nullptr, nullptr, 0u, false}, false};
+    t.ps = PatchSrc{sm.bmap, sm.vbit, sm.xcnt, nullptr, ExcSrc{nullptr, nullptr, 0u, false}, false};
     if (!err) {
         if constexpr (CLS == kClsSim) err = wprologue_sim<TW>(c, sm, lane, dbase);
         else if constexpr (CLS == kClsGscU) err = wprologue_gscu<TW>(c, sm, lane, dbase);
@@ -1329,10 +1359,11 @@ __device__ __forceinline__ void tile_setup(const DecodeArgs &a, const ListDesc &
     // the tile's data rows end with its last record (offsets grow with the tuple)
     uint32_t span = 0;
     if (t.nint) {
-        const uint32_t lr = sm.rec[c.ntup - 1u];
+        const uint32_t lr = tile_recs(sm)(c.ntup - 1u);
         span = min(t.nrow, ((lr >> 6) + (lr & 63u) + 31u) >> 5);
     }
     t.staged = span * t.kq <= (uint32_t)SM::NDATA;
+    bool wrote = false;
     if (t.staged && span) {
         if (EARLY && early && dbase == r0 && span * t.kq <= nch) {
 #pragma unroll
@@ -1340,19 +1371,41 @@ __device__ __forceinline__ void tile_setup(const DecodeArgs &a, const ListDesc &
                 const uint32_t i = (uint32_t)v * 64u + lane;
                 if (i < nch) sm.data[i] = ev[v];
             }
-            wave_lds_sync();
+            wrote = true;
         } else {
             stage_rows<SM::NDATA>(sm.data, (const gu32x4 *)t.rows, span * t.kq, lane);
         }
     }
     if constexpr (CLS == kClsPfd) {
+        // after the staged rows: the exception words, then the values in tile order
+        uint32_t *buf = reinterpret_cast<uint32_t *>(sm.data);
+        constexpr uint32_t kBufWords = 4u * (uint32_t)SM::NB;
+        uint32_t used = t.staged ? 4u * span * t.kq : 0u;
+        ExcSrc &xs = t.ps.xs;
+        if (!err && xs.n <= xn && used + xs.n <= kBufWords) {
+#pragma unroll
+            for (int v = 0; v < XE; v++) {
+                const uint32_t i = (uint32_t)v * 64u + lane;
+                if (i < xs.n) buf[used + i] = xe[v];
+            }
+            xs.lds = buf + used;
+            xs.staged = true;
+            used += xs.n;
+            wrote = true;
+        }
+        if (wrote) wave_lds_sync();
         if (!err) {
             uint32_t nx = 0;
-            err = t.staged ? pfd_marks<TW>(c, sm, lane, reinterpret_cast<const uint32_t *>(sm.data), span, t.ps.xs, nx)
-                           : pfd_marks<TW>(c, sm, lane, (const gu32 *)t.rows, t.nrow, t.ps.xs, nx);
-            t.ps.in_lds = nx <= (uint32_t)SM::NXV;
+            t.ps.xv = buf + used;
+            const uint32_t cap = kBufWords - used;
+            err = t.staged ? pfd_marks<TW>(c, sm, lane, reinterpret_cast<const uint32_t *>(sm.data), span, xs,
+                                           buf + used, cap, nx)
+                           : pfd_marks<TW>(c, sm, lane, (const gu32 *)t.rows, t.nrow, xs, buf + used, cap, nx);
+            t.ps.in_lds = nx <= cap;
             if (err) t.nint = 0u;
         }
+    } else {
+        if (wrote) wave_lds_sync();
     }
     if (!err && (hd.x != L.w0 || hd.y != L.n || hd.z != L.C || hd.w != L.D)) {
         err = kErrHeader;
@@ -1371,11 +1424,11 @@ __device__ __forceinline__ uint32_t tile_total(const TileRun<TW, CLS> &t, WaveSm
     uint32_t s;
     if (t.staged) {
         s = (t.nint == (uint32_t)TW && t.vec)
-                ? quads_lds<R, true, true, true, PATCH>(sm.rec, sm.data, t.tsh, t.kq, t.nint, lane, 0u, t.out, t.vec, t.ps)
-                : quads_lds<R, true, false, true, PATCH>(sm.rec, sm.data, t.tsh, t.kq, t.nint, lane, 0u, t.out, t.vec,
+                ? quads_lds<R, true, true, true, PATCH>(tile_recs(sm), sm.data, t.tsh, t.kq, t.nint, lane, 0u, t.out, t.vec, t.ps)
+                : quads_lds<R, true, false, true, PATCH>(tile_recs(sm), sm.data, t.tsh, t.kq, t.nint, lane, 0u, t.out, t.vec,
                                                          t.ps);
     } else {
-        s = tile_quads<R, true, PATCH>(sm.rec, t.tsh, t.kq, t.rows, t.nrow, t.nint, lane, false, 0u, t.out, t.vec,
+        s = tile_quads<R, true, PATCH>(tile_recs(sm), t.tsh, t.kq, t.rows, t.nrow, t.nint, lane, false, 0u, t.out, t.vec,
                                        t.ps);
     }
     return wave_sum(s);
@@ -1408,14 +1461,14 @@ __device__ void wave_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, ui
         const u32x4 *d = sm.data;
         const bool full = nint == (uint32_t)TW && t.vec;
         if (t.c.h.delta) {
-            if (full) quads_lds<R, false, true, true, PATCH>(sm.rec, d, t.tsh, t.kq, nint, lane, carry0, t.out, t.vec, t.ps);
-            else quads_lds<R, false, false, true, PATCH>(sm.rec, d, t.tsh, t.kq, nint, lane, carry0, t.out, t.vec, t.ps);
+            if (full) quads_lds<R, false, true, true, PATCH>(tile_recs(sm), d, t.tsh, t.kq, nint, lane, carry0, t.out, t.vec, t.ps);
+            else quads_lds<R, false, false, true, PATCH>(tile_recs(sm), d, t.tsh, t.kq, nint, lane, carry0, t.out, t.vec, t.ps);
         } else {
-            if (full) quads_lds<R, false, true, false, PATCH>(sm.rec, d, t.tsh, t.kq, nint, lane, 0u, t.out, t.vec, t.ps);
-            else quads_lds<R, false, false, false, PATCH>(sm.rec, d, t.tsh, t.kq, nint, lane, 0u, t.out, t.vec, t.ps);
+            if (full) quads_lds<R, false, true, false, PATCH>(tile_recs(sm), d, t.tsh, t.kq, nint, lane, 0u, t.out, t.vec, t.ps);
+            else quads_lds<R, false, false, false, PATCH>(tile_recs(sm), d, t.tsh, t.kq, nint, lane, 0u, t.out, t.vec, t.ps);
         }
     } else {
-        (void)tile_quads<R, false, PATCH>(sm.rec, t.tsh, t.kq, t.rows, t.nrow, nint, lane, t.c.h.delta, carry0, t.out,
+        (void)tile_quads<R, false, PATCH>(tile_recs(sm), t.tsh, t.kq, t.rows, t.nrow, nint, lane, t.c.h.delta, carry0, t.out,
                                           t.vec, t.ps);
     }
 }
