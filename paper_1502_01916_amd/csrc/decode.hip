@@ -47,7 +47,7 @@ typedef __attribute__((address_space(1))) u32x4 gu32x4;
 // Small helpers.
 
 constexpr uint32_t kEpochMask = 0x3FFFFFFFu;
-constexpr int kLocWords = kChunkWords / kThreads;  // control words per thread
+constexpr int kLocWords = kChunkWords / 64;  // control words per lane: one wave per chunk
 
 __device__ __forceinline__ uint32_t epoch_next(uint32_t e) {
     return ((e + 1u) & kEpochMask) ? ((e + 1u) & kEpochMask) : 1u;
@@ -128,6 +128,32 @@ __device__ __forceinline__ uint32_t pfd_exc_words(uint32_t desc, int k, int bitm
 // ===========================================================================
 // Locate kernels: reduce -> scan -> emit.
 
+// Tuples of the first ns selectors of a Group-Simple control word, without
+// a branch; *bad is set when one of them is not a selector (10..15, that is
+// bit 3 and bit 2 or 1 set).
+__device__ __forceinline__ uint32_t sim_word_tuples(uint32_t wd, uint32_t ns, bool &bad) {
+    const uint32_t valid = ns >= 8u ? 0xFFFFFFFFu : (1u << (4u * ns)) - 1u;
+    bad |= ((wd >> 3) & ((wd >> 2) | (wd >> 1)) & 0x11111111u & valid) != 0u;
+    uint32_t wt = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < 8u; i++) wt += i < ns ? sim_num((wd >> (4u * i)) & 15u) : 0u;
+    return wt;
+}
+
+// Tuples and component data bits of the four frames of a Group-AFOR control
+// word, without a branch; *bad is set for a class-3 byte or a width above 32.
+__device__ __forceinline__ void afor_word(uint32_t wd, uint32_t &wt, uint32_t &wbits, bool &bad) {
+    wt = wbits = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const uint32_t byte = (wd >> (8 * i)) & 0xFFu, b = byte & 63u, cls = byte >> 6;
+        bad |= cls == 3u || b > 32u;
+        const uint32_t F = 8u << cls;
+        wt += F;
+        wbits += F * b;
+    }
+}
+
 __device__ __forceinline__ uint32_t locate_words(const HeaderFields &h, uint32_t T, uint32_t C, uint32_t D) {
     switch (h.codec) {
     case 0: return min(C, ((D >> h.lk) + 7u) >> 3);          // selectors / 8
@@ -142,8 +168,8 @@ __device__ __forceinline__ uint32_t locate_words(const HeaderFields &h, uint32_t
     }
 }
 
-// One thread's view of a control chunk: its kLocWords words and their
-// aggregate (tuples, exception words, component data bits).
+// One lane's view of a control chunk: its kLocWords consecutive words and
+// their aggregate (tuples, exception words, component data bits).
 struct LocThread {
     HeaderFields h;
     bool ok, bad;
@@ -155,7 +181,7 @@ struct LocThread {
 // The header comes from the host's copy in the list descriptor (validated
 // when the plan was made): the decode tiles compare the stream's own header
 // with it, so the locate pass does not wait for that load.
-__device__ __forceinline__ void locate_thread(const ListDesc &L, uint32_t chunk, LocThread &t) {
+__device__ __forceinline__ void locate_thread(const ListDesc &L, uint32_t chunk, uint32_t lane, LocThread &t) {
     const uint32_t *S = L.stream;
     const uint32_t n = L.n, C = L.C, D = L.D;
     t.ok = header_fields(L.w0, t.h);
@@ -164,15 +190,21 @@ __device__ __forceinline__ void locate_thread(const ListDesc &L, uint32_t chunk,
     t.TT = L.tile_ints >> t.h.lk;
     t.D = D;
     t.nwords = t.ok ? locate_words(t.h, t.T, C, D) : 0u;
-    t.wbase = (chunk * (uint32_t)kThreads + threadIdx.x) * (uint32_t)kLocWords;
+    t.wbase = chunk * (uint32_t)kChunkWords + lane * (uint32_t)kLocWords;
     t.bad = !t.ok;
     t.vt = t.ve = t.vd = 0;
     const uint32_t *ctrl = S + 4;
     const HeaderFields &h = t.h;
+    // 16-byte loads (the control area is a whole number of them), with no
+    // branch between them; a group past the chunk's words reads the header
 #pragma unroll
-    for (int q = 0; q < kLocWords; q++) {
-        const uint32_t w = t.wbase + (uint32_t)q;
-        t.word[q] = w < t.nwords ? ctrl[w] : 0u;
+    for (int g = 0; g < kLocWords; g += 4) {
+        const uint32_t w = t.wbase + (uint32_t)g;
+        const u32x4 v = *(const gu32x4 *)(w < t.nwords ? ctrl + w : S);
+        t.word[g] = w < t.nwords ? v.x : 0u;
+        t.word[g + 1] = w + 1u < t.nwords ? v.y : 0u;
+        t.word[g + 2] = w + 2u < t.nwords ? v.z : 0u;
+        t.word[g + 3] = w + 3u < t.nwords ? v.w : 0u;
     }
 #pragma unroll
     for (int q = 0; q < kLocWords; q++) {
@@ -180,19 +212,9 @@ __device__ __forceinline__ void locate_thread(const ListDesc &L, uint32_t chunk,
         if (w >= t.nwords) continue;
         const uint32_t wd = t.word[q];
         switch (h.codec) {
-        case 0: {
-            const uint32_t S_total = D >> h.lk;
-            for (uint32_t i = 0; i < 8u; i++) {
-                if (8u * w + i >= S_total) break;
-                const uint32_t sel = (wd >> (4u * i)) & 15u;
-                if (sel >= 10u) {
-                    t.bad = true;
-                    continue;
-                }
-                t.vt += sim_num(sel);
-            }
+        case 0:   // w < nwords: at least one of the word's selectors exists
+            t.vt += sim_word_tuples(wd, min(8u, (D >> h.lk) - 8u * w), t.bad);
             break;
-        }
         case 1:
             if (h.ld == GC_LD_BINARY) {
                 const BinUnit u = bin_unit(h.cg);
@@ -208,19 +230,13 @@ __device__ __forceinline__ void locate_thread(const ListDesc &L, uint32_t chunk,
                 if (h.ld == GC_LD_IU) t.vd += (uint32_t)h.cg * iu_useful(wd);
             }
             break;
-        case 2:
-            for (int i = 0; i < 4; i++) {
-                const uint32_t byte = (wd >> (8 * i)) & 0xFFu;
-                const uint32_t b = byte & 63u, cls = byte >> 6;
-                if (cls == 3u || b > 32u) {
-                    t.bad = true;
-                    continue;
-                }
-                const uint32_t F = 8u << cls;
-                t.vt += F;
-                t.vd += F * b;
-            }
+        case 2: {
+            uint32_t wt, wbits;
+            afor_word(wd, wt, wbits, t.bad);
+            t.vt += wt;
+            t.vd += wbits;
             break;
+        }
         default: {
             const uint32_t b = wd & 63u;
             if (b > 32u) t.bad = true;
@@ -260,37 +276,19 @@ __device__ __forceinline__ bool locate_item(const LocateArgs &a, uint32_t item, 
     return true;
 }
 
-// Workgroup totals of three values (one barrier).
-__device__ __forceinline__ void block_sum3(uint32_t &x, uint32_t &y, uint32_t &z, uint32_t (*tmp)[kWaves]) {
-    const uint32_t a = wave_sum(x), b = wave_sum(y), c = wave_sum(z);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        tmp[0][w] = a;
-        tmp[1][w] = b;
-        tmp[2][w] = c;
-    }
-    __syncthreads();
-    x = y = z = 0;
-#pragma unroll
-    for (int i = 0; i < kWaves; i++) {
-        x += tmp[0][i];
-        y += tmp[1][i];
-        z += tmp[2][i];
-    }
-}
-
-// Aggregate of every control chunk.
+// Aggregate of every control chunk (a wave per chunk).
 __global__ __launch_bounds__(kThreads) void gc_locate_reduce(LocateArgs a) {
-    __shared__ uint32_t s_tmp[3][kWaves];
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t item = blockIdx.x * (uint32_t)kWaves + wave;
     ListDesc L;
     uint32_t chunk, list;
-    if (locate_item(a, blockIdx.x, L, chunk, list)) {
+    if (locate_item(a, item, L, chunk, list)) {
         LocThread t;
-        locate_thread(L, chunk, t);
-        uint32_t tt = t.vt, te = t.ve, td = t.vd;
-        block_sum3(tt, te, td, s_tmp);
+        locate_thread(L, chunk, lane, t);
+        const uint32_t tt = wave_sum(t.vt), te = wave_sum(t.ve), td = wave_sum(t.vd);
         if (t.bad) latch(a.status, kErrLocate);
-        if (threadIdx.x == 0) {
+        if (lane == 0) {
             LocVal v;
             v.tup = tt;
             v.exc = te;
@@ -337,19 +335,21 @@ __global__ __launch_bounds__(kThreads) void gc_locate_scan(LocateArgs a) {
     }
 }
 
-// Tile starts from the chunk prefixes, tagged with this run's epoch.
+// Tile starts from the chunk prefixes, tagged with this run's epoch (a
+// wave per chunk).
 __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
-    __shared__ uint32_t s_tmp[kWaves];
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t item = blockIdx.x * (uint32_t)kWaves + wave;
     ListDesc L;
     uint32_t chunk, list;
-    if (locate_item(a, blockIdx.x, L, chunk, list)) {
+    if (locate_item(a, item, L, chunk, list)) {
         const uint32_t epoch = *(const gu32 *)&a.state->epoch;   // advanced by the reduce kernel
         LocThread t;
-        locate_thread(L, chunk, t);
-        uint32_t tt, te, td;
-        const uint32_t xt = block_excl_scan(t.vt, s_tmp, tt);
-        const uint32_t xe = block_excl_scan(t.ve, s_tmp, te);
-        const uint32_t xd = block_excl_scan(t.vd, s_tmp, td);
+        locate_thread(L, chunk, lane, t);
+        const uint32_t xt = wave_incl_scan(t.vt) - t.vt;
+        const uint32_t xe = wave_incl_scan(t.ve) - t.ve;
+        const uint32_t xd = wave_incl_scan(t.vd) - t.vd;
         const LocVal pre = a.pre[L.chunk_base + chunk];
         const uint32_t TT = t.TT, ntiles = L.ntiles, D = t.D;
         const HeaderFields &h = t.h;
@@ -382,12 +382,18 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
                 const uint32_t wd = t.word[q];
                 switch (h.codec) {
                 case 0: {
-                    const uint32_t S_total = D >> h.lk;
-                    for (uint32_t i = 0; i < 8u; i++) {
+                    // the word's selectors are walked only when a tile starts among them
+                    const uint32_t ns = min(8u, (D >> h.lk) - 8u * w);
+                    bool unused = false;
+                    const uint32_t wt = sim_word_tuples(wd, ns, unused);
+                    uint32_t m;
+                    if (!boundary(base_t, wt, m)) {
+                        base_t += wt;
+                        break;
+                    }
+                    for (uint32_t i = 0; i < ns; i++) {
                         const uint32_t s = 8u * w + i;
-                        if (s >= S_total) break;
                         const uint32_t num = sim_num((wd >> (4u * i)) & 15u);
-                        uint32_t m;
                         if (boundary(base_t, num, m)) emit(m, s, m * TT - base_t, 32ull * s, 0);
                         base_t += num;
                     }
@@ -429,11 +435,20 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
                         if (h.ld == GC_LD_IU) base_d += (uint32_t)h.cg * iu_useful(wd);
                     }
                     break;
-                case 2:
+                case 2: {
+                    // the word's frames are walked only when a tile starts among them
+                    uint32_t wt, wbits;
+                    bool unused = false;
+                    afor_word(wd, wt, wbits, unused);
+                    uint32_t m;
+                    if (!boundary(base_t, wt, m)) {
+                        base_t += wt;
+                        base_d += wbits;
+                        break;
+                    }
                     for (int i = 0; i < 4; i++) {
                         const uint32_t byte = (wd >> (8 * i)) & 0xFFu;
                         const uint32_t b = byte & 63u, F = 8u << (byte >> 6);
-                        uint32_t m;
                         if (boundary(base_t, F, m)) {
                             const uint32_t sub = m * TT - base_t;
                             emit(m, 4u * w + (uint32_t)i, sub, base_d + (uint64_t)sub * b, 0);
@@ -442,6 +457,7 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
                         base_d += (uint64_t)F * b;
                     }
                     break;
+                }
                 default: {
                     const uint32_t t0 = 32u * w;
                     if (t0 > 0u && t0 % TT == 0u && t0 / TT < ntiles) emit(t0 / TT, w, 0, base_d, base_e);
@@ -1529,9 +1545,10 @@ int codec_class(uint32_t w0) {
 
 int launch_locate(const LocateArgs &a, hipStream_t s) {
     if (!a.total_items) return 0;
-    hipLaunchKernelGGL(gc_locate_reduce, dim3(a.total_items), dim3(kThreads), 0, s, a);
+    const dim3 grid((a.total_items + kWaves - 1) / kWaves);
+    hipLaunchKernelGGL(gc_locate_reduce, grid, dim3(kThreads), 0, s, a);
     hipLaunchKernelGGL(gc_locate_scan, dim3((a.total_scan + kWaves - 1) / kWaves), dim3(kThreads), 0, s, a);
-    hipLaunchKernelGGL(gc_locate_emit, dim3(a.total_items), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(gc_locate_emit, grid, dim3(kThreads), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
