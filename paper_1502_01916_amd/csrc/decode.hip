@@ -368,13 +368,17 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
             ti.pad = 0;
             tiles[m] = ti;
         };
-        // the tile boundary m*TT (m >= 1) that falls in tuples [t0, t0 + cnt)
-        auto boundary = [&](uint32_t t0, uint32_t cnt, uint32_t &m) -> bool {
-            m = (t0 + TT - 1u) / TT;
-            if (m == 0u) m = 1u;
-            return m < ntiles && (uint64_t)m * TT < (uint64_t)t0 + cnt;
-        };
         if (!t.bad) {
+            // Tile m (m >= 1) starts at tuple m * TT.  A unit (selector,
+            // frame, control word of unary codes, field, block) holds at
+            // most 32 tuples and a tile at least 32, so a unit holds at most
+            // one tile start: the lane keeps the next one, m, found with one
+            // division, and its walk only compares.
+            const bool unary = h.codec == 1 && h.ld != GC_LD_BINARY;
+            const uint32_t t0 = h.codec == 1 ? t.wbase * bin_unit(h.cg).fpw : h.codec == 3 ? 32u * t.wbase : base_t;
+            // unary codes: the tile starts after the terminator of rank m * TT - 1
+            uint32_t m = unary ? base_t / TT + 1u : max(1u, (t0 + TT - 1u) / TT);
+            uint32_t B = m * TT;
 #pragma unroll
             for (int q = 0; q < kLocWords; q++) {
                 const uint32_t w = t.wbase + (uint32_t)q;
@@ -386,15 +390,18 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
                     const uint32_t ns = min(8u, (D >> h.lk) - 8u * w);
                     bool unused = false;
                     const uint32_t wt = sim_word_tuples(wd, ns, unused);
-                    uint32_t m;
-                    if (!boundary(base_t, wt, m)) {
+                    if (!(m < ntiles && B < base_t + wt)) {
                         base_t += wt;
                         break;
                     }
                     for (uint32_t i = 0; i < ns; i++) {
                         const uint32_t s = 8u * w + i;
                         const uint32_t num = sim_num((wd >> (4u * i)) & 15u);
-                        if (boundary(base_t, num, m)) emit(m, s, m * TT - base_t, 32ull * s, 0);
+                        if (m < ntiles && B < base_t + num) {
+                            emit(m, s, B - base_t, 32ull * s, 0);
+                            m++;
+                            B += TT;
+                        }
                         base_t += num;
                     }
                     break;
@@ -405,20 +412,22 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
                         for (uint32_t f = 0; f < u.fpw; f++) {
                             const uint32_t tt2 = w * u.fpw + f;
                             if (tt2 >= t.T) break;
-                            if (tt2 > 0u && tt2 % TT == 0u && tt2 / TT < ntiles) emit(tt2 / TT, tt2, 0, base_d, 0);
+                            if (tt2 == B && m < ntiles) {
+                                emit(m, tt2, 0, base_d, 0);
+                                m++;
+                                B += TT;
+                            }
                             const uint32_t bit = bin_field_bit(tt2, u) & 31u;
                             base_d += (uint32_t)h.cg * (((wd >> bit) & mask_of(u.fb)) + 1u);
                         }
                     } else {
                         // terminators (0 bits) of ranks base_t .. base_t + cnt - 1 end
-                        // in this word; the tile starting at tuple m*TT begins right
-                        // after the terminator of rank m*TT - 1
+                        // in this word
                         const uint32_t z = ~wd;
                         const uint32_t cnt = (uint32_t)__builtin_popcount(z);
-                        const uint32_t m = (base_t + TT) / TT;
-                        if (cnt && m < ntiles && m * TT - 1u < base_t + cnt) {
+                        if (m < ntiles && B - 1u < base_t + cnt) {
                             uint32_t zz = z;
-                            for (uint32_t i = 0; i < m * TT - 1u - base_t; i++) zz &= zz - 1u;
+                            for (uint32_t i = 0; i < B - 1u - base_t; i++) zz &= zz - 1u;
                             const uint32_t bit = (uint32_t)__builtin_ctz(zz);
                             const uint32_t pos = 32u * w + bit + 1u;
                             uint64_t d;
@@ -430,6 +439,8 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
                                 d = base_d + (uint64_t)h.cg * iu_useful(upto);
                             }
                             emit(m, pos, 0, d, 0);
+                            m++;
+                            B += TT;
                         }
                         base_t += cnt;
                         if (h.ld == GC_LD_IU) base_d += (uint32_t)h.cg * iu_useful(wd);
@@ -440,8 +451,7 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
                     uint32_t wt, wbits;
                     bool unused = false;
                     afor_word(wd, wt, wbits, unused);
-                    uint32_t m;
-                    if (!boundary(base_t, wt, m)) {
+                    if (!(m < ntiles && B < base_t + wt)) {
                         base_t += wt;
                         base_d += wbits;
                         break;
@@ -449,9 +459,11 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
                     for (int i = 0; i < 4; i++) {
                         const uint32_t byte = (wd >> (8 * i)) & 0xFFu;
                         const uint32_t b = byte & 63u, F = 8u << (byte >> 6);
-                        if (boundary(base_t, F, m)) {
-                            const uint32_t sub = m * TT - base_t;
+                        if (m < ntiles && B < base_t + F) {
+                            const uint32_t sub = B - base_t;
                             emit(m, 4u * w + (uint32_t)i, sub, base_d + (uint64_t)sub * b, 0);
+                            m++;
+                            B += TT;
                         }
                         base_t += F;
                         base_d += (uint64_t)F * b;
@@ -459,8 +471,11 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
                     break;
                 }
                 default: {
-                    const uint32_t t0 = 32u * w;
-                    if (t0 > 0u && t0 % TT == 0u && t0 / TT < ntiles) emit(t0 / TT, w, 0, base_d, base_e);
+                    if (32u * w == B && m < ntiles) {
+                        emit(m, w, 0, base_d, base_e);
+                        m++;
+                        B += TT;
+                    }
                     base_d += 32u * min(wd & 63u, 32u);
                     base_e += pfd_exc_words(wd, (int)t.k, h.pfd_pos);
                     break;
