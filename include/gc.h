@@ -156,7 +156,14 @@ typedef struct {
                                 pass over every class, then class by class the
                                 other passes; 1: per-class locate kernels on a
                                 second stream, ahead of the other kernels      */
-    uint32_t reserved[2];    /* zero */
+    uint32_t carry_pass;     /* how a tile of a delta list of several tiles gets
+                                its carry (the sum of the list's d-gaps before
+                                it): 1 in the decode pass itself, each tile
+                                publishing its sum and reading those before
+                                it (decoupled look-back); 2 a tile-sum pass
+                                and a carry scan ahead of the decode pass;
+                                0 = default (2)                                */
+    uint32_t reserved;       /* zero */
 } gc_plan_opts;
 
 /* Builds a batched decode plan for nlists lists.  h_headers holds the first
@@ -174,8 +181,8 @@ gc_status gc_plan_destroy(gc_plan *plan);
 
 /* Decodes every list of the plan: the locate pass, then per codec class the
  * tile-sum pass over its delta lists of more than one tile, the carry scan
- * and the decode pass (one hipGraph branch per class when the plan was
- * created with use_graph).                                                 */
+ * and the decode pass (with opts->carry_pass 1, the decode pass alone),
+ * replayed as one hipGraph when the plan was created with use_graph.       */
 gc_status gc_decode_batch(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_out,
                           void *hip_stream);
 
@@ -207,8 +214,9 @@ gc_status gc_decode_each(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_o
 gc_status gc_plan_timings(gc_plan *plan, uint32_t max_runs, float *ms, uint32_t *nruns);
 
 /* Reports the chosen configuration of a plan: the wave-tile and Group-PFD
- * tile sizes, the decode tiles of one run and, of those, the tiles the sum
- * pass decodes as well.  Any pointer may be NULL.                          */
+ * tile sizes, the decode tiles of one run and, of those, the tiles whose
+ * sums a later tile's carry needs (summed in the decode pass, or by the sum
+ * pass with carry_pass 2).  Any pointer may be NULL.                       */
 gc_status gc_plan_config(const gc_plan *plan, uint32_t *tile_ints, uint32_t *pfd_tile_ints,
                          uint64_t *tiles, uint64_t *sum_tiles);
 

@@ -1466,8 +1466,70 @@ __device__ __forceinline__ uint32_t tile_total(const TileRun<TW, CLS> &t, WaveSm
 }
 
 // MODE: 0 decode (a delta tile adds carry[gi], the exclusive prefix of the
-// tile sums of its list), 1 the tile's sum to carry[gi].
-enum : int { kModeDecode = 0, kModeSum = 1 };
+// tile sums of its list), 1 the tile's sum to carry[gi], 2 decode with the
+// carry found in the same pass (decoupled look-back over the flags).
+enum : int { kModeDecode = 0, kModeSum = 1, kModeFused = 2 };
+
+// Single-pass carry of tile gi, the m-th of a delta list, with tile sum s
+// (wave-uniform).  Every tile but the list's last publishes a flag
+// epoch:30 | state:2 | value:32: state 1 with its sum as soon as it has it,
+// state 2 with its inclusive prefix once it has its carry.  The carry is
+// read from the flags before it, 64 at a time (lane l reads tile
+// gi - 1 - l): the nearest inclusive prefix plus the sums after it.  The
+// list's first tile publishes its sum as an inclusive prefix, so the
+// look-back never leaves the list.  Flags of an earlier run carry another
+// epoch and count as not yet written.  A tile waits only for tiles of lower
+// index, which every workgroup dispatcher starts first; the wait is bounded
+// all the same, and on expiry the error is latched.
+constexpr uint64_t kLookbackTicks = 2000000ull;   // 20 ms of the 100 MHz real-time counter
+
+__device__ __forceinline__ void flag_store(unsigned long long *f, unsigned long long v) {
+    __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ uint32_t tile_carry(const DecodeArgs &a, uint32_t gi, uint32_t m, uint32_t ntiles, uint32_t s,
+                               uint32_t epoch, uint32_t lane) {
+    unsigned long long *flags = a.flags;
+    const uint32_t ep = epoch & kEpochMask;
+    const unsigned long long tag = (unsigned long long)ep << 34;
+    const bool last = m + 1u >= ntiles;
+    if (m == 0u) {
+        if (!last && lane == 0) flag_store(flags + gi, tag | (2ull << 32) | s);
+        return 0u;
+    }
+    if (!last && lane == 0) flag_store(flags + gi, tag | (1ull << 32) | s);
+    const uint32_t first = gi - m;
+    uint32_t acc = 0, base = gi;
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
+        const bool in = base >= first + 1u + lane;
+        const uint32_t j = in ? base - 1u - lane : first;
+        const unsigned long long f = __hip_atomic_load(flags + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t st = (uint32_t)(f >> 34) == ep ? (uint32_t)(f >> 32) & 3u : 0u;
+        const uint64_t incl = __ballot(in && st == 2u), wait = __ballot(in && st == 0u);
+        if (incl) {
+            const uint32_t p = (uint32_t)__builtin_ctzll(incl);
+            const uint64_t upto = p == 63u ? ~0ull : (2ull << p) - 1ull;
+            if (!(wait & upto)) {
+                acc += wave_sum(lane <= p ? (uint32_t)f : 0u);
+                break;
+            }
+        } else if (!wait) {
+            // 64 sums and no prefix yet: every lane is inside the list (its
+            // first tile never holds a bare sum)
+            acc += wave_sum((uint32_t)f);
+            base -= 64u;
+            continue;
+        }
+        if (__builtin_amdgcn_s_memrealtime() - t0 > kLookbackTicks) {
+            if (lane == 0) latch(a.status, kErrTimeout);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    if (!last && lane == 0) flag_store(flags + gi, tag | (2ull << 32) | (acc + s));
+    return acc;
+}
 
 template <int TW, int CLS, int MODE>
 __device__ void wave_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, uint32_t gi, const TilePre &pre,
@@ -1486,7 +1548,14 @@ __device__ void wave_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, ui
     }
     HeaderFields hl;
     const bool delta = header_fields(L.w0, hl) && hl.delta;
-    const uint32_t carry0 = (delta && L.ntiles > 1u) ? pre.carry : 0u;
+    uint32_t carry0 = 0;
+    if (delta && L.ntiles > 1u) {
+        if constexpr (MODE == kModeFused) {
+            carry0 = tile_carry(a, gi, m, L.ntiles, tile_total<TW, CLS>(t, sm, lane), loc_tag, lane);
+        } else {
+            carry0 = pre.carry;
+        }
+    }
     const uint32_t nint = t.nint;
     if (t.staged) {
         const u32x4 *d = sm.data;
@@ -1598,10 +1667,13 @@ static const void *decode_fn(int tile, int cls) {
     }
 }
 
-// Launches a pass over a.count tiles: mode 0 decode, 1 tile sums.
+// Launches a pass over a.count tiles: mode 0 decode, 1 tile sums, 2 decode
+// with the single-pass carry.
 int launch_decode(int tile, int cls, int mode, const DecodeArgs &a, hipStream_t s) {
     if (!a.count) return 0;
-    const void *fn = mode == 1 ? decode_fn<kModeSum>(tile, cls) : decode_fn<kModeDecode>(tile, cls);
+    const void *fn = mode == 1   ? decode_fn<kModeSum>(tile, cls)
+                     : mode == 2 ? decode_fn<kModeFused>(tile, cls)
+                                 : decode_fn<kModeDecode>(tile, cls);
     if (!fn) return -2;
     const uint32_t per = (uint32_t)kWaves;
     DecodeArgs arg = a;

@@ -90,6 +90,7 @@ struct DecodeArgs {
     const TileInfo *tiles;
     uint32_t *carry;            // per tile: sum of its gaps (sum pass), then the
                                 // exclusive prefix of those sums in its list
+    unsigned long long *flags;  // single-pass carry: per tile epoch:30 | state:2 | value:32
     const RunState *loc_state;
     Status *status;
 };
@@ -116,6 +117,7 @@ enum : uint32_t {
     kErrLocate = 8,
     kErrCount = 9,
     kErrBitmap = 11,
+    kErrTimeout = 12,   // a carry look-back waited too long for an earlier tile
 };
 
 }  // namespace gcdev

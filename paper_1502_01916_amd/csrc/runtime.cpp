@@ -35,6 +35,10 @@ namespace {
 
 constexpr int kDefaultWaveTile = 2048;
 constexpr int kDefaultPfdTile = 4096;
+// Carries of delta lists: found in the decode pass by decoupled look-back
+// (true), or by a tile-sum pass and a carry scan ahead of it (false, the
+// faster of the two on the mixed batches measured).
+constexpr bool kDefaultFused = false;
 constexpr int kWaveTiles[3] = {1024, 2048, 4096};
 constexpr int kPfdTiles[2] = {2048, 4096};
 constexpr int kClsPfd = 4;
@@ -93,6 +97,7 @@ struct Scratch {
     RunState *state = nullptr;          // [class]
     TileInfo *tiles = nullptr;
     uint32_t *carry = nullptr;
+    unsigned long long *flags = nullptr;   // single-pass carry flags, one per tile
     LocVal *agg = nullptr, *pre = nullptr;
     size_t tiles_cap = 0, chunks_cap = 0;
 
@@ -108,10 +113,14 @@ struct Scratch {
             HIP_OK(hipDeviceSynchronize());
             dev_free(tiles);
             dev_free(carry);
+            dev_free(flags);
             const size_t cap = std::max(ntiles, tiles_cap * 2);
             gc_status rc = dev_alloc(&tiles, cap);
             if (!rc) rc = dev_alloc(&carry, cap);
+            if (!rc) rc = dev_alloc(&flags, cap);
             if (rc) return rc;
+            // no flag may carry an epoch before it is written: zero them once
+            HIP_OK(hipMemset(flags, 0, cap * sizeof(*flags)));
             tiles_cap = cap;
         }
         if (nchunks > chunks_cap) {
@@ -130,6 +139,7 @@ struct Scratch {
         dev_free(state);
         dev_free(tiles);
         dev_free(carry);
+        dev_free(flags);
         dev_free(agg);
         dev_free(pre);
         tiles_cap = chunks_cap = 0;
@@ -216,6 +226,7 @@ struct gc_plan {
     std::vector<hipEvent_t> ev;                // kEvPerSlot per timing slot
     hipStream_t aux = nullptr;                 // timing: the locate stream
     bool serial = true;                        // no locate stream
+    bool fused = kDefaultFused;                // carries found in the decode pass
     uint32_t slots = 0;
     uint64_t runs = 0;
 };
@@ -251,6 +262,7 @@ DecodeArgs make_decode_args(const ListDesc *lists, const ListDesc &single, uint3
     a.count = count;
     a.tiles = sc.tiles;
     a.carry = sc.carry;
+    a.flags = sc.flags;
     a.loc_state = sc.state + cls;
     a.status = st;
     return a;
@@ -299,13 +311,14 @@ DecodeArgs single_args(const ListDesc &L, int cls, Scratch &sc, Status *st) {
 }
 
 // Launches every pass of one list on stream s (the per-list paths).
-gc_status launch_one(const ListDesc &L, int cls, Scratch &sc, Status *st, hipStream_t s) {
+gc_status launch_one(const ListDesc &L, int cls, Scratch &sc, Status *st, hipStream_t s, bool fused) {
     if (L.ntiles > 1) {
         LocateArgs a = make_locate_args(nullptr, nullptr, nullptr, L, L.nchunks, 1, cls, sc, st);
         if (launch_locate(a, s)) return GC_EDEVICE;
     }
     const int tile = (int)L.tile_ints;
     const DecodeArgs d = single_args(L, cls, sc, st);
+    if (fused) return launch_decode(tile, cls, 2, d, s) ? GC_EDEVICE : GC_OK;
     if (L.ntiles > 1 && is_delta(L.w0)) {
         if (launch_decode(tile, cls, 1, d, s)) return GC_EDEVICE;
         if (launch_carry_scan(make_carry_args(nullptr, nullptr, L, 1, sc), s)) return GC_EDEVICE;
@@ -478,6 +491,11 @@ gc_status launch_class_work(gc_plan *p, int c, hipStream_t s, hipEvent_t mid = n
     std::memset(&none, 0, sizeof(none));
     const int tile = c == kClsPfd ? p->tile_p : p->tile_w;
     const int epoch_cls = p->serial ? 0 : c;   // whose locate epoch tags the tile starts
+    if (p->fused) {
+        if (mid) HIP_OK(hipEventRecord(mid, s));
+        DecodeArgs d = make_decode_args(p->d_lists, none, r.lo, r.count, epoch_cls, p->sc, p->ctx->status);
+        return launch_decode(tile, c, 2, d, s) ? GC_EDEVICE : GC_OK;
+    }
     if (r.sum) {
         DecodeArgs d = make_decode_args(p->d_lists, none, r.lo, r.sum, epoch_cls, p->sc, p->ctx->status);
         if (launch_decode(tile, c, 1, d, s)) return GC_EDEVICE;
@@ -654,7 +672,7 @@ std::string plan_key(const gc_plan *p) {
     int lm = 0;
     while ((1ull << lm) < mean) lm++;
     std::string key = "gfx950:k" + std::to_string(1 << lk) + ":n2^" + std::to_string(lg) + ":mean2^" +
-                      std::to_string(lm) + ":mix";
+                      std::to_string(lm) + (p->fused ? ":c1" : ":c2") + ":mix";
     for (int c = 0; c < kClasses; c++)
         key += (c ? "-" : "") + std::to_string(total ? per_cls[c] * 8 / total : 0);
     return key;
@@ -791,7 +809,7 @@ gc_status gc_decode(gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words, 
     L.C = h_header[2];
     L.D = h_header[3];
     if (gc_status rc = ctx->single.reserve(L.ntiles + 1, L.nchunks)) return rc;
-    return launch_one(L, cls, ctx->single, ctx->status, (hipStream_t)hip_stream);
+    return launch_one(L, cls, ctx->single, ctx->status, (hipStream_t)hip_stream, kDefaultFused);
 }
 
 gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists, const uint32_t *h_headers,
@@ -804,7 +822,7 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     if (opts) o = *opts;
     if (o.tile_ints && !valid_wave_tile(o.tile_ints)) return GC_EINVAL;
     if (o.pfd_tile_ints && !valid_pfd_tile(o.pfd_tile_ints)) return GC_EINVAL;
-    if (o.schedule > 1u || o.reserved[0] || o.reserved[1]) return GC_EINVAL;
+    if (o.schedule > 1u || o.carry_pass > 2u || o.reserved) return GC_EINVAL;
     if ((o.autotune || o.use_graph) && nlists && (!d_streams || !d_out)) return GC_EINVAL;
     gc_plan *p = new (std::nothrow) gc_plan();
     if (!p) return GC_ENOMEM;
@@ -814,6 +832,7 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     p->tile_p = o.pfd_tile_ints ? (int)o.pfd_tile_ints : kDefaultPfdTile;
     p->use_graph = o.use_graph != 0;
     p->serial = o.schedule == 0u;
+    p->fused = o.carry_pass ? o.carry_pass == 1u : kDefaultFused;
     p->slots = std::min<uint32_t>(o.timing_slots, 4096u);
     p->h_lists.resize(nlists);
     p->cls.resize(nlists);
@@ -897,7 +916,7 @@ gc_status gc_decode_each(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_o
         if (L.n == 0) continue;
         L.stream = d_streams + plan->stream_off[i];
         L.out = d_out + plan->out_off[i];
-        if (gc_status rc = launch_one(L, plan->cls[i], plan->sc, plan->ctx->status, s)) return rc;
+        if (gc_status rc = launch_one(L, plan->cls[i], plan->sc, plan->ctx->status, s, plan->fused)) return rc;
     }
     return GC_OK;
 }

@@ -60,7 +60,11 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("tile_ints", ctypes.c_uint32), ("pfd_tile_ints", ctypes.c_uint32),
                 ("use_graph", ctypes.c_uint32), ("autotune", ctypes.c_uint32),
                 ("timing_slots", ctypes.c_uint32), ("schedule", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 2)]
+                ("carry_pass", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+# how the tiles of a delta list get their carries (gc_plan_opts.carry_pass)
+CARRY_DEFAULT, CARRY_LOOKBACK, CARRY_SUM_PASS = 0, 1, 2
 
 
 class AdamOpts(ctypes.Structure):
@@ -283,7 +287,8 @@ class Plan:
     """gc_plan_create / gc_decode_batch / gc_decode_each / gc_plan_destroy."""
 
     def __init__(self, ctx: Context, descs, headers, d_streams=None, d_out=None, tile_ints=0,
-                 pfd_tile_ints=0, use_graph=False, autotune=False, timing_slots=0, locate_stream=False):
+                 pfd_tile_ints=0, use_graph=False, autotune=False, timing_slots=0, locate_stream=False,
+                 carry_pass=CARRY_DEFAULT):
         self.ctx = ctx
         nl = len(descs)
         arr = (ListDesc * max(nl, 1))()
@@ -291,7 +296,7 @@ class Plan:
             arr[i] = d
         hdr = np.ascontiguousarray(headers, dtype=np.uint32).reshape(-1)
         opts = PlanOpts(int(tile_ints), int(pfd_tile_ints), int(bool(use_graph)), int(bool(autotune)),
-                        int(timing_slots), int(bool(locate_stream)))
+                        int(timing_slots), int(bool(locate_stream)), int(carry_pass))
         self._h = ctypes.c_void_p()
         rc = lib().gc_plan_create(ctx._h, arr, nl, _u32(hdr), ctypes.byref(opts),
                                   _ptr(d_streams) if d_streams is not None else None,

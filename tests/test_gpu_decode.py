@@ -133,7 +133,8 @@ def make_batch(rng, nlists, kmix=(4,), maxlen=40000):
 
 @pytest.mark.parametrize("tiles", [(1024, 2048), (2048, 4096), (4096, 4096)])
 @pytest.mark.parametrize("graph", [False, True])
-def test_batch_parity(torch_cuda, ctx, tiles, graph):
+@pytest.mark.parametrize("carry", [gc.CARRY_SUM_PASS, gc.CARRY_LOOKBACK])
+def test_batch_parity(torch_cuda, ctx, tiles, graph, carry):
     torch = torch_cuda
     tile, pfd_tile = tiles
     rng = np.random.default_rng(50 + tile + int(graph))
@@ -143,8 +144,9 @@ def test_batch_parity(torch_cuda, ctx, tiles, graph):
     d_s = gc.to_device(flat)
     total = int(out_offs[-1])
     d_o = torch.full((total + 64,), -1, dtype=torch.int32, device="cuda")
-    say("batch tile", tile, "graph", graph, "lists", len(descs), "ints", total)
-    plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=tile, pfd_tile_ints=pfd_tile, use_graph=graph)
+    say("batch tile", tile, "graph", graph, "carry", carry, "lists", len(descs), "ints", total)
+    plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=tile, pfd_tile_ints=pfd_tile, use_graph=graph,
+                   carry_pass=carry)
     want = np.concatenate(lists)
     for rep in range(3):
         d_o.fill_(-1)
@@ -162,6 +164,38 @@ def test_batch_parity(torch_cuda, ctx, tiles, graph):
     assert rc == gc.OK, det
     assert np.array_equal(gc.unpad(gc.to_host(d_o), out_offs, lengths), want)
     plan.close()
+
+
+@pytest.mark.parametrize("codec,kw", [(gc.SIMPLE, {}), (gc.SCHEME, dict(cg=8, ld=gc.LD_IU)), (gc.PFD, {})])
+def test_lookback_long_lists(torch_cuda, ctx, codec, kw):
+    """Single-pass carries over lists of hundreds of tiles, so that a look-back
+    crosses several 64-tile windows, next to short lists; replayed from a
+    graph (each replay a new epoch of flags) and checked every time, then
+    the same plan with the two-pass carry."""
+    torch = torch_cuda
+    rng = np.random.default_rng(int(codec) + 900)
+    lengths = np.array([700 * 1024 + 333, 5, 2048, 300 * 1024, 1, 129 * 1024 + 1], np.int64)
+    lists = [np.sort(rng.choice(1 << 31, int(n), replace=False)).astype(np.uint32) for n in lengths]
+    lists[3] = O.prefix_sum(np.full(int(lengths[3]), (1 << 31) - 1, np.uint32))   # wrapping sums
+    p = O.params(codec, delta=True, cg=kw.get("cg", 1), ld=kw.get("ld", O.LD_CU))
+    streams = [O.encode(x, p) for x in lists]
+    offs = np.concatenate([[0], np.cumsum([x.size for x in streams])]).astype(np.int64)
+    flat = np.concatenate(streams)
+    descs, headers, out_offs = gc.batch_layout(flat, offs, lengths, align=4)
+    d_s = gc.to_device(flat)
+    d_o = torch.full((int(out_offs[-1]),), -1, dtype=torch.int32, device="cuda")
+    want = np.concatenate(lists)
+    for carry in (gc.CARRY_LOOKBACK, gc.CARRY_SUM_PASS):
+        say("look-back long lists codec", codec, "carry", carry)
+        plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=1024, pfd_tile_ints=2048, use_graph=True,
+                       carry_pass=carry)
+        for rep in range(4):
+            d_o.fill_(-1)
+            plan.decode_batch(d_s, d_o)
+            rc, det = ctx.sync_status()
+            assert rc == gc.OK, det
+            assert np.array_equal(gc.unpad(gc.to_host(d_o), out_offs, lengths), want), (carry, rep)
+        plan.close()
 
 
 def test_autotuned_plan(torch_cuda, ctx, tmp_path, monkeypatch):
