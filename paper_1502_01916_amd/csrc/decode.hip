@@ -595,17 +595,27 @@ template <int TW, int CLS>
 struct WaveSmem {
     static constexpr int TTM = TW / 4;
     static constexpr int NCTRL = CLS == kClsSim ? TTM / 8 + 8 : CLS == kClsGscU ? TTM + 8 : 1;
-    static constexpr int NDATA = TW / 8;   // 16-byte data chunks: 16 bits per integer
-    // + one row of 16 chunks that the second row read of a quad may touch
-    static constexpr int NB = (NDATA > (NCTRL + 3) / 4 ? NDATA : (NCTRL + 3) / 4) + 16;
+    // 16-byte chunks: the unit records of the Group-Simple / Group-AFOR prologues
+    static constexpr int NINFO = CLS == kClsSim ? (TTM + 2) / 2 : CLS == kClsAfor ? (TTM / 8 + 3) / 2 : 0;
+    static constexpr int NDATA = TW / 8;   // data rows staged: 16 bits per integer
+    static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+    // + one chunk: a tile stages its rows when the row after its last fits too
+    // (the second row read of a quad may touch it; its bits are masked off)
+    static constexpr int NB = cmax(cmax(NDATA + 1, (NCTRL + 3) / 4), NINFO);
+    static_assert(NB == NDATA + 1, "staged rows are copied up to NDATA chunks");
     // control words or per-unit record bases while the records are built,
     // then the tile's data rows
     union {
         u32x4 data[NB];
         uint32_t ctrl[4 * NB];
     };
-    // tuple records (Group-PFD computes them from its block words instead)
-    uint32_t rec[CLS == kClsPfd ? 4 : TTM + 4];   // + room for one more entry while the records are built
+    // tuple records: bit offset (from the tile's first row, < 2^15) and width;
+    // the offsets hold unit markers (Group-Simple, Group-AFOR) or terminator
+    // positions + 1 (unary Group-Scheme) while the records are built.
+    // Group-PFD computes its records from its block words instead.
+    static constexpr int NREC = CLS == kClsPfd ? 16 : TTM + 16;
+    uint16_t rel[NREC];
+    uint8_t bwid[NREC];
     // Group-PFD only: block descriptors, data row and exception word offsets
     // of the tile's blocks and their record words (row offset | width); the
     // exception bitmap of the tile's integers, per bitmap word the
@@ -622,8 +632,9 @@ struct WaveSmem {
 // Record of tuple t (bit offset << 6 | width): from the record array, or,
 // for a Group-PFD tile, from the record word of its 32-tuple block.
 struct RecArr {
-    const uint32_t *rec;
-    __device__ __forceinline__ uint32_t operator()(uint32_t t) const { return rec[t]; }
+    const uint16_t *rel;
+    const uint8_t *bw;
+    __device__ __forceinline__ uint32_t operator()(uint32_t t) const { return ((uint32_t)rel[t] << 6) | bw[t]; }
 };
 struct RecBlk {
     const uint32_t *brec;
@@ -641,41 +652,51 @@ struct RecBlk {
 // tuples (in-lane, then across the wave) names every tuple's unit.  Lane l
 // owns tuples [l * TPL, (l + 1) * TPL).
 template <int TTM>
-__device__ __forceinline__ void zero_markers(uint32_t *rec, uint32_t lane) {
-    constexpr int V = TTM / 256;
-    u32x4 *r4 = reinterpret_cast<u32x4 *>(rec) + lane * V;
+__device__ __forceinline__ void zero_markers(uint16_t *mk, uint32_t lane) {
+    constexpr int W = TTM / 128;   // 32-bit words (two markers) per lane
+    uint32_t *p = reinterpret_cast<uint32_t *>(mk) + lane * W;
 #pragma unroll
-    for (int v = 0; v < V; v++) r4[v] = u32x4{0u, 0u, 0u, 0u};
+    for (int w = 0; w < W; w++) p[w] = 0u;
+}
+
+// Writes lane l's TPL records (tuples l*TPL ..): offsets two to a word,
+// widths four to a word.
+template <int TPL>
+__device__ __forceinline__ void put_records(uint16_t *rel, uint8_t *bwa, uint32_t lane, const uint32_t *r,
+                                            const uint32_t *b) {
+    uint32_t *pr = reinterpret_cast<uint32_t *>(rel) + lane * (TPL / 2);
+#pragma unroll
+    for (int w = 0; w < TPL / 2; w++) pr[w] = (r[2 * w] & 0xFFFFu) | (r[2 * w + 1] << 16);
+    uint32_t *pb = reinterpret_cast<uint32_t *>(bwa) + lane * (TPL / 4);
+#pragma unroll
+    for (int w = 0; w < TPL / 4; w++)
+        pb[w] = b[4 * w] | (b[4 * w + 1] << 8) | (b[4 * w + 2] << 16) | (b[4 * w + 3] << 24);
 }
 
 template <int TTM>
-__device__ __forceinline__ void expand_records(uint32_t *rec, const uint2 *info, uint32_t lane) {
-    constexpr int V = TTM / 256, TPL = 4 * V;
-    u32x4 *r4 = reinterpret_cast<u32x4 *>(rec) + lane * V;
+__device__ __forceinline__ void expand_records(uint16_t *rel, uint8_t *bwa, const uint2 *info, uint32_t lane) {
+    constexpr int TPL = TTM / 64;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(rel) + lane * (TPL / 2);
     uint32_t mk[TPL];
 #pragma unroll
-    for (int v = 0; v < V; v++) {
-        const u32x4 x = r4[v];
-        mk[4 * v] = x.x;
-        mk[4 * v + 1] = x.y;
-        mk[4 * v + 2] = x.z;
-        mk[4 * v + 3] = x.w;
+    for (int w = 0; w < TPL / 2; w++) {
+        const uint32_t x = src[w];
+        mk[2 * w] = x & 0xFFFFu;
+        mk[2 * w + 1] = x >> 16;
     }
 #pragma unroll
     for (int u = 1; u < TPL; u++) mk[u] = max(mk[u], mk[u - 1]);
     const uint32_t before = wave_shr1(wave_incl_max(mk[TPL - 1]));
     const uint32_t t0 = lane * (uint32_t)TPL;
+    uint32_t r[TPL], b[TPL];
 #pragma unroll
-    for (int v = 0; v < V; v++) {
-        uint32_t o[4];
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const uint32_t m = max(max(mk[4 * v + e], before), 1u) - 1u;
-            const uint2 in = info[m];
-            o[e] = ((in.x + (t0 + (uint32_t)(4 * v + e)) * in.y) << 6) | in.y;
-        }
-        r4[v] = u32x4{o[0], o[1], o[2], o[3]};
+    for (int u = 0; u < TPL; u++) {
+        const uint32_t m = max(max(mk[u], before), 1u) - 1u;
+        const uint2 in = info[m];
+        r[u] = in.x + (t0 + (uint32_t)u) * in.y;
+        b[u] = in.y;
     }
+    put_records<TPL>(rel, bwa, lane, r, b);
     wave_lds_sync();
 }
 
@@ -693,7 +714,7 @@ __device__ uint32_t wprologue_sim(const TileCtx &c, WaveSmem<TW, kClsSim> &sm, u
     const uint32_t nsel = s_end - s_first;
     const uint32_t cw1 = (s_end + 7u) >> 3;
     if (!(s_end <= S_total && s_end > s_first && nsel <= c.TT + 1u && cw1 <= c.C)) return kErrRange;
-    zero_markers<SM::TTM>(sm.rec, lane);
+    zero_markers<SM::TTM>(sm.rel, lane);
     dbase = s_first;
     const gu32 *ctrl = (const gu32 *)c.ctrl;
     uint2 *info = reinterpret_cast<uint2 *>(sm.data);
@@ -715,14 +736,14 @@ __device__ uint32_t wprologue_sim(const TileCtx &c, WaveSmem<TW, kClsSim> &sm, u
         const uint32_t start = base + inc - cnt;
         if (cnt) {
             info[i] = make_uint2(32u * i - (start - j0) * bw, bw);
-            if (start < c.ntup) sm.rec[start] = i + 1u;
+            if (start < c.ntup) sm.rel[start] = (uint16_t)(i + 1u);
         }
         base += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
     }
     if (wave_any(bad)) return kErrSelector;
     if (base < c.ntup) return kErrCount;
     wave_lds_sync();
-    expand_records<SM::TTM>(sm.rec, info, lane);
+    expand_records<SM::TTM>(sm.rel, sm.bwid, info, lane);
     return 0;
 }
 
@@ -775,13 +796,15 @@ __device__ uint32_t wprologue_gscu(const TileCtx &c, WaveSmem<TW, kClsGscU> &sm,
     const uint32_t ic = wave_incl_scan(cnt);
     const uint32_t tcnt = (uint32_t)__builtin_amdgcn_readlane((int)ic, 63);
     if (tcnt < c.ntup) return kErrCount;
-    uint32_t *Z = sm.rec;   // Z[r + 1] = position of terminator r; read before the records overwrite it
-    if (lane == 0) Z[0] = p0r - 1u;
+    // Z[r + 1] = position of terminator r, plus one (16 bits); read before
+    // the records overwrite it
+    uint16_t *Z = sm.rel;
+    if (lane == 0) Z[0] = (uint16_t)p0r;
     uint32_t r = ic - cnt;
     for (uint32_t w = wa; w < wb && r < c.ntup; w++) {
         uint32_t z = zeros(w);
         while (z && r < c.ntup) {
-            Z[++r] = 32u * w + (uint32_t)__builtin_ctz(z);
+            Z[++r] = (uint16_t)(32u * w + (uint32_t)__builtin_ctz(z) + 1u);
             z &= z - 1u;
         }
     }
@@ -789,7 +812,7 @@ __device__ uint32_t wprologue_gscu(const TileCtx &c, WaveSmem<TW, kClsGscU> &sm,
     const uint32_t t0 = lane * (uint32_t)TPL;
     uint32_t zr[TPL + 1];
 #pragma unroll
-    for (int i = 0; i <= TPL; i++) zr[i] = Z[min(t0 + (uint32_t)i, c.ntup)];
+    for (int i = 0; i <= TPL; i++) zr[i] = (uint32_t)Z[min(t0 + (uint32_t)i, c.ntup)] - 1u;
     uint32_t st[TPL], un[TPL];
     uint32_t usum = 0;
     bool bad = false;
@@ -807,19 +830,14 @@ __device__ uint32_t wprologue_gscu(const TileCtx &c, WaveSmem<TW, kClsGscU> &sm,
     if (wave_any(bad)) return kErrUnary;
     uint32_t us = iu ? wave_incl_scan(usum) - usum : 0u;
     const uint32_t rel0 = (uint32_t)(abs0 & 31u);
-    u32x4 *r4 = reinterpret_cast<u32x4 *>(sm.rec) + lane * (uint32_t)(TPL / 4);
+    uint32_t ro[TPL], bo[TPL];
 #pragma unroll
-    for (int v = 0; v < TPL / 4; v++) {
-        uint32_t o[4];
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const int i = 4 * v + e;
-            const uint32_t rel = iu ? rel0 + cg * us : rel0 + cg * (st[i] - p0r);
-            o[e] = rec_pack(rel, cg * un[i]);
-            us += un[i];
-        }
-        r4[v] = u32x4{o[0], o[1], o[2], o[3]};
+    for (int i = 0; i < TPL; i++) {
+        ro[i] = iu ? rel0 + cg * us : rel0 + cg * (st[i] - p0r);
+        bo[i] = cg * un[i];
+        us += un[i];
     }
+    put_records<TPL>(sm.rel, sm.bwid, lane, ro, bo);
     wave_lds_sync();
     return 0;
 }
@@ -850,12 +868,13 @@ __device__ uint32_t wprologue_gscb(const TileCtx &c, WaveSmem<TW, kClsGscB> &sm,
     const uint64_t abs0 = c.st.data;
     dbase = (uint32_t)(abs0 >> 5);
     uint32_t run = wave_incl_scan(sum) - sum + (uint32_t)(abs0 & 31u);
+    uint32_t ro[TPT];
 #pragma unroll
     for (int j = 0; j < TPT; j++) {
-        const uint32_t tt = lane * TPT + (uint32_t)j;
-        if (tt < c.ntup) sm.rec[tt] = rec_pack(run, bw[j]);
+        ro[j] = run;
         run += bw[j];
     }
+    put_records<TPT>(sm.rel, sm.bwid, lane, ro, bw);
     wave_lds_sync();
     return 0;
 }
@@ -904,7 +923,7 @@ __device__ uint32_t wprologue_afor(const TileCtx &c, WaveSmem<TW, kClsAfor> &sm,
     const uint32_t frel0 = (uint32_t)(fdata0 - 32ull * dbase);
     // frame i of the tile marks its first tuple with i + 1 and records
     // {base, b} with base + t * b the bit offset of tile tuple t of it
-    zero_markers<SM::TTM>(sm.rec, lane);
+    zero_markers<SM::TTM>(sm.rel, lane);
     wave_lds_sync();
     uint2 *info = reinterpret_cast<uint2 *>(sm.data);
     uint32_t st_t = ic - csum, off = ib - bsum;
@@ -915,13 +934,13 @@ __device__ uint32_t wprologue_afor(const TileCtx &c, WaveSmem<TW, kClsAfor> &sm,
         const uint32_t j0 = i == 0u ? sub0 : 0u;
         if (cnt[j]) {
             info[i] = make_uint2(frel0 + off + j0 * b - st_t * b, b);
-            if (st_t < c.ntup) sm.rec[st_t] = i + 1u;
+            if (st_t < c.ntup) sm.rel[st_t] = (uint16_t)(i + 1u);
         }
         st_t += cnt[j];
         off += (cnt[j] ? cnt[j] + j0 : 0u) * b;
     }
     wave_lds_sync();
-    expand_records<SM::TTM>(sm.rec, info, lane);
+    expand_records<SM::TTM>(sm.rel, sm.bwid, info, lane);
     return 0;
 }
 
@@ -1305,7 +1324,7 @@ struct TileRun {
 template <int TW, int CLS>
 __device__ __forceinline__ auto tile_recs(const WaveSmem<TW, CLS> &sm) {
     if constexpr (CLS == kClsPfd) return RecBlk{sm.brec};
-    else return RecArr{sm.rec};
+    else return RecArr{sm.rel, sm.bwid};
 }
 
 // Data rows [r0, r1) of a tile, from the tile starts at its two ends (a
@@ -1393,7 +1412,7 @@ __device__ __forceinline__ void tile_setup(const DecodeArgs &a, const ListDesc &
         const uint32_t lr = tile_recs(sm)(c.ntup - 1u);
         span = min(t.nrow, ((lr >> 6) + (lr & 63u) + 31u) >> 5);
     }
-    t.staged = span * t.kq <= (uint32_t)SM::NDATA;
+    t.staged = (span + 1u) * t.kq <= (uint32_t)SM::NB;
     bool wrote = false;
     if (t.staged && span) {
         if (EARLY && early && dbase == r0 && span * t.kq <= nch) {
