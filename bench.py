@@ -232,6 +232,9 @@ def main():
     ap.add_argument("--pfd-tile", type=int, default=0, help="force the Group-PFD tile size (with --tile)")
     ap.add_argument("--locate-stream", action="store_true",
                     help="run the locate kernels on a second stream, ahead of the other kernels")
+    ap.add_argument("--carry-pass", type=int, default=0, choices=(0, 1, 2),
+                    help="carries of delta lists: 1 look-back in the decode pass, 2 tile-sum pass and carry "
+                         "scan, 0 the library default")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the decode path is built and measured on a single "
@@ -259,13 +262,14 @@ def main():
     # the timed plan: autotuned tiles, the whole run captured in one hipGraph
     plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=args.tile, locate_stream=args.locate_stream,
                    pfd_tile_ints=args.pfd_tile or (4096 if args.tile else 0),
-                   autotune=args.tile == 0, use_graph=True)
+                   autotune=args.tile == 0, use_graph=True, carry_pass=args.carry_pass)
     cfg = plan.config()
     log("plan: %s (%.1fs)" % (cfg, time.time() - t))
     # the same tiles with HIP events between the phases (direct launches), for
     # the per-phase times and the dominant kernel's duration
     tplan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=cfg["tile_ints"], pfd_tile_ints=cfg["pfd_tile_ints"],
-                    locate_stream=args.locate_stream, timing_slots=args.steps + args.warmup)
+                    locate_stream=args.locate_stream, timing_slots=args.steps + args.warmup,
+                    carry_pass=args.carry_pass)
 
     elapsed = timed(plan, d_s, d_o, args.steps, args.warmup, torch)
     t_events = timed(tplan, d_s, d_o, args.steps, args.warmup, torch)
@@ -316,7 +320,7 @@ def main():
             ds2 = gc.to_device(s2)
             do2 = torch.empty(int(oo2[-1]), dtype=torch.int32, device="cuda")
             p2 = gc.Plan(ctx, de2, h2, ds2, do2, tile_ints=cfg["tile_ints"],
-                         pfd_tile_ints=cfg["pfd_tile_ints"], timing_slots=args.steps)
+                         pfd_tile_ints=cfg["pfd_tile_ints"], timing_slots=args.steps, carry_pass=args.carry_pass)
             el = timed(p2, ds2, do2, args.steps, 2, torch)
             t2 = p2.timings(args.steps)
             c2 = sub[0]["cls"]
