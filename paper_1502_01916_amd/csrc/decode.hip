@@ -47,7 +47,6 @@ typedef __attribute__((address_space(1))) u32x4 gu32x4;
 // Small helpers.
 
 constexpr uint32_t kEpochMask = 0x3FFFFFFFu;
-constexpr int kLocWords = kChunkWords / 64;  // control words per lane: one wave per chunk
 
 __device__ __forceinline__ uint32_t epoch_next(uint32_t e) {
     return ((e + 1u) & kEpochMask) ? ((e + 1u) & kEpochMask) : 1u;
@@ -168,20 +167,23 @@ __device__ __forceinline__ uint32_t locate_words(const HeaderFields &h, uint32_t
     }
 }
 
-// One lane's view of a control chunk: its kLocWords consecutive words and
-// their aggregate (tuples, exception words, component data bits).
+// One lane's view of a control chunk of 64 * W words (one wave per chunk):
+// its W consecutive words and their aggregate (tuples, exception words,
+// component data bits).
+template <int W>
 struct LocThread {
     HeaderFields h;
     bool ok, bad;
     uint32_t k, T, TT, D, nwords, wbase;
-    uint32_t word[kLocWords];
+    uint32_t word[W];
     uint32_t vt, ve, vd;
 };
 
 // The header comes from the host's copy in the list descriptor (validated
 // when the plan was made): the decode tiles compare the stream's own header
 // with it, so the locate pass does not wait for that load.
-__device__ __forceinline__ void locate_thread(const ListDesc &L, uint32_t chunk, uint32_t lane, LocThread &t) {
+template <int W>
+__device__ __forceinline__ void locate_thread(const ListDesc &L, uint32_t chunk, uint32_t lane, LocThread<W> &t) {
     const uint32_t *S = L.stream;
     const uint32_t n = L.n, C = L.C, D = L.D;
     t.ok = header_fields(L.w0, t.h);
@@ -190,24 +192,35 @@ __device__ __forceinline__ void locate_thread(const ListDesc &L, uint32_t chunk,
     t.TT = L.tile_ints >> t.h.lk;
     t.D = D;
     t.nwords = t.ok ? locate_words(t.h, t.T, C, D) : 0u;
-    t.wbase = chunk * (uint32_t)kChunkWords + lane * (uint32_t)kLocWords;
+    t.wbase = (chunk * 64u + lane) * (uint32_t)W;
     t.bad = !t.ok;
     t.vt = t.ve = t.vd = 0;
     const uint32_t *ctrl = S + 4;
     const HeaderFields &h = t.h;
-    // 16-byte loads (the control area is a whole number of them), with no
-    // branch between them; a group past the chunk's words reads the header
+    // 16-byte (8-byte at W = 2) loads, inside the control area (a whole
+    // number of 16-byte groups), with no branch between them; a group past
+    // the chunk's words reads the header
+    static_assert(W == 2 || W % 4 == 0, "words per lane");
+    if constexpr (W == 2) {
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+        typedef __attribute__((address_space(1))) u32x2 gu32x2;
+        const uint32_t w = t.wbase;
+        const u32x2 v = *(const gu32x2 *)(w < t.nwords ? ctrl + w : S);
+        t.word[0] = w < t.nwords ? v.x : 0u;
+        t.word[1] = w + 1u < t.nwords ? v.y : 0u;
+    } else {
 #pragma unroll
-    for (int g = 0; g < kLocWords; g += 4) {
-        const uint32_t w = t.wbase + (uint32_t)g;
-        const u32x4 v = *(const gu32x4 *)(w < t.nwords ? ctrl + w : S);
-        t.word[g] = w < t.nwords ? v.x : 0u;
-        t.word[g + 1] = w + 1u < t.nwords ? v.y : 0u;
-        t.word[g + 2] = w + 2u < t.nwords ? v.z : 0u;
-        t.word[g + 3] = w + 3u < t.nwords ? v.w : 0u;
+        for (int g = 0; g < W; g += 4) {
+            const uint32_t w = t.wbase + (uint32_t)g;
+            const u32x4 v = *(const gu32x4 *)(w < t.nwords ? ctrl + w : S);
+            t.word[g] = w < t.nwords ? v.x : 0u;
+            t.word[g + 1] = w + 1u < t.nwords ? v.y : 0u;
+            t.word[g + 2] = w + 2u < t.nwords ? v.z : 0u;
+            t.word[g + 3] = w + 3u < t.nwords ? v.w : 0u;
+        }
     }
 #pragma unroll
-    for (int q = 0; q < kLocWords; q++) {
+    for (int q = 0; q < W; q++) {
         const uint32_t w = t.wbase + (uint32_t)q;
         if (w >= t.nwords) continue;
         const uint32_t wd = t.word[q];
@@ -277,6 +290,7 @@ __device__ __forceinline__ bool locate_item(const LocateArgs &a, uint32_t item, 
 }
 
 // Aggregate of every control chunk (a wave per chunk).
+template <int W>
 __global__ __launch_bounds__(kThreads) void gc_locate_reduce(LocateArgs a) {
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t lane = threadIdx.x & 63u;
@@ -284,8 +298,8 @@ __global__ __launch_bounds__(kThreads) void gc_locate_reduce(LocateArgs a) {
     ListDesc L;
     uint32_t chunk, list;
     if (locate_item(a, item, L, chunk, list)) {
-        LocThread t;
-        locate_thread(L, chunk, lane, t);
+        LocThread<W> t;
+        locate_thread<W>(L, chunk, lane, t);
         const uint32_t tt = wave_sum(t.vt), te = wave_sum(t.ve), td = wave_sum(t.vd);
         if (t.bad) latch(a.status, kErrLocate);
         if (lane == 0) {
@@ -337,6 +351,7 @@ __global__ __launch_bounds__(kThreads) void gc_locate_scan(LocateArgs a) {
 
 // Tile starts from the chunk prefixes, tagged with this run's epoch (a
 // wave per chunk).
+template <int W>
 __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t lane = threadIdx.x & 63u;
@@ -345,8 +360,8 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
     uint32_t chunk, list;
     if (locate_item(a, item, L, chunk, list)) {
         const uint32_t epoch = *(const gu32 *)&a.state->epoch;   // advanced by the reduce kernel
-        LocThread t;
-        locate_thread(L, chunk, lane, t);
+        LocThread<W> t;
+        locate_thread<W>(L, chunk, lane, t);
         const uint32_t xt = wave_incl_scan(t.vt) - t.vt;
         const uint32_t xe = wave_incl_scan(t.ve) - t.ve;
         const uint32_t xd = wave_incl_scan(t.vd) - t.vd;
@@ -380,7 +395,7 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
             uint32_t m = unary ? base_t / TT + 1u : max(1u, (t0 + TT - 1u) / TT);
             uint32_t B = m * TT;
 #pragma unroll
-            for (int q = 0; q < kLocWords; q++) {
+            for (int q = 0; q < W; q++) {
                 const uint32_t w = t.wbase + (uint32_t)q;
                 if (w >= t.nwords) break;
                 const uint32_t wd = t.word[q];
@@ -1646,12 +1661,16 @@ int codec_class(uint32_t w0) {
     }
 }
 
-int launch_locate(const LocateArgs &a, hipStream_t s) {
+// chunk_words: kChunkWords or kChunkWordsSmall, as the items were counted.
+int launch_locate(const LocateArgs &a, int chunk_words, hipStream_t s) {
     if (!a.total_items) return 0;
+    if (chunk_words != kChunkWords && chunk_words != kChunkWordsSmall) return -2;
     const dim3 grid((a.total_items + kWaves - 1) / kWaves);
-    hipLaunchKernelGGL(gc_locate_reduce, grid, dim3(kThreads), 0, s, a);
+    if (chunk_words == kChunkWords) hipLaunchKernelGGL(gc_locate_reduce<kChunkWords / 64>, grid, dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL(gc_locate_reduce<kChunkWordsSmall / 64>, grid, dim3(kThreads), 0, s, a);
     hipLaunchKernelGGL(gc_locate_scan, dim3((a.total_scan + kWaves - 1) / kWaves), dim3(kThreads), 0, s, a);
-    hipLaunchKernelGGL(gc_locate_emit, grid, dim3(kThreads), 0, s, a);
+    if (chunk_words == kChunkWords) hipLaunchKernelGGL(gc_locate_emit<kChunkWords / 64>, grid, dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL(gc_locate_emit<kChunkWordsSmall / 64>, grid, dim3(kThreads), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

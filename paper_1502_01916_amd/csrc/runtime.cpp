@@ -24,7 +24,7 @@
 
 namespace gcdev {
 int codec_class(uint32_t w0);
-int launch_locate(const LocateArgs &a, hipStream_t s);
+int launch_locate(const LocateArgs &a, int chunk_words, hipStream_t s);
 int launch_carry_scan(const CarryArgs &a, hipStream_t s);
 int launch_decode(int tile, int cls, int mode, const DecodeArgs &a, hipStream_t s);
 }  // namespace gcdev
@@ -280,10 +280,10 @@ CarryArgs make_carry_args(const ListDesc *lists, const uint32_t *scan_list, cons
     return a;
 }
 
-uint32_t list_chunks(const HeaderFields &h, uint32_t n, uint32_t C, uint32_t D) {
+uint32_t list_chunks(const HeaderFields &h, uint32_t n, uint32_t C, uint32_t D, uint32_t chunk_words) {
     const uint32_t T = (n + (uint32_t)h.k - 1u) >> h.lk;
     const uint32_t nw = locate_words_host(h, T, C, D);
-    return std::max(1u, (nw + kChunkWords - 1u) / kChunkWords);
+    return std::max(1u, (nw + chunk_words - 1u) / chunk_words);
 }
 
 bool is_delta(uint32_t w0) {
@@ -311,10 +311,12 @@ DecodeArgs single_args(const ListDesc &L, int cls, Scratch &sc, Status *st) {
 }
 
 // Launches every pass of one list on stream s (the per-list paths).
-gc_status launch_one(const ListDesc &L, int cls, Scratch &sc, Status *st, hipStream_t s, bool fused) {
+// chunk_words: the control words per locate item that L.nchunks counts.
+gc_status launch_one(const ListDesc &L, int cls, Scratch &sc, Status *st, hipStream_t s, bool fused,
+                     int chunk_words) {
     if (L.ntiles > 1) {
         LocateArgs a = make_locate_args(nullptr, nullptr, nullptr, L, L.nchunks, 1, cls, sc, st);
-        if (launch_locate(a, s)) return GC_EDEVICE;
+        if (launch_locate(a, chunk_words, s)) return GC_EDEVICE;
     }
     const int tile = (int)L.tile_ints;
     const DecodeArgs d = single_args(L, cls, sc, st);
@@ -342,7 +344,7 @@ void build_tables(gc_plan *p) {
         if (L.ntiles > 1) {
             HeaderFields h;
             header_fields(L.w0, h);
-            L.nchunks = list_chunks(h, L.n, L.C, L.D);
+            L.nchunks = list_chunks(h, L.n, L.C, L.D, kChunkWords);
         }
     }
     // Locate items, tiles and carry scans are numbered class by class, so
@@ -460,7 +462,7 @@ gc_status launch_all_locate(gc_plan *p, hipStream_t s) {
     LocateArgs a = make_locate_args(p->d_lists, p->d_item_a, p->d_item_s, none, p->total_a, p->total_s, 0, p->sc,
                                     p->ctx->status);
     a.item_lo = 0;
-    return launch_locate(a, s) ? GC_EDEVICE : GC_OK;
+    return launch_locate(a, kChunkWords, s) ? GC_EDEVICE : GC_OK;
 }
 
 // The class that reports the locate time: with the serial schedule the
@@ -479,7 +481,7 @@ gc_status launch_class_locate(gc_plan *p, int c, hipStream_t s) {
     LocateArgs a = make_locate_args(p->d_lists, p->d_item_a, p->d_item_s + r.lsc_lo, none, r.loc_count,
                                     r.lsc_count, c, p->sc, p->ctx->status);
     a.item_lo = r.loc_lo;
-    return launch_locate(a, s) ? GC_EDEVICE : GC_OK;
+    return launch_locate(a, kChunkWords, s) ? GC_EDEVICE : GC_OK;
 }
 
 // Launches the tile sums and carry scan (delta lists of more than one tile)
@@ -803,13 +805,13 @@ gc_status gc_decode(gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words, 
     L.stream_words = stream_words;
     L.n = n;
     L.ntiles = (uint32_t)((n + (size_t)tile - 1) / (size_t)tile);
-    L.nchunks = L.ntiles > 1 ? list_chunks(h, n, h_header[2], h_header[3]) : 0u;
+    L.nchunks = L.ntiles > 1 ? list_chunks(h, n, h_header[2], h_header[3], kChunkWordsSmall) : 0u;
     L.tile_ints = (uint32_t)tile;
     L.w0 = h_header[0];
     L.C = h_header[2];
     L.D = h_header[3];
     if (gc_status rc = ctx->single.reserve(L.ntiles + 1, L.nchunks)) return rc;
-    return launch_one(L, cls, ctx->single, ctx->status, (hipStream_t)hip_stream, kDefaultFused);
+    return launch_one(L, cls, ctx->single, ctx->status, (hipStream_t)hip_stream, kDefaultFused, kChunkWordsSmall);
 }
 
 gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists, const uint32_t *h_headers,
@@ -916,7 +918,8 @@ gc_status gc_decode_each(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_o
         if (L.n == 0) continue;
         L.stream = d_streams + plan->stream_off[i];
         L.out = d_out + plan->out_off[i];
-        if (gc_status rc = launch_one(L, plan->cls[i], plan->sc, plan->ctx->status, s, plan->fused)) return rc;
+        if (gc_status rc = launch_one(L, plan->cls[i], plan->sc, plan->ctx->status, s, plan->fused, kChunkWords))
+            return rc;
     }
     return GC_OK;
 }
