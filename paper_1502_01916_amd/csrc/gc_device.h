@@ -7,7 +7,7 @@ namespace gcdev {
 
 constexpr int kThreads = 256;          // threads per workgroup (4 wave64)
 constexpr int kWaves = kThreads / 64;
-constexpr int kChunkWords = 512;       // control words per locate work item (one wave, 8 per lane)
+constexpr int kChunkWords = 256;       // control words per locate work item (one wave, 4 per lane)
 constexpr int kChunkWordsSmall = 128;  // the same for a single list decoded alone (2 per lane)
 constexpr int kClasses = 5;                 // decode kernel classes (codec families)
 
