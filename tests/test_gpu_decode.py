@@ -198,6 +198,43 @@ def test_lookback_long_lists(torch_cuda, ctx, codec, kw):
         plan.close()
 
 
+def test_widest_tiles_full_width(torch_cuda, ctx):
+    """4096-integer tiles whose values are all 32 bits wide (gaps of 2^31 and
+    more, plus a TF list of 2^32 - 1): the bit offsets of a tile's tuples then
+    run up to 1024 * 32, the largest a tuple record holds.  Every codec, one
+    batch, both carry modes."""
+    torch = torch_cuda
+    rng = np.random.default_rng(4096)
+    streams, lists = [], []
+    for i, (name, codec, kw) in enumerate(VARIANTS):
+        n = 3 * 4096 + 100 + 37 * i
+        if i % 2 == 0:
+            g = rng.integers(1 << 31, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+            x, delta = O.prefix_sum(g), True
+        else:
+            x, delta = np.full(n, 0xFFFFFFFF, np.uint32), False
+        p = O.params(codec, delta=delta, cg=kw.get("cg", 1), ld=kw.get("ld", O.LD_CU),
+                     pfd_pos=kw.get("pfd_pos", 0), zeta=kw.get("zeta", (1, 10)))
+        streams.append(O.encode(x, p))
+        lists.append(x)
+    lengths = np.array([x.size for x in lists], np.int64)
+    offs = np.concatenate([[0], np.cumsum([x.size for x in streams])]).astype(np.int64)
+    flat = np.concatenate(streams)
+    descs, headers, out_offs = gc.batch_layout(flat, offs, lengths, align=4)
+    d_s = gc.to_device(flat)
+    d_o = torch.full((int(out_offs[-1]),), -1, dtype=torch.int32, device="cuda")
+    want = np.concatenate(lists)
+    for carry in (gc.CARRY_SUM_PASS, gc.CARRY_LOOKBACK):
+        say("full-width 4096 tiles carry", carry)
+        plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=4096, pfd_tile_ints=4096, carry_pass=carry)
+        d_o.fill_(-1)
+        plan.decode_batch(d_s, d_o)
+        rc, det = ctx.sync_status()
+        assert rc == gc.OK, det
+        assert np.array_equal(gc.unpad(gc.to_host(d_o), out_offs, lengths), want), carry
+        plan.close()
+
+
 def test_autotuned_plan(torch_cuda, ctx, tmp_path, monkeypatch):
     torch = torch_cuda
     monkeypatch.setenv("GC_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
