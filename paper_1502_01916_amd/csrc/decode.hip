@@ -720,27 +720,36 @@ __device__ __forceinline__ void expand_records(uint16_t *rel, uint8_t *bwa, cons
 // 64), read straight from the control words; a wave scan of their tuple
 // counts per round places them, and each scatters its unit marker and record
 // base for expand_records.
-template <int TW>
-__device__ uint32_t wprologue_sim(const TileCtx &c, WaveSmem<TW, kClsSim> &sm, uint32_t lane, uint32_t &dbase) {
+template <int TW, int CE>
+__device__ uint32_t wprologue_sim(const TileCtx &c, WaveSmem<TW, kClsSim> &sm, uint32_t lane, uint32_t &dbase,
+                                  const uint32_t (&ce)[CE], bool cok) {
     using SM = WaveSmem<TW, kClsSim>;
     const uint32_t S_total = c.D >> c.lk;
     const uint32_t s_first = c.st.unit, sub0 = c.st.sub;
     const uint32_t s_end = c.has_en ? c.en.unit + (c.en.sub ? 1u : 0u) : S_total;
     const uint32_t nsel = s_end - s_first;
-    const uint32_t cw1 = (s_end + 7u) >> 3;
-    if (!(s_end <= S_total && s_end > s_first && nsel <= c.TT + 1u && cw1 <= c.C)) return kErrRange;
+    const uint32_t cw0 = s_first >> 3, cw1 = (s_end + 7u) >> 3;
+    if (!(s_end <= S_total && s_end > s_first && nsel <= c.TT + 1u && cw1 <= c.C && cok)) return kErrRange;
+    static_assert(64 * CE * 4 <= SM::NREC, "the selector words are staged in the width array");
     zero_markers<SM::TTM>(sm.rel, lane);
+    // the selector words, loaded before the prologue, staged in the width
+    // array (written only once the records are expanded)
+    uint32_t *cws = reinterpret_cast<uint32_t *>(sm.bwid);
+#pragma unroll
+    for (int v = 0; v < CE; v++) {
+        const uint32_t i = (uint32_t)v * 64u + lane;
+        if (i < cw1 - cw0) cws[i] = ce[v];
+    }
     dbase = s_first;
-    const gu32 *ctrl = (const gu32 *)c.ctrl;
     uint2 *info = reinterpret_cast<uint2 *>(sm.data);
     bool bad = false;
     uint32_t base = 0;   // tuples of the tile before this round's selectors
-    wave_lds_sync();     // markers zeroed before the scatter
+    wave_lds_sync();     // markers zeroed and words staged before the scatter
     for (uint32_t i0 = 0; i0 < nsel; i0 += 64u) {
         const uint32_t i = i0 + lane;
         const bool in = i < nsel;
         const uint32_t g = s_first + i;
-        const uint32_t sel = in ? (ctrl[g >> 3] >> (4u * (g & 7u))) & 15u : 0u;
+        const uint32_t sel = in ? (cws[(g >> 3) - cw0] >> (4u * (g & 7u))) & 15u : 0u;
         const uint32_t j0 = i == 0u ? sub0 : 0u;
         const uint32_t num = sim_num(sel);
         const bool okj = sel < 10u && num > j0;
@@ -772,8 +781,9 @@ __device__ uint32_t wprologue_sim(const TileCtx &c, WaveSmem<TW, kClsSim> &sm, u
 // spans the bits after the previous terminator up to its own (incomplete
 // units: not across a byte, so it starts at the byte boundary at the
 // latest), and its data follow the data of the codes before it.
-template <int TW>
-__device__ uint32_t wprologue_gscu(const TileCtx &c, WaveSmem<TW, kClsGscU> &sm, uint32_t lane, uint32_t &dbase) {
+template <int TW, int CE>
+__device__ uint32_t wprologue_gscu(const TileCtx &c, WaveSmem<TW, kClsGscU> &sm, uint32_t lane, uint32_t &dbase,
+                                   const uint32_t (&ce)[CE], bool cok) {
     using SM = WaveSmem<TW, kClsGscU>;
     constexpr int TPL = SM::TTM / 64;
     const uint32_t cg = (uint32_t)c.h.cg, umax = 32u / cg;
@@ -782,15 +792,22 @@ __device__ uint32_t wprologue_gscu(const TileCtx &c, WaveSmem<TW, kClsGscU> &sm,
     const uint32_t p1 = c.has_en ? c.en.unit : 32u * c.C;
     const uint32_t cw0 = p0 >> 5, cw1 = (p1 + 31u) >> 5;
     const uint32_t nctrl = cw1 - cw0;
-    if (!(p1 >= p0 && cw1 <= c.C && nctrl <= (uint32_t)SM::NCTRL)) return kErrRange;
-    const gu32 *ctrl = (const gu32 *)c.ctrl;
-    for (uint32_t i = lane; i < nctrl; i += 64u) {
+    if (!(p1 >= p0 && cw1 <= c.C && nctrl <= (uint32_t)SM::NCTRL && cok)) return kErrRange;
+    // bits outside the tile's [p0, p1) read as 1
+    auto put = [&](uint32_t i, uint32_t v) {
         const uint32_t gw = cw0 + i;
-        uint32_t v = ctrl[gw];
         if (gw == cw0 && (p0 & 31u)) v |= (1u << (p0 & 31u)) - 1u;
         if (gw == (p1 >> 5) && (p1 & 31u)) v |= ~((1u << (p1 & 31u)) - 1u);
         sm.ctrl[i] = v;
+    };
+    // the first 64 * CE words were loaded before the prologue
+#pragma unroll
+    for (int v = 0; v < CE; v++) {
+        const uint32_t i = (uint32_t)v * 64u + lane;
+        if (i < nctrl) put(i, ce[v]);
     }
+    const gu32 *ctrl = (const gu32 *)c.ctrl;
+    for (uint32_t i = 64u * CE + lane; i < nctrl; i += 64u) put(i, ctrl[cw0 + i]);
     const uint64_t abs0 = iu ? c.st.data : (uint64_t)cg * p0;
     dbase = (uint32_t)(abs0 >> 5);
     const uint32_t p0r = p0 & 31u;   // bit positions count from 32 * cw0
@@ -1342,6 +1359,31 @@ __device__ __forceinline__ auto tile_recs(const WaveSmem<TW, CLS> &sm) {
     else return RecArr{sm.rel, sm.bwid};
 }
 
+// Control words [w0, w0 + nw) that the prologue of a tile reads, from the
+// tile starts at its two ends: Group-Simple, the words of its selectors;
+// unary Group-Scheme, the words of its codes.  CE words per lane of them are
+// loaded before the prologue.
+template <int TW, int CLS>
+constexpr int ctrl_early_words() {
+    return CLS == kClsSim ? (TW / 32 + 2 + 63) / 64 : CLS == kClsGscU ? 3 : 0;
+}
+
+template <int CLS>
+__device__ __forceinline__ void tile_ctrl_words(const TileCtx &c, uint32_t &w0, uint32_t &nw) {
+    w0 = nw = 0;
+    if constexpr (CLS == kClsSim) {
+        const uint32_t s_end = c.has_en ? c.en.unit + (c.en.sub ? 1u : 0u) : c.D >> c.lk;
+        w0 = c.st.unit >> 3;
+        const uint32_t w1 = (s_end + 7u) >> 3;
+        nw = s_end > c.st.unit && w1 > w0 ? w1 - w0 : 0u;
+    } else if constexpr (CLS == kClsGscU) {
+        const uint32_t p1 = c.has_en ? c.en.unit : 32u * c.C;
+        w0 = c.st.unit >> 5;
+        const uint32_t w1 = (p1 + 31u) >> 5;
+        nw = p1 >= c.st.unit && w1 > w0 ? w1 - w0 : 0u;
+    }
+}
+
 // Data rows [r0, r1) of a tile, from the tile starts at its two ends (a
 // list's last tile runs to the end of the data area).
 template <int CLS>
@@ -1366,6 +1408,23 @@ __device__ __forceinline__ void tile_setup(const DecodeArgs &a, const ListDesc &
     // loads are under way
     const u32x4 hd = *(const gu32x4 *)L.stream;
     const bool ok = tile_ctx(L, m, pre.s0, pre.s1, (uint32_t)TW, loc_tag, c);
+    // The prologue's control words are loaded first, all at once (no branch
+    // between the loads and their wait), so that the prologue waits for
+    // them alone; a word past the range reads the stream header.
+    constexpr int CE = ctrl_early_words<TW, CLS>();
+    uint32_t ce[CE > 0 ? CE : 1];
+    bool cok = false;
+    if constexpr (CE > 0) {
+        uint32_t w0, nw;
+        tile_ctrl_words<CLS>(c, w0, nw);
+        cok = ok && nw > 0u && w0 + nw <= c.C;
+        const gu32 *g = cok ? (const gu32 *)c.ctrl + w0 : (const gu32 *)L.stream;
+#pragma unroll
+        for (int v = 0; v < CE; v++) {
+            const uint32_t i = (uint32_t)v * 64u + lane;
+            ce[v] = g[cok && i < nw ? i : 0u];
+        }
+    }
     // The data rows are loaded into registers before the prologue reads the
     // control words, so that the two loads wait together; they go to LDS
     // once the prologue no longer needs it.  Tiles whose rows do not fit
@@ -1410,8 +1469,8 @@ __device__ __forceinline__ void tile_setup(const DecodeArgs &a, const ListDesc &
     uint32_t dbase = 0, err = ok ? 0u : kErrLocate;
     t.ps = PatchSrc{sm.bmap, sm.vbit, sm.xcnt, nullptr, ExcSrc{nullptr, nullptr, 0u, false}, false};
     if (!err) {
-        if constexpr (CLS == kClsSim) err = wprologue_sim<TW>(c, sm, lane, dbase);
-        else if constexpr (CLS == kClsGscU) err = wprologue_gscu<TW>(c, sm, lane, dbase);
+        if constexpr (CLS == kClsSim) err = wprologue_sim<TW, CE>(c, sm, lane, dbase, ce, cok);
+        else if constexpr (CLS == kClsGscU) err = wprologue_gscu<TW, CE>(c, sm, lane, dbase, ce, cok);
         else if constexpr (CLS == kClsGscB) err = wprologue_gscb<TW>(c, sm, lane, dbase);
         else if constexpr (CLS == kClsAfor) err = wprologue_afor<TW>(c, sm, lane, dbase);
         else err = wprologue_pfd<TW>(c, sm, lane, dbase, L.stream_words, t.ps.xs);
