@@ -1268,8 +1268,10 @@ __device__ __forceinline__ uint32_t tile_quads(Rec rec, uint32_t tsh, uint32_t k
                                                uint32_t nrow, uint32_t nint, uint32_t lane, bool delta,
                                                uint32_t carry, uint32_t *out, bool vec, const PatchSrc &ps) {
     uint32_t s = 0;
+    const int nr = min(R, (int)((nint + 255u) >> 8));   // rounds that hold integers (wave-uniform)
 #pragma unroll 4
     for (int r = 0; r < R; r++) {
+        if (r >= nr) continue;
         const uint32_t q = (uint32_t)r * 64u + lane;
         u32x4 v = {0u, 0u, 0u, 0u};
         if (4u * q < nint) {
@@ -1305,8 +1307,11 @@ __device__ __forceinline__ uint32_t quads_lds(Rec rec, const u32x4 *data, uint32
                                               bool vec, const PatchSrc &ps) {
     uint32_t s = 0;
     constexpr int U = PATCH ? 2 : (R < 4 ? R : 4);   // deeper unrolling only raised register use
+    // rounds that hold integers (wave-uniform; all of them in a full tile)
+    const int nr = FULL ? R : min(R, (int)((nint + 255u) >> 8));
 #pragma unroll U
     for (int r = 0; r < R; r++) {
+        if (r >= nr) continue;
         const uint32_t q = (uint32_t)r * 64u + lane;
         uint32_t rc = rec(q >> tsh);
         if constexpr (!FULL) rc = 4u * q < nint ? rc : 0u;
