@@ -232,9 +232,10 @@ def main():
     ap.add_argument("--pfd-tile", type=int, default=0, help="force the Group-PFD tile size (with --tile)")
     ap.add_argument("--locate-stream", action="store_true",
                     help="run the locate kernels on a second stream, ahead of the other kernels")
-    ap.add_argument("--carry-pass", type=int, default=0, choices=(0, 1, 2),
+    ap.add_argument("--carry-pass", type=int, default=0, choices=(0, 1, 2, 3),
                     help="carries of delta lists: 1 look-back in the decode pass, 2 tile-sum pass and carry "
-                         "scan, 0 the library default")
+                         "scan, 3 look-back for lists of up to 64 tiles and the tile-sum pass for longer ones, "
+                         "0 the library default")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the decode path is built and measured on a single "

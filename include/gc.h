@@ -162,7 +162,9 @@ typedef struct {
                                 publishing its sum and reading those before
                                 it (decoupled look-back); 2 a tile-sum pass
                                 and a carry scan ahead of the decode pass;
-                                0 = default (2)                                */
+                                3 look-back for lists of at most 64 tiles
+                                (one window of flags), the tile-sum pass for
+                                longer ones; 0 = default (3)                   */
     uint32_t reserved;       /* zero */
 } gc_plan_opts;
 
@@ -180,9 +182,9 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
 gc_status gc_plan_destroy(gc_plan *plan);
 
 /* Decodes every list of the plan: the locate pass, then per codec class the
- * tile-sum pass over its delta lists of more than one tile, the carry scan
- * and the decode pass (with opts->carry_pass 1, the decode pass alone),
- * replayed as one hipGraph when the plan was created with use_graph.       */
+ * tile-sum pass over its delta lists whose tiles take their carries from it
+ * (see opts->carry_pass), the carry scan and the decode pass, replayed as one
+ * hipGraph when the plan was created with use_graph.                       */
 gc_status gc_decode_batch(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_out,
                           void *hip_stream);
 
@@ -214,9 +216,8 @@ gc_status gc_decode_each(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_o
 gc_status gc_plan_timings(gc_plan *plan, uint32_t max_runs, float *ms, uint32_t *nruns);
 
 /* Reports the chosen configuration of a plan: the wave-tile and Group-PFD
- * tile sizes, the decode tiles of one run and, of those, the tiles whose
- * sums a later tile's carry needs (summed in the decode pass, or by the sum
- * pass with carry_pass 2).  Any pointer may be NULL.                       */
+ * tile sizes, the decode tiles of one run and, of those, the tiles of its
+ * tile-sum pass.  Any pointer may be NULL.                                 */
 gc_status gc_plan_config(const gc_plan *plan, uint32_t *tile_ints, uint32_t *pfd_tile_ints,
                          uint64_t *tiles, uint64_t *sum_tiles);
 

@@ -1649,7 +1649,9 @@ __device__ void wave_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, ui
     uint32_t carry0 = 0;
     if (delta && L.ntiles > 1u) {
         if constexpr (MODE == kModeFused) {
-            carry0 = tile_carry(a, gi, m, L.ntiles, tile_total<TW, CLS>(t, sm, lane), loc_tag, lane);
+            carry0 = L.ntiles <= a.lb_max_tiles
+                         ? tile_carry(a, gi, m, L.ntiles, tile_total<TW, CLS>(t, sm, lane), loc_tag, lane)
+                         : pre.carry;
         } else {
             carry0 = pre.carry;
         }

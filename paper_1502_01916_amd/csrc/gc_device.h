@@ -92,6 +92,9 @@ struct DecodeArgs {
     uint32_t *carry;            // per tile: sum of its gaps (sum pass), then the
                                 // exclusive prefix of those sums in its list
     unsigned long long *flags;  // single-pass carry: per tile epoch:30 | state:2 | value:32
+    uint32_t lb_max_tiles;      // mode 2: lists of at most this many tiles take their
+                                // carries by look-back, longer ones from carry[]
+    uint32_t pad2;
     const RunState *loc_state;
     Status *status;
 };

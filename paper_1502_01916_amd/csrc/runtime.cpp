@@ -35,10 +35,16 @@ namespace {
 
 constexpr int kDefaultWaveTile = 2048;
 constexpr int kDefaultPfdTile = 4096;
-// Carries of delta lists: found in the decode pass by decoupled look-back
-// (true), or by a tile-sum pass and a carry scan ahead of it (false, the
-// faster of the two on the mixed batches measured).
-constexpr bool kDefaultFused = false;
+// Carries of delta lists: a list of at most lb_max tiles finds them in the
+// decode pass by decoupled look-back (one window of flags covers a list of
+// up to 64 tiles); longer lists take a tile-sum pass and a carry scan ahead
+// of the decode pass.  0: every list takes the tile-sum pass.  The default
+// mixes the two: on the mixed cfg2 batch it took 0.93 ms per step, against
+// 0.98 ms with the tile-sum pass alone and 1.00 ms with look-back alone
+// (thresholds of 16 to 128 tiles measured alike, 512 worse).
+constexpr uint32_t kLookbackAll = 0xFFFFFFFFu;
+constexpr uint32_t kLookbackHybrid = 64u;
+constexpr uint32_t kDefaultLbMax = kLookbackHybrid;
 constexpr int kWaveTiles[3] = {1024, 2048, 4096};
 constexpr int kPfdTiles[2] = {2048, 4096};
 constexpr int kClsPfd = 4;
@@ -226,7 +232,7 @@ struct gc_plan {
     std::vector<hipEvent_t> ev;                // kEvPerSlot per timing slot
     hipStream_t aux = nullptr;                 // timing: the locate stream
     bool serial = true;                        // no locate stream
-    bool fused = kDefaultFused;                // carries found in the decode pass
+    uint32_t lb_max = kDefaultLbMax;           // lists of at most this many tiles: look-back carries
     uint32_t slots = 0;
     uint64_t runs = 0;
 };
@@ -312,20 +318,21 @@ DecodeArgs single_args(const ListDesc &L, int cls, Scratch &sc, Status *st) {
 
 // Launches every pass of one list on stream s (the per-list paths).
 // chunk_words: the control words per locate item that L.nchunks counts.
-gc_status launch_one(const ListDesc &L, int cls, Scratch &sc, Status *st, hipStream_t s, bool fused,
+gc_status launch_one(const ListDesc &L, int cls, Scratch &sc, Status *st, hipStream_t s, uint32_t lb_max,
                      int chunk_words) {
     if (L.ntiles > 1) {
         LocateArgs a = make_locate_args(nullptr, nullptr, nullptr, L, L.nchunks, 1, cls, sc, st);
         if (launch_locate(a, chunk_words, s)) return GC_EDEVICE;
     }
     const int tile = (int)L.tile_ints;
-    const DecodeArgs d = single_args(L, cls, sc, st);
-    if (fused) return launch_decode(tile, cls, 2, d, s) ? GC_EDEVICE : GC_OK;
-    if (L.ntiles > 1 && is_delta(L.w0)) {
+    DecodeArgs d = single_args(L, cls, sc, st);
+    d.lb_max_tiles = lb_max;
+    const bool lookback = L.ntiles <= lb_max;
+    if (!lookback && L.ntiles > 1 && is_delta(L.w0)) {
         if (launch_decode(tile, cls, 1, d, s)) return GC_EDEVICE;
         if (launch_carry_scan(make_carry_args(nullptr, nullptr, L, 1, sc), s)) return GC_EDEVICE;
     }
-    if (launch_decode(tile, cls, 0, d, s)) return GC_EDEVICE;
+    if (launch_decode(tile, cls, lookback ? 2 : 0, d, s)) return GC_EDEVICE;
     return GC_OK;
 }
 
@@ -372,7 +379,7 @@ void build_tables(gc_plan *p) {
             for (size_t i = 0; i < p->nlists; i++) {
                 ListDesc &L = p->h_lists[i];
                 if (p->cls[i] != c || L.ntiles == 0) continue;
-                const bool summed = L.ntiles > 1 && is_delta(L.w0);
+                const bool summed = L.ntiles > 1 && is_delta(L.w0) && L.ntiles > p->lb_max;
                 if (summed != (pass == 0)) continue;
                 L.tile_base = tb;
                 for (uint32_t m = 0; m < L.ntiles; m++) p->tile_list.push_back((uint32_t)i);
@@ -493,11 +500,6 @@ gc_status launch_class_work(gc_plan *p, int c, hipStream_t s, hipEvent_t mid = n
     std::memset(&none, 0, sizeof(none));
     const int tile = c == kClsPfd ? p->tile_p : p->tile_w;
     const int epoch_cls = p->serial ? 0 : c;   // whose locate epoch tags the tile starts
-    if (p->fused) {
-        if (mid) HIP_OK(hipEventRecord(mid, s));
-        DecodeArgs d = make_decode_args(p->d_lists, none, r.lo, r.count, epoch_cls, p->sc, p->ctx->status);
-        return launch_decode(tile, c, 2, d, s) ? GC_EDEVICE : GC_OK;
-    }
     if (r.sum) {
         DecodeArgs d = make_decode_args(p->d_lists, none, r.lo, r.sum, epoch_cls, p->sc, p->ctx->status);
         if (launch_decode(tile, c, 1, d, s)) return GC_EDEVICE;
@@ -506,7 +508,8 @@ gc_status launch_class_work(gc_plan *p, int c, hipStream_t s, hipEvent_t mid = n
     }
     if (mid) HIP_OK(hipEventRecord(mid, s));
     DecodeArgs d = make_decode_args(p->d_lists, none, r.lo, r.count, epoch_cls, p->sc, p->ctx->status);
-    return launch_decode(tile, c, 0, d, s) ? GC_EDEVICE : GC_OK;
+    d.lb_max_tiles = p->lb_max;
+    return launch_decode(tile, c, p->lb_max ? 2 : 0, d, s) ? GC_EDEVICE : GC_OK;
 }
 
 // Launches a whole run on stream s: without an auxiliary stream, one locate
@@ -674,7 +677,7 @@ std::string plan_key(const gc_plan *p) {
     int lm = 0;
     while ((1ull << lm) < mean) lm++;
     std::string key = "gfx950:k" + std::to_string(1 << lk) + ":n2^" + std::to_string(lg) + ":mean2^" +
-                      std::to_string(lm) + (p->fused ? ":c1" : ":c2") + ":mix";
+                      std::to_string(lm) + ":c" + std::to_string(p->lb_max) + ":mix";
     for (int c = 0; c < kClasses; c++)
         key += (c ? "-" : "") + std::to_string(total ? per_cls[c] * 8 / total : 0);
     return key;
@@ -811,7 +814,7 @@ gc_status gc_decode(gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words, 
     L.C = h_header[2];
     L.D = h_header[3];
     if (gc_status rc = ctx->single.reserve(L.ntiles + 1, L.nchunks)) return rc;
-    return launch_one(L, cls, ctx->single, ctx->status, (hipStream_t)hip_stream, kDefaultFused, kChunkWordsSmall);
+    return launch_one(L, cls, ctx->single, ctx->status, (hipStream_t)hip_stream, kDefaultLbMax, kChunkWordsSmall);
 }
 
 gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists, const uint32_t *h_headers,
@@ -824,7 +827,7 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     if (opts) o = *opts;
     if (o.tile_ints && !valid_wave_tile(o.tile_ints)) return GC_EINVAL;
     if (o.pfd_tile_ints && !valid_pfd_tile(o.pfd_tile_ints)) return GC_EINVAL;
-    if (o.schedule > 1u || o.carry_pass > 2u || o.reserved) return GC_EINVAL;
+    if (o.schedule > 1u || o.carry_pass > 3u || o.reserved) return GC_EINVAL;
     if ((o.autotune || o.use_graph) && nlists && (!d_streams || !d_out)) return GC_EINVAL;
     gc_plan *p = new (std::nothrow) gc_plan();
     if (!p) return GC_ENOMEM;
@@ -834,7 +837,8 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     p->tile_p = o.pfd_tile_ints ? (int)o.pfd_tile_ints : kDefaultPfdTile;
     p->use_graph = o.use_graph != 0;
     p->serial = o.schedule == 0u;
-    p->fused = o.carry_pass ? o.carry_pass == 1u : kDefaultFused;
+    p->lb_max = o.carry_pass == 1u ? kLookbackAll : o.carry_pass == 2u ? 0u
+              : o.carry_pass == 3u ? kLookbackHybrid : kDefaultLbMax;
     p->slots = std::min<uint32_t>(o.timing_slots, 4096u);
     p->h_lists.resize(nlists);
     p->cls.resize(nlists);
@@ -918,7 +922,7 @@ gc_status gc_decode_each(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_o
         if (L.n == 0) continue;
         L.stream = d_streams + plan->stream_off[i];
         L.out = d_out + plan->out_off[i];
-        if (gc_status rc = launch_one(L, plan->cls[i], plan->sc, plan->ctx->status, s, plan->fused, kChunkWords))
+        if (gc_status rc = launch_one(L, plan->cls[i], plan->sc, plan->ctx->status, s, plan->lb_max, kChunkWords))
             return rc;
     }
     return GC_OK;

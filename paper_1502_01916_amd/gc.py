@@ -64,7 +64,7 @@ class PlanOpts(ctypes.Structure):
 
 
 # how the tiles of a delta list get their carries (gc_plan_opts.carry_pass)
-CARRY_DEFAULT, CARRY_LOOKBACK, CARRY_SUM_PASS = 0, 1, 2
+CARRY_DEFAULT, CARRY_LOOKBACK, CARRY_SUM_PASS, CARRY_HYBRID = 0, 1, 2, 3
 
 
 class AdamOpts(ctypes.Structure):

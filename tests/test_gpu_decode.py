@@ -133,7 +133,7 @@ def make_batch(rng, nlists, kmix=(4,), maxlen=40000):
 
 @pytest.mark.parametrize("tiles", [(1024, 2048), (2048, 4096), (4096, 4096)])
 @pytest.mark.parametrize("graph", [False, True])
-@pytest.mark.parametrize("carry", [gc.CARRY_SUM_PASS, gc.CARRY_LOOKBACK])
+@pytest.mark.parametrize("carry", [gc.CARRY_DEFAULT, gc.CARRY_SUM_PASS, gc.CARRY_LOOKBACK])
 def test_batch_parity(torch_cuda, ctx, tiles, graph, carry):
     torch = torch_cuda
     tile, pfd_tile = tiles
@@ -170,8 +170,10 @@ def test_batch_parity(torch_cuda, ctx, tiles, graph, carry):
 def test_lookback_long_lists(torch_cuda, ctx, codec, kw):
     """Single-pass carries over lists of hundreds of tiles, so that a look-back
     crosses several 64-tile windows, next to short lists; replayed from a
-    graph (each replay a new epoch of flags) and checked every time, then
-    the same plan with the two-pass carry."""
+    graph (each replay a new epoch of flags) and checked every time; then the
+    same plan with the two-pass carry, and with the mixed one (look-back for
+    the lists of up to 64 tiles, the tile-sum pass for the longer ones, in
+    the same launches)."""
     torch = torch_cuda
     rng = np.random.default_rng(int(codec) + 900)
     lengths = np.array([700 * 1024 + 333, 5, 2048, 300 * 1024, 1, 129 * 1024 + 1], np.int64)
@@ -185,7 +187,7 @@ def test_lookback_long_lists(torch_cuda, ctx, codec, kw):
     d_s = gc.to_device(flat)
     d_o = torch.full((int(out_offs[-1]),), -1, dtype=torch.int32, device="cuda")
     want = np.concatenate(lists)
-    for carry in (gc.CARRY_LOOKBACK, gc.CARRY_SUM_PASS):
+    for carry in (gc.CARRY_LOOKBACK, gc.CARRY_SUM_PASS, gc.CARRY_HYBRID):
         say("look-back long lists codec", codec, "carry", carry)
         plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=1024, pfd_tile_ints=2048, use_graph=True,
                        carry_pass=carry)
@@ -224,7 +226,7 @@ def test_widest_tiles_full_width(torch_cuda, ctx):
     d_s = gc.to_device(flat)
     d_o = torch.full((int(out_offs[-1]),), -1, dtype=torch.int32, device="cuda")
     want = np.concatenate(lists)
-    for carry in (gc.CARRY_SUM_PASS, gc.CARRY_LOOKBACK):
+    for carry in (gc.CARRY_SUM_PASS, gc.CARRY_LOOKBACK, gc.CARRY_HYBRID):
         say("full-width 4096 tiles carry", carry)
         plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=4096, pfd_tile_ints=4096, carry_pass=carry)
         d_o.fill_(-1)
