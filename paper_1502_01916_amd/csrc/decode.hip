@@ -1585,8 +1585,17 @@ __device__ __forceinline__ void flag_store(unsigned long long *f, unsigned long 
     __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The first window of flags before tile gi (m > 0), read before the tile's
+// own sum is ready so that its latency overlaps the sum.
+__device__ __forceinline__ unsigned long long lookback_first(const DecodeArgs &a, uint32_t gi, uint32_t m,
+                                                             uint32_t lane) {
+    const uint32_t first = gi - m;
+    const uint32_t j = gi >= first + 1u + lane ? gi - 1u - lane : first;
+    return __hip_atomic_load(a.flags + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ uint32_t tile_carry(const DecodeArgs &a, uint32_t gi, uint32_t m, uint32_t ntiles, uint32_t s,
-                               uint32_t epoch, uint32_t lane) {
+                               uint32_t epoch, uint32_t lane, unsigned long long f0) {
     unsigned long long *flags = a.flags;
     const uint32_t ep = epoch & kEpochMask;
     const unsigned long long tag = (unsigned long long)ep << 34;
@@ -1599,10 +1608,11 @@ __device__ uint32_t tile_carry(const DecodeArgs &a, uint32_t gi, uint32_t m, uin
     const uint32_t first = gi - m;
     uint32_t acc = 0, base = gi;
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-    for (;;) {
+    for (bool fresh = true;; fresh = false) {
         const bool in = base >= first + 1u + lane;
         const uint32_t j = in ? base - 1u - lane : first;
-        const unsigned long long f = __hip_atomic_load(flags + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long f =
+            fresh ? f0 : __hip_atomic_load(flags + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t st = (uint32_t)(f >> 34) == ep ? (uint32_t)(f >> 32) & 3u : 0u;
         const uint64_t incl = __ballot(in && st == 2u), wait = __ballot(in && st == 0u);
         if (incl) {
@@ -1649,9 +1659,12 @@ __device__ void wave_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, ui
     uint32_t carry0 = 0;
     if (delta && L.ntiles > 1u) {
         if constexpr (MODE == kModeFused) {
-            carry0 = L.ntiles <= a.lb_max_tiles
-                         ? tile_carry(a, gi, m, L.ntiles, tile_total<TW, CLS>(t, sm, lane), loc_tag, lane)
-                         : pre.carry;
+            if (L.ntiles <= a.lb_max_tiles) {
+                const unsigned long long f0 = m ? lookback_first(a, gi, m, lane) : 0ull;
+                carry0 = tile_carry(a, gi, m, L.ntiles, tile_total<TW, CLS>(t, sm, lane), loc_tag, lane, f0);
+            } else {
+                carry0 = pre.carry;
+            }
         } else {
             carry0 = pre.carry;
         }
