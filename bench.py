@@ -57,9 +57,13 @@ def variants(gc):
 
 
 CLASS_NAMES = ["group-simple", "group-scheme-unary", "group-scheme-binary", "group-afor", "group-pfd"]
-# the decode pass of each class (third template argument: 0 decode, 1 tile sums)
-KERNEL_NAMES = ["gc_wave_kernel<%d, 0, 0>", "gc_wave_kernel<%d, 1, 0>", "gc_wave_kernel<%d, 2, 0>",
-                "gc_wave_kernel<%d, 3, 0>", "gc_wave_kernel<%d, 4, 0>"]
+
+
+def kernel_name(cls, tile, carry_pass):
+    """The decode kernel of a codec class as the profiler names it: tile size,
+    class, and mode 2 (look-back carries) unless every carry comes from the
+    tile-sum pass (mode 0)."""
+    return "gc_wave_kernel<%d, %d, %d>" % (tile, cls, 0 if carry_pass == 2 else 2)
 
 
 def codec_class(gc, codec, kw):
@@ -297,7 +301,8 @@ def main():
     log("dominant kernel: %s decode pass %.3f ms, %.0f GB/s" % (CLASS_NAMES[cls], dec_avg, achieved))
     if not verified:
         raise SystemExit("decoded output differs from the generated lists")
-    traffic = read_traffic(len(descs), KERNEL_NAMES[cls] % cfg["tile_ints" if cls != 4 else "pfd_tile_ints"])
+    kname = kernel_name(cls, cfg["tile_ints"] if cls != 4 else cfg["pfd_tile_ints"], args.carry_pass)
+    traffic = read_traffic(len(descs), kname)
 
     extra = {}
     if not args.no_extra:
@@ -380,7 +385,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": KERNEL_NAMES[cls] % (cfg["tile_ints"] if cls != 4 else cfg["pfd_tile_ints"]),
+            "kernel": kname,
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
