@@ -176,7 +176,9 @@ def test_lookback_long_lists(torch_cuda, ctx, codec, kw):
     the same launches)."""
     torch = torch_cuda
     rng = np.random.default_rng(int(codec) + 900)
-    lengths = np.array([700 * 1024 + 333, 5, 2048, 300 * 1024, 1, 129 * 1024 + 1], np.int64)
+    # 64 and 65 tiles of 1024: the two sides of the mixed mode's threshold
+    lengths = np.array([700 * 1024 + 333, 5, 2048, 300 * 1024, 1, 129 * 1024 + 1, 64 * 1024, 64 * 1024 + 1],
+                       np.int64)
     lists = [np.sort(rng.choice(1 << 31, int(n), replace=False)).astype(np.uint32) for n in lengths]
     lists[3] = O.prefix_sum(np.full(int(lengths[3]), (1 << 31) - 1, np.uint32))   # wrapping sums
     p = O.params(codec, delta=True, cg=kw.get("cg", 1), ld=kw.get("ld", O.LD_CU))
