@@ -1,32 +1,33 @@
 // decode.hip -- gfx950 kernels that decode Group-codec streams and restore
 // docIDs by prefix sum.
 //
-//   locate  Scans the control areas of multi-tile lists (1024 control words
-//           per work item) and records where every decode tile starts: the
-//           control unit, the tuples of it that belong to the previous tile,
-//           the component data bit offset and (Group-PFD) the exception word
-//           offset.  Three kernels: chunk aggregates, their scan within each
-//           list, tile starts.
+//   locate  Scans the control areas of multi-tile lists, one wave per chunk
+//           of 256 control words (128 for a list decoded alone), and records
+//           where every decode tile starts: the control unit, the tuples of
+//           it that belong to the previous tile, the component data bit
+//           offset of the tile's first tuple and (Group-PFD) the exception
+//           word offset.  Three kernels: chunk aggregates, their scan within
+//           each list, tile starts.
 //
-//   decode  One kernel per codec class.  Group-Simple, Group-Scheme (unary
-//           and binary descriptors) and Group-AFOR decode one tile per wave64;
-//           Group-PFD one tile per workgroup, since its exception patching
-//           needs a tile-sized LDS buffer.  A tile's control units are parsed
-//           into per-tuple records (component bit offset, width) in LDS; each
-//           lane then produces four consecutive integers per round from two
-//           16-byte data rows read through the vector cache, with a 64-bit
-//           funnel shift (v_alignbit_b32) and a mask.  Group-PFD patches
-//           exceptions in LDS (linked chains, or bitmap ranks by ballot and
-//           mbcnt).
+//   decode  One kernel per codec class, one tile per wave64 (Group-Simple,
+//           Group-Scheme with unary or binary descriptors, Group-AFOR,
+//           Group-PFD).  A tile's control words and data rows are loaded
+//           first, together; its control units are then parsed into
+//           per-tuple records (component bit offset, width) in LDS, the rows
+//           are staged in LDS, and each lane produces four consecutive
+//           integers per round from two 16-byte rows with a 64-bit funnel
+//           shift (v_alignbit_b32) and a mask.  Group-PFD marks its
+//           exceptions in an LDS bitmap (linked chains, or the block's tuple
+//           and component masks) and patches them by rank.
 //
 //   carry   A delta list of more than one tile is prefix-summed across its
-//           tiles by reduce-then-scan: a sum pass decodes every tile and
-//           stores the sum of its gaps, one workgroup per list scans those
-//           sums into exclusive carries, and the decode pass adds the carry
-//           to its in-tile scan.  No tile ever waits for another, so every
-//           kernel is a plain grid with no work queue, no spinning and no
-//           atomics (the one exception: the first error is latched).  The sum
-//           pass costs a second read of the compressed data only.
+//           tiles.  A short list (one window of 64 tiles) does it in the
+//           decode pass: each tile sums its staged rows, publishes the sum
+//           and reads its carry from the flags of the tiles before it
+//           (decoupled look-back, a bounded wait).  A longer list takes a
+//           sum pass that stores the sum of each tile's gaps, one workgroup
+//           per list that scans those sums into exclusive carries, and the
+//           decode pass that adds the carry to its in-tile scan.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -515,7 +516,6 @@ struct TileCtx {
     TileInfo st, en;
 };
 
-__device__ __forceinline__ uint32_t rec_pack(uint32_t rel, uint32_t bw) { return (rel << 6) | bw; }
 
 // Fills the tile context of tile m (global tile gi) of list L from the
 // host's copy of the header (validated when the plan was made; the stream's
@@ -624,7 +624,7 @@ struct WaveSmem {
         u32x4 data[NB];
         uint32_t ctrl[4 * NB];
     };
-    // tuple records: bit offset (from the tile's first row, < 2^15) and width;
+    // tuple records: bit offset (from the tile's first row, < 2^16) and width;
     // the offsets hold unit markers (Group-Simple, Group-AFOR) or terminator
     // positions + 1 (unary Group-Scheme) while the records are built.
     // Group-PFD computes its records from its block words instead.
