@@ -82,7 +82,7 @@ struct LocateArgs {
 };
 
 // One decode launch covers the tiles [lo, lo + count) of the tile arrays:
-// a wave (Group-PFD: a workgroup) per tile.
+// a wave per tile.
 struct DecodeArgs {
     const ListDesc *lists;      // batch table, or nullptr for `single`
     ListDesc single;
