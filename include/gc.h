@@ -174,7 +174,11 @@ typedef struct {
  * (optionally) an instantiated hipGraph; it allocates everything here, never
  * at execute.  With opts->autotune the plan times candidate tile sizes on the
  * device buffers given (d_streams, d_out) and keeps the fastest; results are
- * cached in a JSON file named by $GC_AUTOTUNE_CACHE when set.  GC_EINVAL for
+ * cached in a JSON file named by $GC_AUTOTUNE_CACHE when set.  For tests of
+ * the look-back's bounded wait only, $GC_TEST_LOOKBACK_STALL = t (ticks of
+ * the 100 MHz real-time counter) makes the plan's tiles withhold their
+ * flags, so every look-back gives up after t ticks and reports GC_ECORRUPT
+ * (detail 12) through gc_sync_status.  GC_EINVAL for
  * a tile size not listed above or nonzero reserved words.                  */
 gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists,
                          const uint32_t *h_headers, const gc_plan_opts *opts,

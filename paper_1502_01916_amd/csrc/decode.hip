@@ -1580,6 +1580,8 @@ enum : int { kModeDecode = 0, kModeSum = 1, kModeFused = 2 };
 // index, which every workgroup dispatcher starts first; the wait is bounded
 // all the same, and on expiry the error is latched.
 constexpr uint64_t kLookbackTicks = 2000000ull;   // 20 ms of the 100 MHz real-time counter
+// (a.lb_stall_ticks, set only by tests of the bounded wait, stops the tiles
+// from publishing and replaces the limit, so that every look-back expires)
 
 __device__ __forceinline__ void flag_store(unsigned long long *f, unsigned long long v) {
     __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1599,7 +1601,9 @@ __device__ uint32_t tile_carry(const DecodeArgs &a, uint32_t gi, uint32_t m, uin
     unsigned long long *flags = a.flags;
     const uint32_t ep = epoch & kEpochMask;
     const unsigned long long tag = (unsigned long long)ep << 34;
-    const bool last = m + 1u >= ntiles;
+    const bool stall = a.lb_stall_ticks != 0u;
+    const uint64_t limit = stall ? (uint64_t)a.lb_stall_ticks : kLookbackTicks;
+    const bool last = m + 1u >= ntiles || stall;
     if (m == 0u) {
         if (!last && lane == 0) flag_store(flags + gi, tag | (2ull << 32) | s);
         return 0u;
@@ -1629,7 +1633,7 @@ __device__ uint32_t tile_carry(const DecodeArgs &a, uint32_t gi, uint32_t m, uin
             base -= 64u;
             continue;
         }
-        if (__builtin_amdgcn_s_memrealtime() - t0 > kLookbackTicks) {
+        if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
             if (lane == 0) latch(a.status, kErrTimeout);
             break;
         }

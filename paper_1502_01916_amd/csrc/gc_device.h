@@ -94,7 +94,9 @@ struct DecodeArgs {
     unsigned long long *flags;  // single-pass carry: per tile epoch:30 | state:2 | value:32
     uint32_t lb_max_tiles;      // mode 2: lists of at most this many tiles take their
                                 // carries by look-back, longer ones from carry[]
-    uint32_t pad2;
+    uint32_t lb_stall_ticks;    // 0, or (tests of the bounded wait only): tiles do not
+                                // publish their flags and a look-back gives up after
+                                // this many ticks of the real-time counter
     const RunState *loc_state;
     Status *status;
 };

@@ -233,6 +233,7 @@ struct gc_plan {
     hipStream_t aux = nullptr;                 // timing: the locate stream
     bool serial = true;                        // no locate stream
     uint32_t lb_max = kDefaultLbMax;           // lists of at most this many tiles: look-back carries
+    uint32_t lb_stall = 0;                     // tests only: see GC_TEST_LOOKBACK_STALL
     uint32_t slots = 0;
     uint64_t runs = 0;
 };
@@ -509,6 +510,7 @@ gc_status launch_class_work(gc_plan *p, int c, hipStream_t s, hipEvent_t mid = n
     if (mid) HIP_OK(hipEventRecord(mid, s));
     DecodeArgs d = make_decode_args(p->d_lists, none, r.lo, r.count, epoch_cls, p->sc, p->ctx->status);
     d.lb_max_tiles = p->lb_max;
+    d.lb_stall_ticks = p->lb_stall;
     return launch_decode(tile, c, p->lb_max ? 2 : 0, d, s) ? GC_EDEVICE : GC_OK;
 }
 
@@ -839,6 +841,9 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     p->serial = o.schedule == 0u;
     p->lb_max = o.carry_pass == 1u ? kLookbackAll : o.carry_pass == 2u ? 0u
               : o.carry_pass == 3u ? kLookbackHybrid : kDefaultLbMax;
+    // tests of the look-back's bounded wait: tiles stop publishing their
+    // flags and a look-back gives up after this many 100 MHz ticks
+    if (const char *e = std::getenv("GC_TEST_LOOKBACK_STALL")) p->lb_stall = (uint32_t)std::strtoul(e, nullptr, 10);
     p->slots = std::min<uint32_t>(o.timing_slots, 4096u);
     p->h_lists.resize(nlists);
     p->cls.resize(nlists);

@@ -202,6 +202,39 @@ def test_lookback_long_lists(torch_cuda, ctx, codec, kw):
         plan.close()
 
 
+def test_lookback_bounded_wait(torch_cuda, ctx, monkeypatch):
+    """The look-back's wait is bounded.  With the plan's tiles withholding
+    their flags (a condition only this test sets, from the host), every
+    look-back gives up after its limit, the kernels finish, and the device
+    reports the expiry (detail 12).  A plan made without it afterwards decodes
+    the same batch exactly."""
+    torch = torch_cuda
+    rng = np.random.default_rng(1212)
+    lengths = np.array([3 * 1024 + 5, 7 * 1024, 40 * 1024 + 1, 2 * 1024], np.int64)
+    lists = [np.sort(rng.choice(1 << 30, int(n), replace=False)).astype(np.uint32) for n in lengths]
+    streams = [O.encode(x, O.params(O.SIMPLE, delta=True)) for x in lists]
+    offs = np.concatenate([[0], np.cumsum([x.size for x in streams])]).astype(np.int64)
+    flat = np.concatenate(streams)
+    descs, headers, out_offs = gc.batch_layout(flat, offs, lengths, align=4)
+    d_s = gc.to_device(flat)
+    d_o = torch.full((int(out_offs[-1]),), -1, dtype=torch.int32, device="cuda")
+    say("look-back bounded wait")
+    monkeypatch.setenv("GC_TEST_LOOKBACK_STALL", "20000")   # 200 us per look-back
+    plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=1024, carry_pass=gc.CARRY_LOOKBACK)
+    plan.decode_batch(d_s, d_o)
+    rc, det = ctx.sync_status()
+    assert rc == gc.ECORRUPT and det == 12, (rc, det)
+    plan.close()
+    monkeypatch.delenv("GC_TEST_LOOKBACK_STALL")
+    plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=1024, carry_pass=gc.CARRY_LOOKBACK)
+    d_o.fill_(-1)
+    plan.decode_batch(d_s, d_o)
+    rc, det = ctx.sync_status()
+    assert rc == gc.OK, det
+    assert np.array_equal(gc.unpad(gc.to_host(d_o), out_offs, lengths), np.concatenate(lists))
+    plan.close()
+
+
 def test_widest_tiles_full_width(torch_cuda, ctx):
     """4096-integer tiles whose values are all 32 bits wide (gaps of 2^31 and
     more, plus a TF list of 2^32 - 1): the bit offsets of a tile's tuples then
