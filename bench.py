@@ -272,7 +272,7 @@ def main():
     log("plan: %s (%.1fs)" % (cfg, time.time() - t))
     # the same tiles with HIP events between the phases (direct launches), for
     # the per-phase times and the dominant kernel's duration
-    tplan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=cfg["tile_ints"], pfd_tile_ints=cfg["pfd_tile_ints"],
+    tplan = gc.Plan(ctx, descs, headers, d_s, d_o, class_tiles=cfg["class_tiles"],
                     locate_stream=args.locate_stream, timing_slots=args.steps + args.warmup,
                     carry_pass=args.carry_pass)
 
@@ -301,7 +301,7 @@ def main():
     log("dominant kernel: %s decode pass %.3f ms, %.0f GB/s" % (CLASS_NAMES[cls], dec_avg, achieved))
     if not verified:
         raise SystemExit("decoded output differs from the generated lists")
-    kname = kernel_name(cls, cfg["tile_ints"] if cls != 4 else cfg["pfd_tile_ints"], args.carry_pass)
+    kname = kernel_name(cls, cfg["class_tiles"][cls], args.carry_pass)
     traffic = read_traffic(len(descs), kname)
 
     extra = {}
@@ -325,8 +325,8 @@ def main():
             de2, h2, oo2 = gc.batch_layout(s2, o2, l2, align=4)
             ds2 = gc.to_device(s2)
             do2 = torch.empty(int(oo2[-1]), dtype=torch.int32, device="cuda")
-            p2 = gc.Plan(ctx, de2, h2, ds2, do2, tile_ints=cfg["tile_ints"],
-                         pfd_tile_ints=cfg["pfd_tile_ints"], timing_slots=args.steps, carry_pass=args.carry_pass)
+            p2 = gc.Plan(ctx, de2, h2, ds2, do2, class_tiles=cfg["class_tiles"], timing_slots=args.steps,
+                         carry_pass=args.carry_pass)
             el = timed(p2, ds2, do2, args.steps, 2, torch)
             t2 = p2.timings(args.steps)
             c2 = sub[0]["cls"]
@@ -379,6 +379,7 @@ def main():
             "bits_per_int": round(32.0 * streams.size / total, 3),
             "tile_ints": cfg["tile_ints"],
             "pfd_tile_ints": cfg["pfd_tile_ints"],
+            "class_tile_ints": cfg["class_tiles"],
             "tiles": cfg["tiles"],
             "sum_tiles": cfg["sum_tiles"],
             "verified_bit_exact": verified,

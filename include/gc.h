@@ -156,6 +156,9 @@ typedef struct {
                                 pass over every class, then class by class the
                                 other passes; 1: per-class locate kernels on a
                                 second stream, ahead of the other kernels      */
+    uint32_t class_tile_ints[5];  /* per codec class (see GC_CLASSES), nonzero
+                                overrides tile_ints / pfd_tile_ints for that
+                                class; the autotuner picks one size per class */
     uint32_t carry_pass;     /* how a tile of a delta list of several tiles gets
                                 its carry (the sum of the list's d-gaps before
                                 it): 1 in the decode pass itself, each tile
@@ -219,11 +222,16 @@ gc_status gc_decode_each(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_o
 #define GC_TIMING_FIELDS (1 + 3 * GC_CLASSES)
 gc_status gc_plan_timings(gc_plan *plan, uint32_t max_runs, float *ms, uint32_t *nruns);
 
-/* Reports the chosen configuration of a plan: the wave-tile and Group-PFD
- * tile sizes, the decode tiles of one run and, of those, the tiles of its
- * tile-sum pass.  Any pointer may be NULL.                                 */
+/* Reports the chosen configuration of a plan: the tile size of its first
+ * non-PFD codec class and of Group-PFD, the decode tiles of one run and, of
+ * those, the tiles of its tile-sum pass.  Any pointer may be NULL.         */
 gc_status gc_plan_config(const gc_plan *plan, uint32_t *tile_ints, uint32_t *pfd_tile_ints,
                          uint64_t *tiles, uint64_t *sum_tiles);
+
+/* The tile size (integers per wave tile) of every codec class of a plan,
+ * GC_CLASSES entries in class order (sizes of classes the plan does not hold
+ * are the defaults).                                                        */
+gc_status gc_plan_class_tiles(const gc_plan *plan, uint32_t *tile_ints);
 
 /* Synchronises hip_stream, then returns (and clears) the first device-side
  * error latched since the previous call: GC_OK or GC_ECORRUPT.  detail, if

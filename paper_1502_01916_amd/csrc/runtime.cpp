@@ -213,7 +213,7 @@ struct ClassRange {
 struct gc_plan {
     gc_ctx *ctx = nullptr;
     size_t nlists = 0;
-    int tile_w = kDefaultWaveTile, tile_p = kDefaultPfdTile;
+    int tile[kClasses] = {kDefaultWaveTile, kDefaultWaveTile, kDefaultWaveTile, kDefaultWaveTile, kDefaultPfdTile};
     ClassRange cr[kClasses];
     uint32_t total_a = 0, total_s = 0, total_t = 0, total_scan = 0;
     bool use_graph = false;
@@ -301,10 +301,11 @@ bool is_delta(uint32_t w0) {
 // A tile must hold at least 32 tuples: every control unit (selector,
 // unary code word, frame, block) spans at most 32 tuples, so the locate pass
 // meets at most one tile boundary per unit.
-int min_wave_tile(const gc_plan *p) {
+int min_class_tile(const gc_plan *p, int c) {
+    if (c == kClsPfd) return 2048;   // whole 32-tuple blocks, up to k = 64
     int t = 1024;
     for (size_t i = 0; i < p->nlists; i++) {
-        if (p->cls[i] == kClsPfd) continue;
+        if (p->cls[i] != c) continue;
         HeaderFields h;
         header_fields(p->h_lists[i].w0, h);
         t = std::max(t, 32 << h.lk);
@@ -339,14 +340,14 @@ gc_status launch_one(const ListDesc &L, int cls, Scratch &sc, Status *st, hipStr
 
 // Builds the tile tables of a plan for its tile sizes.
 void build_tables(gc_plan *p) {
-    p->tile_w = std::max(p->tile_w, min_wave_tile(p));
+    for (int c = 0; c < kClasses; c++) p->tile[c] = std::max(p->tile[c], min_class_tile(p, c));
     p->item_a.clear();
     p->item_s.clear();
     p->tile_list.clear();
     p->scan_list.clear();
     for (size_t i = 0; i < p->nlists; i++) {
         ListDesc &L = p->h_lists[i];
-        L.tile_ints = (uint32_t)(p->cls[i] == kClsPfd ? p->tile_p : p->tile_w);
+        L.tile_ints = (uint32_t)p->tile[p->cls[i]];
         L.ntiles = (uint32_t)((L.n + (uint64_t)L.tile_ints - 1) / (uint64_t)L.tile_ints);
         L.nchunks = 0;
         if (L.ntiles > 1) {
@@ -499,7 +500,7 @@ gc_status launch_class_work(gc_plan *p, int c, hipStream_t s, hipEvent_t mid = n
     const ClassRange &r = p->cr[c];
     ListDesc none;
     std::memset(&none, 0, sizeof(none));
-    const int tile = c == kClsPfd ? p->tile_p : p->tile_w;
+    const int tile = p->tile[c];
     const int epoch_cls = p->serial ? 0 : c;   // whose locate epoch tags the tile starts
     if (r.sum) {
         DecodeArgs d = make_decode_args(p->d_lists, none, r.lo, r.sum, epoch_cls, p->sc, p->ctx->status);
@@ -606,13 +607,13 @@ gc_status plan_run(gc_plan *p, hipStream_t s) {
     return plan_launch(p, s);
 }
 
-// ---- autotune cache: one JSON object {key: [tile, pfd_tile], ...} --------
+// ---- autotune cache: one JSON object {key: [tile of each class], ...} -----
 std::string cache_path() {
     const char *e = std::getenv("GC_AUTOTUNE_CACHE");
     return e ? std::string(e) : std::string();
 }
 
-bool cache_lookup(const std::string &key, int &tile, int &ptile) {
+bool cache_lookup(const std::string &key, int *tiles) {
     const std::string path = cache_path();
     if (path.empty()) return false;
     std::ifstream f(path);
@@ -623,15 +624,17 @@ bool cache_lookup(const std::string &key, int &tile, int &ptile) {
     const std::string pat = "\"" + key + "\": [";
     const size_t at = s.find(pat);
     if (at == std::string::npos) return false;
-    int t = 0, pt = 0;
-    if (std::sscanf(s.c_str() + at + pat.size(), "%d, %d", &t, &pt) != 2) return false;
-    if (!valid_wave_tile((uint32_t)t) || !valid_pfd_tile((uint32_t)pt)) return false;
-    tile = t;
-    ptile = pt;
+    int t[kClasses];
+    static_assert(kClasses == 5, "five classes in the cache format");
+    if (std::sscanf(s.c_str() + at + pat.size(), "%d, %d, %d, %d, %d", &t[0], &t[1], &t[2], &t[3], &t[4]) != 5)
+        return false;
+    for (int c = 0; c < kClasses; c++)   // an entry that fails validation falls back to the defaults
+        if (c == kClsPfd ? !valid_pfd_tile((uint32_t)t[c]) : !valid_wave_tile((uint32_t)t[c])) return false;
+    for (int c = 0; c < kClasses; c++) tiles[c] = t[c];
     return true;
 }
 
-void cache_store(const std::string &key, int tile, int ptile) {
+void cache_store(const std::string &key, const int *tiles) {
     const std::string path = cache_path();
     if (path.empty()) return;
     std::string s;
@@ -654,8 +657,8 @@ void cache_store(const std::string &key, int tile, int ptile) {
         if (k != key) entries.push_back("\"" + k + "\": " + s.substr(lb, rb - lb + 1));
         pos = rb + 1;
     }
-    char buf[64];
-    std::snprintf(buf, sizeof(buf), "[%d, %d]", tile, ptile);
+    char buf[96];
+    std::snprintf(buf, sizeof(buf), "[%d, %d, %d, %d, %d]", tiles[0], tiles[1], tiles[2], tiles[3], tiles[4]);
     entries.push_back("\"" + key + "\": " + buf);
     std::ofstream f(path);
     f << "{\n";
@@ -685,52 +688,57 @@ std::string plan_key(const gc_plan *p) {
     return key;
 }
 
+// Times the candidate tile sizes and keeps, for every codec class, the one
+// whose passes (tile sums, carry scan, decode) took least: one materialised
+// plan per candidate, each class timed by HIP events around its own passes
+// (a class's passes do not depend on the tile sizes of the others).
 gc_status autotune(gc_plan *p, const uint32_t *d_streams, uint32_t *d_out) {
     const std::string key = plan_key(p);
-    int best_w = p->tile_w, best_p = p->tile_p;
-    if (cache_lookup(key, best_w, best_p)) {
-        p->tile_w = best_w;
-        p->tile_p = best_p;
+    int best_t[kClasses];
+    for (int c = 0; c < kClasses; c++) best_t[c] = p->tile[c];
+    if (cache_lookup(key, best_t)) {
+        for (int c = 0; c < kClasses; c++) p->tile[c] = best_t[c];
         return GC_OK;
     }
-    bool has_pfd = false, has_wave = false;
-    for (size_t i = 0; i < p->nlists; i++) (p->cls[i] == kClsPfd ? has_pfd : has_wave) = true;
-    hipEvent_t e0, e1;
-    HIP_OK(hipEventCreate(&e0));
-    HIP_OK(hipEventCreate(&e1));
-    float best = 1e30f;
+    bool present[kClasses] = {};
+    for (size_t i = 0; i < p->nlists; i++) present[p->cls[i]] = true;
+    std::vector<hipEvent_t> ev(kEvPerSlot);
     gc_status rc = GC_OK;
-    const int tw_min = min_wave_tile(p);
-    for (int tw : kWaveTiles) {
-        if ((!has_wave && tw != kDefaultWaveTile) || tw < tw_min) continue;
-        for (int tp : kPfdTiles) {
-            if (!has_pfd && tp != kDefaultPfdTile) continue;
-            p->tile_w = tw;
-            p->tile_p = tp;
-            rc = plan_materialize(p);
-            if (!rc) rc = plan_upload(p, d_streams, d_out);
-            for (int w = 0; w < 2 && !rc; w++) rc = plan_launch(p, nullptr);
-            if (rc) break;
-            HIP_OK(hipEventRecord(e0, nullptr));
-            for (int r = 0; r < 5 && !rc; r++) rc = plan_launch(p, nullptr);
-            HIP_OK(hipEventRecord(e1, nullptr));
-            HIP_OK(hipEventSynchronize(e1));
-            float ms = 0;
-            HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
-                best = ms;
-                best_w = tw;
-                best_p = tp;
+    for (hipEvent_t &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) rc = GC_EDEVICE;
+    float best[kClasses];
+    for (int c = 0; c < kClasses; c++) best[c] = 1e30f;
+    for (int i = 0; i < 3 && !rc; i++) {
+        for (int c = 0; c < kClasses; c++) p->tile[c] = c == kClsPfd ? kPfdTiles[std::min(i, 1)] : kWaveTiles[i];
+        rc = plan_materialize(p);   // raises a class's tile to its minimum
+        if (!rc) rc = plan_upload(p, d_streams, d_out);
+        for (int w = 0; w < 2 && !rc; w++) rc = plan_launch(p, nullptr);
+        float acc[kClasses] = {};
+        for (int r = 0; r < 5 && !rc; r++) {
+            HIP_OK(hipEventRecord(ev[0], nullptr));
+            rc = plan_launch(p, nullptr, nullptr, nullptr, nullptr, ev.data() + 2);
+            HIP_OK(hipEventRecord(ev[1], nullptr));
+            HIP_OK(hipEventSynchronize(ev[1]));
+            for (int c = 0; c < kClasses && !rc; c++) {
+                if (!present[c] || !p->cr[c].count) continue;
+                const hipEvent_t *ce = ev.data() + 2 + 5 * c;
+                float ms = 0;
+                HIP_OK(hipEventElapsedTime(&ms, ce[2], ce[4]));
+                acc[c] += ms;
             }
         }
-        if (rc) break;
+        for (int c = 0; c < kClasses && !rc; c++) {
+            if (present[c] && acc[c] < best[c]) {
+                best[c] = acc[c];
+                best_t[c] = p->tile[c];
+            }
+        }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
     if (rc) return rc;
-    p->tile_w = best_w;
-    p->tile_p = best_p;
-    cache_store(key, best_w, best_p);
+    for (int c = 0; c < kClasses; c++) p->tile[c] = best_t[c];
+    cache_store(key, best_t);
     return GC_OK;
 }
 
@@ -829,14 +837,23 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     if (opts) o = *opts;
     if (o.tile_ints && !valid_wave_tile(o.tile_ints)) return GC_EINVAL;
     if (o.pfd_tile_ints && !valid_pfd_tile(o.pfd_tile_ints)) return GC_EINVAL;
+    bool forced = o.tile_ints || o.pfd_tile_ints;
+    for (int c = 0; c < kClasses; c++) {
+        const uint32_t t = o.class_tile_ints[c];
+        if (t && (c == kClsPfd ? !valid_pfd_tile(t) : !valid_wave_tile(t))) return GC_EINVAL;
+        forced = forced || t;
+    }
     if (o.schedule > 1u || o.carry_pass > 3u || o.reserved) return GC_EINVAL;
     if ((o.autotune || o.use_graph) && nlists && (!d_streams || !d_out)) return GC_EINVAL;
     gc_plan *p = new (std::nothrow) gc_plan();
     if (!p) return GC_ENOMEM;
     p->ctx = ctx;
     p->nlists = nlists;
-    p->tile_w = o.tile_ints ? (int)o.tile_ints : kDefaultWaveTile;
-    p->tile_p = o.pfd_tile_ints ? (int)o.pfd_tile_ints : kDefaultPfdTile;
+    for (int c = 0; c < kClasses; c++) {
+        const uint32_t group = c == kClsPfd ? o.pfd_tile_ints : o.tile_ints;
+        const int dflt = c == kClsPfd ? kDefaultPfdTile : kDefaultWaveTile;
+        p->tile[c] = o.class_tile_ints[c] ? (int)o.class_tile_ints[c] : group ? (int)group : dflt;
+    }
     p->use_graph = o.use_graph != 0;
     p->serial = o.schedule == 0u;
     p->lb_max = o.carry_pass == 1u ? kLookbackAll : o.carry_pass == 2u ? 0u
@@ -875,7 +892,7 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     }
     (void)hipSetDevice(ctx->device);
     gc_status rc = GC_OK;
-    if (o.autotune && nlists && !o.tile_ints && !o.pfd_tile_ints) rc = autotune(p, d_streams, d_out);
+    if (o.autotune && nlists && !forced) rc = autotune(p, d_streams, d_out);
     for (uint32_t i = 0; i < (uint32_t)kEvPerSlot * p->slots && !rc; i++) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) rc = GC_EDEVICE;
@@ -965,10 +982,19 @@ gc_status gc_plan_config(const gc_plan *plan, uint32_t *tile_ints, uint32_t *pfd
         t += plan->cr[c].count;
         st += plan->cr[c].sum;
     }
-    if (tile_ints) *tile_ints = (uint32_t)plan->tile_w;
-    if (pfd_tile_ints) *pfd_tile_ints = (uint32_t)plan->tile_p;
+    int first_wave = 0;   // the first non-PFD class the plan holds
+    for (int c = kClasses - 1; c >= 0; c--)
+        if (c != kClsPfd && plan->cr[c].count) first_wave = c;
+    if (tile_ints) *tile_ints = (uint32_t)plan->tile[first_wave];
+    if (pfd_tile_ints) *pfd_tile_ints = (uint32_t)plan->tile[kClsPfd];
     if (tiles) *tiles = t;
     if (sum_tiles) *sum_tiles = st;
+    return GC_OK;
+}
+
+gc_status gc_plan_class_tiles(const gc_plan *plan, uint32_t *tile_ints) {
+    if (!plan || !tile_ints) return GC_EINVAL;
+    for (int c = 0; c < kClasses; c++) tile_ints[c] = (uint32_t)plan->tile[c];
     return GC_OK;
 }
 

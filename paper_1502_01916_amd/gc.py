@@ -60,7 +60,8 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("tile_ints", ctypes.c_uint32), ("pfd_tile_ints", ctypes.c_uint32),
                 ("use_graph", ctypes.c_uint32), ("autotune", ctypes.c_uint32),
                 ("timing_slots", ctypes.c_uint32), ("schedule", ctypes.c_uint32),
-                ("carry_pass", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("class_tile_ints", ctypes.c_uint32 * 5), ("carry_pass", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 # how the tiles of a delta list get their carries (gc_plan_opts.carry_pass)
@@ -113,6 +114,7 @@ def lib():
         L.gc_decode_batch.argtypes = [vp, vp, vp, vp]
         L.gc_decode_each.argtypes = [vp, vp, vp, vp]
         L.gc_plan_config.argtypes = [vp, u32p, u32p, u64p, u64p]
+        L.gc_plan_class_tiles.argtypes = [vp, u32p]
         L.gc_plan_timings.argtypes = [vp, ctypes.c_uint32, f32p, u32p]
         L.gc_plan_timings.restype = ctypes.c_int
         L.gc_sync_status.argtypes = [vp, vp, u32p]
@@ -134,8 +136,8 @@ def lib():
         L.gc_encode_blocks.argtypes = [vp, vp, sz, i, vp, ctypes.c_uint32, vp, sz, ctypes.POINTER(sz), vp, vp]
         for f in ("gc_encode", "gc_encode_lists", "gc_ctx_create", "gc_ctx_destroy", "gc_decode",
                   "gc_plan_create", "gc_plan_destroy", "gc_decode_batch", "gc_decode_each",
-                  "gc_plan_config", "gc_sync_status", "gc_block_features", "gc_block_sizes",
-                  "gc_blockmix_encode", "gc_mlp_create", "gc_mlp_destroy", "gc_mlp_set_params",
+                  "gc_plan_config", "gc_plan_class_tiles", "gc_sync_status", "gc_block_features",
+                  "gc_block_sizes", "gc_blockmix_encode", "gc_mlp_create", "gc_mlp_destroy", "gc_mlp_set_params",
                   "gc_mlp_get_params", "gc_mlp_forward", "gc_mlp_grad", "gc_mlp_train", "gc_encode_blocks",
                   "gc_mlp_get_state", "gc_mlp_set_state"):
             getattr(L, f).restype = ctypes.c_int
@@ -288,15 +290,16 @@ class Plan:
 
     def __init__(self, ctx: Context, descs, headers, d_streams=None, d_out=None, tile_ints=0,
                  pfd_tile_ints=0, use_graph=False, autotune=False, timing_slots=0, locate_stream=False,
-                 carry_pass=CARRY_DEFAULT):
+                 carry_pass=CARRY_DEFAULT, class_tiles=None):
         self.ctx = ctx
         nl = len(descs)
         arr = (ListDesc * max(nl, 1))()
         for i, d in enumerate(descs):
             arr[i] = d
         hdr = np.ascontiguousarray(headers, dtype=np.uint32).reshape(-1)
+        ct = (ctypes.c_uint32 * 5)(*[int(t) for t in (class_tiles if class_tiles is not None else [0] * 5)])
         opts = PlanOpts(int(tile_ints), int(pfd_tile_ints), int(bool(use_graph)), int(bool(autotune)),
-                        int(timing_slots), int(bool(locate_stream)), int(carry_pass))
+                        int(timing_slots), int(bool(locate_stream)), ct, int(carry_pass))
         self._h = ctypes.c_void_p()
         rc = lib().gc_plan_create(ctx._h, arr, nl, _u32(hdr), ctypes.byref(opts),
                                   _ptr(d_streams) if d_streams is not None else None,
@@ -329,7 +332,10 @@ class Plan:
         n, ns = ctypes.c_uint64(), ctypes.c_uint64()
         _check("gc_plan_config", lib().gc_plan_config(self._h, ctypes.byref(t), ctypes.byref(pt),
                                                       ctypes.byref(n), ctypes.byref(ns)))
-        return dict(tile_ints=t.value, pfd_tile_ints=pt.value, tiles=n.value, sum_tiles=ns.value)
+        ct = (ctypes.c_uint32 * CLASSES)()
+        _check("gc_plan_class_tiles", lib().gc_plan_class_tiles(self._h, ct))
+        return dict(tile_ints=t.value, pfd_tile_ints=pt.value, tiles=n.value, sum_tiles=ns.value,
+                    class_tiles=[int(x) for x in ct])
 
     def close(self):
         if self._h:

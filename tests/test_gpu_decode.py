@@ -272,6 +272,30 @@ def test_widest_tiles_full_width(torch_cuda, ctx):
         plan.close()
 
 
+@pytest.mark.parametrize("class_tiles", [[1024, 4096, 2048, 4096, 2048], [4096, 1024, 4096, 1024, 4096]])
+def test_mixed_class_tiles(torch_cuda, ctx, class_tiles):
+    """A different tile size for the codec classes of one batch (the
+    autotuner's per-class choice), replayed from a graph, every carry mode."""
+    torch = torch_cuda
+    rng = np.random.default_rng(515)
+    flat, offs, lengths, lists = make_batch(rng, 200, kmix=(4, 4, 8))
+    descs, headers, out_offs = gc.batch_layout(flat, offs, lengths, align=4)
+    d_s = gc.to_device(flat)
+    d_o = torch.full((int(out_offs[-1]),), -1, dtype=torch.int32, device="cuda")
+    want = np.concatenate(lists)
+    for carry in (gc.CARRY_DEFAULT, gc.CARRY_SUM_PASS, gc.CARRY_LOOKBACK):
+        say("class tiles", class_tiles, "carry", carry)
+        plan = gc.Plan(ctx, descs, headers, d_s, d_o, class_tiles=class_tiles, use_graph=True, carry_pass=carry)
+        assert plan.config()["class_tiles"] == class_tiles
+        for rep in range(2):
+            d_o.fill_(-1)
+            plan.decode_batch(d_s, d_o)
+            rc, det = ctx.sync_status()
+            assert rc == gc.OK, det
+            assert np.array_equal(gc.unpad(gc.to_host(d_o), out_offs, lengths), want), (carry, rep)
+        plan.close()
+
+
 def test_autotuned_plan(torch_cuda, ctx, tmp_path, monkeypatch):
     torch = torch_cuda
     monkeypatch.setenv("GC_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
@@ -284,13 +308,15 @@ def test_autotuned_plan(torch_cuda, ctx, tmp_path, monkeypatch):
     plan = gc.Plan(ctx, descs, headers, d_s, d_o, autotune=True, use_graph=True)
     cfg = plan.config()
     assert cfg["tile_ints"] in (1024, 2048, 4096) and cfg["pfd_tile_ints"] in (2048, 4096)
+    ct = cfg["class_tiles"]        # one size per codec class
+    assert all(t in (1024, 2048, 4096) for t in ct[:4]) and ct[4] in (2048, 4096)
     assert 1 <= cfg["tiles"] and cfg["sum_tiles"] <= cfg["tiles"]
     plan.decode_batch(d_s, d_o)
     assert ctx.sync_status()[0] == gc.OK
     assert np.array_equal(gc.to_host(d_o)[:int(out_offs[-1])], np.concatenate(lists))
     assert (tmp_path / "tune.json").exists()
     plan2 = gc.Plan(ctx, descs, headers, d_s, d_o, autotune=True)   # served from the cache
-    assert plan2.config()["tile_ints"] == cfg["tile_ints"]
+    assert plan2.config()["class_tiles"] == ct
 
 
 @pytest.mark.parametrize("locate_stream", [False, True])
