@@ -146,7 +146,8 @@ typedef struct {
                                 1024, 2048 or 4096, raised to 32*k for the widest
                                 layout in the batch; 0 = autotuned / default       */
     uint32_t pfd_tile_ints;  /* integers per wave tile of Group-PFD (whole 32-tuple
-                                blocks): 2048 or 4096; 0 = autotuned / default     */
+                                blocks): 1024, 2048 or 4096, raised to 32*k for
+                                the widest layout; 0 = autotuned / default      */
     uint32_t use_graph;      /* 1 = capture the launch sequence in a hipGraph       */
     uint32_t autotune;       /* 1 = time candidate tile sizes at creation           */
     uint32_t timing_slots;   /* > 0: time the kernels of each gc_decode_batch with

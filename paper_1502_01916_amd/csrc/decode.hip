@@ -1770,10 +1770,7 @@ static const void *wave_fn(int cls) {
     case kClsGscU: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsGscU, MODE>);
     case kClsGscB: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsGscB, MODE>);
     case kClsAfor: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsAfor, MODE>);
-    case kClsPfd:
-        // a Group-PFD tile holds whole 32-tuple blocks, up to 2048 integers at k = 64
-        if constexpr (TW >= 2048) return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsPfd, MODE>);
-        return nullptr;
+    case kClsPfd: return reinterpret_cast<const void *>(gc_wave_kernel<TW, kClsPfd, MODE>);
     default: return nullptr;
     }
 }

@@ -46,11 +46,9 @@ constexpr uint32_t kLookbackAll = 0xFFFFFFFFu;
 constexpr uint32_t kLookbackHybrid = 64u;
 constexpr uint32_t kDefaultLbMax = kLookbackHybrid;
 constexpr int kWaveTiles[3] = {1024, 2048, 4096};
-constexpr int kPfdTiles[2] = {2048, 4096};
 constexpr int kClsPfd = 4;
 
 bool valid_wave_tile(uint32_t t) { return t == 1024 || t == 2048 || t == 4096; }
-bool valid_pfd_tile(uint32_t t) { return t == 2048 || t == 4096; }
 
 #define HIP_OK(x)                         \
     do {                                  \
@@ -299,10 +297,10 @@ bool is_delta(uint32_t w0) {
 }
 
 // A tile must hold at least 32 tuples: every control unit (selector,
-// unary code word, frame, block) spans at most 32 tuples, so the locate pass
-// meets at most one tile boundary per unit.
+// unary code word, frame, Group-PFD block) spans at most 32 tuples, so the
+// locate pass meets at most one tile boundary per unit (and a Group-PFD
+// tile holds whole blocks).
 int min_class_tile(const gc_plan *p, int c) {
-    if (c == kClsPfd) return 2048;   // whole 32-tuple blocks, up to k = 64
     int t = 1024;
     for (size_t i = 0; i < p->nlists; i++) {
         if (p->cls[i] != c) continue;
@@ -629,7 +627,7 @@ bool cache_lookup(const std::string &key, int *tiles) {
     if (std::sscanf(s.c_str() + at + pat.size(), "%d, %d, %d, %d, %d", &t[0], &t[1], &t[2], &t[3], &t[4]) != 5)
         return false;
     for (int c = 0; c < kClasses; c++)   // an entry that fails validation falls back to the defaults
-        if (c == kClsPfd ? !valid_pfd_tile((uint32_t)t[c]) : !valid_wave_tile((uint32_t)t[c])) return false;
+        if (!valid_wave_tile((uint32_t)t[c])) return false;
     for (int c = 0; c < kClasses; c++) tiles[c] = t[c];
     return true;
 }
@@ -709,7 +707,7 @@ gc_status autotune(gc_plan *p, const uint32_t *d_streams, uint32_t *d_out) {
     float best[kClasses];
     for (int c = 0; c < kClasses; c++) best[c] = 1e30f;
     for (int i = 0; i < 3 && !rc; i++) {
-        for (int c = 0; c < kClasses; c++) p->tile[c] = c == kClsPfd ? kPfdTiles[std::min(i, 1)] : kWaveTiles[i];
+        for (int c = 0; c < kClasses; c++) p->tile[c] = kWaveTiles[i];
         rc = plan_materialize(p);   // raises a class's tile to its minimum
         if (!rc) rc = plan_upload(p, d_streams, d_out);
         for (int w = 0; w < 2 && !rc; w++) rc = plan_launch(p, nullptr);
@@ -810,7 +808,7 @@ gc_status gc_decode(gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words, 
     const int cls = codec_class(h_header[0]);
     HeaderFields h;
     header_fields(h_header[0], h);
-    const int tile = cls == kClsPfd ? ctx->tile_p : std::max(ctx->tile_w, 32 << h.lk);
+    const int tile = std::max(cls == kClsPfd ? ctx->tile_p : ctx->tile_w, 32 << h.lk);
     ListDesc L;
     std::memset(&L, 0, sizeof(L));
     L.stream = d_stream;
@@ -836,11 +834,11 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     std::memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
     if (o.tile_ints && !valid_wave_tile(o.tile_ints)) return GC_EINVAL;
-    if (o.pfd_tile_ints && !valid_pfd_tile(o.pfd_tile_ints)) return GC_EINVAL;
+    if (o.pfd_tile_ints && !valid_wave_tile(o.pfd_tile_ints)) return GC_EINVAL;
     bool forced = o.tile_ints || o.pfd_tile_ints;
     for (int c = 0; c < kClasses; c++) {
         const uint32_t t = o.class_tile_ints[c];
-        if (t && (c == kClsPfd ? !valid_pfd_tile(t) : !valid_wave_tile(t))) return GC_EINVAL;
+        if (t && !valid_wave_tile(t)) return GC_EINVAL;
         forced = forced || t;
     }
     if (o.schedule > 1u || o.carry_pass > 3u || o.reserved) return GC_EINVAL;

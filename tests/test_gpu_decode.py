@@ -166,6 +166,54 @@ def test_batch_parity(torch_cuda, ctx, tiles, graph, carry):
     plan.close()
 
 
+@pytest.mark.parametrize("carry", [gc.CARRY_DEFAULT, gc.CARRY_SUM_PASS, gc.CARRY_LOOKBACK])
+def test_pfd_1024_tiles(torch_cuda, ctx, carry):
+    """Group-PFD in tiles of 1024 integers (whole 32-tuple blocks up to
+    k = 32): linked and bitmap exceptions and the no-exception form, k = 4 to
+    32, ragged lengths, d-gap lists (carried across tiles) and lists of
+    exception-heavy widths; then with one k = 64 list added, which raises the
+    class's tile to 2048."""
+    torch = torch_cuda
+    rng = np.random.default_rng(300 + carry)
+    pv = [(dict(), 0), (dict(pfd_pos=O.PFD_BITMAP), 0), (dict(zeta=(1, 32)), 0)]
+    streams, lists = [], []
+    i = 0
+    for k in (4, 8, 16, 32):
+        for kw, _ in pv:
+            for n in (1, 127, 1023, 1024, 1025, 5000, 70001):
+                delta = i % 2 == 0
+                x = (np.sort(rng.choice(1 << 28, n, replace=False)).astype(np.uint32) if delta else
+                     (rng.integers(0, 1 << 32, n, dtype=np.uint64) >> rng.integers(0, 33, n).astype(np.uint64))
+                     .astype(np.uint32))
+                streams.append(O.encode(x, O.params(O.PFD, k=k, delta=delta, **kw)))
+                lists.append(x)
+                i += 1
+    wide = np.sort(rng.choice(1 << 28, 9000, replace=False)).astype(np.uint32)
+    for extra in (False, True):
+        ss = streams + ([O.encode(wide, O.params(O.PFD, k=64, delta=True))] if extra else [])
+        ls = lists + ([wide] if extra else [])
+        flat = np.concatenate(ss)
+        offs = np.concatenate([[0], np.cumsum([x.size for x in ss])]).astype(np.int64)
+        lengths = np.array([x.size for x in ls], np.int64)
+        descs, headers, out_offs = gc.batch_layout(flat, offs, lengths, align=4)
+        d_s = gc.to_device(flat)
+        total = int(out_offs[-1])
+        d_o = torch.full((total + 64,), -1, dtype=torch.int32, device="cuda")
+        say("pfd 1024 tiles: carry", carry, "k=64 list", extra, "lists", len(descs), "ints", total)
+        plan = gc.Plan(ctx, descs, headers, d_s, d_o, pfd_tile_ints=1024, use_graph=True, carry_pass=carry)
+        assert plan.config()["pfd_tile_ints"] == (2048 if extra else 1024)
+        want = np.concatenate(ls)
+        for rep in range(2):
+            d_o.fill_(-1)
+            plan.decode_batch(d_s, d_o)
+            rc, det = ctx.sync_status()
+            assert rc == gc.OK, det
+            got = gc.to_host(d_o)
+            assert np.all(got[total:] == 0xFFFFFFFF)
+            assert np.array_equal(gc.unpad(got, out_offs, lengths), want), "replay %d" % rep
+        plan.close()
+
+
 @pytest.mark.parametrize("codec,kw", [(gc.SIMPLE, {}), (gc.SCHEME, dict(cg=8, ld=gc.LD_IU)), (gc.PFD, {})])
 def test_lookback_long_lists(torch_cuda, ctx, codec, kw):
     """Single-pass carries over lists of hundreds of tiles, so that a look-back
@@ -307,9 +355,9 @@ def test_autotuned_plan(torch_cuda, ctx, tmp_path, monkeypatch):
     say("autotune")
     plan = gc.Plan(ctx, descs, headers, d_s, d_o, autotune=True, use_graph=True)
     cfg = plan.config()
-    assert cfg["tile_ints"] in (1024, 2048, 4096) and cfg["pfd_tile_ints"] in (2048, 4096)
+    assert cfg["tile_ints"] in (1024, 2048, 4096) and cfg["pfd_tile_ints"] in (1024, 2048, 4096)
     ct = cfg["class_tiles"]        # one size per codec class
-    assert all(t in (1024, 2048, 4096) for t in ct[:4]) and ct[4] in (2048, 4096)
+    assert all(t in (1024, 2048, 4096) for t in ct)
     assert 1 <= cfg["tiles"] and cfg["sum_tiles"] <= cfg["tiles"]
     plan.decode_batch(d_s, d_o)
     assert ctx.sync_status()[0] == gc.OK
