@@ -307,11 +307,17 @@ __device__ BlockLayout code_block(uint32_t kappa, uint32_t lane, const uint32_t 
 }
 
 // Loads block blk into registers (tuple per lane) and LDS.
-__device__ __forceinline__ void load_block(const uint32_t *in, size_t blk, uint32_t lane, uint32_t (&v)[4],
-                                           uint32_t &W, BlockSmem &sm) {
+// Lane t < 32 loads tuple t of the block (issued apart from its use, so
+// that the kernels' other loads can be in flight with it).
+__device__ __forceinline__ u32x4 block_tuple(const uint32_t *in, size_t blk, uint32_t lane) {
     const gu32x4 *src = (const gu32x4 *)(in + blk * (size_t)kBlockInts);
     u32x4 q = {0u, 0u, 0u, 0u};
     if (lane < (uint32_t)kTuples) q = src[lane];
+    return q;
+}
+
+// The tuple's integers and width in registers, the block in LDS.
+__device__ __forceinline__ void stage_block(u32x4 q, uint32_t lane, uint32_t (&v)[4], uint32_t &W, BlockSmem &sm) {
     v[0] = q.x;
     v[1] = q.y;
     v[2] = q.z;
@@ -325,37 +331,65 @@ __device__ __forceinline__ void load_block(const uint32_t *in, size_t blk, uint3
 // The largest bit width / 32; the histogram of the 32 tuple widths (0..32)
 // / 32, a tuple's width being that of its widest integer; and the integers
 // wider than maxw - t for t = 1..6 (all of them when maxw - t < 0) / 128.
+// Two blocks per wave: lane 32h + t holds tuple t of block 2w + h.
+
+// x reduced over the 32 lanes of each half wave
+__device__ __forceinline__ uint32_t half_max(uint32_t x) {
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) x = max(x, (uint32_t)__shfl_xor((int)x, o));
+    return x;
+}
+__device__ __forceinline__ uint32_t half_sum(uint32_t x) {
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) x += (uint32_t)__shfl_xor((int)x, o);
+    return x;
+}
+
 __global__ __launch_bounds__(kThreads) void gc_block_features_kernel(const uint32_t *in, size_t nblocks,
                                                                      float *feat) {
-    const uint32_t lane = threadIdx.x & 63u;
-    const size_t blk = (size_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (blk >= nblocks) return;
-    const gu32x4 *src = (const gu32x4 *)(in + blk * (size_t)kBlockInts);
-    const bool valid = lane < (uint32_t)kTuples;
+    const uint32_t lane = threadIdx.x & 63u, h = lane >> 5, t = lane & 31u;
+    const size_t pair = (size_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (2u * pair >= nblocks) return;
+    const size_t blk = 2u * pair + h;
+    const bool valid = blk < nblocks;   // the pair's second block may be missing
     u32x4 q = {0u, 0u, 0u, 0u};
-    if (valid) q = src[lane];
-    const uint32_t w[4] = {bitw(q.x), bitw(q.y), bitw(q.z), bitw(q.w)};
+    if (valid) q = ((const gu32x4 *)(in + blk * (size_t)kBlockInts))[t];
     const uint32_t tw = bitw(q.x | q.y | q.z | q.w);
-    const uint32_t maxw = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(tw), 63);
-    uint32_t hist = 0;   // lane j = 1..33: tuples of width j - 1
-    for (uint32_t b = 0; b <= 32u; b++) {
-        const uint32_t c = (uint32_t)__builtin_popcountll(__ballot(valid && tw == b));
-        if (lane == b + 1u) hist = c;
+    const uint32_t maxw = half_max(tw);
+    // histogram bins between the least and the largest tuple width of the
+    // two blocks (the others are empty); per half, its bit count of the ballot
+    const uint32_t lo = 32u - (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(valid ? 32u - tw : 0u), 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(valid ? tw : 0u), 63);
+    uint32_t ha = 0, hb = 0;   // bins t - 1 (features t >= 1) and 31 + t (features 32, 33)
+    for (uint32_t b = lo; b <= hi; b++) {
+        const uint64_t m = __ballot(valid && tw == b);
+        const uint32_t c = (uint32_t)__builtin_popcount(h ? (uint32_t)(m >> 32) : (uint32_t)m);
+        if (b + 1u == t) ha = c;
+        if (b == 31u + t) hb = c;
     }
-    uint32_t wider = 0;  // lane 33 + t: integers wider than maxw - t
-    for (int t = 1; t <= 6; t++) {
-        const int thr = (int)maxw - t;
-        uint32_t c = 0;
-        if (valid)
-            for (int j = 0; j < 4; j++) c += (int)w[j] > thr ? 1u : 0u;
-        c = wave_sum(c);
-        if (lane == 33u + (uint32_t)t) wider = c;
+    // integers by d = maxw - width, for d = 0..5, eight bits per count
+    uint32_t n03 = 0, n45 = 0;
+    const uint32_t v[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint32_t d = maxw - bitw(v[j]);
+        n03 += d < 4u ? 1u << (8u * d) : 0u;
+        n45 += d - 4u < 2u ? 1u << (8u * (d - 4u)) : 0u;
     }
-    float f = 0.0f;
-    if (lane == 0u) f = (float)maxw / 32.0f;
-    else if (lane <= 33u) f = (float)hist / 32.0f;
-    else f = (float)wider / 128.0f;
-    if (lane < (uint32_t)kFeatures) feat[blk * (size_t)kFeatures + lane] = f;
+    if (!valid) n03 = n45 = 0u;
+    n03 = half_sum(n03);
+    n45 = half_sum(n45);
+    // wider than maxw - u: the integers with d < u
+    uint32_t wider = 0;
+#pragma unroll
+    for (uint32_t d = 0; d < 6u; d++) {
+        const uint32_t nd = d < 4u ? (n03 >> (8u * d)) & 255u : (n45 >> (8u * (d - 4u))) & 255u;
+        wider += d + 2u <= t ? nd : 0u;   // lane t = 2..7 takes u = t - 1
+    }
+    if (!valid) return;
+    float *f = feat + blk * (size_t)kFeatures;
+    f[t] = t == 0u ? (float)maxw / 32.0f : (float)ha / 32.0f;
+    if (t < 8u) f[32u + t] = t < 2u ? (float)hb / 32.0f : (float)wider / 128.0f;
 }
 
 // ---- sizes of every class, exhaustive choice -----------------------------------
@@ -368,7 +402,7 @@ __global__ __launch_bounds__(kThreads) void gc_block_sizes_kernel(const uint32_t
     if (blk >= nblocks) return;
     BlockSmem &sm = smem[wave];
     uint32_t v[4], W;
-    load_block(in, blk, lane, v, W, sm);
+    stage_block(block_tuple(in, blk, lane), lane, v, W, sm);
     uint32_t bsize = 0xFFFFFFFFu, bk = 0, mine = 0;
     for (uint32_t kappa = 0; kappa < (uint32_t)kClasses; kappa++) {
         const BlockLayout L = code_block<false>(kappa, lane, v, W, sm);
@@ -397,11 +431,12 @@ __global__ __launch_bounds__(kThreads) void gc_blockmix_size_kernel(const uint32
     const size_t blk = (size_t)blockIdx.x * kWaves + wave;
     if (blk >= nblocks) return;
     BlockSmem &sm = smem[wave];
+    const u32x4 q = block_tuple(in, blk, lane);   // in flight with the class load
     const uint32_t kappa = (uint32_t)__builtin_amdgcn_readfirstlane((int)cls[blk]);
     uint32_t w = 0u;
     if (kappa < (uint32_t)kClasses) {
         uint32_t v[4], W;
-        load_block(in, blk, lane, v, W, sm);
+        stage_block(q, lane, v, W, sm);
         const BlockLayout L = code_block<false>(kappa, lane, v, W, sm);
         w = L.Cw + L.D + L.E;
     } else if (lane == 0u) {
@@ -481,15 +516,18 @@ __global__ __launch_bounds__(kThreads) void gc_blockmix_emit_kernel(const uint32
     const size_t blk = (size_t)blockIdx.x * kWaves + wave;
     if (blk >= nblocks) return;
     BlockSmem &sm = smem[wave];
+    // the block, its class and its offset, loaded together
+    const u32x4 q = block_tuple(in, blk, lane);
     const uint32_t kappa = (uint32_t)__builtin_amdgcn_readfirstlane((int)cls[blk]);
+    const uint32_t off = (uint32_t)__builtin_amdgcn_readfirstlane((int)offs[blk]);
     for (uint32_t w = lane; w < (uint32_t)kMaxCtrlWords; w += 64u) sm.ctrl[w] = 0u;
     for (uint32_t w = lane; w < (uint32_t)kMaxDataWords; w += 64u) sm.data[w] = 0u;
     for (uint32_t w = lane; w < (uint32_t)kMaxExcWords; w += 64u) sm.exc[w] = 0u;
     uint32_t v[4], W;
-    load_block(in, blk, lane, v, W, sm);
+    stage_block(q, lane, v, W, sm);
     const BlockLayout L = code_block<true>(kappa, lane, v, W, sm);
     wave_lds_sync();
-    uint32_t *p = out + 4 + nblocks + offs[blk];
+    uint32_t *p = out + 4 + nblocks + off;
     for (uint32_t w = lane; w < L.Cw; w += 64u) p[w] = sm.ctrl[w];
     for (uint32_t w = lane; w < L.D; w += 64u) p[L.Cw + w] = sm.data[w];
     for (uint32_t w = lane; w < L.E; w += 64u) p[L.Cw + L.D + w] = sm.exc[w];
@@ -502,7 +540,8 @@ static dim3 grid_for(size_t nblocks) { return dim3((unsigned)((nblocks + kWaves 
 
 int launch_block_features(const uint32_t *in, size_t nblocks, float *feat, hipStream_t s) {
     if (!nblocks) return 0;
-    hipLaunchKernelGGL(gc_block_features_kernel, grid_for(nblocks), dim3(kThreads), 0, s, in, nblocks, feat);
+    // two blocks per wave
+    hipLaunchKernelGGL(gc_block_features_kernel, grid_for((nblocks + 1) / 2), dim3(kThreads), 0, s, in, nblocks, feat);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

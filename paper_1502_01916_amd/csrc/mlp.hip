@@ -12,6 +12,7 @@
 // Gradients of a batch are written per workgroup and summed in a fixed
 // order by the reduce/Adam kernel, so a step is deterministic.
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "gc_mlp.h"
@@ -80,6 +81,9 @@ struct __align__(16) NetSmem {
     float bsum[4][2 * kHid + kOut];   // per wave: db1, db2, db3 column sums
     float lsum[4];
 };
+// The forward pass alone uses the activations, the leading members: its
+// workgroups take that much LDS (22 KB against 51 KB), so that seven fit a CU.
+constexpr size_t kFwdSmem = offsetof(NetSmem, g3);
 
 // One dense layer for a wave's 16 rows: out = bf(relu(in W + b)).
 template <int KT>
@@ -106,19 +110,42 @@ __device__ __forceinline__ void dense_relu(const uint16_t *in, int ldin, const u
 template <bool TRAIN>
 __global__ __launch_bounds__(kThreads) void gc_mlp_kernel(Batch b, const float *theta, Packed w, float *partial,
                                                           float *logits, uint8_t *cls) {
-    __shared__ NetSmem sm;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    NetSmem &sm = *reinterpret_cast<NetSmem *>(smem_raw);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, q = lane >> 4, r0 = 16 * wave;
     const size_t base = (size_t)blockIdx.x * kRows;
 
-    for (int e = threadIdx.x; e < kRows * kInPad; e += kThreads) {
-        const int r = e / kInPad, k = e - r * kInPad;
-        float x = 0.f;
-        if (k < kIn && base + r < b.count) {
-            const size_t src = b.index ? (size_t)b.index[b.row0 + base + r] : b.row0 + base + r;
-            x = b.feat[src * kIn + k];
-        }
-        sm.a0[e] = to_bf16(x);
+    // The workgroup's 64 x 48 inputs (40 features, then zero padding).  The
+    // loads are unconditional, a missing row or a padding column reading the
+    // workgroup's first feature, so that a thread's twelve are in flight
+    // together.
+    constexpr int kLoads = kRows * kInPad / kThreads;
+    static_assert(kRows * kInPad % kThreads == 0, "whole loads per thread");
+    size_t src[kLoads];
+#pragma unroll
+    for (int j = 0; j < kLoads; j++) {
+        const int e = threadIdx.x + j * kThreads, r = e / kInPad, k = e - r * kInPad;
+        const bool ok = k < kIn && base + r < b.count;
+        src[j] = b.row0 + (ok ? base + r : base);   // base < count
+    }
+    if (b.index) {   // the sample rows first, all at once
+        uint32_t ix[kLoads];
+#pragma unroll
+        for (int j = 0; j < kLoads; j++) ix[j] = b.index[src[j]];
+#pragma unroll
+        for (int j = 0; j < kLoads; j++) src[j] = ix[j];
+    }
+    float x[kLoads];
+#pragma unroll
+    for (int j = 0; j < kLoads; j++) {
+        const int e = threadIdx.x + j * kThreads, r = e / kInPad, k = e - r * kInPad;
+        x[j] = b.feat[src[j] * kIn + (k < kIn ? k : 0)];
+    }
+#pragma unroll
+    for (int j = 0; j < kLoads; j++) {
+        const int e = threadIdx.x + j * kThreads, r = e / kInPad, k = e - r * kInPad;
+        sm.a0[e] = to_bf16(k < kIn && base + r < b.count ? x[j] : 0.f);
     }
     __syncthreads();
     dense_relu<3>(sm.a0, kInPad, w.w1t, theta + kOffB1, sm.a1, r0, lane);
@@ -156,19 +183,30 @@ __global__ __launch_bounds__(kThreads) void gc_mlp_kernel(Batch b, const float *
     // softmax, loss and G3 = (P - onehot + lam P (c - <P, c>)) / B
     const float inv_b = 1.0f / (float)b.count;
     float lacc = 0.f, db3 = 0.f;
+    // labels and costs of the lane's four rows, loaded together (a missing
+    // row reads the workgroup's first)
+    float cst[4];
+    uint32_t lab[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        const int r = r0 + 4 * q + e;
+        const size_t row = b.row0 + (base + r < b.count ? base + r : base);
+        const size_t src = b.index ? (size_t)b.index[row] : row;
+        cst[e] = b.cost ? b.cost[src * kOut + i] : 0.f;
+        lab[e] = b.label[src];
+    }
 #pragma unroll
     for (int e = 0; e < 4; e++) {
         const int r = r0 + 4 * q + e;
         const bool valid = base + r < b.count;
-        const size_t src = !valid ? 0 : b.index ? (size_t)b.index[b.row0 + base + r] : b.row0 + base + r;
         const float z = z3[e] + b3;
         const float mx = max16(z);
         const float ex = expf(z - mx);
         const float se = sum16(ex);
         const float p = ex / se;
-        const float c = (valid && b.cost) ? b.cost[src * kOut + i] : 0.f;
+        const float c = valid ? cst[e] : 0.f;
         const float ec = sum16(p * c);
-        const bool hit = valid && (int)b.label[src] == i;
+        const bool hit = valid && (int)lab[e] == i;
         float g = 0.f;
         if (valid) {
             g = (p - (hit ? 1.f : 0.f) + b.lam * p * (c - ec)) * inv_b;
@@ -288,6 +326,8 @@ __global__ __launch_bounds__(kThreads) void gc_mlp_reduce_adam_kernel(const floa
     const int p = blockIdx.x * kThreads + threadIdx.x;
     if (p > kParams) return;
     float g = 0.f;
+    // in workgroup order; unrolled so that 16 loads are in flight at once
+#pragma unroll 16
     for (uint32_t k = 0; k < nparts; k++) g += partial[(size_t)k * kPartialStride + p];
     if (p == kParams) {
         if (loss) *loss = g;
@@ -316,7 +356,7 @@ static unsigned groups(size_t rows) { return (unsigned)((rows + kRows - 1) / kRo
 
 int launch_grad_partials(const Batch &b, const float *theta, const Packed &w, float *partial, hipStream_t s) {
     if (!b.count) return 0;
-    hipLaunchKernelGGL(gc_mlp_kernel<true>, dim3(groups(b.count)), dim3(kThreads), 0, s, b, theta, w, partial,
+    hipLaunchKernelGGL(gc_mlp_kernel<true>, dim3(groups(b.count)), dim3(kThreads), sizeof(NetSmem), s, b, theta, w, partial,
                        (float *)nullptr, (uint8_t *)nullptr);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -339,7 +379,7 @@ int launch_forward(const float *feat, size_t n, const float *theta, const Packed
                    hipStream_t s) {
     if (!n) return 0;
     Batch b = {feat, nullptr, nullptr, nullptr, 0, (uint32_t)n, 0.f};
-    hipLaunchKernelGGL(gc_mlp_kernel<false>, dim3(groups(n)), dim3(kThreads), 0, s, b, theta, w, (float *)nullptr,
+    hipLaunchKernelGGL(gc_mlp_kernel<false>, dim3(groups(n)), dim3(kThreads), kFwdSmem, s, b, theta, w, (float *)nullptr,
                        logits, cls);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
