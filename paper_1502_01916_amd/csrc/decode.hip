@@ -1665,7 +1665,9 @@ __device__ void wave_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, ui
         if constexpr (MODE == kModeFused) {
             if (L.ntiles <= a.lb_max_tiles) {
                 const unsigned long long f0 = m ? lookback_first(a, gi, m, lane) : 0ull;
-                carry0 = tile_carry(a, gi, m, L.ntiles, tile_total<TW, CLS>(t, sm, lane), loc_tag, lane, f0);
+                // a list's last tile publishes no flag, so it needs no sum
+                const uint32_t s = m + 1u < L.ntiles ? tile_total<TW, CLS>(t, sm, lane) : 0u;
+                carry0 = tile_carry(a, gi, m, L.ntiles, s, loc_tag, lane, f0);
             } else {
                 carry0 = pre.carry;
             }
