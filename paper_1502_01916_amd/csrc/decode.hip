@@ -1410,8 +1410,12 @@ __device__ __forceinline__ void tile_setup(const DecodeArgs &a, const ListDesc &
     using SM = WaveSmem<TW, CLS>;
     TileCtx &c = t.c;
     // the stream's header, loaded now and compared once the prologue's own
-    // loads are under way
-    const u32x4 hd = *(const gu32x4 *)L.stream;
+    // loads are under way; a vector load (its index a register the compiler
+    // cannot see through), so that waiting on scalar loads does not wait
+    // for it
+    uint32_t vzero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
+    const u32x4 hd = ((const gu32x4 *)L.stream)[vzero];
     const bool ok = tile_ctx(L, m, pre.s0, pre.s1, (uint32_t)TW, loc_tag, c);
     // The prologue's control words are loaded first, all at once (no branch
     // between the loads and their wait), so that the prologue waits for
@@ -1702,6 +1706,12 @@ __global__ __launch_bounds__(kThreads) void gc_wave_kernel(DecodeArgs a) {
     const uint32_t loc_tag = *(const gu32 *)&a.loc_state->epoch;   // written by an earlier kernel
     const TilePre pre = tile_pre(a, gi);
     const ListDesc L = tile_list(a, pre);
+    // These scalar loads would otherwise be sunk past the set-up's branches,
+    // a memory round trip later than the list descriptor; taken here, they
+    // arrive with it, before the set-up issues its vector loads.
+    asm volatile("" ::"s"(loc_tag), "s"(pre.s0.unit), "s"(pre.s0.sub), "s"(pre.s0.exc), "s"(pre.s0.tag),
+                 "s"(pre.s0.data), "s"(pre.s1.unit), "s"(pre.s1.sub), "s"(pre.s1.exc), "s"(pre.s1.tag),
+                 "s"(pre.s1.data), "s"(pre.carry));
     wave_tile<TW, CLS, MODE>(a, L, gi - L.tile_base, gi, pre, loc_tag, sm[wave], lane);
 }
 
