@@ -874,29 +874,43 @@ __device__ uint32_t wprologue_gscu(const TileCtx &c, WaveSmem<TW, kClsGscU> &sm,
     return 0;
 }
 
+// Word i (< 64 * CE) of the control words loaded before the prologue, which
+// lane i % 64 holds in register i / 64 (every lane takes part).
+template <int CE>
+__device__ __forceinline__ uint32_t early_word(const uint32_t (&ce)[CE], uint32_t i) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int v = 0; v < CE; v++) {
+        const uint32_t x = (uint32_t)__shfl((int)ce[v], (int)(i & 63u));
+        w = (i >> 6) == (uint32_t)v ? x : w;
+    }
+    return w;
+}
+
 // ---- Group-Scheme, binary descriptors ---------------------------------------
-template <int TW>
-__device__ uint32_t wprologue_gscb(const TileCtx &c, WaveSmem<TW, kClsGscB> &sm, uint32_t lane, uint32_t &dbase) {
+// The words of the tile's length fields (from the first tuple's on) were
+// loaded before the prologue; cok: they lie inside the control area.
+template <int TW, int CE>
+__device__ uint32_t wprologue_gscb(const TileCtx &c, WaveSmem<TW, kClsGscB> &sm, uint32_t lane, uint32_t &dbase,
+                                   const uint32_t (&ce)[CE], bool cok) {
     using SM = WaveSmem<TW, kClsGscB>;
     const uint32_t cg = (uint32_t)c.h.cg;
     const BinUnit bu = bin_unit(c.h.cg);
     constexpr int TPT = SM::TTM / 64;
+    static_assert(64 * CE >= SM::TTM / 6 + 2, "the length fields fit the early words");
+    if (c.ntup && !cok) return kErrRange;
+    const uint32_t w0 = bin_field_bit(c.t0, bu) >> 5;
     uint32_t bw[TPT];
     uint32_t sum = 0;
-    bool bad = false;
 #pragma unroll
     for (int j = 0; j < TPT; j++) {
         const uint32_t tt = lane * TPT + (uint32_t)j;
-        uint32_t b = 0;
-        if (tt < c.ntup) {
-            const uint32_t bit = bin_field_bit(c.t0 + tt, bu);
-            if ((bit >> 5) >= c.C) bad = true;
-            else b = cg * (((c.ctrl[bit >> 5] >> (bit & 31u)) & mask_of(bu.fb)) + 1u);
-        }
+        const uint32_t bit = bin_field_bit(c.t0 + tt, bu);
+        const uint32_t word = early_word<CE>(ce, (bit >> 5) - w0);
+        const uint32_t b = tt < c.ntup ? cg * (((word >> (bit & 31u)) & mask_of(bu.fb)) + 1u) : 0u;
         bw[j] = b;
         sum += b;
     }
-    if (wave_any(bad)) return kErrRange;
     const uint64_t abs0 = c.st.data;
     dbase = (uint32_t)(abs0 >> 5);
     uint32_t run = wave_incl_scan(sum) - sum + (uint32_t)(abs0 & 31u);
@@ -912,22 +926,27 @@ __device__ uint32_t wprologue_gscb(const TileCtx &c, WaveSmem<TW, kClsGscB> &sm,
 }
 
 // ---- Group-AFOR ---------------------------------------------------------------
-template <int TW>
-__device__ uint32_t wprologue_afor(const TileCtx &c, WaveSmem<TW, kClsAfor> &sm, uint32_t lane, uint32_t &dbase) {
+// The frame bytes of the tile (control words from f0 / 4 on) were loaded
+// before the prologue.
+template <int TW, int CE>
+__device__ uint32_t wprologue_afor(const TileCtx &c, WaveSmem<TW, kClsAfor> &sm, uint32_t lane, uint32_t &dbase,
+                                   const uint32_t (&ce)[CE]) {
     using SM = WaveSmem<TW, kClsAfor>;
     const uint32_t f0 = c.st.unit, sub0 = c.st.sub;
     const uint32_t nfr = min(c.TT / 8u + 2u, 4u * c.C > f0 ? 4u * c.C - f0 : 0u);
     constexpr int FPT = (SM::TTM / 8 + 2 + 63) / 64;
+    static_assert(64 * CE * 4 >= SM::TTM / 8 + 2 + 3, "the frame bytes fit the early words");
     uint32_t cnt[FPT], bb[FPT];
     uint32_t csum = 0, bsum = 0;
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < FPT; j++) {
         const uint32_t i = lane * FPT + (uint32_t)j;
+        const uint32_t f = f0 + i;
+        const uint32_t word = early_word<CE>(ce, (f >> 2) - (f0 >> 2));
         cnt[j] = bb[j] = 0u;
         if (i < nfr) {
-            const uint32_t f = f0 + i;
-            const uint32_t byte = (c.ctrl[f >> 2] >> (8u * (f & 3u))) & 0xFFu;
+            const uint32_t byte = (word >> (8u * (f & 3u))) & 0xFFu;
             uint32_t b = byte & 63u;
             const uint32_t cls = byte >> 6;
             if (cls == 3u || b > 32u) {
@@ -1366,11 +1385,16 @@ __device__ __forceinline__ auto tile_recs(const WaveSmem<TW, CLS> &sm) {
 
 // Control words [w0, w0 + nw) that the prologue of a tile reads, from the
 // tile starts at its two ends: Group-Simple, the words of its selectors;
-// unary Group-Scheme, the words of its codes.  CE words per lane of them are
+// Group-Scheme, the words of its unary codes or binary length fields;
+// Group-AFOR, the words of its frame bytes.  CE words per lane of them are
 // loaded before the prologue.
 template <int TW, int CLS>
 constexpr int ctrl_early_words() {
-    return CLS == kClsSim ? (TW / 32 + 2 + 63) / 64 : CLS == kClsGscU ? 3 : 0;
+    return CLS == kClsSim    ? (TW / 32 + 2 + 63) / 64
+           : CLS == kClsGscU ? 3
+           : CLS == kClsGscB ? (TW / 4 / 6 + 2 + 63) / 64
+           : CLS == kClsAfor ? 1
+                             : 0;
 }
 
 template <int CLS>
@@ -1386,6 +1410,17 @@ __device__ __forceinline__ void tile_ctrl_words(const TileCtx &c, uint32_t &w0, 
         w0 = c.st.unit >> 5;
         const uint32_t w1 = (p1 + 31u) >> 5;
         nw = p1 >= c.st.unit && w1 > w0 ? w1 - w0 : 0u;
+    } else if constexpr (CLS == kClsGscB) {   // the words of its tuples' length fields
+        if (c.ntup) {
+            const BinUnit bu = bin_unit(c.h.cg);
+            w0 = bin_field_bit(c.t0, bu) >> 5;
+            nw = (bin_field_bit(c.t0 + c.ntup - 1u, bu) >> 5) + 1u - w0;
+        }
+    } else if constexpr (CLS == kClsAfor) {   // its frame bytes, four to a word
+        const uint32_t f0 = c.st.unit;
+        const uint32_t nfr = min(c.TT / 8u + 2u, 4u * c.C > f0 ? 4u * c.C - f0 : 0u);
+        w0 = f0 >> 2;
+        nw = nfr ? ((f0 + nfr + 3u) >> 2) - w0 : 0u;
     }
 }
 
@@ -1480,8 +1515,8 @@ __device__ __forceinline__ void tile_setup(const DecodeArgs &a, const ListDesc &
     if (!err) {
         if constexpr (CLS == kClsSim) err = wprologue_sim<TW, CE>(c, sm, lane, dbase, ce, cok);
         else if constexpr (CLS == kClsGscU) err = wprologue_gscu<TW, CE>(c, sm, lane, dbase, ce, cok);
-        else if constexpr (CLS == kClsGscB) err = wprologue_gscb<TW>(c, sm, lane, dbase);
-        else if constexpr (CLS == kClsAfor) err = wprologue_afor<TW>(c, sm, lane, dbase);
+        else if constexpr (CLS == kClsGscB) err = wprologue_gscb<TW, CE>(c, sm, lane, dbase, ce, cok);
+        else if constexpr (CLS == kClsAfor) err = wprologue_afor<TW, CE>(c, sm, lane, dbase, ce);
         else err = wprologue_pfd<TW>(c, sm, lane, dbase, L.stream_words, t.ps.xs);
     }
     t.nrow = Dk > dbase ? Dk - dbase : 0u;
