@@ -45,6 +45,11 @@ constexpr int kDefaultPfdTile = 4096;
 constexpr uint32_t kLookbackAll = 0xFFFFFFFFu;
 constexpr uint32_t kLookbackHybrid = 64u;
 constexpr uint32_t kDefaultLbMax = kLookbackHybrid;
+// A list decoded alone (gc_decode) has no other lists' tiles in flight, so
+// its look-back walks stay short for longer: a list of up to 2048 tiles
+// finds its carries by look-back (2^20 to 2^22 integers: 2-4 us faster
+// than the tile-sum pass and carry scan, equal at 2^23, slower at 2^24).
+constexpr uint32_t kSingleLbMax = 2048u;
 constexpr int kWaveTiles[3] = {1024, 2048, 4096};
 constexpr int kClsPfd = 4;
 
@@ -822,7 +827,7 @@ gc_status gc_decode(gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words, 
     L.C = h_header[2];
     L.D = h_header[3];
     if (gc_status rc = ctx->single.reserve(L.ntiles + 1, L.nchunks)) return rc;
-    return launch_one(L, cls, ctx->single, ctx->status, (hipStream_t)hip_stream, kDefaultLbMax, kChunkWordsSmall);
+    return launch_one(L, cls, ctx->single, ctx->status, (hipStream_t)hip_stream, kSingleLbMax, kChunkWordsSmall);
 }
 
 gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists, const uint32_t *h_headers,

@@ -113,6 +113,22 @@ def test_cfg1_group_simple(torch_cuda, ctx):
     assert np.array_equal(got, d)
 
 
+@pytest.mark.parametrize("codec,kw", [(O.SIMPLE, {}), (O.SCHEME, dict(cg=1, ld=O.LD_CU)), (O.PFD, {})])
+def test_single_list_carry_modes(torch_cuda, ctx, codec, kw):
+    """A list decoded alone finds its carries by look-back up to 2048 tiles
+    and by the tile-sum pass beyond: lists just inside and just past that
+    size (tiles of 2048 integers, 4096 for Group-PFD)."""
+    rng = np.random.default_rng(11 + codec)
+    tile = 4096 if codec == O.PFD else 2048
+    for n in (2048 * tile - 5, 2048 * tile + 77):
+        d = np.sort(rng.choice(1 << 27, n, replace=False)).astype(np.uint32)
+        s = O.encode(d, O.params(codec, delta=True, **kw))
+        say("single list", codec, kw, n)
+        got = gpu_decode(torch_cuda, ctx, s, n)
+        assert np.array_equal(got, d)
+        assert np.array_equal(got, O.decode(s))
+
+
 def make_batch(rng, nlists, kmix=(4,), maxlen=40000):
     lengths = np.clip(np.round(np.exp(rng.normal(np.log(800), 1.6, nlists))), 0, maxlen).astype(np.int64)
     streams, lists, plist = [], [], []
