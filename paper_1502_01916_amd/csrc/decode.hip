@@ -1018,32 +1018,29 @@ struct ExcSrc {
     }
 };
 
+// The tile's block descriptors (lane j: block j) were loaded before the
+// prologue; cok: they lie inside the control area.
 template <int TW>
 __device__ uint32_t wprologue_pfd(const TileCtx &c, WaveSmem<TW, kClsPfd> &sm, uint32_t lane, uint32_t &dbase,
-                                  uint64_t stream_words, ExcSrc &xs) {
+                                  uint64_t stream_words, ExcSrc &xs, uint32_t ce0, bool cok) {
     const uint32_t k = c.k;
     const uint32_t nb = (c.ntup + 31u) >> 5;   // <= NBLK <= 32
-    const uint32_t beta0 = c.t0 >> 5;
     const int bitmap = c.h.pfd_pos;
     uint32_t desc = 0, b = 0, ew = 0;
-    bool bad_range = false, bad_desc = false;
+    bool bad_desc = false;
+    if (nb && !cok) return kErrRange;
     if (lane < nb) {
-        if (beta0 + lane >= c.C) {
-            bad_range = true;
-        } else {
-            desc = ((const gu32 *)c.ctrl)[beta0 + lane];
-            b = desc & 63u;
-            const uint32_t nexc = desc >> 20, wcode = (desc >> 6) & 3u;
-            const uint32_t first = (desc >> 8) & 0xFFFu;
-            if (b > 32u || nexc > 32u * k || (nexc && !wcode) || (bitmap && first > 32u)) {
-                bad_desc = true;
-                b = 0;
-                desc = 0;
-            }
-            ew = pfd_exc_words(desc, (int)k, bitmap);
+        desc = ce0;
+        b = desc & 63u;
+        const uint32_t nexc = desc >> 20, wcode = (desc >> 6) & 3u;
+        const uint32_t first = (desc >> 8) & 0xFFFu;
+        if (b > 32u || nexc > 32u * k || (nexc && !wcode) || (bitmap && first > 32u)) {
+            bad_desc = true;
+            b = 0;
+            desc = 0;
         }
+        ew = pfd_exc_words(desc, (int)k, bitmap);
     }
-    if (wave_any(bad_range)) return kErrRange;
     if (wave_any(bad_desc)) return kErrPfdDesc;
     const uint32_t ib = wave_incl_scan(b), ie = wave_incl_scan(ew);
     const uint32_t xwords = (uint32_t)__builtin_amdgcn_readlane((int)ie, 63);
@@ -1386,15 +1383,15 @@ __device__ __forceinline__ auto tile_recs(const WaveSmem<TW, CLS> &sm) {
 // Control words [w0, w0 + nw) that the prologue of a tile reads, from the
 // tile starts at its two ends: Group-Simple, the words of its selectors;
 // Group-Scheme, the words of its unary codes or binary length fields;
-// Group-AFOR, the words of its frame bytes.  CE words per lane of them are
-// loaded before the prologue.
+// Group-AFOR, the words of its frame bytes; Group-PFD, its block
+// descriptors.  CE words per lane of them are loaded before the prologue.
 template <int TW, int CLS>
 constexpr int ctrl_early_words() {
     return CLS == kClsSim    ? (TW / 32 + 2 + 63) / 64
            : CLS == kClsGscU ? 3
            : CLS == kClsGscB ? (TW / 4 / 6 + 2 + 63) / 64
            : CLS == kClsAfor ? 1
-                             : 0;
+                             : 1;   // Group-PFD: one descriptor per block
 }
 
 template <int CLS>
@@ -1421,6 +1418,9 @@ __device__ __forceinline__ void tile_ctrl_words(const TileCtx &c, uint32_t &w0, 
         const uint32_t nfr = min(c.TT / 8u + 2u, 4u * c.C > f0 ? 4u * c.C - f0 : 0u);
         w0 = f0 >> 2;
         nw = nfr ? ((f0 + nfr + 3u) >> 2) - w0 : 0u;
+    } else {   // Group-PFD: the descriptors of its blocks
+        w0 = c.t0 >> 5;
+        nw = (c.ntup + 31u) >> 5;
     }
 }
 
@@ -1517,7 +1517,7 @@ __device__ __forceinline__ void tile_setup(const DecodeArgs &a, const ListDesc &
         else if constexpr (CLS == kClsGscU) err = wprologue_gscu<TW, CE>(c, sm, lane, dbase, ce, cok);
         else if constexpr (CLS == kClsGscB) err = wprologue_gscb<TW, CE>(c, sm, lane, dbase, ce, cok);
         else if constexpr (CLS == kClsAfor) err = wprologue_afor<TW, CE>(c, sm, lane, dbase, ce);
-        else err = wprologue_pfd<TW>(c, sm, lane, dbase, L.stream_words, t.ps.xs);
+        else err = wprologue_pfd<TW>(c, sm, lane, dbase, L.stream_words, t.ps.xs, ce[0], cok);
     }
     t.nrow = Dk > dbase ? Dk - dbase : 0u;
     t.kq = c.k >> 2;
