@@ -356,17 +356,16 @@ __global__ __launch_bounds__(kThreads) void gc_block_features_kernel(const uint3
     if (valid) q = ((const gu32x4 *)(in + blk * (size_t)kBlockInts))[t];
     const uint32_t tw = bitw(q.x | q.y | q.z | q.w);
     const uint32_t maxw = half_max(tw);
-    // histogram bins between the least and the largest tuple width of the
-    // two blocks (the others are empty); per half, its bit count of the ballot
-    const uint32_t lo = 32u - (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(valid ? 32u - tw : 0u), 63);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(valid ? tw : 0u), 63);
-    uint32_t ha = 0, hb = 0;   // bins t - 1 (features t >= 1) and 31 + t (features 32, 33)
-    for (uint32_t b = lo; b <= hi; b++) {
-        const uint64_t m = __ballot(valid && tw == b);
-        const uint32_t c = (uint32_t)__builtin_popcount(h ? (uint32_t)(m >> 32) : (uint32_t)m);
-        if (b + 1u == t) ha = c;
-        if (b == 31u + t) hb = c;
-    }
+    // the tuple-width histogram of each block in LDS: one atomic add per tuple
+    __shared__ uint32_t hist[kWaves][2][33];
+    uint32_t *hw = hist[threadIdx.x >> 6][h];
+    hw[t] = 0u;
+    if (t == 0u) hw[32] = 0u;
+    gcdev::wave_lds_sync();
+    if (valid) atomicAdd(&hw[tw], 1u);
+    gcdev::wave_lds_sync();
+    const uint32_t ha = t ? hw[t - 1u] : 0u;      // bin t - 1: feature t >= 1
+    const uint32_t hb = t < 2u ? hw[31u + t] : 0u;  // bins 31, 32: features 32, 33
     // integers by d = maxw - width, for d = 0..5, eight bits per count
     uint32_t n03 = 0, n45 = 0;
     const uint32_t v[4] = {q.x, q.y, q.z, q.w};
