@@ -285,11 +285,12 @@ size_t gc_blockmix_bound_words(size_t n);
 /* Codes the n integers of d_in (device memory holding ceil(n/128) * 128
  * integers, the tail zero-padded) into a container at d_out, block b in
  * class d_class[b] (device memory, one byte per block).  *out_words
- * receives the container's length; the call reads that total back from the
- * device (so it returns after the sizing kernels finished) and queues the
- * writing kernels on hip_stream.  GC_ENOSPC if out_cap_words is too small,
+ * receives the container's length.  The sizing, offset and writing kernels
+ * run on hip_stream back to back; the call returns once they have finished
+ * and the total is read back.  GC_ENOSPC if out_cap_words is too small,
  * GC_EINVAL for a class >= GC_BLOCK_CLASSES or when
- * gc_blockmix_bound_words(n) exceeds 2^32 - 1.                              */
+ * gc_blockmix_bound_words(n) exceeds 2^32 - 1; nothing is written past
+ * out_cap_words, and after an error the contents of d_out are undefined.   */
 gc_status gc_blockmix_encode(gc_ctx *ctx, const uint32_t *d_in, size_t n, const uint8_t *d_class,
                              uint32_t *d_out, size_t out_cap_words, size_t *out_words, void *hip_stream);
 

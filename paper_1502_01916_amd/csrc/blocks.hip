@@ -14,6 +14,7 @@
 
 #include "gc.h"
 #include "gc_blocks.h"
+#include "gc_format.h"
 #include "gc_wave.h"
 
 namespace gcblk {
@@ -506,9 +507,14 @@ __global__ __launch_bounds__(kThreads) void gc_scan_apply_kernel(const uint32_t 
 
 // Pass 2: block words and payloads at their offsets (after the header and
 // the block words); the header itself is written by the host side.
+// Writes every block at its offset and, from the first block's wave, the
+// container header; a block of an invalid class, or whose payload would end
+// past cap_words, writes no payload (the host reports either from the
+// sizing pass's flag and total).
 __global__ __launch_bounds__(kThreads) void gc_blockmix_emit_kernel(const uint32_t *in, size_t nblocks,
                                                                     const uint8_t *cls, const uint32_t *offs,
-                                                                    uint32_t *out) {
+                                                                    uint32_t *out, size_t cap_words, uint32_t n,
+                                                                    const uint32_t *total) {
     __shared__ BlockSmem smem[kWaves];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -522,14 +528,22 @@ __global__ __launch_bounds__(kThreads) void gc_blockmix_emit_kernel(const uint32
     for (uint32_t w = lane; w < (uint32_t)kMaxCtrlWords; w += 64u) sm.ctrl[w] = 0u;
     for (uint32_t w = lane; w < (uint32_t)kMaxDataWords; w += 64u) sm.data[w] = 0u;
     for (uint32_t w = lane; w < (uint32_t)kMaxExcWords; w += 64u) sm.exc[w] = 0u;
+    if (blk == 0u && lane < 4u) {
+        const uint32_t t = *total;   // written by the scan
+        out[lane] = lane == 0u ? GC_FMT_VERSION | (4u << 8) | (2u << 12) : lane == 1u ? n : lane == 2u ? (uint32_t)nblocks : t;
+    }
+    if (kappa >= (uint32_t)kClasses) return;
     uint32_t v[4], W;
     stage_block(q, lane, v, W, sm);
     const BlockLayout L = code_block<true>(kappa, lane, v, W, sm);
     wave_lds_sync();
-    uint32_t *p = out + 4 + nblocks + off;
-    for (uint32_t w = lane; w < L.Cw; w += 64u) p[w] = sm.ctrl[w];
-    for (uint32_t w = lane; w < L.D; w += 64u) p[L.Cw + w] = sm.data[w];
-    for (uint32_t w = lane; w < L.E; w += 64u) p[L.Cw + L.D + w] = sm.exc[w];
+    const size_t pay = 4u + nblocks + (size_t)off;
+    if (pay + L.Cw + L.D + L.E <= cap_words) {
+        uint32_t *p = out + pay;
+        for (uint32_t w = lane; w < L.Cw; w += 64u) p[w] = sm.ctrl[w];
+        for (uint32_t w = lane; w < L.D; w += 64u) p[L.Cw + w] = sm.data[w];
+        for (uint32_t w = lane; w < L.E; w += 64u) p[L.Cw + L.D + w] = sm.exc[w];
+    }
     if (lane == 0u) out[4 + blk] = kappa | (L.Cw << 5) | (L.D << 14) | (L.E << 23);
 }
 
@@ -572,10 +586,10 @@ int launch_blockmix_plan(const uint32_t *in, size_t nblocks, const uint8_t *cls,
 }
 
 int launch_blockmix_emit(const uint32_t *in, size_t nblocks, const uint8_t *cls, const uint32_t *offs,
-                         uint32_t *out, hipStream_t s) {
+                         uint32_t *out, size_t cap_words, uint32_t n, const uint32_t *total, hipStream_t s) {
     if (!nblocks) return 0;
     hipLaunchKernelGGL(gc_blockmix_emit_kernel, grid_for(nblocks), dim3(kThreads), 0, s, in, nblocks, cls, offs,
-                       out);
+                       out, cap_words, n, total);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

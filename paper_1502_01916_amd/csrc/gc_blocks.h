@@ -23,7 +23,9 @@ int launch_block_sizes(const uint32_t *in, size_t nblocks, uint32_t *sizes, uint
 size_t scan_chunks(size_t n);
 int launch_blockmix_plan(const uint32_t *in, size_t nblocks, const uint8_t *cls, uint32_t *words, uint32_t *offs,
                          uint32_t *csum, uint32_t *result, hipStream_t s);
+// Writes the container (header included) at out, no payload past cap_words;
+// total: the payload words from the plan's scan (device memory).
 int launch_blockmix_emit(const uint32_t *in, size_t nblocks, const uint8_t *cls, const uint32_t *offs,
-                         uint32_t *out, hipStream_t s);
+                         uint32_t *out, size_t cap_words, uint32_t n, const uint32_t *total, hipStream_t s);
 
 }  // namespace gcblk

@@ -1026,21 +1026,26 @@ size_t gc_blockmix_bound_words(size_t n) {
 // The container of d_in with block b in class cls[b]; ctx->mu held.
 static gc_status blockmix_encode_locked(gc_ctx *ctx, const uint32_t *d_in, size_t n, size_t nb, const uint8_t *cls,
                                         uint32_t *d_out, size_t out_cap_words, size_t *out_words, hipStream_t s) {
+    // sizes, their scan, then the writes, with no host round trip between:
+    // the emit pass writes the header and keeps within the capacity, and
+    // the total and the class check come back at the end
     uint32_t res[2] = {0u, 0u};
     if (nb) {
         if (gcblk::launch_blockmix_plan(d_in, nb, cls, ctx->blk.words, ctx->blk.offs, ctx->blk.csum, ctx->blk.result,
                                         s))
             return GC_EDEVICE;
+        if (gcblk::launch_blockmix_emit(d_in, nb, cls, ctx->blk.offs, d_out, out_cap_words, (uint32_t)n,
+                                        ctx->blk.result, s))
+            return GC_EDEVICE;
         HIP_OK(hipMemcpyAsync(res, ctx->blk.result, sizeof(res), hipMemcpyDeviceToHost, s));
-        HIP_OK(hipStreamSynchronize(s));
-        if (res[1]) return GC_EINVAL;
+    } else {
+        const uint32_t hdr[4] = {GC_FMT_VERSION | (4u << 8) | (2u << 12), (uint32_t)n, 0u, 0u};
+        HIP_OK(hipMemcpyAsync(d_out, hdr, sizeof(hdr), hipMemcpyHostToDevice, s));
     }
+    HIP_OK(hipStreamSynchronize(s));
+    if (res[1]) return GC_EINVAL;
     const size_t total = 4 + nb + (size_t)res[0];
     if (total > out_cap_words) return GC_ENOSPC;
-    const uint32_t hdr[4] = {GC_FMT_VERSION | (4u << 8) | (2u << 12), (uint32_t)n, (uint32_t)nb, res[0]};
-    HIP_OK(hipMemcpyAsync(d_out, hdr, sizeof(hdr), hipMemcpyHostToDevice, s));
-    if (nb && gcblk::launch_blockmix_emit(d_in, nb, cls, ctx->blk.offs, d_out, s)) return GC_EDEVICE;
-    HIP_OK(hipStreamSynchronize(s));
     *out_words = total;
     return GC_OK;
 }
