@@ -1732,7 +1732,9 @@ __device__ void wave_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, ui
 }
 
 template <int TW, int CLS, int MODE>
-__global__ __launch_bounds__(kThreads) void gc_wave_kernel(DecodeArgs a) {
+// (The Group-PFD tile sums are held to seven waves per SIMD, the LDS limit:
+// left alone they took 82 VGPRs and ran five.)
+__global__ __launch_bounds__(kThreads, (MODE == kModeSum && CLS == kClsPfd) ? 7 : 1) void gc_wave_kernel(DecodeArgs a) {
     __shared__ WaveSmem<TW, CLS> sm[kWaves];
     const uint32_t wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63u;
     const uint32_t w = blockIdx.x * (uint32_t)kWaves + wave;
