@@ -21,9 +21,10 @@
 //           and component masks) and patches them by rank.
 //
 //   carry   A delta list of more than one tile is prefix-summed across its
-//           tiles.  A short list (one window of 64 tiles) does it in the
-//           decode pass: each tile sums its staged rows, publishes the sum
-//           and reads its carry from the flags of the tiles before it
+//           tiles.  A short list (in a batch, one window of 64 tiles; a
+//           list decoded alone, up to 2048 tiles) does it in the decode
+//           pass: each tile sums its staged rows, publishes the sum and
+//           reads its carry from the flags of the tiles before it
 //           (decoupled look-back, a bounded wait).  A longer list takes a
 //           sum pass that stores the sum of each tile's gaps, one workgroup
 //           per list that scans those sums into exclusive carries, and the
