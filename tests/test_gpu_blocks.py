@@ -123,4 +123,15 @@ def test_blockmix_errors(torch_cuda, ctx):
     with pytest.raises(gc.GcError) as e:
         ctx.blockmix_encode(d_in, 512, d_k, small)
     assert e.value.code == gc.ENOSPC
-    assert ctx.blockmix_encode(d_in, 512, d_k, d_out) > 8
+    # capacities between the block words and the whole container: nothing
+    # is written past the capacity
+    need = ctx.blockmix_encode(d_in, 512, d_k, d_out)
+    assert need > 8
+    for cap in (8, 9, need - 1):
+        big = torch.full((need + 64,), -7, dtype=torch.int32, device="cuda")
+        with pytest.raises(gc.GcError) as e:
+            ctx.blockmix_encode(d_in, 512, d_k, big[:cap])
+        assert e.value.code == gc.ENOSPC
+        torch.cuda.synchronize()
+        assert torch.all(big[cap:] == -7), cap
+    assert ctx.blockmix_encode(d_in, 512, d_k, d_out) == need
