@@ -1,16 +1,25 @@
 #!/usr/bin/env python3
 """Throughput of batched Group-codec decoding + d-gap prefix sum on one MI355X.
 
-Workload: 10,000 synthetic posting lists (Zipf lengths clipped to
-[128, 2^22], 2^26 docIDs, universe 2^25, 70% sparse / 30% clustered d-gaps)
-and their TF lists, each coded with Group-Simple, Group-Scheme 1-CU,
+Headline workload (cfg3): 100,000 synthetic posting lists with lognormal
+lengths (median 1,024, about 2^28 docIDs, universe 2^25, 70% sparse / 30%
+clustered d-gaps), each coded with one of Group-Simple, Group-Scheme 1-CU,
 Group-Scheme 8-IU, Group-AFOR and Group-PFD (32-tuple blocks, zeta = 1/10) in
-the paper's 4-way layout: 100,000 streams, about 6.7e8 integers.  One step
-decodes every stream (docID lists prefix-summed): the locate kernels, then per
-codec class the tile-sum pass, the carry scan and the decode pass, all captured
-in one hipGraph; `value` times the graph replays.  A second plan with the same
-tiles launches the kernels directly with HIP events between the phases; it
-gives the per-phase times and the dominant kernel's average duration.
+the paper's 4-way layout.  One step decodes every list and prefix-sums it to
+docIDs: the locate kernels, then per codec class the tile-sum pass, the carry
+scan and the decode pass, all captured in one hipGraph (autotuned tile
+sizes); `value` times the graph replays.  A second plan with the same tiles
+launches the kernels directly with HIP events between the phases; it gives the
+per-phase times and the dominant kernel's average duration.
+
+Legs (each verified bit-exact against the generated lists): the same lists
+decoded with one launch sequence per list, directly and replayed from a
+hipGraph; the cfg2 batch (10,000 Zipf-length docID lists and their TF lists in
+five codecs); the four cfg5 batches (1,000,000 lists, median 256, heavy-tailed
+gaps; Group-PFD and Group-AFOR in the 4-way and 64-way layouts); every
+Group-Scheme variant and BP128 beside the other codecs on cfg2; the
+single-list latency of cfg1.  `--workload NAME` measures one workload alone
+(for profiler runs).
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -20,6 +29,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -30,10 +40,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gints/s decoded+prefix-summed, % HBM peak; batched vs per-list on 1 MI355X"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_decode_cfg2.txt")
+PROFILES = os.path.join(ROOT, "profiles")
 # the sources the decode kernels are compiled from
 DECODE_SRCS = [os.path.join(ROOT, "paper_1502_01916_amd", "csrc", f)
                for f in ("decode.hip", "gc_wave.h", "gc_device.h", "gc_format.h")]
+CLASS_NAMES = ["group-simple", "group-scheme-unary", "group-scheme-binary", "group-afor", "group-pfd"]
 
 
 def decode_sources_sha256():
@@ -44,11 +55,16 @@ def decode_sources_sha256():
     return h.hexdigest()
 
 
+def traffic_file(workload):
+    return os.path.join(PROFILES, "traffic_decode_%s.txt" % workload)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def variants(gc):
+def five_codecs(gc):
+    """The five codecs of the cfg2 and cfg3 batches."""
     return [("group-simple", gc.SIMPLE, {}),
             ("group-scheme-1cu", gc.SCHEME, dict(cg=1, ld=gc.LD_CU)),
             ("group-scheme-8iu", gc.SCHEME, dict(cg=8, ld=gc.LD_IU)),
@@ -56,7 +72,29 @@ def variants(gc):
             ("group-pfd", gc.PFD, dict(zeta=(1, 10)))]
 
 
-CLASS_NAMES = ["group-simple", "group-scheme-unary", "group-scheme-binary", "group-afor", "group-pfd"]
+def all_variants(gc):
+    """Every codec variant of Sections 4-6 in the 4-way layout: Group-Simple,
+    the ten Group-Scheme variants (Section 5.2), Group-AFOR, Group-PFD at
+    zeta = 1/10 and BP128 (Group-PFD below zeta = 1/32, Section 6.3)."""
+    v = [("group-simple", gc.SIMPLE, {})]
+    for cg in (1, 2, 4, 8):
+        v.append(("gsc-%d-b" % cg, gc.SCHEME, dict(cg=cg, ld=gc.LD_BINARY)))
+    for cg in (1, 2, 4, 8):
+        v.append(("gsc-%d-cu" % cg, gc.SCHEME, dict(cg=cg, ld=gc.LD_CU)))
+    for cg in (4, 8):
+        v.append(("gsc-%d-iu" % cg, gc.SCHEME, dict(cg=cg, ld=gc.LD_IU)))
+    v += [("group-afor", gc.AFOR, {}), ("group-pfd", gc.PFD, dict(zeta=(1, 10))),
+          ("bp128", gc.PFD, dict(zeta=(1, 32)))]
+    return v
+
+
+CFG5_BATCHES = {
+    "cfg5-pfd-k4": ("PFD", dict(k=4)),
+    "cfg5-afor-k4": ("AFOR", dict(k=4)),
+    "cfg5-pfd-k64": ("PFD", dict(k=64, pfd_pos=1)),
+    "cfg5-afor-k64": ("AFOR", dict(k=64)),
+}
+WORKLOADS = ["cfg3", "cfg2"] + list(CFG5_BATCHES)
 
 
 def kernel_name(cls, tile, carry_pass):
@@ -74,63 +112,129 @@ def codec_class(gc, codec, kw):
     return 3 if codec == gc.AFOR else 4
 
 
-def class_bytes(gc, parts, cls):
-    """Algorithmic bytes of one decode pass of a class: its streams read once
-    and its integers written once."""
-    b = 0
-    for p in parts:
-        if p["cls"] == cls:
-            b += 4 * int(p["streams"].size) + 4 * int(p["flat"].size)
-    return b
+class Workload:
+    """Streams of a batch (concatenated), the lists they decode to, and the
+    codec class of every list."""
+
+    def __init__(self, name, desc, streams, offs, lengths, cls, want):
+        self.name, self.desc = name, desc
+        self.streams, self.offs, self.lengths = streams, offs, lengths
+        self.cls, self.want = cls, want
+        self.ints = int(lengths.sum())
+
+    def class_bytes(self, c):
+        """Algorithmic bytes of one decode pass of class c: its streams read
+        once, its integers written once."""
+        m = self.cls == c
+        words = int(np.sum((self.offs[1:] - self.offs[:-1])[m]))
+        return 4 * words + 4 * int(self.lengths[m].sum())
+
+    def path_bytes(self):
+        return 4 * int(self.streams.size) + 4 * self.ints
 
 
-def build_workload(gc, synth):
-    t = time.time()
-    lengths, docs, tfs = synth.cfg2()
-    log("cfg2 generated: %d lists, %d docIDs (%.1fs)" % (lengths.size, docs.size, time.time() - t))
-    parts = []
-    for name, codec, kw in variants(gc):
-        for kind, flat, delta in (("docids", docs, True), ("tf", tfs, False)):
-            t = time.time()
-            s, offs = gc.encode_lists(flat, lengths, codec, gc.params(delta=delta, **kw))
-            parts.append(dict(name=name, kind=kind, codec=codec, streams=s, offs=offs,
-                              lengths=lengths, flat=flat, cls=codec_class(gc, codec, kw)))
-            log("encoded %-18s %-6s %.2f bits/int (%.1fs)" % (name, kind, 32.0 * s.size / flat.size,
-                                                              time.time() - t))
-    return parts
-
-
-def concat(parts):
-    streams = np.concatenate([p["streams"] for p in parts])
+def concat_parts(parts):
+    streams = np.concatenate([p[0] for p in parts])
     offs, base = [np.zeros(1, np.int64)], 0
-    for p in parts:
-        o = p["offs"].astype(np.int64)
+    for s, o in parts:
+        o = o.astype(np.int64)
         offs.append(o[1:] + base)
         base += int(o[-1])
-    lengths = np.concatenate([p["lengths"] for p in parts])
-    return streams, np.concatenate(offs), lengths
+    return streams, np.concatenate(offs)
 
 
-def read_traffic(units, kernel):
+def build_cfg3(gc, synth):
+    t = time.time()
+    lengths, docs, cidx = synth.cfg3()
+    codecs = five_codecs(gc)
+    cod = np.array([codecs[c][1] for c in cidx], np.int32)
+    plist = [gc.params(delta=True, **codecs[c][2]) for c in cidx]
+    s, offs = gc.encode_lists(docs, lengths, cod, plist)
+    cls = np.array([codec_class(gc, codecs[c][1], codecs[c][2]) for c in cidx], np.int32)
+    log("cfg3: %d lists, %d docIDs, %.2f bits/int (%.1fs)" % (lengths.size, docs.size, 32.0 * s.size / docs.size,
+                                                             time.time() - t))
+    desc = ("100,000 posting lists, lognormal lengths (median 1,024, max 2^22), 2.68e8 docIDs, universe 2^25, "
+            "70% sparse / 30% clustered d-gaps; each list in one of Group-Simple, Group-Scheme 1-CU, "
+            "Group-Scheme 8-IU, Group-AFOR, Group-PFD (zeta 1/10), 4-way layout; all lists decoded and "
+            "prefix-summed per step; seed 3")
+    return Workload("cfg3", desc, s, offs.astype(np.int64), lengths, cls, docs)
+
+
+def build_cfg2(gc, synth, variants=None):
+    t = time.time()
+    lengths, docs, tfs = synth.cfg2()
+    parts, cls, want = [], [], []
+    for name, codec, kw in (variants or five_codecs(gc)):
+        for flat, delta in ((docs, True), (tfs, False)):
+            s, offs = gc.encode_lists(flat, lengths, codec, gc.params(delta=delta, **kw))
+            parts.append((s, offs))
+            cls.append(np.full(lengths.size, codec_class(gc, codec, kw), np.int32))
+            want.append(flat)
+    s, offs = concat_parts(parts)
+    L = np.tile(lengths, len(parts))
+    log("cfg2: %d streams, %d integers, %.2f bits/int (%.1fs)" % (L.size, int(L.sum()), 32.0 * s.size / L.sum(),
+                                                                 time.time() - t))
+    desc = ("10,000 posting lists (Zipf lengths in [128, 2^22], 2^26 docIDs, universe 2^25, 70% sparse / 30% "
+            "clustered d-gaps) plus their TF lists (geometric p=0.4), each coded with Group-Simple, Group-Scheme "
+            "1-CU, Group-Scheme 8-IU, Group-AFOR and Group-PFD (zeta 1/10), 4-way layout; all 100,000 streams "
+            "decoded per step, docID lists prefix-summed; seed 2")
+    return Workload("cfg2", desc, s, offs, L, np.concatenate(cls), np.concatenate(want)), (lengths, docs, tfs)
+
+
+_CFG5 = None
+
+
+def build_cfg5(gc, synth, name):
+    global _CFG5
+    t = time.time()
+    if _CFG5 is None:
+        _CFG5 = synth.cfg5()
+    lengths, docs = _CFG5
+    codec_name, kw = CFG5_BATCHES[name]
+    codec = getattr(gc, codec_name)
+    s, offs = gc.encode_lists(docs, lengths, codec, gc.params(delta=True, **kw))
+    log("%s: %d lists, %d docIDs, %.2f bits/int (%.1fs)" % (name, lengths.size, docs.size,
+                                                           32.0 * s.size / docs.size, time.time() - t))
+    desc = ("1,000,000 posting lists, lognormal lengths (median 256, max 2^22), 5.37e8 docIDs, Pareto(1.2) "
+            "d-gaps with 20%% dense runs of gap 1; Group-%s, %d-way layout%s; all lists decoded and "
+            "prefix-summed per step; seed 6"
+            % ("PFD (zeta 1/10)" if codec_name == "PFD" else "AFOR", kw["k"],
+               ", bitmap exceptions" if kw.get("pfd_pos") else ""))
+    cls = np.full(lengths.size, codec_class(gc, codec, kw), np.int32)
+    return Workload(name, desc, s, offs.astype(np.int64), lengths, cls, docs)
+
+
+def read_traffic(workload, units, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current decode kernel source and this
-    workload."""
-    if not os.path.exists(TRAFFIC_FILE):
+    summary of `workload`, if it was taken on the current decode kernel
+    source, this workload and this kernel."""
+    path = traffic_file(workload)
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    sha = decode_sources_sha256()
-    if (kv.get("decode_sources_sha256") != sha or kv.get("workload_units") != str(units)
+    if (kv.get("decode_sources_sha256") != decode_sources_sha256() or kv.get("workload_units") != str(units)
             or kv.get("kernel") != kernel):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
 def cpu_threads():
@@ -143,7 +247,7 @@ def cpu_threads():
     return max(1, min(16, n))
 
 
-_CPU_PARTS = None
+_CPU_WL = None
 
 
 def _cpu_worker(args):
@@ -151,48 +255,47 @@ def _cpu_worker(args):
     about `seconds`; returns (lists, integers, seconds)."""
     import oracle as O
     order, k, stride, seconds = args
+    wl = _CPU_WL
     done_i = done_l = 0
     t0 = time.perf_counter()
     for idx in range(k, len(order), stride):
-        pi, li = order[idx]
-        p = _CPU_PARTS[pi]
-        done_i += O.decode(p["streams"][int(p["offs"][li]):int(p["offs"][li + 1])]).size
+        li = order[idx]
+        done_i += O.decode(wl.streams[int(wl.offs[li]):int(wl.offs[li + 1])]).size
         done_l += 1
         if time.perf_counter() - t0 > seconds:
             break
     return done_l, done_i, time.perf_counter() - t0
 
 
-def cpu_baseline(parts, seconds):
+def cpu_baseline(wl, seconds):
     """The plain C oracle decoding (and prefix-summing) a random sample of the
-    same streams: first in this process, then in one forked worker process per
-    host core (lists dealt round-robin), each for about `seconds` seconds."""
-    global _CPU_PARTS
+    workload's streams: first in this process, then in one forked worker
+    process per host core (lists dealt round-robin), each for about
+    `seconds` seconds."""
+    global _CPU_WL
     import multiprocessing as mp
-    _CPU_PARTS = parts
-    rng = np.random.default_rng(123)
-    order = [(pi, li) for pi in range(len(parts)) for li in range(parts[pi]["lengths"].size)]
-    rng.shuffle(order)
+    _CPU_WL = wl
+    order = np.random.default_rng(123).permutation(wl.lengths.size)
     one = _cpu_worker((order, 0, 1, seconds))
     nt = cpu_threads()
     with mp.get_context("fork").Pool(nt) as pool:
         res = pool.map(_cpu_worker, [(order, k, nt, seconds) for k in range(nt)])
-    # the slowest worker's decode time (pool start-up excluded)
-    wall = max(r[2] for r in res)
+    wall = max(r[2] for r in res)    # the slowest worker's decode time (pool start-up excluded)
     lists = sum(r[0] for r in res)
     ints = sum(r[1] for r in res)
     return dict(value=round(ints / wall / 1e9, 4), unit="Gints/s", cores=nt, kind="oracle",
                 per_core_value=round(one[1] / one[2] / 1e9, 4),
-                sample="lists drawn at random from the same 100,000 streams, each decoded and "
-                       "prefix-summed by the plain C oracle: %d lists (%d integers) on %d worker processes, the "
-                       "slowest busy %.2f s; in one process: %d lists (%d integers) in %.2f s"
-                       % (lists, ints, nt, wall, one[0], one[1], one[2]))
+                hardware_concurrency=os.cpu_count(), cpu_model=cpu_model(),
+                sample="lists of the %s workload drawn at random, each decoded and prefix-summed by the plain C "
+                       "oracle: %d lists (%d integers) on %d worker processes, the slowest busy %.2f s; in one "
+                       "process: %d lists (%d integers) in %.2f s"
+                       % (wl.name, lists, ints, nt, wall, one[0], one[1], one[2]))
 
 
 def cfg1_latency(gc, synth, ctx, torch, reps=30):
     """One list of 2^20 docIDs (mean gap 16) in Group-Simple, decoded and
-    prefix-summed by gc_decode (locate, tile sums, carry scan, decode):
-    the single-list latency, timed with HIP events around each call."""
+    prefix-summed by gc_decode: the single-list latency, timed with HIP events
+    around each call."""
     docs = synth.cfg1()
     s = gc.encode(docs, gc.SIMPLE, gc.params(delta=True))
     d_s = gc.to_device(s)
@@ -213,15 +316,165 @@ def cfg1_latency(gc, synth, ctx, torch, reps=30):
                 min_us=round(us[0], 2), gints_s=round(docs.size / med / 1e3, 2), verified_bit_exact=bool(ok))
 
 
-def timed(plan, d_s, d_o, steps, warmup, torch):
+def timed(run, steps, warmup, torch):
     for _ in range(warmup):
-        plan.decode_batch(d_s, d_o)
+        run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        plan.decode_batch(d_s, d_o)
+        run()
     torch.cuda.synchronize()
     return time.perf_counter() - t0
+
+
+class Measured:
+    pass
+
+
+def measure(gc, torch, ctx, wl, args, keep_device=False):
+    """Times one workload: an autotuned plan replayed from a hipGraph (the
+    value), then a plan with the same tiles and HIP events between the phases
+    (per-phase times, the dominant decode kernel's duration); verifies the
+    output bit-exact."""
+    descs, headers, out_offs = gc.batch_layout(wl.streams, wl.offs, wl.lengths, align=4)
+    d_s = gc.to_device(wl.streams)
+    d_o = torch.empty(int(out_offs[-1]), dtype=torch.int32, device="cuda")
+    t = time.time()
+    plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=args.tile, locate_stream=args.locate_stream,
+                   pfd_tile_ints=args.pfd_tile or (4096 if args.tile else 0),
+                   autotune=args.tile == 0, use_graph=True, carry_pass=args.carry_pass)
+    cfg = plan.config()
+    log("%s plan: %s (%.1fs)" % (wl.name, cfg, time.time() - t))
+    tplan = gc.Plan(ctx, descs, headers, d_s, d_o, class_tiles=cfg["class_tiles"],
+                    locate_stream=args.locate_stream, timing_slots=args.steps + args.warmup,
+                    carry_pass=args.carry_pass)
+    elapsed = timed(lambda: plan.decode_batch(d_s, d_o), args.steps, args.warmup, torch)
+    t_events = timed(lambda: tplan.decode_batch(d_s, d_o), args.steps, args.warmup, torch)
+    tm = tplan.timings(args.steps)
+    rc, detail = ctx.sync_status()
+    if rc != gc.OK:
+        raise SystemExit("%s: device reported %d (detail %d)" % (wl.name, rc, detail))
+    got = gc.unpad(gc.to_host(d_o), out_offs, wl.lengths)
+    verified = bool(np.array_equal(got, wl.want))
+    del got
+    if not verified:
+        raise SystemExit("%s: decoded output differs from the generated lists" % wl.name)
+    m = Measured()
+    m.cfg, m.verified, m.descs = cfg, verified, descs
+    m.ms_per_step = 1e3 * elapsed / args.steps
+    m.value = wl.ints / (elapsed / args.steps) / 1e9
+    m.path_gbs = wl.path_bytes() / (elapsed / args.steps) / 1e9
+    dec = tm["decode"].mean(axis=0)
+    m.dec = dec
+    m.cls = int(np.argmax(dec))                 # the dominant kernel: the longest decode pass
+    m.cls_bytes = wl.class_bytes(m.cls)
+    m.dec_avg = float(dec[m.cls])
+    m.achieved = m.cls_bytes / (m.dec_avg * 1e-3) / 1e9
+    m.kname = kernel_name(m.cls, cfg["class_tiles"][m.cls], args.carry_pass)
+    present = [c for c in range(5) if np.any(wl.cls == c)]
+    m.phases = {
+        "note": "from a second plan with the same tiles and HIP events between the phases",
+        "gpu_total": round(float(tm["total"].mean()), 4),
+        "events_ms_per_step": round(1e3 * t_events / args.steps, 4),
+        "locate": ({CLASS_NAMES[c]: round(float(tm["locate"][:, c].mean()), 4) for c in present}
+                   if args.locate_stream else {"all classes": round(float(tm["locate"].sum(axis=1).mean()), 4)}),
+        "sum_and_carry": {CLASS_NAMES[c]: round(float(tm["sum"][:, c].mean()), 4) for c in present},
+        "decode": {CLASS_NAMES[c]: round(float(dec[c]), 4) for c in present},
+        "decode_hbm_frac": {CLASS_NAMES[c]: round(wl.class_bytes(c) / (float(dec[c]) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                                  4) for c in present},
+    }
+    log("%s: step %.3f ms, %.1f Gints/s, path %.0f GB/s (%.1f%% of HBM); dominant %s decode %.3f ms, %.0f GB/s; "
+        "phases %s" % (wl.name, m.ms_per_step, m.value, m.path_gbs, 100 * m.path_gbs / HBM_PEAK_GBS,
+                       CLASS_NAMES[m.cls], m.dec_avg, m.achieved, m.phases))
+    tplan.close()
+    if keep_device:
+        m.plan, m.d_s, m.d_o, m.out_offs = plan, d_s, d_o, out_offs
+    else:
+        plan.close()
+        del d_s, d_o
+    return m
+
+
+def leg_record(wl, m):
+    return dict(workload=wl.desc, value=round(m.value, 3), unit="Gints/s", ms_per_step=round(m.ms_per_step, 4),
+                ints_per_step=wl.ints, lists=int(wl.lengths.size), bits_per_int=round(32.0 * wl.streams.size / wl.ints, 3),
+                path_hbm_frac=round(m.path_gbs / HBM_PEAK_GBS, 4), class_tile_ints=m.cfg["class_tiles"],
+                dominant_kernel=m.kname, dominant_kernel_ms=round(m.dec_avg, 4),
+                dominant_kernel_hbm_frac=round(m.achieved / HBM_PEAK_GBS, 4), phases_ms=m.phases,
+                verified_bit_exact=m.verified)
+
+
+def per_list_legs(gc, torch, ctx, wl, m, args):
+    """One launch sequence per list (the same kernels): every list of the
+    workload queued directly on one stream; and, on the first 10,000 lists,
+    those launches replayed from one hipGraph beside the batched plan of the
+    same lists."""
+    res = {}
+    plan, d_s, d_o = m.plan, m.d_s, m.d_o
+    plan.decode_each(d_s, d_o)
+    torch.cuda.synchronize()
+    reps = 2
+    t = timed(lambda: plan.decode_each(d_s, d_o), reps, 0, torch) / reps
+    rc, det = ctx.sync_status()
+    ok = rc == gc.OK and np.array_equal(gc.unpad(gc.to_host(d_o), m.out_offs, wl.lengths), wl.want)
+    res["per_list"] = dict(value=round(wl.ints / t / 1e9, 3), unit="Gints/s", ms_per_run=round(1e3 * t, 2),
+                           batched_speedup=round(m.value / (wl.ints / t / 1e9), 2), verified_bit_exact=bool(ok),
+                           note="one launch sequence per list, all %d lists queued on one stream" % wl.lengths.size)
+    # a subset captured in a graph
+    nsub = min(10_000, wl.lengths.size)
+    s_end = int(wl.offs[nsub])
+    sub_l = wl.lengths[:nsub]
+    descs, headers, out_offs = gc.batch_layout(wl.streams[:s_end], wl.offs[:nsub + 1], sub_l, align=4)
+    ds2 = gc.to_device(wl.streams[:s_end])
+    do2 = torch.full((int(out_offs[-1]),), -1, dtype=torch.int32, device="cuda")
+    want = wl.want[:int(sub_l.sum())]
+    p2 = gc.Plan(ctx, descs, headers, ds2, do2, class_tiles=m.cfg["class_tiles"], use_graph=True,
+                 carry_pass=args.carry_pass)
+    t_b = timed(lambda: p2.decode_batch(ds2, do2), 10, 2, torch) / 10
+    t_d = timed(lambda: p2.decode_each(ds2, do2), 2, 1, torch) / 2
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        p2.decode_each(ds2, do2)
+    do2.fill_(-1)
+    t_g = timed(g.replay, 5, 1, torch) / 5
+    rc, det = ctx.sync_status()
+    ok = rc == gc.OK and np.array_equal(gc.unpad(gc.to_host(do2), out_offs, sub_l), want)
+    n2 = int(sub_l.sum())
+    res["per_list_graph"] = dict(
+        lists=nsub, ints=n2, verified_bit_exact=bool(ok),
+        batched_gints_s=round(n2 / t_b / 1e9, 3), per_list_direct_gints_s=round(n2 / t_d / 1e9, 3),
+        per_list_graph_gints_s=round(n2 / t_g / 1e9, 3), batched_speedup_vs_graph=round(t_g / t_b, 2),
+        note="the first %d lists of the workload: the batched plan, one launch sequence per list queued "
+             "directly, and those per-list launches replayed from one hipGraph" % nsub)
+    log("per-list: %s" % res)
+    del g
+    p2.close()
+    del ds2, do2
+    return res
+
+
+def variants_leg(gc, torch, ctx, synth, args, cfg2_data):
+    """Section 7.2's trade-off on the cfg2 lists: every variant's bits/int,
+    Gints/s and decode-pass % of HBM (docIDs and TFs of one variant per
+    batch)."""
+    lengths, docs, tfs = cfg2_data
+    out = {}
+    for name, codec, kw in all_variants(gc):
+        parts = []
+        for flat, delta in ((docs, True), (tfs, False)):
+            parts.append(gc.encode_lists(flat, lengths, codec, gc.params(delta=delta, **kw)))
+        s, offs = concat_parts(parts)
+        L = np.tile(lengths, 2)
+        c = codec_class(gc, codec, kw)
+        wl = Workload(name, name, s, offs, L, np.full(L.size, c, np.int32), np.concatenate([docs, tfs]))
+        m = measure(gc, torch, ctx, wl, args)
+        out[name] = dict(gints_s=round(m.value, 2), bits_per_int_docids=round(32.0 * parts[0][0].size / docs.size, 3),
+                         bits_per_int_tf=round(32.0 * parts[1][0].size / tfs.size, 3),
+                         path_hbm_frac=round(m.path_gbs / HBM_PEAK_GBS, 4),
+                         decode_ms=round(m.dec_avg, 4), decode_hbm_frac=round(m.achieved / HBM_PEAK_GBS, 4))
+        log("%-14s %s" % (name, out[name]))
+        del wl, s
+    return out
 
 
 def main():
@@ -229,9 +482,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg3", choices=WORKLOADS,
+                    help="the workload timed for `value`; any other than cfg3 is measured alone (no legs)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extra", action="store_true", help="skip per-list and per-codec runs")
+    ap.add_argument("--no-extra", action="store_true", help="skip every leg")
     ap.add_argument("--tile", type=int, default=0, help="force the wave-tile size (0 = autotune)")
     ap.add_argument("--pfd-tile", type=int, default=0, help="force the Group-PFD tile size (with --tile)")
     ap.add_argument("--locate-stream", action="store_true",
@@ -253,158 +508,80 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     gc.lib()
+    legs = args.workload == "cfg3" and not args.no_extra
 
-    parts = build_workload(gc, synth)
-    streams, offs, lengths = concat(parts)
-    descs, headers, out_offs = gc.batch_layout(streams, offs, lengths, align=4)
-    total = int(lengths.sum())
-    out_len = int(out_offs[-1])
-    stream_bytes = 4 * int(streams.size)
+    cfg2_data = None
+    if args.workload == "cfg3":
+        wl = build_cfg3(gc, synth)
+    elif args.workload == "cfg2":
+        wl, cfg2_data = build_cfg2(gc, synth)
+    else:
+        wl = build_cfg5(gc, synth, args.workload)
     ctx = gc.Context(0)
-    d_s = gc.to_device(streams)
-    d_o = torch.empty(out_len, dtype=torch.int32, device="cuda")
-    t = time.time()
-    # the timed plan: autotuned tiles, the whole run captured in one hipGraph
-    plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=args.tile, locate_stream=args.locate_stream,
-                   pfd_tile_ints=args.pfd_tile or (4096 if args.tile else 0),
-                   autotune=args.tile == 0, use_graph=True, carry_pass=args.carry_pass)
-    cfg = plan.config()
-    log("plan: %s (%.1fs)" % (cfg, time.time() - t))
-    # the same tiles with HIP events between the phases (direct launches), for
-    # the per-phase times and the dominant kernel's duration
-    tplan = gc.Plan(ctx, descs, headers, d_s, d_o, class_tiles=cfg["class_tiles"],
-                    locate_stream=args.locate_stream, timing_slots=args.steps + args.warmup,
-                    carry_pass=args.carry_pass)
-
-    elapsed = timed(plan, d_s, d_o, args.steps, args.warmup, torch)
-    t_events = timed(tplan, d_s, d_o, args.steps, args.warmup, torch)
-    tm = tplan.timings(args.steps)
-    rc, detail = ctx.sync_status()
-    if rc != gc.OK:
-        raise SystemExit("device reported %d (detail %d)" % (rc, detail))
-    got = gc.unpad(gc.to_host(d_o), out_offs, lengths)
-    want = np.concatenate([p["flat"] for p in parts])
-    verified = bool(np.array_equal(got, want))
-    del got, want
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = total / (elapsed / args.steps) / 1e9
-    # the dominant kernel: the decode pass of the class that takes longest
-    dec = tm["decode"].mean(axis=0)
-    cls = int(np.argmax(dec))
-    cls_bytes = class_bytes(gc, parts, cls)
-    dec_avg = float(dec[cls])
-    achieved = cls_bytes / (dec_avg * 1e-3) / 1e9
-    log("step %.3f ms  %.1f Gints/s  (with events between phases %.3f ms, GPU %.3f ms; per class locate %s, "
-        "sum+carry %s, decode %s)  verified=%s"
-        % (ms_per_step, value, 1e3 * t_events / args.steps, tm["total"].mean(), np.round(tm["locate"].mean(axis=0), 3),
-           np.round(tm["sum"].mean(axis=0), 3), np.round(dec, 3), verified))
-    log("dominant kernel: %s decode pass %.3f ms, %.0f GB/s" % (CLASS_NAMES[cls], dec_avg, achieved))
-    if not verified:
-        raise SystemExit("decoded output differs from the generated lists")
-    kname = kernel_name(cls, cfg["class_tiles"][cls], args.carry_pass)
-    traffic = read_traffic(len(descs), kname)
+    m = measure(gc, torch, ctx, wl, args, keep_device=True)
+    traffic = read_traffic(wl.name, len(m.descs), m.kname)
 
     extra = {}
-    if not args.no_extra:
-        # one launch sequence per list, same kernels (the per-list baseline)
-        plan.decode_each(d_s, d_o)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        reps = 2
-        for _ in range(reps):
-            plan.decode_each(d_s, d_o)
-        torch.cuda.synchronize()
-        per_list = total / ((time.perf_counter() - t0) / reps) / 1e9
-        extra["per_list"] = dict(value=round(per_list, 3), unit="Gints/s",
-                                 batched_speedup=round(value / per_list, 2))
-        log("per-list launches: %.2f Gints/s, batched speedup %.1fx" % (per_list, value / per_list))
-        per = {}
-        for i in range(0, len(parts), 2):
-            sub = parts[i:i + 2]
-            s2, o2, l2 = concat(sub)
-            de2, h2, oo2 = gc.batch_layout(s2, o2, l2, align=4)
-            ds2 = gc.to_device(s2)
-            do2 = torch.empty(int(oo2[-1]), dtype=torch.int32, device="cuda")
-            p2 = gc.Plan(ctx, de2, h2, ds2, do2, class_tiles=cfg["class_tiles"], timing_slots=args.steps,
-                         carry_pass=args.carry_pass)
-            el = timed(p2, ds2, do2, args.steps, 2, torch)
-            t2 = p2.timings(args.steps)
-            c2 = sub[0]["cls"]
-            n2 = int(l2.sum())
-            gbs = class_bytes(gc, sub, c2) / (float(t2["decode"][:, c2].mean()) * 1e-3) / 1e9
-            per[sub[0]["name"]] = dict(gints_s=round(n2 / (el / args.steps) / 1e9, 2),
-                                       bits_per_int_docids=round(32.0 * sub[0]["streams"].size / n2 * 2, 3),
-                                       bits_per_int_tf=round(32.0 * sub[1]["streams"].size / n2 * 2, 3),
-                                       locate_ms=round(float(t2["locate"][:, c2].mean()), 4),
-                                       sum_ms=round(float(t2["sum"][:, c2].mean()), 4),
-                                       decode_ms=round(float(t2["decode"][:, c2].mean()), 4),
-                                       decode_kernel_gbs=round(gbs, 1),
-                                       hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
-            log("%-18s %s" % (sub[0]["name"], per[sub[0]["name"]]))
-            p2.close()
-            del ds2, do2
-        extra["per_codec"] = per
+    if legs:
+        extra.update(per_list_legs(gc, torch, ctx, wl, m, args))
+    m.plan.close()
+    del m.d_s, m.d_o
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(wl, args.cpu_seconds)
+        log("cpu oracle: %s" % cpu)
+    if legs:
+        w2, cfg2_data = build_cfg2(gc, synth)
+        extra["cfg2"] = leg_record(w2, measure(gc, torch, ctx, w2, args))
+        del w2
+        for name in CFG5_BATCHES:
+            w5 = build_cfg5(gc, synth, name)
+            extra[name] = leg_record(w5, measure(gc, torch, ctx, w5, args))
+            del w5
+        extra["variants_cfg2"] = variants_leg(gc, torch, ctx, synth, args, cfg2_data)
         extra["cfg1_latency"] = cfg1_latency(gc, synth, ctx, torch)
         log("cfg1 single list: %s" % extra["cfg1_latency"])
 
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(parts, args.cpu_seconds)
-        log("cpu oracle: %.4f Gints/s on %d threads, %.4f on one (%s)"
-            % (cpu["value"], cpu["cores"], cpu["per_core_value"], cpu["sample"]))
-
     line = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": round(m.value, 3),
         "unit": "Gints/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(m.ms_per_step, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
         "config": {
-            "workload": "10,000 posting lists (Zipf lengths in [128, 2^22], 2^26 docIDs, universe "
-                        "2^25, 70% sparse / 30% clustered d-gaps) plus their TF lists (geometric "
-                        "p=0.4), each coded with Group-Simple, Group-Scheme 1-CU, Group-Scheme "
-                        "8-IU, Group-AFOR and Group-PFD (zeta 1/10), 4-way layout; all 100,000 "
-                        "streams decoded per step (locate, tile sums, carry scans, decode passes), "
-                        "docID lists prefix-summed; seed 2",
-            "lists": len(descs),
-            "ints_per_step": total,
-            "stream_bytes": stream_bytes,
-            "bits_per_int": round(32.0 * streams.size / total, 3),
-            "tile_ints": cfg["tile_ints"],
-            "pfd_tile_ints": cfg["pfd_tile_ints"],
-            "class_tile_ints": cfg["class_tiles"],
-            "tiles": cfg["tiles"],
-            "sum_tiles": cfg["sum_tiles"],
-            "verified_bit_exact": verified,
+            "workload": wl.desc,
+            "name": wl.name,
+            "lists": len(m.descs),
+            "ints_per_step": wl.ints,
+            "stream_bytes": 4 * int(wl.streams.size),
+            "bits_per_int": round(32.0 * wl.streams.size / wl.ints, 3),
+            "tile_ints": m.cfg["tile_ints"],
+            "pfd_tile_ints": m.cfg["pfd_tile_ints"],
+            "class_tile_ints": m.cfg["class_tiles"],
+            "tiles": m.cfg["tiles"],
+            "sum_tiles": m.cfg["sum_tiles"],
+            "verified_bit_exact": m.verified,
         },
+        "path_hbm_frac": round(m.path_gbs / HBM_PEAK_GBS, 4),
         "roofline": {
             "bound": "hbm",
-            "kernel": kname,
-            "achieved": round(achieved, 1),
+            "kernel": m.kname,
+            "achieved": round(m.achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "frac": round(m.achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "algorithmic_bytes_per_launch": cls_bytes,
-            "avg_kernel_ms": round(dec_avg, 4),
+            "algorithmic_bytes_per_launch": m.cls_bytes,
+            "avg_kernel_ms": round(m.dec_avg, 4),
         },
-        "phases_ms": {
-            "note": "from a second plan with the same tiles and HIP events between the phases",
-            "gpu_total": round(float(tm["total"].mean()), 4),
-            "locate": ({CLASS_NAMES[c]: round(float(tm["locate"][:, c].mean()), 4)
-                        for c in range(5) if dec[c] > 0} if args.locate_stream
-                       else {"all classes": round(float(tm["locate"].sum(axis=1).mean()), 4)}),
-            "sum_and_carry": {CLASS_NAMES[c]: round(float(tm["sum"][:, c].mean()), 4)
-                              for c in range(5) if dec[c] > 0},
-            "decode": {CLASS_NAMES[c]: round(float(dec[c]), 4) for c in range(5) if dec[c] > 0},
-        },
+        "phases_ms": m.phases,
         "cpu_baseline": cpu,
     }
     line.update(extra)
@@ -414,8 +591,6 @@ def main():
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    plan.close()
-    tplan.close()
     ctx.close()
     print(json.dumps(line), flush=True)
 

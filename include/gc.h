@@ -114,9 +114,25 @@ gc_status gc_encode_lists(const uint32_t *h_in, const uint64_t *in_offs, size_t 
 typedef struct gc_ctx gc_ctx;     /* opaque, library-owned */
 typedef struct gc_plan gc_plan;   /* opaque, library-owned */
 
+/* Context options (zero-initialise for defaults). */
+typedef struct {
+    uint64_t max_list_ints;  /* longest list gc_decode decodes and gc_blockmix_encode /
+                                gc_encode_blocks encode (at most 2^32 - 1); their
+                                device tables are sized for it here; 0 = 2^24  */
+    uint32_t reserved[2];    /* zero */
+} gc_ctx_opts;
+
 /* Creates a context on HIP device `device` (made current for the call).
- * Allocates the device status word and the single-list scratch.           */
+ * Allocates the device status word and the tables of single-list decoding
+ * and block encoding, sized for opts->max_list_ints (about 45 bytes per
+ * 1024 integers for decoding, 170 bytes per 128 for block encoding; about
+ * 24 MB at the default 2^24) -- the only allocations a context makes.
+ * gc_ctx_create(device, ctx) is gc_ctx_create_opts(device, NULL, ctx).
+ * GC_EINVAL for nonzero reserved words or a maximum above 2^32 - 1,
+ * GC_ENOMEM if the tables do not fit, GC_EUNSUPPORTED on a device other
+ * than gfx950.                                                             */
 gc_status gc_ctx_create(int device, gc_ctx **ctx);
+gc_status gc_ctx_create_opts(int device, const gc_ctx_opts *opts, gc_ctx **ctx);
 gc_status gc_ctx_destroy(gc_ctx *ctx);
 
 /* Decodes one stream (device memory, stream_words words) into d_out[0..n),
@@ -124,9 +140,15 @@ gc_status gc_ctx_destroy(gc_ctx *ctx);
  * copy of the stream's first 4 words (the index dictionary keeps each list's
  * length and codec, Section 2.1.1, so no device-to-host read is needed); n is
  * h_header[1].  The kernels re-check the device copy against it.
- * Asynchronous on hip_stream.  Calls on one context must not overlap in time
- * (they share its scratch); use one context per concurrent stream.
- * d_stream must be 16-byte aligned.  GC_ECORRUPT if h_header is malformed. */
+ * Asynchronous on hip_stream: it launches kernels only (the locate pass,
+ * for a list of several tiles, and the decode pass, with a tile-sum pass and
+ * carry scan for a long delta list); it allocates nothing and never
+ * synchronises, so it may be captured in a hipGraph and replayed.  Calls on
+ * one context must not overlap in time (they share its tables); use one
+ * context per concurrent stream.  d_stream must be 16-byte aligned.
+ * GC_ECORRUPT if h_header is malformed, GC_ENOSPC if the list is longer
+ * than the context's max_list_ints (or its control area larger than such a
+ * list's can be).                                                          */
 gc_status gc_decode(gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words,
                     const uint32_t *h_header, uint32_t *d_out, void *hip_stream);
 
@@ -169,8 +191,14 @@ typedef struct {
                                 3 look-back for lists of at most 64 tiles
                                 (one window of flags), the tile-sum pass for
                                 longer ones; 0 = default (3)                   */
-    uint32_t reserved;       /* zero */
+    uint32_t pack_ints;      /* lists of at most this many integers (1 .. 2048)
+                                whose streams fit a pack's staging buffer (4
+                                KB) are decoded many to a wave by the pack
+                                kernels instead of by the class passes;
+                                GC_PACK_OFF: none; 0 = autotuned (with
+                                autotune) or the default, 2048               */
 } gc_plan_opts;
+#define GC_PACK_OFF 0x80000000u
 
 /* Builds a batched decode plan for nlists lists.  h_headers holds the first
  * 4 words of every stream (4*nlists words, host memory).  The plan holds the
@@ -189,7 +217,8 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
                          const uint32_t *d_streams, uint32_t *d_out, gc_plan **plan);
 gc_status gc_plan_destroy(gc_plan *plan);
 
-/* Decodes every list of the plan: the locate pass, then per codec class the
+/* Decodes every list of the plan: the pack kernels over the packed lists
+ * (see opts->pack_ints), the locate pass, then per codec class the
  * tile-sum pass over its delta lists whose tiles take their carries from it
  * (see opts->carry_pass), the carry scan and the decode pass, replayed as one
  * hipGraph when the plan was created with use_graph.                       */
@@ -214,13 +243,14 @@ gc_status gc_decode_each(gc_plan *plan, const uint32_t *d_streams, uint32_t *d_o
  *                               others)
  *   [1 + GC_CLASSES + c]        its tile-sum pass and carry scan
  *   [1 + 2 * GC_CLASSES + c]    its decode pass
+ *   [1 + 3 * GC_CLASSES]        the pack kernels
  * with classes c = 0 Group-Simple, 1 Group-Scheme with unary descriptors,
  * 2 Group-Scheme with binary descriptors, 3 Group-AFOR, 4 Group-PFD (0 for a
  * class the plan does not hold).  With schedule 1 locate kernels overlap the
  * other phases, so the phases need not add up to the whole run.  *nruns receives the rows
  * written.  GC_EINVAL if the plan records no events.                       */
 #define GC_CLASSES 5
-#define GC_TIMING_FIELDS (1 + 3 * GC_CLASSES)
+#define GC_TIMING_FIELDS (2 + 3 * GC_CLASSES)
 gc_status gc_plan_timings(gc_plan *plan, uint32_t max_runs, float *ms, uint32_t *nruns);
 
 /* Reports the chosen configuration of a plan: the tile size of its first
@@ -228,6 +258,11 @@ gc_status gc_plan_timings(gc_plan *plan, uint32_t max_runs, float *ms, uint32_t 
  * those, the tiles of its tile-sum pass.  Any pointer may be NULL.         */
 gc_status gc_plan_config(const gc_plan *plan, uint32_t *tile_ints, uint32_t *pfd_tile_ints,
                          uint64_t *tiles, uint64_t *sum_tiles);
+
+/* The packed-list threshold a plan uses (0: no packing), its packs (waves
+ * of the pack kernels) and the lists they hold.  Any pointer may be NULL.  */
+gc_status gc_plan_pack_config(const gc_plan *plan, uint32_t *pack_ints, uint64_t *packs,
+                              uint64_t *packed_lists);
 
 /* The tile size (integers per wave tile) of every codec class of a plan,
  * GC_CLASSES entries in class order (sizes of classes the plan does not hold
@@ -287,7 +322,8 @@ size_t gc_blockmix_bound_words(size_t n);
  * class d_class[b] (device memory, one byte per block).  *out_words
  * receives the container's length.  The sizing, offset and writing kernels
  * run on hip_stream back to back; the call returns once they have finished
- * and the total is read back.  GC_ENOSPC if out_cap_words is too small,
+ * and the total is read back.  GC_ENOSPC if out_cap_words is too small
+ * or n exceeds the context's max_list_ints,
  * GC_EINVAL for a class >= GC_BLOCK_CLASSES or when
  * gc_blockmix_bound_words(n) exceeds 2^32 - 1; nothing is written past
  * out_cap_words, and after an error the contents of d_out are undefined.   */

@@ -1181,9 +1181,9 @@ int or_block_decode(uint32_t blockword, const uint32_t *payload, size_t words, u
 }
 
 /* The 40 block features (a reading of the selector's inputs): the maximum
- * bit width / 32; the histogram of per-integer widths 0..32 / 128; the
- * number of integers wider than maxW - t, t = 1..6, / 128 (all of them when
- * maxW - t < 0). */
+ * bit width / 32; the histogram of the 32 tuple widths (a tuple's width is
+ * its widest integer's), bins 0..32, each count / 32; the number of integers
+ * wider than maxW - t, t = 1..6, / 128 (all of them when maxW - t < 0). */
 void or_block_features(const uint32_t *x, double *f)
 {
     /* the width of a tuple is the width of its widest integer (the width

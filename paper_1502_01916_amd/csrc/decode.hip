@@ -50,8 +50,15 @@ typedef __attribute__((address_space(1))) u32x4 gu32x4;
 
 constexpr uint32_t kEpochMask = 0x3FFFFFFFu;
 
+// Epochs of codec class c run c + 1, c + 1 + kClasses, ... (never 0, the
+// value of a flag or tile start no run has written), so the epochs of two
+// classes never meet: a flag or tile start that one class's run left in a
+// scratch slot cannot pass for another class's, whatever the tile ranges of
+// later runs (a plan re-tiled by the autotuner, a context's single-list
+// scratch shared by every class).
 __device__ __forceinline__ uint32_t epoch_next(uint32_t e) {
-    return ((e + 1u) & kEpochMask) ? ((e + 1u) & kEpochMask) : 1u;
+    const uint32_t n = e + (uint32_t)kClasses;
+    return n <= kEpochMask ? n : (e - 1u) % (uint32_t)kClasses + 1u;
 }
 
 // Exclusive scan over the workgroup; `tmp` holds kWaves words of LDS.
@@ -506,6 +513,14 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
 // Decode kernels.
 
 enum : int { kClsSim = 0, kClsGscU = 1, kClsGscB = 2, kClsAfor = 3, kClsPfd = 4 };
+
+// Decode kernel class of a header word 0 (-1 for a word no decoder accepts).
+__device__ __forceinline__ int codec_class_dev(uint32_t w0) {
+    HeaderFields h;
+    if (!header_fields(w0, h)) return -1;
+    return h.codec == 0 ? kClsSim : h.codec == 1 ? (h.ld == GC_LD_BINARY ? kClsGscB : kClsGscU)
+                                                 : h.codec == 2 ? kClsAfor : kClsPfd;
+}
 
 struct TileCtx {
     const uint32_t *S;
@@ -1754,6 +1769,227 @@ __global__ __launch_bounds__(kThreads, (MODE == kModeSum && CLS == kClsPfd) ? 7 
 }
 
 // ===========================================================================
+// Pack kernel: many short lists per wave.
+//
+// A list of one tile still pays a tile's whole chain of dependent loads
+// (its work item, its descriptor, then its header, control words and rows)
+// for a few hundred integers.  Here a wave takes a pack of up to 64 such
+// lists: lane j loads list j's descriptor, a wave scan places the lists'
+// whole streams one after another in the wave's LDS staging buffer, and the
+// wave copies them in with 16-byte loads, every list's at once.  It then
+// runs, list after list, the codec's prologue on the staged control words
+// and the unpack on the staged rows (tiles of PT integers: 1024, or 2048
+// for the 64-way layout), writing each list to its own output.  Nothing is
+// carried between lists, so a list's prefix sum starts from zero.
+
+template <int PT>
+union PackProlog {
+    WaveSmem<PT, kClsSim> sim;
+    WaveSmem<PT, kClsGscU> gscu;
+    WaveSmem<PT, kClsGscB> gscb;
+    WaveSmem<PT, kClsAfor> afor;
+    WaveSmem<PT, kClsPfd> pfd;
+};
+
+// SBC: staging chunks (16 bytes) for the pack's streams; one row of the
+// widest layout (16 chunks) follows them, which the unpack may read past a
+// list's last row (those bits are masked off).
+template <int PT, int SBC>
+struct PackSmem {
+    PackProlog<PT> u;
+    u32x4 stage[SBC + 16];
+    uint32_t soff[64];     // staging chunk offset of list j (the total for j >= the pack's lists)
+};
+
+// Early control words of a packed list's prologue, from the staged stream:
+// every word the prologue may read (the unary Group-Scheme prologue reads
+// past its early words from global memory otherwise).
+template <int PT, int CLS>
+constexpr int pack_ctrl_words() {
+    return CLS == kClsGscU ? (WaveSmem<PT, kClsGscU>::NCTRL + 63) / 64 : ctrl_early_words<PT, CLS>();
+}
+
+// Decodes packed list `sw` (its stream staged in LDS at sw, the host's
+// copy of its header in w0 / n / C / D) to out.
+template <int PT, int CLS, int SBC>
+__device__ void pack_list(const PackArgs &a, WaveSmem<PT, CLS> &sm, const uint32_t *sw, const uint32_t *S,
+                          uint32_t *out, uint32_t n, uint32_t w0, uint32_t C, uint32_t D, uint32_t words,
+                          uint32_t lane) {
+    using SM = WaveSmem<PT, CLS>;
+    constexpr int R = PT / 256;
+    constexpr bool PATCH = CLS == kClsPfd;
+    TileCtx c;
+    c.S = S;
+    c.n = n;
+    c.C = C;
+    c.D = D;
+    bool ok = header_fields(w0, c.h);
+    c.k = (uint32_t)c.h.k;
+    c.lk = (uint32_t)c.h.lk;
+    c.T = (n + c.k - 1u) >> c.lk;
+    c.TT = (uint32_t)PT >> c.lk;
+    c.t0 = 0;
+    c.i0 = 0;
+    ok = ok && n >= 1u && n <= (uint32_t)PT && (32u << c.lk) <= (uint32_t)PT && 4u + C + D <= words;
+    c.ntup = ok ? c.T : 0u;
+    c.nint = ok ? n : 0u;
+    c.ctrl = S + 4;
+    c.data = S + 4 + C;
+    c.has_en = false;
+    c.st = TileInfo{};
+    c.en = TileInfo{};
+    // the stream's own header against the host's copy
+    if (ok && (sw[0] != w0 || sw[1] != n || sw[2] != C || sw[3] != D)) {
+        if (lane == 0) latch(a.status, kErrHeader);
+        return;
+    }
+    constexpr int CE = pack_ctrl_words<PT, CLS>();
+    uint32_t ce[CE];
+    uint32_t cw0 = 0, nw = 0;
+    tile_ctrl_words<CLS>(c, cw0, nw);
+    const bool cok = ok && nw > 0u && cw0 + nw <= C;
+#pragma unroll
+    for (int v = 0; v < CE; v++) {
+        const uint32_t i = (uint32_t)v * 64u + lane;
+        ce[v] = cok && i < nw ? sw[4u + cw0 + i] : 0u;
+    }
+    uint32_t dbase = 0, err = ok ? 0u : kErrRange;
+    PatchSrc ps{sm.bmap, sm.vbit, sm.xcnt, nullptr, ExcSrc{nullptr, nullptr, 0u, false}, false};
+    if (!err) {
+        if constexpr (CLS == kClsSim) err = wprologue_sim<PT, CE>(c, sm, lane, dbase, ce, cok);
+        else if constexpr (CLS == kClsGscU) err = wprologue_gscu<PT, CE>(c, sm, lane, dbase, ce, cok);
+        else if constexpr (CLS == kClsGscB) err = wprologue_gscb<PT, CE>(c, sm, lane, dbase, ce, cok);
+        else if constexpr (CLS == kClsAfor) err = wprologue_afor<PT, CE>(c, sm, lane, dbase, ce);
+        else err = wprologue_pfd<PT>(c, sm, lane, dbase, words, ps.xs, ce[0], cok);
+    }
+    // the list's rows, staged after its control words (16-byte aligned: the
+    // header and the control area are whole chunks)
+    const uint32_t kq = c.k >> 2;
+    const uint32_t nrow = c.D >> c.lk;
+    const u32x4 *rows = reinterpret_cast<const u32x4 *>(sw + 4u + C);
+    uint32_t nint = err || dbase != 0u ? 0u : c.nint;
+    if (dbase != 0u && !err) err = kErrRange;
+    if constexpr (CLS == kClsPfd) {
+        if (!err) {
+            // the exceptions follow the rows in the staged stream
+            ExcSrc &xs = ps.xs;
+            xs.lds = sw + 4u + C + D;
+            xs.staged = true;
+            uint32_t *xv = reinterpret_cast<uint32_t *>(sm.data);
+            constexpr uint32_t cap = 4u * (uint32_t)SM::NB;
+            uint32_t nx = 0;
+            err = pfd_marks<PT>(c, sm, lane, reinterpret_cast<const uint32_t *>(rows), nrow, xs, xv, cap, nx);
+            ps.xv = xv;
+            ps.in_lds = nx <= cap;
+            if (err) nint = 0u;
+        }
+    }
+    if (err && lane == 0) latch(a.status, err);
+    if (!nint) return;
+    const bool vec = (reinterpret_cast<uintptr_t>(out) & 15u) == 0u;
+    const bool full = nint == (uint32_t)PT && vec;
+    const uint32_t tsh = c.lk - 2u;
+    if (c.h.delta) {
+        if (full) quads_lds<R, false, true, true, PATCH>(tile_recs(sm), rows, tsh, kq, nint, lane, 0u, out, vec, ps);
+        else quads_lds<R, false, false, true, PATCH>(tile_recs(sm), rows, tsh, kq, nint, lane, 0u, out, vec, ps);
+    } else {
+        if (full) quads_lds<R, false, true, false, PATCH>(tile_recs(sm), rows, tsh, kq, nint, lane, 0u, out, vec, ps);
+        else quads_lds<R, false, false, false, PATCH>(tile_recs(sm), rows, tsh, kq, nint, lane, 0u, out, vec, ps);
+    }
+}
+
+template <int PT, int SBC>
+__global__ __launch_bounds__(kThreads) void gc_pack_kernel(PackArgs a) {
+    __shared__ PackSmem<PT, SBC> smem[kWaves];
+    const uint32_t wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63u;
+    const uint32_t p = blockIdx.x * (uint32_t)kWaves + wave;
+    if (p >= a.npacks) return;
+    PackSmem<PT, SBC> &sm = smem[wave];
+    const uint32_t f0 = ((const gu32 *)a.first)[p], f1 = ((const gu32 *)a.first)[p + 1u];
+    const uint32_t np = min(f1 - f0, 64u);
+    // lane j: list j's descriptor
+    union {
+        u32x4 v[2];
+        PackDesc d;
+    } u;
+    u.v[0] = u32x4{0u, 0u, 0u, 0u};
+    u.v[1] = u32x4{0u, 0u, 0u, 0u};
+    if (lane < np) {
+        const gu32x4 *g = (const gu32x4 *)(a.descs + f0 + lane);
+        u.v[0] = g[0];
+        u.v[1] = g[1];
+    }
+    const PackDesc d = u.d;
+    const uint32_t ch = d.words >> 2;
+    const uint32_t inc = wave_incl_scan(ch);
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+    if (f1 - f0 > 64u || total > (uint32_t)SBC) {
+        if (lane == 0) latch(a.status, kErrPack);
+        return;
+    }
+    sm.soff[lane] = lane < np ? inc - ch : total;
+    wave_lds_sync();
+    // the pack's streams, chunk c to stage[c]: the list of a chunk by binary
+    // search over the offsets, its stream pointer from that list's lane;
+    // four 16-byte loads per lane in flight
+    const uint64_t sp = reinterpret_cast<uint64_t>(d.stream);
+    constexpr int RNDS = (SBC + 63) / 64;
+    constexpr int BATCH = RNDS < 4 ? RNDS : 4;
+#pragma unroll
+    for (int r0 = 0; r0 < RNDS; r0 += BATCH) {
+        if ((uint32_t)r0 * 64u >= total) break;
+        u32x4 t[BATCH];
+#pragma unroll
+        for (int b = 0; b < BATCH; b++) {
+            const uint32_t cidx = (uint32_t)(r0 + b) * 64u + lane;
+            uint32_t j = 0;
+#pragma unroll
+            for (uint32_t step = 32u; step; step >>= 1)
+                j = sm.soff[j + step] <= cidx ? j + step : j;
+            const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)sp, (int)j);
+            const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(sp >> 32), (int)j);
+            const gu32x4 *src = reinterpret_cast<const gu32x4 *>(((uint64_t)hi << 32) | lo);
+            if (cidx < total) t[b] = src[cidx - sm.soff[j]];
+        }
+#pragma unroll
+        for (int b = 0; b < BATCH; b++) {
+            const uint32_t cidx = (uint32_t)(r0 + b) * 64u + lane;
+            if (cidx < total) sm.stage[cidx] = t[b];
+        }
+    }
+    wave_lds_sync();
+    const uint32_t *stage = reinterpret_cast<const uint32_t *>(sm.stage);
+    for (uint32_t j = 0; j < np; j++) {
+        const uint32_t so = uniform(sm.soff[j]);
+        const uint64_t spj = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(sp >> 32), (int)j) << 32) |
+                             (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sp, (int)j);
+        const uint64_t op = reinterpret_cast<uint64_t>(d.out);
+        const uint64_t opj = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(op >> 32), (int)j) << 32) |
+                             (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)op, (int)j);
+        const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)d.n, (int)j);
+        const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)d.w0, (int)j);
+        const uint32_t cd = (uint32_t)__builtin_amdgcn_readlane((int)d.cd, (int)j);
+        const uint32_t words = (uint32_t)__builtin_amdgcn_readlane((int)d.words, (int)j);
+        const uint32_t *S = reinterpret_cast<const uint32_t *>(spj);
+        uint32_t *out = reinterpret_cast<uint32_t *>(opj);
+        const uint32_t *sw = stage + 4u * so;
+        const uint32_t C = cd & 0xFFFFu, D = cd >> 16;
+        switch (codec_class_dev(w0)) {
+        case kClsSim: pack_list<PT, kClsSim, SBC>(a, sm.u.sim, sw, S, out, n, w0, C, D, words, lane); break;
+        case kClsGscU: pack_list<PT, kClsGscU, SBC>(a, sm.u.gscu, sw, S, out, n, w0, C, D, words, lane); break;
+        case kClsGscB: pack_list<PT, kClsGscB, SBC>(a, sm.u.gscb, sw, S, out, n, w0, C, D, words, lane); break;
+        case kClsAfor: pack_list<PT, kClsAfor, SBC>(a, sm.u.afor, sw, S, out, n, w0, C, D, words, lane); break;
+        case kClsPfd: pack_list<PT, kClsPfd, SBC>(a, sm.u.pfd, sw, S, out, n, w0, C, D, words, lane); break;
+        default:
+            if (lane == 0) latch(a.status, kErrHeader);
+            break;
+        }
+        // the next list's prologue rewrites what this one's unpack read
+        wave_lds_sync();
+    }
+}
+
+// ===========================================================================
 // Carry scan: the tile sums of one delta list become exclusive carries, in
 // place, 1024 tiles per round (the last tile's sum is never read: the sum
 // pass skips it).
@@ -1833,6 +2069,17 @@ static const void *decode_fn(int tile, int cls) {
     case 4096: return wave_fn<4096, MODE>(cls);
     default: return nullptr;
     }
+}
+
+// Launches the pack kernel of tile size pt (1024 or 2048) over a.npacks
+// packs.
+int launch_pack(int pt, const PackArgs &a, hipStream_t s) {
+    if (!a.npacks) return 0;
+    const dim3 grid((a.npacks + kWaves - 1) / kWaves);
+    if (pt == 1024) hipLaunchKernelGGL((gc_pack_kernel<1024, kPackChunks>), grid, dim3(kThreads), 0, s, a);
+    else if (pt == 2048) hipLaunchKernelGGL((gc_pack_kernel<2048, kPackChunks>), grid, dim3(kThreads), 0, s, a);
+    else return -2;
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 // Launches a pass over a.count tiles: mode 0 decode, 1 tile sums, 2 decode

@@ -11,6 +11,14 @@ constexpr int kChunkWords = 256;       // control words per locate work item (on
 constexpr int kChunkWordsSmall = 128;  // the same for a single list decoded alone (2 per lane)
 constexpr int kClasses = 5;                 // decode kernel classes (codec families)
 
+// Tables of a list decoded alone, for lists of up to max_ints integers: a
+// tile holds at least 1024 integers (one spare entry follows the last), and
+// a locate chunk 128 control words, of which a list has at most one per
+// tuple of four integers (a unary Group-Scheme code is at most 32 bits) plus
+// padding.
+constexpr uint64_t single_tiles_cap(uint64_t max_ints) { return (max_ints + 1023u) / 1024u + 1u; }
+constexpr uint64_t single_chunks_cap(uint64_t max_ints) { return ((max_ints + 3u) / 4u + 4u + 127u) / 128u + 1u; }
+
 // One list of a launch.  For a batch these live in a device table; for a
 // single list the runtime passes one by value.  The header words come from
 // the host's copy of the header; kernels check the stream against them.
@@ -101,6 +109,30 @@ struct DecodeArgs {
     Status *status;
 };
 
+constexpr int kPackChunks = 256;   // staging buffer of a pack: 4 KB of whole streams per wave
+
+// A list the pack kernel decodes: a list of one tile whose whole stream fits
+// a pack's staging buffer.  The lists of a pack are consecutive entries.
+struct PackDesc {
+    const uint32_t *stream;   // 16-byte aligned
+    uint32_t *out;
+    uint32_t n;
+    uint32_t w0;              // header word 0 (host copy)
+    uint32_t cd;              // header words 2 and 3 (host copy): C | D << 16, both < 2^16
+    uint32_t words;           // stream words, a multiple of 4
+};
+
+// Pack kernel launch: a wave per pack; pack p holds the descriptors
+// [first[p], first[p + 1]), at most 64 lists whose streams fit the
+// kernel's staging buffer together.
+struct PackArgs {
+    const PackDesc *descs;
+    const uint32_t *first;    // npacks + 1 entries
+    uint32_t npacks;
+    uint32_t pad;
+    Status *status;
+};
+
 // Carry scan: one workgroup per delta list of more than one tile.
 struct CarryArgs {
     const ListDesc *lists;      // batch table, or nullptr for `single`
@@ -124,6 +156,7 @@ enum : uint32_t {
     kErrCount = 9,
     kErrBitmap = 11,
     kErrTimeout = 12,   // a carry look-back waited too long for an earlier tile
+    kErrPack = 13,      // a pack's streams do not fit its staging buffer
 };
 
 }  // namespace gcdev

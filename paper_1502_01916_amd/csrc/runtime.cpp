@@ -27,6 +27,7 @@ int codec_class(uint32_t w0);
 int launch_locate(const LocateArgs &a, int chunk_words, hipStream_t s);
 int launch_carry_scan(const CarryArgs &a, hipStream_t s);
 int launch_decode(int tile, int cls, int mode, const DecodeArgs &a, hipStream_t s);
+int launch_pack(int pt, const PackArgs &a, hipStream_t s);
 }  // namespace gcdev
 
 using namespace gcdev;
@@ -51,6 +52,10 @@ constexpr uint32_t kDefaultLbMax = kLookbackHybrid;
 // than the tile-sum pass and carry scan, equal at 2^23, slower at 2^24).
 constexpr uint32_t kSingleLbMax = 2048u;
 constexpr int kWaveTiles[3] = {1024, 2048, 4096};
+// Longest list a context decodes alone (gc_decode) and encodes as a block
+// container, unless gc_ctx_create_opts says otherwise.
+constexpr uint64_t kDefaultMaxListInts = 1ull << 24;
+
 constexpr int kClsPfd = 4;
 
 bool valid_wave_tile(uint32_t t) { return t == 1024 || t == 2048 || t == 4096; }
@@ -89,9 +94,18 @@ gc_status dev_alloc(T **p, size_t count) {
         *p = nullptr;
         return GC_ENOMEM;
     }
-    if (hipMemset(*p, 0, count * sizeof(T)) != hipSuccess) return GC_EDEVICE;
+    if (hipMemset(*p, 0, count * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(*p);
+        *p = nullptr;
+        return GC_EDEVICE;
+    }
     return GC_OK;
 }
+
+// First locate epoch of codec class c (the device advances it by kClasses
+// per run, so the epochs of different classes never coincide).
+uint32_t first_epoch(int c) { return (uint32_t)c + 1u; }
 
 template <typename T>
 void dev_free(T *&p) {
@@ -113,36 +127,49 @@ struct Scratch {
     gc_status init_state() {
         gc_status rc = dev_alloc(&state, kClasses);
         if (rc) return rc;
-        std::vector<RunState> h(kClasses, RunState{1u, {0u, 0u, 0u}});
+        std::vector<RunState> h(kClasses);
+        for (int c = 0; c < kClasses; c++) h[c] = RunState{first_epoch(c), {0u, 0u, 0u}};
         HIP_OK(hipMemcpy(state, h.data(), h.size() * sizeof(RunState), hipMemcpyHostToDevice));
         return GC_OK;
     }
+    // Grows the tables (plans and contexts call this only when they are
+    // created, never on a decode).  On any failure every table is freed and
+    // both capacities drop to zero, so a later call reallocates them all.
     gc_status reserve(size_t ntiles, size_t nchunks) {
+        gc_status rc = GC_OK;
         if (ntiles > tiles_cap) {
-            HIP_OK(hipDeviceSynchronize());
+            if (hipDeviceSynchronize() != hipSuccess) rc = GC_EDEVICE;
             dev_free(tiles);
             dev_free(carry);
             dev_free(flags);
-            const size_t cap = std::max(ntiles, tiles_cap * 2);
-            gc_status rc = dev_alloc(&tiles, cap);
+            tiles_cap = 0;
+            const size_t cap = ntiles;
+            if (!rc) rc = dev_alloc(&tiles, cap);
             if (!rc) rc = dev_alloc(&carry, cap);
+            // no flag may carry an epoch before it is written: zeroed once here
             if (!rc) rc = dev_alloc(&flags, cap);
-            if (rc) return rc;
-            // no flag may carry an epoch before it is written: zero them once
-            HIP_OK(hipMemset(flags, 0, cap * sizeof(*flags)));
-            tiles_cap = cap;
+            if (!rc) tiles_cap = cap;
         }
-        if (nchunks > chunks_cap) {
-            HIP_OK(hipDeviceSynchronize());
+        if (!rc && nchunks > chunks_cap) {
+            if (hipDeviceSynchronize() != hipSuccess) rc = GC_EDEVICE;
             dev_free(agg);
             dev_free(pre);
-            const size_t cap = std::max(nchunks, chunks_cap * 2);
-            gc_status rc = dev_alloc(&agg, cap);
+            chunks_cap = 0;
+            const size_t cap = nchunks;
+            if (!rc) rc = dev_alloc(&agg, cap);
             if (!rc) rc = dev_alloc(&pre, cap);
-            if (rc) return rc;
-            chunks_cap = cap;
+            if (!rc) chunks_cap = cap;
         }
-        return GC_OK;
+        if (rc) {
+            (void)hipGetLastError();
+            dev_free(tiles);
+            dev_free(carry);
+            dev_free(flags);
+            dev_free(agg);
+            dev_free(pre);
+            tiles_cap = chunks_cap = 0;
+        }
+        return rc;
     }
     void release() {
         dev_free(state);
@@ -164,9 +191,8 @@ struct BlockScratch {
     float *feat = nullptr;   // features of every block (selector input)
     uint8_t *cls = nullptr;  // class of every block
     size_t cap = 0;
+    // Called once, when the context is created; on failure nothing is kept.
     gc_status reserve(size_t nblocks) {
-        if (nblocks <= cap && result) return GC_OK;
-        HIP_OK(hipDeviceSynchronize());
         release();
         const size_t c = std::max(nblocks, (size_t)1024);
         gc_status rc = dev_alloc(&words, c);
@@ -175,7 +201,8 @@ struct BlockScratch {
         if (!rc) rc = dev_alloc(&result, 2);
         if (!rc) rc = dev_alloc(&feat, c * gcblk::kFeatures);
         if (!rc) rc = dev_alloc(&cls, c);
-        if (!rc) cap = c;
+        if (rc) release();
+        else cap = c;
         return rc;
     }
     void release() {
@@ -193,8 +220,10 @@ struct gc_ctx {
     int device = 0;
     int num_cus = 0;
     Status *status = nullptr;
-    Scratch single;
-    BlockScratch blk;
+    Scratch single;             // gc_decode's tables, sized for max_list_ints at creation
+    BlockScratch blk;           // the block encoder's, likewise
+    uint64_t max_list_ints = 0;
+    std::string arch;           // the device's architecture name (autotune cache keys)
     int tile_w = kDefaultWaveTile, tile_p = kDefaultPfdTile;
     std::mutex mu;
 };
@@ -211,6 +240,17 @@ struct ClassRange {
     uint32_t sum = 0;       // leading tiles that need a tile sum
     uint32_t scan_lo = 0;   // first entry of the class in the scan list
     uint32_t scans = 0;     // lists to scan
+};
+
+// The packs of one pack kernel (tile size kPackTiles[i]): descriptors in
+// pack order, the list of each, and every pack's first descriptor.
+struct PackSet {
+    std::vector<PackDesc> h;       // pointers filled at upload
+    std::vector<uint32_t> list;    // descriptor -> list
+    std::vector<uint32_t> first;   // packs + 1 entries
+    PackDesc *d = nullptr;
+    uint32_t *d_first = nullptr;
+    uint32_t packs() const { return first.empty() ? 0u : (uint32_t)first.size() - 1u; }
 };
 
 struct gc_plan {
@@ -239,9 +279,23 @@ struct gc_plan {
     uint32_t lb_stall = 0;                     // tests only: see GC_TEST_LOOKBACK_STALL
     uint32_t slots = 0;
     uint64_t runs = 0;
+    // lists of at most pack_max integers (one tile) whose streams fit a
+    // pack's staging buffer are decoded by the pack kernels instead of the
+    // class passes; 0: none
+    uint32_t pack_max = 0;
+    bool pack_forced = false;                  // pack_max set by the plan options
+    std::vector<uint8_t> packed;               // per list
+    PackSet pk[2];                             // pack kernels of 1024- and 2048-integer tiles
+    uint32_t total_chunks = 0;                 // locate chunks of every list (batch items first)
 };
 
 namespace {
+
+constexpr int kPackTiles[2] = {1024, 2048};
+// Default pack_max: every list of one 2048-integer tile.
+constexpr uint32_t kDefaultPackMax = 2048u;
+constexpr uint32_t kPackOff = 0x80000000u;
+constexpr uint32_t kPackMaxLists = 64u;
 
 LocateArgs make_locate_args(const ListDesc *lists, const uint32_t *item_list, const uint32_t *scan_list,
                             const ListDesc &single, uint32_t total, uint32_t total_scan, int cls, Scratch &sc,
@@ -341,6 +395,20 @@ gc_status launch_one(const ListDesc &L, int cls, Scratch &sc, Status *st, hipStr
     return GC_OK;
 }
 
+// The pack kernel (index into kPackTiles) that decodes list L, or -1 when
+// it takes the class passes: a list of 1 .. pack_max integers in one tile
+// of its pack kernel (2048 integers for the 64-way layout, whose blocks are
+// that long; 1024 otherwise when it fits) whose whole stream fits the
+// staging buffer.
+int pack_kind(const ListDesc &L, uint32_t pack_max) {
+    if (L.n == 0 || L.n > pack_max || L.n > (uint32_t)kPackTiles[1]) return -1;
+    if (L.stream_words > 4ull * (uint64_t)kPackChunks || (L.stream_words & 3u)) return -1;
+    HeaderFields h;
+    if (!header_fields(L.w0, h)) return -1;
+    const uint32_t need = std::max<uint32_t>(L.n, 32u << h.lk);
+    return need <= (uint32_t)kPackTiles[0] ? 0 : need <= (uint32_t)kPackTiles[1] ? 1 : -1;
+}
+
 // Builds the tile tables of a plan for its tile sizes.
 void build_tables(gc_plan *p) {
     for (int c = 0; c < kClasses; c++) p->tile[c] = std::max(p->tile[c], min_class_tile(p, c));
@@ -348,6 +416,13 @@ void build_tables(gc_plan *p) {
     p->item_s.clear();
     p->tile_list.clear();
     p->scan_list.clear();
+    p->packed.assign(p->nlists, 0);
+    for (PackSet &ps : p->pk) {
+        ps.h.clear();
+        ps.list.clear();
+        ps.first.clear();
+    }
+    uint32_t pack_words[2] = {0, 0};
     for (size_t i = 0; i < p->nlists; i++) {
         ListDesc &L = p->h_lists[i];
         L.tile_ints = (uint32_t)p->tile[p->cls[i]];
@@ -359,9 +434,40 @@ void build_tables(gc_plan *p) {
             L.nchunks = list_chunks(h, L.n, L.C, L.D, kChunkWords);
         }
     }
+    // Packs: consecutive packed lists, class by class, while they fit the
+    // staging buffer and number at most 64.
+    for (int c = 0; c < kClasses; c++) {
+        for (size_t i = 0; i < p->nlists; i++) {
+            if (p->cls[i] != c) continue;
+            const ListDesc &L = p->h_lists[i];
+            const int kind = pack_kind(L, p->pack_max);
+            if (kind < 0) continue;
+            PackSet &ps = p->pk[kind];
+            const uint32_t w = (uint32_t)L.stream_words;
+            if (ps.first.empty() || (uint32_t)ps.h.size() - ps.first.back() >= kPackMaxLists ||
+                pack_words[kind] + w > 4u * (uint32_t)kPackChunks) {
+                ps.first.push_back((uint32_t)ps.h.size());
+                pack_words[kind] = 0;
+            }
+            PackDesc d;
+            std::memset(&d, 0, sizeof(d));
+            d.n = L.n;
+            d.w0 = L.w0;
+            d.cd = L.C | (L.D << 16);
+            d.words = w;
+            ps.h.push_back(d);
+            ps.list.push_back((uint32_t)i);
+            pack_words[kind] += w;
+            p->packed[i] = 1;
+        }
+    }
+    for (PackSet &ps : p->pk)
+        if (!ps.first.empty()) ps.first.push_back((uint32_t)ps.h.size());
     // Locate items, tiles and carry scans are numbered class by class, so
     // each class's kernels cover one range of each table.  Within a class
-    // the delta lists of more than one tile come first.
+    // the delta lists of more than one tile come first.  Packed lists come
+    // after every class: the batch does not run them through these tables,
+    // but one launch sequence per list (gc_decode_each) does.
     uint32_t cb = 0, tb = 0;
     for (int c = 0; c < kClasses; c++) {
         ClassRange &r = p->cr[c];
@@ -370,7 +476,7 @@ void build_tables(gc_plan *p) {
         r.lsc_lo = (uint32_t)p->item_s.size();
         for (size_t i = 0; i < p->nlists; i++) {
             ListDesc &L = p->h_lists[i];
-            if (p->cls[i] != c || !L.nchunks) continue;
+            if (p->cls[i] != c || !L.nchunks || p->packed[i]) continue;
             L.chunk_base = cb;
             for (uint32_t k = 0; k < L.nchunks; k++) p->item_a.push_back((uint32_t)i);
             p->item_s.push_back((uint32_t)i);
@@ -383,7 +489,7 @@ void build_tables(gc_plan *p) {
         for (int pass = 0; pass < 2; pass++) {
             for (size_t i = 0; i < p->nlists; i++) {
                 ListDesc &L = p->h_lists[i];
-                if (p->cls[i] != c || L.ntiles == 0) continue;
+                if (p->cls[i] != c || L.ntiles == 0 || p->packed[i]) continue;
                 const bool summed = L.ntiles > 1 && is_delta(L.w0) && L.ntiles > p->lb_max;
                 if (summed != (pass == 0)) continue;
                 L.tile_base = tb;
@@ -400,8 +506,18 @@ void build_tables(gc_plan *p) {
     }
     p->total_a = (uint32_t)p->item_a.size();
     p->total_s = (uint32_t)p->item_s.size();
-    p->total_t = tb;
     p->total_scan = (uint32_t)p->scan_list.size();
+    for (size_t i = 0; i < p->nlists; i++) {
+        ListDesc &L = p->h_lists[i];
+        if (!p->packed[i]) continue;
+        L.chunk_base = cb;
+        cb += L.nchunks;
+        L.tile_base = tb;
+        for (uint32_t m = 0; m < L.ntiles; m++) p->tile_list.push_back((uint32_t)i);
+        tb += L.ntiles;
+    }
+    p->total_chunks = cb;
+    p->total_t = tb;
 }
 
 void plan_free_graphs(gc_plan *p) {
@@ -415,6 +531,10 @@ void plan_free_device(gc_plan *p) {
     dev_free(p->d_item_a);
     dev_free(p->d_item_s);
     dev_free(p->d_scan_list);
+    for (PackSet &ps : p->pk) {
+        dev_free(ps.d);
+        dev_free(ps.d_first);
+    }
     p->sc.release();
 }
 
@@ -425,6 +545,14 @@ gc_status plan_upload(gc_plan *p, const uint32_t *d_streams, uint32_t *d_out) {
         t[i].out = d_out + p->out_off[i];
     }
     HIP_OK(hipMemcpy(p->d_lists, t.data(), t.size() * sizeof(ListDesc), hipMemcpyHostToDevice));
+    for (PackSet &ps : p->pk) {
+        if (ps.h.empty()) continue;
+        for (size_t j = 0; j < ps.h.size(); j++) {
+            ps.h[j].stream = d_streams + p->stream_off[ps.list[j]];
+            ps.h[j].out = d_out + p->out_off[ps.list[j]];
+        }
+        HIP_OK(hipMemcpy(ps.d, ps.h.data(), ps.h.size() * sizeof(PackDesc), hipMemcpyHostToDevice));
+    }
     p->bound_streams = d_streams;
     p->bound_out = d_out;
     return GC_OK;
@@ -450,7 +578,11 @@ gc_status plan_materialize(gc_plan *p) {
     if (!rc) rc = upload_vec(&p->d_item_s, p->item_s);
 
     if (!rc) rc = upload_vec(&p->d_scan_list, p->scan_list);
-    if (!rc) rc = p->sc.reserve(p->total_t + 1, p->total_a);
+    for (PackSet &ps : p->pk) {
+        if (!rc) rc = upload_vec(&ps.d, ps.h);
+        if (!rc) rc = upload_vec(&ps.d_first, ps.first);
+    }
+    if (!rc) rc = p->sc.reserve(p->total_t + 1, p->total_chunks);
     if (!rc && p->total_t) {
         // every tile names its list; the locate pass rewrites the entries of
         // tiles m >= 1 on each run, tile 0 of a list starts at zero
@@ -498,13 +630,15 @@ gc_status launch_class_locate(gc_plan *p, int c, hipStream_t s) {
 
 // Launches the tile sums and carry scan (delta lists of more than one tile)
 // and the decode pass of codec class c on stream s; `mid`, if given, is
-// recorded between the two.
-gc_status launch_class_work(gc_plan *p, int c, hipStream_t s, hipEvent_t mid = nullptr) {
+// recorded between the two.  per_class: the tile starts were written by the
+// class's own locate kernels (tagged with its epoch), not by the one locate
+// pass over every class (tagged with class 0's).
+gc_status launch_class_work(gc_plan *p, int c, hipStream_t s, bool per_class, hipEvent_t mid = nullptr) {
     const ClassRange &r = p->cr[c];
     ListDesc none;
     std::memset(&none, 0, sizeof(none));
     const int tile = p->tile[c];
-    const int epoch_cls = p->serial ? 0 : c;   // whose locate epoch tags the tile starts
+    const int epoch_cls = per_class ? c : 0;   // whose locate epoch tags the tile starts
     if (r.sum) {
         DecodeArgs d = make_decode_args(p->d_lists, none, r.lo, r.sum, epoch_cls, p->sc, p->ctx->status);
         if (launch_decode(tile, c, 1, d, s)) return GC_EDEVICE;
@@ -527,12 +661,36 @@ gc_status launch_class_work(gc_plan *p, int c, hipStream_t s, hipEvent_t mid = n
 // of class c's locate; with `tev` (timing), class c records tev[5c .. 5c+4]:
 // before and after its locate, before its tile sums, before and after its
 // decode pass.
+// Launches the pack kernels on stream s.
+gc_status launch_packs(gc_plan *p, hipStream_t s) {
+    for (int k = 0; k < 2; k++) {
+        const PackSet &ps = p->pk[k];
+        if (!ps.packs()) continue;
+        PackArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.descs = ps.d;
+        a.first = ps.d_first;
+        a.npacks = ps.packs();
+        a.status = p->ctx->status;
+        if (launch_pack(kPackTiles[k], a, s)) return GC_EDEVICE;
+    }
+    return GC_OK;
+}
+
+// The two events around the pack kernels, after the classes' five each
+// (indices into the events plan_launch records).
+constexpr int kTevPack = 5 * kClasses;
+
 gc_status plan_launch(gc_plan *p, hipStream_t s, hipStream_t aux = nullptr, hipEvent_t start = nullptr,
                       hipEvent_t *sync = nullptr, hipEvent_t *tev = nullptr) {
     if (aux) {
         HIP_OK(hipEventRecord(start, s));
         HIP_OK(hipStreamWaitEvent(aux, start, 0));
     }
+    // the packed lists depend on nothing the other passes compute
+    if (tev) HIP_OK(hipEventRecord(tev[kTevPack], s));
+    if (gc_status rc = launch_packs(p, s)) return rc;
+    if (tev) HIP_OK(hipEventRecord(tev[kTevPack + 1], s));
     hipStream_t ls = aux ? aux : s;
     if (!aux) {
         const int c0 = first_class(p);
@@ -550,7 +708,7 @@ gc_status plan_launch(gc_plan *p, hipStream_t s, hipStream_t aux = nullptr, hipE
         if (!p->cr[c].count) continue;
         if (aux) HIP_OK(hipStreamWaitEvent(s, tev ? tev[5 * c + 1] : sync[c], 0));
         if (tev) HIP_OK(hipEventRecord(tev[5 * c + 2], s));
-        if (gc_status rc = launch_class_work(p, c, s, tev ? tev[5 * c + 3] : nullptr)) return rc;
+        if (gc_status rc = launch_class_work(p, c, s, aux != nullptr, tev ? tev[5 * c + 3] : nullptr)) return rc;
         if (tev) HIP_OK(hipEventRecord(tev[5 * c + 4], s));
     }
     return GC_OK;
@@ -590,9 +748,9 @@ gc_status plan_capture(gc_plan *p) {
     return capture_one(p, &p->graph, &p->exec);
 }
 
-// Events of one timing slot: run start and end on the launch stream, then
-// five per class (see plan_launch).
-constexpr int kEvPerSlot = 2 + 5 * kClasses;
+// Events of one timing slot: run start and end on the launch stream, five
+// per class and two around the pack kernels (see plan_launch).
+constexpr int kEvPerSlot = 4 + 5 * kClasses;
 
 gc_status plan_run(gc_plan *p, hipStream_t s) {
     if (p->slots) {
@@ -616,7 +774,7 @@ std::string cache_path() {
     return e ? std::string(e) : std::string();
 }
 
-bool cache_lookup(const std::string &key, int *tiles) {
+bool cache_lookup(const std::string &key, int *tiles, uint32_t *pack_max) {
     const std::string path = cache_path();
     if (path.empty()) return false;
     std::ifstream f(path);
@@ -628,16 +786,20 @@ bool cache_lookup(const std::string &key, int *tiles) {
     const size_t at = s.find(pat);
     if (at == std::string::npos) return false;
     int t[kClasses];
+    unsigned pm = 0;
     static_assert(kClasses == 5, "five classes in the cache format");
-    if (std::sscanf(s.c_str() + at + pat.size(), "%d, %d, %d, %d, %d", &t[0], &t[1], &t[2], &t[3], &t[4]) != 5)
+    if (std::sscanf(s.c_str() + at + pat.size(), "%d, %d, %d, %d, %d, %u", &t[0], &t[1], &t[2], &t[3], &t[4],
+                    &pm) != 6)
         return false;
     for (int c = 0; c < kClasses; c++)   // an entry that fails validation falls back to the defaults
         if (!valid_wave_tile((uint32_t)t[c])) return false;
+    if (pm > (uint32_t)kPackTiles[1]) return false;
     for (int c = 0; c < kClasses; c++) tiles[c] = t[c];
+    *pack_max = pm;
     return true;
 }
 
-void cache_store(const std::string &key, const int *tiles) {
+void cache_store(const std::string &key, const int *tiles, uint32_t pack_max) {
     const std::string path = cache_path();
     if (path.empty()) return;
     std::string s;
@@ -660,8 +822,9 @@ void cache_store(const std::string &key, const int *tiles) {
         if (k != key) entries.push_back("\"" + k + "\": " + s.substr(lb, rb - lb + 1));
         pos = rb + 1;
     }
-    char buf[96];
-    std::snprintf(buf, sizeof(buf), "[%d, %d, %d, %d, %d]", tiles[0], tiles[1], tiles[2], tiles[3], tiles[4]);
+    char buf[128];
+    std::snprintf(buf, sizeof(buf), "[%d, %d, %d, %d, %d, %u]", tiles[0], tiles[1], tiles[2], tiles[3], tiles[4],
+                  pack_max);
     entries.push_back("\"" + key + "\": " + buf);
     std::ofstream f(path);
     f << "{\n";
@@ -684,23 +847,34 @@ std::string plan_key(const gc_plan *p) {
     const uint64_t mean = p->nlists ? total / p->nlists : 0;
     int lm = 0;
     while ((1ull << lm) < mean) lm++;
-    std::string key = "gfx950:k" + std::to_string(1 << lk) + ":n2^" + std::to_string(lg) + ":mean2^" +
-                      std::to_string(lm) + ":c" + std::to_string(p->lb_max) + ":mix";
+    // short lists decide the pack kernels' share: the fraction (in eighths)
+    // of lists of one 2048-integer tile
+    uint64_t short_lists = 0;
+    for (size_t i = 0; i < p->nlists; i++) short_lists += p->h_lists[i].n <= (uint32_t)kPackTiles[1];
+    std::string key = p->ctx->arch + ":k" + std::to_string(1 << lk) + ":n2^" + std::to_string(lg) + ":mean2^" +
+                      std::to_string(lm) + ":c" + std::to_string(p->lb_max) + ":s" +
+                      std::to_string(p->nlists ? short_lists * 8 / p->nlists : 0) +
+                      (p->pack_forced ? ":p" + std::to_string(p->pack_max) : std::string()) + ":mix";
     for (int c = 0; c < kClasses; c++)
         key += (c ? "-" : "") + std::to_string(total ? per_cls[c] * 8 / total : 0);
     return key;
 }
 
-// Times the candidate tile sizes and keeps, for every codec class, the one
-// whose passes (tile sums, carry scan, decode) took least: one materialised
-// plan per candidate, each class timed by HIP events around its own passes
-// (a class's passes do not depend on the tile sizes of the others).
+// Times the candidates and keeps the fastest: first the packed-list
+// threshold (no packing, lists of up to 1024 or 2048 integers; unless the
+// plan fixes it), by the whole run at the default tile sizes; then, for
+// every codec class, the tile size whose passes (tile sums, carry scan,
+// decode) took least: one materialised plan per candidate, each class timed
+// by HIP events around its own passes (a class's passes do not depend on
+// the tile sizes of the others).
 gc_status autotune(gc_plan *p, const uint32_t *d_streams, uint32_t *d_out) {
     const std::string key = plan_key(p);
     int best_t[kClasses];
     for (int c = 0; c < kClasses; c++) best_t[c] = p->tile[c];
-    if (cache_lookup(key, best_t)) {
+    uint32_t best_pm = p->pack_max;
+    if (cache_lookup(key, best_t, &best_pm)) {
         for (int c = 0; c < kClasses; c++) p->tile[c] = best_t[c];
+        p->pack_max = best_pm;
         return GC_OK;
     }
     bool present[kClasses] = {};
@@ -709,6 +883,31 @@ gc_status autotune(gc_plan *p, const uint32_t *d_streams, uint32_t *d_out) {
     gc_status rc = GC_OK;
     for (hipEvent_t &e : ev)
         if (hipEventCreate(&e) != hipSuccess) rc = GC_EDEVICE;
+    if (!p->pack_forced) {
+        const uint32_t cand[3] = {0u, (uint32_t)kPackTiles[0], (uint32_t)kPackTiles[1]};
+        float best_ms = 1e30f;
+        for (int i = 0; i < 3 && !rc; i++) {
+            p->pack_max = cand[i];
+            rc = plan_materialize(p);
+            if (!rc) rc = plan_upload(p, d_streams, d_out);
+            for (int w = 0; w < 2 && !rc; w++) rc = plan_launch(p, nullptr);
+            float acc = 0;
+            for (int r = 0; r < 5 && !rc; r++) {
+                HIP_OK(hipEventRecord(ev[0], nullptr));
+                rc = plan_launch(p, nullptr);
+                HIP_OK(hipEventRecord(ev[1], nullptr));
+                HIP_OK(hipEventSynchronize(ev[1]));
+                float ms = 0;
+                HIP_OK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+                acc += ms;
+            }
+            if (!rc && acc < best_ms) {
+                best_ms = acc;
+                best_pm = cand[i];
+            }
+        }
+        p->pack_max = best_pm;
+    }
     float best[kClasses];
     for (int c = 0; c < kClasses; c++) best[c] = 1e30f;
     for (int i = 0; i < 3 && !rc; i++) {
@@ -741,7 +940,7 @@ gc_status autotune(gc_plan *p, const uint32_t *d_streams, uint32_t *d_out) {
         if (e) (void)hipEventDestroy(e);
     if (rc) return rc;
     for (int c = 0; c < kClasses; c++) p->tile[c] = best_t[c];
-    cache_store(key, best_t);
+    cache_store(key, best_t, p->pack_max);
     return GC_OK;
 }
 
@@ -756,15 +955,55 @@ gc_status validate_header(const uint32_t *hd, uint64_t n, uint64_t stream_words)
     return GC_OK;
 }
 
+// The descriptor of a list decoded alone, from the host copy of its header;
+// *empty when it has no integers (nothing to launch).
+gc_status single_list(const gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words, const uint32_t *h_header,
+                      uint32_t *d_out, ListDesc &L, int &cls, bool &empty) {
+    empty = false;
+    if (!d_stream || !h_header || stream_words < 4) return GC_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(d_stream) & 15u) != 0u) return GC_EINVAL;
+    const uint32_t n = h_header[1];
+    if (gc_status rc = validate_header(h_header, n, stream_words)) return rc;
+    if (n == 0) {
+        empty = true;
+        return GC_OK;
+    }
+    if (!d_out) return GC_EINVAL;
+    cls = codec_class(h_header[0]);
+    HeaderFields h;
+    header_fields(h_header[0], h);
+    const int tile = std::max(cls == kClsPfd ? ctx->tile_p : ctx->tile_w, 32 << h.lk);
+    std::memset(&L, 0, sizeof(L));
+    L.stream = d_stream;
+    L.out = d_out;
+    L.stream_words = stream_words;
+    L.n = n;
+    L.ntiles = (uint32_t)((n + (size_t)tile - 1) / (size_t)tile);
+    L.nchunks = L.ntiles > 1 ? list_chunks(h, n, h_header[2], h_header[3], kChunkWordsSmall) : 0u;
+    L.tile_ints = (uint32_t)tile;
+    L.w0 = h_header[0];
+    L.C = h_header[2];
+    L.D = h_header[3];
+    return GC_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char *gc_version(void) { return "libgc 0.3 (gfx950)"; }
 
-gc_status gc_ctx_create(int device, gc_ctx **ctx) {
+gc_status gc_ctx_create(int device, gc_ctx **ctx) { return gc_ctx_create_opts(device, nullptr, ctx); }
+
+gc_status gc_ctx_create_opts(int device, const gc_ctx_opts *opts, gc_ctx **ctx) {
     if (!ctx) return GC_EINVAL;
     *ctx = nullptr;
+    uint64_t max_ints = kDefaultMaxListInts;
+    if (opts) {
+        if (opts->reserved[0] || opts->reserved[1]) return GC_EINVAL;
+        if (opts->max_list_ints) max_ints = opts->max_list_ints;
+    }
+    if (max_ints > 0xFFFFFFFFull) return GC_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
         (void)hipGetLastError();
@@ -778,11 +1017,18 @@ gc_status gc_ctx_create(int device, gc_ctx **ctx) {
     if (!c) return GC_ENOMEM;
     c->device = device;
     c->num_cus = prop.multiProcessorCount;
+    c->max_list_ints = max_ints;
+    c->arch = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':'));
     gc_status rc = dev_alloc(&c->status, 1);
     if (!rc) rc = c->single.init_state();
+    if (!rc) rc = c->single.reserve(single_tiles_cap(max_ints), single_chunks_cap(max_ints));
+    if (!rc) rc = c->blk.reserve((size_t)((max_ints + gcblk::kBlockInts - 1) / gcblk::kBlockInts));
+    if (!rc && hipDeviceSynchronize() != hipSuccess) rc = GC_EDEVICE;
     if (rc) {
+        (void)hipGetLastError();
         dev_free(c->status);
         c->single.release();
+        c->blk.release();
         delete c;
         return rc;
     }
@@ -802,31 +1048,19 @@ gc_status gc_ctx_destroy(gc_ctx *ctx) {
 }
 
 gc_status gc_decode(gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words, const uint32_t *h_header,
-                    uint32_t *d_out, void *hip_stream) {
-    if (!ctx || !d_stream || !h_header || stream_words < 4) return GC_EINVAL;
-    if ((reinterpret_cast<uintptr_t>(d_stream) & 15u) != 0u) return GC_EINVAL;
-    const uint32_t n = h_header[1];
-    if (gc_status rc = validate_header(h_header, n, stream_words)) return rc;
-    if (n == 0) return GC_OK;
-    if (!d_out) return GC_EINVAL;
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    const int cls = codec_class(h_header[0]);
-    HeaderFields h;
-    header_fields(h_header[0], h);
-    const int tile = std::max(cls == kClsPfd ? ctx->tile_p : ctx->tile_w, 32 << h.lk);
+                               uint32_t *d_out, void *hip_stream) {
+    if (!ctx) return GC_EINVAL;
     ListDesc L;
-    std::memset(&L, 0, sizeof(L));
-    L.stream = d_stream;
-    L.out = d_out;
-    L.stream_words = stream_words;
-    L.n = n;
-    L.ntiles = (uint32_t)((n + (size_t)tile - 1) / (size_t)tile);
-    L.nchunks = L.ntiles > 1 ? list_chunks(h, n, h_header[2], h_header[3], kChunkWordsSmall) : 0u;
-    L.tile_ints = (uint32_t)tile;
-    L.w0 = h_header[0];
-    L.C = h_header[2];
-    L.D = h_header[3];
-    if (gc_status rc = ctx->single.reserve(L.ntiles + 1, L.nchunks)) return rc;
+    int cls = 0;
+    bool empty = false;
+    if (gc_status rc = single_list(ctx, d_stream, stream_words, h_header, d_out, L, cls, empty)) return rc;
+    if (empty) return GC_OK;
+    // the tables were sized when the context was created: nothing is
+    // allocated here, and a list that needs more is refused
+    if ((uint64_t)L.n > ctx->max_list_ints || L.ntiles + 1u > ctx->single.tiles_cap ||
+        L.nchunks > ctx->single.chunks_cap)
+        return GC_ENOSPC;
+    std::lock_guard<std::mutex> lk(ctx->mu);
     return launch_one(L, cls, ctx->single, ctx->status, (hipStream_t)hip_stream, kSingleLbMax, kChunkWordsSmall);
 }
 
@@ -846,7 +1080,8 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
         if (t && !valid_wave_tile(t)) return GC_EINVAL;
         forced = forced || t;
     }
-    if (o.schedule > 1u || o.carry_pass > 3u || o.reserved) return GC_EINVAL;
+    if (o.schedule > 1u || o.carry_pass > 3u) return GC_EINVAL;
+    if (o.pack_ints && o.pack_ints != GC_PACK_OFF && o.pack_ints > (uint32_t)kPackTiles[1]) return GC_EINVAL;
     if ((o.autotune || o.use_graph) && nlists && (!d_streams || !d_out)) return GC_EINVAL;
     gc_plan *p = new (std::nothrow) gc_plan();
     if (!p) return GC_ENOMEM;
@@ -859,6 +1094,8 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     }
     p->use_graph = o.use_graph != 0;
     p->serial = o.schedule == 0u;
+    p->pack_forced = o.pack_ints != 0u;
+    p->pack_max = o.pack_ints == GC_PACK_OFF ? 0u : o.pack_ints ? o.pack_ints : kDefaultPackMax;
     p->lb_max = o.carry_pass == 1u ? kLookbackAll : o.carry_pass == 2u ? 0u
               : o.carry_pass == 3u ? kLookbackHybrid : kDefaultLbMax;
     // tests of the look-back's bounded wait: tiles stop publishing their
@@ -972,6 +1209,7 @@ gc_status gc_plan_timings(gc_plan *plan, uint32_t max_runs, float *ms, uint32_t 
             HIP_OK(hipEventElapsedTime(&row[1 + kClasses + c], ce[2], ce[3]));
             HIP_OK(hipEventElapsedTime(&row[1 + 2 * kClasses + c], ce[3], ce[4]));
         }
+        HIP_OK(hipEventElapsedTime(&row[1 + 3 * kClasses], e[2 + kTevPack], e[2 + kTevPack + 1]));
     }
     *nruns = n;
     return GC_OK;
@@ -992,6 +1230,19 @@ gc_status gc_plan_config(const gc_plan *plan, uint32_t *tile_ints, uint32_t *pfd
     if (pfd_tile_ints) *pfd_tile_ints = (uint32_t)plan->tile[kClsPfd];
     if (tiles) *tiles = t;
     if (sum_tiles) *sum_tiles = st;
+    return GC_OK;
+}
+
+gc_status gc_plan_pack_config(const gc_plan *plan, uint32_t *pack_ints, uint64_t *packs, uint64_t *packed_lists) {
+    if (!plan) return GC_EINVAL;
+    uint64_t np = 0, nl = 0;
+    for (const PackSet &ps : plan->pk) {
+        np += ps.packs();
+        nl += ps.h.size();
+    }
+    if (pack_ints) *pack_ints = plan->pack_max;
+    if (packs) *packs = np;
+    if (packed_lists) *packed_lists = nl;
     return GC_OK;
 }
 
@@ -1057,10 +1308,9 @@ gc_status gc_blockmix_encode(gc_ctx *ctx, const uint32_t *d_in, size_t n, const 
     if (gc_blockmix_bound_words(n) > 0xFFFFFFFFull) return GC_EINVAL;
     const size_t nb = (n + gcblk::kBlockInts - 1) / gcblk::kBlockInts;
     if (out_cap_words < 4 + nb) return GC_ENOSPC;
+    if (n > ctx->max_list_ints || nb > ctx->blk.cap) return GC_ENOSPC;   // sized when the context was created
     (void)hipSetDevice(ctx->device);
     std::lock_guard<std::mutex> lk(ctx->mu);
-    if (nb)
-        if (gc_status rc = ctx->blk.reserve(nb)) return rc;
     return blockmix_encode_locked(ctx, d_in, n, nb, d_class, d_out, out_cap_words, out_words,
                                   (hipStream_t)hip_stream);
 }
@@ -1240,12 +1490,12 @@ gc_status gc_encode_blocks(gc_ctx *ctx, const uint32_t *d_in, size_t n, int mode
     if (gc_blockmix_bound_words(n) > 0xFFFFFFFFull) return GC_EINVAL;
     const size_t nb = (n + gcblk::kBlockInts - 1) / gcblk::kBlockInts;
     if (out_cap_words < 4 + nb) return GC_ENOSPC;
+    if (n > ctx->max_list_ints || nb > ctx->blk.cap) return GC_ENOSPC;   // sized when the context was created
     (void)hipSetDevice(ctx->device);
     std::lock_guard<std::mutex> lk(ctx->mu);
     hipStream_t s = (hipStream_t)hip_stream;
     uint8_t *cls = d_class_out;
     if (nb) {
-        if (gc_status rc = ctx->blk.reserve(nb)) return rc;
         if (!cls) cls = ctx->blk.cls;
         int err = 0;
         if (mode == GC_SELECT_EXHAUSTIVE) {

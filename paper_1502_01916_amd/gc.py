@@ -24,7 +24,8 @@ DELTA = 1
 # decode kernel classes (gc_plan_timings columns)
 CLS_SIMPLE, CLS_SCHEME_UNARY, CLS_SCHEME_BINARY, CLS_AFOR, CLS_PFD = range(5)
 CLASSES = 5
-TIMING_FIELDS = 1 + 3 * CLASSES
+TIMING_FIELDS = 2 + 3 * CLASSES
+PACK_OFF = 0x80000000   # gc_plan_opts.pack_ints: no packed lists
 OK, EINVAL, ENOSPC, ECORRUPT, EDEVICE, EUNSUPPORTED, ENOMEM = 0, -1, -2, -3, -4, -5, -6
 _NAMES = {0: "GC_OK", -1: "GC_EINVAL", -2: "GC_ENOSPC", -3: "GC_ECORRUPT", -4: "GC_EDEVICE",
           -5: "GC_EUNSUPPORTED", -6: "GC_ENOMEM"}
@@ -56,12 +57,16 @@ class ListDesc(ctypes.Structure):
                 ("out_off", ctypes.c_uint64), ("n", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
+class CtxOpts(ctypes.Structure):
+    _fields_ = [("max_list_ints", ctypes.c_uint64), ("reserved", ctypes.c_uint32 * 2)]
+
+
 class PlanOpts(ctypes.Structure):
     _fields_ = [("tile_ints", ctypes.c_uint32), ("pfd_tile_ints", ctypes.c_uint32),
                 ("use_graph", ctypes.c_uint32), ("autotune", ctypes.c_uint32),
                 ("timing_slots", ctypes.c_uint32), ("schedule", ctypes.c_uint32),
                 ("class_tile_ints", ctypes.c_uint32 * 5), ("carry_pass", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("pack_ints", ctypes.c_uint32)]
 
 
 # how the tiles of a delta list get their carries (gc_plan_opts.carry_pass)
@@ -106,6 +111,7 @@ def lib():
         L.gc_encode_lists.argtypes = [u32p, u64p, sz, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Params),
                                       i, u32p, sz, u64p, i]
         L.gc_ctx_create.argtypes = [i, ctypes.POINTER(vp)]
+        L.gc_ctx_create_opts.argtypes = [i, ctypes.POINTER(CtxOpts), ctypes.POINTER(vp)]
         L.gc_ctx_destroy.argtypes = [vp]
         L.gc_decode.argtypes = [vp, vp, sz, u32p, vp, vp]
         L.gc_plan_create.argtypes = [vp, ctypes.POINTER(ListDesc), sz, u32p, ctypes.POINTER(PlanOpts),
@@ -115,6 +121,7 @@ def lib():
         L.gc_decode_each.argtypes = [vp, vp, vp, vp]
         L.gc_plan_config.argtypes = [vp, u32p, u32p, u64p, u64p]
         L.gc_plan_class_tiles.argtypes = [vp, u32p]
+        L.gc_plan_pack_config.argtypes = [vp, u32p, u64p, u64p]
         L.gc_plan_timings.argtypes = [vp, ctypes.c_uint32, f32p, u32p]
         L.gc_plan_timings.restype = ctypes.c_int
         L.gc_sync_status.argtypes = [vp, vp, u32p]
@@ -134,9 +141,10 @@ def lib():
         L.gc_mlp_grad.argtypes = [vp, vp, vp, vp, vp, ctypes.c_uint32, ctypes.c_float, vp, vp, vp]
         L.gc_mlp_train.argtypes = [vp, vp, vp, vp, vp, sz, ctypes.POINTER(AdamOpts), vp, vp]
         L.gc_encode_blocks.argtypes = [vp, vp, sz, i, vp, ctypes.c_uint32, vp, sz, ctypes.POINTER(sz), vp, vp]
-        for f in ("gc_encode", "gc_encode_lists", "gc_ctx_create", "gc_ctx_destroy", "gc_decode",
+        for f in ("gc_encode", "gc_encode_lists", "gc_ctx_create", "gc_ctx_create_opts", "gc_ctx_destroy",
+                  "gc_decode",
                   "gc_plan_create", "gc_plan_destroy", "gc_decode_batch", "gc_decode_each",
-                  "gc_plan_config", "gc_plan_class_tiles", "gc_sync_status", "gc_block_features",
+                  "gc_plan_config", "gc_plan_class_tiles", "gc_plan_pack_config", "gc_sync_status", "gc_block_features",
                   "gc_block_sizes", "gc_blockmix_encode", "gc_mlp_create", "gc_mlp_destroy", "gc_mlp_set_params",
                   "gc_mlp_get_params", "gc_mlp_forward", "gc_mlp_grad", "gc_mlp_train", "gc_encode_blocks",
                   "gc_mlp_get_state", "gc_mlp_set_state"):
@@ -220,11 +228,15 @@ def _ptr(t):
 
 
 class Context:
-    """gc_ctx_create / gc_decode / gc_sync_status / gc_ctx_destroy."""
+    """gc_ctx_create_opts / gc_decode / gc_sync_status / gc_ctx_destroy.
+    max_list_ints: the longest list decode() and the block encoders accept
+    (0 = the library's default, 2^24)."""
 
-    def __init__(self, device=0):
+    def __init__(self, device=0, max_list_ints=0):
         self._h = ctypes.c_void_p()
-        _check("gc_ctx_create", lib().gc_ctx_create(int(device), ctypes.byref(self._h)))
+        opts = CtxOpts(int(max_list_ints))
+        _check("gc_ctx_create_opts", lib().gc_ctx_create_opts(int(device), ctypes.byref(opts),
+                                                                ctypes.byref(self._h)))
 
     def decode(self, d_stream, stream_words, header, d_out, stream=None):
         """gc_decode: `header` is the host copy of the stream's first 4 words."""
@@ -290,7 +302,7 @@ class Plan:
 
     def __init__(self, ctx: Context, descs, headers, d_streams=None, d_out=None, tile_ints=0,
                  pfd_tile_ints=0, use_graph=False, autotune=False, timing_slots=0, locate_stream=False,
-                 carry_pass=CARRY_DEFAULT, class_tiles=None):
+                 carry_pass=CARRY_DEFAULT, class_tiles=None, pack_ints=0):
         self.ctx = ctx
         nl = len(descs)
         arr = (ListDesc * max(nl, 1))()
@@ -299,7 +311,7 @@ class Plan:
         hdr = np.ascontiguousarray(headers, dtype=np.uint32).reshape(-1)
         ct = (ctypes.c_uint32 * 5)(*[int(t) for t in (class_tiles if class_tiles is not None else [0] * 5)])
         opts = PlanOpts(int(tile_ints), int(pfd_tile_ints), int(bool(use_graph)), int(bool(autotune)),
-                        int(timing_slots), int(bool(locate_stream)), ct, int(carry_pass))
+                        int(timing_slots), int(bool(locate_stream)), ct, int(carry_pass), int(pack_ints))
         self._h = ctypes.c_void_p()
         rc = lib().gc_plan_create(ctx._h, arr, nl, _u32(hdr), ctypes.byref(opts),
                                   _ptr(d_streams) if d_streams is not None else None,
@@ -323,7 +335,7 @@ class Plan:
         _check("gc_plan_timings", lib().gc_plan_timings(self._h, int(max_runs), a, ctypes.byref(n)))
         m = np.array(a[:n.value * TIMING_FIELDS], dtype=np.float64).reshape(n.value, TIMING_FIELDS)
         return dict(total=m[:, 0], locate=m[:, 1:1 + CLASSES], sum=m[:, 1 + CLASSES:1 + 2 * CLASSES],
-                    decode=m[:, 1 + 2 * CLASSES:1 + 3 * CLASSES])
+                    decode=m[:, 1 + 2 * CLASSES:1 + 3 * CLASSES], pack=m[:, 1 + 3 * CLASSES])
 
     def config(self):
         """Chosen tile sizes, decode tiles per run and the tiles of those the
@@ -334,8 +346,12 @@ class Plan:
                                                       ctypes.byref(n), ctypes.byref(ns)))
         ct = (ctypes.c_uint32 * CLASSES)()
         _check("gc_plan_class_tiles", lib().gc_plan_class_tiles(self._h, ct))
+        pi, npk, npl = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check("gc_plan_pack_config", lib().gc_plan_pack_config(self._h, ctypes.byref(pi), ctypes.byref(npk),
+                                                                ctypes.byref(npl)))
         return dict(tile_ints=t.value, pfd_tile_ints=pt.value, tiles=n.value, sum_tiles=ns.value,
-                    class_tiles=[int(x) for x in ct])
+                    class_tiles=[int(x) for x in ct], pack_ints=pi.value, packs=npk.value,
+                    packed_lists=npl.value)
 
     def close(self):
         if self._h:

@@ -25,9 +25,9 @@ def test_kernel_names():
     assert bench.kernel_name(0, 1024, 1) == "gc_wave_kernel<1024, 0, 2>"
 
 
-def summary():
+def summary(path):
     kv = {}
-    with open(bench.TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
@@ -36,12 +36,27 @@ def summary():
 
 
 def test_traffic_only_for_the_profiled_sources_workload_and_kernel():
-    kv = summary()
-    units, kernel = int(kv["workload_units"]), kv["kernel"]
-    got = bench.read_traffic(units, kernel)
-    if kv["decode_sources_sha256"] == bench.decode_sources_sha256():
-        assert got == float(kv["hbm_bytes_per_launch"])
-    else:
-        assert got is None          # stale summary: traffic is reported as null
-    assert bench.read_traffic(units + 1, kernel) is None
-    assert bench.read_traffic(units, "gc_wave_kernel<9999, 9, 9>") is None
+    found = 0
+    for wl in bench.WORKLOADS:
+        path = bench.traffic_file(wl)
+        if not os.path.exists(path):
+            assert bench.read_traffic(wl, 100000, "gc_wave_kernel<2048, 1, 2>") is None
+            continue
+        found += 1
+        kv = summary(path)
+        units, kernel = int(kv["workload_units"]), kv["kernel"]
+        got = bench.read_traffic(wl, units, kernel)
+        if kv["decode_sources_sha256"] == bench.decode_sources_sha256():
+            assert got == float(kv["hbm_bytes_per_launch"])
+        else:
+            assert got is None          # stale summary: traffic is reported as null
+        assert bench.read_traffic(wl, units + 1, kernel) is None
+        assert bench.read_traffic(wl, units, "gc_wave_kernel<9999, 9, 9>") is None
+    assert found >= 1
+
+
+def test_variant_table_covers_every_codec_variant():
+    from paper_1502_01916_amd import gc
+    names = [v[0] for v in bench.all_variants(gc)]
+    assert len(names) == len(set(names)) == 14    # Simple, ten Group-Scheme, AFOR, PFD, BP128
+    assert sum(1 for n in names if n.startswith("gsc-")) == 10

@@ -67,7 +67,7 @@ def gen_inputs(rng, n):
     yield "spiky", x, False
 
 
-@pytest.mark.parametrize("k", [4, 8, 64])
+@pytest.mark.parametrize("k", [4, 8, 16, 32, 64])
 @pytest.mark.parametrize("vi", range(len(VARIANTS)))
 def test_single_list_parity(torch_cuda, ctx, vi, k):
     name, codec, kw = VARIANTS[vi]
@@ -130,11 +130,15 @@ def test_single_list_carry_modes(torch_cuda, ctx, codec, kw):
 
 
 def make_batch(rng, nlists, kmix=(4,), maxlen=40000):
+    """nlists lists cycling through the variants; each pass over them takes
+    the next layout width of kmix, and delta and TF lists alternate between
+    passes, so every (variant, k, delta) combination occurs once nlists
+    reaches 2 * len(kmix) * len(VARIANTS)."""
     lengths = np.clip(np.round(np.exp(rng.normal(np.log(800), 1.6, nlists))), 0, maxlen).astype(np.int64)
     streams, lists, plist = [], [], []
     for i, L in enumerate(lengths):
         name, codec, kw = VARIANTS[i % len(VARIANTS)]
-        k = kmix[i % len(kmix)]
+        k = kmix[(i // len(VARIANTS)) % len(kmix)]
         delta = (i // len(VARIANTS)) % 2 == 0
         x = (np.sort(rng.choice(1 << 28, int(L), replace=False)).astype(np.uint32) if delta
              else rng.geometric(0.2, int(L)).astype(np.uint32))
@@ -154,7 +158,7 @@ def test_batch_parity(torch_cuda, ctx, tiles, graph, carry):
     torch = torch_cuda
     tile, pfd_tile = tiles
     rng = np.random.default_rng(50 + tile + int(graph))
-    flat, offs, lengths, lists = make_batch(rng, 240, kmix=(4, 4, 8, 64))
+    flat, offs, lengths, lists = make_batch(rng, 300, kmix=(4, 8, 16, 32, 64))
     align = 4 if graph else 1        # 16-byte aligned lists take the vector-store path
     descs, headers, out_offs = gc.batch_layout(flat, offs, lengths, align=align)
     d_s = gc.to_device(flat)
@@ -503,3 +507,105 @@ def test_cfg2_full_size_batch(torch_cuda, ctx):
                 assert np.array_equal(got[lo[i]:lo[i + 1]], O.decode(seg))
             plan.close()
             del d_s, d_o
+
+
+def test_single_lists_of_different_classes(torch_cuda):
+    """One context decodes multi-tile delta lists of different codec classes
+    in turn (its single-list tables, look-back flags included, are shared by
+    every class): each output equals the oracle's, on a fresh context so the
+    classes' run counts stay level."""
+    torch = torch_cuda
+    c = gc.Context(0)
+    rng = np.random.default_rng(4242)
+    order = [(O.SIMPLE, {}), (O.SCHEME, dict(cg=1, ld=O.LD_CU)), (O.SCHEME, dict(cg=2, ld=O.LD_BINARY)),
+             (O.AFOR, {}), (O.PFD, {})]
+    for rnd in range(3):
+        for codec, kw in order:
+            n = int(rng.integers(20000, 60000))
+            d = np.sort(rng.choice(1 << 28, n, replace=False)).astype(np.uint32)
+            s = O.encode(d, O.params(codec, delta=True, **kw))
+            say("cross-class round", rnd, codec, kw, n)
+            got = gpu_decode(torch, c, s, n)
+            assert np.array_equal(got, O.decode(s)), (rnd, codec, kw)
+    c.close()
+
+
+def test_decode_captured_in_graph(torch_cuda, ctx):
+    """gc_decode allocates nothing and never synchronises, so it can be
+    captured in a hipGraph: the captured decode of a multi-tile delta list is
+    replayed several times, with eager work between the replays, and every
+    replay equals the oracle's decode."""
+    torch = torch_cuda
+    rng = np.random.default_rng(808)
+    for codec, kw in ((O.SIMPLE, {}), (O.PFD, {}), (O.SCHEME, dict(cg=8, ld=O.LD_IU))):
+        n = 300001
+        d = np.sort(rng.choice(1 << 28, n, replace=False)).astype(np.uint32)
+        s = O.encode(d, O.params(codec, delta=True, **kw))
+        want = O.decode(s)
+        d_s = gc.to_device(s)
+        d_o = torch.full((n + 64,), -1, dtype=torch.int32, device="cuda")
+        ctx.decode(d_s, s.size, s[:4], d_o)          # eager warm-up
+        torch.cuda.synchronize()
+        say("graph capture of gc_decode", codec, kw)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            ctx.decode(d_s, s.size, s[:4], d_o)
+        for rep in range(4):
+            d_o.fill_(-1)
+            g.replay()
+            rc, det = ctx.sync_status()
+            assert rc == gc.OK, det
+            out = gc.to_host(d_o)
+            assert np.array_equal(out[:n], want), rep
+            assert np.all(out[n:] == 0xFFFFFFFF)
+            _ = (d_o[:16].sum() + 1).item()     # unrelated eager work between replays
+        del g
+
+
+def test_decode_over_context_limit(torch_cuda):
+    """A list longer than the context's max_list_ints is refused with
+    GC_ENOSPC (nothing is launched or allocated); lists within it decode."""
+    torch = torch_cuda
+    c = gc.Context(0, max_list_ints=4096)
+    d = np.arange(5000, dtype=np.uint32) * 3
+    s = O.encode(d, O.params(O.SIMPLE, delta=True))
+    d_s = gc.to_device(s)
+    d_o = torch.full((5064,), -1, dtype=torch.int32, device="cuda")
+    with pytest.raises(gc.GcError) as e:
+        c.decode(d_s, s.size, s[:4], d_o)
+    assert e.value.code == gc.ENOSPC
+    assert np.all(gc.to_host(d_o) == 0xFFFFFFFF)
+    s2 = O.encode(d[:4096], O.params(O.SIMPLE, delta=True))
+    assert np.array_equal(gpu_decode(torch, c, s2, 4096), d[:4096])
+    c.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_autotuned_plan_with_locate_stream(torch_cuda, ctx, tmp_path, monkeypatch, graph):
+    """Autotuning a plan whose locate kernels run on a second stream: the
+    candidate runs and the final plan agree on whose locate epoch tags the
+    tile starts, so every run decodes (status OK) and matches the oracle."""
+    torch = torch_cuda
+    monkeypatch.setenv("GC_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    rng = np.random.default_rng(78 + int(graph))
+    flat, offs, lengths, lists = make_batch(rng, 150, kmix=(4, 8))
+    descs, headers, out_offs = gc.batch_layout(flat, offs, lengths, align=4)
+    d_s = gc.to_device(flat)
+    d_o = torch.full((int(out_offs[-1]),), -1, dtype=torch.int32, device="cuda")
+    want = np.concatenate(lists)
+    say("autotune with locate stream, graph", graph)
+    plan = gc.Plan(ctx, descs, headers, d_s, d_o, autotune=True, locate_stream=True, use_graph=graph)
+    rc, det = ctx.sync_status()
+    assert rc == gc.OK, det        # the autotuner's own runs
+    for rep in range(3):
+        d_o.fill_(-1)
+        plan.decode_batch(d_s, d_o)
+        rc, det = ctx.sync_status()
+        assert rc == gc.OK, det
+        assert np.array_equal(gc.unpad(gc.to_host(d_o), out_offs, lengths), want), rep
+    d_o.fill_(-1)
+    plan.decode_each(d_s, d_o)
+    rc, det = ctx.sync_status()
+    assert rc == gc.OK, det
+    assert np.array_equal(gc.unpad(gc.to_host(d_o), out_offs, lengths), want)
+    plan.close()

@@ -36,7 +36,7 @@ def torch_cuda():
 
 @pytest.fixture(scope="module")
 def ctx(torch_cuda):
-    c = gc.Context(0)
+    c = gc.Context(0, max_list_ints=EVAL_INTS)
     yield c
     c.close()
 
