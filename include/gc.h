@@ -152,6 +152,23 @@ gc_status gc_ctx_destroy(gc_ctx *ctx);
 gc_status gc_decode(gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words,
                     const uint32_t *h_header, uint32_t *d_out, void *hip_stream);
 
+/* gc_decode for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, output and errors as gc_decode, and the same kernels, but
+ * the single-list tables (locate epochs, tile starts, tile carries,
+ * look-back flags, locate chunk aggregates) live in one fixed device array
+ * of about 434 KB that the library holds on each GPU it runs on until the
+ * process ends; the array is found and cleared once per device when the
+ * first context on it is created.  The call itself allocates nothing,
+ * neither here nor in any library it calls, and never synchronises.
+ * Lists of up to 2^22 integers (GC_ENOSPC above; a context's max_list_ints
+ * does not apply).  Device errors go to ctx's status word (gc_sync_status).
+ * Every call on one GPU shares that GPU's array, whatever the context:
+ * calls that overlap in time on one GPU race and must be serialised by the
+ * caller (one stream, or events between them).                            */
+gc_status gc_decode_noalloc(gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words,
+                            const uint32_t *h_header, uint32_t *d_out, void *hip_stream);
+
 /* One list of a batch: its stream at d_streams + stream_off_words (16-byte
  * aligned, stream_words long), its output at d_out + out_off (n words).    */
 typedef struct {

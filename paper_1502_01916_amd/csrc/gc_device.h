@@ -19,6 +19,17 @@ constexpr int kClasses = 5;                 // decode kernel classes (codec fami
 constexpr uint64_t single_tiles_cap(uint64_t max_ints) { return (max_ints + 1023u) / 1024u + 1u; }
 constexpr uint64_t single_chunks_cap(uint64_t max_ints) { return ((max_ints + 3u) / 4u + 4u + 127u) / 128u + 1u; }
 
+// The fixed device scratch of the allocation-free single-list decode: the
+// same tables for lists of up to kNoallocMaxInts integers, at 256-byte
+// aligned offsets (about 434 KB).
+constexpr uint64_t kNoallocMaxInts = 1ull << 22;
+constexpr uint64_t noalloc_round(uint64_t b) { return (b + 255u) & ~(uint64_t)255u; }
+struct NoallocLayout {
+    uint64_t state, tiles, carry, flags, agg, pre, bytes;
+    uint64_t tiles_cap, chunks_cap;
+};
+constexpr NoallocLayout noalloc_layout();   // defined after the structures it sizes
+
 // One list of a launch.  For a batch these live in a device table; for a
 // single list the runtime passes one by value.  The header words come from
 // the host's copy of the header; kernels check the stream against them.
@@ -69,6 +80,22 @@ struct LocVal {
     uint32_t exc;      // exception words
     uint64_t data;     // component data bits
 };
+
+constexpr NoallocLayout noalloc_layout() {
+    NoallocLayout l{};
+    l.tiles_cap = single_tiles_cap(kNoallocMaxInts);
+    l.chunks_cap = single_chunks_cap(kNoallocMaxInts);
+    l.state = 0;
+    l.tiles = noalloc_round(l.state + kClasses * sizeof(RunState));
+    l.carry = noalloc_round(l.tiles + l.tiles_cap * sizeof(TileInfo));
+    l.flags = noalloc_round(l.carry + l.tiles_cap * sizeof(uint32_t));
+    l.agg = noalloc_round(l.flags + l.tiles_cap * sizeof(unsigned long long));
+    l.pre = noalloc_round(l.agg + l.chunks_cap * sizeof(LocVal));
+    l.bytes = noalloc_round(l.pre + l.chunks_cap * sizeof(LocVal));
+    return l;
+}
+constexpr uint64_t kNoallocScratchBytes = noalloc_layout().bytes;
+static_assert(kNoallocScratchBytes < (1u << 20), "the fixed scratch stays modest");
 
 // Locate runs as three fence-free kernels: reduce (one aggregate per control
 // chunk), scan (exclusive prefix of the aggregates within each list) and emit

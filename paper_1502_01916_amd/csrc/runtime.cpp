@@ -28,6 +28,8 @@ int launch_locate(const LocateArgs &a, int chunk_words, hipStream_t s);
 int launch_carry_scan(const CarryArgs &a, hipStream_t s);
 int launch_decode(int tile, int cls, int mode, const DecodeArgs &a, hipStream_t s);
 int launch_pack(int pt, const PackArgs &a, hipStream_t s);
+int noalloc_setup(int device, void **ptr);
+void *noalloc_ptr(int device);
 }  // namespace gcdev
 
 using namespace gcdev;
@@ -1023,6 +1025,9 @@ gc_status gc_ctx_create_opts(int device, const gc_ctx_opts *opts, gc_ctx **ctx) 
     if (!rc) rc = c->single.init_state();
     if (!rc) rc = c->single.reserve(single_tiles_cap(max_ints), single_chunks_cap(max_ints));
     if (!rc) rc = c->blk.reserve((size_t)((max_ints + gcblk::kBlockInts - 1) / gcblk::kBlockInts));
+    // the fixed scratch of gc_decode_noalloc on this device (set up once)
+    void *fixed = nullptr;
+    if (!rc && noalloc_setup(device, &fixed)) rc = GC_EDEVICE;
     if (!rc && hipDeviceSynchronize() != hipSuccess) rc = GC_EDEVICE;
     if (rc) {
         (void)hipGetLastError();
@@ -1062,6 +1067,33 @@ gc_status gc_decode(gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words, 
         return GC_ENOSPC;
     std::lock_guard<std::mutex> lk(ctx->mu);
     return launch_one(L, cls, ctx->single, ctx->status, (hipStream_t)hip_stream, kSingleLbMax, kChunkWordsSmall);
+}
+
+gc_status gc_decode_noalloc(gc_ctx *ctx, const uint32_t *d_stream, size_t stream_words, const uint32_t *h_header,
+                            uint32_t *d_out, void *hip_stream) {
+    if (!ctx) return GC_EINVAL;
+    ListDesc L;
+    int cls = 0;
+    bool empty = false;
+    if (gc_status rc = single_list(ctx, d_stream, stream_words, h_header, d_out, L, cls, empty)) return rc;
+    if (empty) return GC_OK;
+    constexpr NoallocLayout lay = noalloc_layout();
+    if ((uint64_t)L.n > kNoallocMaxInts || L.ntiles + 1u > lay.tiles_cap || L.nchunks > lay.chunks_cap)
+        return GC_ENOSPC;
+    uint8_t *base = static_cast<uint8_t *>(noalloc_ptr(ctx->device));
+    if (!base) return GC_EDEVICE;
+    // a view of the fixed array, in the layout of the context's own tables
+    // (nothing here owns or frees it)
+    Scratch sc;
+    sc.state = reinterpret_cast<RunState *>(base + lay.state);
+    sc.tiles = reinterpret_cast<TileInfo *>(base + lay.tiles);
+    sc.carry = reinterpret_cast<uint32_t *>(base + lay.carry);
+    sc.flags = reinterpret_cast<unsigned long long *>(base + lay.flags);
+    sc.agg = reinterpret_cast<LocVal *>(base + lay.agg);
+    sc.pre = reinterpret_cast<LocVal *>(base + lay.pre);
+    sc.tiles_cap = lay.tiles_cap;
+    sc.chunks_cap = lay.chunks_cap;
+    return launch_one(L, cls, sc, ctx->status, (hipStream_t)hip_stream, kSingleLbMax, kChunkWordsSmall);
 }
 
 gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists, const uint32_t *h_headers,

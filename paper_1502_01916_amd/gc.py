@@ -114,6 +114,7 @@ def lib():
         L.gc_ctx_create_opts.argtypes = [i, ctypes.POINTER(CtxOpts), ctypes.POINTER(vp)]
         L.gc_ctx_destroy.argtypes = [vp]
         L.gc_decode.argtypes = [vp, vp, sz, u32p, vp, vp]
+        L.gc_decode_noalloc.argtypes = [vp, vp, sz, u32p, vp, vp]
         L.gc_plan_create.argtypes = [vp, ctypes.POINTER(ListDesc), sz, u32p, ctypes.POINTER(PlanOpts),
                                      vp, vp, ctypes.POINTER(vp)]
         L.gc_plan_destroy.argtypes = [vp]
@@ -142,7 +143,7 @@ def lib():
         L.gc_mlp_train.argtypes = [vp, vp, vp, vp, vp, sz, ctypes.POINTER(AdamOpts), vp, vp]
         L.gc_encode_blocks.argtypes = [vp, vp, sz, i, vp, ctypes.c_uint32, vp, sz, ctypes.POINTER(sz), vp, vp]
         for f in ("gc_encode", "gc_encode_lists", "gc_ctx_create", "gc_ctx_create_opts", "gc_ctx_destroy",
-                  "gc_decode",
+                  "gc_decode", "gc_decode_noalloc",
                   "gc_plan_create", "gc_plan_destroy", "gc_decode_batch", "gc_decode_each",
                   "gc_plan_config", "gc_plan_class_tiles", "gc_plan_pack_config", "gc_sync_status", "gc_block_features",
                   "gc_block_sizes", "gc_blockmix_encode", "gc_mlp_create", "gc_mlp_destroy", "gc_mlp_set_params",
@@ -243,6 +244,13 @@ class Context:
         hdr = np.ascontiguousarray(header, dtype=np.uint32)[:4]
         _check("gc_decode", lib().gc_decode(self._h, _ptr(d_stream), int(stream_words), _u32(hdr),
                                             _ptr(d_out), _stream_handle(stream)))
+
+    def decode_noalloc(self, d_stream, stream_words, header, d_out, stream=None):
+        """gc_decode_noalloc: gc_decode with the library's fixed device
+        scratch (lists of up to 2^22 integers); allocates nothing."""
+        hdr = np.ascontiguousarray(header, dtype=np.uint32)[:4]
+        _check("gc_decode_noalloc", lib().gc_decode_noalloc(self._h, _ptr(d_stream), int(stream_words), _u32(hdr),
+                                                            _ptr(d_out), _stream_handle(stream)))
 
     def sync_status(self, stream=None):
         """Returns (status, detail) of the first device error since the last call."""

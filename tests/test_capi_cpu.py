@@ -113,6 +113,7 @@ def test_encode_reports_small_capacity():
 def test_device_entry_points_validate_arguments_without_touching_a_gpu():
     L = gc.lib()
     assert L.gc_decode(None, None, 0, None, None, None) == gc.EINVAL
+    assert L.gc_decode_noalloc(None, None, 0, None, None, None) == gc.EINVAL
     assert L.gc_plan_destroy(None) == gc.EINVAL
     assert L.gc_decode_batch(None, None, None, None) == gc.EINVAL
     assert L.gc_sync_status(None, None, None) == gc.EINVAL
