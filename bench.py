@@ -104,6 +104,11 @@ def kernel_name(cls, tile, carry_pass):
     return "gc_wave_kernel<%d, %d, %d>" % (tile, cls, 0 if carry_pass == 2 else 2)
 
 
+def pack_kernel_name(pack_ints):
+    """The pack kernel a plan with this packed-list threshold launches."""
+    return "gc_pack_kernel<2048, 512>" if pack_ints <= 2048 else "gc_pack_kernel<4096, 1024>"
+
+
 def codec_class(gc, codec, kw):
     if codec == gc.SIMPLE:
         return 0
@@ -122,10 +127,16 @@ class Workload:
         self.cls, self.want = cls, want
         self.ints = int(lengths.sum())
 
-    def class_bytes(self, c):
+    def class_bytes(self, c, packed=None):
         """Algorithmic bytes of one decode pass of class c: its streams read
-        once, its integers written once."""
+        once, its integers written once (lists the pack kernel decodes
+        excluded)."""
         m = self.cls == c
+        if packed is not None:
+            m = m & ~packed
+        return self.bytes_of(m)
+
+    def bytes_of(self, m):
         words = int(np.sum((self.offs[1:] - self.offs[:-1])[m]))
         return 4 * words + 4 * int(self.lengths[m].sum())
 
@@ -347,7 +358,8 @@ def measure(gc, torch, ctx, wl, args, keep_device=False):
     log("%s plan: %s (%.1fs)" % (wl.name, cfg, time.time() - t))
     tplan = gc.Plan(ctx, descs, headers, d_s, d_o, class_tiles=cfg["class_tiles"],
                     locate_stream=args.locate_stream, timing_slots=args.steps + args.warmup,
-                    carry_pass=args.carry_pass)
+                    carry_pass=args.carry_pass, pack_ints=cfg["pack_ints"] or gc.PACK_OFF)
+    packed = plan.packed_lists(wl.lengths.size)
     elapsed = timed(lambda: plan.decode_batch(d_s, d_o), args.steps, args.warmup, torch)
     t_events = timed(lambda: tplan.decode_batch(d_s, d_o), args.steps, args.warmup, torch)
     tm = tplan.timings(args.steps)
@@ -365,13 +377,21 @@ def measure(gc, torch, ctx, wl, args, keep_device=False):
     m.value = wl.ints / (elapsed / args.steps) / 1e9
     m.path_gbs = wl.path_bytes() / (elapsed / args.steps) / 1e9
     dec = tm["decode"].mean(axis=0)
+    pack_ms = float(tm["pack"].mean())
     m.dec = dec
-    m.cls = int(np.argmax(dec))                 # the dominant kernel: the longest decode pass
-    m.cls_bytes = wl.class_bytes(m.cls)
-    m.dec_avg = float(dec[m.cls])
+    # the dominant kernel: the longest decode pass, or the pack kernel
+    m.cls = int(np.argmax(dec))
+    if cfg["packs"] and pack_ms > dec[m.cls]:
+        m.cls = -1
+        m.cls_bytes = wl.bytes_of(packed)
+        m.dec_avg = pack_ms
+        m.kname = pack_kernel_name(cfg["pack_ints"])
+    else:
+        m.cls_bytes = wl.class_bytes(m.cls, packed)
+        m.dec_avg = float(dec[m.cls])
+        m.kname = kernel_name(m.cls, cfg["class_tiles"][m.cls], args.carry_pass)
     m.achieved = m.cls_bytes / (m.dec_avg * 1e-3) / 1e9
-    m.kname = kernel_name(m.cls, cfg["class_tiles"][m.cls], args.carry_pass)
-    present = [c for c in range(5) if np.any(wl.cls == c)]
+    present = [c for c in range(5) if np.any((wl.cls == c) & ~packed)]
     m.phases = {
         "note": "from a second plan with the same tiles and HIP events between the phases",
         "gpu_total": round(float(tm["total"].mean()), 4),
@@ -380,12 +400,17 @@ def measure(gc, torch, ctx, wl, args, keep_device=False):
                    if args.locate_stream else {"all classes": round(float(tm["locate"].sum(axis=1).mean()), 4)}),
         "sum_and_carry": {CLASS_NAMES[c]: round(float(tm["sum"][:, c].mean()), 4) for c in present},
         "decode": {CLASS_NAMES[c]: round(float(dec[c]), 4) for c in present},
-        "decode_hbm_frac": {CLASS_NAMES[c]: round(wl.class_bytes(c) / (float(dec[c]) * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                                  4) for c in present},
+        "decode_hbm_frac": {CLASS_NAMES[c]: round(wl.class_bytes(c, packed) / (float(dec[c]) * 1e-3) / 1e9
+                                                  / HBM_PEAK_GBS, 4) for c in present},
     }
-    log("%s: step %.3f ms, %.1f Gints/s, path %.0f GB/s (%.1f%% of HBM); dominant %s decode %.3f ms, %.0f GB/s; "
+    if cfg["packs"]:
+        m.phases["pack"] = round(pack_ms, 4)
+        m.phases["pack_lists"] = int(packed.sum())
+        m.phases["pack_ints"] = int(wl.lengths[packed].sum())
+        m.phases["pack_hbm_frac"] = round(wl.bytes_of(packed) / (pack_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    log("%s: step %.3f ms, %.1f Gints/s, path %.0f GB/s (%.1f%% of HBM); dominant %s %.3f ms, %.0f GB/s; "
         "phases %s" % (wl.name, m.ms_per_step, m.value, m.path_gbs, 100 * m.path_gbs / HBM_PEAK_GBS,
-                       CLASS_NAMES[m.cls], m.dec_avg, m.achieved, m.phases))
+                       m.kname, m.dec_avg, m.achieved, m.phases))
     tplan.close()
     if keep_device:
         m.plan, m.d_s, m.d_o, m.out_offs = plan, d_s, d_o, out_offs
@@ -567,6 +592,9 @@ def main():
             "class_tile_ints": m.cfg["class_tiles"],
             "tiles": m.cfg["tiles"],
             "sum_tiles": m.cfg["sum_tiles"],
+            "pack_ints": m.cfg["pack_ints"],
+            "packs": m.cfg["packs"],
+            "packed_lists": m.cfg["packed_lists"],
             "verified_bit_exact": m.verified,
         },
         "path_hbm_frac": round(m.path_gbs / HBM_PEAK_GBS, 4),

@@ -208,11 +208,14 @@ typedef struct {
                                 3 look-back for lists of at most 64 tiles
                                 (one window of flags), the tile-sum pass for
                                 longer ones; 0 = default (3)                   */
-    uint32_t pack_ints;      /* lists of at most this many integers (1 .. 2048)
-                                whose streams fit a pack's staging buffer (4
-                                KB) are decoded many to a wave by the pack
-                                kernels instead of by the class passes;
-                                GC_PACK_OFF: none; 0 = autotuned (with
+    uint32_t pack_ints;      /* lists of at most this many integers (1 .. 4096)
+                                are decoded many to a wave by the pack kernel
+                                instead of by the class passes, when their
+                                streams fit a pack (2 KB of stream for a
+                                threshold up to 2048, else 4 KB); a pack holds
+                                up to 64 lists of one stream format (codec,
+                                k and codec parameters; docID and TF lists
+                                mix); GC_PACK_OFF: none; 0 = autotuned (with
                                 autotune) or the default, 2048               */
 } gc_plan_opts;
 #define GC_PACK_OFF 0x80000000u
@@ -280,6 +283,10 @@ gc_status gc_plan_config(const gc_plan *plan, uint32_t *tile_ints, uint32_t *pfd
  * of the pack kernels) and the lists they hold.  Any pointer may be NULL.  */
 gc_status gc_plan_pack_config(const gc_plan *plan, uint32_t *pack_ints, uint64_t *packs,
                               uint64_t *packed_lists);
+
+/* Which lists of a plan the pack kernel decodes: h_packed[i] (host memory,
+ * nlists bytes) = 1 for a packed list, 0 for one the class passes decode.  */
+gc_status gc_plan_packed_lists(const gc_plan *plan, uint8_t *h_packed, size_t nlists);
 
 /* The tile size (integers per wave tile) of every codec class of a plan,
  * GC_CLASSES entries in class order (sizes of classes the plan does not hold

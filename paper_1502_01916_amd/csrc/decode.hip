@@ -1769,223 +1769,612 @@ __global__ __launch_bounds__(kThreads, (MODE == kModeSum && CLS == kClsPfd) ? 7 
 }
 
 // ===========================================================================
-// Pack kernel: many short lists per wave.
+// Pack kernel: many short lists per wave, decoded together.
 //
-// A list of one tile still pays a tile's whole chain of dependent loads
-// (its work item, its descriptor, then its header, control words and rows)
-// for a few hundred integers.  Here a wave takes a pack of up to 64 such
-// lists: lane j loads list j's descriptor, a wave scan places the lists'
-// whole streams one after another in the wave's LDS staging buffer, and the
-// wave copies them in with 16-byte loads, every list's at once.  It then
-// runs, list after list, the codec's prologue on the staged control words
-// and the unpack on the staged rows (tiles of PT integers: 1024, or 2048
-// for the 64-way layout), writing each list to its own output.  Nothing is
-// carried between lists, so a list's prefix sum starts from zero.
+// A list of one tile still pays a tile's whole chain of dependent loads and
+// its prologue for a few hundred integers.  Here a wave takes a pack of up
+// to 64 short lists that share one stream format (codec, layout width and
+// codec parameters; docID and TF lists mix): lane j loads list j's
+// descriptor, wave scans place the lists' streams one after another in the
+// wave's LDS staging buffer (16-byte loads, every list's at once) and their
+// tuples one after another in the pack's tuple space (each list's first
+// tuple at a multiple of 32 / k tuples, so every list -- and every Group-PFD
+// block -- starts at a 32-integer boundary of the pack's integer space).
+// The control units of all the lists (selectors, unary code words, length
+// fields, frame bytes, block descriptors) are then parsed together, lane by
+// lane, with scans that restart at each list's first unit; they give one
+// record per tuple of the pack: list, data row (a 16-byte chunk of the
+// staging buffer), bit shift and width.  The unpack walks the pack's quads
+// 64 at a time: each lane makes four integers from its tuple's record and
+// two staged rows, Group-PFD patches them from a bitmap of the pack's
+// exception positions, and docID lists are prefix-summed by a wave scan that
+// restarts at each list's first quad.
 
-template <int PT>
-union PackProlog {
-    WaveSmem<PT, kClsSim> sim;
-    WaveSmem<PT, kClsGscU> gscu;
-    WaveSmem<PT, kClsGscB> gscb;
-    WaveSmem<PT, kClsAfor> afor;
-    WaveSmem<PT, kClsPfd> pfd;
-};
+constexpr uint32_t kPackLists = 64;
 
-// SBC: staging chunks (16 bytes) for the pack's streams; one row of the
-// widest layout (16 chunks) follows them, which the unpack may read past a
-// list's last row (those bits are masked off).
-template <int PT, int SBC>
-struct PackSmem {
-    PackProlog<PT> u;
-    u32x4 stage[SBC + 16];
-    uint32_t soff[64];     // staging chunk offset of list j (the total for j >= the pack's lists)
-};
-
-// Early control words of a packed list's prologue, from the staged stream:
-// every word the prologue may read (the unary Group-Scheme prologue reads
-// past its early words from global memory otherwise).
-template <int PT, int CLS>
-constexpr int pack_ctrl_words() {
-    return CLS == kClsGscU ? (WaveSmem<PT, kClsGscU>::NCTRL + 63) / 64 : ctrl_early_words<PT, CLS>();
+// Records of the pack's tuples: list:6 | row chunk:12 | shift:5 | width:6.
+__device__ __forceinline__ uint32_t pack_rec(uint32_t j, uint32_t chunk, uint32_t sh, uint32_t bw) {
+    return (j << 23) | ((chunk & 0xFFFu) << 11) | (sh << 6) | bw;
+}
+// The record of a tuple O bits into the column that starts at row chunk c0.
+__device__ __forceinline__ uint32_t pack_rec_at(uint32_t j, uint32_t c0, uint32_t kq, uint32_t O, uint32_t bw) {
+    return pack_rec(j, c0 + (O >> 5) * kq, O & 31u, bw);
 }
 
-// Decodes packed list `sw` (its stream staged in LDS at sw, the host's
-// copy of its header in w0 / n / C / D) to out.
-template <int PT, int CLS, int SBC>
-__device__ void pack_list(const PackArgs &a, WaveSmem<PT, CLS> &sm, const uint32_t *sw, const uint32_t *S,
-                          uint32_t *out, uint32_t n, uint32_t w0, uint32_t C, uint32_t D, uint32_t words,
-                          uint32_t lane) {
-    using SM = WaveSmem<PT, CLS>;
-    constexpr int R = PT / 256;
-    constexpr bool PATCH = CLS == kClsPfd;
-    TileCtx c;
-    c.S = S;
-    c.n = n;
-    c.C = C;
-    c.D = D;
-    bool ok = header_fields(w0, c.h);
-    c.k = (uint32_t)c.h.k;
-    c.lk = (uint32_t)c.h.lk;
-    c.T = (n + c.k - 1u) >> c.lk;
-    c.TT = (uint32_t)PT >> c.lk;
-    c.t0 = 0;
-    c.i0 = 0;
-    ok = ok && n >= 1u && n <= (uint32_t)PT && (32u << c.lk) <= (uint32_t)PT && 4u + C + D <= words;
-    c.ntup = ok ? c.T : 0u;
-    c.nint = ok ? n : 0u;
-    c.ctrl = S + 4;
-    c.data = S + 4 + C;
-    c.has_en = false;
-    c.st = TileInfo{};
-    c.en = TileInfo{};
-    // the stream's own header against the host's copy
-    if (ok && (sw[0] != w0 || sw[1] != n || sw[2] != C || sw[3] != D)) {
-        if (lane == 0) latch(a.status, kErrHeader);
-        return;
-    }
-    constexpr int CE = pack_ctrl_words<PT, CLS>();
-    uint32_t ce[CE];
-    uint32_t cw0 = 0, nw = 0;
-    tile_ctrl_words<CLS>(c, cw0, nw);
-    const bool cok = ok && nw > 0u && cw0 + nw <= C;
+// Capacities of one pack: PI integers of tuple space (PI / 4 tuples), SW
+// staged stream words, 64 lists.
+template <int PI, int SW>
+struct PackSmem {
+    static constexpr int TUP = PI / 4;
+    static constexpr int TPL = TUP / 64;                       // tuples per lane in the record expansion
+    static constexpr int NU = SW / 4 > TUP / 8 + 64 ? SW / 4 : TUP / 8 + 64;   // selector / frame records
+    static constexpr int NBLK = TUP / 32 + 64;                 // Group-PFD blocks
+    static constexpr int NBM = PI / 32;                        // exception bitmap words
+    u32x4 stage[SW / 4 + 16];     // the streams (+ one row of the widest layout, read past a list's last row)
+    uint32_t rec[TUP];            // tuple records (unit markers while the records are built)
+    u32x4 lst[kPackLists];        // list j: tuple base | delta << 31, n, output pointer (low, high word)
+    uint32_t so[kPackLists + 1];  // staging chunk of list j (the pack's total from the last list on)
+    uint32_t tb[kPackLists + 1];  // tuple base of list j (likewise)
+    uint32_t ub[kPackLists + 1];  // first control unit of list j (likewise)
+    // list j: tuples, stage word of its control area, control words, data
+    // words, stream words, chunk of its data area
+    uint32_t lt[6][kPackLists];
+    union {
+        uint2 info[NU];           // Group-Simple, Group-AFOR: unit {tuple start | bit << 16, record base}
+        uint16_t z[TUP];          // unary Group-Scheme: terminator position of each tuple's code
+        struct {
+            u32x4 blk[NBLK];      // Group-PFD block: descriptor, first row chunk, exception word, list
+            uint32_t bmap[NBM], xcnt[NBM], vbit[NBM];
+        } p;
+    } u;
+};
+
+// The list of unit x: the last j with base[j] <= x (base[j] holds the
+// pack's total for the lists after its last, so those are never chosen).
+__device__ __forceinline__ uint32_t pack_list_of(const uint32_t *base, uint32_t x) {
+    uint32_t j = 0;
 #pragma unroll
-    for (int v = 0; v < CE; v++) {
-        const uint32_t i = (uint32_t)v * 64u + lane;
-        ce[v] = cok && i < nw ? sw[4u + cw0 + i] : 0u;
+    for (uint32_t step = 32u; step; step >>= 1) j = base[j + step] <= x ? j + step : j;
+    return j;
+}
+
+// Exclusive scan of x over the lanes of one round that restarts at every
+// lane with `head` set; lanes before the round's first head continue the
+// running total `carry` of the previous rounds, which is advanced.
+__device__ __forceinline__ uint32_t seg_excl_scan(uint32_t x, bool head, uint32_t lane, uint32_t &carry) {
+    const uint32_t inc = wave_incl_scan(x);
+    const uint32_t ex = inc - x;
+    const uint32_t hl = wave_incl_max(head ? lane + 1u : 0u);   // 1 + the last head at or before this lane
+    const uint32_t hx = (uint32_t)__shfl((int)ex, (int)(hl ? hl - 1u : 0u));
+    const uint32_t e = hl ? ex - hx : carry + ex;
+    carry = (uint32_t)__builtin_amdgcn_readlane((int)(e + x), 63);
+    return e;
+}
+
+// Unit records (Group-Simple selectors, Group-AFOR frames) to tuple
+// records: every unit marked its first tuple with its index + 1; a running
+// maximum over the tuples names each tuple's unit.  Lane l owns tuples
+// [l * TPL, (l + 1) * TPL).
+template <int PI, int SW>
+__device__ __forceinline__ void pack_expand(PackSmem<PI, SW> &sm, uint32_t lane, uint32_t kq) {
+    using SM = PackSmem<PI, SW>;
+    constexpr int TPL = SM::TPL;
+    const uint32_t t0 = lane * (uint32_t)TPL;
+    uint32_t mk[TPL];
+#pragma unroll
+    for (int i = 0; i < TPL; i++) mk[i] = sm.rec[t0 + (uint32_t)i];
+#pragma unroll
+    for (int i = 1; i < TPL; i++) mk[i] = max(mk[i], mk[i - 1]);
+    const uint32_t before = wave_shr1(wave_incl_max(mk[TPL - 1]));
+#pragma unroll
+    for (int i = 0; i < TPL; i++) {
+        const uint32_t m = max(max(mk[i], before), 1u) - 1u;
+        const uint2 in = sm.u.info[m];
+        const uint32_t t = t0 + (uint32_t)i;
+        const uint32_t bw = in.y & 63u;
+        const uint32_t O = (in.x >> 16) + (t - (in.x & 0xFFFFu)) * bw;
+        sm.rec[t] = in.y + (((O >> 5) * kq) << 11) + ((O & 31u) << 6);
     }
-    uint32_t dbase = 0, err = ok ? 0u : kErrRange;
-    PatchSrc ps{sm.bmap, sm.vbit, sm.xcnt, nullptr, ExcSrc{nullptr, nullptr, 0u, false}, false};
-    if (!err) {
-        if constexpr (CLS == kClsSim) err = wprologue_sim<PT, CE>(c, sm, lane, dbase, ce, cok);
-        else if constexpr (CLS == kClsGscU) err = wprologue_gscu<PT, CE>(c, sm, lane, dbase, ce, cok);
-        else if constexpr (CLS == kClsGscB) err = wprologue_gscb<PT, CE>(c, sm, lane, dbase, ce, cok);
-        else if constexpr (CLS == kClsAfor) err = wprologue_afor<PT, CE>(c, sm, lane, dbase, ce);
-        else err = wprologue_pfd<PT>(c, sm, lane, dbase, words, ps.xs, ce[0], cok);
+    wave_lds_sync();
+}
+
+// ---- Group-Simple: one selector per data row --------------------------------
+template <int PI, int SW>
+__device__ uint32_t pack_units_sim(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t U,
+                                   uint32_t kq, const uint32_t *Tl, const uint32_t *cwl, const uint32_t *Cl,
+                                   const uint32_t *d0l) {
+    using SM = PackSmem<PI, SW>;
+    uint32_t carry = 0, nu = 0;
+    bool bad = false, cnt_bad = false, rng = false;
+    for (uint32_t g0 = 0; g0 < U; g0 += 64u) {
+        const uint32_t g = g0 + lane;
+        const bool in = g < U;
+        const uint32_t j = in ? pack_list_of(sm.ub, g) : 0u;
+        const uint32_t s = g - sm.ub[j];
+        const uint32_t Tj = Tl[j], cw = cwl[j];
+        const bool wok = (s >> 3) < Cl[j];
+        rng |= in && !wok;
+        const uint32_t sel = in && wok ? (sw[cw + (s >> 3)] >> (4u * (s & 7u))) & 15u : 15u;
+        const uint32_t num = in && sel < 10u ? sim_num(sel) : 0u;
+        const uint32_t st = seg_excl_scan(num, in && s == 0u, lane, carry);
+        const bool valid = in && st < Tj;
+        bad |= valid && sel >= 10u;
+        // the list's last selector: its selectors cover its tuples
+        if (in && g + 1u == sm.ub[j + 1u] && st + num < Tj) cnt_bad = true;
+        const uint64_t ball = __ballot(valid);
+        const uint32_t uid = nu + (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(ball >> 32),
+                                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)ball, 0u));
+        if (valid && uid < (uint32_t)SM::NU) {
+            const uint32_t t = sm.tb[j] + st;
+            sm.u.info[uid] = make_uint2(t, pack_rec(j, d0l[j] + s * kq, 0u, sim_bw(sel)));
+            sm.rec[t] = uid + 1u;
+        }
+        nu += (uint32_t)__builtin_popcountll(ball);
     }
-    // the list's rows, staged after its control words (16-byte aligned: the
-    // header and the control area are whole chunks)
-    const uint32_t kq = c.k >> 2;
-    const uint32_t nrow = c.D >> c.lk;
-    const u32x4 *rows = reinterpret_cast<const u32x4 *>(sw + 4u + C);
-    uint32_t nint = err || dbase != 0u ? 0u : c.nint;
-    if (dbase != 0u && !err) err = kErrRange;
-    if constexpr (CLS == kClsPfd) {
-        if (!err) {
-            // the exceptions follow the rows in the staged stream
-            ExcSrc &xs = ps.xs;
-            xs.lds = sw + 4u + C + D;
-            xs.staged = true;
-            uint32_t *xv = reinterpret_cast<uint32_t *>(sm.data);
-            constexpr uint32_t cap = 4u * (uint32_t)SM::NB;
-            uint32_t nx = 0;
-            err = pfd_marks<PT>(c, sm, lane, reinterpret_cast<const uint32_t *>(rows), nrow, xs, xv, cap, nx);
-            ps.xv = xv;
-            ps.in_lds = nx <= cap;
-            if (err) nint = 0u;
+    if (wave_any(rng)) return kErrRange;
+    if (wave_any(bad)) return kErrSelector;
+    if (wave_any(cnt_bad)) return kErrCount;
+    if (nu > (uint32_t)SM::NU) return kErrPack;
+    return 0;
+}
+
+// ---- Group-AFOR: frame bytes ------------------------------------------------
+template <int PI, int SW>
+__device__ uint32_t pack_units_afor(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t U,
+                                    uint32_t kq, uint32_t lk, const uint32_t *Tl, const uint32_t *cwl,
+                                    const uint32_t *Dl, const uint32_t *d0l) {
+    using SM = PackSmem<PI, SW>;
+    uint32_t c_t = 0, c_b = 0, nu = 0;
+    bool bad = false, cnt_bad = false, rng = false;
+    for (uint32_t g0 = 0; g0 < U; g0 += 64u) {
+        const uint32_t g = g0 + lane;
+        const bool in = g < U;
+        const uint32_t j = in ? pack_list_of(sm.ub, g) : 0u;
+        const uint32_t s = g - sm.ub[j];
+        const uint32_t Tj = Tl[j];
+        const uint32_t byte = in ? (sw[cwl[j] + (s >> 2)] >> (8u * (s & 3u))) & 0xFFu : 0u;
+        const uint32_t cls = byte >> 6, b = byte & 63u;
+        const bool fok = cls != 3u && b <= 32u;
+        const uint32_t F = in ? 8u << (fok ? cls : 0u) : 0u;
+        const uint32_t bb = fok ? b : 0u;
+        const bool head = in && s == 0u;
+        const uint32_t st = seg_excl_scan(F, head, lane, c_t);
+        const uint32_t fb = seg_excl_scan(F * bb, head, lane, c_b);
+        const bool valid = in && st < Tj;
+        bad |= valid && !fok;
+        rng |= valid && fb + F * bb > 32u * (Dl[j] >> lk);   // the frame's data inside the data area
+        if (in && g + 1u == sm.ub[j + 1u] && st + F < Tj) cnt_bad = true;
+        const uint64_t ball = __ballot(valid);
+        const uint32_t uid = nu + (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(ball >> 32),
+                                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)ball, 0u));
+        if (valid && uid < (uint32_t)SM::NU) {
+            const uint32_t t = sm.tb[j] + st;
+            sm.u.info[uid] = make_uint2(t | ((fb & 31u) << 16), pack_rec(j, d0l[j] + (fb >> 5) * kq, 0u, bb));
+            sm.rec[t] = uid + 1u;
+        }
+        nu += (uint32_t)__builtin_popcountll(ball);
+    }
+    if (wave_any(bad)) return kErrFrame;
+    if (wave_any(rng)) return kErrRange;
+    if (wave_any(cnt_bad)) return kErrCount;
+    if (nu > (uint32_t)SM::NU) return kErrPack;
+    return 0;
+}
+
+// ---- Group-Scheme, binary descriptors: one length field per tuple ----------
+template <int PI, int SW>
+__device__ uint32_t pack_recs_gscb(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t TT,
+                                   uint32_t kq, uint32_t lk, uint32_t cg, const uint32_t *Tl,
+                                   const uint32_t *cwl, const uint32_t *Cl, const uint32_t *Dl,
+                                   const uint32_t *d0l) {
+    const BinUnit bu = bin_unit((int)cg);
+    uint32_t carry = 0;
+    bool bad = false;
+    for (uint32_t g0 = 0; g0 < TT; g0 += 64u) {
+        const uint32_t g = g0 + lane;
+        const bool in = g < TT;
+        const uint32_t j = in ? pack_list_of(sm.tb, g) : 0u;
+        const uint32_t u = g - sm.tb[j];
+        const bool real = in && u < Tl[j];
+        const uint32_t bit = bin_field_bit(u, bu);
+        const bool wok = (bit >> 5) < Cl[j];
+        bad |= real && !wok;
+        const uint32_t word = real && wok ? sw[cwl[j] + (bit >> 5)] : 0u;
+        const uint32_t b = real && wok ? cg * (((word >> (bit & 31u)) & mask_of(bu.fb)) + 1u) : 0u;
+        const uint32_t O = seg_excl_scan(b, in && u == 0u, lane, carry);
+        bad |= real && O + b > 32u * (Dl[j] >> lk);   // the tuple's data inside the data area
+        if (in) sm.rec[g] = pack_rec_at(j, d0l[j], kq, O, b);
+    }
+    return wave_any(bad) ? kErrRange : 0u;
+}
+
+// ---- Group-Scheme, unary descriptors: every 0 bit ends one tuple's code ------
+template <int PI, int SW>
+__device__ uint32_t pack_recs_gscu(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t U,
+                                   uint32_t TT, uint32_t kq, uint32_t lk, uint32_t cg, bool iu,
+                                   const uint32_t *Tl, const uint32_t *cwl, const uint32_t *Dl,
+                                   const uint32_t *d0l) {
+    uint32_t carry = 0;
+    bool cnt_bad = false;
+    // terminator r of list j at z[tb[j] + r] (for r < the list's tuples)
+    for (uint32_t g0 = 0; g0 < U; g0 += 64u) {
+        const uint32_t g = g0 + lane;
+        const bool in = g < U;
+        const uint32_t j = in ? pack_list_of(sm.ub, g) : 0u;
+        const uint32_t s = g - sm.ub[j];
+        const uint32_t Tj = Tl[j];
+        uint32_t z = in ? ~sw[cwl[j] + s] : 0u;
+        const uint32_t cnt = (uint32_t)__builtin_popcount(z);
+        uint32_t r = seg_excl_scan(cnt, in && s == 0u, lane, carry);
+        if (in && g + 1u == sm.ub[j + 1u] && r + cnt < Tj) cnt_bad = true;
+        const uint32_t base = sm.tb[j];
+        while (z && r < Tj) {
+            sm.u.z[base + r] = (uint16_t)(32u * s + (uint32_t)__builtin_ctz(z));
+            z &= z - 1u;
+            r++;
         }
     }
-    if (err && lane == 0) latch(a.status, err);
-    if (!nint) return;
-    const bool vec = (reinterpret_cast<uintptr_t>(out) & 15u) == 0u;
-    const bool full = nint == (uint32_t)PT && vec;
-    const uint32_t tsh = c.lk - 2u;
-    if (c.h.delta) {
-        if (full) quads_lds<R, false, true, true, PATCH>(tile_recs(sm), rows, tsh, kq, nint, lane, 0u, out, vec, ps);
-        else quads_lds<R, false, false, true, PATCH>(tile_recs(sm), rows, tsh, kq, nint, lane, 0u, out, vec, ps);
-    } else {
-        if (full) quads_lds<R, false, true, false, PATCH>(tile_recs(sm), rows, tsh, kq, nint, lane, 0u, out, vec, ps);
-        else quads_lds<R, false, false, false, PATCH>(tile_recs(sm), rows, tsh, kq, nint, lane, 0u, out, vec, ps);
+    if (wave_any(cnt_bad)) return kErrCount;
+    wave_lds_sync();
+    const uint32_t umax = 32u / cg;
+    uint32_t c_u = 0;
+    bool bad = false, rng = false;
+    for (uint32_t g0 = 0; g0 < TT; g0 += 64u) {
+        const uint32_t g = g0 + lane;
+        const bool in = g < TT;
+        const uint32_t j = in ? pack_list_of(sm.tb, g) : 0u;
+        const uint32_t u = g - sm.tb[j];
+        const bool real = in && u < Tl[j];
+        const uint32_t zp = real ? (uint32_t)sm.u.z[g] : 0u;
+        const uint32_t p1 = real && u ? (uint32_t)sm.u.z[g - 1u] + 1u : 0u;   // just after the previous code
+        const uint32_t start = iu ? max(p1, zp & ~7u) : p1;
+        const uint32_t un = zp + 1u - start;
+        bad |= real && (zp < start || un > umax);
+        const uint32_t units = real ? min(un, umax) : 0u;
+        const uint32_t us = iu ? seg_excl_scan(units, in && u == 0u, lane, c_u) : 0u;
+        const uint32_t O = cg * (iu ? us : start);
+        rng |= real && O + cg * units > 32u * (Dl[j] >> lk);   // the tuple's data inside the data area
+        if (in) sm.rec[g] = pack_rec_at(j, d0l[j], kq, O, cg * units);
+    }
+    if (wave_any(bad)) return kErrUnary;
+    return wave_any(rng) ? kErrRange : 0u;
+}
+
+// ---- Group-PFD (Section 6.2): block descriptors, records, exception marks ----
+template <int PI, int SW>
+__device__ uint32_t pack_recs_pfd(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t U,
+                                  uint32_t TT, uint32_t k, uint32_t lk, bool bitmap, const uint32_t *Tl,
+                                  const uint32_t *cwl, const uint32_t *Cl, const uint32_t *Dl,
+                                  const uint32_t *Wl, const uint32_t *d0l) {
+    const uint32_t kq = k >> 2;
+    const uint32_t BI = 32u * k;
+    uint32_t c_r = 0, c_x = 0;
+    bool bad = false, rng = false;
+    for (uint32_t g0 = 0; g0 < U; g0 += 64u) {
+        const uint32_t g = g0 + lane;
+        const bool in = g < U;
+        const uint32_t j = in ? pack_list_of(sm.ub, g) : 0u;
+        const uint32_t s = g - sm.ub[j];
+        const uint32_t Cj = Cl[j], Dj = Dl[j];
+        const bool sok = s < Cj;
+        uint32_t desc = in && sok ? sw[cwl[j] + s] : 0u;
+        uint32_t b = desc & 63u;
+        const uint32_t nexc = desc >> 20, wcode = (desc >> 6) & 3u, first = (desc >> 8) & 0xFFFu;
+        if (b > 32u || nexc > BI || (nexc && !wcode) || (bitmap && first > 32u)) {
+            bad |= in;
+            desc = 0u;
+            b = 0u;
+        }
+        rng |= in && !sok;
+        const uint32_t ew = pfd_exc_words(desc, (int)k, bitmap ? 1 : 0);
+        const bool head = in && s == 0u;
+        const uint32_t rows = seg_excl_scan(b, head, lane, c_r);
+        const uint32_t xw = seg_excl_scan(ew, head, lane, c_x);
+        rng |= in && ((rows + b) << lk > Dj || 4u + Cj + Dj + xw + ew > Wl[j]);
+        if (in) {
+            const uint32_t c0 = d0l[j] + rows * kq;
+            sm.u.p.blk[g] = u32x4{desc, c0, cwl[j] + Cj + Dj + xw, j};
+            // the block's 32 tuple records (those inside the list's tuple space)
+            const uint32_t tb = sm.tb[j] + 32u * s;
+            const uint32_t nt = min(32u, sm.tb[j + 1u] - min(sm.tb[j + 1u], tb));
+            for (uint32_t tt = 0; tt < nt; tt++) sm.rec[tb + tt] = pack_rec_at(j, c0, kq, tt * b, b);
+        }
+    }
+    if (wave_any(bad)) return kErrPfdDesc;
+    if (wave_any(rng)) return kErrRange;
+    // the exception bitmap over the pack's integers
+    const uint32_t nbw = (TT << lk) >> 5;
+    for (uint32_t w = lane; w < nbw; w += 64u) sm.u.p.bmap[w] = 0u;
+    wave_lds_sync();
+    bool chain_bad = false;
+    for (uint32_t g = lane; g < U; g += 64u) {
+        const u32x4 bk = sm.u.p.blk[g];
+        const uint32_t desc = bk.x, c0 = bk.y, xb = bk.z, j = bk.w;
+        const uint32_t s = g - sm.ub[j];
+        const uint32_t nexc = desc >> 20, b = desc & 63u, M = mask_of(b);
+        const uint32_t real_t = Tl[j] - 32u * s;                 // real tuples of the block (> 0)
+        const uint32_t ibase = (sm.tb[j] + 32u * s) << lk;       // its first integer in the pack
+        if (!nexc) continue;
+        if (!bitmap) {
+            uint32_t p = (desc >> 8) & 0xFFFu;
+            for (uint32_t e = 0; e < nexc; e++) {
+                if (p >= BI || (p >> lk) >= real_t) {
+                    chain_bad = true;
+                    break;
+                }
+                const uint32_t q = ibase + p;
+                atomicOr(&sm.u.p.bmap[q >> 5], 1u << (q & 31u));
+                const uint32_t O = (p >> lk) * b, c = p & (k - 1u);
+                const uint32_t at = 4u * (c0 + (O >> 5) * kq) + c;
+                const uint32_t slot = b ? funnel(sw[at + k], sw[at], O & 31u) & M : 0u;
+                p = slot < BI ? p + slot + 1u : BI;
+            }
+        } else {
+            const uint32_t tm = sw[xb];
+            if ((uint32_t)__builtin_popcount(tm) != ((desc >> 8) & 0xFFFu) || (real_t < 32u && (tm >> real_t))) {
+                chain_bad = true;
+                continue;
+            }
+            uint32_t m = tm, r = 0;
+            while (m) {
+                const uint32_t t = (uint32_t)__builtin_ctz(m);
+                m &= m - 1u;
+                const uint32_t bit = r * k, q = ibase + t * k;
+                if (k < 32u) {
+                    const uint32_t cm = (sw[xb + 1u + (bit >> 5)] >> (bit & 31u)) & mask_of(k);
+                    atomicOr(&sm.u.p.bmap[q >> 5], cm << (q & 31u));
+                } else {
+                    for (uint32_t h = 0; h < (k >> 5); h++) sm.u.p.bmap[(q >> 5) + h] = sw[xb + 1u + (bit >> 5) + h];
+                }
+                r++;
+            }
+        }
+    }
+    if (wave_any(chain_bad)) return bitmap ? kErrBitmap : kErrPfdChain;
+    wave_lds_sync();
+    // exceptions before every bitmap word, pack-wide
+    uint32_t run = 0;
+    for (uint32_t w0 = 0; w0 < nbw; w0 += 64u) {
+        const uint32_t w = w0 + lane;
+        const uint32_t c = w < nbw ? (uint32_t)__builtin_popcount(sm.u.p.bmap[w]) : 0u;
+        const uint32_t inc = wave_incl_scan(c);
+        if (w < nbw) sm.u.p.xcnt[w] = run + inc - c;
+        run += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+    }
+    wave_lds_sync();
+    // per word: bit offset (in the staging buffer) of its first exception
+    // value | width code; every block marks exactly its exception count
+    bool cbad = false;
+    for (uint32_t w = lane; w < nbw; w += 64u) {
+        const uint32_t t = (32u * w) >> lk;
+        const uint32_t j = (sm.rec[t] >> 23) & (kPackLists - 1u);
+        const uint32_t u = t - sm.tb[j];
+        uint32_t vb = 0;
+        if (u < Tl[j]) {
+            const uint32_t s = u >> 5;
+            const u32x4 bk = sm.u.p.blk[sm.ub[j] + s];
+            const uint32_t desc = bk.x, nexc = desc >> 20, wcode = (desc >> 6) & 3u;
+            const uint32_t wfirst = ((sm.tb[j] + 32u * s) << lk) >> 5;
+            const uint32_t nreal = min(32u, Tl[j] - 32u * s);
+            const uint32_t wend = (((sm.tb[j] + 32u * s) << lk) + (nreal << lk) + 31u) >> 5;
+            const uint32_t before = sm.u.p.xcnt[w] - sm.u.p.xcnt[wfirst];
+            const uint32_t v0 = bitmap ? bk.z + 1u + ((((desc >> 8) & 0xFFFu) * k + 31u) >> 5) : bk.z;
+            vb = ((32u * v0 + before * (4u << wcode)) << 2) | wcode;
+            if (w + 1u == wend && before + (uint32_t)__builtin_popcount(sm.u.p.bmap[w]) != nexc) cbad = true;
+        }
+        sm.u.p.vbit[w] = vb;
+    }
+    if (wave_any(cbad)) return bitmap ? kErrBitmap : kErrPfdChain;
+    wave_lds_sync();
+    return 0;
+}
+
+// The pack's quads, 64 per round: lane l takes quad r * 64 + l of the pack
+// (tuple q >> tsh, component quad q mod k/4).
+template <bool PATCH, int PI, int SW>
+__device__ __forceinline__ void pack_unpack(PackSmem<PI, SW> &sm, uint32_t lane, uint32_t NQ, uint32_t tsh,
+                                            uint32_t kq, uint32_t lk, const PatchSrc &ps) {
+    uint32_t carry = 0;
+    for (uint32_t g0 = 0; g0 < NQ; g0 += 64u) {
+        const uint32_t q = g0 + lane;
+        const bool in = q < NQ;
+        const uint32_t t = q >> tsh, cq = q & (kq - 1u);
+        const uint32_t rc = in ? sm.rec[t] : 0u;
+        const u32x4 L = sm.lst[(rc >> 23) & (kPackLists - 1u)];
+        const uint32_t li = ((t - (L.x & 0x7FFFFFFFu)) << lk) + 4u * cq;   // the quad's first integer in its list
+        const bool valid = in && li < L.y;
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (valid) {
+            const uint32_t c = (rc >> 11) & 0xFFFu, sh = (rc >> 6) & 31u, bw = rc & 63u;
+            const u32x4 lo = sm.stage[c + cq], hi = sm.stage[c + kq + cq];
+            const uint32_t M = (uint32_t)(0xFFFFFFFFull >> (32u - bw));
+            v.x = funnel(hi.x, lo.x, sh) & M;
+            v.y = funnel(hi.y, lo.y, sh) & M;
+            v.z = funnel(hi.z, lo.z, sh) & M;
+            v.w = funnel(hi.w, lo.w, sh) & M;
+            if constexpr (PATCH) pfd_patch(v, q, ps);
+        }
+        const bool delta = valid && (L.x >> 31);
+        if (wave_any(delta)) {
+            if (delta) {
+                v.y += v.x;
+                v.z += v.y;
+                v.w += v.z;
+            }
+            const uint32_t e = seg_excl_scan(delta ? v.w : 0u, valid && li == 0u, lane, carry);
+            if (delta) v += e;
+        } else {
+            carry = 0u;   // no docID list continues into the next round
+        }
+        if (valid) {
+            uint32_t *out = reinterpret_cast<uint32_t *>(((uint64_t)L.w << 32) | L.z) + li;
+            const uint32_t n = L.y;
+            if ((L.z & 15u) == 0u && li + 4u <= n) {
+                __builtin_nontemporal_store(v, (gu32x4 *)out);
+            } else {
+                out[0] = v.x;
+                if (li + 1u < n) out[1] = v.y;
+                if (li + 2u < n) out[2] = v.z;
+                if (li + 3u < n) out[3] = v.w;
+            }
+        }
     }
 }
 
-template <int PT, int SBC>
+template <int PI, int SW>
 __global__ __launch_bounds__(kThreads) void gc_pack_kernel(PackArgs a) {
-    __shared__ PackSmem<PT, SBC> smem[kWaves];
+    using SM = PackSmem<PI, SW>;
+    __shared__ SM smem[kWaves];
     const uint32_t wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63u;
     const uint32_t p = blockIdx.x * (uint32_t)kWaves + wave;
     if (p >= a.npacks) return;
-    PackSmem<PT, SBC> &sm = smem[wave];
+    SM &sm = smem[wave];
     const uint32_t f0 = ((const gu32 *)a.first)[p], f1 = ((const gu32 *)a.first)[p + 1u];
-    const uint32_t np = min(f1 - f0, 64u);
+    const uint32_t np = f1 - f0;
+    if (np == 0u || np > kPackLists) {
+        if (lane == 0) latch(a.status, kErrPack);
+        return;
+    }
     // lane j: list j's descriptor
     union {
         u32x4 v[2];
         PackDesc d;
-    } u;
-    u.v[0] = u32x4{0u, 0u, 0u, 0u};
-    u.v[1] = u32x4{0u, 0u, 0u, 0u};
-    if (lane < np) {
+    } ud;
+    ud.v[0] = u32x4{0u, 0u, 0u, 0u};
+    ud.v[1] = u32x4{0u, 0u, 0u, 0u};
+    const bool mine = lane < np;
+    if (mine) {
         const gu32x4 *g = (const gu32x4 *)(a.descs + f0 + lane);
-        u.v[0] = g[0];
-        u.v[1] = g[1];
+        ud.v[0] = g[0];
+        ud.v[1] = g[1];
     }
-    const PackDesc d = u.d;
-    const uint32_t ch = d.words >> 2;
-    const uint32_t inc = wave_incl_scan(ch);
-    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
-    if (f1 - f0 > 64u || total > (uint32_t)SBC) {
+    const PackDesc d = ud.d;
+    // every list of a pack has the stream format of the first (delta aside)
+    const uint32_t w0 = uniform(d.w0) & ~(1u << 19);
+    HeaderFields h;
+    const bool hok = header_fields(w0, h);
+    const uint32_t C = d.cd & 0xFFFFu, D = d.cd >> 16;
+    const bool same = !mine || (d.w0 & ~(1u << 19)) == w0;
+    const uint32_t k = (uint32_t)h.k, lk = (uint32_t)h.lk, kq = k >> 2;
+    const uint32_t T = mine ? (d.n + k - 1u) >> lk : 0u;
+    const uint32_t tpu = lk >= 5u ? 1u : 32u >> lk;   // tuples per 32 integers
+    const uint32_t Tp = (T + tpu - 1u) & ~(tpu - 1u);
+    const uint32_t ch = mine ? d.words >> 2 : 0u;
+    const bool dok = !mine || (d.n >= 1u && (d.words & 3u) == 0u && (C & 3u) == 0u && 4u + C + D <= d.words &&
+                               (D & (k - 1u)) == 0u);
+    const int cls = hok ? (h.codec == 0 ? kClsSim : h.codec == 1 ? (h.ld == GC_LD_BINARY ? kClsGscB : kClsGscU)
+                                        : h.codec == 2 ? kClsAfor : kClsPfd) : -1;
+    // control units of the list
+    const uint32_t units = !mine ? 0u
+                         : cls == kClsSim  ? D >> lk
+                         : cls == kClsAfor ? 4u * C
+                         : cls == kClsGscU ? C
+                         : cls == kClsPfd  ? (T + 31u) >> 5
+                                           : 0u;
+    const uint32_t i_ch = wave_incl_scan(ch), i_t = wave_incl_scan(Tp), i_u = wave_incl_scan(units);
+    const uint32_t tot_ch = (uint32_t)__builtin_amdgcn_readlane((int)i_ch, 63);
+    const uint32_t TT = (uint32_t)__builtin_amdgcn_readlane((int)i_t, 63);
+    const uint32_t U = (uint32_t)__builtin_amdgcn_readlane((int)i_u, 63);
+    if (wave_any(!same || !dok) || !hok || cls < 0) {
+        if (lane == 0) latch(a.status, kErrHeader);
+        return;
+    }
+    // a list with tuples but no control units (Group-Simple, unary
+    // Group-Scheme, Group-AFOR) would leave its tuples unclaimed
+    if (wave_any(mine && T && !units && cls != kClsGscB)) {
+        if (lane == 0) latch(a.status, kErrCount);
+        return;
+    }
+    if (tot_ch > (uint32_t)SW / 4u || TT > (uint32_t)SM::TUP || (TT << lk) > (uint32_t)PI ||
+        (cls == kClsPfd && U > (uint32_t)SM::NBLK)) {
         if (lane == 0) latch(a.status, kErrPack);
         return;
     }
-    sm.soff[lane] = lane < np ? inc - ch : total;
+    const uint32_t so = i_ch - ch, tbase = i_t - Tp;
+    sm.so[lane] = mine ? so : tot_ch;
+    sm.tb[lane] = mine ? tbase : TT;
+    sm.ub[lane] = mine ? i_u - units : U;
+    if (lane == 0) {
+        sm.so[64] = tot_ch;
+        sm.tb[64] = TT;
+        sm.ub[64] = U;
+    }
+    // (lanes past the pack's lists: no integers, so nothing is ever stored for them)
+    const uint64_t op = reinterpret_cast<uint64_t>(d.out);
+    sm.lst[lane] = mine ? u32x4{tbase | ((d.w0 >> 19) & 1u) << 31, d.n, (uint32_t)op, (uint32_t)(op >> 32)}
+                        : u32x4{0u, 0u, 0u, 0u};
     wave_lds_sync();
     // the pack's streams, chunk c to stage[c]: the list of a chunk by binary
     // search over the offsets, its stream pointer from that list's lane;
     // four 16-byte loads per lane in flight
     const uint64_t sp = reinterpret_cast<uint64_t>(d.stream);
-    constexpr int RNDS = (SBC + 63) / 64;
+    constexpr int RNDS = (SW / 4 + 63) / 64;
     constexpr int BATCH = RNDS < 4 ? RNDS : 4;
 #pragma unroll
     for (int r0 = 0; r0 < RNDS; r0 += BATCH) {
-        if ((uint32_t)r0 * 64u >= total) break;
+        if ((uint32_t)r0 * 64u >= tot_ch) break;
         u32x4 t[BATCH];
 #pragma unroll
         for (int b = 0; b < BATCH; b++) {
             const uint32_t cidx = (uint32_t)(r0 + b) * 64u + lane;
-            uint32_t j = 0;
-#pragma unroll
-            for (uint32_t step = 32u; step; step >>= 1)
-                j = sm.soff[j + step] <= cidx ? j + step : j;
+            const uint32_t j = pack_list_of(sm.so, cidx);
             const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)sp, (int)j);
             const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(sp >> 32), (int)j);
             const gu32x4 *src = reinterpret_cast<const gu32x4 *>(((uint64_t)hi << 32) | lo);
-            if (cidx < total) t[b] = src[cidx - sm.soff[j]];
+            if (cidx < tot_ch) t[b] = src[cidx - sm.so[j]];
         }
 #pragma unroll
         for (int b = 0; b < BATCH; b++) {
             const uint32_t cidx = (uint32_t)(r0 + b) * 64u + lane;
-            if (cidx < total) sm.stage[cidx] = t[b];
+            if (cidx < tot_ch) sm.stage[cidx] = t[b];
         }
     }
     wave_lds_sync();
-    const uint32_t *stage = reinterpret_cast<const uint32_t *>(sm.stage);
-    for (uint32_t j = 0; j < np; j++) {
-        const uint32_t so = uniform(sm.soff[j]);
-        const uint64_t spj = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(sp >> 32), (int)j) << 32) |
-                             (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sp, (int)j);
-        const uint64_t op = reinterpret_cast<uint64_t>(d.out);
-        const uint64_t opj = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(op >> 32), (int)j) << 32) |
-                             (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)op, (int)j);
-        const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)d.n, (int)j);
-        const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)d.w0, (int)j);
-        const uint32_t cd = (uint32_t)__builtin_amdgcn_readlane((int)d.cd, (int)j);
-        const uint32_t words = (uint32_t)__builtin_amdgcn_readlane((int)d.words, (int)j);
-        const uint32_t *S = reinterpret_cast<const uint32_t *>(spj);
-        uint32_t *out = reinterpret_cast<uint32_t *>(opj);
-        const uint32_t *sw = stage + 4u * so;
-        const uint32_t C = cd & 0xFFFFu, D = cd >> 16;
-        switch (codec_class_dev(w0)) {
-        case kClsSim: pack_list<PT, kClsSim, SBC>(a, sm.u.sim, sw, S, out, n, w0, C, D, words, lane); break;
-        case kClsGscU: pack_list<PT, kClsGscU, SBC>(a, sm.u.gscu, sw, S, out, n, w0, C, D, words, lane); break;
-        case kClsGscB: pack_list<PT, kClsGscB, SBC>(a, sm.u.gscb, sw, S, out, n, w0, C, D, words, lane); break;
-        case kClsAfor: pack_list<PT, kClsAfor, SBC>(a, sm.u.afor, sw, S, out, n, w0, C, D, words, lane); break;
-        case kClsPfd: pack_list<PT, kClsPfd, SBC>(a, sm.u.pfd, sw, S, out, n, w0, C, D, words, lane); break;
-        default:
-            if (lane == 0) latch(a.status, kErrHeader);
-            break;
-        }
-        // the next list's prologue rewrites what this one's unpack read
+    const uint32_t *sw = reinterpret_cast<const uint32_t *>(sm.stage);
+    // every list's staged header against its descriptor
+    const uint32_t cwo = 4u * so + 4u;   // stage word of the control area
+    bool hbad = false;
+    if (mine) hbad = sw[4u * so] != d.w0 || sw[4u * so + 1u] != d.n || sw[4u * so + 2u] != C || sw[4u * so + 3u] != D;
+    if (wave_any(hbad)) {
+        if (lane == 0) latch(a.status, kErrHeader);
+        return;
+    }
+    // per-list values for the record builders
+    uint32_t *Tl = sm.lt[0], *cwl = sm.lt[1], *Cl = sm.lt[2], *Dl = sm.lt[3], *Wl = sm.lt[4], *d0l = sm.lt[5];
+    Tl[lane] = T;
+    cwl[lane] = cwo;
+    Cl[lane] = C;
+    Dl[lane] = D;
+    Wl[lane] = mine ? d.words : 0u;
+    d0l[lane] = so + 1u + (C >> 2);   // chunk of the data area
+    wave_lds_sync();
+    uint32_t err = 0;
+    if (cls == kClsSim || cls == kClsAfor) {
+        for (uint32_t t = lane; t < (uint32_t)SM::TUP; t += 64u) sm.rec[t] = 0u;
         wave_lds_sync();
+        err = cls == kClsSim ? pack_units_sim(sm, sw, lane, U, kq, Tl, cwl, Cl, d0l)
+                             : pack_units_afor(sm, sw, lane, U, kq, lk, Tl, cwl, Dl, d0l);
+        wave_lds_sync();
+        if (!err) pack_expand(sm, lane, kq);
+    } else if (cls == kClsGscB) {
+        err = pack_recs_gscb(sm, sw, lane, TT, kq, lk, (uint32_t)h.cg, Tl, cwl, Cl, Dl, d0l);
+    } else if (cls == kClsGscU) {
+        err = pack_recs_gscu(sm, sw, lane, U, TT, kq, lk, (uint32_t)h.cg, h.ld == GC_LD_IU, Tl, cwl, Dl, d0l);
+    } else {
+        err = pack_recs_pfd(sm, sw, lane, U, TT, k, lk, h.pfd_pos != 0, Tl, cwl, Cl, Dl, Wl, d0l);
+    }
+    if (err) {
+        if (lane == 0) latch(a.status, err);
+        return;
+    }
+    wave_lds_sync();
+    const uint32_t NQ = TT * kq;
+    if (cls == kClsPfd) {
+        PatchSrc ps{sm.u.p.bmap, sm.u.p.vbit, sm.u.p.xcnt, nullptr, ExcSrc{sw, nullptr, (uint32_t)SW, true}, false};
+        pack_unpack<true>(sm, lane, NQ, lk - 2u, kq, lk, ps);
+    } else {
+        PatchSrc ps{nullptr, nullptr, nullptr, nullptr, ExcSrc{nullptr, nullptr, 0u, false}, false};
+        pack_unpack<false>(sm, lane, NQ, lk - 2u, kq, lk, ps);
     }
 }
 
@@ -2071,13 +2460,13 @@ static const void *decode_fn(int tile, int cls) {
     }
 }
 
-// Launches the pack kernel of tile size pt (1024 or 2048) over a.npacks
-// packs.
-int launch_pack(int pt, const PackArgs &a, hipStream_t s) {
+// Launches the pack kernel of capacity pi integers (2048 or 4096) over
+// a.npacks packs.
+int launch_pack(int pi, const PackArgs &a, hipStream_t s) {
     if (!a.npacks) return 0;
     const dim3 grid((a.npacks + kWaves - 1) / kWaves);
-    if (pt == 1024) hipLaunchKernelGGL((gc_pack_kernel<1024, kPackChunks>), grid, dim3(kThreads), 0, s, a);
-    else if (pt == 2048) hipLaunchKernelGGL((gc_pack_kernel<2048, kPackChunks>), grid, dim3(kThreads), 0, s, a);
+    if (pi == 2048) hipLaunchKernelGGL((gc_pack_kernel<2048, 512>), grid, dim3(kThreads), 0, s, a);
+    else if (pi == 4096) hipLaunchKernelGGL((gc_pack_kernel<4096, 1024>), grid, dim3(kThreads), 0, s, a);
     else return -2;
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

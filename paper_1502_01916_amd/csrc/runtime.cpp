@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <map>
 #include <mutex>
 #include <new>
 #include <sstream>
@@ -244,7 +245,7 @@ struct ClassRange {
     uint32_t scans = 0;     // lists to scan
 };
 
-// The packs of one pack kernel (tile size kPackTiles[i]): descriptors in
+// The packs of one pack kernel (capacity kPackInts[i]): descriptors in
 // pack order, the list of each, and every pack's first descriptor.
 struct PackSet {
     std::vector<PackDesc> h;       // pointers filled at upload
@@ -281,23 +282,26 @@ struct gc_plan {
     uint32_t lb_stall = 0;                     // tests only: see GC_TEST_LOOKBACK_STALL
     uint32_t slots = 0;
     uint64_t runs = 0;
-    // lists of at most pack_max integers (one tile) whose streams fit a
-    // pack's staging buffer are decoded by the pack kernels instead of the
-    // class passes; 0: none
+    // lists of at most pack_max integers whose streams fit a pack are
+    // decoded by the pack kernel instead of the class passes; 0: none
     uint32_t pack_max = 0;
     bool pack_forced = false;                  // pack_max set by the plan options
     std::vector<uint8_t> packed;               // per list
-    PackSet pk[2];                             // pack kernels of 1024- and 2048-integer tiles
+    PackSet pk[2];                             // packs of the kernel of capacity kPackInts[0] / [1] (one is used)
     uint32_t total_chunks = 0;                 // locate chunks of every list (batch items first)
 };
 
 namespace {
 
-constexpr int kPackTiles[2] = {1024, 2048};
-// Default pack_max: every list of one 2048-integer tile.
+// The pack kernels: integers of tuple space and staged stream words per
+// pack; a plan uses the smaller one when its threshold allows.
+constexpr uint32_t kPackInts[2] = {2048u, 4096u};
+constexpr uint32_t kPackWords[2] = {512u, 1024u};
+// Default pack_max: lists of up to 2048 integers.
 constexpr uint32_t kDefaultPackMax = 2048u;
 constexpr uint32_t kPackOff = 0x80000000u;
 constexpr uint32_t kPackMaxLists = 64u;
+int pack_cfg(uint32_t pack_max) { return pack_max <= kPackInts[0] ? 0 : 1; }
 
 LocateArgs make_locate_args(const ListDesc *lists, const uint32_t *item_list, const uint32_t *scan_list,
                             const ListDesc &single, uint32_t total, uint32_t total_scan, int cls, Scratch &sc,
@@ -397,18 +401,22 @@ gc_status launch_one(const ListDesc &L, int cls, Scratch &sc, Status *st, hipStr
     return GC_OK;
 }
 
-// The pack kernel (index into kPackTiles) that decodes list L, or -1 when
-// it takes the class passes: a list of 1 .. pack_max integers in one tile
-// of its pack kernel (2048 integers for the 64-way layout, whose blocks are
-// that long; 1024 otherwise when it fits) whose whole stream fits the
-// staging buffer.
-int pack_kind(const ListDesc &L, uint32_t pack_max) {
-    if (L.n == 0 || L.n > pack_max || L.n > (uint32_t)kPackTiles[1]) return -1;
-    if (L.stream_words > 4ull * (uint64_t)kPackChunks || (L.stream_words & 3u)) return -1;
+// Tuples of list L in a pack's tuple space (its first at a multiple of
+// 32 / k tuples, so every list starts at a 32-integer boundary).
+uint32_t pack_tuples(const ListDesc &L, const HeaderFields &h) {
+    const uint32_t T = (L.n + (uint32_t)h.k - 1u) >> h.lk;
+    const uint32_t u = h.lk >= 5 ? 1u : 32u >> h.lk;
+    return (T + u - 1u) & ~(u - 1u);
+}
+
+// Whether list L goes to the pack kernel of configuration cfg: 1 ..
+// pack_max integers, its padded tuples and its stream within one pack.
+bool pack_fits(const ListDesc &L, uint32_t pack_max, int cfg) {
+    if (L.n == 0 || L.n > pack_max) return false;
     HeaderFields h;
-    if (!header_fields(L.w0, h)) return -1;
-    const uint32_t need = std::max<uint32_t>(L.n, 32u << h.lk);
-    return need <= (uint32_t)kPackTiles[0] ? 0 : need <= (uint32_t)kPackTiles[1] ? 1 : -1;
+    if (!header_fields(L.w0, h)) return false;
+    if (L.stream_words > kPackWords[cfg] || (L.stream_words & 3u) || (L.C & 3u)) return false;
+    return ((uint64_t)pack_tuples(L, h) << h.lk) <= kPackInts[cfg];
 }
 
 // Builds the tile tables of a plan for its tile sizes.
@@ -424,7 +432,6 @@ void build_tables(gc_plan *p) {
         ps.list.clear();
         ps.first.clear();
     }
-    uint32_t pack_words[2] = {0, 0};
     for (size_t i = 0; i < p->nlists; i++) {
         ListDesc &L = p->h_lists[i];
         L.tile_ints = (uint32_t)p->tile[p->cls[i]];
@@ -436,35 +443,51 @@ void build_tables(gc_plan *p) {
             L.nchunks = list_chunks(h, L.n, L.C, L.D, kChunkWords);
         }
     }
-    // Packs: consecutive packed lists, class by class, while they fit the
-    // staging buffer and number at most 64.
-    for (int c = 0; c < kClasses; c++) {
+    // Packs: lists of one stream format (header word 0 without its delta
+    // bit), in list order, while they number at most 64 and their streams
+    // and padded tuple spaces fit the kernel's buffers.
+    if (p->pack_max) {
+        const int cfg = pack_cfg(p->pack_max);
+        PackSet &ps = p->pk[cfg];
+        std::map<uint32_t, std::vector<uint32_t>> by_fmt;
+        std::vector<uint32_t> order;   // formats in order of first appearance
         for (size_t i = 0; i < p->nlists; i++) {
-            if (p->cls[i] != c) continue;
             const ListDesc &L = p->h_lists[i];
-            const int kind = pack_kind(L, p->pack_max);
-            if (kind < 0) continue;
-            PackSet &ps = p->pk[kind];
-            const uint32_t w = (uint32_t)L.stream_words;
-            if (ps.first.empty() || (uint32_t)ps.h.size() - ps.first.back() >= kPackMaxLists ||
-                pack_words[kind] + w > 4u * (uint32_t)kPackChunks) {
-                ps.first.push_back((uint32_t)ps.h.size());
-                pack_words[kind] = 0;
-            }
-            PackDesc d;
-            std::memset(&d, 0, sizeof(d));
-            d.n = L.n;
-            d.w0 = L.w0;
-            d.cd = L.C | (L.D << 16);
-            d.words = w;
-            ps.h.push_back(d);
-            ps.list.push_back((uint32_t)i);
-            pack_words[kind] += w;
-            p->packed[i] = 1;
+            if (!pack_fits(L, p->pack_max, cfg)) continue;
+            const uint32_t f = L.w0 & ~(1u << 19);
+            auto &v = by_fmt[f];
+            if (v.empty()) order.push_back(f);
+            v.push_back((uint32_t)i);
         }
-    }
-    for (PackSet &ps : p->pk)
+        for (uint32_t f : order) {
+            uint32_t words = 0, ints = 0;
+            bool fresh = true;   // the format's first list opens a pack
+            for (uint32_t i : by_fmt[f]) {
+                const ListDesc &L = p->h_lists[i];
+                HeaderFields h;
+                header_fields(L.w0, h);
+                const uint32_t w = (uint32_t)L.stream_words, pi = pack_tuples(L, h) << h.lk;
+                if (fresh || (uint32_t)ps.h.size() - ps.first.back() >= kPackMaxLists ||
+                    words + w > kPackWords[cfg] || ints + pi > kPackInts[cfg]) {
+                    fresh = false;
+                    ps.first.push_back((uint32_t)ps.h.size());
+                    words = ints = 0;
+                }
+                PackDesc d;
+                std::memset(&d, 0, sizeof(d));
+                d.n = L.n;
+                d.w0 = L.w0;
+                d.cd = L.C | (L.D << 16);
+                d.words = w;
+                ps.h.push_back(d);
+                ps.list.push_back(i);
+                words += w;
+                ints += pi;
+                p->packed[i] = 1;
+            }
+        }
         if (!ps.first.empty()) ps.first.push_back((uint32_t)ps.h.size());
+    }
     // Locate items, tiles and carry scans are numbered class by class, so
     // each class's kernels cover one range of each table.  Within a class
     // the delta lists of more than one tile come first.  Packed lists come
@@ -674,7 +697,7 @@ gc_status launch_packs(gc_plan *p, hipStream_t s) {
         a.first = ps.d_first;
         a.npacks = ps.packs();
         a.status = p->ctx->status;
-        if (launch_pack(kPackTiles[k], a, s)) return GC_EDEVICE;
+        if (launch_pack((int)kPackInts[k], a, s)) return GC_EDEVICE;
     }
     return GC_OK;
 }
@@ -795,7 +818,7 @@ bool cache_lookup(const std::string &key, int *tiles, uint32_t *pack_max) {
         return false;
     for (int c = 0; c < kClasses; c++)   // an entry that fails validation falls back to the defaults
         if (!valid_wave_tile((uint32_t)t[c])) return false;
-    if (pm > (uint32_t)kPackTiles[1]) return false;
+    if (pm > kPackInts[1]) return false;
     for (int c = 0; c < kClasses; c++) tiles[c] = t[c];
     *pack_max = pm;
     return true;
@@ -850,9 +873,9 @@ std::string plan_key(const gc_plan *p) {
     int lm = 0;
     while ((1ull << lm) < mean) lm++;
     // short lists decide the pack kernels' share: the fraction (in eighths)
-    // of lists of one 2048-integer tile
+    // of lists of at most 2048 integers
     uint64_t short_lists = 0;
-    for (size_t i = 0; i < p->nlists; i++) short_lists += p->h_lists[i].n <= (uint32_t)kPackTiles[1];
+    for (size_t i = 0; i < p->nlists; i++) short_lists += p->h_lists[i].n <= kPackInts[0];
     std::string key = p->ctx->arch + ":k" + std::to_string(1 << lk) + ":n2^" + std::to_string(lg) + ":mean2^" +
                       std::to_string(lm) + ":c" + std::to_string(p->lb_max) + ":s" +
                       std::to_string(p->nlists ? short_lists * 8 / p->nlists : 0) +
@@ -863,8 +886,8 @@ std::string plan_key(const gc_plan *p) {
 }
 
 // Times the candidates and keeps the fastest: first the packed-list
-// threshold (no packing, lists of up to 1024 or 2048 integers; unless the
-// plan fixes it), by the whole run at the default tile sizes; then, for
+// threshold (no packing, lists of up to 1024, 2048 or 4096 integers; unless
+// the plan fixes it), by the whole run at the default tile sizes; then, for
 // every codec class, the tile size whose passes (tile sums, carry scan,
 // decode) took least: one materialised plan per candidate, each class timed
 // by HIP events around its own passes (a class's passes do not depend on
@@ -886,9 +909,9 @@ gc_status autotune(gc_plan *p, const uint32_t *d_streams, uint32_t *d_out) {
     for (hipEvent_t &e : ev)
         if (hipEventCreate(&e) != hipSuccess) rc = GC_EDEVICE;
     if (!p->pack_forced) {
-        const uint32_t cand[3] = {0u, (uint32_t)kPackTiles[0], (uint32_t)kPackTiles[1]};
+        const uint32_t cand[4] = {0u, 1024u, kPackInts[0], kPackInts[1]};
         float best_ms = 1e30f;
-        for (int i = 0; i < 3 && !rc; i++) {
+        for (int i = 0; i < 4 && !rc; i++) {
             p->pack_max = cand[i];
             rc = plan_materialize(p);
             if (!rc) rc = plan_upload(p, d_streams, d_out);
@@ -1113,7 +1136,7 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
         forced = forced || t;
     }
     if (o.schedule > 1u || o.carry_pass > 3u) return GC_EINVAL;
-    if (o.pack_ints && o.pack_ints != GC_PACK_OFF && o.pack_ints > (uint32_t)kPackTiles[1]) return GC_EINVAL;
+    if (o.pack_ints && o.pack_ints != GC_PACK_OFF && o.pack_ints > kPackInts[1]) return GC_EINVAL;
     if ((o.autotune || o.use_graph) && nlists && (!d_streams || !d_out)) return GC_EINVAL;
     gc_plan *p = new (std::nothrow) gc_plan();
     if (!p) return GC_ENOMEM;
@@ -1275,6 +1298,12 @@ gc_status gc_plan_pack_config(const gc_plan *plan, uint32_t *pack_ints, uint64_t
     if (pack_ints) *pack_ints = plan->pack_max;
     if (packs) *packs = np;
     if (packed_lists) *packed_lists = nl;
+    return GC_OK;
+}
+
+gc_status gc_plan_packed_lists(const gc_plan *plan, uint8_t *h_packed, size_t nlists) {
+    if (!plan || !h_packed || nlists != plan->nlists) return GC_EINVAL;
+    for (size_t i = 0; i < nlists; i++) h_packed[i] = i < plan->packed.size() ? plan->packed[i] : 0u;
     return GC_OK;
 }
 

@@ -123,6 +123,7 @@ def lib():
         L.gc_plan_config.argtypes = [vp, u32p, u32p, u64p, u64p]
         L.gc_plan_class_tiles.argtypes = [vp, u32p]
         L.gc_plan_pack_config.argtypes = [vp, u32p, u64p, u64p]
+        L.gc_plan_packed_lists.argtypes = [vp, vp, sz]
         L.gc_plan_timings.argtypes = [vp, ctypes.c_uint32, f32p, u32p]
         L.gc_plan_timings.restype = ctypes.c_int
         L.gc_sync_status.argtypes = [vp, vp, u32p]
@@ -145,7 +146,8 @@ def lib():
         for f in ("gc_encode", "gc_encode_lists", "gc_ctx_create", "gc_ctx_create_opts", "gc_ctx_destroy",
                   "gc_decode", "gc_decode_noalloc",
                   "gc_plan_create", "gc_plan_destroy", "gc_decode_batch", "gc_decode_each",
-                  "gc_plan_config", "gc_plan_class_tiles", "gc_plan_pack_config", "gc_sync_status", "gc_block_features",
+                  "gc_plan_config", "gc_plan_class_tiles", "gc_plan_pack_config", "gc_plan_packed_lists",
+                  "gc_sync_status", "gc_block_features",
                   "gc_block_sizes", "gc_blockmix_encode", "gc_mlp_create", "gc_mlp_destroy", "gc_mlp_set_params",
                   "gc_mlp_get_params", "gc_mlp_forward", "gc_mlp_grad", "gc_mlp_train", "gc_encode_blocks",
                   "gc_mlp_get_state", "gc_mlp_set_state"):
@@ -360,6 +362,14 @@ class Plan:
         return dict(tile_ints=t.value, pfd_tile_ints=pt.value, tiles=n.value, sum_tiles=ns.value,
                     class_tiles=[int(x) for x in ct], pack_ints=pi.value, packs=npk.value,
                     packed_lists=npl.value)
+
+    def packed_lists(self, nlists):
+        """gc_plan_packed_lists: a bool array, True for the lists the pack
+        kernel decodes."""
+        out = np.zeros(int(nlists), dtype=np.uint8)
+        _check("gc_plan_packed_lists", lib().gc_plan_packed_lists(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                                                  int(nlists)))
+        return out.astype(bool)
 
     def close(self):
         if self._h:

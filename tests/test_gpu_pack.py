@@ -168,8 +168,8 @@ def test_pack_incompressible_lists(torch_cuda, ctx):
 
 
 def test_pack_autotuned(torch_cuda, ctx, tmp_path, monkeypatch):
-    """The autotuner chooses a threshold among none, 1024 and 2048 (cached
-    with the tile sizes); the plan decodes exactly."""
+    """The autotuner chooses a threshold among none, 1024, 2048 and 4096
+    (cached with the tile sizes); the plan decodes exactly."""
     torch = torch_cuda
     monkeypatch.setenv("GC_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
     rng = np.random.default_rng(8500)
@@ -181,7 +181,7 @@ def test_pack_autotuned(torch_cuda, ctx, tmp_path, monkeypatch):
     plan = gc.Plan(ctx, descs, headers, d_s, d_o, autotune=True, use_graph=True)
     cfg = plan.config()
     say("autotuned pack", cfg)
-    assert cfg["pack_ints"] in (0, 1024, 2048)
+    assert cfg["pack_ints"] in (0, 1024, 2048, 4096)
     plan.decode_batch(d_s, d_o)
     rc, det = ctx.sync_status()
     assert rc == gc.OK, det
