@@ -217,6 +217,9 @@ typedef struct {
                                 k and codec parameters; docID and TF lists
                                 mix); GC_PACK_OFF: none; 0 = autotuned (with
                                 autotune) or the default, 2048               */
+    uint32_t pack_serial;    /* 1 = a graph runs the pack kernel ahead of the
+                                other passes; 0 = on a branch of its own,
+                                beside the locate and class passes           */
 } gc_plan_opts;
 #define GC_PACK_OFF 0x80000000u
 

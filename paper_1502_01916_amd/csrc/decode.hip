@@ -1796,9 +1796,11 @@ constexpr uint32_t kPackLists = 64;
 __device__ __forceinline__ uint32_t pack_rec(uint32_t j, uint32_t chunk, uint32_t sh, uint32_t bw) {
     return (j << 23) | ((chunk & 0xFFFu) << 11) | (sh << 6) | bw;
 }
-// The record of a tuple O bits into the column that starts at row chunk c0.
+// The record of a tuple O bits into the column that starts at row chunk c0
+// (row O / 32 of the column is chunk c0 + (O / 32) * k/4; chunks and shifts
+// in range, as the record builders check, so the fields do not spill).
 __device__ __forceinline__ uint32_t pack_rec_at(uint32_t j, uint32_t c0, uint32_t kq, uint32_t O, uint32_t bw) {
-    return pack_rec(j, c0 + (O >> 5) * kq, O & 31u, bw);
+    return ((j << 23) | (c0 << 11) | bw) + (O << 6) + (((O >> 5) * (kq - 1u)) << 11);
 }
 
 // Capacities of one pack: PI integers of tuple space (PI / 4 tuples), SW
@@ -1838,18 +1840,20 @@ __device__ __forceinline__ uint32_t pack_list_of(const uint32_t *base, uint32_t 
     return j;
 }
 
-// Exclusive scan of x over the lanes of one round that restarts at every
-// lane with `head` set; lanes before the round's first head continue the
-// running total `carry` of the previous rounds, which is advanced.
-__device__ __forceinline__ uint32_t seg_excl_scan(uint32_t x, bool head, uint32_t lane, uint32_t &carry) {
+// Exclusive scan of x over the lanes of one round, by segment: h is the
+// lane (of this round) where the lane's segment starts, negative for a
+// segment that began in an earlier round, whose lanes continue the running
+// total `carry` of the previous rounds; `carry` is advanced to the total of
+// the segment lane 63 belongs to.
+__device__ __forceinline__ uint32_t seg_excl_scan(uint32_t x, int h, uint32_t &carry) {
     const uint32_t inc = wave_incl_scan(x);
-    const uint32_t ex = inc - x;
-    const uint32_t hl = wave_incl_max(head ? lane + 1u : 0u);   // 1 + the last head at or before this lane
-    const uint32_t hx = (uint32_t)__shfl((int)ex, (int)(hl ? hl - 1u : 0u));
-    const uint32_t e = hl ? ex - hx : carry + ex;
+    const uint32_t hx = (uint32_t)__shfl((int)inc, max(h, 1) - 1);   // the scan just before the segment
+    const uint32_t e = inc - x + (h < 0 ? carry : h > 0 ? 0u - hx : 0u);
     carry = (uint32_t)__builtin_amdgcn_readlane((int)(e + x), 63);
     return e;
 }
+// The lane of round g0 where the segment starting at unit `first` begins.
+__device__ __forceinline__ int seg_head(uint32_t first, uint32_t g0) { return (int)first - (int)g0; }
 
 // Unit records (Group-Simple selectors, Group-AFOR frames) to tuple
 // records: every unit marked its first tuple with its index + 1; a running
@@ -1880,7 +1884,7 @@ __device__ __forceinline__ void pack_expand(PackSmem<PI, SW> &sm, uint32_t lane,
 
 // ---- Group-Simple: one selector per data row --------------------------------
 template <int PI, int SW>
-__device__ uint32_t pack_units_sim(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t U,
+__device__ __forceinline__ uint32_t pack_units_sim(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t U,
                                    uint32_t kq, const uint32_t *Tl, const uint32_t *cwl, const uint32_t *Cl,
                                    const uint32_t *d0l) {
     using SM = PackSmem<PI, SW>;
@@ -1896,7 +1900,7 @@ __device__ uint32_t pack_units_sim(PackSmem<PI, SW> &sm, const uint32_t *sw, uin
         rng |= in && !wok;
         const uint32_t sel = in && wok ? (sw[cw + (s >> 3)] >> (4u * (s & 7u))) & 15u : 15u;
         const uint32_t num = in && sel < 10u ? sim_num(sel) : 0u;
-        const uint32_t st = seg_excl_scan(num, in && s == 0u, lane, carry);
+        const uint32_t st = seg_excl_scan(num, seg_head(sm.ub[j], g0), carry);
         const bool valid = in && st < Tj;
         bad |= valid && sel >= 10u;
         // the list's last selector: its selectors cover its tuples
@@ -1920,7 +1924,7 @@ __device__ uint32_t pack_units_sim(PackSmem<PI, SW> &sm, const uint32_t *sw, uin
 
 // ---- Group-AFOR: frame bytes ------------------------------------------------
 template <int PI, int SW>
-__device__ uint32_t pack_units_afor(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t U,
+__device__ __forceinline__ uint32_t pack_units_afor(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t U,
                                     uint32_t kq, uint32_t lk, const uint32_t *Tl, const uint32_t *cwl,
                                     const uint32_t *Dl, const uint32_t *d0l) {
     using SM = PackSmem<PI, SW>;
@@ -1937,9 +1941,9 @@ __device__ uint32_t pack_units_afor(PackSmem<PI, SW> &sm, const uint32_t *sw, ui
         const bool fok = cls != 3u && b <= 32u;
         const uint32_t F = in ? 8u << (fok ? cls : 0u) : 0u;
         const uint32_t bb = fok ? b : 0u;
-        const bool head = in && s == 0u;
-        const uint32_t st = seg_excl_scan(F, head, lane, c_t);
-        const uint32_t fb = seg_excl_scan(F * bb, head, lane, c_b);
+        const int head = seg_head(sm.ub[j], g0);
+        const uint32_t st = seg_excl_scan(F, head, c_t);
+        const uint32_t fb = seg_excl_scan(F * bb, head, c_b);
         const bool valid = in && st < Tj;
         bad |= valid && !fok;
         rng |= valid && fb + F * bb > 32u * (Dl[j] >> lk);   // the frame's data inside the data area
@@ -1963,7 +1967,7 @@ __device__ uint32_t pack_units_afor(PackSmem<PI, SW> &sm, const uint32_t *sw, ui
 
 // ---- Group-Scheme, binary descriptors: one length field per tuple ----------
 template <int PI, int SW>
-__device__ uint32_t pack_recs_gscb(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t TT,
+__device__ __forceinline__ uint32_t pack_recs_gscb(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t TT,
                                    uint32_t kq, uint32_t lk, uint32_t cg, const uint32_t *Tl,
                                    const uint32_t *cwl, const uint32_t *Cl, const uint32_t *Dl,
                                    const uint32_t *d0l) {
@@ -1981,7 +1985,7 @@ __device__ uint32_t pack_recs_gscb(PackSmem<PI, SW> &sm, const uint32_t *sw, uin
         bad |= real && !wok;
         const uint32_t word = real && wok ? sw[cwl[j] + (bit >> 5)] : 0u;
         const uint32_t b = real && wok ? cg * (((word >> (bit & 31u)) & mask_of(bu.fb)) + 1u) : 0u;
-        const uint32_t O = seg_excl_scan(b, in && u == 0u, lane, carry);
+        const uint32_t O = seg_excl_scan(b, seg_head(sm.tb[j], g0), carry);
         bad |= real && O + b > 32u * (Dl[j] >> lk);   // the tuple's data inside the data area
         if (in) sm.rec[g] = pack_rec_at(j, d0l[j], kq, O, b);
     }
@@ -1990,7 +1994,7 @@ __device__ uint32_t pack_recs_gscb(PackSmem<PI, SW> &sm, const uint32_t *sw, uin
 
 // ---- Group-Scheme, unary descriptors: every 0 bit ends one tuple's code ------
 template <int PI, int SW>
-__device__ uint32_t pack_recs_gscu(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t U,
+__device__ __forceinline__ uint32_t pack_recs_gscu(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t U,
                                    uint32_t TT, uint32_t kq, uint32_t lk, uint32_t cg, bool iu,
                                    const uint32_t *Tl, const uint32_t *cwl, const uint32_t *Dl,
                                    const uint32_t *d0l) {
@@ -2005,7 +2009,7 @@ __device__ uint32_t pack_recs_gscu(PackSmem<PI, SW> &sm, const uint32_t *sw, uin
         const uint32_t Tj = Tl[j];
         uint32_t z = in ? ~sw[cwl[j] + s] : 0u;
         const uint32_t cnt = (uint32_t)__builtin_popcount(z);
-        uint32_t r = seg_excl_scan(cnt, in && s == 0u, lane, carry);
+        uint32_t r = seg_excl_scan(cnt, seg_head(sm.ub[j], g0), carry);
         if (in && g + 1u == sm.ub[j + 1u] && r + cnt < Tj) cnt_bad = true;
         const uint32_t base = sm.tb[j];
         while (z && r < Tj) {
@@ -2031,7 +2035,7 @@ __device__ uint32_t pack_recs_gscu(PackSmem<PI, SW> &sm, const uint32_t *sw, uin
         const uint32_t un = zp + 1u - start;
         bad |= real && (zp < start || un > umax);
         const uint32_t units = real ? min(un, umax) : 0u;
-        const uint32_t us = iu ? seg_excl_scan(units, in && u == 0u, lane, c_u) : 0u;
+        const uint32_t us = iu ? seg_excl_scan(units, seg_head(sm.tb[j], g0), c_u) : 0u;
         const uint32_t O = cg * (iu ? us : start);
         rng |= real && O + cg * units > 32u * (Dl[j] >> lk);   // the tuple's data inside the data area
         if (in) sm.rec[g] = pack_rec_at(j, d0l[j], kq, O, cg * units);
@@ -2042,7 +2046,7 @@ __device__ uint32_t pack_recs_gscu(PackSmem<PI, SW> &sm, const uint32_t *sw, uin
 
 // ---- Group-PFD (Section 6.2): block descriptors, records, exception marks ----
 template <int PI, int SW>
-__device__ uint32_t pack_recs_pfd(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t U,
+__device__ __forceinline__ uint32_t pack_recs_pfd(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t U,
                                   uint32_t TT, uint32_t k, uint32_t lk, bool bitmap, const uint32_t *Tl,
                                   const uint32_t *cwl, const uint32_t *Cl, const uint32_t *Dl,
                                   const uint32_t *Wl, const uint32_t *d0l) {
@@ -2067,17 +2071,28 @@ __device__ uint32_t pack_recs_pfd(PackSmem<PI, SW> &sm, const uint32_t *sw, uint
         }
         rng |= in && !sok;
         const uint32_t ew = pfd_exc_words(desc, (int)k, bitmap ? 1 : 0);
-        const bool head = in && s == 0u;
-        const uint32_t rows = seg_excl_scan(b, head, lane, c_r);
-        const uint32_t xw = seg_excl_scan(ew, head, lane, c_x);
+        const int head = seg_head(sm.ub[j], g0);
+        const uint32_t rows = seg_excl_scan(b, head, c_r);
+        const uint32_t xw = seg_excl_scan(ew, head, c_x);
         rng |= in && ((rows + b) << lk > Dj || 4u + Cj + Dj + xw + ew > Wl[j]);
         if (in) {
             const uint32_t c0 = d0l[j] + rows * kq;
             sm.u.p.blk[g] = u32x4{desc, c0, cwl[j] + Cj + Dj + xw, j};
-            // the block's 32 tuple records (those inside the list's tuple space)
+            // the block's 32 tuple records (those inside the list's tuple
+            // space); at k <= 8 a list's tuple space is a multiple of 4
+            // tuples from a multiple of 4, so four records go at once
             const uint32_t tb = sm.tb[j] + 32u * s;
             const uint32_t nt = min(32u, sm.tb[j + 1u] - min(sm.tb[j + 1u], tb));
-            for (uint32_t tt = 0; tt < nt; tt++) sm.rec[tb + tt] = pack_rec_at(j, c0, kq, tt * b, b);
+            if (k <= 8u) {
+                for (uint32_t tt = 0; tt < nt; tt += 4u) {
+                    const uint32_t O = tt * b;
+                    *reinterpret_cast<u32x4 *>(&sm.rec[tb + tt]) =
+                        u32x4{pack_rec_at(j, c0, kq, O, b), pack_rec_at(j, c0, kq, O + b, b),
+                              pack_rec_at(j, c0, kq, O + 2u * b, b), pack_rec_at(j, c0, kq, O + 3u * b, b)};
+                }
+            } else {
+                for (uint32_t tt = 0; tt < nt; tt++) sm.rec[tb + tt] = pack_rec_at(j, c0, kq, tt * b, b);
+            }
         }
     }
     if (wave_any(bad)) return kErrPfdDesc;
@@ -2170,23 +2185,27 @@ __device__ uint32_t pack_recs_pfd(PackSmem<PI, SW> &sm, const uint32_t *sw, uint
 }
 
 // The pack's quads, 64 per round: lane l takes quad r * 64 + l of the pack
-// (tuple q >> tsh, component quad q mod k/4).
-template <bool PATCH, int PI, int SW>
+// (tuple q >> tsh, component quad q mod k/4; K4: k = 4, a quad per tuple).
+// A docID list's scan starts at its first quad: lanes of a list that began
+// in an earlier round add the running total `carry`, lanes of one that
+// begins in this round subtract the scan at the lane before its first.
+template <bool PATCH, bool K4, int PI, int SW>
 __device__ __forceinline__ void pack_unpack(PackSmem<PI, SW> &sm, uint32_t lane, uint32_t NQ, uint32_t tsh,
                                             uint32_t kq, uint32_t lk, const PatchSrc &ps) {
     uint32_t carry = 0;
     for (uint32_t g0 = 0; g0 < NQ; g0 += 64u) {
         const uint32_t q = g0 + lane;
         const bool in = q < NQ;
-        const uint32_t t = q >> tsh, cq = q & (kq - 1u);
+        const uint32_t t = K4 ? q : q >> tsh, cq = K4 ? 0u : q & (kq - 1u);
         const uint32_t rc = in ? sm.rec[t] : 0u;
         const u32x4 L = sm.lst[(rc >> 23) & (kPackLists - 1u)];
-        const uint32_t li = ((t - (L.x & 0x7FFFFFFFu)) << lk) + 4u * cq;   // the quad's first integer in its list
+        const uint32_t tb = L.x & 0x7FFFFFFFu;
+        const uint32_t li = K4 ? (t - tb) << 2 : ((t - tb) << lk) + 4u * cq;   // the quad's first integer in its list
         const bool valid = in && li < L.y;
         u32x4 v = {0u, 0u, 0u, 0u};
         if (valid) {
             const uint32_t c = (rc >> 11) & 0xFFFu, sh = (rc >> 6) & 31u, bw = rc & 63u;
-            const u32x4 lo = sm.stage[c + cq], hi = sm.stage[c + kq + cq];
+            const u32x4 lo = sm.stage[c + cq], hi = sm.stage[c + (K4 ? 1u : kq) + cq];
             const uint32_t M = (uint32_t)(0xFFFFFFFFull >> (32u - bw));
             v.x = funnel(hi.x, lo.x, sh) & M;
             v.y = funnel(hi.y, lo.y, sh) & M;
@@ -2201,13 +2220,14 @@ __device__ __forceinline__ void pack_unpack(PackSmem<PI, SW> &sm, uint32_t lane,
                 v.z += v.y;
                 v.w += v.z;
             }
-            const uint32_t e = seg_excl_scan(delta ? v.w : 0u, valid && li == 0u, lane, carry);
+            // the list's first quad is its segment's start
+            const uint32_t e = seg_excl_scan(delta ? v.w : 0u, seg_head(K4 ? tb : tb * kq, g0), carry);
             if (delta) v += e;
         } else {
             carry = 0u;   // no docID list continues into the next round
         }
         if (valid) {
-            uint32_t *out = reinterpret_cast<uint32_t *>(((uint64_t)L.w << 32) | L.z) + li;
+            gu32 *out = (gu32 *)(((uint64_t)L.w << 32) | L.z) + li;
             const uint32_t n = L.y;
             if ((L.z & 15u) == 0u && li + 4u <= n) {
                 __builtin_nontemporal_store(v, (gu32x4 *)out);
@@ -2371,10 +2391,12 @@ __global__ __launch_bounds__(kThreads) void gc_pack_kernel(PackArgs a) {
     const uint32_t NQ = TT * kq;
     if (cls == kClsPfd) {
         PatchSrc ps{sm.u.p.bmap, sm.u.p.vbit, sm.u.p.xcnt, nullptr, ExcSrc{sw, nullptr, (uint32_t)SW, true}, false};
-        pack_unpack<true>(sm, lane, NQ, lk - 2u, kq, lk, ps);
+        if (k == 4u) pack_unpack<true, true>(sm, lane, NQ, 0u, 1u, 2u, ps);
+        else pack_unpack<true, false>(sm, lane, NQ, lk - 2u, kq, lk, ps);
     } else {
         PatchSrc ps{nullptr, nullptr, nullptr, nullptr, ExcSrc{nullptr, nullptr, 0u, false}, false};
-        pack_unpack<false>(sm, lane, NQ, lk - 2u, kq, lk, ps);
+        if (k == 4u) pack_unpack<false, true>(sm, lane, NQ, 0u, 1u, 2u, ps);
+        else pack_unpack<false, false>(sm, lane, NQ, lk - 2u, kq, lk, ps);
     }
 }
 

@@ -288,6 +288,7 @@ struct gc_plan {
     bool pack_forced = false;                  // pack_max set by the plan options
     std::vector<uint8_t> packed;               // per list
     PackSet pk[2];                             // packs of the kernel of capacity kPackInts[0] / [1] (one is used)
+    bool pack_branch = true;                   // graph: the pack kernel on a branch beside the other passes
     uint32_t total_chunks = 0;                 // locate chunks of every list (batch items first)
 };
 
@@ -706,16 +707,26 @@ gc_status launch_packs(gc_plan *p, hipStream_t s) {
 // (indices into the events plan_launch records).
 constexpr int kTevPack = 5 * kClasses;
 
+// With a pack stream `pks` (and its fork / join events), the pack kernel
+// runs there, beside the locate pass and the class passes.
 gc_status plan_launch(gc_plan *p, hipStream_t s, hipStream_t aux = nullptr, hipEvent_t start = nullptr,
-                      hipEvent_t *sync = nullptr, hipEvent_t *tev = nullptr) {
+                      hipEvent_t *sync = nullptr, hipEvent_t *tev = nullptr, hipStream_t pks = nullptr,
+                      hipEvent_t pk_fork = nullptr, hipEvent_t pk_join = nullptr) {
     if (aux) {
         HIP_OK(hipEventRecord(start, s));
         HIP_OK(hipStreamWaitEvent(aux, start, 0));
     }
     // the packed lists depend on nothing the other passes compute
-    if (tev) HIP_OK(hipEventRecord(tev[kTevPack], s));
-    if (gc_status rc = launch_packs(p, s)) return rc;
-    if (tev) HIP_OK(hipEventRecord(tev[kTevPack + 1], s));
+    const bool fork = pks && (p->pk[0].packs() || p->pk[1].packs());
+    if (fork) {
+        HIP_OK(hipEventRecord(pk_fork, s));
+        HIP_OK(hipStreamWaitEvent(pks, pk_fork, 0));
+    }
+    const hipStream_t ps = fork ? pks : s;
+    if (tev) HIP_OK(hipEventRecord(tev[kTevPack], ps));
+    if (gc_status rc = launch_packs(p, ps)) return rc;
+    if (tev) HIP_OK(hipEventRecord(tev[kTevPack + 1], ps));
+    if (fork) HIP_OK(hipEventRecord(pk_join, ps));
     hipStream_t ls = aux ? aux : s;
     if (!aux) {
         const int c0 = first_class(p);
@@ -736,21 +747,27 @@ gc_status plan_launch(gc_plan *p, hipStream_t s, hipStream_t aux = nullptr, hipE
         if (gc_status rc = launch_class_work(p, c, s, aux != nullptr, tev ? tev[5 * c + 3] : nullptr)) return rc;
         if (tev) HIP_OK(hipEventRecord(tev[5 * c + 4], s));
     }
+    if (fork) HIP_OK(hipStreamWaitEvent(s, pk_join, 0));
     return GC_OK;
 }
 
 gc_status capture_one(gc_plan *p, hipGraph_t *graph, hipGraphExec_t *exec) {
-    hipStream_t s, aux;
-    hipEvent_t start, sync[kClasses];
+    hipStream_t s, aux, pks;
+    hipEvent_t start, sync[kClasses], fork, join;
     HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     HIP_OK(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
+    HIP_OK(hipStreamCreateWithFlags(&pks, hipStreamNonBlocking));
     HIP_OK(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
     for (int c = 0; c < kClasses; c++) HIP_OK(hipEventCreateWithFlags(&sync[c], hipEventDisableTiming));
     gc_status rc = GC_OK;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         rc = GC_EDEVICE;
     } else {
-        rc = plan_launch(p, s, p->serial ? nullptr : aux, start, sync);
+        // the graph's pack kernel is a branch of its own
+        rc = plan_launch(p, s, p->serial ? nullptr : aux, start, sync, nullptr, p->pack_branch ? pks : nullptr,
+                         fork, join);
         hipGraph_t g = nullptr;
         if (hipStreamEndCapture(s, &g) != hipSuccess || rc) {
             rc = GC_EDEVICE;
@@ -762,6 +779,9 @@ gc_status capture_one(gc_plan *p, hipGraph_t *graph, hipGraphExec_t *exec) {
     }
     for (int c = 0; c < kClasses; c++) (void)hipEventDestroy(sync[c]);
     (void)hipEventDestroy(start);
+    (void)hipEventDestroy(fork);
+    (void)hipEventDestroy(join);
+    (void)hipStreamDestroy(pks);
     (void)hipStreamDestroy(aux);
     (void)hipStreamDestroy(s);
     (void)hipGetLastError();
@@ -1150,6 +1170,11 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     p->use_graph = o.use_graph != 0;
     p->serial = o.schedule == 0u;
     p->pack_forced = o.pack_ints != 0u;
+    if (o.pack_serial > 1u) {
+        delete p;
+        return GC_EINVAL;
+    }
+    p->pack_branch = o.pack_serial == 0u;
     p->pack_max = o.pack_ints == GC_PACK_OFF ? 0u : o.pack_ints ? o.pack_ints : kDefaultPackMax;
     p->lb_max = o.carry_pass == 1u ? kLookbackAll : o.carry_pass == 2u ? 0u
               : o.carry_pass == 3u ? kLookbackHybrid : kDefaultLbMax;
