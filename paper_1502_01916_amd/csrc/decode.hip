@@ -1826,7 +1826,7 @@ struct PackSmem {
         uint16_t z[TUP];          // unary Group-Scheme: terminator position of each tuple's code
         struct {
             u32x4 blk[NBLK];      // Group-PFD block: descriptor, first row chunk, exception word, list
-            uint32_t bmap[NBM], xcnt[NBM], vbit[NBM];
+            uint32_t bmap[NBM], vbit[NBM];
         } p;
     } u;
 };
@@ -2097,36 +2097,89 @@ __device__ __forceinline__ uint32_t pack_recs_pfd(PackSmem<PI, SW> &sm, const ui
     }
     if (wave_any(bad)) return kErrPfdDesc;
     if (wave_any(rng)) return kErrRange;
-    // the exception bitmap over the pack's integers
-    const uint32_t nbw = (TT << lk) >> 5;
-    for (uint32_t w = lane; w < nbw; w += 64u) sm.u.p.bmap[w] = 0u;
-    wave_lds_sync();
+    // The exception bitmap over the pack's integers, block by block: a
+    // block starts at a 32-integer boundary, so the bitmap words of its
+    // integers are its own.  One lane per block marks its exceptions (the
+    // linked chain through the slots, or the tuple and component masks) and
+    // writes, for each of its words, the staged bit offset of the word's
+    // first exception value | width code, from the block's count so far.
     bool chain_bad = false;
     for (uint32_t g = lane; g < U; g += 64u) {
         const u32x4 bk = sm.u.p.blk[g];
         const uint32_t desc = bk.x, c0 = bk.y, xb = bk.z, j = bk.w;
         const uint32_t s = g - sm.ub[j];
-        const uint32_t nexc = desc >> 20, b = desc & 63u, M = mask_of(b);
-        const uint32_t real_t = Tl[j] - 32u * s;                 // real tuples of the block (> 0)
-        const uint32_t ibase = (sm.tb[j] + 32u * s) << lk;       // its first integer in the pack
-        if (!nexc) continue;
-        if (!bitmap) {
-            uint32_t p = (desc >> 8) & 0xFFFu;
+        const uint32_t nexc = desc >> 20, b = desc & 63u, M = mask_of(b), wcode = (desc >> 6) & 3u;
+        const uint32_t real_t = min(32u, Tl[j] - 32u * s);       // real tuples of the block (> 0)
+        const uint32_t wfirst = ((sm.tb[j] + 32u * s) << lk) >> 5;   // its first bitmap word
+        const uint32_t nw = ((real_t << lk) + 31u) >> 5;             // words holding its integers
+        const uint32_t ew = 4u << wcode;
+        const uint32_t first = (desc >> 8) & 0xFFFu;
+        const uint32_t v0 = bitmap ? xb + 1u + ((first * k + 31u) >> 5) : xb;   // its first exception value
+        uint32_t *bm = sm.u.p.bmap + wfirst;
+        uint32_t *vb = sm.u.p.vbit + wfirst;
+        if (!nexc) {
+            for (uint32_t w = 0; w < nw; w++) bm[w] = 0u;
+            continue;
+        }
+        if (!bitmap && k == 4u) {
+            // 128 positions: the block's four words in registers
+            uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+            uint32_t p = first;
+            const uint32_t lim = real_t << 2;
             for (uint32_t e = 0; e < nexc; e++) {
-                if (p >= BI || (p >> lk) >= real_t) {
+                if (p >= lim) {
                     chain_bad = true;
                     break;
                 }
-                const uint32_t q = ibase + p;
-                atomicOr(&sm.u.p.bmap[q >> 5], 1u << (q & 31u));
+                const uint32_t bit = 1u << (p & 31u), wq = p >> 5;
+                m0 |= wq == 0u ? bit : 0u;
+                m1 |= wq == 1u ? bit : 0u;
+                m2 |= wq == 2u ? bit : 0u;
+                m3 |= wq == 3u ? bit : 0u;
+                const uint32_t O = (p >> 2) * b;
+                const uint32_t at = 4u * (c0 + (O >> 5)) + (p & 3u);
+                const uint32_t slot = b ? funnel(sw[at + 4u], sw[at], O & 31u) & M : 0u;
+                p = p + slot + 1u;
+            }
+            const uint32_t c1 = (uint32_t)__builtin_popcount(m0), c2 = c1 + (uint32_t)__builtin_popcount(m1),
+                           c3 = c2 + (uint32_t)__builtin_popcount(m2);
+            const uint32_t vb0 = 32u * v0;
+            bm[0] = m0;
+            vb[0] = (vb0 << 2) | wcode;
+            if (nw > 1u) {
+                bm[1] = m1;
+                vb[1] = ((vb0 + c1 * ew) << 2) | wcode;
+            }
+            if (nw > 2u) {
+                bm[2] = m2;
+                vb[2] = ((vb0 + c2 * ew) << 2) | wcode;
+            }
+            if (nw > 3u) {
+                bm[3] = m3;
+                vb[3] = ((vb0 + c3 * ew) << 2) | wcode;
+            }
+            continue;
+        }
+        for (uint32_t w = 0; w < nw; w++) bm[w] = 0u;
+        uint32_t marked = 0;
+        if (!bitmap) {
+            const uint32_t BI = 32u * k, lim = real_t << lk;
+            uint32_t p = first;
+            for (uint32_t e = 0; e < nexc; e++) {
+                if (p >= lim) {
+                    chain_bad = true;
+                    break;
+                }
+                bm[p >> 5] |= 1u << (p & 31u);
                 const uint32_t O = (p >> lk) * b, c = p & (k - 1u);
                 const uint32_t at = 4u * (c0 + (O >> 5) * kq) + c;
                 const uint32_t slot = b ? funnel(sw[at + k], sw[at], O & 31u) & M : 0u;
                 p = slot < BI ? p + slot + 1u : BI;
             }
+            marked = nexc;
         } else {
             const uint32_t tm = sw[xb];
-            if ((uint32_t)__builtin_popcount(tm) != ((desc >> 8) & 0xFFFu) || (real_t < 32u && (tm >> real_t))) {
+            if ((uint32_t)__builtin_popcount(tm) != first || (real_t < 32u && (tm >> real_t))) {
                 chain_bad = true;
                 continue;
             }
@@ -2134,52 +2187,29 @@ __device__ __forceinline__ uint32_t pack_recs_pfd(PackSmem<PI, SW> &sm, const ui
             while (m) {
                 const uint32_t t = (uint32_t)__builtin_ctz(m);
                 m &= m - 1u;
-                const uint32_t bit = r * k, q = ibase + t * k;
+                const uint32_t bit = r * k, q = t * k;
                 if (k < 32u) {
                     const uint32_t cm = (sw[xb + 1u + (bit >> 5)] >> (bit & 31u)) & mask_of(k);
-                    atomicOr(&sm.u.p.bmap[q >> 5], cm << (q & 31u));
+                    bm[q >> 5] |= cm << (q & 31u);
+                    marked += (uint32_t)__builtin_popcount(cm);
                 } else {
-                    for (uint32_t h = 0; h < (k >> 5); h++) sm.u.p.bmap[(q >> 5) + h] = sw[xb + 1u + (bit >> 5) + h];
+                    for (uint32_t h = 0; h < (k >> 5); h++) {
+                        const uint32_t cm = sw[xb + 1u + (bit >> 5) + h];
+                        bm[(q >> 5) + h] = cm;
+                        marked += (uint32_t)__builtin_popcount(cm);
+                    }
                 }
                 r++;
             }
         }
+        if (marked != nexc) chain_bad = true;
+        uint32_t before = 0;
+        for (uint32_t w = 0; w < nw; w++) {
+            vb[w] = ((32u * v0 + before * ew) << 2) | wcode;
+            before += (uint32_t)__builtin_popcount(bm[w]);
+        }
     }
     if (wave_any(chain_bad)) return bitmap ? kErrBitmap : kErrPfdChain;
-    wave_lds_sync();
-    // exceptions before every bitmap word, pack-wide
-    uint32_t run = 0;
-    for (uint32_t w0 = 0; w0 < nbw; w0 += 64u) {
-        const uint32_t w = w0 + lane;
-        const uint32_t c = w < nbw ? (uint32_t)__builtin_popcount(sm.u.p.bmap[w]) : 0u;
-        const uint32_t inc = wave_incl_scan(c);
-        if (w < nbw) sm.u.p.xcnt[w] = run + inc - c;
-        run += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
-    }
-    wave_lds_sync();
-    // per word: bit offset (in the staging buffer) of its first exception
-    // value | width code; every block marks exactly its exception count
-    bool cbad = false;
-    for (uint32_t w = lane; w < nbw; w += 64u) {
-        const uint32_t t = (32u * w) >> lk;
-        const uint32_t j = (sm.rec[t] >> 23) & (kPackLists - 1u);
-        const uint32_t u = t - sm.tb[j];
-        uint32_t vb = 0;
-        if (u < Tl[j]) {
-            const uint32_t s = u >> 5;
-            const u32x4 bk = sm.u.p.blk[sm.ub[j] + s];
-            const uint32_t desc = bk.x, nexc = desc >> 20, wcode = (desc >> 6) & 3u;
-            const uint32_t wfirst = ((sm.tb[j] + 32u * s) << lk) >> 5;
-            const uint32_t nreal = min(32u, Tl[j] - 32u * s);
-            const uint32_t wend = (((sm.tb[j] + 32u * s) << lk) + (nreal << lk) + 31u) >> 5;
-            const uint32_t before = sm.u.p.xcnt[w] - sm.u.p.xcnt[wfirst];
-            const uint32_t v0 = bitmap ? bk.z + 1u + ((((desc >> 8) & 0xFFFu) * k + 31u) >> 5) : bk.z;
-            vb = ((32u * v0 + before * (4u << wcode)) << 2) | wcode;
-            if (w + 1u == wend && before + (uint32_t)__builtin_popcount(sm.u.p.bmap[w]) != nexc) cbad = true;
-        }
-        sm.u.p.vbit[w] = vb;
-    }
-    if (wave_any(cbad)) return bitmap ? kErrBitmap : kErrPfdChain;
     wave_lds_sync();
     return 0;
 }
@@ -2390,7 +2420,7 @@ __global__ __launch_bounds__(kThreads) void gc_pack_kernel(PackArgs a) {
     wave_lds_sync();
     const uint32_t NQ = TT * kq;
     if (cls == kClsPfd) {
-        PatchSrc ps{sm.u.p.bmap, sm.u.p.vbit, sm.u.p.xcnt, nullptr, ExcSrc{sw, nullptr, (uint32_t)SW, true}, false};
+        PatchSrc ps{sm.u.p.bmap, sm.u.p.vbit, nullptr, nullptr, ExcSrc{sw, nullptr, (uint32_t)SW, true}, false};
         if (k == 4u) pack_unpack<true, true>(sm, lane, NQ, 0u, 1u, 2u, ps);
         else pack_unpack<true, false>(sm, lane, NQ, lk - 2u, kq, lk, ps);
     } else {

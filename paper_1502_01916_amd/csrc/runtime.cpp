@@ -300,7 +300,6 @@ constexpr uint32_t kPackInts[2] = {2048u, 4096u};
 constexpr uint32_t kPackWords[2] = {512u, 1024u};
 // Default pack_max: lists of up to 2048 integers.
 constexpr uint32_t kDefaultPackMax = 2048u;
-constexpr uint32_t kPackOff = 0x80000000u;
 constexpr uint32_t kPackMaxLists = 64u;
 int pack_cfg(uint32_t pack_max) { return pack_max <= kPackInts[0] ? 0 : 1; }
 
