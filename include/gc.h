@@ -213,7 +213,7 @@ typedef struct {
                                 instead of by the class passes, when their
                                 streams fit a pack (2 KB of stream for a
                                 threshold up to 2048, else 4 KB); a pack holds
-                                up to 64 lists of one stream format (codec,
+                                up to 32 lists of one stream format (codec,
                                 k and codec parameters; docID and TF lists
                                 mix); GC_PACK_OFF: none; 0 = autotuned (with
                                 autotune) or the default, 2048               */

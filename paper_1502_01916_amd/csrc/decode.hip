@@ -1773,7 +1773,7 @@ __global__ __launch_bounds__(kThreads, (MODE == kModeSum && CLS == kClsPfd) ? 7 
 //
 // A list of one tile still pays a tile's whole chain of dependent loads and
 // its prologue for a few hundred integers.  Here a wave takes a pack of up
-// to 64 short lists that share one stream format (codec, layout width and
+// to 32 short lists that share one stream format (codec, layout width and
 // codec parameters; docID and TF lists mix): lane j loads list j's
 // descriptor, wave scans place the lists' streams one after another in the
 // wave's LDS staging buffer (16-byte loads, every list's at once) and their
@@ -1790,7 +1790,7 @@ __global__ __launch_bounds__(kThreads, (MODE == kModeSum && CLS == kClsPfd) ? 7 
 // exception positions, and docID lists are prefix-summed by a wave scan that
 // restarts at each list's first quad.
 
-constexpr uint32_t kPackLists = 64;
+constexpr uint32_t kPackLists = 32;   // lists per pack (lanes 0 .. 31 hold their descriptors)
 
 // Records of the pack's tuples: list:6 | row chunk:12 | shift:5 | width:6.
 __device__ __forceinline__ uint32_t pack_rec(uint32_t j, uint32_t chunk, uint32_t sh, uint32_t bw) {
@@ -1804,23 +1804,23 @@ __device__ __forceinline__ uint32_t pack_rec_at(uint32_t j, uint32_t c0, uint32_
 }
 
 // Capacities of one pack: PI integers of tuple space (PI / 4 tuples), SW
-// staged stream words, 64 lists.
+// staged stream words, kPackLists lists.
 template <int PI, int SW>
 struct PackSmem {
     static constexpr int TUP = PI / 4;
     static constexpr int TPL = TUP / 64;                       // tuples per lane in the record expansion
-    static constexpr int NU = SW / 4 > TUP / 8 + 64 ? SW / 4 : TUP / 8 + 64;   // selector / frame records
-    static constexpr int NBLK = TUP / 32 + 64;                 // Group-PFD blocks
+    static constexpr int NU = SW / 4 > TUP / 8 + (int)kPackLists ? SW / 4 : TUP / 8 + (int)kPackLists;   // selector / frame records
+    static constexpr int NBLK = TUP / 32 + (int)kPackLists;    // Group-PFD blocks
     static constexpr int NBM = PI / 32;                        // exception bitmap words
     u32x4 stage[SW / 4 + 16];     // the streams (+ one row of the widest layout, read past a list's last row)
     uint32_t rec[TUP];            // tuple records (unit markers while the records are built)
     u32x4 lst[kPackLists];        // list j: tuple base | delta << 31, n, output pointer (low, high word)
-    uint32_t so[kPackLists + 1];  // staging chunk of list j (the pack's total from the last list on)
-    uint32_t tb[kPackLists + 1];  // tuple base of list j (likewise)
-    uint32_t ub[kPackLists + 1];  // first control unit of list j (likewise)
+    uint16_t so[kPackLists + 1];  // staging chunk of list j (the pack's total from the last list on)
+    uint16_t tb[kPackLists + 1];  // tuple base of list j (likewise)
+    uint16_t ub[kPackLists + 1];  // first control unit of list j (likewise)
     // list j: tuples, stage word of its control area, control words, data
-    // words, stream words, chunk of its data area
-    uint32_t lt[6][kPackLists];
+    // words, stream words, chunk of its data area (all below 2^16)
+    uint16_t lt[6][kPackLists];
     union {
         uint2 info[NU];           // Group-Simple, Group-AFOR: unit {tuple start | bit << 16, record base}
         uint16_t z[TUP];          // unary Group-Scheme: terminator position of each tuple's code
@@ -1833,10 +1833,10 @@ struct PackSmem {
 
 // The list of unit x: the last j with base[j] <= x (base[j] holds the
 // pack's total for the lists after its last, so those are never chosen).
-__device__ __forceinline__ uint32_t pack_list_of(const uint32_t *base, uint32_t x) {
+__device__ __forceinline__ uint32_t pack_list_of(const uint16_t *base, uint32_t x) {
     uint32_t j = 0;
 #pragma unroll
-    for (uint32_t step = 32u; step; step >>= 1) j = base[j + step] <= x ? j + step : j;
+    for (uint32_t step = kPackLists / 2u; step; step >>= 1) j = base[j + step] <= x ? j + step : j;
     return j;
 }
 
@@ -1885,8 +1885,8 @@ __device__ __forceinline__ void pack_expand(PackSmem<PI, SW> &sm, uint32_t lane,
 // ---- Group-Simple: one selector per data row --------------------------------
 template <int PI, int SW>
 __device__ __forceinline__ uint32_t pack_units_sim(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t U,
-                                   uint32_t kq, const uint32_t *Tl, const uint32_t *cwl, const uint32_t *Cl,
-                                   const uint32_t *d0l) {
+                                   uint32_t kq, const uint16_t *Tl, const uint16_t *cwl, const uint16_t *Cl,
+                                   const uint16_t *d0l) {
     using SM = PackSmem<PI, SW>;
     uint32_t carry = 0, nu = 0;
     bool bad = false, cnt_bad = false, rng = false;
@@ -1925,8 +1925,8 @@ __device__ __forceinline__ uint32_t pack_units_sim(PackSmem<PI, SW> &sm, const u
 // ---- Group-AFOR: frame bytes ------------------------------------------------
 template <int PI, int SW>
 __device__ __forceinline__ uint32_t pack_units_afor(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t U,
-                                    uint32_t kq, uint32_t lk, const uint32_t *Tl, const uint32_t *cwl,
-                                    const uint32_t *Dl, const uint32_t *d0l) {
+                                    uint32_t kq, uint32_t lk, const uint16_t *Tl, const uint16_t *cwl,
+                                    const uint16_t *Dl, const uint16_t *d0l) {
     using SM = PackSmem<PI, SW>;
     uint32_t c_t = 0, c_b = 0, nu = 0;
     bool bad = false, cnt_bad = false, rng = false;
@@ -1968,9 +1968,9 @@ __device__ __forceinline__ uint32_t pack_units_afor(PackSmem<PI, SW> &sm, const 
 // ---- Group-Scheme, binary descriptors: one length field per tuple ----------
 template <int PI, int SW>
 __device__ __forceinline__ uint32_t pack_recs_gscb(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t TT,
-                                   uint32_t kq, uint32_t lk, uint32_t cg, const uint32_t *Tl,
-                                   const uint32_t *cwl, const uint32_t *Cl, const uint32_t *Dl,
-                                   const uint32_t *d0l) {
+                                   uint32_t kq, uint32_t lk, uint32_t cg, const uint16_t *Tl,
+                                   const uint16_t *cwl, const uint16_t *Cl, const uint16_t *Dl,
+                                   const uint16_t *d0l) {
     const BinUnit bu = bin_unit((int)cg);
     uint32_t carry = 0;
     bool bad = false;
@@ -1996,8 +1996,8 @@ __device__ __forceinline__ uint32_t pack_recs_gscb(PackSmem<PI, SW> &sm, const u
 template <int PI, int SW>
 __device__ __forceinline__ uint32_t pack_recs_gscu(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t U,
                                    uint32_t TT, uint32_t kq, uint32_t lk, uint32_t cg, bool iu,
-                                   const uint32_t *Tl, const uint32_t *cwl, const uint32_t *Dl,
-                                   const uint32_t *d0l) {
+                                   const uint16_t *Tl, const uint16_t *cwl, const uint16_t *Dl,
+                                   const uint16_t *d0l) {
     uint32_t carry = 0;
     bool cnt_bad = false;
     // terminator r of list j at z[tb[j] + r] (for r < the list's tuples)
@@ -2047,9 +2047,9 @@ __device__ __forceinline__ uint32_t pack_recs_gscu(PackSmem<PI, SW> &sm, const u
 // ---- Group-PFD (Section 6.2): block descriptors, records, exception marks ----
 template <int PI, int SW>
 __device__ __forceinline__ uint32_t pack_recs_pfd(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t U,
-                                  uint32_t TT, uint32_t k, uint32_t lk, bool bitmap, const uint32_t *Tl,
-                                  const uint32_t *cwl, const uint32_t *Cl, const uint32_t *Dl,
-                                  const uint32_t *Wl, const uint32_t *d0l) {
+                                  uint32_t TT, uint32_t k, uint32_t lk, bool bitmap, const uint16_t *Tl,
+                                  const uint16_t *cwl, const uint16_t *Cl, const uint16_t *Dl,
+                                  const uint16_t *Wl, const uint16_t *d0l) {
     const uint32_t kq = k >> 2;
     const uint32_t BI = 32u * k;
     uint32_t c_r = 0, c_x = 0;
@@ -2341,18 +2341,16 @@ __global__ __launch_bounds__(kThreads) void gc_pack_kernel(PackArgs a) {
         return;
     }
     const uint32_t so = i_ch - ch, tbase = i_t - Tp;
-    sm.so[lane] = mine ? so : tot_ch;
-    sm.tb[lane] = mine ? tbase : TT;
-    sm.ub[lane] = mine ? i_u - units : U;
-    if (lane == 0) {
-        sm.so[64] = tot_ch;
-        sm.tb[64] = TT;
-        sm.ub[64] = U;
+    if (lane <= kPackLists) {
+        sm.so[lane] = (uint16_t)(mine ? so : tot_ch);
+        sm.tb[lane] = (uint16_t)(mine ? tbase : TT);
+        sm.ub[lane] = (uint16_t)(mine ? i_u - units : U);
     }
     // (lanes past the pack's lists: no integers, so nothing is ever stored for them)
     const uint64_t op = reinterpret_cast<uint64_t>(d.out);
-    sm.lst[lane] = mine ? u32x4{tbase | ((d.w0 >> 19) & 1u) << 31, d.n, (uint32_t)op, (uint32_t)(op >> 32)}
-                        : u32x4{0u, 0u, 0u, 0u};
+    if (lane < kPackLists)
+        sm.lst[lane] = mine ? u32x4{tbase | ((d.w0 >> 19) & 1u) << 31, d.n, (uint32_t)op, (uint32_t)(op >> 32)}
+                            : u32x4{0u, 0u, 0u, 0u};
     wave_lds_sync();
     // the pack's streams, chunk c to stage[c]: the list of a chunk by binary
     // search over the offsets, its stream pointer from that list's lane;
@@ -2390,13 +2388,15 @@ __global__ __launch_bounds__(kThreads) void gc_pack_kernel(PackArgs a) {
         return;
     }
     // per-list values for the record builders
-    uint32_t *Tl = sm.lt[0], *cwl = sm.lt[1], *Cl = sm.lt[2], *Dl = sm.lt[3], *Wl = sm.lt[4], *d0l = sm.lt[5];
-    Tl[lane] = T;
-    cwl[lane] = cwo;
-    Cl[lane] = C;
-    Dl[lane] = D;
-    Wl[lane] = mine ? d.words : 0u;
-    d0l[lane] = so + 1u + (C >> 2);   // chunk of the data area
+    uint16_t *Tl = sm.lt[0], *cwl = sm.lt[1], *Cl = sm.lt[2], *Dl = sm.lt[3], *Wl = sm.lt[4], *d0l = sm.lt[5];
+    if (lane < kPackLists) {
+        Tl[lane] = (uint16_t)T;
+        cwl[lane] = (uint16_t)cwo;
+        Cl[lane] = (uint16_t)C;
+        Dl[lane] = (uint16_t)D;
+        Wl[lane] = (uint16_t)(mine ? d.words : 0u);
+        d0l[lane] = (uint16_t)(so + 1u + (C >> 2));   // chunk of the data area
+    }
     wave_lds_sync();
     uint32_t err = 0;
     if (cls == kClsSim || cls == kClsAfor) {

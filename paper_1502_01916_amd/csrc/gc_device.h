@@ -136,10 +136,8 @@ struct DecodeArgs {
     Status *status;
 };
 
-constexpr int kPackChunks = 256;   // staging buffer of a pack: 4 KB of whole streams per wave
-
-// A list the pack kernel decodes: a list of one tile whose whole stream fits
-// a pack's staging buffer.  The lists of a pack are consecutive entries.
+// A list the pack kernel decodes: a short list whose whole stream fits a
+// pack's staging buffer.  The lists of a pack are consecutive entries.
 struct PackDesc {
     const uint32_t *stream;   // 16-byte aligned
     uint32_t *out;
@@ -150,7 +148,7 @@ struct PackDesc {
 };
 
 // Pack kernel launch: a wave per pack; pack p holds the descriptors
-// [first[p], first[p + 1]), at most 64 lists whose streams fit the
+// [first[p], first[p + 1]), at most 32 lists whose streams fit the
 // kernel's staging buffer together.
 struct PackArgs {
     const PackDesc *descs;

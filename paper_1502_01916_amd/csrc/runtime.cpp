@@ -300,7 +300,7 @@ constexpr uint32_t kPackInts[2] = {2048u, 4096u};
 constexpr uint32_t kPackWords[2] = {512u, 1024u};
 // Default pack_max: lists of up to 2048 integers.
 constexpr uint32_t kDefaultPackMax = 2048u;
-constexpr uint32_t kPackMaxLists = 64u;
+constexpr uint32_t kPackMaxLists = 32u;
 int pack_cfg(uint32_t pack_max) { return pack_max <= kPackInts[0] ? 0 : 1; }
 
 LocateArgs make_locate_args(const ListDesc *lists, const uint32_t *item_list, const uint32_t *scan_list,
@@ -444,7 +444,7 @@ void build_tables(gc_plan *p) {
         }
     }
     // Packs: lists of one stream format (header word 0 without its delta
-    // bit), in list order, while they number at most 64 and their streams
+    // bit), in list order, while they number at most 32 and their streams
     // and padded tuple spaces fit the kernel's buffers.
     if (p->pack_max) {
         const int cfg = pack_cfg(p->pack_max);
