@@ -109,6 +109,25 @@ gc_status gc_encode_lists(const uint32_t *h_in, const uint64_t *in_offs, size_t 
                           uint32_t *h_out, size_t out_cap_words, uint64_t *out_offs,
                           int nthreads);
 
+/* Encodes nlists lists on the GPU, with one codec and parameter set for
+ * all: list i is d_in[h_in_offs[i] .. h_in_offs[i+1]) (device memory; at
+ * most 2^28 integers).  Writes exactly the streams gc_encode_lists writes
+ * for the same lists (Algorithm 1 for Group-Simple, Section 4.2; eq. (1)-(2)
+ * and the length descriptors of Section 5.2.1 for Group-Scheme; the optimal
+ * frame partition of Section 6.1 for Group-AFOR; encoding steps 1-4 of
+ * Section 6.2 for Group-PFD), back to back into d_out (device memory,
+ * capacity out_cap_words); h_out_offs[i] (host memory, nlists + 1 entries)
+ * receives stream i's word offset and h_out_offs[nlists] the total.
+ * Index build, not the decode path: it allocates device scratch for the
+ * call (about 12 bytes per integer at most), reads the stream sizes back to
+ * the host, and returns once the streams are written (it synchronises
+ * hip_stream).  GC_EINVAL for bad parameters, GC_ENOSPC if the streams do
+ * not fit (h_out_offs then holds their sizes), GC_ENOMEM if the scratch
+ * does not fit.                                                            */
+gc_status gc_encode_lists_gpu(const uint32_t *d_in, const uint64_t *h_in_offs, size_t nlists,
+                              gc_codec codec, const gc_params *p, uint32_t *d_out,
+                              size_t out_cap_words, uint64_t *h_out_offs, void *hip_stream);
+
 /* ---- device context ---------------------------------------------------- */
 
 typedef struct gc_ctx gc_ctx;     /* opaque, library-owned */

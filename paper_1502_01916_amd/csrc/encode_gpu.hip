@@ -1,0 +1,875 @@
+// encode_gpu.hip -- Group-codec encoders on the GPU (index build).
+//
+// Writes the same streams as the host encoder (include/gc.h, byte for byte)
+// for many lists at once, with one codec and one parameter set:
+//
+//   widths   one pass over the input: the d-gaps of docID lists and the bit
+//            width of every tuple (the width of the OR of its k integers,
+//            Section 4.4).
+//   sizing   per codec, the control, data and exception words of every list;
+//            the host turns them into stream offsets.
+//   emit     the header, control area, data rows and exception area of every
+//            stream, into an output area cleared first (unary Group-Scheme
+//            control areas are set to ones and their terminators cleared).
+//
+// Group-Simple's selectors (Algorithm 1, Section 4.2) and Group-AFOR's
+// frames (Section 6.1) form chains: where the next unit starts depends on
+// where this one did.  The incomplete-unary Group-Scheme control stream
+// (Section 5.2.1) carries a state too, its position within a byte.  These
+// run in three steps over chunks of a list: every chunk computes, for each
+// state it may be entered in (the tuple or octet offset where the chain
+// enters it, or the bit position mod 8), the state it leaves in and what it
+// emitted (units, bits); one lane per list then walks its chunks and finds
+// each chunk's true entry state and the counts before it; every chunk then
+// runs once more from its entry state and writes its units.  Group-AFOR's
+// frame sizes come from the exact dynamic programme of Section 6.1, run
+// backwards: a chunk maps the costs at its end to the costs at its start by
+// a 4 x 4 min-plus matrix (its four columns from four runs, each with one
+// end state at cost 0 and the others unreachable), the lane of a list
+// multiplies them from the last chunk back to find every chunk's end costs,
+// and each chunk then runs the programme once with its true end costs and
+// keeps its choices.  Group-PFD codes 32-tuple blocks independently
+// (Section 6.2): one lane per block.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "gc.h"
+#include "gc_format.h"
+
+namespace gcenc {
+
+typedef __attribute__((address_space(1))) uint32_t gu32;
+
+constexpr int kThreads = 256;
+constexpr uint32_t kTupChunk = 2048;   // tuples per chunk (Group-Simple, Group-Scheme)
+constexpr uint32_t kOctChunk = 256;    // octets (8 tuples) per chunk (Group-AFOR)
+constexpr uint64_t kInf = 1ull << 62;  // an unreachable cost
+
+// Group-Simple (Table III): NUM and BW of selectors 0..9.
+__constant__ uint8_t kNum[10] = {32, 16, 10, 8, 6, 5, 4, 3, 2, 1};
+__constant__ uint8_t kBw[10] = {1, 2, 3, 4, 5, 6, 8, 10, 16, 32};
+
+// One list of the call.
+struct EList {
+    uint64_t in_off;    // first input integer
+    uint64_t out_off;   // first stream word (set once the streams are sized)
+    uint64_t t0;        // first tuple in the per-tuple arrays (padded tuples)
+    uint32_t n, T, M;   // integers, tuples, padded tuples (to the codec's unit)
+    uint32_t c0, nch;   // first chunk, chunks
+    uint32_t b0;        // first Group-PFD block
+};
+
+// A chunk: units [u0, u0 + nu) of list `list` (tuples, or octets for
+// Group-AFOR).
+struct EChunk {
+    uint32_t list, u0, nu, pad;
+};
+
+struct EArgs {
+    const uint32_t *in;
+    const EList *lists;
+    const EChunk *chunks;
+    uint32_t nlists, nchunks;
+    uint64_t ntup;          // padded tuples of all lists
+    uint32_t k, lk, cg, ld, delta, pfd_pos, zn, zd, nblocks, pad;
+    uint8_t *W;             // width of every padded tuple
+    uint32_t *sizes;        // per list: C, D, E (words)
+    uint32_t *out;          // the streams
+    uint64_t out_words;
+    // per codec scratch
+    uint32_t *chs;          // chunk summaries
+    uint32_t *chb;          // per chunk: entry state and bases
+    uint32_t *tw;           // per tuple words (positions, offsets, selector info)
+    uint32_t *tw2;
+    uint8_t *ob;            // per octet bytes (Group-AFOR: omax, then frame widths)
+    uint8_t *och;           // Group-AFOR: frame choice per octet
+    uint64_t *mat;          // Group-AFOR: chunk matrices (16) and end costs (4)
+    uint32_t *blk;          // Group-PFD: per block desc, exception words, row base, exception base
+    uint32_t *slot;         // Group-PFD: slot of every integer
+    uint32_t *xbit;         // Group-PFD: exception bitmap of every integer
+};
+
+__device__ __forceinline__ uint32_t width_of(uint32_t x) { return x ? 32u - (uint32_t)__builtin_clz(x) : 0u; }
+
+// Integer i of list L as coded: its d-gap for a docID list, 0 past the end.
+__device__ __forceinline__ uint32_t coded(const EArgs &a, const EList &L, uint64_t i) {
+    if (i >= L.n) return 0u;
+    const uint32_t *x = a.in + L.in_off;
+    return a.delta ? x[i] - (i ? x[i - 1] : 0u) : x[i];
+}
+
+// List of global tuple g (binary search over the lists' first tuples).
+__device__ __forceinline__ uint32_t list_of_tuple(const EArgs &a, uint64_t g) {
+    uint32_t lo = 0, hi = a.nlists;   // invariant: lists[lo].t0 <= g < lists[hi].t0 (hi: end)
+    while (hi - lo > 1u) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a.lists[mid].t0 <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// ---- widths ----------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_widths(EArgs a) {
+    const uint64_t g = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (g >= a.ntup) return;
+    const EList L = a.lists[list_of_tuple(a, g)];
+    const uint64_t t = g - L.t0;
+    uint32_t o = 0;
+    for (uint32_t c = 0; c < a.k; c++) o |= coded(a, L, t * a.k + c);
+    a.W[g] = (uint8_t)width_of(o);
+}
+
+// ---- Group-Scheme (Section 5) --------------------------------------------------
+// unary code length u of a tuple of width w (eq. (1)); its width is cg * u (eq. (2))
+__device__ __forceinline__ uint32_t gsc_units(uint32_t w, uint32_t cg) { return max(1u, (w + cg - 1u) / cg); }
+
+// One tuple's step of the control stream: the position of its terminator
+// and the position after it (incomplete units do not cross a byte).
+__device__ __forceinline__ uint32_t gsc_step(uint32_t pos, uint32_t u, bool iu, uint32_t &z) {
+    if (iu) {
+        const uint32_t left = 8u - (pos & 7u);
+        if (u > left) pos += left;
+    }
+    z = pos + u - 1u;
+    return pos + u;
+}
+
+// Step A, one lane per (chunk, entry state s): IU enters at bit s mod 8;
+// summary per state: exit state | control bits << 3; plus the chunk's data
+// bits (state 0's lane).
+__global__ __launch_bounds__(kThreads) void k_gsc_chunkA(EArgs a) {
+    const uint32_t id = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t ns = a.ld == GC_LD_IU ? 8u : 1u;
+    if (id >= a.nchunks * ns) return;
+    const uint32_t ch = id / ns, s = id % ns;
+    const EChunk C = a.chunks[ch];
+    const EList L = a.lists[C.list];
+    const uint8_t *W = a.W + L.t0 + C.u0;
+    uint32_t pos = s, dbits = 0, z;
+    for (uint32_t t = 0; t < C.nu; t++) {
+        const uint32_t u = gsc_units(W[t], a.cg);
+        pos = gsc_step(pos, u, a.ld == GC_LD_IU, z);
+        dbits += a.cg * u;
+    }
+    a.chs[2u * (ch * 8u + s)] = ((pos - s) << 3) | (pos & 7u);
+    if (s == 0) a.chs[2u * (ch * 8u) + 1u] = dbits;
+}
+
+// Step B, one lane per list: every chunk's entry control bit and data bit;
+// the list's C and D.
+__global__ __launch_bounds__(kThreads) void k_gsc_listB(EArgs a) {
+    const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= a.nlists) return;
+    const EList L = a.lists[i];
+    uint32_t pos = 0, dbits = 0;
+    for (uint32_t c = L.c0; c < L.c0 + L.nch; c++) {
+        a.chb[2u * c] = pos;
+        a.chb[2u * c + 1u] = dbits;
+        const uint32_t s = a.ld == GC_LD_IU ? pos & 7u : 0u;
+        pos += a.chs[2u * (c * 8u + s)] >> 3;
+        dbits += a.chs[2u * (c * 8u) + 1u];
+    }
+    uint32_t cbits = pos;
+    if (a.ld == GC_LD_BINARY) {
+        const uint32_t fields = a.cg == 1u ? 3u : a.cg == 8u ? 4u : 2u, ubits = a.cg == 1u ? 16u : 8u;
+        cbits = L.T ? ((L.T - 1u) / fields + 1u) * ubits : 0u;
+    }
+    a.sizes[3u * i] = ((cbits + 31u) / 32u + 3u) / 4u * 4u;
+    a.sizes[3u * i + 1u] = a.k * ((dbits + 31u) / 32u);
+    a.sizes[3u * i + 2u] = 0u;
+}
+
+// Step C, one lane per chunk: every tuple's terminator (unary) and data bit.
+__global__ __launch_bounds__(kThreads) void k_gsc_chunkC(EArgs a) {
+    const uint32_t ch = blockIdx.x * kThreads + threadIdx.x;
+    if (ch >= a.nchunks) return;
+    const EChunk C = a.chunks[ch];
+    const EList L = a.lists[C.list];
+    const uint64_t g0 = L.t0 + C.u0;
+    uint32_t pos = a.chb[2u * ch], dbits = a.chb[2u * ch + 1u], z = 0;
+    for (uint32_t t = 0; t < C.nu; t++) {
+        const uint32_t u = gsc_units(a.W[g0 + t], a.cg);
+        pos = gsc_step(pos, u, a.ld == GC_LD_IU, z);
+        a.tw[g0 + t] = z;
+        a.tw2[g0 + t] = dbits;
+        dbits += a.cg * u;
+    }
+}
+
+// ---- Group-Simple (Section 4, Algorithm 1) -------------------------------------
+// From tuple j: the first selector whose NUM next tuples -- or all that
+// remain -- fit its width; code = selector | tuples covered << 4.
+__global__ __launch_bounds__(kThreads) void k_sim_cover(EArgs a) {
+    const uint64_t g = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (g >= a.ntup) return;
+    const EList L = a.lists[list_of_tuple(a, g)];
+    const uint32_t j = (uint32_t)(g - L.t0);
+    const uint8_t *W = a.W + L.t0;
+    const uint32_t left = L.T - j;
+    uint32_t pick = 9, cover = 1;
+    for (uint32_t i = 0; i < 10u; i++) {
+        const uint32_t num = kNum[i], lim = min(num, left);
+        uint32_t p = 0;
+        while (p < lim && W[j + p] <= kBw[i]) p++;
+        if (p == num || p == left) {
+            pick = i;
+            cover = p;
+            break;
+        }
+    }
+    a.tw[g] = pick | (cover << 4);
+}
+
+// Step A, one lane per (chunk, entry offset e < 32): the chain entering the
+// chunk at tuple u0 + e; summary: exit offset | selectors << 5.
+__global__ __launch_bounds__(kThreads) void k_sim_chainA(EArgs a) {
+    const uint32_t id = blockIdx.x * kThreads + threadIdx.x;
+    if (id >= a.nchunks * 32u) return;
+    const uint32_t ch = id >> 5, e = id & 31u;
+    const EChunk C = a.chunks[ch];
+    const EList L = a.lists[C.list];
+    const uint32_t *cv = a.tw + L.t0;
+    const uint32_t end = C.u0 + C.nu;
+    uint32_t j = C.u0 + e, cnt = 0;
+    while (j < end) {
+        j += cv[j] >> 4;
+        cnt++;
+    }
+    a.chs[ch * 32u + e] = (j - end) | (cnt << 5);
+}
+
+// Step B, one lane per list: entry offset and first selector of every
+// chunk; C and D.
+__global__ __launch_bounds__(kThreads) void k_sim_listB(EArgs a) {
+    const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= a.nlists) return;
+    const EList L = a.lists[i];
+    uint32_t e = 0, sel = 0;
+    for (uint32_t c = L.c0; c < L.c0 + L.nch; c++) {
+        a.chb[2u * c] = e;
+        a.chb[2u * c + 1u] = sel;
+        const uint32_t v = a.chs[c * 32u + e];
+        e = v & 31u;
+        sel += v >> 5;
+    }
+    a.sizes[3u * i] = ((sel * 4u + 31u) / 32u + 3u) / 4u * 4u;
+    a.sizes[3u * i + 1u] = a.k * sel;
+    a.sizes[3u * i + 2u] = 0u;
+}
+
+// Step C, one lane per chunk: every tuple's selector index << 10 | selector
+// << 5 | its place in the selector; selectors to the control area.
+__global__ __launch_bounds__(kThreads) void k_sim_chainC(EArgs a) {
+    const uint32_t ch = blockIdx.x * kThreads + threadIdx.x;
+    if (ch >= a.nchunks) return;
+    const EChunk C = a.chunks[ch];
+    const EList L = a.lists[C.list];
+    const uint32_t *cv = a.tw + L.t0;
+    uint32_t *info = a.tw2 + L.t0;
+    gu32 *ctrl = (gu32 *)(a.out + L.out_off + 4u);
+    const uint32_t end = C.u0 + C.nu;
+    uint32_t j = C.u0 + a.chb[2u * ch], s = a.chb[2u * ch + 1u];
+    while (j < end) {
+        const uint32_t v = cv[j], sel = v & 15u, cover = v >> 4;
+        atomicOr((uint32_t *)&ctrl[s >> 3], sel << (4u * (s & 7u)));
+        for (uint32_t jj = 0; jj < cover; jj++) info[j + jj] = (s << 10) | (sel << 5) | jj;
+        j += cover;
+        s++;
+    }
+}
+
+// ---- Group-AFOR (Section 6.1) ---------------------------------------------------
+// Octet o (8 tuples): the widest tuple.
+__global__ __launch_bounds__(kThreads) void k_afor_omax(EArgs a) {
+    const uint64_t o = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (o >= a.ntup / 8u) return;
+    uint32_t m = 0;
+    for (int t = 0; t < 8; t++) m = max(m, (uint32_t)a.W[8u * o + t]);
+    a.ob[o] = (uint8_t)m;
+}
+
+// The backward programme over octets [o0, o1) of a list of `oct` octets
+// (global octet o of the list at om[o]), from the costs v[0..3] of octets
+// o1 .. o1 + 3; returns the costs of o0 .. o0 + 3 in v; with `ch`, writes
+// every octet's choice (frame of 32, 16 or 8 tuples; ties keep the larger).
+__device__ __forceinline__ void afor_dp(const uint8_t *om, uint32_t oct, uint32_t o0, uint32_t o1, uint32_t k,
+                                        uint64_t (&v)[4], uint8_t *ch) {
+    uint64_t c1 = v[0], c2 = v[1], c3 = v[2], c4 = v[3];   // cost[o + 1 .. o + 4]
+    for (uint32_t o = o1; o-- > o0;) {
+        uint64_t best = kInf;
+        uint32_t bf = 8;
+        uint32_t b = 0;
+        const uint32_t F[3] = {32u, 16u, 8u};
+        for (int fi = 0; fi < 3; fi++) {
+            const uint32_t no = F[fi] / 8u;
+            if (o + no > oct) continue;
+            b = 0;
+            for (uint32_t q = o; q < o + no; q++) b = max(b, (uint32_t)om[q]);
+            const uint64_t next = no == 4u ? c4 : no == 2u ? c2 : c1;
+            const uint64_t c = next >= kInf ? kInf : 8ull + (uint64_t)k * F[fi] * b + next;
+            if (c < best) {
+                best = c;
+                bf = F[fi];
+            }
+        }
+        if (ch) ch[o] = (uint8_t)bf;
+        c4 = c3;
+        c3 = c2;
+        c2 = c1;
+        c1 = best;
+    }
+    v[0] = c1;
+    v[1] = c2;
+    v[2] = c3;
+    v[3] = c4;
+}
+
+// Step A of the costs, one lane per (chunk, column j < 4): the chunk's
+// min-plus matrix column j (start costs from end costs e_j).
+__global__ __launch_bounds__(kThreads) void k_afor_dpA(EArgs a) {
+    const uint32_t id = blockIdx.x * kThreads + threadIdx.x;
+    if (id >= a.nchunks * 4u) return;
+    const uint32_t ch = id >> 2, j = id & 3u;
+    const EChunk C = a.chunks[ch];
+    const EList L = a.lists[C.list];
+    uint64_t v[4] = {kInf, kInf, kInf, kInf};
+    v[j] = 0;
+    afor_dp(a.ob + L.t0 / 8u, L.M / 8u, C.u0, C.u0 + C.nu, a.k, v, nullptr);
+    for (int i = 0; i < 4; i++) a.mat[20u * ch + 4u * i + j] = v[i];
+}
+
+// Step B of the costs, one lane per list, from its last chunk back: the
+// true costs at every chunk's end.
+__global__ __launch_bounds__(kThreads) void k_afor_dpB(EArgs a) {
+    const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= a.nlists) return;
+    const EList L = a.lists[i];
+    uint64_t v[4] = {0, kInf, kInf, kInf};   // past the last octet
+    for (uint32_t c = L.c0 + L.nch; c-- > L.c0;) {
+        uint64_t *m = a.mat + 20u * c;
+        for (int r = 0; r < 4; r++) m[16 + r] = v[r];
+        uint64_t w[4];
+        for (int r = 0; r < 4; r++) {
+            uint64_t best = kInf;
+            for (int q = 0; q < 4; q++)
+                if (m[4 * r + q] < kInf && v[q] < kInf) best = min(best, m[4 * r + q] + v[q]);
+            w[r] = best;
+        }
+        for (int r = 0; r < 4; r++) v[r] = w[r];
+    }
+}
+
+// Step C of the costs, one lane per chunk: the choices from the true end
+// costs.
+__global__ __launch_bounds__(kThreads) void k_afor_dpC(EArgs a) {
+    const uint32_t ch = blockIdx.x * kThreads + threadIdx.x;
+    if (ch >= a.nchunks) return;
+    const EChunk C = a.chunks[ch];
+    const EList L = a.lists[C.list];
+    uint64_t v[4];
+    for (int r = 0; r < 4; r++) v[r] = a.mat[20u * ch + 16u + r];
+    afor_dp(a.ob + L.t0 / 8u, L.M / 8u, C.u0, C.u0 + C.nu, a.k, v, a.och + L.t0 / 8u);
+}
+
+// width of the frame of F tuples from octet o
+__device__ __forceinline__ uint32_t afor_b(const uint8_t *om, uint32_t o, uint32_t F) {
+    uint32_t b = 0;
+    for (uint32_t q = o; q < o + F / 8u; q++) b = max(b, (uint32_t)om[q]);
+    return b;
+}
+
+// Step A of the frames, one lane per (chunk, entry octet e < 4): exit
+// octet, frames and data bits of the chain.
+__global__ __launch_bounds__(kThreads) void k_afor_chainA(EArgs a) {
+    const uint32_t id = blockIdx.x * kThreads + threadIdx.x;
+    if (id >= a.nchunks * 4u) return;
+    const uint32_t ch = id >> 2, e = id & 3u;
+    const EChunk C = a.chunks[ch];
+    const EList L = a.lists[C.list];
+    const uint8_t *om = a.ob + L.t0 / 8u, *cho = a.och + L.t0 / 8u;
+    const uint32_t end = C.u0 + C.nu;
+    uint32_t o = C.u0 + e, frames = 0, bits = 0;
+    while (o < end) {
+        const uint32_t F = cho[o];
+        bits += F * afor_b(om, o, F);
+        frames++;
+        o += F / 8u;
+    }
+    a.chs[3u * (ch * 4u + e)] = o - end;
+    a.chs[3u * (ch * 4u + e) + 1u] = frames;
+    a.chs[3u * (ch * 4u + e) + 2u] = bits;
+}
+
+// Step B of the frames, one lane per list.
+__global__ __launch_bounds__(kThreads) void k_afor_chainB(EArgs a) {
+    const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= a.nlists) return;
+    const EList L = a.lists[i];
+    uint32_t e = 0, frames = 0, bits = 0;
+    for (uint32_t c = L.c0; c < L.c0 + L.nch; c++) {
+        a.chb[3u * c] = e;
+        a.chb[3u * c + 1u] = frames;
+        a.chb[3u * c + 2u] = bits;
+        const uint32_t *s = a.chs + 3u * (c * 4u + e);
+        e = s[0];
+        frames += s[1];
+        bits += s[2];
+    }
+    a.sizes[3u * i] = ((frames * 8u + 31u) / 32u + 3u) / 4u * 4u;
+    a.sizes[3u * i + 1u] = a.k * ((bits + 31u) / 32u);
+    a.sizes[3u * i + 2u] = 0u;
+}
+
+// Step C of the frames, one lane per chunk: frame bytes to the control
+// area; every octet's data bit and width (octet words in tw, widths in och).
+__global__ __launch_bounds__(kThreads) void k_afor_chainC(EArgs a) {
+    const uint32_t ch = blockIdx.x * kThreads + threadIdx.x;
+    if (ch >= a.nchunks) return;
+    const EChunk C = a.chunks[ch];
+    const EList L = a.lists[C.list];
+    const uint8_t *om = a.ob + L.t0 / 8u;
+    uint8_t *cho = a.och + L.t0 / 8u;
+    uint32_t *ooff = a.tw + L.t0 / 8u;
+    gu32 *ctrl = (gu32 *)(a.out + L.out_off + 4u);
+    const uint32_t end = C.u0 + C.nu;
+    uint32_t o = C.u0 + a.chb[3u * ch], f = a.chb[3u * ch + 1u], bits = a.chb[3u * ch + 2u];
+    while (o < end) {
+        const uint32_t F = cho[o], b = afor_b(om, o, F);
+        const uint32_t cls = F == 8u ? 0u : F == 16u ? 1u : 2u;
+        atomicOr((uint32_t *)&ctrl[f >> 2], (b | (cls << 6)) << (8u * (f & 3u)));
+        for (uint32_t q = 0; q < F / 8u; q++) {
+            ooff[o + q] = bits + q * 8u * b;
+            cho[o + q] = (uint8_t)b;   // the choice is no longer needed past here
+        }
+        bits += F * b;
+        f++;
+        o += F / 8u;
+    }
+}
+
+// ---- data rows of Group-Simple, Group-Scheme and Group-AFOR ------------------------
+// One lane per tuple: its k integers at their component bit offset.
+__global__ __launch_bounds__(kThreads) void k_emit_tuples(EArgs a, int codec) {
+    const uint64_t g = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (g >= a.ntup) return;
+    const EList L = a.lists[list_of_tuple(a, g)];
+    const uint32_t t = (uint32_t)(g - L.t0);
+    if (t >= L.T) return;
+    uint32_t *base = a.out + L.out_off;
+    const uint32_t C = base[2];
+    gu32 *data = (gu32 *)(base + 4u + C);
+    uint32_t O, bw;
+    if (codec == GC_SIMPLE) {
+        const uint32_t v = a.tw2[g], s = v >> 10, sel = (v >> 5) & 15u, jj = v & 31u;
+        bw = kBw[sel];
+        // a selector's row holds its tuples side by side (NUM * BW <= 32)
+        for (uint32_t c = 0; c < a.k; c++)
+            atomicOr((uint32_t *)&data[s * a.k + c], coded(a, L, (uint64_t)t * a.k + c) << (jj * bw));
+        return;
+    }
+    if (codec == GC_SCHEME) {
+        bw = a.cg * gsc_units(a.W[g], a.cg);
+        O = a.tw2[g];
+        // control: clear the unary terminator, or set the binary length field
+        gu32 *ctrl = (gu32 *)(base + 4u);
+        const uint32_t u = bw / a.cg;
+        if (a.ld == GC_LD_BINARY) {
+            const uint32_t fields = a.cg == 1u ? 3u : a.cg == 8u ? 4u : 2u, ubits = a.cg == 1u ? 16u : 8u;
+            const uint32_t fb = a.cg == 1u ? 5u : a.cg == 2u ? 4u : a.cg == 4u ? 3u : 2u;
+            const uint32_t pos = (t / fields) * ubits + (t % fields) * fb;
+            atomicOr((uint32_t *)&ctrl[pos >> 5], (u - 1u) << (pos & 31u));
+        } else {
+            const uint32_t z = a.tw[g];
+            atomicAnd((uint32_t *)&ctrl[z >> 5], ~(1u << (z & 31u)));
+        }
+    } else {
+        const uint32_t o = t >> 3;
+        bw = a.och[L.t0 / 8u + o];
+        O = a.tw[L.t0 / 8u + o] + (t & 7u) * bw;
+    }
+    if (!bw) return;
+    const uint32_t wi = O >> 5, sh = O & 31u;
+    for (uint32_t c = 0; c < a.k; c++) {
+        const uint32_t x = coded(a, L, (uint64_t)t * a.k + c);
+        atomicOr((uint32_t *)&data[wi * a.k + c], x << sh);
+        if (sh + bw > 32u) atomicOr((uint32_t *)&data[(wi + 1u) * a.k + c], x >> (32u - sh));
+    }
+}
+
+// ---- Group-PFD (Section 6.2) -------------------------------------------------------
+// One lane per 32-tuple block: b (Step 2), the exceptions (Step 3), their
+// value width (Step 4) and, for the linked layout, the compulsory
+// exceptions; every slot and the exception bitmap to scratch; the block's
+// descriptor and exception words.
+__global__ __launch_bounds__(kThreads) void k_pfd_blocks(EArgs a) {
+    const uint32_t bi = blockIdx.x * kThreads + threadIdx.x;
+    if (bi >= a.nblocks) return;
+    const uint64_t g0 = 32ull * bi;   // first tuple
+    const EList L = a.lists[list_of_tuple(a, g0)];
+    const uint32_t t0 = (uint32_t)(g0 - L.t0);
+    const uint32_t k = a.k, BI = 32u * k;
+    const uint8_t *W = a.W + g0;
+    uint32_t cnt[34];
+    for (int i = 0; i < 34; i++) cnt[i] = 0;
+    for (int t = 0; t < 32; t++) cnt[W[t]]++;
+    uint32_t wider = 32u - cnt[0], b = 0;
+    while ((uint64_t)wider * a.zd >= (uint64_t)a.zn * 32u) {
+        b++;
+        wider -= cnt[b];
+    }
+    const uint64_t x0 = (uint64_t)t0 * k;   // first integer of the block in its list
+    uint32_t *slot = a.slot + g0 * k;
+    uint32_t *xb = a.xbit + g0 * k / 32u;
+    for (uint32_t w = 0; w < BI / 32u; w++) xb[w] = 0u;
+    uint32_t nx = 0, maxw = 0, nt = 0;
+    for (uint32_t t = 0; t < 32u; t++) {
+        const bool wide = W[t] > b;
+        bool any = false;
+        for (uint32_t c = 0; c < k; c++) {
+            const uint32_t p = t * k + c;
+            const uint32_t x = coded(a, L, x0 + p);
+            const uint32_t w = width_of(x);
+            slot[p] = x;
+            if (wide && w > b) {
+                xb[p >> 5] |= 1u << (p & 31u);
+                nx++;
+                any = true;
+                maxw = max(maxw, w);
+            }
+        }
+        nt += any ? 1u : 0u;
+    }
+    const uint32_t wcode = nx == 0 ? 0u : maxw <= 8u ? 1u : maxw <= 16u ? 2u : 3u;
+    const uint32_t ew = wcode ? 4u << wcode : 0u;
+    uint32_t nexc = 0, first = 0;
+    const uint32_t M = b >= 32u ? 0xFFFFFFFFu : (1u << b) - 1u;
+    if (a.pfd_pos == GC_PFD_LINKED) {
+        // the chain through the slots, with a compulsory exception wherever
+        // the gap to the next one does not fit b bits
+        const uint64_t lim = b >= 32u ? ~0ull : (1ull << b) - 1u;
+        int64_t prev = -1;
+        for (uint32_t p = 0; p < BI; p++) {
+            if (!((xb[p >> 5] >> (p & 31u)) & 1u)) continue;
+            if (prev >= 0) {
+                while ((uint64_t)((int64_t)p - prev - 1) > lim) {
+                    const uint32_t cp = (uint32_t)(prev + (int64_t)(1ull << b));
+                    xb[cp >> 5] |= 1u << (cp & 31u);
+                    slot[(uint32_t)prev] = cp - (uint32_t)prev - 1u;
+                    prev = cp;
+                    nexc++;
+                }
+                slot[(uint32_t)prev] = p - (uint32_t)prev - 1u;
+            } else {
+                first = p;
+            }
+            prev = p;
+            nexc++;
+        }
+        if (prev >= 0) slot[(uint32_t)prev] = 0u;
+    } else {
+        nexc = nx;
+        first = nt;
+        for (uint32_t p = 0; p < BI; p++)
+            if ((xb[p >> 5] >> (p & 31u)) & 1u) slot[p] &= M;
+    }
+    const uint32_t vals = nexc ? (nexc * ew + 31u) / 32u : 0u;
+    const uint32_t xw = !nexc ? 0u : a.pfd_pos == GC_PFD_BITMAP ? 1u + (first * k + 31u) / 32u + vals : vals;
+    uint32_t *bk = a.blk + 4u * bi;
+    bk[0] = b | (wcode << 6) | (first << 8) | (nexc << 20);
+    bk[1] = xw;
+}
+
+// One lane per list: row and exception word bases of its blocks; C, D, E.
+__global__ __launch_bounds__(kThreads) void k_pfd_listB(EArgs a) {
+    const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= a.nlists) return;
+    const EList L = a.lists[i];
+    const uint32_t nb = L.M / 32u;
+    uint32_t rows = 0, xw = 0;
+    for (uint32_t j = 0; j < nb; j++) {
+        uint32_t *bk = a.blk + 4u * (L.b0 + j);
+        bk[2] = rows;
+        bk[3] = xw;
+        rows += bk[0] & 63u;
+        xw += bk[1];
+    }
+    a.sizes[3u * i] = (nb + 3u) / 4u * 4u;
+    a.sizes[3u * i + 1u] = a.k * rows;
+    a.sizes[3u * i + 2u] = xw;
+}
+
+// Appends v (nb bits) to a word stream at out[*w], bit position *acc_n of
+// the 64-bit accumulator.
+struct WordSink {
+    gu32 *out;
+    uint32_t stride, w, n;
+    uint64_t acc;
+    __device__ __forceinline__ void put(uint32_t v, uint32_t nb) {
+        if (!nb) return;
+        acc |= (uint64_t)(nb >= 32u ? v : (v & ((1u << nb) - 1u))) << n;
+        n += nb;
+        while (n >= 32u) {
+            out[(uint64_t)w * stride] = (uint32_t)acc;
+            w++;
+            acc >>= 32;
+            n -= 32u;
+        }
+    }
+    __device__ __forceinline__ void flush() {
+        if (n) out[(uint64_t)w * stride] = (uint32_t)acc;
+        if (n) w++;
+        acc = 0;
+        n = 0;
+    }
+};
+
+// One lane per block: descriptor, data rows (component c of row r at word
+// k*r + c) and exception words.
+__global__ __launch_bounds__(kThreads) void k_pfd_emit(EArgs a) {
+    const uint32_t bi = blockIdx.x * kThreads + threadIdx.x;
+    if (bi >= a.nblocks) return;
+    const uint64_t g0 = 32ull * bi;
+    const EList L = a.lists[list_of_tuple(a, g0)];
+    const uint32_t j = (uint32_t)((g0 - L.t0) / 32u);
+    const uint32_t k = a.k, BI = 32u * k;
+    const uint32_t *bk = a.blk + 4u * bi;
+    const uint32_t desc = bk[0], b = desc & 63u, wcode = (desc >> 6) & 3u, first = (desc >> 8) & 0xFFFu,
+                   nexc = desc >> 20;
+    uint32_t *base = a.out + L.out_off;
+    const uint32_t C = base[2], D = base[3];
+    gu32 *ctrl = (gu32 *)(base + 4u);
+    ctrl[j] = desc;
+    const uint32_t *slot = a.slot + g0 * k;
+    const uint32_t *xb = a.xbit + g0 * k / 32u;
+    gu32 *rows = (gu32 *)(base + 4u + C) + (uint64_t)bk[2] * k;
+    for (uint32_t c = 0; c < k && b; c++) {
+        WordSink s{rows + c, k, 0u, 0u, 0ull};
+        for (uint32_t t = 0; t < 32u; t++) s.put(slot[t * k + c], b);
+    }
+    if (!nexc) return;
+    WordSink e{(gu32 *)(base + 4u + C + D) + bk[3], 1u, 0u, 0u, 0ull};
+    if (a.pfd_pos == GC_PFD_BITMAP) {
+        uint32_t tm = 0;
+        for (uint32_t t = 0; t < 32u; t++) {
+            bool any = false;
+            for (uint32_t c = 0; c < k; c++) any |= ((xb[(t * k + c) >> 5] >> ((t * k + c) & 31u)) & 1u) != 0u;
+            tm |= (any ? 1u : 0u) << t;
+        }
+        e.put(tm, 32u);
+        for (uint32_t t = 0; t < 32u; t++) {
+            if (!((tm >> t) & 1u)) continue;
+            for (uint32_t c = 0; c < k; c++) e.put((xb[(t * k + c) >> 5] >> ((t * k + c) & 31u)) & 1u, 1u);
+        }
+        e.flush();
+        (void)first;
+    }
+    const uint32_t ew = 4u << wcode;
+    const uint64_t x0 = (uint64_t)(j * 32u) * k;
+    for (uint32_t p = 0; p < BI; p++)
+        if ((xb[p >> 5] >> (p & 31u)) & 1u) e.put(coded(a, L, x0 + p), ew);
+    e.flush();
+}
+
+// ---- output area -------------------------------------------------------------------------
+// One lane per output word: 0, or 1s over a unary Group-Scheme control
+// area; the four header words of every stream.
+__global__ __launch_bounds__(kThreads) void k_fill(EArgs a, uint32_t w0h, int unary) {
+    const uint64_t w = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (w >= a.out_words) return;
+    uint32_t lo = 0, hi = a.nlists;
+    while (hi - lo > 1u) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a.lists[mid].out_off <= w) lo = mid;
+        else hi = mid;
+    }
+    const EList L = a.lists[lo];
+    const uint64_t r = w - L.out_off;
+    const uint32_t C = a.sizes[3u * lo];
+    uint32_t v = 0;
+    if (r == 0) v = w0h;
+    else if (r == 1) v = L.n;
+    else if (r == 2) v = C;
+    else if (r == 3) v = a.sizes[3u * lo + 1u];
+    else if (unary && r < 4u + C) v = 0xFFFFFFFFu;
+    a.out[w] = v;
+}
+
+}  // namespace gcenc
+
+using namespace gcenc;
+
+namespace {
+
+template <typename T>
+gc_status dalloc(T **p, size_t n, std::vector<void *> &keep) {
+    *p = nullptr;
+    if (!n) n = 1;
+    if (hipMalloc((void **)p, n * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        return GC_ENOMEM;
+    }
+    keep.push_back((void *)*p);
+    return GC_OK;
+}
+
+unsigned grid(uint64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+#define ENC_OK(x)                                \
+    do {                                         \
+        if ((x) != hipSuccess) {                 \
+            (void)hipGetLastError();             \
+            rc = GC_EDEVICE;                     \
+            goto done;                           \
+        }                                        \
+    } while (0)
+
+}  // namespace
+
+extern "C" gc_status gc_encode_lists_gpu(const uint32_t *d_in, const uint64_t *h_in_offs, size_t nlists,
+                                         gc_codec codec, const gc_params *p, uint32_t *d_out,
+                                         size_t out_cap_words, uint64_t *h_out_offs, void *hip_stream) {
+    if (!d_in || !h_in_offs || !p || !d_out || !h_out_offs || nlists == 0 || nlists > 0x0FFFFFFFu)
+        return GC_EINVAL;
+    if ((int)codec < 0 || (int)codec > 3 || p->k < 4 || p->k > 64 || (p->k & (p->k - 1)) || (p->flags & ~GC_DELTA))
+        return GC_EINVAL;
+    if (codec == GC_SCHEME && ((p->cg != 1 && p->cg != 2 && p->cg != 4 && p->cg != 8) || p->ld > 2 ||
+                               (p->ld == GC_LD_IU && p->cg < 4)))
+        return GC_EINVAL;
+    if (codec == GC_PFD && (p->zeta_num == 0 || p->zeta_den == 0 || p->zeta_num >= p->zeta_den || p->pfd_pos > 1))
+        return GC_EINVAL;
+    const uint32_t k = p->k;
+    uint32_t lk = 0;
+    while ((1u << lk) < k) lk++;
+    const uint32_t unit = codec == GC_AFOR ? 8u : codec == GC_PFD ? 32u : 1u;
+    // lists, chunks
+    std::vector<EList> L(nlists);
+    std::vector<EChunk> CH;
+    uint64_t ntup = 0;
+    uint32_t nblocks = 0;
+    for (size_t i = 0; i < nlists; i++) {
+        if (h_in_offs[i + 1] < h_in_offs[i]) return GC_EINVAL;
+        const uint64_t n = h_in_offs[i + 1] - h_in_offs[i];
+        if (n > (1ull << 28)) return GC_EINVAL;   // component bit offsets stay below 2^32
+        EList &e = L[i];
+        e.in_off = h_in_offs[i];
+        e.out_off = 0;
+        e.t0 = ntup;
+        e.n = (uint32_t)n;
+        e.T = (uint32_t)((n + k - 1) / k);
+        e.M = (e.T + unit - 1) / unit * unit;
+        e.b0 = nblocks;
+        if (codec == GC_PFD) nblocks += e.M / 32u;
+        const uint32_t units = codec == GC_AFOR ? e.M / 8u : e.T;
+        const uint32_t per = codec == GC_AFOR ? kOctChunk : kTupChunk;
+        e.c0 = (uint32_t)CH.size();
+        e.nch = codec == GC_PFD ? 0u : (units + per - 1u) / per;
+        for (uint32_t c = 0; c < e.nch; c++) CH.push_back(EChunk{(uint32_t)i, c * per, std::min(per, units - c * per), 0u});
+        ntup += e.M;
+    }
+    if (ntup * k > (1ull << 34)) return GC_EINVAL;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    std::vector<void *> keep;
+    gc_status rc = GC_OK;
+    EArgs a;
+    std::memset(&a, 0, sizeof(a));
+    std::vector<uint32_t> sizes(3 * nlists);
+    uint64_t total = 0;
+    EList *d_lists = nullptr;
+    EChunk *d_chunks = nullptr;
+    const uint32_t nch = (uint32_t)CH.size();
+    if ((rc = dalloc(&d_lists, nlists, keep)) || (rc = dalloc(&d_chunks, nch, keep))) goto done;
+    ENC_OK(hipMemcpyAsync(d_lists, L.data(), nlists * sizeof(EList), hipMemcpyHostToDevice, s));
+    if (nch) ENC_OK(hipMemcpyAsync(d_chunks, CH.data(), nch * sizeof(EChunk), hipMemcpyHostToDevice, s));
+    a.in = d_in;
+    a.lists = d_lists;
+    a.chunks = d_chunks;
+    a.nlists = (uint32_t)nlists;
+    a.nchunks = nch;
+    a.ntup = ntup;
+    a.k = k;
+    a.lk = lk;
+    a.cg = codec == GC_SCHEME ? p->cg : 1u;
+    a.ld = codec == GC_SCHEME ? p->ld : 0u;
+    a.delta = (p->flags & GC_DELTA) ? 1u : 0u;
+    a.pfd_pos = codec == GC_PFD ? p->pfd_pos : 0u;
+    a.zn = p->zeta_num;
+    a.zd = p->zeta_den;
+    a.nblocks = nblocks;
+    a.out = d_out;
+    if ((rc = dalloc(&a.W, ntup, keep)) || (rc = dalloc(&a.sizes, 3 * nlists, keep))) goto done;
+    if (ntup) hipLaunchKernelGGL(k_widths, dim3(grid(ntup)), dim3(kThreads), 0, s, a);
+    // sizing
+    if (codec == GC_SCHEME) {
+        if ((rc = dalloc(&a.chs, 16ull * nch, keep)) || (rc = dalloc(&a.chb, 2ull * nch, keep)) ||
+            (rc = dalloc(&a.tw, ntup, keep)) || (rc = dalloc(&a.tw2, ntup, keep)))
+            goto done;
+        const uint32_t ns = a.ld == GC_LD_IU ? 8u : 1u;
+        if (nch) hipLaunchKernelGGL(k_gsc_chunkA, dim3(grid((uint64_t)nch * ns)), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL(k_gsc_listB, dim3(grid(nlists)), dim3(kThreads), 0, s, a);
+        if (nch) hipLaunchKernelGGL(k_gsc_chunkC, dim3(grid(nch)), dim3(kThreads), 0, s, a);
+    } else if (codec == GC_SIMPLE) {
+        if ((rc = dalloc(&a.chs, 32ull * nch, keep)) || (rc = dalloc(&a.chb, 2ull * nch, keep)) ||
+            (rc = dalloc(&a.tw, ntup, keep)) || (rc = dalloc(&a.tw2, ntup, keep)))
+            goto done;
+        if (ntup) hipLaunchKernelGGL(k_sim_cover, dim3(grid(ntup)), dim3(kThreads), 0, s, a);
+        if (nch) hipLaunchKernelGGL(k_sim_chainA, dim3(grid(32ull * nch)), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL(k_sim_listB, dim3(grid(nlists)), dim3(kThreads), 0, s, a);
+    } else if (codec == GC_AFOR) {
+        if ((rc = dalloc(&a.ob, ntup / 8u, keep)) || (rc = dalloc(&a.och, ntup / 8u, keep)) ||
+            (rc = dalloc(&a.mat, 20ull * nch, keep)) || (rc = dalloc(&a.chs, 12ull * nch, keep)) ||
+            (rc = dalloc(&a.chb, 3ull * nch, keep)) || (rc = dalloc(&a.tw, ntup / 8u, keep)))
+            goto done;
+        if (ntup) hipLaunchKernelGGL(k_afor_omax, dim3(grid(ntup / 8u)), dim3(kThreads), 0, s, a);
+        if (nch) hipLaunchKernelGGL(k_afor_dpA, dim3(grid(4ull * nch)), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL(k_afor_dpB, dim3(grid(nlists)), dim3(kThreads), 0, s, a);
+        if (nch) hipLaunchKernelGGL(k_afor_dpC, dim3(grid(nch)), dim3(kThreads), 0, s, a);
+        if (nch) hipLaunchKernelGGL(k_afor_chainA, dim3(grid(4ull * nch)), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL(k_afor_chainB, dim3(grid(nlists)), dim3(kThreads), 0, s, a);
+    } else {
+        if ((rc = dalloc(&a.blk, 4ull * nblocks, keep)) || (rc = dalloc(&a.slot, ntup * k, keep)) ||
+            (rc = dalloc(&a.xbit, ntup * k / 32u + 1u, keep)))
+            goto done;
+        if (nblocks) hipLaunchKernelGGL(k_pfd_blocks, dim3(grid(nblocks)), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL(k_pfd_listB, dim3(grid(nlists)), dim3(kThreads), 0, s, a);
+    }
+    ENC_OK(hipGetLastError());
+    ENC_OK(hipMemcpyAsync(sizes.data(), a.sizes, sizes.size() * 4, hipMemcpyDeviceToHost, s));
+    ENC_OK(hipStreamSynchronize(s));
+    for (size_t i = 0; i < nlists; i++) {
+        L[i].out_off = total;
+        h_out_offs[i] = total;
+        const uint64_t e4 = ((uint64_t)sizes[3 * i + 2] + 3u) / 4u * 4u;
+        total += 4ull + sizes[3 * i] + sizes[3 * i + 1] + e4;
+    }
+    h_out_offs[nlists] = total;
+    if (total > out_cap_words) {
+        rc = GC_ENOSPC;
+        goto done;
+    }
+    a.out_words = total;
+    ENC_OK(hipMemcpyAsync(d_lists, L.data(), nlists * sizeof(EList), hipMemcpyHostToDevice, s));
+    {
+        const uint32_t w0h = header_word0((int)codec, (int)k, codec == GC_SCHEME ? p->cg : 1,
+                                          codec == GC_SCHEME ? p->ld : 0, a.delta, codec == GC_PFD ? p->pfd_pos : 0);
+        hipLaunchKernelGGL(k_fill, dim3(grid(total)), dim3(kThreads), 0, s, a, w0h,
+                           codec == GC_SCHEME && p->ld != GC_LD_BINARY ? 1 : 0);
+    }
+    if (codec == GC_SIMPLE && nch) hipLaunchKernelGGL(k_sim_chainC, dim3(grid(nch)), dim3(kThreads), 0, s, a);
+    if (codec == GC_AFOR && nch) hipLaunchKernelGGL(k_afor_chainC, dim3(grid(nch)), dim3(kThreads), 0, s, a);
+    if (codec == GC_PFD) {
+        if (nblocks) hipLaunchKernelGGL(k_pfd_emit, dim3(grid(nblocks)), dim3(kThreads), 0, s, a);
+    } else if (ntup) {
+        hipLaunchKernelGGL(k_emit_tuples, dim3(grid(ntup)), dim3(kThreads), 0, s, a, (int)codec);
+    }
+    ENC_OK(hipGetLastError());
+    ENC_OK(hipStreamSynchronize(s));
+done:
+    (void)hipStreamSynchronize(s);
+    for (void *q : keep) (void)hipFree(q);
+    return rc;
+}

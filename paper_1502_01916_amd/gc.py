@@ -115,6 +115,8 @@ def lib():
         L.gc_ctx_destroy.argtypes = [vp]
         L.gc_decode.argtypes = [vp, vp, sz, u32p, vp, vp]
         L.gc_decode_noalloc.argtypes = [vp, vp, sz, u32p, vp, vp]
+        L.gc_encode_lists_gpu.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), sz, i, ctypes.POINTER(Params), vp,
+                                          sz, ctypes.POINTER(ctypes.c_uint64), vp]
         L.gc_plan_create.argtypes = [vp, ctypes.POINTER(ListDesc), sz, u32p, ctypes.POINTER(PlanOpts),
                                      vp, vp, ctypes.POINTER(vp)]
         L.gc_plan_destroy.argtypes = [vp]
@@ -144,7 +146,7 @@ def lib():
         L.gc_mlp_train.argtypes = [vp, vp, vp, vp, vp, sz, ctypes.POINTER(AdamOpts), vp, vp]
         L.gc_encode_blocks.argtypes = [vp, vp, sz, i, vp, ctypes.c_uint32, vp, sz, ctypes.POINTER(sz), vp, vp]
         for f in ("gc_encode", "gc_encode_lists", "gc_ctx_create", "gc_ctx_create_opts", "gc_ctx_destroy",
-                  "gc_decode", "gc_decode_noalloc",
+                  "gc_decode", "gc_decode_noalloc", "gc_encode_lists_gpu",
                   "gc_plan_create", "gc_plan_destroy", "gc_decode_batch", "gc_decode_each",
                   "gc_plan_config", "gc_plan_class_tiles", "gc_plan_pack_config", "gc_plan_packed_lists",
                   "gc_sync_status", "gc_block_features",
@@ -214,6 +216,31 @@ def encode_lists(flat, lengths, codecs, plist, nthreads=0):
                                int(nthreads))
     _check("gc_encode_lists", rc)
     return out[:int(offs[-1])], offs
+
+
+def encode_lists_gpu(d_flat, lengths, codec, p, d_out=None, stream=None):
+    """gc_encode_lists_gpu: the lists concatenated in the device tensor
+    d_flat (int32), one codec / Params for all, encoded on the GPU.  Returns
+    (d_streams, stream_offsets[nlists+1]); d_streams is d_out (or a new
+    tensor sized by gc_encoded_bound_words_lists) cut to the streams."""
+    import torch
+    lengths = np.asarray(lengths, dtype=np.int64)
+    nl = lengths.size
+    in_offs = np.zeros(nl + 1, np.uint64)
+    np.cumsum(lengths, out=in_offs[1:])
+    if d_out is None:
+        cod = np.full(nl, int(codec), np.int32)
+        parr = (Params * 1)()
+        parr[0] = p
+        cap = lib().gc_encoded_bound_words_lists(in_offs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), nl,
+                                                 cod.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), parr, 1)
+        d_out = torch.empty(max(int(cap), 1), dtype=torch.int32, device=d_flat.device)
+    offs = np.zeros(nl + 1, np.uint64)
+    rc = lib().gc_encode_lists_gpu(_ptr(d_flat), in_offs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), nl,
+                                   int(codec), ctypes.byref(p), _ptr(d_out), int(d_out.numel()),
+                                   offs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), _stream_handle(stream))
+    _check("gc_encode_lists_gpu", rc)
+    return d_out[:int(offs[-1])], offs
 
 
 # ---------------------------------------------------------------------------
