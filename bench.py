@@ -17,9 +17,10 @@ decoded with one launch sequence per list, directly and replayed from a
 hipGraph; the cfg2 batch (10,000 Zipf-length docID lists and their TF lists in
 five codecs); the four cfg5 batches (1,000,000 lists, median 256, heavy-tailed
 gaps; Group-PFD and Group-AFOR in the 4-way and 64-way layouts); every
-Group-Scheme variant and BP128 beside the other codecs on cfg2; the
-single-list latency of cfg1.  `--workload NAME` measures one workload alone
-(for profiler runs).
+Group-Scheme variant and BP128 beside the other codecs on cfg2; encode speed
+on cfg2, GPU list encoders against the host encoder (streams checked equal);
+the single-list latency of cfg1.  `--workload NAME` measures one workload
+alone (for profiler runs).
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -479,6 +480,42 @@ def per_list_legs(gc, torch, ctx, wl, m, args):
     return res
 
 
+def encode_leg(gc, torch, cfg2_data, reps=3):
+    """Encode speed (Section 7.3.2, Table VII's encode columns) on the cfg2
+    lists, docIDs and TFs, in the five codecs (4-way layout): the GPU list
+    encoders (gc_encode_lists_gpu, input already on the device, streams
+    written to device memory, sizes read back) against the host encoder on
+    every host core (gc_encode_lists); the streams are checked equal."""
+    lengths, docs, tfs = cfg2_data
+    d_docs, d_tfs = gc.to_device(docs), gc.to_device(tfs)
+    out = {}
+    for name, codec, kw in five_codecs(gc):
+        ints = 0
+        t_gpu = t_host = 0.0
+        same = True
+        for flat, d_flat, delta in ((docs, d_docs, True), (tfs, d_tfs, False)):
+            p = gc.params(delta=delta, **kw)
+            got, goffs = gc.encode_lists_gpu(d_flat, lengths, codec, p)   # warm-up, sizes the output
+            d_out = torch.empty(int(goffs[-1]), dtype=torch.int32, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                got, goffs = gc.encode_lists_gpu(d_flat, lengths, codec, p, d_out=d_out)
+            torch.cuda.synchronize()
+            t_gpu += (time.perf_counter() - t0) / reps
+            t0 = time.perf_counter()
+            want, woffs = gc.encode_lists(flat, lengths, codec, p)
+            t_host += time.perf_counter() - t0
+            same = same and np.array_equal(goffs, woffs) and np.array_equal(gc.to_host(got), want)
+            ints += flat.size
+            del got, d_out
+        out[name] = dict(gpu_gints_s=round(ints / t_gpu / 1e9, 3), host_gints_s=round(ints / t_host / 1e9, 3),
+                         gpu_ms=round(1e3 * t_gpu, 3), host_ms=round(1e3 * t_host, 2),
+                         host_threads=os.cpu_count(), identical=bool(same))
+        log("encode %-18s %s" % (name, out[name]))
+    return out
+
+
 def variants_leg(gc, torch, ctx, synth, args, cfg2_data):
     """Section 7.2's trade-off on the cfg2 lists: every variant's bits/int,
     Gints/s and decode-pass % of HBM (docIDs and TFs of one variant per
@@ -567,6 +604,7 @@ def main():
             extra[name] = leg_record(w5, measure(gc, torch, ctx, w5, args))
             del w5
         extra["variants_cfg2"] = variants_leg(gc, torch, ctx, synth, args, cfg2_data)
+        extra["encode_cfg2"] = encode_leg(gc, torch, cfg2_data)
         extra["cfg1_latency"] = cfg1_latency(gc, synth, ctx, torch)
         log("cfg1 single list: %s" % extra["cfg1_latency"])
 
