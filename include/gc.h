@@ -320,6 +320,46 @@ gc_status gc_plan_class_tiles(const gc_plan *plan, uint32_t *tile_ints);
  * not NULL, receives an implementation-specific code of the failed check.  */
 gc_status gc_sync_status(gc_ctx *ctx, void *hip_stream, uint32_t *detail);
 
+/* ---- query processing over decoded lists (Section 7.4) ----------------- */
+
+/* Okapi BM25 parameters (the paper cites Robertson et al. and gives no
+ * values; k1 = 1.2, b = 0.75 are the usual ones).                          */
+typedef struct {
+    float k1, b;
+    float avgdl;          /* mean document length                                */
+    uint32_t topk;        /* documents kept per query, 1 .. 64 (10 in the paper) */
+    uint32_t ndocs;       /* N, documents in the collection (idf; doclen size)   */
+    uint32_t reserved[2]; /* zero                                                */
+} gc_bm25_params;
+
+typedef struct gc_query_plan gc_query_plan;   /* opaque, library-owned */
+
+/* A batch of AND queries over nterms terms: query q has the terms
+ * h_query_terms[q*terms_per_query ..] (term indices, -1 = none; at most 8
+ * per query); h_term_len[t] is the length of term t's posting list.  The
+ * plan cuts every query's shortest list into work items of 8192 postings
+ * and allocates their partial results (device memory, here only).
+ * GC_EINVAL for a term index out of range or bad parameters.               */
+gc_status gc_query_plan_create(const uint32_t *h_term_len, size_t nterms, const int32_t *h_query_terms,
+                               uint32_t terms_per_query, uint32_t nq, const gc_bm25_params *p,
+                               gc_query_plan **plan);
+gc_status gc_query_plan_destroy(gc_query_plan *plan);
+
+/* Runs the plan's queries over decoded lists in device memory: term t's
+ * docIDs (ascending) at d_docs + d_term_off[t] and its TFs at the same
+ * offset of d_tfs (as gc_decode_batch writes them), document lengths
+ * d_doclen[0 .. ndocs).  Every query keeps the documents in all its terms'
+ * lists, scores each by BM25 (the sum over its terms of
+ * idf * tf * (k1 + 1) / (tf + k1 * (1 - b + b * dl / avgdl)), idf =
+ * ln(1 + (N - df + 0.5) / (df + 0.5)), single precision) and writes its
+ * topk best to d_top_doc / d_top_score[q*topk ..], higher score first, then
+ * smaller docID; unused places get docID 0xFFFFFFFF and score 0.  Lookups
+ * go through the lists' block heads every 512 postings (skip pointers,
+ * Section 7.4).  Asynchronous on hip_stream; allocates nothing.             */
+gc_status gc_query_run(gc_query_plan *plan, const uint32_t *d_docs, const uint32_t *d_tfs,
+                       const uint64_t *d_term_off, const uint16_t *d_doclen, uint32_t *d_top_doc,
+                       float *d_top_score, void *hip_stream);
+
 /* ---- per-block container of the learned codec selector -----------------
  * Not part of the paper: a container in which every block of
  * GC_BLOCK_INTS integers (32 tuples of the 4-way layout) is coded on its own

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgc.so")
 
-SOURCES = ["encode.cpp", "runtime.cpp", "decode.hip", "blocks.hip", "mlp.hip", "noalloc.hip", "encode_gpu.hip"]
+SOURCES = ["encode.cpp", "runtime.cpp", "decode.hip", "blocks.hip", "mlp.hip", "noalloc.hip", "encode_gpu.hip", "query.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

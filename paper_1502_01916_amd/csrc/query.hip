@@ -1,0 +1,350 @@
+// query.hip -- AND queries with Okapi BM25 top-k over decoded posting lists.
+//
+// The consumer of the decoded lists (Section 7.4): an AND query keeps the
+// documents present in every one of its terms' lists, scores each with
+// BM25 and returns the k best.  The lists are decoded by the batched decode
+// path (docIDs prefix-summed, TFs) into device arenas.  A query plan cuts
+// every query's shortest list (the pivot) into segments of 8192 docIDs, one
+// work item each, so long queries spread over many waves:
+//   - a wave takes the pivot's docIDs of its segment 64 at a time, one per
+//     lane;
+//   - every other term looks each docID up: first over its block heads, one
+//     every 512 postings (the paper's skip pointers), then inside the block;
+//     a term's search starts where the previous round's last docID landed,
+//     since the pivot's docIDs increase;
+//   - a document found in every list is scored (single precision) and
+//     offered to the wave's top-k, kept sorted in LDS (higher score first,
+//     then the smaller docID);
+// then one wave per query merges its segments' top-k lists, in segment
+// (docID) order.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "gc.h"
+
+namespace gcq {
+
+typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef __attribute__((address_space(1))) uint16_t gu16;
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr uint32_t kMaxTerms = 8;
+constexpr uint32_t kMaxTopk = 64;
+constexpr uint32_t kSkip = 512;     // postings between skip pointers
+constexpr uint32_t kSeg = 8192;     // pivot docIDs per work item
+
+// A work item: pivot docIDs [s0, s1) of query q.
+struct QItem {
+    uint32_t q, s0, s1, pad;
+};
+
+struct QArgs {
+    const uint32_t *docs, *tfs;
+    const uint64_t *term_off;
+    const uint32_t *term_len;
+    const int32_t *qterms;
+    const uint16_t *doclen;
+    const QItem *items;
+    const uint32_t *first;      // per query: its first item (nq + 1 entries)
+    uint32_t *part_doc;         // per item: topk docIDs, then its count at [nitems * topk + item]
+    float *part_score;
+    uint32_t *out_doc;
+    float *out_score;
+    uint32_t tpq, nq, nitems, ndocs, topk;
+    float avgdl, k1, b;
+};
+
+__device__ __forceinline__ float bm25_weight(uint32_t tf, uint32_t dl, float idf, const QArgs &a) {
+    const float t = (float)tf;
+    return idf * t * (a.k1 + 1.0f) / (t + a.k1 * (1.0f - a.b + a.b * (float)dl / a.avgdl));
+}
+
+// First index p in [lo, n) with v[p] >= key (n if none): the block heads
+// v[512 j] inside [lo, n) first, then the postings of one block.
+__device__ __forceinline__ uint32_t skip_lower_bound(const gu32 *v, uint32_t lo, uint32_t n, uint32_t key) {
+    uint32_t l = lo, r = n;
+    const uint32_t j0 = (l + kSkip - 1u) / kSkip;
+    uint32_t jl = j0, jr = (r + kSkip - 1u) / kSkip;   // heads kSkip * j, j in [jl, jr), lie in [l, r)
+    while (jl < jr) {
+        const uint32_t m = (jl + jr) >> 1;
+        if (v[kSkip * m] < key) jl = m + 1u;
+        else jr = m;
+    }
+    if (jl > j0) l = max(l, kSkip * (jl - 1u) + 1u);    // heads before jl are below the key
+    if (kSkip * jl < r) r = kSkip * jl;                  // head jl is not
+    while (l < r) {
+        const uint32_t m = (l + r) >> 1;
+        if (v[m] < key) l = m + 1u;
+        else r = m;
+    }
+    return l;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Offers (s, d) to a sorted top-k of `count` entries (lane 0 writes):
+// after the entries of equal or higher score, since documents are offered
+// in increasing docID order.  Returns the new count.
+__device__ __forceinline__ uint32_t topk_insert(float *sc, uint32_t *dc, uint32_t count, uint32_t topk, float s,
+                                                uint32_t d, uint32_t lane) {
+    if (lane == 0) {
+        uint32_t pos = count;
+        while (pos > 0 && s > sc[pos - 1]) pos--;
+        const uint32_t lim = min(count, topk - 1u);
+        for (uint32_t r = lim; r > pos; r--) {
+            sc[r] = sc[r - 1];
+            dc[r] = dc[r - 1];
+        }
+        if (pos < topk) {
+            sc[pos] = s;
+            dc[pos] = d;
+        }
+    }
+    wave_sync_lds();
+    return min(count + 1u, topk);
+}
+
+// One wave per work item: its pivot docIDs found in every other list,
+// scored, into the item's top-k.
+__global__ __launch_bounds__(kThreads) void k_and_topk(QArgs a) {
+    __shared__ float s_sc[kWaves][kMaxTopk];
+    __shared__ uint32_t s_dc[kWaves][kMaxTopk];
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t w = blockIdx.x * (uint32_t)kWaves + wave;
+    if (w >= a.nitems) return;
+    float *sc = s_sc[wave];
+    uint32_t *dc = s_dc[wave];
+    const QItem it = a.items[w];
+    // lane i < tpq: term i of the query
+    const int32_t t = lane < a.tpq ? a.qterms[(uint64_t)it.q * a.tpq + lane] : -1;
+    const bool valid = t >= 0;
+    const uint32_t len = valid ? a.term_len[t] : 0u;
+    const uint64_t off = valid ? a.term_off[t] : 0u;
+    const float idf = valid ? logf(1.0f + ((float)a.ndocs - (float)len + 0.5f) / ((float)len + 0.5f)) : 0.0f;
+    const uint64_t vb = __ballot(valid);
+    uint32_t count = 0;
+    // the pivot: the shortest list (the first of equal lengths)
+    uint32_t mlen = valid ? len : 0xFFFFFFFFu;
+    for (uint32_t m = 1; m < 64u; m <<= 1) mlen = min(mlen, (uint32_t)__shfl_xor((int)mlen, (int)m));
+    const uint32_t piv = vb ? (uint32_t)__builtin_ctzll(__ballot(valid && len == mlen)) : 0u;
+    const uint64_t offp = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(off >> 32), (int)piv) << 32) |
+                          (uint32_t)__shfl((int)(uint32_t)off, (int)piv);
+    const float idfp = __shfl(idf, (int)piv);
+    const uint32_t s1 = vb ? min(it.s1, mlen) : 0u;
+    uint32_t from[kMaxTerms];   // where each term's search starts (uniform)
+#pragma unroll
+    for (uint32_t j = 0; j < kMaxTerms; j++) from[j] = 0;
+    float thr = -1.0f;
+    for (uint32_t base = it.s0; base < s1; base += 64u) {
+        const uint32_t i = base + lane;
+        const bool in = i < s1;
+        const uint32_t d = in ? ((const gu32 *)a.docs)[offp + i] : 0xFFFFFFFFu;
+        const uint32_t dl = in && d < a.ndocs ? ((const gu16 *)a.doclen)[d] : 1u;
+        bool ok = in && d < a.ndocs;
+        float score = ok ? bm25_weight(((const gu32 *)a.tfs)[offp + i], dl, idfp, a) : 0.0f;
+        const uint32_t last = min(63u, s1 - base - 1u);
+#pragma unroll
+        for (uint32_t j = 0; j < kMaxTerms; j++) {
+            if (j >= a.tpq) break;
+            if (j == piv || !((vb >> j) & 1ull)) continue;
+            const uint32_t lj = (uint32_t)__shfl((int)len, (int)j);
+            const uint64_t oj = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(off >> 32), (int)j) << 32) |
+                                (uint32_t)__shfl((int)(uint32_t)off, (int)j);
+            const float idfj = __shfl(idf, (int)j);
+            const gu32 *v = (const gu32 *)a.docs + oj;
+            const uint32_t p = in ? skip_lower_bound(v, from[j], lj, d) : lj;
+            const bool found = p < lj && v[p] == d;
+            if (ok && found) score += bm25_weight(((const gu32 *)a.tfs)[oj + p], dl, idfj, a);
+            ok = ok && found;
+            from[j] = (uint32_t)__shfl((int)p, (int)last);
+        }
+        // offer the round's documents to the top-k, in docID order
+        const float cand = ok ? score : -1.0f;
+        uint64_t m = __ballot(ok && cand > thr);
+        while (m) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(m);
+            count = topk_insert(sc, dc, count, a.topk, __shfl(cand, (int)l), (uint32_t)__shfl((int)d, (int)l), lane);
+            thr = count == a.topk ? sc[a.topk - 1u] : -1.0f;
+            m &= m - 1u;
+            m &= __ballot(ok && cand > thr);
+        }
+    }
+    for (uint32_t r = lane; r < a.topk; r += 64u) {
+        a.part_doc[(uint64_t)w * a.topk + r] = r < count ? dc[r] : 0xFFFFFFFFu;
+        a.part_score[(uint64_t)w * a.topk + r] = r < count ? sc[r] : 0.0f;
+    }
+    if (lane == 0) a.part_doc[(uint64_t)a.nitems * a.topk + w] = count;
+}
+
+// One wave per query: its items' top-k lists merged in item (docID) order.
+__global__ __launch_bounds__(kThreads) void k_merge_topk(QArgs a) {
+    __shared__ float s_sc[kWaves][kMaxTopk];
+    __shared__ uint32_t s_dc[kWaves][kMaxTopk];
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t q = blockIdx.x * (uint32_t)kWaves + wave;
+    if (q >= a.nq) return;
+    float *sc = s_sc[wave];
+    uint32_t *dc = s_dc[wave];
+    uint32_t count = 0;
+    float thr = -1.0f;
+    for (uint32_t w = a.first[q]; w < a.first[q + 1]; w++) {
+        const uint32_t n = a.part_doc[(uint64_t)a.nitems * a.topk + w];
+        const bool in = lane < n;
+        const float s = in ? a.part_score[(uint64_t)w * a.topk + lane] : -1.0f;
+        const uint32_t d = in ? a.part_doc[(uint64_t)w * a.topk + lane] : 0xFFFFFFFFu;
+        uint64_t m = __ballot(in && s > thr);
+        while (m) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(m);
+            count = topk_insert(sc, dc, count, a.topk, __shfl(s, (int)l), (uint32_t)__shfl((int)d, (int)l), lane);
+            thr = count == a.topk ? sc[a.topk - 1u] : -1.0f;
+            m &= m - 1u;
+            m &= __ballot(in && s > thr);
+        }
+    }
+    for (uint32_t r = lane; r < a.topk; r += 64u) {
+        a.out_doc[(uint64_t)q * a.topk + r] = r < count ? dc[r] : 0xFFFFFFFFu;
+        a.out_score[(uint64_t)q * a.topk + r] = r < count ? sc[r] : 0.0f;
+    }
+}
+
+}  // namespace gcq
+
+using namespace gcq;
+
+struct gc_query_plan {
+    QArgs a;
+    int device = 0;
+    void *mem[6] = {};
+};
+
+namespace {
+
+template <typename T>
+bool qalloc(gc_query_plan *p, int slot, T **ptr, size_t n) {
+    void *m = nullptr;
+    if (hipMalloc(&m, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    p->mem[slot] = m;
+    *ptr = static_cast<T *>(m);
+    return true;
+}
+
+void qfree(gc_query_plan *p) {
+    for (void *&m : p->mem)
+        if (m) (void)hipFree(m), m = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+gc_status gc_query_plan_create(const uint32_t *h_term_len, size_t nterms, const int32_t *h_query_terms,
+                               uint32_t terms_per_query, uint32_t nq, const gc_bm25_params *bp,
+                               gc_query_plan **plan) {
+    if (!plan) return GC_EINVAL;
+    *plan = nullptr;
+    if (!bp || !h_term_len || (nq && !h_query_terms) || nterms > 0x7FFFFFFFu) return GC_EINVAL;
+    if (terms_per_query == 0 || terms_per_query > kMaxTerms || bp->topk == 0 || bp->topk > kMaxTopk ||
+        bp->ndocs == 0 || !(bp->avgdl > 0.0f) || !(bp->k1 >= 0.0f) || !(bp->b >= 0.0f && bp->b <= 1.0f) ||
+        bp->reserved[0] || bp->reserved[1])
+        return GC_EINVAL;
+    // work items: every query's pivot (its shortest list) in segments
+    std::vector<QItem> items;
+    std::vector<uint32_t> first(nq + 1u, 0u);
+    for (uint32_t q = 0; q < nq; q++) {
+        first[q] = (uint32_t)items.size();
+        uint32_t piv = 0xFFFFFFFFu;
+        bool any = false;
+        for (uint32_t i = 0; i < terms_per_query; i++) {
+            const int32_t t = h_query_terms[(size_t)q * terms_per_query + i];
+            if (t < -1 || t >= (int64_t)nterms) return GC_EINVAL;
+            if (t < 0) continue;
+            any = true;
+            piv = std::min(piv, h_term_len[t]);
+        }
+        if (!any) continue;
+        for (uint32_t s0 = 0; s0 < piv; s0 += kSeg) items.push_back(QItem{q, s0, std::min(piv, s0 + kSeg), 0u});
+    }
+    first[nq] = (uint32_t)items.size();
+    gc_query_plan *p = new (std::nothrow) gc_query_plan();
+    if (!p) return GC_ENOMEM;
+    (void)hipGetDevice(&p->device);
+    std::memset(&p->a, 0, sizeof(p->a));
+    QArgs &a = p->a;
+    a.tpq = terms_per_query;
+    a.nq = nq;
+    a.nitems = (uint32_t)items.size();
+    a.ndocs = bp->ndocs;
+    a.topk = bp->topk;
+    a.avgdl = bp->avgdl;
+    a.k1 = bp->k1;
+    a.b = bp->b;
+    uint32_t *tl = nullptr, *fi = nullptr, *pd = nullptr;
+    int32_t *qt = nullptr;
+    QItem *it = nullptr;
+    float *ps = nullptr;
+    const size_t nit = items.size();
+    bool ok = qalloc(p, 0, &tl, nterms) && qalloc(p, 1, &qt, (size_t)nq * terms_per_query) &&
+              qalloc(p, 2, &it, nit) && qalloc(p, 3, &fi, (size_t)nq + 1u) &&
+              qalloc(p, 4, &pd, nit * bp->topk + nit) && qalloc(p, 5, &ps, nit * bp->topk);
+    ok = ok && hipMemcpy(tl, h_term_len, nterms * 4, hipMemcpyHostToDevice) == hipSuccess &&
+         (!nq || hipMemcpy(qt, h_query_terms, (size_t)nq * terms_per_query * 4, hipMemcpyHostToDevice) == hipSuccess) &&
+         (!nit || hipMemcpy(it, items.data(), nit * sizeof(QItem), hipMemcpyHostToDevice) == hipSuccess) &&
+         hipMemcpy(fi, first.data(), first.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        qfree(p);
+        delete p;
+        return GC_ENOMEM;
+    }
+    a.term_len = tl;
+    a.qterms = qt;
+    a.items = it;
+    a.first = fi;
+    a.part_doc = pd;
+    a.part_score = ps;
+    *plan = p;
+    return GC_OK;
+}
+
+gc_status gc_query_run(gc_query_plan *plan, const uint32_t *d_docs, const uint32_t *d_tfs,
+                       const uint64_t *d_term_off, const uint16_t *d_doclen, uint32_t *d_top_doc,
+                       float *d_top_score, void *hip_stream) {
+    if (!plan || !d_docs || !d_tfs || !d_term_off || !d_doclen || !d_top_doc || !d_top_score) return GC_EINVAL;
+    QArgs a = plan->a;
+    if (!a.nq) return GC_OK;
+    a.docs = d_docs;
+    a.tfs = d_tfs;
+    a.term_off = d_term_off;
+    a.doclen = d_doclen;
+    a.out_doc = d_top_doc;
+    a.out_score = d_top_score;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    if (a.nitems) hipLaunchKernelGGL(k_and_topk, dim3((a.nitems + kWaves - 1) / kWaves), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(k_merge_topk, dim3((a.nq + kWaves - 1) / kWaves), dim3(kThreads), 0, s, a);
+    return hipGetLastError() == hipSuccess ? GC_OK : GC_EDEVICE;
+}
+
+gc_status gc_query_plan_destroy(gc_query_plan *plan) {
+    if (!plan) return GC_EINVAL;
+    (void)hipSetDevice(plan->device);
+    (void)hipDeviceSynchronize();
+    qfree(plan);
+    delete plan;
+    return GC_OK;
+}
+
+}  // extern "C"

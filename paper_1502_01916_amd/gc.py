@@ -73,6 +73,11 @@ class PlanOpts(ctypes.Structure):
 CARRY_DEFAULT, CARRY_LOOKBACK, CARRY_SUM_PASS, CARRY_HYBRID = 0, 1, 2, 3
 
 
+class BM25Params(ctypes.Structure):
+    _fields_ = [("k1", ctypes.c_float), ("b", ctypes.c_float), ("avgdl", ctypes.c_float),
+                ("topk", ctypes.c_uint32), ("ndocs", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
+
+
 class AdamOpts(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float), ("lam", ctypes.c_float), ("batch", ctypes.c_uint32),
@@ -115,6 +120,10 @@ def lib():
         L.gc_ctx_destroy.argtypes = [vp]
         L.gc_decode.argtypes = [vp, vp, sz, u32p, vp, vp]
         L.gc_decode_noalloc.argtypes = [vp, vp, sz, u32p, vp, vp]
+        L.gc_query_plan_create.argtypes = [vp, sz, vp, ctypes.c_uint32, ctypes.c_uint32,
+                                           ctypes.POINTER(BM25Params), ctypes.POINTER(vp)]
+        L.gc_query_plan_destroy.argtypes = [vp]
+        L.gc_query_run.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.gc_encode_lists_gpu.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), sz, i, ctypes.POINTER(Params), vp,
                                           sz, ctypes.POINTER(ctypes.c_uint64), vp]
         L.gc_plan_create.argtypes = [vp, ctypes.POINTER(ListDesc), sz, u32p, ctypes.POINTER(PlanOpts),
@@ -146,7 +155,8 @@ def lib():
         L.gc_mlp_train.argtypes = [vp, vp, vp, vp, vp, sz, ctypes.POINTER(AdamOpts), vp, vp]
         L.gc_encode_blocks.argtypes = [vp, vp, sz, i, vp, ctypes.c_uint32, vp, sz, ctypes.POINTER(sz), vp, vp]
         for f in ("gc_encode", "gc_encode_lists", "gc_ctx_create", "gc_ctx_create_opts", "gc_ctx_destroy",
-                  "gc_decode", "gc_decode_noalloc", "gc_encode_lists_gpu",
+                  "gc_decode", "gc_decode_noalloc", "gc_encode_lists_gpu", "gc_query_plan_create",
+                  "gc_query_plan_destroy", "gc_query_run",
                   "gc_plan_create", "gc_plan_destroy", "gc_decode_batch", "gc_decode_each",
                   "gc_plan_config", "gc_plan_class_tiles", "gc_plan_pack_config", "gc_plan_packed_lists",
                   "gc_sync_status", "gc_block_features",
@@ -526,3 +536,38 @@ def to_device(a_u32, device="cuda"):
 
 def to_host(t):
     return t.cpu().numpy().view(np.uint32)
+
+
+class QueryPlan:
+    """gc_query_plan_create / gc_query_run / gc_query_plan_destroy: AND
+    queries with BM25 top-k over decoded lists.  term_len: length of every
+    term's list (host); queries: (nq, terms_per_query) term indices, -1 =
+    none."""
+
+    def __init__(self, term_len, queries, ndocs, avgdl, topk=10, k1=1.2, b=0.75):
+        tl = np.ascontiguousarray(term_len, dtype=np.uint32)
+        qt = np.ascontiguousarray(queries, dtype=np.int32)
+        self.nq, self.tpq, self.topk = int(qt.shape[0]), int(qt.shape[1]), int(topk)
+        bp = BM25Params(float(k1), float(b), float(avgdl), int(topk), int(ndocs))
+        self._h = ctypes.c_void_p()
+        _check("gc_query_plan_create", lib().gc_query_plan_create(
+            tl.ctypes.data_as(ctypes.c_void_p), tl.size, qt.ctypes.data_as(ctypes.c_void_p), self.tpq, self.nq,
+            ctypes.byref(bp), ctypes.byref(self._h)))
+
+    def run(self, d_docs, d_tfs, d_term_off, d_doclen, d_top_doc, d_top_score, stream=None):
+        """d_docs / d_tfs: decoded arenas (int32), d_term_off: int64 offsets,
+        d_doclen: int16 document lengths; outputs (nq * topk) int32 / float32."""
+        _check("gc_query_run", lib().gc_query_run(self._h, _ptr(d_docs), _ptr(d_tfs), _ptr(d_term_off),
+                                                  _ptr(d_doclen), _ptr(d_top_doc), _ptr(d_top_score),
+                                                  _stream_handle(stream)))
+
+    def close(self):
+        if self._h:
+            lib().gc_query_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

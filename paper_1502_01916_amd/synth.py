@@ -192,3 +192,26 @@ def cfg5(seed=6, nlists=1_000_000, median=256, sigma=1.217):
     g = pareto_gaps(rng, int(L.sum()))
     d = _segmented_cumsum(g, L)
     return L, d
+
+
+def doc_lengths(seed=8, ndocs=U25, median=300, sigma=0.8):
+    """Length of every document of the collection (for BM25's length
+    normalisation): lognormal, median 300 terms, in [1, 65535], uint16."""
+    rng = np.random.default_rng(seed)
+    x = np.exp(rng.normal(np.log(median), sigma, ndocs))
+    return np.clip(np.round(x), 1, 65535).astype(np.uint16)
+
+
+def queries(lengths, seed=7, nq=1000, min_terms=2, max_terms=4):
+    """AND queries over the lists of a collection: 2 to 4 distinct terms
+    each, a term drawn with probability proportional to its list's length
+    (frequent terms are queried more, as in query logs).  Returns an
+    (nq, max_terms) int64 array of list indices, padded with -1."""
+    rng = np.random.default_rng(seed)
+    p = np.asarray(lengths, np.float64)
+    p = p / p.sum()
+    out = np.full((nq, max_terms), -1, np.int64)
+    for q in range(nq):
+        m = int(rng.integers(min_terms, max_terms + 1))
+        out[q, :m] = rng.choice(p.size, m, replace=False, p=p)
+    return out

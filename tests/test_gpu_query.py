@@ -1,0 +1,129 @@
+"""AND queries with BM25 top-k on the GPU (gc_query_plan_create /
+gc_query_run) over lists decoded by the batched decode path, against the
+float64 reference (oracle/query_ref.py).  Scores are single precision on the
+GPU: the number of results must match exactly, every returned document must
+be in the intersection, and the score at every rank must match the
+reference's within a relative 2e-5 (so near-ties may swap documents, but only
+between documents whose reference scores agree to that tolerance)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import query_ref as Q
+from paper_1502_01916_amd import gc, synth
+
+pytestmark = pytest.mark.gpu
+RTOL = 2e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def index(torch_cuda):
+    """A 2,000-term collection (cfg2 model, 2^22 postings) coded with
+    Group-PFD (docIDs) and Group-Simple (TFs), decoded on the GPU by one
+    batched plan into docID and TF arenas with equal offsets."""
+    torch = torch_cuda
+    lengths, docs, tfs = synth.cfg2(seed=12, nlists=2000, total=1 << 22)
+    s_d, o_d = gc.encode_lists(docs, lengths, gc.PFD, gc.params(delta=True))
+    s_t, o_t = gc.encode_lists(tfs, lengths, gc.SIMPLE, gc.params())
+    streams = np.concatenate([s_d, s_t])
+    offs = np.concatenate([o_d[:-1], o_t + o_d[-1]]).astype(np.int64)
+    L2 = np.concatenate([lengths, lengths])
+    descs, headers, out_offs = gc.batch_layout(streams, offs, L2, align=4)
+    ctx = gc.Context(0)
+    d_s = gc.to_device(streams)
+    arena = torch.full((int(out_offs[-1]),), -1, dtype=torch.int32, device="cuda")
+    plan = gc.Plan(ctx, descs, headers, d_s, arena, use_graph=True)
+    plan.decode_batch(d_s, arena)
+    rc, det = ctx.sync_status()
+    assert rc == gc.OK, det
+    n = lengths.size
+    half = int(out_offs[n])
+    assert np.array_equal(out_offs[n:2 * n] - half, out_offs[:n])
+    term_off = torch.from_numpy(out_offs[:n].astype(np.int64)).cuda()
+    doclen = synth.doc_lengths(ndocs=synth.U25)
+    d_doclen = torch.from_numpy(doclen.view(np.int16)).cuda()
+    lo = np.concatenate([[0], np.cumsum(lengths)])
+    doc_lists = [docs[lo[i]:lo[i + 1]] for i in range(n)]
+    tf_lists = [tfs[lo[i]:lo[i + 1]] for i in range(n)]
+    # the decoded arenas hold the generated lists
+    got = gc.to_host(arena)
+    assert np.array_equal(gc.unpad(got, out_offs[:n + 1], lengths), docs)
+    assert np.array_equal(gc.unpad(got[half:], out_offs[n:] - half, lengths), tfs)
+    yield dict(lengths=lengths, doc_lists=doc_lists, tf_lists=tf_lists, arena=arena, half=half,
+               term_off=term_off, doclen=doclen, d_doclen=d_doclen, avgdl=float(doclen.mean()))
+    plan.close()
+    ctx.close()
+
+
+def run_queries(torch, ix, queries, topk, k1=1.2, b=0.75):
+    qp = gc.QueryPlan(ix["lengths"], queries, synth.U25, ix["avgdl"], topk=topk, k1=k1, b=b)
+    nq = queries.shape[0]
+    d_doc = torch.empty(nq * topk, dtype=torch.int32, device="cuda")
+    d_sc = torch.empty(nq * topk, dtype=torch.float32, device="cuda")
+    qp.run(ix["arena"], ix["arena"][ix["half"]:], ix["term_off"], ix["d_doclen"], d_doc, d_sc)
+    torch.cuda.synchronize()
+    qp.close()
+    return gc.to_host(d_doc).reshape(nq, topk), d_sc.cpu().numpy().reshape(nq, topk)
+
+
+def check(ix, queries, docs, scores, topk, k1=1.2, b=0.75):
+    for q in range(queries.shape[0]):
+        want = Q.and_topk(ix["doc_lists"], ix["tf_lists"], queries[q], ix["doclen"], synth.U25, ix["avgdl"],
+                          k=topk, k1=k1, b=b)
+        n = len(want)
+        got_d = docs[q]
+        assert np.all(got_d[n:] == 0xFFFFFFFF), (q, "extra results")
+        assert np.all(got_d[:n] != 0xFFFFFFFF), (q, "missing results")
+        if not n:
+            continue
+        ws = np.array([s for s, _ in want])
+        assert np.allclose(scores[q, :n], ws, rtol=RTOL, atol=0), (q, scores[q, :n], ws)
+        # every returned document is in the intersection, with the score of its rank
+        terms = [int(t) for t in queries[q] if t >= 0]
+        full = {d: s for s, d in Q.and_topk(ix["doc_lists"], ix["tf_lists"], terms, ix["doclen"], synth.U25,
+                                            ix["avgdl"], k=1 << 30, k1=k1, b=b)}
+        for r in range(n):
+            d = int(got_d[r])
+            assert d in full, (q, r, d)
+            assert full[d] == pytest.approx(ws[r], rel=RTOL), (q, r, d)
+
+
+def test_queries_top10(torch_cuda, index):
+    """300 queries of 2 to 4 terms drawn by list length, top-10."""
+    queries = synth.queries(index["lengths"], seed=7, nq=300)
+    say("queries", queries.shape)
+    docs, scores = run_queries(torch_cuda, index, queries, 10)
+    check(index, queries, docs, scores, 10)
+    hits = int(np.sum(docs != 0xFFFFFFFF))
+    say("results", hits)
+    assert hits > 300      # the queries are not all empty
+
+
+def test_queries_edge_cases(torch_cuda, index):
+    """Single-term queries (the whole list ranked), empty queries, terms
+    that never meet, repeated terms; top-1 and top-64; other BM25
+    parameters."""
+    L = index["lengths"]
+    big = np.argsort(L)[::-1]
+    small = np.argsort(L)[:4]
+    queries = np.array([[big[0], -1, -1, -1], [small[0], -1, -1, -1], [-1, -1, -1, -1],
+                        [big[0], big[1], big[2], big[3]], [small[0], small[1], -1, -1],
+                        [big[5], big[0], -1, -1], [big[1], -1, big[7], -1], [big[2], big[2], -1, -1]], np.int64)
+    for topk, k1, b in ((1, 1.2, 0.75), (64, 1.2, 0.75), (10, 0.9, 0.4)):
+        say("edge topk", topk, k1, b)
+        docs, scores = run_queries(torch_cuda, index, queries, topk, k1, b)
+        check(index, queries, docs, scores, topk, k1, b)
