@@ -19,6 +19,7 @@ five codecs); the four cfg5 batches (1,000,000 lists, median 256, heavy-tailed
 gaps; Group-PFD and Group-AFOR in the 4-way and 64-way layouts); every
 Group-Scheme variant and BP128 beside the other codecs on cfg2; encode speed
 on cfg2, GPU list encoders against the host encoder (streams checked equal);
+AND queries with BM25 top-10 over the cfg2 index (decode + query per batch);
 the single-list latency of cfg1.  `--workload NAME` measures one workload
 alone (for profiler runs).
 
@@ -516,6 +517,80 @@ def encode_leg(gc, torch, cfg2_data, reps=3):
     return out
 
 
+def query_leg(gc, torch, ctx, synth, cfg2_data, nq=1000, reps=5):
+    """Query processing (Section 7.4, Table X): 1,000 AND queries of 2 to 4
+    terms (drawn by list length) over the cfg2 index, docIDs and TFs in one
+    codec; per batch, one graph replay decodes the lists of the batch's
+    distinct terms, then the AND / BM25 top-10 kernels run.  Reports
+    queries/s and the share of the batch spent decoding (the paper finds
+    decoding 15-35% of query time on its CPU); checks a sample of queries
+    against the float64 reference."""
+    from oracle import query_ref as Q
+    lengths, docs, tfs = cfg2_data
+    queries = synth.queries(lengths, seed=7, nq=nq)
+    terms = np.unique(queries[queries >= 0])
+    remap = np.full(lengths.size, -1, np.int64)
+    remap[terms] = np.arange(terms.size)
+    qloc = np.where(queries >= 0, remap[np.maximum(queries, 0)], -1)
+    sub_len = lengths[terms]
+    lo = np.concatenate([[0], np.cumsum(lengths)])
+    sub_docs = np.concatenate([docs[lo[t]:lo[t + 1]] for t in terms])
+    sub_tfs = np.concatenate([tfs[lo[t]:lo[t + 1]] for t in terms])
+    doclen = synth.doc_lengths(ndocs=synth.U25)
+    d_doclen = torch.from_numpy(doclen.view(np.int16)).cuda()
+    avgdl = float(doclen.mean())
+    out = {}
+    for name, codec, kw in five_codecs(gc):
+        s_d, o_d = gc.encode_lists(sub_docs, sub_len, codec, gc.params(delta=True, **kw))
+        s_t, o_t = gc.encode_lists(sub_tfs, sub_len, codec, gc.params(**kw))
+        streams = np.concatenate([s_d, s_t])
+        offs = np.concatenate([o_d[:-1], o_t + o_d[-1]]).astype(np.int64)
+        descs, headers, out_offs = gc.batch_layout(streams, offs, np.concatenate([sub_len, sub_len]), align=4)
+        n = terms.size
+        half = int(out_offs[n])
+        d_s = gc.to_device(streams)
+        arena = torch.empty(int(out_offs[-1]), dtype=torch.int32, device="cuda")
+        plan = gc.Plan(ctx, descs, headers, d_s, arena, use_graph=True)
+        term_off = torch.from_numpy(out_offs[:n].astype(np.int64)).cuda()
+        qp = gc.QueryPlan(sub_len, qloc, synth.U25, avgdl, topk=10)
+        d_doc = torch.empty(nq * 10, dtype=torch.int32, device="cuda")
+        d_sc = torch.empty(nq * 10, dtype=torch.float32, device="cuda")
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        dec = qry = 0.0
+        for r in range(reps + 1):
+            ev[0].record()
+            plan.decode_batch(d_s, arena)
+            ev[1].record()
+            qp.run(arena, arena[half:], term_off, d_doclen, d_doc, d_sc)
+            ev[2].record()
+            torch.cuda.synchronize()
+            if r:
+                dec += ev[0].elapsed_time(ev[1]) / reps
+                qry += ev[1].elapsed_time(ev[2]) / reps
+        rc, det = ctx.sync_status()
+        got_d = gc.to_host(d_doc).reshape(nq, 10)
+        got_s = d_sc.cpu().numpy().reshape(nq, 10)
+        sample = np.random.default_rng(1).choice(nq, 50, replace=False)
+        ok = rc == gc.OK
+        sub_doc_lists = [sub_docs[int(o):int(o) + int(L)] for o, L in zip(np.concatenate([[0], np.cumsum(sub_len)]), sub_len)]
+        sub_tf_lists = [sub_tfs[int(o):int(o) + int(L)] for o, L in zip(np.concatenate([[0], np.cumsum(sub_len)]), sub_len)]
+        for q in sample:
+            want = Q.and_topk(sub_doc_lists, sub_tf_lists, qloc[q], doclen, synth.U25, avgdl, k=10)
+            nw = len(want)
+            ok = ok and bool(np.all(got_d[q, nw:] == 0xFFFFFFFF)) and bool(
+                np.allclose(got_s[q, :nw], [s for s, _ in want], rtol=2e-5, atol=0))
+        total = dec + qry
+        out[name] = dict(queries_per_s=round(nq / (total * 1e-3), 1), ms_per_batch=round(total, 4),
+                         decode_ms=round(dec, 4), query_ms=round(qry, 4),
+                         decode_share=round(dec / total, 4), terms=int(n), postings=int(2 * sub_len.sum()),
+                         verified_sample=bool(ok))
+        log("query %-18s %s" % (name, out[name]))
+        qp.close()
+        plan.close()
+        del d_s, arena
+    return out
+
+
 def variants_leg(gc, torch, ctx, synth, args, cfg2_data):
     """Section 7.2's trade-off on the cfg2 lists: every variant's bits/int,
     Gints/s and decode-pass % of HBM (docIDs and TFs of one variant per
@@ -605,6 +680,7 @@ def main():
             del w5
         extra["variants_cfg2"] = variants_leg(gc, torch, ctx, synth, args, cfg2_data)
         extra["encode_cfg2"] = encode_leg(gc, torch, cfg2_data)
+        extra["query_cfg2"] = query_leg(gc, torch, ctx, synth, cfg2_data)
         extra["cfg1_latency"] = cfg1_latency(gc, synth, ctx, torch)
         log("cfg1 single list: %s" % extra["cfg1_latency"])
 
