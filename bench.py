@@ -356,7 +356,7 @@ def measure(gc, torch, ctx, wl, args, keep_device=False):
     plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=args.tile, locate_stream=args.locate_stream,
                    pfd_tile_ints=args.pfd_tile or (4096 if args.tile else 0),
                    autotune=args.tile == 0, use_graph=True, carry_pass=args.carry_pass,
-                   pack_serial=args.pack_serial)
+                   graph_serial=args.graph_serial)
     cfg = plan.config()
     log("%s plan: %s (%.1fs)" % (wl.name, cfg, time.time() - t))
     tplan = gc.Plan(ctx, descs, headers, d_s, d_o, class_tiles=cfg["class_tiles"],
@@ -624,8 +624,8 @@ def main():
                     help="the workload timed for `value`; any other than cfg3 is measured alone (no legs)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--pack-serial", action="store_true",
-                    help="graph: run the pack kernel ahead of the other passes instead of beside them")
+    ap.add_argument("--graph-serial", action="store_true",
+                    help="graph: one chain of kernels instead of branches for the pack kernel and each class")
     ap.add_argument("--no-extra", action="store_true", help="skip every leg")
     ap.add_argument("--tile", type=int, default=0, help="force the wave-tile size (0 = autotune)")
     ap.add_argument("--pfd-tile", type=int, default=0, help="force the Group-PFD tile size (with --tile)")

@@ -236,9 +236,12 @@ typedef struct {
                                 k and codec parameters; docID and TF lists
                                 mix); GC_PACK_OFF: none; 0 = autotuned (with
                                 autotune) or the default, 2048               */
-    uint32_t pack_serial;    /* 1 = a graph runs the pack kernel ahead of the
-                                other passes; 0 = on a branch of its own,
-                                beside the locate and class passes           */
+    uint32_t graph_serial;   /* 1 = a graph runs its kernels in one chain (the
+                                pack kernel, the locate pass, then class after
+                                class); 0 = branches: the pack kernel beside
+                                the rest, and after the locate pass each
+                                codec class's passes on a branch of their own
+                                (with schedule 0)                            */
 } gc_plan_opts;
 #define GC_PACK_OFF 0x80000000u
 

@@ -288,7 +288,7 @@ struct gc_plan {
     bool pack_forced = false;                  // pack_max set by the plan options
     std::vector<uint8_t> packed;               // per list
     PackSet pk[2];                             // packs of the kernel of capacity kPackInts[0] / [1] (one is used)
-    bool pack_branch = true;                   // graph: the pack kernel on a branch beside the other passes
+    bool branches = true;                      // graph: the pack kernel and each class's passes on branches
     uint32_t total_chunks = 0;                 // locate chunks of every list (batch items first)
 };
 
@@ -707,10 +707,14 @@ gc_status launch_packs(gc_plan *p, hipStream_t s) {
 constexpr int kTevPack = 5 * kClasses;
 
 // With a pack stream `pks` (and its fork / join events), the pack kernel
-// runs there, beside the locate pass and the class passes.
+// runs there, beside the locate pass and the class passes.  With class
+// streams `cls` (one locate pass, no auxiliary stream), the passes of class
+// c run on cls[c] once the locate pass is done (event loc_done), and s
+// waits for all of them (events cjoin[c]).
 gc_status plan_launch(gc_plan *p, hipStream_t s, hipStream_t aux = nullptr, hipEvent_t start = nullptr,
                       hipEvent_t *sync = nullptr, hipEvent_t *tev = nullptr, hipStream_t pks = nullptr,
-                      hipEvent_t pk_fork = nullptr, hipEvent_t pk_join = nullptr) {
+                      hipEvent_t pk_fork = nullptr, hipEvent_t pk_join = nullptr, hipStream_t *cls = nullptr,
+                      hipEvent_t loc_done = nullptr, hipEvent_t *cjoin = nullptr) {
     if (aux) {
         HIP_OK(hipEventRecord(start, s));
         HIP_OK(hipStreamWaitEvent(aux, start, 0));
@@ -739,34 +743,46 @@ gc_status plan_launch(gc_plan *p, hipStream_t s, hipStream_t aux = nullptr, hipE
         if (gc_status rc = launch_class_locate(p, c, ls)) return rc;
         HIP_OK(hipEventRecord(tev ? tev[5 * c + 1] : sync[c], ls));
     }
+    const bool branch = cls && !aux && !tev;
+    if (branch) HIP_OK(hipEventRecord(loc_done, s));
     for (int c = 0; c < kClasses; c++) {
         if (!p->cr[c].count) continue;
+        const hipStream_t cs = branch ? cls[c] : s;
+        if (branch) HIP_OK(hipStreamWaitEvent(cs, loc_done, 0));
         if (aux) HIP_OK(hipStreamWaitEvent(s, tev ? tev[5 * c + 1] : sync[c], 0));
         if (tev) HIP_OK(hipEventRecord(tev[5 * c + 2], s));
-        if (gc_status rc = launch_class_work(p, c, s, aux != nullptr, tev ? tev[5 * c + 3] : nullptr)) return rc;
+        if (gc_status rc = launch_class_work(p, c, cs, aux != nullptr, tev ? tev[5 * c + 3] : nullptr)) return rc;
         if (tev) HIP_OK(hipEventRecord(tev[5 * c + 4], s));
+        if (branch) HIP_OK(hipEventRecord(cjoin[c], cs));
     }
+    for (int c = 0; c < kClasses && branch; c++)
+        if (p->cr[c].count) HIP_OK(hipStreamWaitEvent(s, cjoin[c], 0));
     if (fork) HIP_OK(hipStreamWaitEvent(s, pk_join, 0));
     return GC_OK;
 }
 
 gc_status capture_one(gc_plan *p, hipGraph_t *graph, hipGraphExec_t *exec) {
-    hipStream_t s, aux, pks;
-    hipEvent_t start, sync[kClasses], fork, join;
+    hipStream_t s, aux, pks, cls[kClasses];
+    hipEvent_t start, sync[kClasses], fork, join, loc_done, cjoin[kClasses];
     HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     HIP_OK(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
     HIP_OK(hipStreamCreateWithFlags(&pks, hipStreamNonBlocking));
     HIP_OK(hipEventCreateWithFlags(&start, hipEventDisableTiming));
     HIP_OK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
     HIP_OK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
-    for (int c = 0; c < kClasses; c++) HIP_OK(hipEventCreateWithFlags(&sync[c], hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&loc_done, hipEventDisableTiming));
+    for (int c = 0; c < kClasses; c++) {
+        HIP_OK(hipEventCreateWithFlags(&sync[c], hipEventDisableTiming));
+        HIP_OK(hipEventCreateWithFlags(&cjoin[c], hipEventDisableTiming));
+        HIP_OK(hipStreamCreateWithFlags(&cls[c], hipStreamNonBlocking));
+    }
     gc_status rc = GC_OK;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         rc = GC_EDEVICE;
     } else {
         // the graph's pack kernel is a branch of its own
-        rc = plan_launch(p, s, p->serial ? nullptr : aux, start, sync, nullptr, p->pack_branch ? pks : nullptr,
-                         fork, join);
+        rc = plan_launch(p, s, p->serial ? nullptr : aux, start, sync, nullptr, p->branches ? pks : nullptr,
+                         fork, join, p->branches ? cls : nullptr, loc_done, cjoin);
         hipGraph_t g = nullptr;
         if (hipStreamEndCapture(s, &g) != hipSuccess || rc) {
             rc = GC_EDEVICE;
@@ -776,10 +792,15 @@ gc_status capture_one(gc_plan *p, hipGraph_t *graph, hipGraphExec_t *exec) {
             if (hipGraphInstantiate(exec, g, nullptr, nullptr, 0) != hipSuccess) rc = GC_EDEVICE;
         }
     }
-    for (int c = 0; c < kClasses; c++) (void)hipEventDestroy(sync[c]);
+    for (int c = 0; c < kClasses; c++) {
+        (void)hipEventDestroy(sync[c]);
+        (void)hipEventDestroy(cjoin[c]);
+        (void)hipStreamDestroy(cls[c]);
+    }
     (void)hipEventDestroy(start);
     (void)hipEventDestroy(fork);
     (void)hipEventDestroy(join);
+    (void)hipEventDestroy(loc_done);
     (void)hipStreamDestroy(pks);
     (void)hipStreamDestroy(aux);
     (void)hipStreamDestroy(s);
@@ -1169,11 +1190,11 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     p->use_graph = o.use_graph != 0;
     p->serial = o.schedule == 0u;
     p->pack_forced = o.pack_ints != 0u;
-    if (o.pack_serial > 1u) {
+    if (o.graph_serial > 1u) {
         delete p;
         return GC_EINVAL;
     }
-    p->pack_branch = o.pack_serial == 0u;
+    p->branches = o.graph_serial == 0u;
     p->pack_max = o.pack_ints == GC_PACK_OFF ? 0u : o.pack_ints ? o.pack_ints : kDefaultPackMax;
     p->lb_max = o.carry_pass == 1u ? kLookbackAll : o.carry_pass == 2u ? 0u
               : o.carry_pass == 3u ? kLookbackHybrid : kDefaultLbMax;

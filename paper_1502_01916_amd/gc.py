@@ -66,7 +66,7 @@ class PlanOpts(ctypes.Structure):
                 ("use_graph", ctypes.c_uint32), ("autotune", ctypes.c_uint32),
                 ("timing_slots", ctypes.c_uint32), ("schedule", ctypes.c_uint32),
                 ("class_tile_ints", ctypes.c_uint32 * 5), ("carry_pass", ctypes.c_uint32),
-                ("pack_ints", ctypes.c_uint32), ("pack_serial", ctypes.c_uint32)]
+                ("pack_ints", ctypes.c_uint32), ("graph_serial", ctypes.c_uint32)]
 
 
 # how the tiles of a delta list get their carries (gc_plan_opts.carry_pass)
@@ -349,7 +349,7 @@ class Plan:
 
     def __init__(self, ctx: Context, descs, headers, d_streams=None, d_out=None, tile_ints=0,
                  pfd_tile_ints=0, use_graph=False, autotune=False, timing_slots=0, locate_stream=False,
-                 carry_pass=CARRY_DEFAULT, class_tiles=None, pack_ints=0, pack_serial=False):
+                 carry_pass=CARRY_DEFAULT, class_tiles=None, pack_ints=0, graph_serial=False):
         self.ctx = ctx
         nl = len(descs)
         arr = (ListDesc * max(nl, 1))()
@@ -359,7 +359,7 @@ class Plan:
         ct = (ctypes.c_uint32 * 5)(*[int(t) for t in (class_tiles if class_tiles is not None else [0] * 5)])
         opts = PlanOpts(int(tile_ints), int(pfd_tile_ints), int(bool(use_graph)), int(bool(autotune)),
                         int(timing_slots), int(bool(locate_stream)), ct, int(carry_pass), int(pack_ints),
-                        int(bool(pack_serial)))
+                        int(bool(graph_serial)))
         self._h = ctypes.c_void_p()
         rc = lib().gc_plan_create(ctx._h, arr, nl, _u32(hdr), ctypes.byref(opts),
                                   _ptr(d_streams) if d_streams is not None else None,
