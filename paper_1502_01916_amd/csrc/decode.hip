@@ -789,14 +789,34 @@ __device__ uint32_t wprologue_sim(const TileCtx &c, WaveSmem<TW, kClsSim> &sm, u
 
 // ---- Group-Scheme, unary descriptors ----------------------------------------
 // Every 0 bit of the control area ends one tuple's code (bits outside the
-// tile's [p0, p1) read as 1).  The control bits are split into 64 ranges of
-// equal length; each lane counts the terminators in its range and, after a
-// wave scan of the counts, writes their positions in rank order to Z (a
-// compaction with Z[0] = the position just before the tile).  Lane l then
-// turns Z[l*TPL .. l*TPL + TPL] into the records of its TPL tuples: a code
-// spans the bits after the previous terminator up to its own (incomplete
-// units: not across a byte, so it starts at the byte boundary at the
-// latest), and its data follow the data of the codes before it.
+// tile's [p0, p1) read as 1).  Terminator r (r-th zero bit of the tile) is
+// found in two steps.  A pass over the staged words (64 per round, one per
+// lane) counts each word's zeros; their exclusive prefix ZE[w] is the rank
+// of word w's first terminator, and each word with zeros leaves its index
+// + 1 as a marker at that rank.  Lane l owns tuples t0 = l*TPL .. t0+TPL-1:
+// a running maximum over the markers of ranks up to t0 + i (in-lane, then
+// across the wave) names the word of terminator t0 + i.  The lane selects
+// terminator t0 in its word (rank t0 - ZE[w] among the word's zeros) and
+// steps through the next ones with ctz; terminator t0 - 1 comes from the
+// lane before (lane 0: the position just before the tile).  A code spans
+// the bits after the previous terminator up to its own (incomplete units:
+// not across a byte, so it starts at the byte boundary at the latest), and
+// its data follow the data of the codes before it.
+
+// Position of the k-th (from 0) set bit of x (k < popcount(x)).
+__device__ __forceinline__ uint32_t select_bit(uint32_t x, uint32_t k) {
+    uint32_t pos = 0;
+#pragma unroll
+    for (uint32_t h = 16u; h; h >>= 1) {
+        const uint32_t c = (uint32_t)__builtin_popcount(x & ((1u << h) - 1u));
+        const bool up = k >= c;
+        k = up ? k - c : k;
+        x = up ? x >> h : x;
+        pos = up ? pos + h : pos;
+    }
+    return pos;
+}
+
 template <int TW, int CE>
 __device__ uint32_t wprologue_gscu(const TileCtx &c, WaveSmem<TW, kClsGscU> &sm, uint32_t lane, uint32_t &dbase,
                                    const uint32_t (&ce)[CE], bool cok) {
@@ -809,6 +829,9 @@ __device__ uint32_t wprologue_gscu(const TileCtx &c, WaveSmem<TW, kClsGscU> &sm,
     const uint32_t cw0 = p0 >> 5, cw1 = (p1 + 31u) >> 5;
     const uint32_t nctrl = cw1 - cw0;
     if (!(p1 >= p0 && cw1 <= c.C && nctrl <= (uint32_t)SM::NCTRL && cok)) return kErrRange;
+    // the rank markers, in the record offsets until the records are written
+    uint16_t *mk = sm.rel;
+    zero_markers<SM::TTM>(mk, lane);
     // bits outside the tile's [p0, p1) read as 1
     auto put = [&](uint32_t i, uint32_t v) {
         const uint32_t gw = cw0 + i;
@@ -828,39 +851,59 @@ __device__ uint32_t wprologue_gscu(const TileCtx &c, WaveSmem<TW, kClsGscU> &sm,
     dbase = (uint32_t)(abs0 >> 5);
     const uint32_t p0r = p0 & 31u;   // bit positions count from 32 * cw0
     wave_lds_sync();
-    const uint32_t nbits = 32u * nctrl;
-    const uint32_t B = (nbits + 63u) >> 6;
-    const uint32_t ra = min(lane * B, nbits), rb = min(ra + B, nbits);
-    const uint32_t wa = ra >> 5, wb = (rb + 31u) >> 5;
-    auto zeros = [&](uint32_t w) -> uint32_t {   // terminators of word w inside [ra, rb)
-        uint32_t z = ~sm.ctrl[w];
-        const uint32_t lo = 32u * w;
-        if (ra > lo) z &= ~0u << (ra - lo);
-        if (rb < lo + 32u) z &= (1u << (rb - lo)) - 1u;
-        return z;
-    };
-    uint32_t cnt = 0;
-    for (uint32_t w = wa; w < wb; w++) cnt += (uint32_t)__builtin_popcount(zeros(w));
-    const uint32_t ic = wave_incl_scan(cnt);
-    const uint32_t tcnt = (uint32_t)__builtin_amdgcn_readlane((int)ic, 63);
-    if (tcnt < c.ntup) return kErrCount;
-    // Z[r + 1] = position of terminator r, plus one (16 bits); read before
-    // the records overwrite it
-    uint16_t *Z = sm.rel;
-    if (lane == 0) Z[0] = (uint16_t)p0r;
-    uint32_t r = ic - cnt;
-    for (uint32_t w = wa; w < wb && r < c.ntup; w++) {
-        uint32_t z = zeros(w);
-        while (z && r < c.ntup) {
-            Z[++r] = (uint16_t)(32u * w + (uint32_t)__builtin_ctz(z) + 1u);
-            z &= z - 1u;
-        }
+    // ZE[w] (16 bits) after the largest control area, and the markers
+    static_assert(SM::NCTRL + (SM::NCTRL + 1) / 2 <= 4 * SM::NB, "the word ranks fit the staging buffer");
+    uint16_t *ZE = reinterpret_cast<uint16_t *>(sm.ctrl + SM::NCTRL);
+    uint32_t run = 0;
+    for (uint32_t w0 = 0; w0 < nctrl; w0 += 64u) {
+        const uint32_t w = w0 + lane;
+        const bool in = w < nctrl;
+        const uint32_t cnt = in ? (uint32_t)__builtin_popcount(~sm.ctrl[w]) : 0u;
+        const uint32_t inc = wave_incl_scan(cnt);
+        const uint32_t ze = run + inc - cnt;
+        if (in) ZE[w] = (uint16_t)ze;
+        if (cnt && ze < c.ntup) mk[ze] = (uint16_t)(w + 1u);
+        run += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
     }
+    if (run < c.ntup) return kErrCount;
     wave_lds_sync();
     const uint32_t t0 = lane * (uint32_t)TPL;
-    uint32_t zr[TPL + 1];
+    // the word of terminator t0 + i: running maximum of the markers
+    uint32_t wd[TPL];
+    {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(mk) + lane * (TPL / 2);
 #pragma unroll
-    for (int i = 0; i <= TPL; i++) zr[i] = (uint32_t)Z[min(t0 + (uint32_t)i, c.ntup)] - 1u;
+        for (int h = 0; h < TPL / 2; h++) {
+            const uint32_t x = src[h];
+            wd[2 * h] = x & 0xFFFFu;
+            wd[2 * h + 1] = x >> 16;
+        }
+#pragma unroll
+        for (int i = 1; i < TPL; i++) wd[i] = max(wd[i], wd[i - 1]);
+        const uint32_t before = wave_shr1(wave_incl_max(wd[TPL - 1]));
+        // (rank 0's word always holds a marker, so every word index is >= 0;
+        // a lane past the tile's tuples repeats the last word with zeros)
+#pragma unroll
+        for (int i = 0; i < TPL; i++) wd[i] = max(max(wd[i], before), 1u) - 1u;
+    }
+    // positions of terminators t0 .. t0 + TPL - 1 (garbage past the tile's
+    // tuples, which no record uses)
+    uint32_t zr[TPL + 1];
+    {
+        uint32_t m = ~sm.ctrl[wd[0]];
+        const uint32_t p = select_bit(m, t0 - (uint32_t)ZE[wd[0]]);
+        zr[1] = 32u * wd[0] + p;
+        m &= ~(0xFFFFFFFFu >> (31u - p));   // the zeros after it
+#pragma unroll
+        for (int i = 1; i < TPL; i++) {
+            const uint32_t nw = ~sm.ctrl[wd[i]];
+            m = wd[i] != wd[i - 1] ? nw : m;
+            zr[i + 1] = 32u * wd[i] + (uint32_t)__builtin_ctz(m | 0x80000000u);
+            m &= m - 1u;
+        }
+        const uint32_t prev = wave_shr1(zr[TPL]);
+        zr[0] = lane ? prev : p0r - 1u;
+    }
     uint32_t st[TPL], un[TPL];
     uint32_t usum = 0;
     bool bad = false;
@@ -1080,6 +1123,8 @@ __device__ uint32_t wprologue_pfd(const TileCtx &c, WaveSmem<TW, kClsPfd> &sm, u
 template <int TW, typename W>
 __device__ uint32_t pfd_marks(const TileCtx &c, WaveSmem<TW, kClsPfd> &sm, uint32_t lane, W rows, uint32_t nrow,
                               const ExcSrc &xs, uint32_t *xv, uint32_t xv_cap, uint32_t &nexc_tile) {
+    // rows staged in LDS, or read from global memory
+    constexpr bool STAGED = __is_same(W, const uint32_t *);
     const uint32_t k = c.k, lk = c.lk;
     const uint32_t nb = (c.ntup + 31u) >> 5;
     const uint32_t BI = 32u * k;        // positions per block
@@ -1088,10 +1133,33 @@ __device__ uint32_t pfd_marks(const TileCtx &c, WaveSmem<TW, kClsPfd> &sm, uint3
     for (uint32_t w = lane; w < nbw; w += 64u) sm.bmap[w] = 0u;
     wave_lds_sync();
     bool bad = false;
-    if (linked) {
+    if (linked && STAGED) {
         // one lane walks the chain of one block; position p is component
-        // p mod k of the block's tuple p / k, at bit (p / k) * b of its rows.
-        // At k = 4 the block's four bitmap words stay in registers.
+        // p mod k of the block's tuple p / k, at bit (p / k) * b of its rows,
+        // and sets its bit in the block's k bitmap words.  The row is
+        // clamped to the staged span, whose padding row follows it, so the
+        // second read needs no test.
+        const uint32_t km1 = k - 1u, rlast = nrow ? nrow - 1u : 0u;
+        for (uint32_t j = lane; j < nb; j += 64u) {
+            const uint32_t desc = sm.bdesc[j], nexc = desc >> 20, b = desc & 63u, M = mask_of(b);
+            const uint32_t o0 = 32u * sm.brow[j];
+            uint32_t *bw = sm.bmap + j * k;
+            uint32_t p = (desc >> 8) & 0xFFFu;
+            for (uint32_t e = 0; e < nexc; e++) {
+                if (p >= BI) {
+                    bad = true;
+                    break;
+                }
+                const uint32_t O = o0 + __umul24(p >> lk, b);
+                const uint32_t at = (min(O >> 5, rlast) << lk) | (p & km1);
+                const uint32_t slot = funnel(rows[at + k], rows[at], O) & M;
+                atomicOr(bw + (p >> 5), 1u << (p & 31u));
+                p += 1u + min(slot, BI);
+            }
+        }
+    } else if (linked) {
+        // the same walk over rows in global memory, with clamped reads; at
+        // k = 4 the block's four bitmap words stay in registers
         for (uint32_t j = lane; j < nb; j += 64u) {
             const uint32_t desc = sm.bdesc[j], nexc = desc >> 20, b = desc & 63u, M = mask_of(b);
             const uint32_t o0 = 32u * sm.brow[j];
@@ -2122,8 +2190,10 @@ __device__ __forceinline__ uint32_t pack_recs_pfd(PackSmem<PI, SW> &sm, const ui
             continue;
         }
         if (!bitmap && k == 4u) {
-            // 128 positions: the block's four words in registers
-            uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+            // 128 positions: each exception's bit goes into the block's
+            // words by an LDS or; the words are read back for their counts.
+            // A block with b = 0 reads its first data row (masked off).
+            for (uint32_t w = 0; w < nw; w++) bm[w] = 0u;
             uint32_t p = first;
             const uint32_t lim = real_t << 2;
             for (uint32_t e = 0; e < nexc; e++) {
@@ -2131,32 +2201,16 @@ __device__ __forceinline__ uint32_t pack_recs_pfd(PackSmem<PI, SW> &sm, const ui
                     chain_bad = true;
                     break;
                 }
-                const uint32_t bit = 1u << (p & 31u), wq = p >> 5;
-                m0 |= wq == 0u ? bit : 0u;
-                m1 |= wq == 1u ? bit : 0u;
-                m2 |= wq == 2u ? bit : 0u;
-                m3 |= wq == 3u ? bit : 0u;
+                atomicOr(bm + (p >> 5), 1u << (p & 31u));
                 const uint32_t O = (p >> 2) * b;
-                const uint32_t at = 4u * (c0 + (O >> 5)) + (p & 3u);
-                const uint32_t slot = b ? funnel(sw[at + 4u], sw[at], O & 31u) & M : 0u;
-                p = p + slot + 1u;
+                const uint32_t at = ((c0 + (O >> 5)) << 2) | (p & 3u);
+                const uint32_t slot = funnel(sw[at + 4u], sw[at], O) & M;
+                p += 1u + min(slot, 128u);
             }
-            const uint32_t c1 = (uint32_t)__builtin_popcount(m0), c2 = c1 + (uint32_t)__builtin_popcount(m1),
-                           c3 = c2 + (uint32_t)__builtin_popcount(m2);
-            const uint32_t vb0 = 32u * v0;
-            bm[0] = m0;
-            vb[0] = (vb0 << 2) | wcode;
-            if (nw > 1u) {
-                bm[1] = m1;
-                vb[1] = ((vb0 + c1 * ew) << 2) | wcode;
-            }
-            if (nw > 2u) {
-                bm[2] = m2;
-                vb[2] = ((vb0 + c2 * ew) << 2) | wcode;
-            }
-            if (nw > 3u) {
-                bm[3] = m3;
-                vb[3] = ((vb0 + c3 * ew) << 2) | wcode;
+            uint32_t before = 0;
+            for (uint32_t w = 0; w < nw; w++) {
+                vb[w] = ((32u * v0 + before * ew) << 2) | wcode;
+                before += (uint32_t)__builtin_popcount(bm[w]);
             }
             continue;
         }
