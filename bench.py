@@ -361,7 +361,8 @@ def measure(gc, torch, ctx, wl, args, keep_device=False):
     log("%s plan: %s (%.1fs)" % (wl.name, cfg, time.time() - t))
     tplan = gc.Plan(ctx, descs, headers, d_s, d_o, class_tiles=cfg["class_tiles"],
                     locate_stream=args.locate_stream, timing_slots=args.steps + args.warmup,
-                    carry_pass=args.carry_pass, pack_ints=cfg["pack_ints"] or gc.PACK_OFF)
+                    carry_pass=args.carry_pass, pack_ints=cfg["pack_ints"] or gc.PACK_OFF,
+                    pack_groups=cfg["pack_groups"])
     packed = plan.packed_lists(wl.lengths.size)
     elapsed = timed(lambda: plan.decode_batch(d_s, d_o), args.steps, args.warmup, torch)
     t_events = timed(lambda: tplan.decode_batch(d_s, d_o), args.steps, args.warmup, torch)
@@ -427,6 +428,8 @@ def leg_record(wl, m):
     return dict(workload=wl.desc, value=round(m.value, 3), unit="Gints/s", ms_per_step=round(m.ms_per_step, 4),
                 ints_per_step=wl.ints, lists=int(wl.lengths.size), bits_per_int=round(32.0 * wl.streams.size / wl.ints, 3),
                 path_hbm_frac=round(m.path_gbs / HBM_PEAK_GBS, 4), class_tile_ints=m.cfg["class_tiles"],
+                pack_ints=m.cfg["pack_ints"], packs=m.cfg["packs"],
+                pack_groups_per_cu=(None if m.cfg["pack_groups"] == 0x80000000 else m.cfg["pack_groups"]),
                 dominant_kernel=m.kname, dominant_kernel_ms=round(m.dec_avg, 4),
                 dominant_kernel_hbm_frac=round(m.achieved / HBM_PEAK_GBS, 4), phases_ms=m.phases,
                 verified_bit_exact=m.verified)
@@ -712,6 +715,7 @@ def main():
             "pack_ints": m.cfg["pack_ints"],
             "packs": m.cfg["packs"],
             "packed_lists": m.cfg["packed_lists"],
+            "pack_groups_per_cu": (None if m.cfg["pack_groups"] == gc.PACK_GROUPS_ALL else m.cfg["pack_groups"]),
             "verified_bit_exact": m.verified,
         },
         "path_hbm_frac": round(m.path_gbs / HBM_PEAK_GBS, 4),

@@ -242,8 +242,14 @@ typedef struct {
                                 the rest, and after the locate pass each
                                 codec class's passes on a branch of their own
                                 (with schedule 0)                            */
+    uint32_t pack_groups;    /* workgroups (four waves) of the pack kernel per
+                                CU, 1 .. 64: each wave then decodes packs in
+                                turn, leaving room on every CU for the other
+                                passes; GC_PACK_GROUPS_ALL: one wave per pack;
+                                0 = autotuned (with autotune) or the default, 5 */
 } gc_plan_opts;
 #define GC_PACK_OFF 0x80000000u
+#define GC_PACK_GROUPS_ALL 0x80000000u
 
 /* Builds a batched decode plan for nlists lists.  h_headers holds the first
  * 4 words of every stream (4*nlists words, host memory).  The plan holds the
@@ -305,9 +311,11 @@ gc_status gc_plan_config(const gc_plan *plan, uint32_t *tile_ints, uint32_t *pfd
                          uint64_t *tiles, uint64_t *sum_tiles);
 
 /* The packed-list threshold a plan uses (0: no packing), its packs (waves
- * of the pack kernels) and the lists they hold.  Any pointer may be NULL.  */
+ * of the pack kernels), the lists they hold and the pack kernel's
+ * workgroups per CU (GC_PACK_GROUPS_ALL: one wave per pack).  Any pointer
+ * may be NULL.                                                             */
 gc_status gc_plan_pack_config(const gc_plan *plan, uint32_t *pack_ints, uint64_t *packs,
-                              uint64_t *packed_lists);
+                              uint64_t *packed_lists, uint32_t *pack_groups);
 
 /* Which lists of a plan the pack kernel decodes: h_packed[i] (host memory,
  * nlists bytes) = 1 for a packed list, 0 for one the class passes decode.  */

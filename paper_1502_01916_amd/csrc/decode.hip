@@ -2325,19 +2325,15 @@ __device__ __forceinline__ void pack_unpack(PackSmem<PI, SW> &sm, uint32_t lane,
     }
 }
 
+// Pack p, decoded by one wave; false after latching an error.
 template <int PI, int SW>
-__global__ __launch_bounds__(kThreads) void gc_pack_kernel(PackArgs a) {
+__device__ __forceinline__ bool pack_one(const PackArgs &a, PackSmem<PI, SW> &sm, uint32_t p, uint32_t lane) {
     using SM = PackSmem<PI, SW>;
-    __shared__ SM smem[kWaves];
-    const uint32_t wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63u;
-    const uint32_t p = blockIdx.x * (uint32_t)kWaves + wave;
-    if (p >= a.npacks) return;
-    SM &sm = smem[wave];
     const uint32_t f0 = ((const gu32 *)a.first)[p], f1 = ((const gu32 *)a.first)[p + 1u];
     const uint32_t np = f1 - f0;
     if (np == 0u || np > kPackLists) {
         if (lane == 0) latch(a.status, kErrPack);
-        return;
+        return false;
     }
     // lane j: list j's descriptor
     union {
@@ -2381,18 +2377,18 @@ __global__ __launch_bounds__(kThreads) void gc_pack_kernel(PackArgs a) {
     const uint32_t U = (uint32_t)__builtin_amdgcn_readlane((int)i_u, 63);
     if (wave_any(!same || !dok) || !hok || cls < 0) {
         if (lane == 0) latch(a.status, kErrHeader);
-        return;
+        return false;
     }
     // a list with tuples but no control units (Group-Simple, unary
     // Group-Scheme, Group-AFOR) would leave its tuples unclaimed
     if (wave_any(mine && T && !units && cls != kClsGscB)) {
         if (lane == 0) latch(a.status, kErrCount);
-        return;
+        return false;
     }
     if (tot_ch > (uint32_t)SW / 4u || TT > (uint32_t)SM::TUP || (TT << lk) > (uint32_t)PI ||
         (cls == kClsPfd && U > (uint32_t)SM::NBLK)) {
         if (lane == 0) latch(a.status, kErrPack);
-        return;
+        return false;
     }
     const uint32_t so = i_ch - ch, tbase = i_t - Tp;
     if (lane <= kPackLists) {
@@ -2439,7 +2435,7 @@ __global__ __launch_bounds__(kThreads) void gc_pack_kernel(PackArgs a) {
     if (mine) hbad = sw[4u * so] != d.w0 || sw[4u * so + 1u] != d.n || sw[4u * so + 2u] != C || sw[4u * so + 3u] != D;
     if (wave_any(hbad)) {
         if (lane == 0) latch(a.status, kErrHeader);
-        return;
+        return false;
     }
     // per-list values for the record builders
     uint16_t *Tl = sm.lt[0], *cwl = sm.lt[1], *Cl = sm.lt[2], *Dl = sm.lt[3], *Wl = sm.lt[4], *d0l = sm.lt[5];
@@ -2469,7 +2465,7 @@ __global__ __launch_bounds__(kThreads) void gc_pack_kernel(PackArgs a) {
     }
     if (err) {
         if (lane == 0) latch(a.status, err);
-        return;
+        return false;
     }
     wave_lds_sync();
     const uint32_t NQ = TT * kq;
@@ -2481,6 +2477,21 @@ __global__ __launch_bounds__(kThreads) void gc_pack_kernel(PackArgs a) {
         PatchSrc ps{nullptr, nullptr, nullptr, nullptr, ExcSrc{nullptr, nullptr, 0u, false}, false};
         if (k == 4u) pack_unpack<false, true>(sm, lane, NQ, 0u, 1u, 2u, ps);
         else pack_unpack<false, false>(sm, lane, NQ, lk - 2u, kq, lk, ps);
+    }
+    return true;
+}
+
+// A wave per pack, the grid striding over the packs when it is smaller
+// than their number (the launch caps it, so that the packs, which depend on
+// nothing else, leave room on every CU for the passes beside them).
+template <int PI, int SW>
+__global__ __launch_bounds__(kThreads) void gc_pack_kernel(PackArgs a) {
+    __shared__ PackSmem<PI, SW> smem[kWaves];
+    const uint32_t wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63u;
+    const uint32_t stride = gridDim.x * (uint32_t)kWaves;
+    for (uint32_t p = blockIdx.x * (uint32_t)kWaves + wave; p < a.npacks; p += stride) {
+        if (!pack_one<PI, SW>(a, smem[wave], p, lane)) return;
+        wave_lds_sync();
     }
 }
 
@@ -2567,10 +2578,12 @@ static const void *decode_fn(int tile, int cls) {
 }
 
 // Launches the pack kernel of capacity pi integers (2048 or 4096) over
-// a.npacks packs.
-int launch_pack(int pi, const PackArgs &a, hipStream_t s) {
+// a.npacks packs, with at most max_groups workgroups (0: one wave per pack).
+int launch_pack(int pi, const PackArgs &a, hipStream_t s, uint32_t max_groups) {
     if (!a.npacks) return 0;
-    const dim3 grid((a.npacks + kWaves - 1) / kWaves);
+    uint32_t groups = (a.npacks + kWaves - 1) / kWaves;
+    if (max_groups && groups > max_groups) groups = max_groups;
+    const dim3 grid(groups);
     if (pi == 2048) hipLaunchKernelGGL((gc_pack_kernel<2048, 512>), grid, dim3(kThreads), 0, s, a);
     else if (pi == 4096) hipLaunchKernelGGL((gc_pack_kernel<4096, 1024>), grid, dim3(kThreads), 0, s, a);
     else return -2;

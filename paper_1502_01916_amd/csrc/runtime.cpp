@@ -28,7 +28,7 @@ int codec_class(uint32_t w0);
 int launch_locate(const LocateArgs &a, int chunk_words, hipStream_t s);
 int launch_carry_scan(const CarryArgs &a, hipStream_t s);
 int launch_decode(int tile, int cls, int mode, const DecodeArgs &a, hipStream_t s);
-int launch_pack(int pt, const PackArgs &a, hipStream_t s);
+int launch_pack(int pt, const PackArgs &a, hipStream_t s, uint32_t max_groups);
 int noalloc_setup(int device, void **ptr);
 void *noalloc_ptr(int device);
 }  // namespace gcdev
@@ -39,6 +39,8 @@ namespace {
 
 constexpr int kDefaultWaveTile = 2048;
 constexpr int kDefaultPfdTile = 4096;
+// Pack kernel workgroups per CU by default: five of the six its LDS allows.
+constexpr uint32_t kDefaultPackGroups = 5u;
 // Carries of delta lists: a list of at most lb_max tiles finds them in the
 // decode pass by decoupled look-back (one window of flags covers a list of
 // up to 64 tiles); longer lists take a tile-sum pass and a carry scan ahead
@@ -286,6 +288,8 @@ struct gc_plan {
     // decoded by the pack kernel instead of the class passes; 0: none
     uint32_t pack_max = 0;
     bool pack_forced = false;                  // pack_max set by the plan options
+    uint32_t pack_groups = kDefaultPackGroups; // pack workgroups per CU (GC_PACK_GROUPS_ALL: a wave per pack)
+    bool groups_forced = false;                // pack_groups set by the plan options
     std::vector<uint8_t> packed;               // per list
     PackSet pk[2];                             // packs of the kernel of capacity kPackInts[0] / [1] (one is used)
     bool branches = true;                      // graph: the pack kernel and each class's passes on branches
@@ -697,7 +701,8 @@ gc_status launch_packs(gc_plan *p, hipStream_t s) {
         a.first = ps.d_first;
         a.npacks = ps.packs();
         a.status = p->ctx->status;
-        if (launch_pack((int)kPackInts[k], a, s)) return GC_EDEVICE;
+        const uint32_t cap = p->pack_groups == GC_PACK_GROUPS_ALL ? 0u : p->pack_groups * (uint32_t)p->ctx->num_cus;
+        if (launch_pack((int)kPackInts[k], a, s, cap)) return GC_EDEVICE;
     }
     return GC_OK;
 }
@@ -833,13 +838,14 @@ gc_status plan_run(gc_plan *p, hipStream_t s) {
     return plan_launch(p, s);
 }
 
-// ---- autotune cache: one JSON object {key: [tile of each class], ...} -----
+// ---- autotune cache: one JSON object {key: [tile of each class, packed-list
+// threshold, pack workgroups per CU], ...} ------------------------------------
 std::string cache_path() {
     const char *e = std::getenv("GC_AUTOTUNE_CACHE");
     return e ? std::string(e) : std::string();
 }
 
-bool cache_lookup(const std::string &key, int *tiles, uint32_t *pack_max) {
+bool cache_lookup(const std::string &key, int *tiles, uint32_t *pack_max, uint32_t *pack_groups) {
     const std::string path = cache_path();
     if (path.empty()) return false;
     std::ifstream f(path);
@@ -851,20 +857,23 @@ bool cache_lookup(const std::string &key, int *tiles, uint32_t *pack_max) {
     const size_t at = s.find(pat);
     if (at == std::string::npos) return false;
     int t[kClasses];
-    unsigned pm = 0;
+    unsigned pm = 0, pg = kDefaultPackGroups;
     static_assert(kClasses == 5, "five classes in the cache format");
-    if (std::sscanf(s.c_str() + at + pat.size(), "%d, %d, %d, %d, %d, %u", &t[0], &t[1], &t[2], &t[3], &t[4],
-                    &pm) != 6)
+    // [tiles of the five classes, packed-list threshold, pack workgroups per CU]
+    if (std::sscanf(s.c_str() + at + pat.size(), "%d, %d, %d, %d, %d, %u, %u", &t[0], &t[1], &t[2], &t[3], &t[4],
+                    &pm, &pg) != 7)
         return false;
+    if (pg != GC_PACK_GROUPS_ALL && (pg == 0u || pg > 64u)) return false;
     for (int c = 0; c < kClasses; c++)   // an entry that fails validation falls back to the defaults
         if (!valid_wave_tile((uint32_t)t[c])) return false;
     if (pm > kPackInts[1]) return false;
     for (int c = 0; c < kClasses; c++) tiles[c] = t[c];
     *pack_max = pm;
+    *pack_groups = pg;
     return true;
 }
 
-void cache_store(const std::string &key, const int *tiles, uint32_t pack_max) {
+void cache_store(const std::string &key, const int *tiles, uint32_t pack_max, uint32_t pack_groups) {
     const std::string path = cache_path();
     if (path.empty()) return;
     std::string s;
@@ -888,8 +897,8 @@ void cache_store(const std::string &key, const int *tiles, uint32_t pack_max) {
         pos = rb + 1;
     }
     char buf[128];
-    std::snprintf(buf, sizeof(buf), "[%d, %d, %d, %d, %d, %u]", tiles[0], tiles[1], tiles[2], tiles[3], tiles[4],
-                  pack_max);
+    std::snprintf(buf, sizeof(buf), "[%d, %d, %d, %d, %d, %u, %u]", tiles[0], tiles[1], tiles[2], tiles[3],
+                  tiles[4], pack_max, pack_groups);
     entries.push_back("\"" + key + "\": " + buf);
     std::ofstream f(path);
     f << "{\n";
@@ -919,7 +928,8 @@ std::string plan_key(const gc_plan *p) {
     std::string key = p->ctx->arch + ":k" + std::to_string(1 << lk) + ":n2^" + std::to_string(lg) + ":mean2^" +
                       std::to_string(lm) + ":c" + std::to_string(p->lb_max) + ":s" +
                       std::to_string(p->nlists ? short_lists * 8 / p->nlists : 0) +
-                      (p->pack_forced ? ":p" + std::to_string(p->pack_max) : std::string()) + ":mix";
+                      (p->pack_forced ? ":p" + std::to_string(p->pack_max) : std::string()) +
+                      (p->groups_forced ? ":g" + std::to_string(p->pack_groups) : std::string()) + ":mix";
     for (int c = 0; c < kClasses; c++)
         key += (c ? "-" : "") + std::to_string(total ? per_cls[c] * 8 / total : 0);
     return key;
@@ -937,10 +947,11 @@ gc_status autotune(gc_plan *p, const uint32_t *d_streams, uint32_t *d_out) {
     const std::string key = plan_key(p);
     int best_t[kClasses];
     for (int c = 0; c < kClasses; c++) best_t[c] = p->tile[c];
-    uint32_t best_pm = p->pack_max;
-    if (cache_lookup(key, best_t, &best_pm)) {
+    uint32_t best_pm = p->pack_max, best_pg = p->pack_groups;
+    if (cache_lookup(key, best_t, &best_pm, &best_pg)) {
         for (int c = 0; c < kClasses; c++) p->tile[c] = best_t[c];
         p->pack_max = best_pm;
+        p->pack_groups = best_pg;
         return GC_OK;
     }
     bool present[kClasses] = {};
@@ -978,16 +989,29 @@ gc_status autotune(gc_plan *p, const uint32_t *d_streams, uint32_t *d_out) {
         }
     }
     for (int c = 0; c < kClasses; c++) p->tile[c] = best_t[c];
-    if (!p->pack_forced) {
+    if (!p->pack_forced || !p->groups_forced) {
+        // the packed-list threshold and the pack kernel's workgroups per CU:
         // three sweeps over the candidates, each timing 8 runs queued back
         // to back (as a caller replays them, so that launching one overlaps
         // the previous), the best sweep kept: the candidates can differ by a
         // few per cent, and interleaving them spreads clock and cache drift
-        const uint32_t cand[4] = {0u, 1024u, kPackInts[0], kPackInts[1]};
-        float best_ms[4] = {1e30f, 1e30f, 1e30f, 1e30f};
-        for (int sweep = 0; sweep < 3 && !rc; sweep++) {
-            for (int i = 0; i < 4 && !rc; i++) {
-                p->pack_max = cand[i];
+        std::vector<std::pair<uint32_t, uint32_t>> cand;
+        const uint32_t pms[4] = {0u, 1024u, kPackInts[0], kPackInts[1]};
+        const uint32_t gs[2] = {GC_PACK_GROUPS_ALL, kDefaultPackGroups};
+        for (uint32_t pm : pms) {
+            if (p->pack_forced && pm != p->pack_max) continue;
+            for (uint32_t g : gs) {
+                if (p->groups_forced && g != p->pack_groups) continue;
+                if (pm == 0u && !cand.empty() && cand.back().first == 0u) continue;   // no packs: one candidate
+                cand.emplace_back(pm, p->groups_forced ? p->pack_groups : g);
+            }
+        }
+        if (cand.empty()) cand.emplace_back(p->pack_max, p->pack_groups);
+        std::vector<float> best_ms(cand.size(), 1e30f);
+        for (int sweep = 0; sweep < 3 && !rc && cand.size() > 1; sweep++) {
+            for (size_t i = 0; i < cand.size() && !rc; i++) {
+                p->pack_max = cand[i].first;
+                p->pack_groups = cand[i].second;
                 rc = plan_materialize(p);
                 if (!rc) rc = plan_upload(p, d_streams, d_out);
                 // a plan replayed from a graph is timed that way: its
@@ -1009,15 +1033,18 @@ gc_status autotune(gc_plan *p, const uint32_t *d_streams, uint32_t *d_out) {
                 best_ms[i] = std::min(best_ms[i], ms);
             }
         }
-        if (!rc) best_pm = cand[std::min_element(best_ms, best_ms + 4) - best_ms];
+        const size_t bi = cand.size() > 1 ? std::min_element(best_ms.begin(), best_ms.end()) - best_ms.begin() : 0;
+        best_pm = cand[bi].first;
+        best_pg = cand[bi].second;
         plan_free_graphs(p);
         p->pack_max = best_pm;
+        p->pack_groups = best_pg;
     }
     for (hipEvent_t e : ev)
         if (e) (void)hipEventDestroy(e);
     if (rc) return rc;
     for (int c = 0; c < kClasses; c++) p->tile[c] = best_t[c];
-    cache_store(key, best_t, p->pack_max);
+    cache_store(key, best_t, p->pack_max, p->pack_groups);
     return GC_OK;
 }
 
@@ -1189,6 +1216,7 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     }
     if (o.schedule > 1u || o.carry_pass > 3u) return GC_EINVAL;
     if (o.pack_ints && o.pack_ints != GC_PACK_OFF && o.pack_ints > kPackInts[1]) return GC_EINVAL;
+    if (o.pack_groups && o.pack_groups != GC_PACK_GROUPS_ALL && o.pack_groups > 64u) return GC_EINVAL;
     if ((o.autotune || o.use_graph) && nlists && (!d_streams || !d_out)) return GC_EINVAL;
     gc_plan *p = new (std::nothrow) gc_plan();
     if (!p) return GC_ENOMEM;
@@ -1208,6 +1236,8 @@ gc_status gc_plan_create(gc_ctx *ctx, const gc_list_desc *h_descs, size_t nlists
     }
     p->branches = o.graph_serial == 0u;
     p->pack_max = o.pack_ints == GC_PACK_OFF ? 0u : o.pack_ints ? o.pack_ints : kDefaultPackMax;
+    p->groups_forced = o.pack_groups != 0u;
+    if (o.pack_groups) p->pack_groups = o.pack_groups;
     p->lb_max = o.carry_pass == 1u ? kLookbackAll : o.carry_pass == 2u ? 0u
               : o.carry_pass == 3u ? kLookbackHybrid : kDefaultLbMax;
     // tests of the look-back's bounded wait: tiles stop publishing their
@@ -1345,7 +1375,8 @@ gc_status gc_plan_config(const gc_plan *plan, uint32_t *tile_ints, uint32_t *pfd
     return GC_OK;
 }
 
-gc_status gc_plan_pack_config(const gc_plan *plan, uint32_t *pack_ints, uint64_t *packs, uint64_t *packed_lists) {
+gc_status gc_plan_pack_config(const gc_plan *plan, uint32_t *pack_ints, uint64_t *packs, uint64_t *packed_lists,
+                              uint32_t *pack_groups) {
     if (!plan) return GC_EINVAL;
     uint64_t np = 0, nl = 0;
     for (const PackSet &ps : plan->pk) {
@@ -1355,6 +1386,7 @@ gc_status gc_plan_pack_config(const gc_plan *plan, uint32_t *pack_ints, uint64_t
     if (pack_ints) *pack_ints = plan->pack_max;
     if (packs) *packs = np;
     if (packed_lists) *packed_lists = nl;
+    if (pack_groups) *pack_groups = plan->pack_groups;
     return GC_OK;
 }
 

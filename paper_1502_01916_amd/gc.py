@@ -26,6 +26,7 @@ CLS_SIMPLE, CLS_SCHEME_UNARY, CLS_SCHEME_BINARY, CLS_AFOR, CLS_PFD = range(5)
 CLASSES = 5
 TIMING_FIELDS = 2 + 3 * CLASSES
 PACK_OFF = 0x80000000   # gc_plan_opts.pack_ints: no packed lists
+PACK_GROUPS_ALL = 0x80000000   # gc_plan_opts.pack_groups: one wave per pack
 OK, EINVAL, ENOSPC, ECORRUPT, EDEVICE, EUNSUPPORTED, ENOMEM = 0, -1, -2, -3, -4, -5, -6
 _NAMES = {0: "GC_OK", -1: "GC_EINVAL", -2: "GC_ENOSPC", -3: "GC_ECORRUPT", -4: "GC_EDEVICE",
           -5: "GC_EUNSUPPORTED", -6: "GC_ENOMEM"}
@@ -66,7 +67,8 @@ class PlanOpts(ctypes.Structure):
                 ("use_graph", ctypes.c_uint32), ("autotune", ctypes.c_uint32),
                 ("timing_slots", ctypes.c_uint32), ("schedule", ctypes.c_uint32),
                 ("class_tile_ints", ctypes.c_uint32 * 5), ("carry_pass", ctypes.c_uint32),
-                ("pack_ints", ctypes.c_uint32), ("graph_serial", ctypes.c_uint32)]
+                ("pack_ints", ctypes.c_uint32), ("graph_serial", ctypes.c_uint32),
+                ("pack_groups", ctypes.c_uint32)]
 
 
 # how the tiles of a delta list get their carries (gc_plan_opts.carry_pass)
@@ -133,7 +135,7 @@ def lib():
         L.gc_decode_each.argtypes = [vp, vp, vp, vp]
         L.gc_plan_config.argtypes = [vp, u32p, u32p, u64p, u64p]
         L.gc_plan_class_tiles.argtypes = [vp, u32p]
-        L.gc_plan_pack_config.argtypes = [vp, u32p, u64p, u64p]
+        L.gc_plan_pack_config.argtypes = [vp, u32p, u64p, u64p, u32p]
         L.gc_plan_packed_lists.argtypes = [vp, vp, sz]
         L.gc_plan_timings.argtypes = [vp, ctypes.c_uint32, f32p, u32p]
         L.gc_plan_timings.restype = ctypes.c_int
@@ -349,7 +351,7 @@ class Plan:
 
     def __init__(self, ctx: Context, descs, headers, d_streams=None, d_out=None, tile_ints=0,
                  pfd_tile_ints=0, use_graph=False, autotune=False, timing_slots=0, locate_stream=False,
-                 carry_pass=CARRY_DEFAULT, class_tiles=None, pack_ints=0, graph_serial=False):
+                 carry_pass=CARRY_DEFAULT, class_tiles=None, pack_ints=0, graph_serial=False, pack_groups=0):
         self.ctx = ctx
         nl = len(descs)
         arr = (ListDesc * max(nl, 1))()
@@ -359,7 +361,7 @@ class Plan:
         ct = (ctypes.c_uint32 * 5)(*[int(t) for t in (class_tiles if class_tiles is not None else [0] * 5)])
         opts = PlanOpts(int(tile_ints), int(pfd_tile_ints), int(bool(use_graph)), int(bool(autotune)),
                         int(timing_slots), int(bool(locate_stream)), ct, int(carry_pass), int(pack_ints),
-                        int(bool(graph_serial)))
+                        int(bool(graph_serial)), int(pack_groups))
         self._h = ctypes.c_void_p()
         rc = lib().gc_plan_create(ctx._h, arr, nl, _u32(hdr), ctypes.byref(opts),
                                   _ptr(d_streams) if d_streams is not None else None,
@@ -394,12 +396,12 @@ class Plan:
                                                       ctypes.byref(n), ctypes.byref(ns)))
         ct = (ctypes.c_uint32 * CLASSES)()
         _check("gc_plan_class_tiles", lib().gc_plan_class_tiles(self._h, ct))
-        pi, npk, npl = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
+        pi, npk, npl, pg = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint32()
         _check("gc_plan_pack_config", lib().gc_plan_pack_config(self._h, ctypes.byref(pi), ctypes.byref(npk),
-                                                                ctypes.byref(npl)))
+                                                                ctypes.byref(npl), ctypes.byref(pg)))
         return dict(tile_ints=t.value, pfd_tile_ints=pt.value, tiles=n.value, sum_tiles=ns.value,
                     class_tiles=[int(x) for x in ct], pack_ints=pi.value, packs=npk.value,
-                    packed_lists=npl.value)
+                    packed_lists=npl.value, pack_groups=pg.value)
 
     def packed_lists(self, nlists):
         """gc_plan_packed_lists: a bool array, True for the lists the pack

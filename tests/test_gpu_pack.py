@@ -1,8 +1,10 @@
-"""GPU parity of the pack kernels, which decode many short lists per wave
-(each list's whole stream staged in LDS, the codec's prologue and unpack run
-list after list): element by element against the oracle, for every codec
-variant and layout width, ragged and aligned outputs, replayed from a graph,
-and beside lists that stay on the class passes."""
+"""GPU parity of the pack kernels, which decode up to 32 short lists of one
+stream format per wave (their streams staged in LDS together, their control
+units parsed and their integers unpacked together): element by element
+against the oracle, for every codec variant and layout width, ragged and
+aligned outputs, replayed from a graph, beside lists that stay on the class
+passes, and with the kernel's grid capped so that each wave decodes many
+packs in turn."""
 import sys
 
 import numpy as np
@@ -75,12 +77,13 @@ def short_batch(rng, nlists, ks, lengths):
     return np.concatenate(streams), offs, np.array([x.size for x in lists], np.int64), lists
 
 
-def check_plan(torch, ctx, flat, offs, lengths, lists, align, graph, pack_ints, reps=2, expect_packed=True):
+def check_plan(torch, ctx, flat, offs, lengths, lists, align, graph, pack_ints, reps=2, expect_packed=True,
+               pack_groups=0):
     descs, headers, out_offs = gc.batch_layout(flat, offs, lengths, align=align)
     d_s = gc.to_device(flat)
     total = int(out_offs[-1])
     d_o = torch.full((total + 64,), -1, dtype=torch.int32, device="cuda")
-    plan = gc.Plan(ctx, descs, headers, d_s, d_o, use_graph=graph, pack_ints=pack_ints)
+    plan = gc.Plan(ctx, descs, headers, d_s, d_o, use_graph=graph, pack_ints=pack_ints, pack_groups=pack_groups)
     cfg = plan.config()
     say("  plan", cfg)
     if expect_packed:
@@ -182,12 +185,38 @@ def test_pack_autotuned(torch_cuda, ctx, tmp_path, monkeypatch):
     cfg = plan.config()
     say("autotuned pack", cfg)
     assert cfg["pack_ints"] in (0, 1024, 2048, 4096)
+    assert cfg["pack_groups"] in (5, gc.PACK_GROUPS_ALL)
     plan.decode_batch(d_s, d_o)
     rc, det = ctx.sync_status()
     assert rc == gc.OK, det
     assert np.array_equal(gc.unpad(gc.to_host(d_o), out_offs, L), np.concatenate(lists))
     plan2 = gc.Plan(ctx, descs, headers, d_s, d_o, autotune=True)      # from the cache
     assert plan2.config()["pack_ints"] == cfg["pack_ints"]
+    assert plan2.config()["pack_groups"] == cfg["pack_groups"]
     assert plan2.config()["class_tiles"] == cfg["class_tiles"]
     plan.close()
     plan2.close()
+
+
+@pytest.mark.parametrize("pack_groups", [1, 5, gc.PACK_GROUPS_ALL])
+@pytest.mark.parametrize("name", ["pfd", "afor", "gsc8iu"])
+def test_pack_groups(torch_cuda, ctx, name, pack_groups):
+    """20,000 lists of 1 to 700 integers in one format (about 8,000 packs):
+    with one pack workgroup per CU every wave decodes several packs in
+    turn, with five fewer, with GC_PACK_GROUPS_ALL one each; all decode
+    exactly, replayed from a graph."""
+    rng = np.random.default_rng(8600 + len(name))
+    _, codec, kw = next(v for v in VARIANTS if v[0] == name)
+    lengths = rng.integers(1, 701, 20000)
+    streams, lists = [], []
+    for i, n in enumerate(lengths):
+        x, delta = values(rng, int(n), "docids" if i % 3 else "spiky")
+        p = O.params(codec, k=4, delta=delta, cg=kw.get("cg", 1), ld=kw.get("ld", O.LD_CU))
+        streams.append(O.encode(x, p))
+        lists.append(x)
+    offs = np.concatenate([[0], np.cumsum([s.size for s in streams])]).astype(np.int64)
+    say("pack groups", name, pack_groups, int(lengths.sum()))
+    cfg = check_plan(torch_cuda, ctx, np.concatenate(streams), offs, lengths.astype(np.int64), lists, 4, True,
+                     1024, reps=2, pack_groups=pack_groups)
+    assert cfg["pack_groups"] == pack_groups
+    assert cfg["packs"] > 4 * 256
