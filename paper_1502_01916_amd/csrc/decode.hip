@@ -1881,7 +1881,8 @@ struct PackSmem {
     static constexpr int NBLK = TUP / 32 + (int)kPackLists;    // Group-PFD blocks
     static constexpr int NBM = PI / 32;                        // exception bitmap words
     u32x4 stage[SW / 4 + 16];     // the streams (+ one row of the widest layout, read past a list's last row)
-    uint32_t rec[TUP];            // tuple records (unit markers while the records are built)
+    uint32_t rec[TUP];            // tuple records (unit markers while the records are built);
+                                  // Group-PFD: the block of each 32 integers (16 bits)
     u32x4 lst[kPackLists];        // list j: tuple base | delta << 31, n, output pointer (low, high word)
     uint16_t so[kPackLists + 1];  // staging chunk of list j (the pack's total from the last list on)
     uint16_t tb[kPackLists + 1];  // tuple base of list j (likewise)
@@ -1893,7 +1894,9 @@ struct PackSmem {
         uint2 info[NU];           // Group-Simple, Group-AFOR: unit {tuple start | bit << 16, record base}
         uint16_t z[TUP];          // unary Group-Scheme: terminator position of each tuple's code
         struct {
-            u32x4 blk[NBLK];      // Group-PFD block: descriptor, first row chunk, exception word, list
+            // Group-PFD block: descriptor, first row chunk, exception word,
+            // list | first tuple << 8
+            u32x4 blk[NBLK];
             uint32_t bmap[NBM], vbit[NBM];
         } p;
     } u;
@@ -2144,23 +2147,17 @@ __device__ __forceinline__ uint32_t pack_recs_pfd(PackSmem<PI, SW> &sm, const ui
         const uint32_t xw = seg_excl_scan(ew, head, c_x);
         rng |= in && ((rows + b) << lk > Dj || 4u + Cj + Dj + xw + ew > Wl[j]);
         if (in) {
+            // no per-tuple records: the unpack finds a tuple's block by its
+            // 32 integers (a list starts at a 32-integer boundary and a
+            // block holds 32k integers, so each 32 belong to one block) and
+            // its bit offset from the block's first tuple
             const uint32_t c0 = d0l[j] + rows * kq;
-            sm.u.p.blk[g] = u32x4{desc, c0, cwl[j] + Cj + Dj + xw, j};
-            // the block's 32 tuple records (those inside the list's tuple
-            // space); at k <= 8 a list's tuple space is a multiple of 4
-            // tuples from a multiple of 4, so four records go at once
             const uint32_t tb = sm.tb[j] + 32u * s;
+            sm.u.p.blk[g] = u32x4{desc, c0, cwl[j] + Cj + Dj + xw, j | (tb << 8)};
             const uint32_t nt = min(32u, sm.tb[j + 1u] - min(sm.tb[j + 1u], tb));
-            if (k <= 8u) {
-                for (uint32_t tt = 0; tt < nt; tt += 4u) {
-                    const uint32_t O = tt * b;
-                    *reinterpret_cast<u32x4 *>(&sm.rec[tb + tt]) =
-                        u32x4{pack_rec_at(j, c0, kq, O, b), pack_rec_at(j, c0, kq, O + b, b),
-                              pack_rec_at(j, c0, kq, O + 2u * b, b), pack_rec_at(j, c0, kq, O + 3u * b, b)};
-                }
-            } else {
-                for (uint32_t tt = 0; tt < nt; tt++) sm.rec[tb + tt] = pack_rec_at(j, c0, kq, tt * b, b);
-            }
+            const uint32_t g0i = (tb << lk) >> 5, g1i = ((tb + nt) << lk) >> 5;
+            uint16_t *gb = reinterpret_cast<uint16_t *>(sm.rec);
+            for (uint32_t x = g0i; x < g1i; x++) gb[x] = (uint16_t)g;
         }
     }
     if (wave_any(bad)) return kErrPfdDesc;
@@ -2174,7 +2171,7 @@ __device__ __forceinline__ uint32_t pack_recs_pfd(PackSmem<PI, SW> &sm, const ui
     bool chain_bad = false;
     for (uint32_t g = lane; g < U; g += 64u) {
         const u32x4 bk = sm.u.p.blk[g];
-        const uint32_t desc = bk.x, c0 = bk.y, xb = bk.z, j = bk.w;
+        const uint32_t desc = bk.x, c0 = bk.y, xb = bk.z, j = bk.w & 0xFFu;
         const uint32_t s = g - sm.ub[j];
         const uint32_t nexc = desc >> 20, b = desc & 63u, M = mask_of(b), wcode = (desc >> 6) & 3u;
         const uint32_t real_t = min(32u, Tl[j] - 32u * s);       // real tuples of the block (> 0)
@@ -2281,7 +2278,16 @@ __device__ __forceinline__ void pack_unpack(PackSmem<PI, SW> &sm, uint32_t lane,
         const uint32_t q = g0 + lane;
         const bool in = q < NQ;
         const uint32_t t = K4 ? q : q >> tsh, cq = K4 ? 0u : q & (kq - 1u);
-        const uint32_t rc = in ? sm.rec[t] : 0u;
+        uint32_t rc;
+        if constexpr (PATCH) {
+            // Group-PFD: the record from the tuple's block
+            const u32x4 bk = sm.u.p.blk[in ? reinterpret_cast<const uint16_t *>(sm.rec)[q >> 3] : 0u];
+            const uint32_t b = bk.x & 63u;
+            const uint32_t O = __umul24(t - (bk.w >> 8), b);
+            rc = in ? pack_rec_at(bk.w & 0xFFu, bk.y, kq, O, b) : 0u;
+        } else {
+            rc = in ? sm.rec[t] : 0u;
+        }
         const u32x4 L = sm.lst[(rc >> 23) & (kPackLists - 1u)];
         const uint32_t tb = L.x & 0x7FFFFFFFu;
         const uint32_t li = K4 ? (t - tb) << 2 : ((t - tb) << lk) + 4u * cq;   // the quad's first integer in its list
