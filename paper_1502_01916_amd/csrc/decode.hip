@@ -306,7 +306,9 @@ __global__ __launch_bounds__(kThreads) void gc_locate_reduce(LocateArgs a) {
     const uint32_t item = blockIdx.x * (uint32_t)kWaves + wave;
     ListDesc L;
     uint32_t chunk, list;
-    if (locate_item(a, item, L, chunk, list)) {
+    // a list of one chunk needs no aggregate (its prefix is zero); the emit
+    // kernel checks its words
+    if (locate_item(a, item, L, chunk, list) && L.nchunks > 1u) {
         LocThread<W> t;
         locate_thread<W>(L, chunk, lane, t);
         const uint32_t tt = wave_sum(t.vt), te = wave_sum(t.ve), td = wave_sum(t.vd);
@@ -328,11 +330,13 @@ __global__ __launch_bounds__(kThreads) void gc_locate_reduce(LocateArgs a) {
     }
 }
 
-// Exclusive prefix of the chunk aggregates of one list per wave.
+// Exclusive prefix of the chunk aggregates of one list per wave (lists of
+// more than one chunk; a batch lists only those).
 __global__ __launch_bounds__(kThreads) void gc_locate_scan(LocateArgs a) {
     const uint32_t item = blockIdx.x * (uint32_t)kWaves + (threadIdx.x >> 6);
     if (item >= a.total_scan) return;
     const ListDesc L = a.lists ? a.lists[a.scan_list[item]] : a.single;
+    if (L.nchunks <= 1u) return;
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t ct = 0, ce = 0;
     uint64_t cd = 0;
@@ -374,7 +378,16 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
         const uint32_t xt = wave_incl_scan(t.vt) - t.vt;
         const uint32_t xe = wave_incl_scan(t.ve) - t.ve;
         const uint32_t xd = wave_incl_scan(t.vd) - t.vd;
-        const LocVal pre = a.pre[L.chunk_base + chunk];
+        // a list of one chunk: no aggregate was taken, its prefix is zero
+        // and its words are checked here
+        LocVal pre;
+        if (L.nchunks > 1u) {
+            pre = a.pre[L.chunk_base + chunk];
+        } else {
+            pre.tup = pre.exc = 0u;
+            pre.data = 0ull;
+            if (t.bad) latch(a.status, kErrLocate);
+        }
         const uint32_t TT = t.TT, ntiles = L.ntiles, D = t.D;
         const HeaderFields &h = t.h;
         uint32_t base_t = pre.tup + xt;
@@ -2549,7 +2562,8 @@ int launch_locate(const LocateArgs &a, int chunk_words, hipStream_t s) {
     const dim3 grid((a.total_items + kWaves - 1) / kWaves);
     if (chunk_words == kChunkWords) hipLaunchKernelGGL(gc_locate_reduce<kChunkWords / 64>, grid, dim3(kThreads), 0, s, a);
     else hipLaunchKernelGGL(gc_locate_reduce<kChunkWordsSmall / 64>, grid, dim3(kThreads), 0, s, a);
-    hipLaunchKernelGGL(gc_locate_scan, dim3((a.total_scan + kWaves - 1) / kWaves), dim3(kThreads), 0, s, a);
+    if (a.total_scan)   // lists of one chunk need no scan
+        hipLaunchKernelGGL(gc_locate_scan, dim3((a.total_scan + kWaves - 1) / kWaves), dim3(kThreads), 0, s, a);
     if (chunk_words == kChunkWords) hipLaunchKernelGGL(gc_locate_emit<kChunkWords / 64>, grid, dim3(kThreads), 0, s, a);
     else hipLaunchKernelGGL(gc_locate_emit<kChunkWordsSmall / 64>, grid, dim3(kThreads), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -508,7 +508,7 @@ void build_tables(gc_plan *p) {
             if (p->cls[i] != c || !L.nchunks || p->packed[i]) continue;
             L.chunk_base = cb;
             for (uint32_t k = 0; k < L.nchunks; k++) p->item_a.push_back((uint32_t)i);
-            p->item_s.push_back((uint32_t)i);
+            if (L.nchunks > 1) p->item_s.push_back((uint32_t)i);   // one chunk: no scan
             cb += L.nchunks;
         }
         r.loc_count = cb - r.loc_lo;
