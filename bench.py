@@ -217,26 +217,33 @@ def build_cfg5(gc, synth, name):
     return Workload(name, desc, s, offs.astype(np.int64), lengths, cls, docs)
 
 
-def read_traffic(workload, units, kernel):
+def read_traffic(workload, units, kernel, alg_bytes):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary of `workload`, if it was taken on the current decode kernel
-    source, this workload and this kernel."""
+    summary of `workload`: one block per plan profiled (blocks begin with a
+    `kernel:` line), the one taken on the current decode kernel source, this
+    workload, this kernel and a plan that gives the kernel the same
+    algorithmic bytes per launch."""
     path = traffic_file(workload)
     if not os.path.exists(path):
         return None
-    kv = {}
+    blocks, kv = [], None
     with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
-                kv[k.strip()] = v.strip()
-    if (kv.get("decode_sources_sha256") != decode_sources_sha256() or kv.get("workload_units") != str(units)
-            or kv.get("kernel") != kernel):
-        return None
-    try:
-        return float(kv["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+                if k.strip() == "kernel":
+                    kv = {}
+                    blocks.append(kv)
+                if kv is not None:
+                    kv[k.strip()] = v.strip()
+    for kv in blocks:
+        if (kv.get("decode_sources_sha256") == decode_sources_sha256() and kv.get("workload_units") == str(units)
+                and kv.get("kernel") == kernel and kv.get("algorithmic_bytes_per_launch") == str(int(alg_bytes))):
+            try:
+                return float(kv["hbm_bytes_per_launch"])
+            except (KeyError, ValueError):
+                return None
+    return None
 
 
 def cpu_model():
@@ -344,6 +351,11 @@ class Measured:
     pass
 
 
+def pack_option(gc, v):
+    """--pack-ints: 'auto' (0, autotuned), 'off' or a threshold."""
+    return 0 if v == "auto" else gc.PACK_OFF if v == "off" else int(v)
+
+
 def measure(gc, torch, ctx, wl, args, keep_device=False):
     """Times one workload: an autotuned plan replayed from a hipGraph (the
     value), then a plan with the same tiles and HIP events between the phases
@@ -356,7 +368,8 @@ def measure(gc, torch, ctx, wl, args, keep_device=False):
     plan = gc.Plan(ctx, descs, headers, d_s, d_o, tile_ints=args.tile, locate_stream=args.locate_stream,
                    pfd_tile_ints=args.pfd_tile or (4096 if args.tile else 0),
                    autotune=args.tile == 0, use_graph=True, carry_pass=args.carry_pass,
-                   graph_serial=args.graph_serial)
+                   graph_serial=args.graph_serial,
+                   pack_ints=pack_option(gc, args.pack_ints))
     cfg = plan.config()
     log("%s plan: %s (%.1fs)" % (wl.name, cfg, time.time() - t))
     tplan = gc.Plan(ctx, descs, headers, d_s, d_o, class_tiles=cfg["class_tiles"],
@@ -631,6 +644,8 @@ def main():
                     help="graph: one chain of kernels instead of branches for the pack kernel and each class")
     ap.add_argument("--no-extra", action="store_true", help="skip every leg")
     ap.add_argument("--tile", type=int, default=0, help="force the wave-tile size (0 = autotune)")
+    ap.add_argument("--pack-ints", default="auto",
+                    help="packed-list threshold: auto (autotuned), off, or 1 .. 4096 integers")
     ap.add_argument("--pfd-tile", type=int, default=0, help="force the Group-PFD tile size (with --tile)")
     ap.add_argument("--locate-stream", action="store_true",
                     help="run the locate kernels on a second stream, ahead of the other kernels")
@@ -662,7 +677,7 @@ def main():
         wl = build_cfg5(gc, synth, args.workload)
     ctx = gc.Context(0)
     m = measure(gc, torch, ctx, wl, args, keep_device=True)
-    traffic = read_traffic(wl.name, len(m.descs), m.kname)
+    traffic = read_traffic(wl.name, len(m.descs), m.kname, m.cls_bytes)
 
     extra = {}
     if legs:

@@ -1033,7 +1033,7 @@ gc_status autotune(gc_plan *p, const uint32_t *d_streams, uint32_t *d_out) {
                 best_ms[i] = std::min(best_ms[i], ms);
             }
         }
-        const size_t bi = cand.size() > 1 ? std::min_element(best_ms.begin(), best_ms.end()) - best_ms.begin() : 0;
+        const size_t bi = std::min_element(best_ms.begin(), best_ms.end()) - best_ms.begin();
         best_pm = cand[bi].first;
         best_pg = cand[bi].second;
         plan_free_graphs(p);

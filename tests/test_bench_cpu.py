@@ -1,7 +1,8 @@
 """Host-side checks of bench.py (no GPU): it refuses more than one GPU with a
 message, names the decode kernels as the profiler does, and takes HBM
 traffic only from a counter summary of the current decode sources, the same
-workload and the same kernel."""
+workload, the same kernel and a plan that gives that kernel the same
+algorithmic bytes."""
 import os
 import subprocess
 import sys
@@ -40,18 +41,20 @@ def test_traffic_only_for_the_profiled_sources_workload_and_kernel():
     for wl in bench.WORKLOADS:
         path = bench.traffic_file(wl)
         if not os.path.exists(path):
-            assert bench.read_traffic(wl, 100000, "gc_wave_kernel<2048, 1, 2>") is None
+            assert bench.read_traffic(wl, 100000, "gc_wave_kernel<2048, 1, 2>", 1) is None
             continue
         found += 1
         kv = summary(path)
-        units, kernel = int(kv["workload_units"]), kv["kernel"]
-        got = bench.read_traffic(wl, units, kernel)
+        units, kernel, alg = int(kv["workload_units"]), kv["kernel"], int(kv["algorithmic_bytes_per_launch"])
+        got = bench.read_traffic(wl, units, kernel, alg)
         if kv["decode_sources_sha256"] == bench.decode_sources_sha256():
             assert got == float(kv["hbm_bytes_per_launch"])
         else:
             assert got is None          # stale summary: traffic is reported as null
-        assert bench.read_traffic(wl, units + 1, kernel) is None
-        assert bench.read_traffic(wl, units, "gc_wave_kernel<9999, 9, 9>") is None
+        assert bench.read_traffic(wl, units + 1, kernel, alg) is None
+        assert bench.read_traffic(wl, units, "gc_wave_kernel<9999, 9, 9>", alg) is None
+        # another plan (a different packed-list threshold) gives the kernel other bytes
+        assert bench.read_traffic(wl, units, kernel, alg + 4) is None
     assert found >= 1
 
 
