@@ -136,6 +136,21 @@ __device__ __forceinline__ uint32_t pfd_exc_words(uint32_t desc, int k, int bitm
 // ===========================================================================
 // Locate kernels: reduce -> scan -> emit.
 
+// Position of the k-th (from 0) set bit of x (k < popcount(x)).
+__device__ __forceinline__ uint32_t select_bit(uint32_t x, uint32_t k) {
+    uint32_t pos = 0;
+#pragma unroll
+    for (uint32_t h = 16u; h; h >>= 1) {
+        const uint32_t c = (uint32_t)__builtin_popcount(x & ((1u << h) - 1u));
+        const bool up = k >= c;
+        k = up ? k - c : k;
+        x = up ? x >> h : x;
+        pos = up ? pos + h : pos;
+    }
+    return pos;
+}
+
+
 // Tuples of the first ns selectors of a Group-Simple control word, without
 // a branch; *bad is set when one of them is not a selector (10..15, that is
 // bit 3 and bit 2 or 1 set).
@@ -185,6 +200,7 @@ struct LocThread {
     bool ok, bad;
     uint32_t k, T, TT, D, nwords, wbase;
     uint32_t word[W];
+    uint32_t wt[W], wb[W];   // per word: tuples, and component data bits (Group-AFOR, incomplete unary)
     uint32_t vt, ve, vd;
 };
 
@@ -230,12 +246,14 @@ __device__ __forceinline__ void locate_thread(const ListDesc &L, uint32_t chunk,
     }
 #pragma unroll
     for (int q = 0; q < W; q++) {
+        t.wt[q] = t.wb[q] = 0u;
         const uint32_t w = t.wbase + (uint32_t)q;
         if (w >= t.nwords) continue;
         const uint32_t wd = t.word[q];
         switch (h.codec) {
         case 0:   // w < nwords: at least one of the word's selectors exists
-            t.vt += sim_word_tuples(wd, min(8u, (D >> h.lk) - 8u * w), t.bad);
+            t.wt[q] = sim_word_tuples(wd, min(8u, (D >> h.lk) - 8u * w), t.bad);
+            t.vt += t.wt[q];
             break;
         case 1:
             if (h.ld == GC_LD_BINARY) {
@@ -248,15 +266,18 @@ __device__ __forceinline__ void locate_thread(const ListDesc &L, uint32_t chunk,
                     t.vd += (uint32_t)h.cg * (((wd >> bit) & mask_of(u.fb)) + 1u);
                 }
             } else {
-                t.vt += (uint32_t)__builtin_popcount(~wd);
-                if (h.ld == GC_LD_IU) t.vd += (uint32_t)h.cg * iu_useful(wd);
+                t.wt[q] = (uint32_t)__builtin_popcount(~wd);
+                t.vt += t.wt[q];
+                if (h.ld == GC_LD_IU) {
+                    t.wb[q] = (uint32_t)h.cg * iu_useful(wd);
+                    t.vd += t.wb[q];
+                }
             }
             break;
         case 2: {
-            uint32_t wt, wbits;
-            afor_word(wd, wt, wbits, t.bad);
-            t.vt += wt;
-            t.vd += wbits;
+            afor_word(wd, t.wt[q], t.wb[q], t.bad);
+            t.vt += t.wt[q];
+            t.vd += t.wb[q];
             break;
         }
         default: {
@@ -425,8 +446,7 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
                 case 0: {
                     // the word's selectors are walked only when a tile starts among them
                     const uint32_t ns = min(8u, (D >> h.lk) - 8u * w);
-                    bool unused = false;
-                    const uint32_t wt = sim_word_tuples(wd, ns, unused);
+                    const uint32_t wt = t.wt[q];
                     if (!(m < ntiles && B < base_t + wt)) {
                         base_t += wt;
                         break;
@@ -461,8 +481,9 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
                         // terminators (0 bits) of ranks base_t .. base_t + cnt - 1 end
                         // in this word
                         const uint32_t z = ~wd;
-                        const uint32_t cnt = (uint32_t)__builtin_popcount(z);
+                        const uint32_t cnt = t.wt[q];
                         if (m < ntiles && B - 1u < base_t + cnt) {
+                            // (a tile start is rarely more than a few terminators into a word)
                             uint32_t zz = z;
                             for (uint32_t i = 0; i < B - 1u - base_t; i++) zz &= zz - 1u;
                             const uint32_t bit = (uint32_t)__builtin_ctz(zz);
@@ -480,14 +501,12 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
                             B += TT;
                         }
                         base_t += cnt;
-                        if (h.ld == GC_LD_IU) base_d += (uint32_t)h.cg * iu_useful(wd);
+                        base_d += t.wb[q];
                     }
                     break;
                 case 2: {
                     // the word's frames are walked only when a tile starts among them
-                    uint32_t wt, wbits;
-                    bool unused = false;
-                    afor_word(wd, wt, wbits, unused);
+                    const uint32_t wt = t.wt[q], wbits = t.wb[q];
                     if (!(m < ntiles && B < base_t + wt)) {
                         base_t += wt;
                         base_d += wbits;
@@ -815,20 +834,6 @@ __device__ uint32_t wprologue_sim(const TileCtx &c, WaveSmem<TW, kClsSim> &sm, u
 // the bits after the previous terminator up to its own (incomplete units:
 // not across a byte, so it starts at the byte boundary at the latest), and
 // its data follow the data of the codes before it.
-
-// Position of the k-th (from 0) set bit of x (k < popcount(x)).
-__device__ __forceinline__ uint32_t select_bit(uint32_t x, uint32_t k) {
-    uint32_t pos = 0;
-#pragma unroll
-    for (uint32_t h = 16u; h; h >>= 1) {
-        const uint32_t c = (uint32_t)__builtin_popcount(x & ((1u << h) - 1u));
-        const bool up = k >= c;
-        k = up ? k - c : k;
-        x = up ? x >> h : x;
-        pos = up ? pos + h : pos;
-    }
-    return pos;
-}
 
 template <int TW, int CE>
 __device__ uint32_t wprologue_gscu(const TileCtx &c, WaveSmem<TW, kClsGscU> &sm, uint32_t lane, uint32_t &dbase,
@@ -1865,11 +1870,13 @@ __global__ __launch_bounds__(kThreads, (MODE == kModeSum && CLS == kClsPfd) ? 7 
 // fields, frame bytes, block descriptors) are then parsed together, lane by
 // lane, with scans that restart at each list's first unit; they give one
 // record per tuple of the pack: list, data row (a 16-byte chunk of the
-// staging buffer), bit shift and width.  The unpack walks the pack's quads
-// 64 at a time: each lane makes four integers from its tuple's record and
-// two staged rows, Group-PFD patches them from a bitmap of the pack's
-// exception positions, and docID lists are prefix-summed by a wave scan that
-// restarts at each list's first quad.
+// staging buffer), bit shift and width (Group-PFD: computed in the unpack
+// from the tuple's block, which a table of the block of every 32 integers
+// names).  The unpack walks the pack's quads 64 at a time: each lane makes
+// four integers from its tuple's record and two staged rows, Group-PFD
+// patches them from a bitmap of the pack's exception positions, and docID
+// lists are prefix-summed by a wave scan that restarts at each list's first
+// quad.
 
 constexpr uint32_t kPackLists = 32;   // lists per pack (lanes 0 .. 31 hold their descriptors)
 
