@@ -692,18 +692,23 @@ struct WaveSmem {
     uint32_t bmap[NBM], xcnt[NBM], vbit[NBM];
 };
 
-// Record of tuple t (bit offset << 6 | width): from the record array, or,
-// for a Group-PFD tile, from the record word of its 32-tuple block.
+// Record of tuple t (bit offset O from the tile's first row, width b): from
+// the record arrays, or, for a Group-PFD tile, from the record word (row
+// offset << 6 | width) of its 32-tuple block.
 struct RecArr {
     const uint16_t *rel;
     const uint8_t *bw;
-    __device__ __forceinline__ uint32_t operator()(uint32_t t) const { return ((uint32_t)rel[t] << 6) | bw[t]; }
+    __device__ __forceinline__ void operator()(uint32_t t, uint32_t &O, uint32_t &b) const {
+        O = rel[t];
+        b = bw[t];
+    }
 };
 struct RecBlk {
     const uint32_t *brec;
-    __device__ __forceinline__ uint32_t operator()(uint32_t t) const {
-        const uint32_t w = brec[t >> 5], b = w & 63u;
-        return (((w >> 6) << 11) + (((t & 31u) * b) << 6)) | b;
+    __device__ __forceinline__ void operator()(uint32_t t, uint32_t &O, uint32_t &b) const {
+        const uint32_t w = brec[t >> 5];
+        b = w & 63u;
+        O = ((w >> 6) << 5) + __umul24(t & 31u, b);
     }
 };
 
@@ -1324,8 +1329,8 @@ __device__ __forceinline__ void pfd_patch(u32x4 &v, uint32_t q, const PatchSrc &
 // Four consecutive integers of quad q from the tuple records and data rows
 // (in global memory, or staged in LDS).
 template <typename RowPtr>
-__device__ __forceinline__ u32x4 extract_quad(uint32_t rc, uint32_t q, uint32_t kq, RowPtr rows, uint32_t nrow) {
-    const uint32_t O = rc >> 6, bw = rc & 63u;
+__device__ __forceinline__ u32x4 extract_quad(uint32_t O, uint32_t bw, uint32_t q, uint32_t kq, RowPtr rows,
+                                              uint32_t nrow) {
     u32x4 v = {0u, 0u, 0u, 0u};
     if (bw && nrow) {
         const uint32_t cq = q & (kq - 1u);
@@ -1393,7 +1398,9 @@ __device__ __forceinline__ uint32_t tile_quads(Rec rec, uint32_t tsh, uint32_t k
         const uint32_t q = (uint32_t)r * 64u + lane;
         u32x4 v = {0u, 0u, 0u, 0u};
         if (4u * q < nint) {
-            v = extract_quad(rec(q >> tsh), q, kq, rows, nrow);
+            uint32_t O, bw;
+            rec(q >> tsh, O, bw);
+            v = extract_quad(O, bw, q, kq, rows, nrow);
             if constexpr (PATCH) pfd_patch(v, q, ps);
         }
         if constexpr (SUM) {
@@ -1419,7 +1426,7 @@ __device__ __forceinline__ uint32_t tile_quads(Rec rec, uint32_t tsh, uint32_t k
 // the carry of the earlier rounds).  FULL: a whole tile with a 16-byte
 // aligned output, so no quad needs a bounds check.  Rows are read without a
 // clamp: the row after the last holds padding, and its bits are masked off.
-template <int R, bool SUM, bool FULL, bool DELTA, bool PATCH, typename Rec>
+template <int R, bool SUM, bool FULL, bool DELTA, bool PATCH, bool K4, typename Rec>
 __device__ __forceinline__ uint32_t quads_lds(Rec rec, const u32x4 *data, uint32_t tsh, uint32_t kq,
                                               uint32_t nint, uint32_t lane, uint32_t carry, uint32_t *out,
                                               bool vec, const PatchSrc &ps) {
@@ -1431,11 +1438,16 @@ __device__ __forceinline__ uint32_t quads_lds(Rec rec, const u32x4 *data, uint32
     for (int r = 0; r < R; r++) {
         if (r >= nr) continue;
         const uint32_t q = (uint32_t)r * 64u + lane;
-        uint32_t rc = rec(q >> tsh);
-        if constexpr (!FULL) rc = 4u * q < nint ? rc : 0u;
-        const uint32_t O = rc >> 6, bw = rc & 63u, sh = O & 31u;
-        const uint32_t idx = (O >> 5) * kq + (q & (kq - 1u));
-        const u32x4 lo = data[idx], hi = data[idx + kq];
+        uint32_t O, bw;
+        rec(K4 ? q : q >> tsh, O, bw);
+        if constexpr (!FULL) {
+            const bool in = 4u * q < nint;
+            O = in ? O : 0u;
+            bw = in ? bw : 0u;
+        }
+        const uint32_t sh = O & 31u;
+        const uint32_t idx = K4 ? O >> 5 : (O >> 5) * kq + (q & (kq - 1u));
+        const u32x4 lo = data[idx], hi = data[idx + (K4 ? 1u : kq)];
         const uint32_t M = (uint32_t)(0xFFFFFFFFull >> (32u - bw));
         u32x4 v;
         v.x = funnel(hi.x, lo.x, sh) & M;
@@ -1629,8 +1641,9 @@ __device__ __forceinline__ void tile_setup(const DecodeArgs &a, const ListDesc &
     // the tile's data rows end with its last record (offsets grow with the tuple)
     uint32_t span = 0;
     if (t.nint) {
-        const uint32_t lr = tile_recs(sm)(c.ntup - 1u);
-        span = min(t.nrow, ((lr >> 6) + (lr & 63u) + 31u) >> 5);
+        uint32_t lo_bit, lw;
+        tile_recs(sm)(c.ntup - 1u, lo_bit, lw);
+        span = min(t.nrow, (lo_bit + lw + 31u) >> 5);
     }
     t.staged = (span + 1u) * t.kq <= (uint32_t)SM::NB;
     bool wrote = false;
@@ -1693,10 +1706,15 @@ __device__ __forceinline__ uint32_t tile_total(const TileRun<TW, CLS> &t, WaveSm
     constexpr bool PATCH = CLS == kClsPfd;
     uint32_t s;
     if (t.staged) {
-        s = (t.nint == (uint32_t)TW && t.vec)
-                ? quads_lds<R, true, true, true, PATCH>(tile_recs(sm), sm.data, t.tsh, t.kq, t.nint, lane, 0u, t.out, t.vec, t.ps)
-                : quads_lds<R, true, false, true, PATCH>(tile_recs(sm), sm.data, t.tsh, t.kq, t.nint, lane, 0u, t.out, t.vec,
-                                                         t.ps);
+        const bool full = t.nint == (uint32_t)TW && t.vec;
+        const auto rc = tile_recs(sm);
+        const u32x4 *d = sm.data;
+        if (t.kq == 1u)   // 4-way layout: a quad per tuple
+            s = full ? quads_lds<R, true, true, true, PATCH, true>(rc, d, t.tsh, 1u, t.nint, lane, 0u, t.out, t.vec, t.ps)
+                     : quads_lds<R, true, false, true, PATCH, true>(rc, d, t.tsh, 1u, t.nint, lane, 0u, t.out, t.vec, t.ps);
+        else
+            s = full ? quads_lds<R, true, true, true, PATCH, false>(rc, d, t.tsh, t.kq, t.nint, lane, 0u, t.out, t.vec, t.ps)
+                     : quads_lds<R, true, false, true, PATCH, false>(rc, d, t.tsh, t.kq, t.nint, lane, 0u, t.out, t.vec, t.ps);
     } else {
         s = tile_quads<R, true, PATCH>(tile_recs(sm), t.tsh, t.kq, t.rows, t.nrow, t.nint, lane, false, 0u, t.out, t.vec,
                                        t.ps);
@@ -1820,12 +1838,24 @@ __device__ void wave_tile(const DecodeArgs &a, const ListDesc &L, uint32_t m, ui
     if (t.staged) {
         const u32x4 *d = sm.data;
         const bool full = nint == (uint32_t)TW && t.vec;
+        const auto rc = tile_recs(sm);
+        const uint32_t kq = t.kq, tsh = t.tsh;
         if (t.c.h.delta) {
-            if (full) quads_lds<R, false, true, true, PATCH>(tile_recs(sm), d, t.tsh, t.kq, nint, lane, carry0, t.out, t.vec, t.ps);
-            else quads_lds<R, false, false, true, PATCH>(tile_recs(sm), d, t.tsh, t.kq, nint, lane, carry0, t.out, t.vec, t.ps);
+            if (kq == 1u) {   // 4-way layout: a quad per tuple
+                if (full) quads_lds<R, false, true, true, PATCH, true>(rc, d, tsh, 1u, nint, lane, carry0, t.out, t.vec, t.ps);
+                else quads_lds<R, false, false, true, PATCH, true>(rc, d, tsh, 1u, nint, lane, carry0, t.out, t.vec, t.ps);
+            } else {
+                if (full) quads_lds<R, false, true, true, PATCH, false>(rc, d, tsh, kq, nint, lane, carry0, t.out, t.vec, t.ps);
+                else quads_lds<R, false, false, true, PATCH, false>(rc, d, tsh, kq, nint, lane, carry0, t.out, t.vec, t.ps);
+            }
         } else {
-            if (full) quads_lds<R, false, true, false, PATCH>(tile_recs(sm), d, t.tsh, t.kq, nint, lane, 0u, t.out, t.vec, t.ps);
-            else quads_lds<R, false, false, false, PATCH>(tile_recs(sm), d, t.tsh, t.kq, nint, lane, 0u, t.out, t.vec, t.ps);
+            if (kq == 1u) {
+                if (full) quads_lds<R, false, true, false, PATCH, true>(rc, d, tsh, 1u, nint, lane, 0u, t.out, t.vec, t.ps);
+                else quads_lds<R, false, false, false, PATCH, true>(rc, d, tsh, 1u, nint, lane, 0u, t.out, t.vec, t.ps);
+            } else {
+                if (full) quads_lds<R, false, true, false, PATCH, false>(rc, d, tsh, kq, nint, lane, 0u, t.out, t.vec, t.ps);
+                else quads_lds<R, false, false, false, PATCH, false>(rc, d, tsh, kq, nint, lane, 0u, t.out, t.vec, t.ps);
+            }
         }
     } else {
         (void)tile_quads<R, false, PATCH>(tile_recs(sm), t.tsh, t.kq, t.rows, t.nrow, nint, lane, t.c.h.delta, carry0, t.out,
