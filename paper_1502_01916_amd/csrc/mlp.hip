@@ -2,8 +2,9 @@
 // 40 block features -> 64 -> 64 -> 16 class logits with ReLU, softmax
 // cross-entropy plus an expected size-excess term, trained with Adam.
 //
-// Matrix products run on the matrix cores (v_mfma_f32_16x16x16_bf16): bf16
-// operands, fp32 accumulation.  Each workgroup of four waves takes 64 samples;
+// Matrix products run on the matrix cores (v_mfma_f32_16x16x32_bf16, and
+// v_mfma_f32_16x16x16_bf16 for a remaining 16 of K): bf16 operands, fp32
+// accumulation.  Each workgroup of four waves takes 64 samples;
 // wave w owns rows 16w..16w+15 in the forward pass and in the backward
 // products through the layers, and the weight gradients are contractions
 // over all 64 rows, one output tile row per wave.  Activations and
@@ -20,6 +21,8 @@
 namespace gcmlp {
 
 typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
@@ -34,6 +37,10 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
 __device__ __forceinline__ f32x4 mfma(s16x4 a, s16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f32x4 mfma32(s16x8 a, s16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                   0, 0);
+}
 
 // Fragments of a 16x16x16 product, lane l = 16q + i:
 //   A (16 rows x 16 k): row r0 + i, k = k0 + 4q + j (j = 0..3)
@@ -43,14 +50,19 @@ __device__ __forceinline__ f32x4 mfma(s16x4 a, s16x4 b, f32x4 c) {
 __device__ __forceinline__ s16x4 frag_kc(const uint16_t *M, int ld, int x0, int k0, int lane) {
     return *reinterpret_cast<const s16x4 *>(M + (x0 + (lane & 15)) * ld + k0 + 4 * (lane >> 4));
 }
-// M[k][x] with x contiguous: four 2-byte loads.
-__device__ __forceinline__ s16x4 frag_ks(const uint16_t *M, int ld, int x0, int k0, int lane) {
-    const uint16_t *p = M + (k0 + 4 * (lane >> 4)) * ld + x0 + (lane & 15);
-    s16x4 r;
-    r.x = (short)p[0];
-    r.y = (short)p[ld];
-    r.z = (short)p[2 * ld];
-    r.w = (short)p[3 * ld];
+// Fragments of a 16x16x32 product, lane l = 16q + i: the same with
+// k = k0 + 8q + j (j = 0..7).  M[x][k] with k contiguous: one 16-byte load
+// (every row stride and k0 here is a multiple of 8 elements).
+__device__ __forceinline__ s16x8 frag8_kc(const uint16_t *M, int ld, int x0, int k0, int lane) {
+    return *reinterpret_cast<const s16x8 *>(M + (x0 + (lane & 15)) * ld + k0 + 8 * (lane >> 4));
+}
+
+// M[k][x] with x contiguous: eight 2-byte loads.
+__device__ __forceinline__ s16x8 frag8_ks(const uint16_t *M, int ld, int x0, int k0, int lane) {
+    const uint16_t *p = M + (k0 + 8 * (lane >> 4)) * ld + x0 + (lane & 15);
+    s16x8 r;
+#pragma unroll
+    for (int j = 0; j < 8; j++) r[j] = (short)p[j * ld];
     return r;
 }
 
@@ -94,8 +106,10 @@ __device__ __forceinline__ void dense_relu(const uint16_t *in, int ldin, const u
     for (int nt = 0; nt < kHid / 16; nt++) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < KT; kt++)
-            acc = mfma(frag_kc(in, ldin, r0, 16 * kt, lane), frag_kc(wt, KT * 16, 16 * nt, 16 * kt, lane), acc);
+        for (int kt = 0; kt + 1 < KT; kt += 2)
+            acc = mfma32(frag8_kc(in, ldin, r0, 16 * kt, lane), frag8_kc(wt, KT * 16, 16 * nt, 16 * kt, lane), acc);
+        if constexpr (KT % 2)
+            acc = mfma(frag_kc(in, ldin, r0, 16 * (KT - 1), lane), frag_kc(wt, KT * 16, 16 * nt, 16 * (KT - 1), lane), acc);
         const int col = 16 * nt + i;
         const float b = bias[col];
 #pragma unroll
@@ -154,7 +168,8 @@ __global__ __launch_bounds__(kThreads) void gc_mlp_kernel(Batch b, const float *
     __syncthreads();
     f32x4 z3 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kt = 0; kt < 4; kt++) z3 = mfma(frag_kc(sm.a2, kHid, r0, 16 * kt, lane), frag_kc(w.w3t, kHid, 0, 16 * kt, lane), z3);
+    for (int kt = 0; kt < 4; kt += 2)
+        z3 = mfma32(frag8_kc(sm.a2, kHid, r0, 16 * kt, lane), frag8_kc(w.w3t, kHid, 0, 16 * kt, lane), z3);
     const float b3 = theta[kOffB3 + i];
 
     if (!TRAIN) {
@@ -244,8 +259,8 @@ __global__ __launch_bounds__(kThreads) void gc_mlp_kernel(Batch b, const float *
     for (int nt = 0; nt < 4; nt++) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < 4; kt++)
-            acc = mfma(frag_kc(sm.d2, kHid, r0, 16 * kt, lane), frag_kc(w.w2, kHid, 16 * nt, 16 * kt, lane), acc);
+        for (int kt = 0; kt < 4; kt += 2)
+            acc = mfma32(frag8_kc(sm.d2, kHid, r0, 16 * kt, lane), frag8_kc(w.w2, kHid, 16 * nt, 16 * kt, lane), acc);
         const int col = 16 * nt + i;
         float cs = 0.f;
 #pragma unroll
@@ -265,8 +280,8 @@ __global__ __launch_bounds__(kThreads) void gc_mlp_kernel(Batch b, const float *
     {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < 4; kt++)
-            acc = mfma(frag_ks(sm.a2, kHid, r0, 16 * kt, lane), frag_ks(sm.g3, kOut, 0, 16 * kt, lane), acc);
+        for (int kt = 0; kt < 4; kt += 2)
+            acc = mfma32(frag8_ks(sm.a2, kHid, r0, 16 * kt, lane), frag8_ks(sm.g3, kOut, 0, 16 * kt, lane), acc);
 #pragma unroll
         for (int e = 0; e < 4; e++) part[kOffW3 + (r0 + 4 * q + e) * kOut + i] = acc[e];
     }
@@ -275,8 +290,8 @@ __global__ __launch_bounds__(kThreads) void gc_mlp_kernel(Batch b, const float *
     for (int ot = 0; ot < 4; ot++) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < 4; kt++)
-            acc = mfma(frag_ks(sm.a1, kHid, r0, 16 * kt, lane), frag_ks(sm.d2, kHid, 16 * ot, 16 * kt, lane), acc);
+        for (int kt = 0; kt < 4; kt += 2)
+            acc = mfma32(frag8_ks(sm.a1, kHid, r0, 16 * kt, lane), frag8_ks(sm.d2, kHid, 16 * ot, 16 * kt, lane), acc);
 #pragma unroll
         for (int e = 0; e < 4; e++) part[kOffW2 + (r0 + 4 * q + e) * kHid + 16 * ot + i] = acc[e];
     }
@@ -285,8 +300,8 @@ __global__ __launch_bounds__(kThreads) void gc_mlp_kernel(Batch b, const float *
     for (int it = 0; it < 3; it++) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < 4; kt++)
-            acc = mfma(frag_ks(sm.a0, kInPad, 16 * it, 16 * kt, lane), frag_ks(sm.d1, kHid, r0, 16 * kt, lane), acc);
+        for (int kt = 0; kt < 4; kt += 2)
+            acc = mfma32(frag8_ks(sm.a0, kInPad, 16 * it, 16 * kt, lane), frag8_ks(sm.d1, kHid, r0, 16 * kt, lane), acc);
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             const int in = 16 * it + 4 * q + e;
