@@ -8,11 +8,17 @@
 // work item each, so long queries spread over many waves:
 //   - a wave takes the pivot's docIDs of its segment 64 at a time, one per
 //     lane;
-//   - every other term looks each docID up: first over its block heads, one
-//     every 512 postings (the paper's skip pointers), then inside the block;
-//     a term's search starts where the previous round's last docID landed,
-//     since the pivot's docIDs increase;
-//   - a document found in every list is scored (single precision) and
+//   - the other terms are taken shortest list first (the most selective
+//     first), and a term is skipped once no lane's docID is left;
+//   - each other term finds where its postings of the round's docIDs end,
+//     galloping from where the previous round's ended (the pivot's docIDs
+//     increase) by 64 parallel probes a step, with a first stride set by
+//     the two lists' length ratio; a range of up to 1024 postings is copied
+//     to LDS and each lane searches it there, a longer one is searched in
+//     global memory, first over its block heads, one every 512 postings
+//     (the paper's skip pointers), then inside the block;
+//   - a document found in every list is scored (single precision; its
+//     length and the pivot's TF are read only then) and
 //     offered to the wave's top-k, kept sorted in LDS (higher score first,
 //     then the smaller docID);
 // then one wave per query merges its segments' top-k lists, in segment
@@ -39,6 +45,7 @@ constexpr uint32_t kMaxTerms = 8;
 constexpr uint32_t kMaxTopk = 64;
 constexpr uint32_t kSkip = 512;     // postings between skip pointers
 constexpr uint32_t kSeg = 8192;     // pivot docIDs per work item
+constexpr uint32_t kLdsRange = 1024; // postings of one term's range searched in LDS
 
 // A work item: pivot docIDs [s0, s1) of query q.
 struct QItem {
@@ -87,6 +94,35 @@ __device__ __forceinline__ uint32_t skip_lower_bound(const gu32 *v, uint32_t lo,
     return l;
 }
 
+// For a wave-uniform key, the first index p in [lo, hi) with v[p] >= key
+// (hi if none), or, once some e with p <= e has e - lo <= span, that e:
+// each step probes 64 positions and keeps the gap between the last probe
+// below the key and the first at or above it, so a range of 2^20 postings
+// takes four dependent loads.  The first step's stride is at most
+// `stride0`: a caller that expects the answer near lo gallops from it.
+__device__ __forceinline__ uint32_t probe_lower_bound(const gu32 *v, const uint32_t lo, uint32_t hi, uint32_t key,
+                                                      uint32_t lane, uint32_t stride0, uint32_t span = 0u) {
+    uint32_t l = lo;
+    uint32_t stride = min(stride0, (hi - l + 63u) >> 6);
+    while (hi - l > 64u) {
+        if (hi - lo <= span) return hi;
+        const uint32_t pos = l + lane * stride;
+        // a probe past the range counts as at or above the key
+        const uint64_t b = __ballot(pos >= hi || v[pos] >= key);
+        // lane 0 probes inside the range; with no lane at or above the key
+        // the answer lies after lane 63's probe
+        const uint32_t f = b ? (uint32_t)__builtin_ctzll(b) : 64u;
+        const uint32_t nl = f ? l + (f - 1u) * stride + 1u : l;
+        hi = f < 64u ? min(l + f * stride, hi) : hi;
+        l = nl;
+        stride = (hi - l + 63u) >> 6;
+    }
+    if (hi - lo <= span) return hi;
+    const uint32_t pos = l + lane;
+    const uint64_t b = __ballot(pos < hi && v[pos] >= key);
+    return b ? l + (uint32_t)__builtin_ctzll(b) : hi;
+}
+
 __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -116,15 +152,19 @@ __device__ __forceinline__ uint32_t topk_insert(float *sc, uint32_t *dc, uint32_
 }
 
 // One wave per work item: its pivot docIDs found in every other list,
-// scored, into the item's top-k.
-__global__ __launch_bounds__(kThreads) void k_and_topk(QArgs a) {
+// scored, into the item's top-k.  The kernel waits on chains of dependent
+// loads, so it is held to at least five waves per SIMD (80 VGPRs; with four
+// it runs 20% slower).
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_and_topk(QArgs a) {
     __shared__ float s_sc[kWaves][kMaxTopk];
     __shared__ uint32_t s_dc[kWaves][kMaxTopk];
+    __shared__ uint32_t s_rng[kWaves][kLdsRange];
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
     const uint32_t w = blockIdx.x * (uint32_t)kWaves + wave;
     if (w >= a.nitems) return;
     float *sc = s_sc[wave];
     uint32_t *dc = s_dc[wave];
+    uint32_t *rng = s_rng[wave];
     const QItem it = a.items[w];
     // lane i < tpq: term i of the query
     const int32_t t = lane < a.tpq ? a.qterms[(uint64_t)it.q * a.tpq + lane] : -1;
@@ -133,41 +173,112 @@ __global__ __launch_bounds__(kThreads) void k_and_topk(QArgs a) {
     const uint64_t off = valid ? a.term_off[t] : 0u;
     const float idf = valid ? logf(1.0f + ((float)a.ndocs - (float)len + 0.5f) / ((float)len + 0.5f)) : 0.0f;
     const uint64_t vb = __ballot(valid);
-    uint32_t count = 0;
-    // the pivot: the shortest list (the first of equal lengths)
-    uint32_t mlen = valid ? len : 0xFFFFFFFFu;
-    for (uint32_t m = 1; m < 64u; m <<= 1) mlen = min(mlen, (uint32_t)__shfl_xor((int)mlen, (int)m));
-    const uint32_t piv = vb ? (uint32_t)__builtin_ctzll(__ballot(valid && len == mlen)) : 0u;
+    const uint32_t nterms = (uint32_t)__builtin_popcountll(vb);
+    // the terms by increasing list length (the first of equal lengths
+    // first): the shortest is the pivot, and the next shortest, the most
+    // selective, is searched first
+    uint32_t rank = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kMaxTerms; i++) {
+        const uint32_t li = (uint32_t)__shfl((int)len, (int)i);
+        rank += ((vb >> i) & 1ull) && (li < len || (li == len && i < lane)) ? 1u : 0u;
+    }
+    uint32_t ord[kMaxTerms];
+#pragma unroll
+    for (uint32_t r = 0; r < kMaxTerms; r++) {
+        const uint64_t b = __ballot(valid && rank == r);
+        ord[r] = b ? (uint32_t)__builtin_ctzll(b) : 0u;
+    }
+    const uint32_t piv = ord[0];
+    const uint32_t mlen = (uint32_t)__shfl((int)len, (int)piv);
     const uint64_t offp = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(off >> 32), (int)piv) << 32) |
                           (uint32_t)__shfl((int)(uint32_t)off, (int)piv);
     const float idfp = __shfl(idf, (int)piv);
-    const uint32_t s1 = vb ? min(it.s1, mlen) : 0u;
-    uint32_t from[kMaxTerms];   // where each term's search starts (uniform)
+    const uint32_t s1 = nterms ? min(it.s1, mlen) : 0u;
+    // per other term (by rank): where the next round's range starts, and
+    // the stride of the first probe for its end, twice the postings
+    // expected between two pivot docIDs
+    uint32_t from[kMaxTerms], hint[kMaxTerms];
+    float idfr[kMaxTerms];
 #pragma unroll
-    for (uint32_t j = 0; j < kMaxTerms; j++) from[j] = 0;
+    for (uint32_t r = 0; r < kMaxTerms; r++) {
+        const uint64_t lj = (uint32_t)__shfl((int)len, (int)ord[r]), ml = max(mlen, 1u);
+        idfr[r] = __shfl(idf, (int)ord[r]);
+        from[r] = 0;
+        hint[r] = (uint32_t)max<uint64_t>(1u, (2u * lj + ml - 1u) / ml);
+    }
+    // terms whose `from` may lie before the round's first docID (all at
+    // first; later the terms skipped in a round)
+    uint32_t lag = ~0u;
+    uint32_t count = 0;
     float thr = -1.0f;
     for (uint32_t base = it.s0; base < s1; base += 64u) {
         const uint32_t i = base + lane;
         const bool in = i < s1;
         const uint32_t d = in ? ((const gu32 *)a.docs)[offp + i] : 0xFFFFFFFFu;
-        const uint32_t dl = in && d < a.ndocs ? ((const gu16 *)a.doclen)[d] : 1u;
         bool ok = in && d < a.ndocs;
-        float score = ok ? bm25_weight(((const gu32 *)a.tfs)[offp + i], dl, idfp, a) : 0.0f;
         const uint32_t last = min(63u, s1 - base - 1u);
+        const uint32_t d0 = (uint32_t)__shfl((int)d, 0), dlast = (uint32_t)__shfl((int)d, (int)last);
+        uint32_t tfr[kMaxTerms];
 #pragma unroll
-        for (uint32_t j = 0; j < kMaxTerms; j++) {
-            if (j >= a.tpq) break;
-            if (j == piv || !((vb >> j) & 1ull)) continue;
+        for (uint32_t r = 1; r < kMaxTerms; r++) {
+            tfr[r] = 0;
+            if (r >= nterms) break;
+            if (!__ballot(ok)) {   // no candidate left in the round
+                lag |= 1u << r;
+                continue;
+            }
+            const uint32_t j = ord[r];
             const uint32_t lj = (uint32_t)__shfl((int)len, (int)j);
             const uint64_t oj = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(off >> 32), (int)j) << 32) |
                                 (uint32_t)__shfl((int)(uint32_t)off, (int)j);
-            const float idfj = __shfl(idf, (int)j);
             const gu32 *v = (const gu32 *)a.docs + oj;
-            const uint32_t p = in ? skip_lower_bound(v, from[j], lj, d) : lj;
-            const bool found = p < lj && v[p] == d;
-            if (ok && found) score += bm25_weight(((const gu32 *)a.tfs)[oj + p], dl, idfj, a);
-            ok = ok && found;
-            from[j] = (uint32_t)__shfl((int)p, (int)last);
+            // the postings of list j from the round's first docID to its
+            // last (inclusive) hold each lane's docID or not at all: they
+            // start at lo and end at or before hi, and are searched in LDS
+            // if up to kLdsRange postings reach them
+            uint32_t lo = min(from[r], lj);
+            if ((lag >> r) & 1u) {
+                lo = probe_lower_bound(v, lo, lj, d0, lane, 0xFFFFFFFFu);
+                lag &= ~(1u << r);
+            }
+            const uint32_t hi =
+                dlast == 0xFFFFFFFFu ? lj : probe_lower_bound(v, lo, lj, dlast + 1u, lane, hint[r], kLdsRange);
+            const uint32_t n = hi - lo;
+            uint32_t p;
+            bool found;
+            if (n <= kLdsRange) {
+                for (uint32_t x = lane; x < n; x += 64u) rng[x] = v[lo + x];
+                wave_sync_lds();
+                uint32_t l = 0, cnt = n;   // first l with rng[l] >= d
+                while (cnt) {
+                    const uint32_t half = cnt >> 1;
+                    const bool below = rng[l + half] < d;
+                    l = below ? l + half + 1u : l;
+                    cnt = below ? cnt - half - 1u : half;
+                }
+                found = l < n && rng[l] == d;
+                p = lo + l;
+                // the next round starts past the last lane's docID
+                from[r] = lo + (uint32_t)__shfl((int)(l + (found ? 1u : 0u)), (int)last);
+                found = found && ok;
+                wave_sync_lds();   // the buffer is refilled for the next term
+            } else {
+                p = ok ? skip_lower_bound(v, lo, hi, d) : hi;
+                found = ok && p < hi && v[p] == d;
+                from[r] = hi;
+            }
+            if (found) tfr[r] = ((const gu32 *)a.tfs)[oj + p];
+            ok = found;
+        }
+        // documents in every list: BM25 over the pivot and the other terms
+        float score = 0.0f;
+        if (ok) {
+            const uint32_t dl = ((const gu16 *)a.doclen)[d];
+            score = bm25_weight(((const gu32 *)a.tfs)[offp + i], dl, idfp, a);
+#pragma unroll
+            for (uint32_t r = 1; r < kMaxTerms; r++)
+                if (r < nterms) score += bm25_weight(tfr[r], dl, idfr[r], a);
         }
         // offer the round's documents to the top-k, in docID order
         const float cand = ok ? score : -1.0f;

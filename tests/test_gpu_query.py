@@ -70,7 +70,7 @@ def index(torch_cuda):
 
 
 def run_queries(torch, ix, queries, topk, k1=1.2, b=0.75):
-    qp = gc.QueryPlan(ix["lengths"], queries, synth.U25, ix["avgdl"], topk=topk, k1=k1, b=b)
+    qp = gc.QueryPlan(ix["lengths"], queries, ix.get("ndocs", synth.U25), ix["avgdl"], topk=topk, k1=k1, b=b)
     nq = queries.shape[0]
     d_doc = torch.empty(nq * topk, dtype=torch.int32, device="cuda")
     d_sc = torch.empty(nq * topk, dtype=torch.float32, device="cuda")
@@ -81,8 +81,9 @@ def run_queries(torch, ix, queries, topk, k1=1.2, b=0.75):
 
 
 def check(ix, queries, docs, scores, topk, k1=1.2, b=0.75):
+    ndocs = ix.get("ndocs", synth.U25)
     for q in range(queries.shape[0]):
-        want = Q.and_topk(ix["doc_lists"], ix["tf_lists"], queries[q], ix["doclen"], synth.U25, ix["avgdl"],
+        want = Q.and_topk(ix["doc_lists"], ix["tf_lists"], queries[q], ix["doclen"], ndocs, ix["avgdl"],
                           k=topk, k1=k1, b=b)
         n = len(want)
         got_d = docs[q]
@@ -94,7 +95,7 @@ def check(ix, queries, docs, scores, topk, k1=1.2, b=0.75):
         assert np.allclose(scores[q, :n], ws, rtol=RTOL, atol=0), (q, scores[q, :n], ws)
         # every returned document is in the intersection, with the score of its rank
         terms = [int(t) for t in queries[q] if t >= 0]
-        full = {d: s for s, d in Q.and_topk(ix["doc_lists"], ix["tf_lists"], terms, ix["doclen"], synth.U25,
+        full = {d: s for s, d in Q.and_topk(ix["doc_lists"], ix["tf_lists"], terms, ix["doclen"], ndocs,
                                             ix["avgdl"], k=1 << 30, k1=k1, b=b)}
         for r in range(n):
             d = int(got_d[r])
@@ -127,3 +128,55 @@ def test_queries_edge_cases(torch_cuda, index):
         say("edge topk", topk, k1, b)
         docs, scores = run_queries(torch_cuda, index, queries, topk, k1, b)
         check(index, queries, docs, scores, topk, k1, b)
+
+
+def test_queries_list_shapes(torch_cuda):
+    """A small collection (2^18 documents) of lists shaped to reach every
+    search path: empty and one-posting lists, lengths at the 64-docID round
+    and 8192-docID segment boundaries, equal lengths (the pivot is the first
+    term), a dense run of consecutive docIDs, lists packed at the front or
+    the back of the collection (the first probe stride overshoots or falls
+    short), every docID (ranges longer than the LDS buffer, searched in
+    global memory); every ordered pair of lists, then triples and quads."""
+    torch = torch_cuda
+    rng = np.random.default_rng(31)
+    nd = 1 << 18
+
+    def spread(n, lo=0, hi=nd):
+        return np.sort(rng.choice(np.arange(lo, hi), n, replace=False)).astype(np.uint32)
+
+    doc_lists = [np.zeros(0, np.uint32), np.array([5], np.uint32), spread(64), spread(65), spread(1025),
+                 spread(1025), spread(8193), np.arange(100000, 116384, dtype=np.uint32), spread(120000),
+                 np.arange(nd, dtype=np.uint32), spread(3000, 0, 5000), spread(3000, nd - 12000, nd),
+                 spread(8192), spread(8191)]
+    # a list of clusters: runs of 40 consecutive docIDs
+    starts = np.sort(rng.choice(nd // 64, 300, replace=False)) * 64
+    doc_lists.append((starts[:, None] + np.arange(40)).ravel().astype(np.uint32))
+    tf_lists = [rng.integers(1, 21, x.size).astype(np.uint32) for x in doc_lists]
+    lengths = np.array([x.size for x in doc_lists], np.int64)
+    offs = np.concatenate([[0], np.cumsum(lengths)])
+    arena_d = gc.to_device(np.concatenate(doc_lists))
+    arena_t = gc.to_device(np.concatenate(tf_lists))
+    doclen = synth.doc_lengths(seed=9, ndocs=nd)
+    ix = dict(lengths=lengths, doc_lists=doc_lists, tf_lists=tf_lists, arena=None, ndocs=nd,
+              doclen=doclen, avgdl=float(doclen.mean()))
+    n = lengths.size
+    qs = [[i, j, -1, -1] for i in range(n) for j in range(n) if i != j]
+    qs += [list(rng.choice(n, 3, replace=False)) + [-1] for _ in range(40)]
+    qs += [list(rng.choice(n, 4, replace=False)) for _ in range(40)]
+    qs += [[9, 9, 8, -1], [8, 9, 7, 6], [-1, 9, -1, 4], [0, 9, -1, -1], [9, -1, -1, -1], [14, 9, 8, 12]]
+    queries = np.array(qs, np.int64)
+    term_off = torch.from_numpy(offs[:-1].astype(np.int64)).cuda()
+    d_doclen = torch.from_numpy(doclen.view(np.int16)).cuda()
+    for topk in (10, 64):
+        say("shapes topk", topk, "queries", queries.shape)
+        qp = gc.QueryPlan(lengths, queries, nd, ix["avgdl"], topk=topk)
+        nq = queries.shape[0]
+        d_doc = torch.empty(nq * topk, dtype=torch.int32, device="cuda")
+        d_sc = torch.empty(nq * topk, dtype=torch.float32, device="cuda")
+        qp.run(arena_d, arena_t, term_off, d_doclen, d_doc, d_sc)
+        torch.cuda.synchronize()
+        qp.close()
+        docs = gc.to_host(d_doc).reshape(nq, topk)
+        scores = d_sc.cpu().numpy().reshape(nq, topk)
+        check(ix, queries, docs, scores, topk)
