@@ -102,6 +102,13 @@ __device__ __forceinline__ uint32_t coded(const EArgs &a, const EList &L, uint64
     return a.delta ? x[i] - (i ? x[i - 1] : 0u) : x[i];
 }
 
+// Orders a wave's LDS accesses before and after it (lanes of one wave).
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // List of global tuple g (binary search over the lists' first tuples).
 __device__ __forceinline__ uint32_t list_of_tuple(const EArgs &a, uint64_t g) {
     uint32_t lo = 0, hi = a.nlists;   // invariant: lists[lo].t0 <= g < lists[hi].t0 (hi: end)
@@ -453,154 +460,302 @@ __global__ __launch_bounds__(kThreads) void k_afor_chainC(EArgs a) {
 }
 
 // ---- data rows of Group-Simple, Group-Scheme and Group-AFOR ------------------------
-// One lane per tuple: its k integers at their component bit offset.
-__global__ __launch_bounds__(kThreads) void k_emit_tuples(EArgs a, int codec) {
-    const uint64_t g = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (g >= a.ntup) return;
-    const EList L = a.lists[list_of_tuple(a, g)];
-    const uint32_t t = (uint32_t)(g - L.t0);
-    if (t >= L.T) return;
-    uint32_t *base = a.out + L.out_off;
-    const uint32_t C = base[2];
-    gu32 *data = (gu32 *)(base + 4u + C);
-    uint32_t O, bw;
+// Where tuple t of list L goes: its first data word wi (component c at word
+// wi * k + c), the bit shift sh there and its width bw (its bits run into
+// word wi + 1 if sh + bw > 32); for Group-Scheme, the control word cw and
+// the bits to clear there (unary: the terminator) or to set (binary: the
+// length field) in cm.
+struct TuplePlace {
+    uint32_t wi, sh, bw, cw, cm;
+};
+
+__device__ __forceinline__ TuplePlace tuple_place(const EArgs &a, const EList &L, uint64_t g, uint32_t t, int codec) {
+    TuplePlace P{0u, 0u, 0u, 0u, 0u};
     if (codec == GC_SIMPLE) {
-        const uint32_t v = a.tw2[g], s = v >> 10, sel = (v >> 5) & 15u, jj = v & 31u;
-        bw = kBw[sel];
         // a selector's row holds its tuples side by side (NUM * BW <= 32)
-        for (uint32_t c = 0; c < a.k; c++)
-            atomicOr((uint32_t *)&data[s * a.k + c], coded(a, L, (uint64_t)t * a.k + c) << (jj * bw));
-        return;
+        const uint32_t v = a.tw2[g], sel = (v >> 5) & 15u;
+        P.bw = kBw[sel];
+        P.wi = v >> 10;
+        P.sh = (v & 31u) * P.bw;
+        return P;
     }
+    uint32_t O;
     if (codec == GC_SCHEME) {
-        bw = a.cg * gsc_units(a.W[g], a.cg);
+        P.bw = a.cg * gsc_units(a.W[g], a.cg);
         O = a.tw2[g];
-        // control: clear the unary terminator, or set the binary length field
-        gu32 *ctrl = (gu32 *)(base + 4u);
-        const uint32_t u = bw / a.cg;
+        const uint32_t u = P.bw / a.cg;
         if (a.ld == GC_LD_BINARY) {
             const uint32_t fields = a.cg == 1u ? 3u : a.cg == 8u ? 4u : 2u, ubits = a.cg == 1u ? 16u : 8u;
             const uint32_t fb = a.cg == 1u ? 5u : a.cg == 2u ? 4u : a.cg == 4u ? 3u : 2u;
             const uint32_t pos = (t / fields) * ubits + (t % fields) * fb;
-            atomicOr((uint32_t *)&ctrl[pos >> 5], (u - 1u) << (pos & 31u));
+            P.cw = pos >> 5;
+            P.cm = (u - 1u) << (pos & 31u);
         } else {
             const uint32_t z = a.tw[g];
-            atomicAnd((uint32_t *)&ctrl[z >> 5], ~(1u << (z & 31u)));
+            P.cw = z >> 5;
+            P.cm = 1u << (z & 31u);
         }
     } else {
         const uint32_t o = t >> 3;
-        bw = a.och[L.t0 / 8u + o];
-        O = a.tw[L.t0 / 8u + o] + (t & 7u) * bw;
+        P.bw = a.och[L.t0 / 8u + o];
+        O = a.tw[L.t0 / 8u + o] + (t & 7u) * P.bw;
     }
-    if (!bw) return;
-    const uint32_t wi = O >> 5, sh = O & 31u;
-    for (uint32_t c = 0; c < a.k; c++) {
-        const uint32_t x = coded(a, L, (uint64_t)t * a.k + c);
-        atomicOr((uint32_t *)&data[wi * a.k + c], x << sh);
-        if (sh + bw > 32u) atomicOr((uint32_t *)&data[(wi + 1u) * a.k + c], x >> (32u - sh));
+    P.wi = O >> 5;
+    P.sh = O & 31u;
+    return P;
+}
+
+// A tile's span of data words per component, and of control words, held in
+// LDS: 256 tuples of at most 32 bits (plus one word for the first's
+// offset); incomplete-unary control adds under 8 bits per tuple.
+constexpr uint32_t kEmitSpan = kThreads + 1u;
+constexpr uint32_t kCtrlSpan = 320u;
+
+// One lane per tuple: its k integers at their component bit offset, and its
+// Group-Scheme control bits.  The tuples of the workgroup's first list
+// gather their words in LDS: words only they touch are stored whole, the
+// first and last (which neighbouring workgroups may share) merged by
+// atomics.  Tuples of later lists in the tile (a list starting inside it),
+// and tiles whose words exceed the LDS span (k = 64), use global atomics.
+// Dynamic LDS: kEmitSpan * k words when k <= 32.
+__global__ __launch_bounds__(kThreads) void k_emit_tuples(EArgs a, int codec) {
+    extern __shared__ uint32_t s_data[];
+    __shared__ uint32_t s_ctrl[kCtrlSpan];
+    __shared__ uint32_t s_list, s_lo, s_hi, s_clo, s_chi;
+    const uint64_t g0 = (uint64_t)blockIdx.x * kThreads;
+    const uint64_t g = g0 + threadIdx.x;
+    const uint32_t k = a.k, lk = a.lk;
+    const bool unary = codec == GC_SCHEME && a.ld != GC_LD_BINARY;
+    if (threadIdx.x == 0) {
+        s_list = list_of_tuple(a, g0);
+        s_lo = s_clo = 0xFFFFFFFFu;
+        s_hi = s_chi = 0u;
+    }
+    __syncthreads();
+    const uint32_t li0 = s_list;
+    const uint64_t t00 = a.lists[li0].t0;
+    bool act = g < a.ntup;
+    const bool first = !act || g - t00 < a.lists[li0].M;
+    const EList L = a.lists[first ? li0 : list_of_tuple(a, g)];
+    const uint32_t t = act ? (uint32_t)(g - L.t0) : 0u;
+    act = act && t < L.T;
+    TuplePlace P{0u, 0u, 0u, 0u, 0u};
+    if (act) P = tuple_place(a, L, g, t, codec);
+    const bool cross = P.sh + P.bw > 32u;
+    const bool gather = k <= 32u && act && first;
+    if (gather && P.bw) {
+        atomicMin(&s_lo, P.wi);
+        atomicMax(&s_hi, P.wi + (cross ? 1u : 0u));
+    }
+    if (gather && codec == GC_SCHEME) {
+        atomicMin(&s_clo, P.cw);
+        atomicMax(&s_chi, P.cw);
+    }
+    __syncthreads();
+    const uint32_t lo = s_lo, hi = s_hi, clo = s_clo, chi = s_chi;
+    const uint32_t span = lo <= hi ? hi - lo + 1u : 0u, cspan = clo <= chi ? chi - clo + 1u : 0u;
+    // uniform over the workgroup: gather in LDS, or every lane by atomics
+    const bool lds = k <= 32u && span <= kEmitSpan && cspan <= kCtrlSpan;
+    for (uint32_t x = threadIdx.x; lds && x < (span << lk); x += kThreads) s_data[x] = 0u;
+    for (uint32_t x = threadIdx.x; lds && x < cspan; x += kThreads) s_ctrl[x] = unary ? 0xFFFFFFFFu : 0u;
+    __syncthreads();
+    uint32_t *base = a.out + L.out_off;
+    gu32 *ctrl = (gu32 *)(base + 4u);
+    gu32 *data = (gu32 *)(base + 4u + base[2]);
+    const bool here = lds && gather;
+    if (act && codec == GC_SCHEME) {
+        if (here) {
+            if (unary) atomicAnd(&s_ctrl[P.cw - clo], ~P.cm);
+            else atomicOr(&s_ctrl[P.cw - clo], P.cm);
+        } else {
+            if (unary) atomicAnd((uint32_t *)&ctrl[P.cw], ~P.cm);
+            else atomicOr((uint32_t *)&ctrl[P.cw], P.cm);
+        }
+    }
+    if (act && P.bw) {
+        for (uint32_t c = 0; c < k; c++) {
+            const uint32_t x = coded(a, L, (uint64_t)t * k + c);
+            const uint32_t v0 = x << P.sh, v1 = cross ? x >> (32u - P.sh) : 0u;
+            if (here) {
+                atomicOr(&s_data[((P.wi - lo) << lk) + c], v0);
+                if (cross) atomicOr(&s_data[((P.wi + 1u - lo) << lk) + c], v1);
+            } else {
+                atomicOr((uint32_t *)&data[P.wi * k + c], v0);
+                if (cross) atomicOr((uint32_t *)&data[(P.wi + 1u) * k + c], v1);
+            }
+        }
+    }
+    if (!lds) return;
+    __syncthreads();
+    // the first list's words, out of LDS
+    uint32_t *base0 = a.out + a.lists[li0].out_off;
+    gu32 *data0 = (gu32 *)(base0 + 4u + base0[2]);
+    for (uint32_t x = threadIdx.x; x < (span << lk); x += kThreads) {
+        const uint32_t w = lo + (x >> lk), v = s_data[x];
+        gu32 *dst = data0 + ((uint64_t)lo << lk) + x;
+        if (w != lo && w != hi) *dst = v;
+        else if (v) atomicOr((uint32_t *)dst, v);
+    }
+    gu32 *ctrl0 = (gu32 *)(base0 + 4u);
+    for (uint32_t x = threadIdx.x; x < cspan; x += kThreads) {
+        const uint32_t w = clo + x, v = s_ctrl[x];
+        if (w != clo && w != chi) ctrl0[w] = v;
+        else if (unary && v != 0xFFFFFFFFu) atomicAnd((uint32_t *)&ctrl0[w], v);
+        else if (!unary && v) atomicOr((uint32_t *)&ctrl0[w], v);
     }
 }
 
 // ---- Group-PFD (Section 6.2) -------------------------------------------------------
-// One lane per 32-tuple block: b (Step 2), the exceptions (Step 3), their
-// value width (Step 4) and, for the linked layout, the compulsory
-// exceptions; every slot and the exception bitmap to scratch; the block's
-// descriptor and exception words.
+// Half a wave per 32-tuple block, lane t on tuple t: b (Step 2) by ballots
+// over the tuple widths, the exceptions (Step 3) and their value width
+// (Step 4), every slot and the exception bitmap (gathered in LDS) to
+// scratch; for the linked layout one lane then walks the exceptions in
+// order and adds the compulsory ones; the block's descriptor and exception
+// words.
 __global__ __launch_bounds__(kThreads) void k_pfd_blocks(EArgs a) {
-    const uint32_t bi = blockIdx.x * kThreads + threadIdx.x;
-    if (bi >= a.nblocks) return;
-    const uint64_t g0 = 32ull * bi;   // first tuple
+    __shared__ uint32_t s_xb[kThreads / 32u][64];   // each block's bitmap (k words, k <= 64)
+    const uint32_t lane = threadIdx.x & 63u, h = threadIdx.x >> 5, t = threadIdx.x & 31u;
+    const uint32_t bi = blockIdx.x * (kThreads / 32u) + h;
+    const bool valid = bi < a.nblocks;
+    const uint64_t hm = lane < 32u ? 0xFFFFFFFFull : 0xFFFFFFFF00000000ull;
+    const uint32_t k = a.k;
+    const bool linked = a.pfd_pos == GC_PFD_LINKED;
+    uint32_t *xbl = s_xb[h];
+    for (uint32_t w = t; w < k; w += 32u) xbl[w] = 0u;
+    const uint64_t g0 = 32ull * (valid ? bi : 0u);   // first tuple
     const EList L = a.lists[list_of_tuple(a, g0)];
     const uint32_t t0 = (uint32_t)(g0 - L.t0);
-    const uint32_t k = a.k, BI = 32u * k;
-    const uint8_t *W = a.W + g0;
-    uint32_t cnt[34];
-    for (int i = 0; i < 34; i++) cnt[i] = 0;
-    for (int t = 0; t < 32; t++) cnt[W[t]]++;
-    uint32_t wider = 32u - cnt[0], b = 0;
-    while ((uint64_t)wider * a.zd >= (uint64_t)a.zn * 32u) {
-        b++;
-        wider -= cnt[b];
+    const uint32_t Wt = valid ? a.W[g0 + t] : 0u;
+    // the smallest b leaving fewer than the fraction zn / zd of the tuples wider
+    uint32_t b = 0;
+    for (;;) {
+        const uint32_t wider = (uint32_t)__builtin_popcountll(__ballot(Wt > b) & hm);
+        const bool more = valid && b < 32u && (uint64_t)wider * a.zd >= (uint64_t)a.zn * 32u;
+        if (!__ballot(more)) break;
+        b += more ? 1u : 0u;
     }
+    const uint32_t M = b >= 32u ? 0xFFFFFFFFu : (1u << b) - 1u;
     const uint64_t x0 = (uint64_t)t0 * k;   // first integer of the block in its list
     uint32_t *slot = a.slot + g0 * k;
-    uint32_t *xb = a.xbit + g0 * k / 32u;
-    for (uint32_t w = 0; w < BI / 32u; w++) xb[w] = 0u;
-    uint32_t nx = 0, maxw = 0, nt = 0;
-    for (uint32_t t = 0; t < 32u; t++) {
-        const bool wide = W[t] > b;
-        bool any = false;
+    const bool wide = Wt > b;
+    uint32_t nxl = 0, mwl = 0;
+    wave_lds_fence();
+    if (valid) {
         for (uint32_t c = 0; c < k; c++) {
             const uint32_t p = t * k + c;
             const uint32_t x = coded(a, L, x0 + p);
             const uint32_t w = width_of(x);
-            slot[p] = x;
-            if (wide && w > b) {
-                xb[p >> 5] |= 1u << (p & 31u);
-                nx++;
-                any = true;
-                maxw = max(maxw, w);
+            const bool e = wide && w > b;
+            slot[p] = e && !linked ? x & M : x;
+            if (e) {
+                atomicOr(&xbl[p >> 5], 1u << (p & 31u));
+                nxl++;
+                mwl = max(mwl, w);
             }
         }
-        nt += any ? 1u : 0u;
     }
-    const uint32_t wcode = nx == 0 ? 0u : maxw <= 8u ? 1u : maxw <= 16u ? 2u : 3u;
-    const uint32_t ew = wcode ? 4u << wcode : 0u;
-    uint32_t nexc = 0, first = 0;
-    const uint32_t M = b >= 32u ? 0xFFFFFFFFu : (1u << b) - 1u;
-    if (a.pfd_pos == GC_PFD_LINKED) {
+    uint32_t nx = nxl, maxw = mwl;
+#pragma unroll
+    for (uint32_t m = 1; m < 32u; m <<= 1) {
+        nx += (uint32_t)__shfl_xor((int)nx, (int)m);
+        maxw = max(maxw, (uint32_t)__shfl_xor((int)maxw, (int)m));
+    }
+    const uint32_t nt = (uint32_t)__builtin_popcountll(__ballot(nxl > 0u) & hm);
+    wave_lds_fence();
+    uint32_t nexc = nx, first = nt;
+    if (linked) {
         // the chain through the slots, with a compulsory exception wherever
         // the gap to the next one does not fit b bits
-        const uint64_t lim = b >= 32u ? ~0ull : (1ull << b) - 1u;
-        int64_t prev = -1;
-        for (uint32_t p = 0; p < BI; p++) {
-            if (!((xb[p >> 5] >> (p & 31u)) & 1u)) continue;
-            if (prev >= 0) {
-                while ((uint64_t)((int64_t)p - prev - 1) > lim) {
-                    const uint32_t cp = (uint32_t)(prev + (int64_t)(1ull << b));
-                    xb[cp >> 5] |= 1u << (cp & 31u);
-                    slot[(uint32_t)prev] = cp - (uint32_t)prev - 1u;
-                    prev = cp;
+        nexc = first = 0;
+        if (valid && t == 0u) {
+            __threadfence_block();   // the slots above are stored before the chain's
+            const uint64_t lim = b >= 32u ? ~0ull : (1ull << b) - 1u;
+            int64_t prev = -1;
+            for (uint32_t w = 0; w < k; w++) {
+                uint32_t bits = xbl[w];
+                while (bits) {
+                    const uint32_t p = 32u * w + (uint32_t)__builtin_ctz(bits);
+                    bits &= bits - 1u;
+                    if (prev >= 0) {
+                        while ((uint64_t)((int64_t)p - prev - 1) > lim) {
+                            const uint32_t cp = (uint32_t)(prev + (int64_t)(1ull << b));
+                            xbl[cp >> 5] |= 1u << (cp & 31u);
+                            slot[(uint32_t)prev] = cp - (uint32_t)prev - 1u;
+                            prev = cp;
+                            nexc++;
+                        }
+                        slot[(uint32_t)prev] = p - (uint32_t)prev - 1u;
+                    } else {
+                        first = p;
+                    }
+                    prev = p;
                     nexc++;
                 }
-                slot[(uint32_t)prev] = p - (uint32_t)prev - 1u;
-            } else {
-                first = p;
             }
-            prev = p;
-            nexc++;
+            if (prev >= 0) slot[(uint32_t)prev] = 0u;
         }
-        if (prev >= 0) slot[(uint32_t)prev] = 0u;
-    } else {
-        nexc = nx;
-        first = nt;
-        for (uint32_t p = 0; p < BI; p++)
-            if ((xb[p >> 5] >> (p & 31u)) & 1u) slot[p] &= M;
+        nexc = (uint32_t)__shfl((int)nexc, (int)(lane & 32u));
+        first = (uint32_t)__shfl((int)first, (int)(lane & 32u));
+        wave_lds_fence();
     }
-    const uint32_t vals = nexc ? (nexc * ew + 31u) / 32u : 0u;
-    const uint32_t xw = !nexc ? 0u : a.pfd_pos == GC_PFD_BITMAP ? 1u + (first * k + 31u) / 32u + vals : vals;
-    uint32_t *bk = a.blk + 4u * bi;
-    bk[0] = b | (wcode << 6) | (first << 8) | (nexc << 20);
-    bk[1] = xw;
+    if (!valid) return;
+    uint32_t *xb = a.xbit + g0 * k / 32u;
+    for (uint32_t w = t; w < k; w += 32u) xb[w] = xbl[w];
+    if (t == 0u) {
+        const uint32_t wcode = nx == 0 ? 0u : maxw <= 8u ? 1u : maxw <= 16u ? 2u : 3u;
+        const uint32_t ew = wcode ? 4u << wcode : 0u;
+        const uint32_t vals = nexc ? (nexc * ew + 31u) / 32u : 0u;
+        const uint32_t xw = !nexc ? 0u : a.pfd_pos == GC_PFD_BITMAP ? 1u + (first * k + 31u) / 32u + vals : vals;
+        uint32_t *bk = a.blk + 4u * bi;
+        bk[0] = b | (wcode << 6) | (first << 8) | (nexc << 20);
+        bk[1] = xw;
+    }
 }
 
-// One lane per list: row and exception word bases of its blocks; C, D, E.
+// Per list, one wave: every block's data-row base and exception-word base
+// (exclusive sums over the list's blocks, eight consecutive blocks a lane,
+// 512 a step), and the list's C, D and E.
+constexpr uint32_t kPfdPer = 8;
+
 __global__ __launch_bounds__(kThreads) void k_pfd_listB(EArgs a) {
-    const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t i = blockIdx.x * (kThreads / 64u) + (threadIdx.x >> 6), lane = threadIdx.x & 63u;
     if (i >= a.nlists) return;
     const EList L = a.lists[i];
     const uint32_t nb = L.M / 32u;
-    uint32_t rows = 0, xw = 0;
-    for (uint32_t j = 0; j < nb; j++) {
-        uint32_t *bk = a.blk + 4u * (L.b0 + j);
-        bk[2] = rows;
-        bk[3] = xw;
-        rows += bk[0] & 63u;
-        xw += bk[1];
+    uint32_t rows = 0, xw = 0;   // over the blocks before the step (uniform)
+    for (uint32_t j0 = 0; j0 < nb; j0 += 64u * kPfdPer) {
+        const uint32_t j1 = j0 + lane * kPfdPer;
+        uint32_t r[kPfdPer], x[kPfdPer], sr = 0, sx = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < kPfdPer; q++) {
+            const uint2 bk = j1 + q < nb ? *reinterpret_cast<const uint2 *>(a.blk + 4u * (L.b0 + j1 + q)) : make_uint2(0u, 0u);
+            r[q] = bk.x & 63u;
+            x[q] = bk.y;
+            sr += r[q];
+            sx += x[q];
+        }
+        uint32_t ir = sr, ix = sx;   // inclusive sums over the lanes
+#pragma unroll
+        for (uint32_t d = 1; d < 64u; d <<= 1) {
+            const uint32_t ur = (uint32_t)__shfl_up((int)ir, d), ux = (uint32_t)__shfl_up((int)ix, d);
+            ir += lane >= d ? ur : 0u;
+            ix += lane >= d ? ux : 0u;
+        }
+        uint32_t pr = rows + ir - sr, px = xw + ix - sx;
+#pragma unroll
+        for (uint32_t q = 0; q < kPfdPer; q++) {
+            if (j1 + q < nb) *reinterpret_cast<uint2 *>(a.blk + 4u * (L.b0 + j1 + q) + 2u) = make_uint2(pr, px);
+            pr += r[q];
+            px += x[q];
+        }
+        rows += (uint32_t)__shfl((int)ir, 63);
+        xw += (uint32_t)__shfl((int)ix, 63);
     }
-    a.sizes[3u * i] = (nb + 3u) / 4u * 4u;
-    a.sizes[3u * i + 1u] = a.k * rows;
-    a.sizes[3u * i + 2u] = xw;
+    if (lane == 0) {
+        a.sizes[3u * i] = (nb + 3u) / 4u * 4u;
+        a.sizes[3u * i + 1u] = a.k * rows;
+        a.sizes[3u * i + 2u] = xw;
+    }
 }
 
 // Appends v (nb bits) to a word stream at out[*w], bit position *acc_n of
@@ -628,50 +783,65 @@ struct WordSink {
     }
 };
 
-// One lane per block: descriptor, data rows (component c of row r at word
-// k*r + c) and exception words.
+// Half a wave per block, the descriptor to the control area, data rows and
+// exception words to their places: lane t assembles whole row words
+// (component c of row r at word k*r + c) from the slots they hold; lane 0
+// writes the exception area (a block has few exceptions), walking the set
+// bits of the bitmap.
 __global__ __launch_bounds__(kThreads) void k_pfd_emit(EArgs a) {
-    const uint32_t bi = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63u, t = threadIdx.x & 31u;
+    const uint32_t bi = blockIdx.x * (kThreads / 32u) + (threadIdx.x >> 5);
     if (bi >= a.nblocks) return;
     const uint64_t g0 = 32ull * bi;
     const EList L = a.lists[list_of_tuple(a, g0)];
     const uint32_t j = (uint32_t)((g0 - L.t0) / 32u);
-    const uint32_t k = a.k, BI = 32u * k;
+    const uint32_t k = a.k, lk = a.lk;
     const uint32_t *bk = a.blk + 4u * bi;
-    const uint32_t desc = bk[0], b = desc & 63u, wcode = (desc >> 6) & 3u, first = (desc >> 8) & 0xFFFu,
-                   nexc = desc >> 20;
+    const uint32_t desc = bk[0], b = desc & 63u, wcode = (desc >> 6) & 3u, nexc = desc >> 20;
     uint32_t *base = a.out + L.out_off;
     const uint32_t C = base[2], D = base[3];
-    gu32 *ctrl = (gu32 *)(base + 4u);
-    ctrl[j] = desc;
+    if (t == 0u) ((gu32 *)(base + 4u))[j] = desc;
     const uint32_t *slot = a.slot + g0 * k;
     const uint32_t *xb = a.xbit + g0 * k / 32u;
     gu32 *rows = (gu32 *)(base + 4u + C) + (uint64_t)bk[2] * k;
-    for (uint32_t c = 0; c < k && b; c++) {
-        WordSink s{rows + c, k, 0u, 0u, 0ull};
-        for (uint32_t t = 0; t < 32u; t++) s.put(slot[t * k + c], b);
+    const uint32_t M = b >= 32u ? 0xFFFFFFFFu : (1u << b) - 1u;
+    // tuple tt of component c holds bits [tt*b, tt*b + b) of the
+    // component's b words
+    for (uint32_t idx = t; idx < (b << lk); idx += 32u) {
+        const uint32_t r = idx >> lk, c = idx & (k - 1u), lo = 32u * r;
+        const uint32_t ta = lo / b, tb = min(31u, (lo + 31u) / b);
+        uint32_t v = 0;
+        for (uint32_t tt = ta; tt <= tb; tt++) {
+            const uint32_t x = slot[tt * k + c] & M, off = tt * b;
+            v |= off >= lo ? x << (off - lo) : x >> (lo - off);
+        }
+        rows[idx] = v;
     }
-    if (!nexc) return;
+    // the tuples with an exception (for the bitmap layout)
+    const uint32_t kmask = k >= 32u ? 0xFFFFFFFFu : (1u << k) - 1u;
+    const bool any = k <= 32u ? ((xb[(t * k) >> 5] >> ((t * k) & 31u)) & kmask) != 0u
+                              : (xb[2u * t] | xb[2u * t + 1u]) != 0u;
+    const uint32_t tm = (uint32_t)(__ballot(any) >> (lane & 32u));
+    if (t != 0u || !nexc) return;
     WordSink e{(gu32 *)(base + 4u + C + D) + bk[3], 1u, 0u, 0u, 0ull};
     if (a.pfd_pos == GC_PFD_BITMAP) {
-        uint32_t tm = 0;
-        for (uint32_t t = 0; t < 32u; t++) {
-            bool any = false;
-            for (uint32_t c = 0; c < k; c++) any |= ((xb[(t * k + c) >> 5] >> ((t * k + c) & 31u)) & 1u) != 0u;
-            tm |= (any ? 1u : 0u) << t;
-        }
+        // the tuple mask, then each marked tuple's k exception bits
         e.put(tm, 32u);
-        for (uint32_t t = 0; t < 32u; t++) {
-            if (!((tm >> t) & 1u)) continue;
-            for (uint32_t c = 0; c < k; c++) e.put((xb[(t * k + c) >> 5] >> ((t * k + c) & 31u)) & 1u, 1u);
+        for (uint32_t m = tm; m; m &= m - 1u) {
+            const uint32_t tt = (uint32_t)__builtin_ctz(m);
+            if (k <= 32u) {
+                e.put(xb[(tt * k) >> 5] >> ((tt * k) & 31u), k);
+            } else {
+                e.put(xb[2u * tt], 32u);
+                e.put(xb[2u * tt + 1u], 32u);
+            }
         }
         e.flush();
-        (void)first;
     }
     const uint32_t ew = 4u << wcode;
     const uint64_t x0 = (uint64_t)(j * 32u) * k;
-    for (uint32_t p = 0; p < BI; p++)
-        if ((xb[p >> 5] >> (p & 31u)) & 1u) e.put(coded(a, L, x0 + p), ew);
+    for (uint32_t w = 0; w < k; w++)
+        for (uint32_t m = xb[w]; m; m &= m - 1u) e.put(coded(a, L, x0 + 32u * w + (uint32_t)__builtin_ctz(m)), ew);
     e.flush();
 }
 
@@ -834,8 +1004,8 @@ extern "C" gc_status gc_encode_lists_gpu(const uint32_t *d_in, const uint64_t *h
         if ((rc = dalloc(&a.blk, 4ull * nblocks, keep)) || (rc = dalloc(&a.slot, ntup * k, keep)) ||
             (rc = dalloc(&a.xbit, ntup * k / 32u + 1u, keep)))
             goto done;
-        if (nblocks) hipLaunchKernelGGL(k_pfd_blocks, dim3(grid(nblocks)), dim3(kThreads), 0, s, a);
-        hipLaunchKernelGGL(k_pfd_listB, dim3(grid(nlists)), dim3(kThreads), 0, s, a);
+        if (nblocks) hipLaunchKernelGGL(k_pfd_blocks, dim3((nblocks + kThreads / 32 - 1) / (kThreads / 32)), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL(k_pfd_listB, dim3((nlists + kThreads / 64 - 1) / (kThreads / 64)), dim3(kThreads), 0, s, a);
     }
     ENC_OK(hipGetLastError());
     ENC_OK(hipMemcpyAsync(sizes.data(), a.sizes, sizes.size() * 4, hipMemcpyDeviceToHost, s));
@@ -862,9 +1032,10 @@ extern "C" gc_status gc_encode_lists_gpu(const uint32_t *d_in, const uint64_t *h
     if (codec == GC_SIMPLE && nch) hipLaunchKernelGGL(k_sim_chainC, dim3(grid(nch)), dim3(kThreads), 0, s, a);
     if (codec == GC_AFOR && nch) hipLaunchKernelGGL(k_afor_chainC, dim3(grid(nch)), dim3(kThreads), 0, s, a);
     if (codec == GC_PFD) {
-        if (nblocks) hipLaunchKernelGGL(k_pfd_emit, dim3(grid(nblocks)), dim3(kThreads), 0, s, a);
+        if (nblocks) hipLaunchKernelGGL(k_pfd_emit, dim3((nblocks + kThreads / 32 - 1) / (kThreads / 32)), dim3(kThreads), 0, s, a);
     } else if (ntup) {
-        hipLaunchKernelGGL(k_emit_tuples, dim3(grid(ntup)), dim3(kThreads), 0, s, a, (int)codec);
+        const size_t lds = a.k <= 32u ? sizeof(uint32_t) * kEmitSpan * a.k : 0;
+        hipLaunchKernelGGL(k_emit_tuples, dim3(grid(ntup)), dim3(kThreads), lds, s, a, (int)codec);
     }
     ENC_OK(hipGetLastError());
     ENC_OK(hipStreamSynchronize(s));
