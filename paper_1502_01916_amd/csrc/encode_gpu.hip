@@ -146,25 +146,74 @@ __device__ __forceinline__ uint32_t gsc_step(uint32_t pos, uint32_t u, bool iu, 
     return pos + u;
 }
 
-// Step A, one lane per (chunk, entry state s): IU enters at bit s mod 8;
-// summary per state: exit state | control bits << 3; plus the chunk's data
-// bits (state 0's lane).
+// A chunk's walks on one wave: lane l takes tuples [32 l, 32 l + 32) of
+// the chunk.  The units of the lane's tuples, four to a word (0 past the
+// chunk's end), and their data bits.
+constexpr uint32_t kSegUnits = 32;   // units of a chunk per lane
+static_assert(kTupChunk == 64u * kSegUnits, "a chunk is 64 lane segments");
+
+__device__ __forceinline__ void gsc_seg_units(const EArgs &a, const uint8_t *W, uint32_t nu, uint32_t lane,
+                                              uint32_t (&pu)[8], uint32_t &dbits) {
+    dbits = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < 8u; i++) {
+        uint32_t w = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < 4u; q++) {
+            const uint32_t t = kSegUnits * lane + 4u * i + q;
+            const uint32_t u = t < nu ? gsc_units(W[t], a.cg) : 0u;
+            dbits += a.cg * u;
+            w |= u << (8u * q);
+        }
+        pu[i] = w;
+    }
+}
+
+// The control position after the lane's tuples, entered at pos.
+__device__ __forceinline__ uint32_t gsc_seg_walk(uint32_t pos, const uint32_t (&pu)[8], bool iu) {
+#pragma unroll
+    for (uint32_t i = 0; i < kSegUnits; i++) {
+        const uint32_t u = (pu[i >> 2] >> (8u * (i & 3u))) & 0xFFu;
+        uint32_t z;
+        if (u) pos = gsc_step(pos, u, iu, z);
+    }
+    return pos;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v, uint32_t lane) {
+#pragma unroll
+    for (uint32_t d = 1; d < 64u; d <<= 1) {
+        const uint32_t u = (uint32_t)__shfl_up((int)v, d);
+        v += lane >= d ? u : 0u;
+    }
+    return v;
+}
+
+// Step A, one wave per chunk: for every entry state s (IU enters at bit
+// s mod 8; the other layouts have one state), exit state | control bits
+// << 3, from the lanes' advances per state chained in LDS; plus the
+// chunk's data bits.
 __global__ __launch_bounds__(kThreads) void k_gsc_chunkA(EArgs a) {
-    const uint32_t id = blockIdx.x * kThreads + threadIdx.x;
-    const uint32_t ns = a.ld == GC_LD_IU ? 8u : 1u;
-    if (id >= a.nchunks * ns) return;
-    const uint32_t ch = id / ns, s = id % ns;
+    __shared__ uint32_t s_adv[kThreads / 64u][64][8];
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t ch = blockIdx.x * (kThreads / 64u) + wave;
+    if (ch >= a.nchunks) return;
     const EChunk C = a.chunks[ch];
     const EList L = a.lists[C.list];
-    const uint8_t *W = a.W + L.t0 + C.u0;
-    uint32_t pos = s, dbits = 0, z;
-    for (uint32_t t = 0; t < C.nu; t++) {
-        const uint32_t u = gsc_units(W[t], a.cg);
-        pos = gsc_step(pos, u, a.ld == GC_LD_IU, z);
-        dbits += a.cg * u;
+    const bool iu = a.ld == GC_LD_IU;
+    const uint32_t ns = iu ? 8u : 1u;
+    uint32_t pu[8], db;
+    gsc_seg_units(a, a.W + L.t0 + C.u0, C.nu, lane, pu, db);
+    // the control bits the lane's tuples take, entered at bit s mod 8
+    for (uint32_t st = 0; st < ns; st++) s_adv[wave][lane][st] = gsc_seg_walk(st, pu, iu) - st;
+    db = (uint32_t)__shfl((int)wave_incl_sum(db, lane), 63);
+    wave_lds_fence();
+    if (lane < ns) {
+        uint32_t pos = lane;
+        for (uint32_t l = 0; l < 64u; l++) pos += s_adv[wave][l][iu ? pos & 7u : 0u];
+        a.chs[2u * (ch * 8u + lane)] = ((pos - lane) << 3) | (pos & 7u);
+        if (lane == 0) a.chs[2u * (ch * 8u) + 1u] = db;
     }
-    a.chs[2u * (ch * 8u + s)] = ((pos - s) << 3) | (pos & 7u);
-    if (s == 0) a.chs[2u * (ch * 8u) + 1u] = dbits;
 }
 
 // Step B, one lane per list: every chunk's entry control bit and data bit;
@@ -191,20 +240,44 @@ __global__ __launch_bounds__(kThreads) void k_gsc_listB(EArgs a) {
     a.sizes[3u * i + 2u] = 0u;
 }
 
-// Step C, one lane per chunk: every tuple's terminator (unary) and data bit.
+// Step C, one wave per chunk: every tuple's terminator (unary) and data
+// bit.  Lane 0 chains the lanes' advances from the chunk's entry bit; each
+// lane then walks its own tuples from its entry.
 __global__ __launch_bounds__(kThreads) void k_gsc_chunkC(EArgs a) {
-    const uint32_t ch = blockIdx.x * kThreads + threadIdx.x;
+    __shared__ uint32_t s_adv[kThreads / 64u][64][8];
+    __shared__ uint32_t s_pos[kThreads / 64u][64];
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t ch = blockIdx.x * (kThreads / 64u) + wave;
     if (ch >= a.nchunks) return;
     const EChunk C = a.chunks[ch];
     const EList L = a.lists[C.list];
-    const uint64_t g0 = L.t0 + C.u0;
-    uint32_t pos = a.chb[2u * ch], dbits = a.chb[2u * ch + 1u], z = 0;
-    for (uint32_t t = 0; t < C.nu; t++) {
-        const uint32_t u = gsc_units(a.W[g0 + t], a.cg);
-        pos = gsc_step(pos, u, a.ld == GC_LD_IU, z);
-        a.tw[g0 + t] = z;
-        a.tw2[g0 + t] = dbits;
-        dbits += a.cg * u;
+    const bool iu = a.ld == GC_LD_IU;
+    const uint32_t ns = iu ? 8u : 1u;
+    uint32_t pu[8], db;
+    gsc_seg_units(a, a.W + L.t0 + C.u0, C.nu, lane, pu, db);
+    for (uint32_t st = 0; st < ns; st++) s_adv[wave][lane][st] = gsc_seg_walk(st, pu, iu) - st;
+    uint32_t dbits = a.chb[2u * ch + 1u] + wave_incl_sum(db, lane) - db;
+    wave_lds_fence();
+    if (lane == 0) {
+        uint32_t pos = a.chb[2u * ch];
+        for (uint32_t l = 0; l < 64u; l++) {
+            s_pos[wave][l] = pos;
+            pos += s_adv[wave][l][iu ? pos & 7u : 0u];
+        }
+    }
+    wave_lds_fence();
+    uint32_t pos = s_pos[wave][lane];
+    const uint64_t g0 = (uint64_t)L.t0 + C.u0 + kSegUnits * lane;
+#pragma unroll
+    for (uint32_t i = 0; i < kSegUnits; i++) {
+        const uint32_t u = (pu[i >> 2] >> (8u * (i & 3u))) & 0xFFu;
+        if (u) {
+            uint32_t z;
+            pos = gsc_step(pos, u, iu, z);
+            a.tw[g0 + i] = z;
+            a.tw2[g0 + i] = dbits;
+            dbits += a.cg * u;
+        }
     }
 }
 
@@ -232,22 +305,58 @@ __global__ __launch_bounds__(kThreads) void k_sim_cover(EArgs a) {
     a.tw[g] = pick | (cover << 4);
 }
 
-// Step A, one lane per (chunk, entry offset e < 32): the chain entering the
-// chunk at tuple u0 + e; summary: exit offset | selectors << 5.
+// The selector chain over a chunk on one wave: lane l takes tuples
+// [32 l, 32 l + 32) of the chunk, and for every entry offset p < 32 into
+// them finds, by a backward pass, where the chain entered at p leaves
+// (offset x from the lane's first tuple, x >= 32 into the next lane's; a
+// chain that ends at the chunk's end, or the list's, stops there) and the
+// selectors it starts: tab[p] = x | selectors << 6, in LDS.
+__device__ __forceinline__ void sim_seg_table(const uint32_t *cv, uint32_t base, uint32_t end, uint16_t *tab) {
+    for (uint32_t p = kSegUnits; p-- > 0u;) {
+        if (base + p >= end) {
+            tab[p] = (uint16_t)p;   // no chain starts here
+            continue;
+        }
+        const uint32_t q = p + (cv[base + p] >> 4);
+        tab[p] = (uint16_t)(q >= kSegUnits || base + q >= end ? q | (1u << 6) : tab[q] + (1u << 6));
+    }
+}
+
+// Follows the lanes' tables from entry offset e into lane 0's tuples; with
+// `in`, notes each lane's entry offset and first selector (or 0xFFFF: the
+// chain does not reach it).  Returns the tuple where the chain leaves the
+// chunk (relative to u0) and adds its selectors to *sel.
+__device__ __forceinline__ uint32_t sim_chain(const uint16_t (*tab)[kSegUnits], uint32_t e, uint32_t nu, uint32_t &sel,
+                                              uint32_t *in) {
+    uint32_t l = 0;
+    for (;;) {
+        const uint32_t j = kSegUnits * l + e;
+        if (j >= nu) return j;
+        if (in) in[l] = e | (sel << 5);
+        const uint32_t v = tab[l][e], x = v & 63u;
+        sel += v >> 6;
+        if (x < kSegUnits || l == 63u) return kSegUnits * l + x;
+        l++;
+        e = x - kSegUnits;
+    }
+}
+
+// Step A, one wave per chunk: for every entry offset e < 32, the chain
+// entering the chunk at tuple u0 + e; summary: exit offset | selectors << 5.
 __global__ __launch_bounds__(kThreads) void k_sim_chainA(EArgs a) {
-    const uint32_t id = blockIdx.x * kThreads + threadIdx.x;
-    if (id >= a.nchunks * 32u) return;
-    const uint32_t ch = id >> 5, e = id & 31u;
+    __shared__ uint16_t s_tab[kThreads / 64u][64][kSegUnits];
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t ch = blockIdx.x * (kThreads / 64u) + wave;
+    if (ch >= a.nchunks) return;
     const EChunk C = a.chunks[ch];
     const EList L = a.lists[C.list];
-    const uint32_t *cv = a.tw + L.t0;
-    const uint32_t end = C.u0 + C.nu;
-    uint32_t j = C.u0 + e, cnt = 0;
-    while (j < end) {
-        j += cv[j] >> 4;
-        cnt++;
+    sim_seg_table(a.tw + L.t0 + C.u0, kSegUnits * lane, C.nu, s_tab[wave][lane]);
+    wave_lds_fence();
+    if (lane < kSegUnits) {
+        uint32_t sel = 0;
+        const uint32_t j = sim_chain(s_tab[wave], lane, C.nu, sel, nullptr);
+        a.chs[ch * 32u + lane] = (j - C.nu) | (sel << 5);
     }
-    a.chs[ch * 32u + e] = (j - end) | (cnt << 5);
 }
 
 // Step B, one lane per list: entry offset and first selector of every
@@ -269,19 +378,34 @@ __global__ __launch_bounds__(kThreads) void k_sim_listB(EArgs a) {
     a.sizes[3u * i + 2u] = 0u;
 }
 
-// Step C, one lane per chunk: every tuple's selector index << 10 | selector
-// << 5 | its place in the selector; selectors to the control area.
+// Step C, one wave per chunk: every tuple's selector index << 10 |
+// selector << 5 | its place in the selector; selectors to the control
+// area.  Lane 0 follows the tables from the chunk's entry; each lane then
+// walks the selectors that start in its tuples.
 __global__ __launch_bounds__(kThreads) void k_sim_chainC(EArgs a) {
-    const uint32_t ch = blockIdx.x * kThreads + threadIdx.x;
+    __shared__ uint16_t s_tab[kThreads / 64u][64][kSegUnits];
+    __shared__ uint32_t s_in[kThreads / 64u][64];
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t ch = blockIdx.x * (kThreads / 64u) + wave;
     if (ch >= a.nchunks) return;
     const EChunk C = a.chunks[ch];
     const EList L = a.lists[C.list];
-    const uint32_t *cv = a.tw + L.t0;
-    uint32_t *info = a.tw2 + L.t0;
+    const uint32_t *cv = a.tw + L.t0 + C.u0;
+    sim_seg_table(cv, kSegUnits * lane, C.nu, s_tab[wave][lane]);
+    s_in[wave][lane] = 0xFFFFFFFFu;
+    wave_lds_fence();
+    if (lane == 0) {
+        uint32_t sel = a.chb[2u * ch + 1u];
+        (void)sim_chain(s_tab[wave], a.chb[2u * ch], C.nu, sel, s_in[wave]);
+    }
+    wave_lds_fence();
+    const uint32_t in = s_in[wave][lane];
+    if (in == 0xFFFFFFFFu) return;
+    uint32_t *info = a.tw2 + L.t0 + C.u0;
     gu32 *ctrl = (gu32 *)(a.out + L.out_off + 4u);
-    const uint32_t end = C.u0 + C.nu;
-    uint32_t j = C.u0 + a.chb[2u * ch], s = a.chb[2u * ch + 1u];
-    while (j < end) {
+    const uint32_t lim = min(C.nu, kSegUnits * (lane + 1u));
+    uint32_t j = kSegUnits * lane + (in & 31u), s = in >> 5;
+    while (j < lim) {
         const uint32_t v = cv[j], sel = v & 15u, cover = v >> 4;
         atomicOr((uint32_t *)&ctrl[s >> 3], sel << (4u * (s & 7u)));
         for (uint32_t jj = 0; jj < cover; jj++) info[j + jj] = (s << 10) | (sel << 5) | jj;
@@ -350,24 +474,79 @@ __global__ __launch_bounds__(kThreads) void k_afor_dpA(EArgs a) {
     for (int i = 0; i < 4; i++) a.mat[20u * ch + 4u * i + j] = v[i];
 }
 
-// Step B of the costs, one lane per list, from its last chunk back: the
-// true costs at every chunk's end.
+// Min-plus sum with an unreachable cost absorbing.
+__device__ __forceinline__ uint64_t mp_add(uint64_t x, uint64_t y) { return x >= kInf || y >= kInf ? kInf : x + y; }
+
+// Step B of the costs, one wave per list: the true costs at every chunk's
+// end.  The end costs of chunk c are M_{c+1} (x) ... (x) M_last applied to
+// the costs past the last octet (min-plus products of the chunks'
+// matrices); lane l takes chunk l of a group of 64, a reverse scan forms
+// its suffix product within the group, and the groups run from the last
+// back, each starting from the costs at its end.
 __global__ __launch_bounds__(kThreads) void k_afor_dpB(EArgs a) {
-    const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t i = blockIdx.x * (kThreads / 64u) + (threadIdx.x >> 6);
     if (i >= a.nlists) return;
     const EList L = a.lists[i];
-    uint64_t v[4] = {0, kInf, kInf, kInf};   // past the last octet
-    for (uint32_t c = L.c0 + L.nch; c-- > L.c0;) {
-        uint64_t *m = a.mat + 20u * c;
-        for (int r = 0; r < 4; r++) m[16 + r] = v[r];
-        uint64_t w[4];
-        for (int r = 0; r < 4; r++) {
-            uint64_t best = kInf;
-            for (int q = 0; q < 4; q++)
-                if (m[4 * r + q] < kInf && v[q] < kInf) best = min(best, m[4 * r + q] + v[q]);
-            w[r] = best;
+    uint64_t e[4] = {0, kInf, kInf, kInf};   // costs at the group's end (past the last octet at first)
+    for (uint32_t gend = L.nch; gend > 0u;) {
+        const uint32_t gbeg = gend > 64u ? gend - 64u : 0u;
+        const bool valid = gbeg + lane < gend;
+        const uint64_t *m = a.mat + 20ull * (L.c0 + gbeg + lane);
+        uint64_t P[16];
+#pragma unroll
+        for (uint32_t x = 0; x < 16u; x++) P[x] = valid ? m[x] : (x % 5u == 0u ? 0ull : kInf);
+        // P_l = M_l (x) M_{l+1} (x) ... over the group (identity past its end)
+#pragma unroll
+        for (uint32_t d = 1; d < 64u; d <<= 1) {
+            uint64_t Q[16];
+#pragma unroll
+            for (uint32_t x = 0; x < 16u; x++) {
+                const uint64_t q = __shfl(P[x], (int)min(lane + d, 63u));
+                Q[x] = lane + d < 64u ? q : (x % 5u == 0u ? 0ull : kInf);
+            }
+            uint64_t R[16];
+#pragma unroll
+            for (uint32_t r = 0; r < 4u; r++)
+#pragma unroll
+                for (uint32_t q = 0; q < 4u; q++) {
+                    uint64_t best = kInf;
+#pragma unroll
+                    for (uint32_t t = 0; t < 4u; t++) best = min(best, mp_add(P[4u * r + t], Q[4u * t + q]));
+                    R[4u * r + q] = best;
+                }
+#pragma unroll
+            for (uint32_t x = 0; x < 16u; x++) P[x] = R[x];
         }
-        for (int r = 0; r < 4; r++) v[r] = w[r];
+        // chunk l's end costs: the product of the chunks after it, applied to e
+        uint64_t end[4];
+#pragma unroll
+        for (uint32_t r = 0; r < 4u; r++) {
+            uint64_t best = kInf;
+#pragma unroll
+            for (uint32_t q = 0; q < 4u; q++) {
+                const uint64_t n = __shfl(P[4u * r + q], (int)min(lane + 1u, 63u));
+                best = min(best, mp_add(lane < 63u ? n : (r == q ? 0ull : kInf), e[q]));
+            }
+            end[r] = best;
+        }
+        if (valid) {
+            uint64_t *me = a.mat + 20ull * (L.c0 + gbeg + lane) + 16u;
+#pragma unroll
+            for (uint32_t r = 0; r < 4u; r++) me[r] = end[r];
+        }
+        // the costs at the previous group's end: the whole group applied to e
+        uint64_t ne[4];
+#pragma unroll
+        for (uint32_t r = 0; r < 4u; r++) {
+            uint64_t best = kInf;
+#pragma unroll
+            for (uint32_t q = 0; q < 4u; q++) best = min(best, mp_add(__shfl(P[4u * r + q], 0), e[q]));
+            ne[r] = best;
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < 4u; r++) e[r] = ne[r];
+        gend = gbeg;
     }
 }
 
@@ -888,6 +1067,8 @@ gc_status dalloc(T **p, size_t n, std::vector<void *> &keep) {
 }
 
 unsigned grid(uint64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+// one wave per item
+unsigned wave_grid(uint64_t n) { return (unsigned)((n + kThreads / 64 - 1) / (kThreads / 64)); }
 
 #define ENC_OK(x)                                \
     do {                                         \
@@ -978,16 +1159,15 @@ extern "C" gc_status gc_encode_lists_gpu(const uint32_t *d_in, const uint64_t *h
         if ((rc = dalloc(&a.chs, 16ull * nch, keep)) || (rc = dalloc(&a.chb, 2ull * nch, keep)) ||
             (rc = dalloc(&a.tw, ntup, keep)) || (rc = dalloc(&a.tw2, ntup, keep)))
             goto done;
-        const uint32_t ns = a.ld == GC_LD_IU ? 8u : 1u;
-        if (nch) hipLaunchKernelGGL(k_gsc_chunkA, dim3(grid((uint64_t)nch * ns)), dim3(kThreads), 0, s, a);
+        if (nch) hipLaunchKernelGGL(k_gsc_chunkA, dim3(wave_grid(nch)), dim3(kThreads), 0, s, a);
         hipLaunchKernelGGL(k_gsc_listB, dim3(grid(nlists)), dim3(kThreads), 0, s, a);
-        if (nch) hipLaunchKernelGGL(k_gsc_chunkC, dim3(grid(nch)), dim3(kThreads), 0, s, a);
+        if (nch) hipLaunchKernelGGL(k_gsc_chunkC, dim3(wave_grid(nch)), dim3(kThreads), 0, s, a);
     } else if (codec == GC_SIMPLE) {
         if ((rc = dalloc(&a.chs, 32ull * nch, keep)) || (rc = dalloc(&a.chb, 2ull * nch, keep)) ||
             (rc = dalloc(&a.tw, ntup, keep)) || (rc = dalloc(&a.tw2, ntup, keep)))
             goto done;
         if (ntup) hipLaunchKernelGGL(k_sim_cover, dim3(grid(ntup)), dim3(kThreads), 0, s, a);
-        if (nch) hipLaunchKernelGGL(k_sim_chainA, dim3(grid(32ull * nch)), dim3(kThreads), 0, s, a);
+        if (nch) hipLaunchKernelGGL(k_sim_chainA, dim3(wave_grid(nch)), dim3(kThreads), 0, s, a);
         hipLaunchKernelGGL(k_sim_listB, dim3(grid(nlists)), dim3(kThreads), 0, s, a);
     } else if (codec == GC_AFOR) {
         if ((rc = dalloc(&a.ob, ntup / 8u, keep)) || (rc = dalloc(&a.och, ntup / 8u, keep)) ||
@@ -996,7 +1176,7 @@ extern "C" gc_status gc_encode_lists_gpu(const uint32_t *d_in, const uint64_t *h
             goto done;
         if (ntup) hipLaunchKernelGGL(k_afor_omax, dim3(grid(ntup / 8u)), dim3(kThreads), 0, s, a);
         if (nch) hipLaunchKernelGGL(k_afor_dpA, dim3(grid(4ull * nch)), dim3(kThreads), 0, s, a);
-        hipLaunchKernelGGL(k_afor_dpB, dim3(grid(nlists)), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL(k_afor_dpB, dim3(wave_grid(nlists)), dim3(kThreads), 0, s, a);
         if (nch) hipLaunchKernelGGL(k_afor_dpC, dim3(grid(nch)), dim3(kThreads), 0, s, a);
         if (nch) hipLaunchKernelGGL(k_afor_chainA, dim3(grid(4ull * nch)), dim3(kThreads), 0, s, a);
         hipLaunchKernelGGL(k_afor_chainB, dim3(grid(nlists)), dim3(kThreads), 0, s, a);
@@ -1005,7 +1185,7 @@ extern "C" gc_status gc_encode_lists_gpu(const uint32_t *d_in, const uint64_t *h
             (rc = dalloc(&a.xbit, ntup * k / 32u + 1u, keep)))
             goto done;
         if (nblocks) hipLaunchKernelGGL(k_pfd_blocks, dim3((nblocks + kThreads / 32 - 1) / (kThreads / 32)), dim3(kThreads), 0, s, a);
-        hipLaunchKernelGGL(k_pfd_listB, dim3((nlists + kThreads / 64 - 1) / (kThreads / 64)), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL(k_pfd_listB, dim3(wave_grid(nlists)), dim3(kThreads), 0, s, a);
     }
     ENC_OK(hipGetLastError());
     ENC_OK(hipMemcpyAsync(sizes.data(), a.sizes, sizes.size() * 4, hipMemcpyDeviceToHost, s));
@@ -1029,7 +1209,7 @@ extern "C" gc_status gc_encode_lists_gpu(const uint32_t *d_in, const uint64_t *h
         hipLaunchKernelGGL(k_fill, dim3(grid(total)), dim3(kThreads), 0, s, a, w0h,
                            codec == GC_SCHEME && p->ld != GC_LD_BINARY ? 1 : 0);
     }
-    if (codec == GC_SIMPLE && nch) hipLaunchKernelGGL(k_sim_chainC, dim3(grid(nch)), dim3(kThreads), 0, s, a);
+    if (codec == GC_SIMPLE && nch) hipLaunchKernelGGL(k_sim_chainC, dim3(wave_grid(nch)), dim3(kThreads), 0, s, a);
     if (codec == GC_AFOR && nch) hipLaunchKernelGGL(k_afor_chainC, dim3(grid(nch)), dim3(kThreads), 0, s, a);
     if (codec == GC_PFD) {
         if (nblocks) hipLaunchKernelGGL(k_pfd_emit, dim3((nblocks + kThreads / 32 - 1) / (kThreads / 32)), dim3(kThreads), 0, s, a);
