@@ -118,10 +118,12 @@ gc_status gc_encode_lists(const uint32_t *h_in, const uint64_t *in_offs, size_t 
  * Section 6.2 for Group-PFD), back to back into d_out (device memory,
  * capacity out_cap_words); h_out_offs[i] (host memory, nlists + 1 entries)
  * receives stream i's word offset and h_out_offs[nlists] the total.
- * Index build, not the decode path: it allocates device scratch for the
- * call (about 12 bytes per integer at most), reads the stream sizes back to
- * the host, and returns once the streams are written (it synchronises
- * hip_stream).  GC_EINVAL for bad parameters, GC_ENOSPC if the streams do
+ * Index build, not the decode path: it reads the stream sizes back to the
+ * host and returns once the streams are written (it synchronises
+ * hip_stream).  Its device scratch (about 12 bytes per integer at most) and
+ * pinned host staging are kept per device, for later calls, until the
+ * process ends, and grow when a call needs more; calls on one device run
+ * one at a time.  GC_EINVAL for bad parameters, GC_ENOSPC if the streams do
  * not fit (h_out_offs then holds their sizes), GC_ENOMEM if the scratch
  * does not fit.                                                            */
 gc_status gc_encode_lists_gpu(const uint32_t *d_in, const uint64_t *h_in_offs, size_t nlists,

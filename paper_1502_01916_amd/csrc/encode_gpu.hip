@@ -35,6 +35,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "gc.h"
@@ -88,6 +89,8 @@ struct EArgs {
     uint8_t *ob;            // per octet bytes (Group-AFOR: omax, then frame widths)
     uint8_t *och;           // Group-AFOR: frame choice per octet
     uint64_t *mat;          // Group-AFOR: chunk matrices (16) and end costs (4)
+    const uint32_t *tl;     // per 256 tuples: the list of the first (tiles + 1 entries)
+    const uint32_t *wl;     // per 256 stream words: the list of the first (tiles + 1 entries)
     uint32_t *blk;          // Group-PFD: per block desc, exception words, row base, exception base
     uint32_t *slot;         // Group-PFD: slot of every integer
     uint32_t *xbit;         // Group-PFD: exception bitmap of every integer
@@ -109,9 +112,14 @@ __device__ __forceinline__ void wave_lds_fence() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// List of global tuple g (binary search over the lists' first tuples).
+constexpr uint32_t kTileShift = 8;   // list tables per 256 tuples or stream words
+
+// List of global tuple g: a binary search over the lists' first tuples,
+// between those of g's 256-tuple tile and the next.
 __device__ __forceinline__ uint32_t list_of_tuple(const EArgs &a, uint64_t g) {
-    uint32_t lo = 0, hi = a.nlists;   // invariant: lists[lo].t0 <= g < lists[hi].t0 (hi: end)
+    const uint64_t tile = g >> kTileShift;
+    // invariant: lists[lo].t0 <= g < lists[hi].t0 (hi: end)
+    uint32_t lo = a.tl[tile], hi = min(a.tl[tile + 1u] + 1u, a.nlists);
     while (hi - lo > 1u) {
         const uint32_t mid = (lo + hi) >> 1;
         if (a.lists[mid].t0 <= g) lo = mid;
@@ -1030,7 +1038,7 @@ __global__ __launch_bounds__(kThreads) void k_pfd_emit(EArgs a) {
 __global__ __launch_bounds__(kThreads) void k_fill(EArgs a, uint32_t w0h, int unary) {
     const uint64_t w = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     if (w >= a.out_words) return;
-    uint32_t lo = 0, hi = a.nlists;
+    uint32_t lo = a.wl[w >> kTileShift], hi = min(a.wl[(w >> kTileShift) + 1u] + 1u, a.nlists);
     while (hi - lo > 1u) {
         const uint32_t mid = (lo + hi) >> 1;
         if (a.lists[mid].out_off <= w) lo = mid;
@@ -1054,15 +1062,52 @@ using namespace gcenc;
 
 namespace {
 
+// Device scratch and pinned host staging, kept per device from one call to
+// the next and grown when a call needs more; a call holds its device's
+// lock throughout (it returns with its stream synchronised).
+struct EncCache {
+    std::mutex m;
+    char *dev = nullptr, *host = nullptr;
+    size_t dev_cap = 0, host_cap = 0;
+};
+constexpr int kMaxDevices = 64;
+EncCache g_cache[kMaxDevices];
+
+constexpr size_t align256(size_t n) { return (n + 255u) & ~(size_t)255u; }
+
+// Carves the call's buffers out of a cached area in order.
+struct Bump {
+    char *base;
+    size_t cap, used;
+    template <typename T>
+    T *take(size_t n) {
+        const size_t bytes = align256(std::max<size_t>(n, 1) * sizeof(T));
+        if (used + bytes > cap) return nullptr;
+        T *p = reinterpret_cast<T *>(base + used);
+        used += bytes;
+        return p;
+    }
+};
+
 template <typename T>
-gc_status dalloc(T **p, size_t n, std::vector<void *> &keep) {
-    *p = nullptr;
-    if (!n) n = 1;
-    if (hipMalloc((void **)p, n * sizeof(T)) != hipSuccess) {
+gc_status dalloc(T **p, size_t n, Bump &b) {
+    *p = b.take<T>(n);
+    return *p ? GC_OK : GC_ENOMEM;
+}
+
+// Grows a cached area to at least `need` bytes (its old contents are not kept).
+gc_status grow(char **area, size_t *cap, size_t need, bool host) {
+    if (need <= *cap) return GC_OK;
+    if (*area) (void)(host ? hipHostFree(*area) : hipFree(*area));
+    *area = nullptr;
+    *cap = 0;
+    void *q = nullptr;
+    if ((host ? hipHostMalloc(&q, need, hipHostMallocDefault) : hipMalloc(&q, need)) != hipSuccess) {
         (void)hipGetLastError();
         return GC_ENOMEM;
     }
-    keep.push_back((void *)*p);
+    *area = static_cast<char *>(q);
+    *cap = need;
     return GC_OK;
 }
 
@@ -1123,22 +1168,77 @@ extern "C" gc_status gc_encode_lists_gpu(const uint32_t *d_in, const uint64_t *h
         ntup += e.M;
     }
     if (ntup * k > (1ull << 34)) return GC_EINVAL;
+    // per 256 tuples, the list of the first (the last list with t0 at or
+    // before it), and one entry past the last tile
+    auto tile_lists = [&](uint64_t units, bool words) {
+        std::vector<uint32_t> t((size_t)((units + (1u << kTileShift) - 1) >> kTileShift) + 1u);
+        size_t i = 0;
+        for (size_t x = 0; x < t.size(); x++) {
+            const uint64_t at = (uint64_t)x << kTileShift;
+            while (i + 1 < nlists && (words ? L[i + 1].out_off : L[i + 1].t0) <= at) i++;
+            t[x] = (uint32_t)i;
+        }
+        return t;
+    };
+    const std::vector<uint32_t> TL = tile_lists(ntup, false);
+    std::vector<uint32_t> WL;
+    const uint32_t nch = (uint32_t)CH.size();
+    // the stream-word tile table, sized for streams of up to twice the
+    // input words (a larger one takes an allocation of its own)
+    const size_t nwl_guess = (size_t)((2u * ntup * k + 16u * nlists) >> kTileShift) + 2u;
+    // device scratch in allocation order below, and host staging
+    size_t need = align256(nlists * sizeof(EList)) + align256(std::max<size_t>(nch, 1) * sizeof(EChunk)) +
+                  align256(TL.size() * 4) + align256(std::max<uint64_t>(ntup, 1)) + align256(12 * nlists) +
+                  align256(nwl_guess * 4);
+    if (codec == GC_SCHEME || codec == GC_SIMPLE)
+        need += align256((codec == GC_SCHEME ? 64ull : 128ull) * std::max(nch, 1u)) + align256(8ull * std::max(nch, 1u)) +
+                2 * align256(4 * std::max<uint64_t>(ntup, 1));
+    else if (codec == GC_AFOR)
+        need += 2 * align256(std::max<uint64_t>(ntup / 8u, 1)) + align256(160ull * std::max(nch, 1u)) +
+                align256(48ull * std::max(nch, 1u)) + align256(12ull * std::max(nch, 1u)) +
+                align256(4 * std::max<uint64_t>(ntup / 8u, 1));
+    else
+        need += align256(16ull * std::max(nblocks, 1u)) + align256(4 * std::max<uint64_t>(ntup * k, 1)) +
+                align256(4 * (ntup * k / 32u + 1u));
+    const size_t hneed = align256(nlists * sizeof(EList)) + align256(std::max<size_t>(nch, 1) * sizeof(EChunk)) +
+                         align256(TL.size() * 4) + align256(12 * nlists) + align256(nwl_guess * 4);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return GC_EDEVICE;
+    }
+    EncCache &cache = g_cache[dev];
+    std::lock_guard<std::mutex> lock(cache.m);
     const hipStream_t s = (hipStream_t)hip_stream;
-    std::vector<void *> keep;
     gc_status rc = GC_OK;
+    if ((rc = grow(&cache.dev, &cache.dev_cap, need, false)) || (rc = grow(&cache.host, &cache.host_cap, hneed, true)))
+        return rc;
+    Bump b{cache.dev, cache.dev_cap, 0};
+    Bump hb{cache.host, cache.host_cap, 0};
+    EList *h_lists = hb.take<EList>(nlists);
+    EChunk *h_chunks = hb.take<EChunk>(nch);
+    uint32_t *h_tl = hb.take<uint32_t>(TL.size());
+    uint32_t *h_sizes = hb.take<uint32_t>(3 * nlists);
+    uint32_t *h_wl = hb.take<uint32_t>(nwl_guess);
+    void *wl_own = nullptr;   // the stream-word table, if larger than the guess
     EArgs a;
     std::memset(&a, 0, sizeof(a));
-    std::vector<uint32_t> sizes(3 * nlists);
     uint64_t total = 0;
     EList *d_lists = nullptr;
     EChunk *d_chunks = nullptr;
-    const uint32_t nch = (uint32_t)CH.size();
-    if ((rc = dalloc(&d_lists, nlists, keep)) || (rc = dalloc(&d_chunks, nch, keep))) goto done;
-    ENC_OK(hipMemcpyAsync(d_lists, L.data(), nlists * sizeof(EList), hipMemcpyHostToDevice, s));
-    if (nch) ENC_OK(hipMemcpyAsync(d_chunks, CH.data(), nch * sizeof(EChunk), hipMemcpyHostToDevice, s));
+    uint32_t *d_tl = nullptr, *d_wl = nullptr;
+    std::memcpy(h_lists, L.data(), nlists * sizeof(EList));
+    if (nch) std::memcpy(h_chunks, CH.data(), nch * sizeof(EChunk));
+    std::memcpy(h_tl, TL.data(), TL.size() * 4);
+    if ((rc = dalloc(&d_lists, nlists, b)) || (rc = dalloc(&d_chunks, nch, b)) || (rc = dalloc(&d_tl, TL.size(), b)))
+        goto done;
+    ENC_OK(hipMemcpyAsync(d_lists, h_lists, nlists * sizeof(EList), hipMemcpyHostToDevice, s));
+    ENC_OK(hipMemcpyAsync(d_tl, h_tl, TL.size() * 4, hipMemcpyHostToDevice, s));
+    if (nch) ENC_OK(hipMemcpyAsync(d_chunks, h_chunks, nch * sizeof(EChunk), hipMemcpyHostToDevice, s));
     a.in = d_in;
     a.lists = d_lists;
     a.chunks = d_chunks;
+    a.tl = d_tl;
     a.nlists = (uint32_t)nlists;
     a.nchunks = nch;
     a.ntup = ntup;
@@ -1152,27 +1252,28 @@ extern "C" gc_status gc_encode_lists_gpu(const uint32_t *d_in, const uint64_t *h
     a.zd = p->zeta_den;
     a.nblocks = nblocks;
     a.out = d_out;
-    if ((rc = dalloc(&a.W, ntup, keep)) || (rc = dalloc(&a.sizes, 3 * nlists, keep))) goto done;
+    if ((rc = dalloc(&a.W, ntup, b)) || (rc = dalloc(&a.sizes, 3 * nlists, b)) || (rc = dalloc(&d_wl, nwl_guess, b)))
+        goto done;
     if (ntup) hipLaunchKernelGGL(k_widths, dim3(grid(ntup)), dim3(kThreads), 0, s, a);
     // sizing
     if (codec == GC_SCHEME) {
-        if ((rc = dalloc(&a.chs, 16ull * nch, keep)) || (rc = dalloc(&a.chb, 2ull * nch, keep)) ||
-            (rc = dalloc(&a.tw, ntup, keep)) || (rc = dalloc(&a.tw2, ntup, keep)))
+        if ((rc = dalloc(&a.chs, 16ull * nch, b)) || (rc = dalloc(&a.chb, 2ull * nch, b)) ||
+            (rc = dalloc(&a.tw, ntup, b)) || (rc = dalloc(&a.tw2, ntup, b)))
             goto done;
         if (nch) hipLaunchKernelGGL(k_gsc_chunkA, dim3(wave_grid(nch)), dim3(kThreads), 0, s, a);
         hipLaunchKernelGGL(k_gsc_listB, dim3(grid(nlists)), dim3(kThreads), 0, s, a);
         if (nch) hipLaunchKernelGGL(k_gsc_chunkC, dim3(wave_grid(nch)), dim3(kThreads), 0, s, a);
     } else if (codec == GC_SIMPLE) {
-        if ((rc = dalloc(&a.chs, 32ull * nch, keep)) || (rc = dalloc(&a.chb, 2ull * nch, keep)) ||
-            (rc = dalloc(&a.tw, ntup, keep)) || (rc = dalloc(&a.tw2, ntup, keep)))
+        if ((rc = dalloc(&a.chs, 32ull * nch, b)) || (rc = dalloc(&a.chb, 2ull * nch, b)) ||
+            (rc = dalloc(&a.tw, ntup, b)) || (rc = dalloc(&a.tw2, ntup, b)))
             goto done;
         if (ntup) hipLaunchKernelGGL(k_sim_cover, dim3(grid(ntup)), dim3(kThreads), 0, s, a);
         if (nch) hipLaunchKernelGGL(k_sim_chainA, dim3(wave_grid(nch)), dim3(kThreads), 0, s, a);
         hipLaunchKernelGGL(k_sim_listB, dim3(grid(nlists)), dim3(kThreads), 0, s, a);
     } else if (codec == GC_AFOR) {
-        if ((rc = dalloc(&a.ob, ntup / 8u, keep)) || (rc = dalloc(&a.och, ntup / 8u, keep)) ||
-            (rc = dalloc(&a.mat, 20ull * nch, keep)) || (rc = dalloc(&a.chs, 12ull * nch, keep)) ||
-            (rc = dalloc(&a.chb, 3ull * nch, keep)) || (rc = dalloc(&a.tw, ntup / 8u, keep)))
+        if ((rc = dalloc(&a.ob, ntup / 8u, b)) || (rc = dalloc(&a.och, ntup / 8u, b)) ||
+            (rc = dalloc(&a.mat, 20ull * nch, b)) || (rc = dalloc(&a.chs, 12ull * nch, b)) ||
+            (rc = dalloc(&a.chb, 3ull * nch, b)) || (rc = dalloc(&a.tw, ntup / 8u, b)))
             goto done;
         if (ntup) hipLaunchKernelGGL(k_afor_omax, dim3(grid(ntup / 8u)), dim3(kThreads), 0, s, a);
         if (nch) hipLaunchKernelGGL(k_afor_dpA, dim3(grid(4ull * nch)), dim3(kThreads), 0, s, a);
@@ -1181,20 +1282,20 @@ extern "C" gc_status gc_encode_lists_gpu(const uint32_t *d_in, const uint64_t *h
         if (nch) hipLaunchKernelGGL(k_afor_chainA, dim3(grid(4ull * nch)), dim3(kThreads), 0, s, a);
         hipLaunchKernelGGL(k_afor_chainB, dim3(grid(nlists)), dim3(kThreads), 0, s, a);
     } else {
-        if ((rc = dalloc(&a.blk, 4ull * nblocks, keep)) || (rc = dalloc(&a.slot, ntup * k, keep)) ||
-            (rc = dalloc(&a.xbit, ntup * k / 32u + 1u, keep)))
+        if ((rc = dalloc(&a.blk, 4ull * nblocks, b)) || (rc = dalloc(&a.slot, ntup * k, b)) ||
+            (rc = dalloc(&a.xbit, ntup * k / 32u + 1u, b)))
             goto done;
         if (nblocks) hipLaunchKernelGGL(k_pfd_blocks, dim3((nblocks + kThreads / 32 - 1) / (kThreads / 32)), dim3(kThreads), 0, s, a);
         hipLaunchKernelGGL(k_pfd_listB, dim3(wave_grid(nlists)), dim3(kThreads), 0, s, a);
     }
     ENC_OK(hipGetLastError());
-    ENC_OK(hipMemcpyAsync(sizes.data(), a.sizes, sizes.size() * 4, hipMemcpyDeviceToHost, s));
+    ENC_OK(hipMemcpyAsync(h_sizes, a.sizes, 12 * nlists, hipMemcpyDeviceToHost, s));
     ENC_OK(hipStreamSynchronize(s));
     for (size_t i = 0; i < nlists; i++) {
         L[i].out_off = total;
         h_out_offs[i] = total;
-        const uint64_t e4 = ((uint64_t)sizes[3 * i + 2] + 3u) / 4u * 4u;
-        total += 4ull + sizes[3 * i] + sizes[3 * i + 1] + e4;
+        const uint64_t e4 = ((uint64_t)h_sizes[3 * i + 2] + 3u) / 4u * 4u;
+        total += 4ull + h_sizes[3 * i] + h_sizes[3 * i + 1] + e4;
     }
     h_out_offs[nlists] = total;
     if (total > out_cap_words) {
@@ -1202,7 +1303,22 @@ extern "C" gc_status gc_encode_lists_gpu(const uint32_t *d_in, const uint64_t *h
         goto done;
     }
     a.out_words = total;
-    ENC_OK(hipMemcpyAsync(d_lists, L.data(), nlists * sizeof(EList), hipMemcpyHostToDevice, s));
+    WL = tile_lists(total, true);
+    if (WL.size() <= nwl_guess) {
+        std::memcpy(h_wl, WL.data(), WL.size() * 4);
+        ENC_OK(hipMemcpyAsync(d_wl, h_wl, WL.size() * 4, hipMemcpyHostToDevice, s));
+    } else {
+        if (hipMalloc(&wl_own, WL.size() * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = GC_ENOMEM;
+            goto done;
+        }
+        d_wl = static_cast<uint32_t *>(wl_own);
+        ENC_OK(hipMemcpyAsync(d_wl, WL.data(), WL.size() * 4, hipMemcpyHostToDevice, s));
+    }
+    a.wl = d_wl;
+    std::memcpy(h_lists, L.data(), nlists * sizeof(EList));
+    ENC_OK(hipMemcpyAsync(d_lists, h_lists, nlists * sizeof(EList), hipMemcpyHostToDevice, s));
     {
         const uint32_t w0h = header_word0((int)codec, (int)k, codec == GC_SCHEME ? p->cg : 1,
                                           codec == GC_SCHEME ? p->ld : 0, a.delta, codec == GC_PFD ? p->pfd_pos : 0);
@@ -1221,6 +1337,6 @@ extern "C" gc_status gc_encode_lists_gpu(const uint32_t *d_in, const uint64_t *h
     ENC_OK(hipStreamSynchronize(s));
 done:
     (void)hipStreamSynchronize(s);
-    for (void *q : keep) (void)hipFree(q);
+    if (wl_own) (void)hipFree(wl_own);
     return rc;
 }
