@@ -468,29 +468,94 @@ __device__ __forceinline__ void afor_dp(const uint8_t *om, uint32_t oct, uint32_
     v[3] = c4;
 }
 
-// Step A of the costs, one lane per (chunk, column j < 4): the chunk's
-// min-plus matrix column j (start costs from end costs e_j).
-__global__ __launch_bounds__(kThreads) void k_afor_dpA(EArgs a) {
-    const uint32_t id = blockIdx.x * kThreads + threadIdx.x;
-    if (id >= a.nchunks * 4u) return;
-    const uint32_t ch = id >> 2, j = id & 3u;
-    const EChunk C = a.chunks[ch];
-    const EList L = a.lists[C.list];
-    uint64_t v[4] = {kInf, kInf, kInf, kInf};
-    v[j] = 0;
-    afor_dp(a.ob + L.t0 / 8u, L.M / 8u, C.u0, C.u0 + C.nu, a.k, v, nullptr);
-    for (int i = 0; i < 4; i++) a.mat[20u * ch + 4u * i + j] = v[i];
-}
-
 // Min-plus sum with an unreachable cost absorbing.
 __device__ __forceinline__ uint64_t mp_add(uint64_t x, uint64_t y) { return x >= kInf || y >= kInf ? kInf : x + y; }
 
+__device__ __forceinline__ uint64_t mp_ident(uint32_t x) { return x % 5u == 0u ? 0ull : kInf; }
+
+// P_l = M_l (x) M_{l+1} (x) ... (x) M_63 over the wave's lanes (min-plus
+// products of 4 x 4 matrices, row-major).
+__device__ __forceinline__ void mp_suffix_scan(uint64_t (&P)[16], uint32_t lane) {
+#pragma unroll
+    for (uint32_t d = 1; d < 64u; d <<= 1) {
+        uint64_t Q[16];
+#pragma unroll
+        for (uint32_t x = 0; x < 16u; x++) {
+            const uint64_t q = __shfl(P[x], (int)min(lane + d, 63u));
+            Q[x] = lane + d < 64u ? q : mp_ident(x);
+        }
+        uint64_t R[16];
+#pragma unroll
+        for (uint32_t r = 0; r < 4u; r++)
+#pragma unroll
+            for (uint32_t q = 0; q < 4u; q++) {
+                uint64_t best = kInf;
+#pragma unroll
+                for (uint32_t t = 0; t < 4u; t++) best = min(best, mp_add(P[4u * r + t], Q[4u * t + q]));
+                R[4u * r + q] = best;
+            }
+#pragma unroll
+        for (uint32_t x = 0; x < 16u; x++) P[x] = R[x];
+    }
+}
+
+// The product of the lanes after this one, applied to e (e itself for
+// lane 63), from the scanned P.
+__device__ __forceinline__ void mp_after(const uint64_t (&P)[16], const uint64_t (&e)[4], uint32_t lane,
+                                         uint64_t (&out)[4]) {
+#pragma unroll
+    for (uint32_t r = 0; r < 4u; r++) {
+        uint64_t best = kInf;
+#pragma unroll
+        for (uint32_t q = 0; q < 4u; q++) {
+            const uint64_t n = __shfl(P[4u * r + q], (int)min(lane + 1u, 63u));
+            best = min(best, mp_add(lane < 63u ? n : mp_ident(4u * r + q), e[q]));
+        }
+        out[r] = best;
+    }
+}
+
+// A chunk's costs on one wave: lane l takes octets [4 l, 4 l + 4) of the
+// chunk; its min-plus matrix (start costs from end costs), column j from
+// the programme run with end state j at cost 0 and the others unreachable.
+constexpr uint32_t kSegOct = 4;   // octets of a chunk per lane
+static_assert(kOctChunk == 64u * kSegOct, "a chunk is 64 lane segments");
+
+__device__ __forceinline__ void afor_seg_matrix(const uint8_t *om, uint32_t oct, uint32_t s0, uint32_t s1, uint32_t k,
+                                                uint64_t (&P)[16]) {
+#pragma unroll
+    for (uint32_t j = 0; j < 4u; j++) {
+        uint64_t v[4] = {kInf, kInf, kInf, kInf};
+        v[j] = 0;
+        afor_dp(om, oct, s0, s1, k, v, nullptr);
+#pragma unroll
+        for (uint32_t i = 0; i < 4u; i++) P[4u * i + j] = v[i];
+    }
+}
+
+// Step A of the costs, one wave per chunk: the chunk's min-plus matrix, the
+// product of its lanes' matrices.
+__global__ __launch_bounds__(kThreads) void k_afor_dpA(EArgs a) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t ch = blockIdx.x * (kThreads / 64u) + (threadIdx.x >> 6);
+    if (ch >= a.nchunks) return;
+    const EChunk C = a.chunks[ch];
+    const EList L = a.lists[C.list];
+    const uint32_t end = C.u0 + C.nu, s0 = min(C.u0 + kSegOct * lane, end), s1 = min(s0 + kSegOct, end);
+    uint64_t P[16];
+    afor_seg_matrix(a.ob + L.t0 / 8u, L.M / 8u, s0, s1, a.k, P);
+    mp_suffix_scan(P, lane);
+    if (lane == 0) {
+#pragma unroll
+        for (uint32_t x = 0; x < 16u; x++) a.mat[20ull * ch + x] = P[x];
+    }
+}
+
 // Step B of the costs, one wave per list: the true costs at every chunk's
 // end.  The end costs of chunk c are M_{c+1} (x) ... (x) M_last applied to
-// the costs past the last octet (min-plus products of the chunks'
-// matrices); lane l takes chunk l of a group of 64, a reverse scan forms
-// its suffix product within the group, and the groups run from the last
-// back, each starting from the costs at its end.
+// the costs past the last octet; lane l takes chunk l of a group of 64, and
+// the groups run from the last back, each starting from the costs at its
+// end.
 __global__ __launch_bounds__(kThreads) void k_afor_dpB(EArgs a) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t i = blockIdx.x * (kThreads / 64u) + (threadIdx.x >> 6);
@@ -503,41 +568,10 @@ __global__ __launch_bounds__(kThreads) void k_afor_dpB(EArgs a) {
         const uint64_t *m = a.mat + 20ull * (L.c0 + gbeg + lane);
         uint64_t P[16];
 #pragma unroll
-        for (uint32_t x = 0; x < 16u; x++) P[x] = valid ? m[x] : (x % 5u == 0u ? 0ull : kInf);
-        // P_l = M_l (x) M_{l+1} (x) ... over the group (identity past its end)
-#pragma unroll
-        for (uint32_t d = 1; d < 64u; d <<= 1) {
-            uint64_t Q[16];
-#pragma unroll
-            for (uint32_t x = 0; x < 16u; x++) {
-                const uint64_t q = __shfl(P[x], (int)min(lane + d, 63u));
-                Q[x] = lane + d < 64u ? q : (x % 5u == 0u ? 0ull : kInf);
-            }
-            uint64_t R[16];
-#pragma unroll
-            for (uint32_t r = 0; r < 4u; r++)
-#pragma unroll
-                for (uint32_t q = 0; q < 4u; q++) {
-                    uint64_t best = kInf;
-#pragma unroll
-                    for (uint32_t t = 0; t < 4u; t++) best = min(best, mp_add(P[4u * r + t], Q[4u * t + q]));
-                    R[4u * r + q] = best;
-                }
-#pragma unroll
-            for (uint32_t x = 0; x < 16u; x++) P[x] = R[x];
-        }
-        // chunk l's end costs: the product of the chunks after it, applied to e
+        for (uint32_t x = 0; x < 16u; x++) P[x] = valid ? m[x] : mp_ident(x);
+        mp_suffix_scan(P, lane);
         uint64_t end[4];
-#pragma unroll
-        for (uint32_t r = 0; r < 4u; r++) {
-            uint64_t best = kInf;
-#pragma unroll
-            for (uint32_t q = 0; q < 4u; q++) {
-                const uint64_t n = __shfl(P[4u * r + q], (int)min(lane + 1u, 63u));
-                best = min(best, mp_add(lane < 63u ? n : (r == q ? 0ull : kInf), e[q]));
-            }
-            end[r] = best;
-        }
+        mp_after(P, e, lane, end);
         if (valid) {
             uint64_t *me = a.mat + 20ull * (L.c0 + gbeg + lane) + 16u;
 #pragma unroll
@@ -558,16 +592,25 @@ __global__ __launch_bounds__(kThreads) void k_afor_dpB(EArgs a) {
     }
 }
 
-// Step C of the costs, one lane per chunk: the choices from the true end
-// costs.
+// Step C of the costs, one wave per chunk: each lane's end costs from the
+// chunk's true end costs and the lanes after it; the lane then runs the
+// programme over its octets and keeps its choices.
 __global__ __launch_bounds__(kThreads) void k_afor_dpC(EArgs a) {
-    const uint32_t ch = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t ch = blockIdx.x * (kThreads / 64u) + (threadIdx.x >> 6);
     if (ch >= a.nchunks) return;
     const EChunk C = a.chunks[ch];
     const EList L = a.lists[C.list];
-    uint64_t v[4];
-    for (int r = 0; r < 4; r++) v[r] = a.mat[20u * ch + 16u + r];
-    afor_dp(a.ob + L.t0 / 8u, L.M / 8u, C.u0, C.u0 + C.nu, a.k, v, a.och + L.t0 / 8u);
+    const uint32_t end = C.u0 + C.nu, s0 = min(C.u0 + kSegOct * lane, end), s1 = min(s0 + kSegOct, end);
+    const uint8_t *om = a.ob + L.t0 / 8u;
+    uint64_t P[16];
+    afor_seg_matrix(om, L.M / 8u, s0, s1, a.k, P);
+    mp_suffix_scan(P, lane);
+    uint64_t e[4], v[4];
+#pragma unroll
+    for (uint32_t r = 0; r < 4u; r++) e[r] = a.mat[20ull * ch + 16u + r];
+    mp_after(P, e, lane, v);
+    afor_dp(om, L.M / 8u, s0, s1, a.k, v, a.och + L.t0 / 8u);
 }
 
 // width of the frame of F tuples from octet o
@@ -577,26 +620,71 @@ __device__ __forceinline__ uint32_t afor_b(const uint8_t *om, uint32_t o, uint32
     return b;
 }
 
-// Step A of the frames, one lane per (chunk, entry octet e < 4): exit
-// octet, frames and data bits of the chain.
+// The frame chain over a chunk on one wave: lane l takes octets
+// [4 l, 4 l + 4) of the chunk, and for every entry offset p < 4 into them
+// finds, by a backward pass, where the chain entered at p leaves (offset x
+// from the lane's first octet, x >= 4 into the next lane's; a chain that
+// reaches the chunk's end stops there), the frames it starts and their data
+// bits: tab[p] = x | frames << 3 | bits << 6, in LDS.
+// Octets before the chunk's entry may already hold the previous chunk's
+// frame widths (step C rewrites them); their entries are never followed, and
+// a value that is no frame size starts no chain.
+__device__ __forceinline__ void afor_seg_table(const uint8_t *om, const uint8_t *cho, uint32_t oct, uint32_t s0,
+                                               uint32_t end, uint32_t *tab) {
+    for (uint32_t p = kSegOct; p-- > 0u;) {
+        const uint32_t o = s0 + p;
+        const uint32_t F = o < end ? cho[o] : 0u;
+        if ((F != 8u && F != 16u && F != 32u) || o + F / 8u > oct) {
+            tab[p] = p;   // no chain starts here
+            continue;
+        }
+        const uint32_t q = p + F / 8u, fb = F * afor_b(om, o, F);
+        tab[p] = q >= kSegOct || s0 + q >= end ? q | (1u << 3) | (fb << 6) : tab[q] + (1u << 3) + (fb << 6);
+    }
+}
+
+// Follows the lanes' tables from entry offset e into lane 0's octets,
+// adding frames and bits; with `in`, notes each lane's entry (e, frames,
+// bits before it; e = 0xFFFFFFFF: the chain does not reach the lane).
+// Returns the octet where the chain leaves the chunk (relative to u0).
+__device__ __forceinline__ uint32_t afor_chain(const uint32_t (*tab)[kSegOct], uint32_t e, uint32_t nu, uint32_t &frames,
+                                               uint32_t &bits, uint32_t (*in)[3]) {
+    uint32_t l = 0;
+    for (;;) {
+        const uint32_t o = kSegOct * l + e;
+        if (o >= nu) return o;
+        if (in) {
+            in[l][0] = e;
+            in[l][1] = frames;
+            in[l][2] = bits;
+        }
+        const uint32_t v = tab[l][e], x = v & 7u;
+        frames += (v >> 3) & 7u;
+        bits += v >> 6;
+        if (x < kSegOct || l == 63u) return kSegOct * l + x;
+        l++;
+        e = x - kSegOct;
+    }
+}
+
+// Step A of the frames, one wave per chunk: for every entry octet e < 4,
+// exit octet, frames and data bits of the chain.
 __global__ __launch_bounds__(kThreads) void k_afor_chainA(EArgs a) {
-    const uint32_t id = blockIdx.x * kThreads + threadIdx.x;
-    if (id >= a.nchunks * 4u) return;
-    const uint32_t ch = id >> 2, e = id & 3u;
+    __shared__ uint32_t s_tab[kThreads / 64u][64][kSegOct];
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t ch = blockIdx.x * (kThreads / 64u) + wave;
+    if (ch >= a.nchunks) return;
     const EChunk C = a.chunks[ch];
     const EList L = a.lists[C.list];
-    const uint8_t *om = a.ob + L.t0 / 8u, *cho = a.och + L.t0 / 8u;
-    const uint32_t end = C.u0 + C.nu;
-    uint32_t o = C.u0 + e, frames = 0, bits = 0;
-    while (o < end) {
-        const uint32_t F = cho[o];
-        bits += F * afor_b(om, o, F);
-        frames++;
-        o += F / 8u;
+    afor_seg_table(a.ob + L.t0 / 8u, a.och + L.t0 / 8u, L.M / 8u, C.u0 + kSegOct * lane, C.u0 + C.nu, s_tab[wave][lane]);
+    wave_lds_fence();
+    if (lane < 4u) {
+        uint32_t frames = 0, bits = 0;
+        const uint32_t o = afor_chain(s_tab[wave], lane, C.nu, frames, bits, nullptr);
+        a.chs[3u * (ch * 4u + lane)] = o - C.nu;
+        a.chs[3u * (ch * 4u + lane) + 1u] = frames;
+        a.chs[3u * (ch * 4u + lane) + 2u] = bits;
     }
-    a.chs[3u * (ch * 4u + e)] = o - end;
-    a.chs[3u * (ch * 4u + e) + 1u] = frames;
-    a.chs[3u * (ch * 4u + e) + 2u] = bits;
 }
 
 // Step B of the frames, one lane per list.
@@ -619,20 +707,35 @@ __global__ __launch_bounds__(kThreads) void k_afor_chainB(EArgs a) {
     a.sizes[3u * i + 2u] = 0u;
 }
 
-// Step C of the frames, one lane per chunk: frame bytes to the control
-// area; every octet's data bit and width (octet words in tw, widths in och).
+// Step C of the frames, one wave per chunk: frame bytes to the control
+// area; every octet's data bit and width (octet words in tw, widths in
+// och).  Lane 0 follows the tables from the chunk's entry; each lane then
+// writes the frames that start in its octets.
 __global__ __launch_bounds__(kThreads) void k_afor_chainC(EArgs a) {
-    const uint32_t ch = blockIdx.x * kThreads + threadIdx.x;
+    __shared__ uint32_t s_tab[kThreads / 64u][64][kSegOct];
+    __shared__ uint32_t s_in[kThreads / 64u][64][3];
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t ch = blockIdx.x * (kThreads / 64u) + wave;
     if (ch >= a.nchunks) return;
     const EChunk C = a.chunks[ch];
     const EList L = a.lists[C.list];
     const uint8_t *om = a.ob + L.t0 / 8u;
     uint8_t *cho = a.och + L.t0 / 8u;
+    const uint32_t s0 = C.u0 + kSegOct * lane, end = C.u0 + C.nu;
+    afor_seg_table(om, cho, L.M / 8u, s0, end, s_tab[wave][lane]);
+    s_in[wave][lane][0] = 0xFFFFFFFFu;
+    wave_lds_fence();
+    if (lane == 0) {
+        uint32_t frames = a.chb[3u * ch + 1u], bits = a.chb[3u * ch + 2u];
+        (void)afor_chain(s_tab[wave], a.chb[3u * ch], C.nu, frames, bits, s_in[wave]);
+    }
+    wave_lds_fence();
+    if (s_in[wave][lane][0] == 0xFFFFFFFFu) return;
     uint32_t *ooff = a.tw + L.t0 / 8u;
     gu32 *ctrl = (gu32 *)(a.out + L.out_off + 4u);
-    const uint32_t end = C.u0 + C.nu;
-    uint32_t o = C.u0 + a.chb[3u * ch], f = a.chb[3u * ch + 1u], bits = a.chb[3u * ch + 2u];
-    while (o < end) {
+    const uint32_t lim = min(end, s0 + kSegOct);
+    uint32_t o = s0 + s_in[wave][lane][0], f = s_in[wave][lane][1], bits = s_in[wave][lane][2];
+    while (o < lim) {
         const uint32_t F = cho[o], b = afor_b(om, o, F);
         const uint32_t cls = F == 8u ? 0u : F == 16u ? 1u : 2u;
         atomicOr((uint32_t *)&ctrl[f >> 2], (b | (cls << 6)) << (8u * (f & 3u)));
@@ -1276,10 +1379,10 @@ extern "C" gc_status gc_encode_lists_gpu(const uint32_t *d_in, const uint64_t *h
             (rc = dalloc(&a.chb, 3ull * nch, b)) || (rc = dalloc(&a.tw, ntup / 8u, b)))
             goto done;
         if (ntup) hipLaunchKernelGGL(k_afor_omax, dim3(grid(ntup / 8u)), dim3(kThreads), 0, s, a);
-        if (nch) hipLaunchKernelGGL(k_afor_dpA, dim3(grid(4ull * nch)), dim3(kThreads), 0, s, a);
+        if (nch) hipLaunchKernelGGL(k_afor_dpA, dim3(wave_grid(nch)), dim3(kThreads), 0, s, a);
         hipLaunchKernelGGL(k_afor_dpB, dim3(wave_grid(nlists)), dim3(kThreads), 0, s, a);
-        if (nch) hipLaunchKernelGGL(k_afor_dpC, dim3(grid(nch)), dim3(kThreads), 0, s, a);
-        if (nch) hipLaunchKernelGGL(k_afor_chainA, dim3(grid(4ull * nch)), dim3(kThreads), 0, s, a);
+        if (nch) hipLaunchKernelGGL(k_afor_dpC, dim3(wave_grid(nch)), dim3(kThreads), 0, s, a);
+        if (nch) hipLaunchKernelGGL(k_afor_chainA, dim3(wave_grid(nch)), dim3(kThreads), 0, s, a);
         hipLaunchKernelGGL(k_afor_chainB, dim3(grid(nlists)), dim3(kThreads), 0, s, a);
     } else {
         if ((rc = dalloc(&a.blk, 4ull * nblocks, b)) || (rc = dalloc(&a.slot, ntup * k, b)) ||
@@ -1326,7 +1429,7 @@ extern "C" gc_status gc_encode_lists_gpu(const uint32_t *d_in, const uint64_t *h
                            codec == GC_SCHEME && p->ld != GC_LD_BINARY ? 1 : 0);
     }
     if (codec == GC_SIMPLE && nch) hipLaunchKernelGGL(k_sim_chainC, dim3(wave_grid(nch)), dim3(kThreads), 0, s, a);
-    if (codec == GC_AFOR && nch) hipLaunchKernelGGL(k_afor_chainC, dim3(grid(nch)), dim3(kThreads), 0, s, a);
+    if (codec == GC_AFOR && nch) hipLaunchKernelGGL(k_afor_chainC, dim3(wave_grid(nch)), dim3(kThreads), 0, s, a);
     if (codec == GC_PFD) {
         if (nblocks) hipLaunchKernelGGL(k_pfd_emit, dim3((nblocks + kThreads / 32 - 1) / (kThreads / 32)), dim3(kThreads), 0, s, a);
     } else if (ntup) {
