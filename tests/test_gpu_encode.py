@@ -131,3 +131,49 @@ def test_gpu_encoder_cfg2(torch_cuda, k):
             assert np.array_equal(goffs, woffs), (name, what)
             assert np.array_equal(gc.to_host(got_d), want), (name, what)
             del got_d
+
+
+def test_gpu_encoder_threads_and_kept_scratch(torch_cuda):
+    """The encoder keeps its scratch per device across calls: four host
+    threads encode different list sets on one device at once (each on its
+    own stream; the calls take the device's scratch in turn), then a small
+    call runs in the grown scratch.  Every stream set equals the host
+    encoder's."""
+    import threading
+    torch = torch_cuda
+    rng = np.random.default_rng(77)
+    picks = [VARIANTS[0], VARIANTS[11], VARIANTS[12], VARIANTS[6]]
+    sets = []
+    for i, (name, codec, kw) in enumerate(picks):
+        lists = make_lists(rng, "docids", [100000 + 1000 * i, 5000, 0, 70001, 33])
+        lengths = np.array([x.size for x in lists], np.int64)
+        flat = np.concatenate(lists)
+        sets.append((name, lengths, flat, gc.to_device(flat), codec, gc.params(k=4, delta=True, **kw)))
+    torch.cuda.synchronize()
+    got = [None] * len(sets)
+    errors = []
+
+    def work(i):
+        try:
+            name, lengths, flat, d_flat, codec, p = sets[i]
+            st = torch.cuda.Stream()
+            d, offs = gc.encode_lists_gpu(d_flat, lengths, codec, p, stream=st.cuda_stream)
+            st.synchronize()
+            got[i] = (gc.to_host(d), offs)
+        except Exception as e:   # reported below, in the test's thread
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(len(sets))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for (name, lengths, flat, _, codec, p), (streams, offs) in zip(sets, got):
+        say("threads", name)
+        want, woffs = gc.encode_lists(flat, lengths, codec, p)
+        assert np.array_equal(offs, woffs), name
+        assert np.array_equal(streams, want), name
+    small = [np.arange(1, 300, 3, dtype=np.uint32), np.arange(7, dtype=np.uint32)]
+    say("small call after the threads")
+    compare(torch, small, gc.PFD, gc.params(k=4, delta=True))
