@@ -292,18 +292,24 @@ __global__ __launch_bounds__(kThreads) void k_gsc_chunkC(EArgs a) {
 // ---- Group-Simple (Section 4, Algorithm 1) -------------------------------------
 // From tuple j: the first selector whose NUM next tuples -- or all that
 // remain -- fit its width; code = selector | tuples covered << 4.
+// The workgroup's widths, and the 32 after them, are read into LDS first.
 __global__ __launch_bounds__(kThreads) void k_sim_cover(EArgs a) {
-    const uint64_t g = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    __shared__ uint8_t s_w[kThreads + 32u];
+    const uint64_t gb = (uint64_t)blockIdx.x * kThreads;
+    for (uint32_t x = threadIdx.x; x < kThreads + 32u; x += kThreads)
+        if (gb + x < a.ntup) s_w[x] = a.W[gb + x];
+    __syncthreads();
+    const uint64_t g = gb + threadIdx.x;
     if (g >= a.ntup) return;
     const EList L = a.lists[list_of_tuple(a, g)];
     const uint32_t j = (uint32_t)(g - L.t0);
-    const uint8_t *W = a.W + L.t0;
+    const uint8_t *W = s_w + threadIdx.x;   // W[p]: tuple j + p
     const uint32_t left = L.T - j;
     uint32_t pick = 9, cover = 1;
     for (uint32_t i = 0; i < 10u; i++) {
         const uint32_t num = kNum[i], lim = min(num, left);
         uint32_t p = 0;
-        while (p < lim && W[j + p] <= kBw[i]) p++;
+        while (p < lim && W[p] <= kBw[i]) p++;
         if (p == num || p == left) {
             pick = i;
             cover = p;
