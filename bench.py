@@ -649,6 +649,8 @@ def main():
     ap.add_argument("--pfd-tile", type=int, default=0, help="force the Group-PFD tile size (with --tile)")
     ap.add_argument("--locate-stream", action="store_true",
                     help="run the locate kernels on a second stream, ahead of the other kernels")
+    ap.add_argument("--leg", choices=("encode", "query"),
+                    help="run only this cfg2 leg (the list encoders, or AND queries) and print its record")
     ap.add_argument("--carry-pass", type=int, default=0, choices=(0, 1, 2, 3),
                     help="carries of delta lists: 1 look-back in the decode pass, 2 tile-sum pass and carry "
                          "scan, 3 look-back for lists of up to 64 tiles and the tile-sum pass for longer ones, "
@@ -666,6 +668,14 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     gc.lib()
+    if args.leg:
+        data = synth.cfg2()
+        if args.leg == "encode":
+            rec = encode_leg(gc, torch, data)
+        else:
+            rec = query_leg(gc, torch, gc.Context(0), synth, data)
+        print(json.dumps({"leg": args.leg + "_cfg2", "record": rec}), flush=True)
+        return
     legs = args.workload == "cfg3" and not args.no_extra
 
     cfg2_data = None
