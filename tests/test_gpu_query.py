@@ -133,7 +133,7 @@ def test_queries_edge_cases(torch_cuda, index):
 def test_queries_list_shapes(torch_cuda):
     """A small collection (2^18 documents) of lists shaped to reach every
     search path: empty and one-posting lists, lengths at the 64-docID round
-    and 8192-docID segment boundaries, equal lengths (the pivot is the first
+    and 4096-docID segment boundaries, equal lengths (the pivot is the first
     term), a dense run of consecutive docIDs, lists packed at the front or
     the back of the collection (the first probe stride overshoots or falls
     short), every docID (ranges longer than the LDS buffer, searched in
@@ -148,7 +148,7 @@ def test_queries_list_shapes(torch_cuda):
     doc_lists = [np.zeros(0, np.uint32), np.array([5], np.uint32), spread(64), spread(65), spread(1025),
                  spread(1025), spread(8193), np.arange(100000, 116384, dtype=np.uint32), spread(120000),
                  np.arange(nd, dtype=np.uint32), spread(3000, 0, 5000), spread(3000, nd - 12000, nd),
-                 spread(8192), spread(8191)]
+                 spread(8192), spread(8191), spread(4096), spread(4097)]
     # a list of clusters: runs of 40 consecutive docIDs
     starts = np.sort(rng.choice(nd // 64, 300, replace=False)) * 64
     doc_lists.append((starts[:, None] + np.arange(40)).ravel().astype(np.uint32))
@@ -164,7 +164,8 @@ def test_queries_list_shapes(torch_cuda):
     qs = [[i, j, -1, -1] for i in range(n) for j in range(n) if i != j]
     qs += [list(rng.choice(n, 3, replace=False)) + [-1] for _ in range(40)]
     qs += [list(rng.choice(n, 4, replace=False)) for _ in range(40)]
-    qs += [[9, 9, 8, -1], [8, 9, 7, 6], [-1, 9, -1, 4], [0, 9, -1, -1], [9, -1, -1, -1], [14, 9, 8, 12]]
+    qs += [[9, 9, 8, -1], [8, 9, 7, 6], [-1, 9, -1, 4], [0, 9, -1, -1], [9, -1, -1, -1], [16, 9, 8, 12],
+           [14, 15, 9, -1], [15, 14, 6, -1]]
     queries = np.array(qs, np.int64)
     term_off = torch.from_numpy(offs[:-1].astype(np.int64)).cuda()
     d_doclen = torch.from_numpy(doclen.view(np.int16)).cuda()
