@@ -21,8 +21,8 @@
 //     length and the pivot's TF are read only then) and
 //     offered to the wave's top-k, kept sorted in LDS (higher score first,
 //     then the smaller docID);
-// then one wave per query merges its segments' top-k lists, in segment
-// (docID) order.
+// then the segments' top-k lists of each query are merged as a tree, up
+// to 64 lists a node, one wave per node.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -298,34 +298,99 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) v
     if (lane == 0) a.part_doc[(uint64_t)a.nitems * a.topk + w] = count;
 }
 
-// One wave per query: its items' top-k lists merged in item (docID) order.
-__global__ __launch_bounds__(kThreads) void k_merge_topk(QArgs a) {
-    __shared__ float s_sc[kWaves][kMaxTopk];
-    __shared__ uint32_t s_dc[kWaves][kMaxTopk];
+// Whether (s1, d1) ranks before (s2, d2): the higher score, then the
+// smaller docID.
+__device__ __forceinline__ bool ranks_before(float s1, uint32_t d1, float s2, uint32_t d2) {
+    return s1 > s2 || (s1 == s2 && d1 < d2);
+}
+
+constexpr uint32_t kMergeBuf = 1024;   // list entries a wave holds in LDS
+
+// Lists merged by one wave: up to 64, at most 1024 entries.
+__host__ __device__ constexpr uint32_t merge_group(uint32_t topk) {
+    return 64u < kMergeBuf / topk ? 64u : kMergeBuf / topk;
+}
+
+// One level of the merge of a query's item lists (each sorted), as a tree:
+// the lists stand at the query's item slots first, first + stride, ...; the
+// wave of a group's first slot w merges the group's lists (slots w, w +
+// stride, ..., up to merge_group(topk) of them, copied to LDS) and writes
+// the result to slot w.  Lane l follows list l, and each of the next top-k
+// is the best of the lanes' heads (a wave-wide arg-max).
+__global__ __launch_bounds__(kThreads) void k_merge_level(QArgs a, uint32_t stride) {
+    __shared__ float s_ns[kWaves][kMaxTopk];
+    __shared__ uint32_t s_nd[kWaves][kMaxTopk];
+    __shared__ float s_bs[kWaves][kMergeBuf];
+    __shared__ uint32_t s_bd[kWaves][kMergeBuf];
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t w = blockIdx.x * (uint32_t)kWaves + wave;
+    if (w >= a.nitems) return;
+    const uint32_t topk = a.topk, G = merge_group(topk);
+    const uint32_t q = a.items[w].q, f0 = a.first[q], f1 = a.first[q + 1];
+    if ((w - f0) % (stride * G) != 0u) return;   // not a group's first slot
+    const uint32_t ng = min(G, (f1 - w + stride - 1u) / stride);
+    if (ng < 2u) return;   // a lone list stays as it is
+    float *bs = s_bs[wave], *ns = s_ns[wave];
+    uint32_t *bd = s_bd[wave], *nd = s_nd[wave];
+    // all of the group's loads issued before the first is waited for
+#pragma unroll
+    for (uint32_t r = 0; r < kMergeBuf / 64u; r++) {
+        const uint32_t x = 64u * r + lane;
+        if (x < ng * topk) {
+            const uint32_t l = x / topk, j = x - l * topk;
+            const uint64_t at = (uint64_t)(w + l * stride) * topk + j;
+            bs[x] = a.part_score[at];
+            bd[x] = a.part_doc[at];
+        }
+    }
+    const uint32_t n = lane < ng ? a.part_doc[(uint64_t)a.nitems * topk + w + lane * stride] : 0u;
+    wave_sync_lds();
+    uint32_t h = 0, out = 0;
+    while (out < topk) {
+        // the best head over the lanes; a lane whose list is exhausted ranks
+        // last (cl: the lane holding the best)
+        uint32_t cv = h < n ? 1u : 0u, cl = lane;
+        float cs = cv ? bs[lane * topk + h] : 0.0f;
+        uint32_t cd = cv ? bd[lane * topk + h] : 0xFFFFFFFFu;
+#pragma unroll
+        for (uint32_t m = 1; m < 64u; m <<= 1) {
+            const float os = __shfl_xor(cs, (int)m);
+            const uint32_t od = (uint32_t)__shfl_xor((int)cd, (int)m), ol = (uint32_t)__shfl_xor((int)cl, (int)m);
+            const uint32_t ov = (uint32_t)__shfl_xor((int)cv, (int)m);
+            const bool take =
+                ov > cv || (ov == cv && (ranks_before(os, od, cs, cd) || (os == cs && od == cd && ol < cl)));
+            cs = take ? os : cs;
+            cd = take ? od : cd;
+            cl = take ? ol : cl;
+            cv = take ? ov : cv;
+        }
+        if (!cv) break;   // every list is exhausted
+        if (lane == 0) {
+            ns[out] = cs;
+            nd[out] = cd;
+        }
+        h += lane == cl ? 1u : 0u;
+        out++;
+    }
+    wave_sync_lds();
+    for (uint32_t r = lane; r < out; r += 64u) {
+        a.part_score[(uint64_t)w * topk + r] = ns[r];
+        a.part_doc[(uint64_t)w * topk + r] = nd[r];
+    }
+    if (lane == 0) a.part_doc[(uint64_t)a.nitems * topk + w] = out;
+}
+
+// One wave per query: its merged list (at its first item slot) to the
+// output, padded with empty entries.
+__global__ __launch_bounds__(kThreads) void k_topk_out(QArgs a) {
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
     const uint32_t q = blockIdx.x * (uint32_t)kWaves + wave;
     if (q >= a.nq) return;
-    float *sc = s_sc[wave];
-    uint32_t *dc = s_dc[wave];
-    uint32_t count = 0;
-    float thr = -1.0f;
-    for (uint32_t w = a.first[q]; w < a.first[q + 1]; w++) {
-        const uint32_t n = a.part_doc[(uint64_t)a.nitems * a.topk + w];
-        const bool in = lane < n;
-        const float s = in ? a.part_score[(uint64_t)w * a.topk + lane] : -1.0f;
-        const uint32_t d = in ? a.part_doc[(uint64_t)w * a.topk + lane] : 0xFFFFFFFFu;
-        uint64_t m = __ballot(in && s > thr);
-        while (m) {
-            const uint32_t l = (uint32_t)__builtin_ctzll(m);
-            count = topk_insert(sc, dc, count, a.topk, __shfl(s, (int)l), (uint32_t)__shfl((int)d, (int)l), lane);
-            thr = count == a.topk ? sc[a.topk - 1u] : -1.0f;
-            m &= m - 1u;
-            m &= __ballot(in && s > thr);
-        }
-    }
-    for (uint32_t r = lane; r < a.topk; r += 64u) {
-        a.out_doc[(uint64_t)q * a.topk + r] = r < count ? dc[r] : 0xFFFFFFFFu;
-        a.out_score[(uint64_t)q * a.topk + r] = r < count ? sc[r] : 0.0f;
+    const uint32_t f0 = a.first[q], topk = a.topk;
+    const uint32_t count = f0 < a.first[q + 1] ? a.part_doc[(uint64_t)a.nitems * topk + f0] : 0u;
+    for (uint32_t r = lane; r < topk; r += 64u) {
+        a.out_doc[(uint64_t)q * topk + r] = r < count ? a.part_doc[(uint64_t)f0 * topk + r] : 0xFFFFFFFFu;
+        a.out_score[(uint64_t)q * topk + r] = r < count ? a.part_score[(uint64_t)f0 * topk + r] : 0.0f;
     }
 }
 
@@ -335,6 +400,7 @@ using namespace gcq;
 
 struct gc_query_plan {
     QArgs a;
+    uint32_t max_items = 0;   // the most work items of one query
     int device = 0;
     void *mem[6] = {};
 };
@@ -392,6 +458,7 @@ gc_status gc_query_plan_create(const uint32_t *h_term_len, size_t nterms, const 
     first[nq] = (uint32_t)items.size();
     gc_query_plan *p = new (std::nothrow) gc_query_plan();
     if (!p) return GC_ENOMEM;
+    for (uint32_t q = 0; q < nq; q++) p->max_items = std::max(p->max_items, first[q + 1] - first[q]);
     (void)hipGetDevice(&p->device);
     std::memset(&p->a, 0, sizeof(p->a));
     QArgs &a = p->a;
@@ -445,7 +512,12 @@ gc_status gc_query_run(gc_query_plan *plan, const uint32_t *d_docs, const uint32
     a.out_score = d_top_score;
     const hipStream_t s = (hipStream_t)hip_stream;
     if (a.nitems) hipLaunchKernelGGL(k_and_topk, dim3((a.nitems + kWaves - 1) / kWaves), dim3(kThreads), 0, s, a);
-    hipLaunchKernelGGL(k_merge_topk, dim3((a.nq + kWaves - 1) / kWaves), dim3(kThreads), 0, s, a);
+    // the items' lists merged per query as a tree, merge_group(topk) lists a node
+    const uint32_t G = merge_group(a.topk);
+    for (uint64_t stride = 1; stride < plan->max_items; stride *= G)
+        hipLaunchKernelGGL(k_merge_level, dim3((a.nitems + kWaves - 1) / kWaves), dim3(kThreads), 0, s, a,
+                           (uint32_t)stride);
+    hipLaunchKernelGGL(k_topk_out, dim3((a.nq + kWaves - 1) / kWaves), dim3(kThreads), 0, s, a);
     return hipGetLastError() == hipSuccess ? GC_OK : GC_EDEVICE;
 }
 
