@@ -4,7 +4,7 @@
 // documents present in every one of its terms' lists, scores each with
 // BM25 and returns the k best.  The lists are decoded by the batched decode
 // path (docIDs prefix-summed, TFs) into device arenas.  A query plan cuts
-// every query's shortest list (the pivot) into segments of 4096 docIDs, one
+// every query's shortest list (the pivot) into segments of 2048 docIDs, one
 // work item each, so long queries spread over many waves:
 //   - a wave takes the pivot's docIDs of its segment 64 at a time, one per
 //     lane;
@@ -44,7 +44,7 @@ constexpr int kWaves = kThreads / 64;
 constexpr uint32_t kMaxTerms = 8;
 constexpr uint32_t kMaxTopk = 64;
 constexpr uint32_t kSkip = 512;     // postings between skip pointers
-constexpr uint32_t kSeg = 4096;     // pivot docIDs per work item
+constexpr uint32_t kSeg = 2048;     // pivot docIDs per work item
 constexpr uint32_t kLdsRange = 1024; // postings of one term's range searched in LDS
 
 // A work item: pivot docIDs [s0, s1) of query q.

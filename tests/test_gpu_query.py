@@ -133,7 +133,7 @@ def test_queries_edge_cases(torch_cuda, index):
 def test_queries_list_shapes(torch_cuda):
     """A small collection (2^18 documents) of lists shaped to reach every
     search path: empty and one-posting lists, lengths at the 64-docID round
-    and 4096-docID segment boundaries, equal lengths (the pivot is the first
+    and 2048-docID segment boundaries, equal lengths (the pivot is the first
     term), a dense run of consecutive docIDs, lists packed at the front or
     the back of the collection (the first probe stride overshoots or falls
     short), every docID (ranges longer than the LDS buffer, searched in
@@ -148,7 +148,7 @@ def test_queries_list_shapes(torch_cuda):
     doc_lists = [np.zeros(0, np.uint32), np.array([5], np.uint32), spread(64), spread(65), spread(1025),
                  spread(1025), spread(8193), np.arange(100000, 116384, dtype=np.uint32), spread(120000),
                  np.arange(nd, dtype=np.uint32), spread(3000, 0, 5000), spread(3000, nd - 12000, nd),
-                 spread(8192), spread(8191), spread(4096), spread(4097)]
+                 spread(8192), spread(8191), spread(2048), spread(2049)]
     # a list of clusters: runs of 40 consecutive docIDs
     starts = np.sort(rng.choice(nd // 64, 300, replace=False)) * 64
     doc_lists.append((starts[:, None] + np.arange(40)).ravel().astype(np.uint32))
