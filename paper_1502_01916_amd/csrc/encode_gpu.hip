@@ -21,15 +21,19 @@
 // enters it, or the bit position mod 8), the state it leaves in and what it
 // emitted (units, bits); one lane per list then walks its chunks and finds
 // each chunk's true entry state and the counts before it; every chunk then
-// runs once more from its entry state and writes its units.  Group-AFOR's
-// frame sizes come from the exact dynamic programme of Section 6.1, run
-// backwards: a chunk maps the costs at its end to the costs at its start by
-// a 4 x 4 min-plus matrix (its four columns from four runs, each with one
-// end state at cost 0 and the others unreachable), the lane of a list
-// multiplies them from the last chunk back to find every chunk's end costs,
-// and each chunk then runs the programme once with its true end costs and
-// keeps its choices.  Group-PFD codes 32-tuple blocks independently
-// (Section 6.2): one lane per block.
+// runs once more from its entry state and writes its units.  A chunk runs
+// on one wave: each lane tabulates its 32 tuples (or 4 octets) for every
+// entry state, one lane chains the tables, and each lane then walks its own
+// part from its true entry.  Group-AFOR's frame sizes come from the exact
+// dynamic programme of Section 6.1, run backwards: a stretch of octets maps
+// the costs at its end to the costs at its start by a 4 x 4 min-plus
+// matrix (its four columns from four runs, each with one end state at cost
+// 0 and the others unreachable); the products are associative, so a wave
+// combines its lanes' matrices, and each list's chunk matrices, by reverse
+// scans, and each lane then runs the programme once over its octets with
+// its true end costs and keeps its choices.  Group-PFD codes 32-tuple
+// blocks independently (Section 6.2): half a wave per block.
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
