@@ -153,8 +153,8 @@ __device__ __forceinline__ uint32_t topk_insert(float *sc, uint32_t *dc, uint32_
 
 // One wave per work item: its pivot docIDs found in every other list,
 // scored, into the item's top-k.  The kernel waits on chains of dependent
-// loads, so it is held to at least five waves per SIMD (80 VGPRs; with four
-// it runs 20% slower).
+// loads, so it is held to at least five waves per SIMD (it takes 78 VGPRs
+// and runs six; with four it ran 20% slower).
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_and_topk(QArgs a) {
     __shared__ float s_sc[kWaves][kMaxTopk];
     __shared__ uint32_t s_dc[kWaves][kMaxTopk];
