@@ -24,7 +24,7 @@ _SRCS = [os.path.join(_HERE, "gc_oracle.c")]
 _lock = threading.Lock()
 _lib = None
 
-SIMPLE, SCHEME, AFOR, PFD = 0, 1, 2, 3
+SIMPLE, SCHEME, AFOR, PFD, VSE = 0, 1, 2, 3, 4
 LD_BINARY, LD_CU, LD_IU = 0, 1, 2
 PFD_LINKED, PFD_BITMAP = 0, 1
 OK, EINVAL, ENOSPC, ECORRUPT = 0, -1, -2, -3
@@ -71,6 +71,8 @@ def lib():
             L.or_gsc_units.argtypes = [ctypes.c_uint32, ctypes.c_int]
             L.or_afor_partition.argtypes = [u32p, sz, ctypes.c_int, u8p]
             L.or_afor_partition.restype = sz
+            L.or_vse_partition.argtypes = [u32p, sz, ctypes.c_int, u8p]
+            L.or_vse_partition.restype = sz
             L.or_pfd_width.argtypes = [u32p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
             L.or_encode.argtypes = [u32p, sz, ctypes.POINTER(Params), u32p, sz]
             L.or_encode.restype = ctypes.c_long
@@ -164,6 +166,13 @@ def afor_partition(qmax, k=4):
     q = np.ascontiguousarray(qmax, dtype=np.uint32)
     F = np.zeros(q.size // 8 + 1, np.uint8)
     nf = lib().or_afor_partition(_u32(q), q.size, k, _u8(F))
+    return [int(f) for f in F[:nf]]
+
+
+def vse_partition(qmax, k=4):
+    q = np.ascontiguousarray(qmax, dtype=np.uint32)
+    F = np.zeros(q.size // 8 + 1, np.uint8)
+    nf = lib().or_vse_partition(_u32(q), q.size, k, _u8(F))
     return [int(f) for f in F[:nf]]
 
 

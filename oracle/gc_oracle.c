@@ -196,7 +196,7 @@ static int log2_int(int v)
 
 static int params_ok(const or_params *p)
 {
-    if (p->codec < 0 || p->codec > 3)
+    if (p->codec < 0 || p->codec > 4)
         return 0;
     if (p->k < 4 || p->k > 64 || (p->k & (p->k - 1)) != 0)
         return 0;
@@ -250,7 +250,7 @@ int or_parse_header(uint32_t w0, or_params *p)
     p->pfd_pos = (int)((w0 >> 20) & 1u);
     p->zeta_num = 1;
     p->zeta_den = 10;
-    if (p->codec > 3 || lk < 2 || lk > 6)
+    if (p->codec > 4 || lk < 2 || lk > 6)
         return 0;
     if (p->codec == OR_SCHEME) {
         if (p->ld > 2 || (p->ld == OR_LD_IU && p->cg < 4))
@@ -560,6 +560,45 @@ size_t or_afor_partition(const uint32_t *qmax, size_t M, int k, uint8_t *Fout)
     return nf;
 }
 
+/* Group-VSEncoding: the same frames and control bytes, partitioned by the
+ * dynamic programme of VSEncoding (Section 2.2 names its frame-length set
+ * {1, 2, 4, 8, 12, 16, 32, 64}).  A group frame is a run of whole tuples
+ * between 8 and 32 tuples long (the shortest and longest Group-AFOR frame),
+ * so the lengths kept are 8, 12, 16 and 32 tuples; class 3 of the control
+ * byte, unused by Group-AFOR, is the 12-tuple frame.  Frames start at
+ * multiples of 4 tuples.  Same cost and tie rule as Group-AFOR.            */
+size_t or_vse_partition(const uint32_t *qmax, size_t M, int k, uint8_t *Fout)
+{
+    static const int Fs[4] = {32, 16, 12, 8};
+    uint64_t *cost = (uint64_t *)calloc(M + 1, 8);
+    uint8_t *choice = (uint8_t *)calloc(M + 1, 1);
+    cost[M] = 0;
+    for (size_t ii = M; ii-- > 0;) {
+        if ((ii % 4) != 0)
+            continue;
+        uint64_t best = UINT64_MAX;
+        int bestF = 0;
+        for (int f = 0; f < 4; f++) {
+            size_t F = (size_t)Fs[f];
+            if (ii + F > M || cost[ii + F] == UINT64_MAX)
+                continue;
+            uint64_t c = 8 + (uint64_t)k * F * (uint64_t)max_width(qmax, ii, F) + cost[ii + F];
+            if (c < best) {
+                best = c;
+                bestF = (int)F;
+            }
+        }
+        cost[ii] = best;
+        choice[ii] = (uint8_t)bestF;
+    }
+    size_t nf = 0;
+    for (size_t i = 0; i < M; i += choice[i])
+        Fout[nf++] = choice[i];
+    free(cost);
+    free(choice);
+    return nf;
+}
+
 static void afor_encode_frames(const uint32_t *x, size_t M, int k, const uint8_t *F,
                                size_t nf, areas *a)
 {
@@ -569,7 +608,7 @@ static void afor_encode_frames(const uint32_t *x, size_t M, int k, const uint8_t
     uint64_t O = 0;
     size_t t0 = 0;
     for (size_t f = 0; f < nf; f++) {
-        int cls = F[f] == 8 ? 0 : F[f] == 16 ? 1 : 2;
+        int cls = F[f] == 8 ? 0 : F[f] == 16 ? 1 : F[f] == 32 ? 2 : 3;   /* 3: 12 tuples */
         int b = max_width(qmax, t0, F[f]);
         sink_value(&cs, (uint32_t)b, 6);      /* control byte: b:6 | class:2 */
         sink_value(&cs, (uint32_t)cls, 2);
@@ -593,8 +632,9 @@ static void afor_encode_frames(const uint32_t *x, size_t M, int k, const uint8_t
     free(qmax);
 }
 
+/* vse: class 3 is a 12-tuple frame (Group-VSEncoding); otherwise corrupt. */
 static int afor_decode(const uint32_t *ctrl, size_t C, const uint32_t *data, size_t D,
-                       size_t T, int k, uint32_t *x)
+                       size_t T, int k, int vse, uint32_t *x)
 {
     bitsrc cs = {ctrl, C, 1, 0, 0, 0};
     uint64_t O = 0;
@@ -602,9 +642,9 @@ static int afor_decode(const uint32_t *ctrl, size_t C, const uint32_t *data, siz
     while (t0 < T) {
         uint32_t b = src_value(&cs, 6);
         uint32_t cls = src_value(&cs, 2);
-        if (cs.err || cls == 3 || b > 32)
+        if (cs.err || (cls == 3 && !vse) || b > 32)
             return OR_ECORRUPT;
-        size_t F = (size_t)8 << cls;
+        size_t F = cls == 3 ? 12 : (size_t)8 << cls;
         for (size_t j = 0; j < F; j++)
             for (int c = 0; c < k; c++) {
                 bitsrc ds = {data, D, k, c, O + j * (uint64_t)b, 0};
@@ -902,7 +942,7 @@ static uint32_t *prepare(const uint32_t *in, size_t n, const or_params *p, size_
                          size_t *Tpad_out)
 {
     size_t T = ceil_div(n, (size_t)p->k);
-    size_t unit = p->codec == OR_AFOR ? 8 : p->codec == OR_PFD ? 32 : 1;
+    size_t unit = p->codec == OR_AFOR || p->codec == OR_VSE ? 8 : p->codec == OR_PFD ? 32 : 1;
     size_t Tp = round_up(T, unit);
     uint32_t *x = (uint32_t *)calloc(Tp * (size_t)p->k + 1, 4);
     if (!x)
@@ -934,11 +974,12 @@ long or_encode(const uint32_t *in, size_t n, const or_params *p, uint32_t *out, 
         gsim_encode(x, T, p->k, &a, NULL, 0);
     } else if (p->codec == OR_SCHEME) {
         gsc_encode(x, T, p->k, p->cg, p->ld, &a);
-    } else if (p->codec == OR_AFOR) {
+    } else if (p->codec == OR_AFOR || p->codec == OR_VSE) {
         uint32_t *qmax = (uint32_t *)calloc(Tp + 1, 4);
         uint8_t *F = (uint8_t *)calloc(Tp / 8 + 1, 1);
         or_tuple_max(x, Tp, p->k, qmax);
-        size_t nf = or_afor_partition(qmax, Tp, p->k, F);
+        size_t nf = p->codec == OR_AFOR ? or_afor_partition(qmax, Tp, p->k, F)
+                                        : or_vse_partition(qmax, Tp, p->k, F);
         afor_encode_frames(x, Tp, p->k, F, nf, &a);
         free(qmax);
         free(F);
@@ -980,18 +1021,19 @@ long or_gsim_encode_with(const uint32_t *in, size_t n, const or_params *p, const
     return r;
 }
 
-/* Group-AFOR with a caller-chosen partition (frame sizes in tuples). */
+/* Group-AFOR (or Group-VSEncoding) with a caller-chosen partition (frame
+ * sizes in tuples; 12 only for Group-VSEncoding). */
 long or_afor_encode_with(const uint32_t *in, size_t n, const or_params *p, const uint8_t *F,
                          size_t nf, uint32_t *out, size_t cap)
 {
-    if (!params_ok(p) || p->codec != OR_AFOR)
+    if (!params_ok(p) || (p->codec != OR_AFOR && p->codec != OR_VSE))
         return OR_EINVAL;
     size_t T, Tp;
     uint32_t *x = prepare(in, n, p, &T, &Tp);
     areas a;
     areas_alloc(&a, Tp + 64, p->k);
     for (size_t f = 0; f < nf; f++)
-        if (F[f] != 8 && F[f] != 16 && F[f] != 32)
+        if (F[f] != 8 && F[f] != 16 && F[f] != 32 && !(F[f] == 12 && p->codec == OR_VSE))
             a.err = 1;
     afor_encode_frames(x, Tp, p->k, F, nf, &a);
     long r = assemble(p, n, &a, out, cap);
@@ -1013,7 +1055,7 @@ long or_decode(const uint32_t *s, size_t words, uint32_t *out, size_t cap)
     if (n > cap)
         return OR_ENOSPC;
     size_t T = ceil_div(n, (size_t)p.k);
-    size_t unit = p.codec == OR_AFOR ? 8 : p.codec == OR_PFD ? 32 : 1;
+    size_t unit = p.codec == OR_AFOR || p.codec == OR_VSE ? 8 : p.codec == OR_PFD ? 32 : 1;
     size_t Tp = round_up(T, unit);
     uint32_t *x = (uint32_t *)calloc(Tp * (size_t)p.k + 1, 4);
     if (!x)
@@ -1024,7 +1066,8 @@ long or_decode(const uint32_t *s, size_t words, uint32_t *out, size_t cap)
     switch (p.codec) {
     case OR_SIMPLE: rc = gsim_decode(ctrl, C, data, D, T, p.k, x); break;
     case OR_SCHEME: rc = gsc_decode(ctrl, C, data, D, T, p.k, p.cg, p.ld, x); break;
-    case OR_AFOR: rc = afor_decode(ctrl, C, data, D, T, p.k, x); break;
+    case OR_AFOR: rc = afor_decode(ctrl, C, data, D, T, p.k, 0, x); break;
+    case OR_VSE: rc = afor_decode(ctrl, C, data, D, T, p.k, 1, x); break;
     default: rc = pfd_decode(ctrl, C, data, D, exc, Emax, Tp, p.k, p.pfd_pos, x); break;
     }
     if (rc == OR_OK) {

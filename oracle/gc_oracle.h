@@ -15,7 +15,7 @@
 #define OR_ECORRUPT (-3)
 #define OR_ENOMEM (-6)
 
-enum { OR_SIMPLE = 0, OR_SCHEME = 1, OR_AFOR = 2, OR_PFD = 3 };
+enum { OR_SIMPLE = 0, OR_SCHEME = 1, OR_AFOR = 2, OR_PFD = 3, OR_VSE = 4 };
 enum { OR_LD_BINARY = 0, OR_LD_CU = 1, OR_LD_IU = 2 };
 enum { OR_PFD_LINKED = 0, OR_PFD_BITMAP = 1 };
 
@@ -39,6 +39,7 @@ size_t or_gsim_select(const uint32_t *MaxArr, size_t L, uint8_t *ModeArr);
 int or_parse_header(uint32_t w0, or_params *p);
 int or_gsc_units(uint32_t quadmax, int cg);
 size_t or_afor_partition(const uint32_t *qmax, size_t M, int k, uint8_t *Fout);
+size_t or_vse_partition(const uint32_t *qmax, size_t M, int k, uint8_t *Fout);
 int or_pfd_width(const uint32_t *qmax, int ntuples, int num, int den);
 long or_encode(const uint32_t *in, size_t n, const or_params *p, uint32_t *out, size_t cap);
 long or_gsim_encode_with(const uint32_t *in, size_t n, const or_params *p, const uint8_t *sel,

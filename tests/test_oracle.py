@@ -380,6 +380,91 @@ def test_afor_control_byte():
 
 
 # --------------------------------------------------------------------------
+# Group-VSEncoding: VSEncoding's frame lengths that fit a group frame (8, 12,
+# 16 and 32 tuples), Group-AFOR's control byte with class 3 = 12 tuples.
+
+def vse_partitions(m):
+    if m == 0:
+        yield []
+        return
+    for F in (8, 12, 16, 32):
+        if F <= m:
+            for rest in vse_partitions(m - F):
+                yield [F] + rest
+
+
+def test_vse_dp_is_bruteforce_minimum():
+    rng = np.random.default_rng(28)
+    for trial in range(40):
+        m = 8 * int(rng.integers(1, 9))
+        w = rng.integers(0, 20, m) if trial % 2 else np.repeat(rng.integers(0, 20, m // 4), 4)
+        tm = np.array([(1 << int(b)) - 1 if b else 0 for b in w], np.uint32)
+        dp = O.vse_partition(tm)
+        assert sum(dp) == m and all(F in (8, 12, 16, 32) for F in dp)
+        best = min(afor_cost(tm, p) for p in vse_partitions(m))
+        assert afor_cost(tm, dp) == best
+        # no worse than Group-AFOR, whose frame set it contains
+        assert best <= afor_cost(tm, O.afor_partition(tm))
+        # ties go to the larger first frame
+        j = 0
+        for F in dp:
+            for G in (32, 16, 12):
+                if G > F and j + G <= m:
+                    rest = [afor_cost(tm[j + G:], p) for p in vse_partitions(m - j - G)]
+                    if rest:
+                        head = afor_cost(tm[j:j + G], [G])
+                        assert head + min(rest) > afor_cost(tm[j:], O.vse_partition(tm[j:]))
+            j += F
+
+
+def test_vse_every_partition_decodes():
+    rng = np.random.default_rng(29)
+    x = rng.geometric(0.1, 4 * 48).astype(np.uint32)
+    p = O.params(O.VSE)
+    n = 0
+    for part in vse_partitions(48):
+        s = O.afor_encode_with(x, part, p)
+        assert np.array_equal(O.decode(s), x)
+        n += 1
+    assert n == 41                                      # compositions of 48 into 8, 12, 16, 32
+    with pytest.raises(ValueError):                    # no 12-tuple frame in Group-AFOR
+        O.afor_encode_with(x, [12, 12, 8, 16], O.params(O.AFOR))
+
+
+def test_vse_control_byte():
+    # 12 tuples of width 2 then 12 of width 10: two 12-tuple frames cost
+    # 16 + 4*12*2 + 4*12*10 = 592 bits; the best frames of 8/16/32 (8 then
+    # 16) cost 16 + 4*8*2 + 4*16*10 = 720
+    x = from_tuples([3] * 12 + [1000] * 12)
+    s = O.encode(x, O.params(O.VSE))
+    ctrl, _, _ = areas(s)
+    b0, b1 = int(ctrl[0]) & 0xFF, (int(ctrl[0]) >> 8) & 0xFF
+    assert (b0 & 63, b0 >> 6) == (2, 3)
+    assert (b1 & 63, b1 >> 6) == (10, 3)
+    assert int(s[3]) == 4 * ((12 * 2 + 12 * 10 + 31) // 32)
+    assert (int(s[0]) >> 8) & 15 == 4
+    a = O.encode(x, O.params(O.AFOR))
+    assert O.afor_partition(O.tuple_max(x)) == [8, 16]
+    assert int(a[3]) == 4 * ((8 * 2 + 16 * 10 + 31) // 32)
+    assert np.array_equal(O.decode(s), x) and np.array_equal(O.decode(a), x)
+    # the same byte in a Group-AFOR stream is corrupt
+    bad = a.copy()
+    bad[4] = int(bad[4]) | 0xC0
+    assert O.decode_status(bad) == O.ECORRUPT
+
+
+@pytest.mark.parametrize("k", [4, 8, 16, 32, 64])
+def test_vse_roundtrip_sizes(k):
+    rng = np.random.default_rng(30 + k)
+    for n in (1, 7, k * 12, k * 12 + 1, 3000):
+        d = np.cumsum(rng.geometric(0.05, n)).astype(np.uint32)
+        s = O.encode(d, O.params(O.VSE, k=k, delta=True))
+        assert np.array_equal(O.decode(s), d)
+        sa = O.encode(d, O.params(O.AFOR, k=k, delta=True))
+        assert s.size <= sa.size + 4                    # control padding aside
+
+
+# --------------------------------------------------------------------------
 # Group-PFD.
 
 def parse_pfd_descriptors(s):
