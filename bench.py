@@ -77,7 +77,8 @@ def five_codecs(gc):
 def all_variants(gc):
     """Every codec variant of Sections 4-6 in the 4-way layout: Group-Simple,
     the ten Group-Scheme variants (Section 5.2), Group-AFOR, Group-PFD at
-    zeta = 1/10 and BP128 (Group-PFD below zeta = 1/32, Section 6.3)."""
+    zeta = 1/10, BP128 (Group-PFD below zeta = 1/32, Section 6.3) and
+    Group-VSEncoding (Group-AFOR's stream with 12-tuple frames as well)."""
     v = [("group-simple", gc.SIMPLE, {})]
     for cg in (1, 2, 4, 8):
         v.append(("gsc-%d-b" % cg, gc.SCHEME, dict(cg=cg, ld=gc.LD_BINARY)))
@@ -86,7 +87,7 @@ def all_variants(gc):
     for cg in (4, 8):
         v.append(("gsc-%d-iu" % cg, gc.SCHEME, dict(cg=cg, ld=gc.LD_IU)))
     v += [("group-afor", gc.AFOR, {}), ("group-pfd", gc.PFD, dict(zeta=(1, 10))),
-          ("bp128", gc.PFD, dict(zeta=(1, 32)))]
+          ("bp128", gc.PFD, dict(zeta=(1, 32))), ("group-vse", gc.VSE, {})]
     return v
 
 
@@ -116,7 +117,7 @@ def codec_class(gc, codec, kw):
         return 0
     if codec == gc.SCHEME:
         return 2 if kw.get("ld", gc.LD_CU) == gc.LD_BINARY else 1
-    return 3 if codec == gc.AFOR else 4
+    return 3 if codec in (gc.AFOR, gc.VSE) else 4
 
 
 class Workload:
@@ -649,8 +650,9 @@ def main():
     ap.add_argument("--pfd-tile", type=int, default=0, help="force the Group-PFD tile size (with --tile)")
     ap.add_argument("--locate-stream", action="store_true",
                     help="run the locate kernels on a second stream, ahead of the other kernels")
-    ap.add_argument("--leg", choices=("encode", "query"),
-                    help="run only this cfg2 leg (the list encoders, or AND queries) and print its record")
+    ap.add_argument("--leg", choices=("encode", "query", "variants"),
+                    help="run only this cfg2 leg (the list encoders, AND queries, or every codec variant) "
+                         "and print its record")
     ap.add_argument("--carry-pass", type=int, default=0, choices=(0, 1, 2, 3),
                     help="carries of delta lists: 1 look-back in the decode pass, 2 tile-sum pass and carry "
                          "scan, 3 look-back for lists of up to 64 tiles and the tile-sum pass for longer ones, "
@@ -672,6 +674,8 @@ def main():
         data = synth.cfg2()
         if args.leg == "encode":
             rec = encode_leg(gc, torch, data)
+        elif args.leg == "variants":
+            rec = variants_leg(gc, torch, gc.Context(0), synth, args, data)
         else:
             rec = query_leg(gc, torch, gc.Context(0), synth, data)
         print(json.dumps({"leg": args.leg + "_cfg2", "record": rec}), flush=True)

@@ -58,7 +58,12 @@ typedef enum {
     GC_SIMPLE = 0,  /* Group-Simple: 4-bit selectors of Table III, one vector each   */
     GC_SCHEME = 1,  /* Group-Scheme CG-LD: eq. (1)-(2), unary or binary descriptors   */
     GC_AFOR = 2,    /* Group-AFOR: frames of 8/16/32 tuples, DP partition            */
-    GC_PFD = 3      /* Group-PFD: 32-tuple blocks, exceptions in a separate area      */
+    GC_PFD = 3,     /* Group-PFD: 32-tuple blocks, exceptions in a separate area      */
+    GC_VSE = 4      /* Group-VSEncoding (Section 6.1 names it; Section 2.2 gives
+                     * VSEncoding's frame lengths): Group-AFOR's stream with frames
+                     * of 8/12/16/32 tuples (class 3 = 12), DP partition.  Host
+                     * encoder and GPU decoders only: gc_encode_lists_gpu returns
+                     * GC_EINVAL for it.                                          */
 } gc_codec;
 
 /* Group-Scheme length descriptor (Section 5.2.1). */

@@ -163,15 +163,16 @@ __device__ __forceinline__ uint32_t sim_word_tuples(uint32_t wd, uint32_t ns, bo
     return wt;
 }
 
-// Tuples and component data bits of the four frames of a Group-AFOR control
-// word, without a branch; *bad is set for a class-3 byte or a width above 32.
-__device__ __forceinline__ void afor_word(uint32_t wd, uint32_t &wt, uint32_t &wbits, bool &bad) {
+// Tuples and component data bits of the four frames of a Group-AFOR (vse:
+// Group-VSEncoding) control word, without a branch; *bad is set for a width
+// above 32 or, in Group-AFOR, a class-3 byte.
+__device__ __forceinline__ void afor_word(uint32_t wd, bool vse, uint32_t &wt, uint32_t &wbits, bool &bad) {
     wt = wbits = 0;
 #pragma unroll
     for (int i = 0; i < 4; i++) {
         const uint32_t byte = (wd >> (8 * i)) & 0xFFu, b = byte & 63u, cls = byte >> 6;
-        bad |= cls == 3u || b > 32u;
-        const uint32_t F = 8u << cls;
+        bad |= (cls == 3u && !vse) || b > 32u;
+        const uint32_t F = frame_tuples(cls);
         wt += F;
         wbits += F * b;
     }
@@ -186,7 +187,8 @@ __device__ __forceinline__ uint32_t locate_words(const HeaderFields &h, uint32_t
             return min(C, (T + u.fpw - 1u) / u.fpw);
         }
         return C;
-    case 2: return C;
+    case 2:
+    case 4: return C;
     default: return min(C, (T + 31u) >> 5);                  // one descriptor per block
     }
 }
@@ -274,8 +276,9 @@ __device__ __forceinline__ void locate_thread(const ListDesc &L, uint32_t chunk,
                 }
             }
             break;
-        case 2: {
-            afor_word(wd, t.wt[q], t.wb[q], t.bad);
+        case 2:
+        case 4: {
+            afor_word(wd, h.codec == 4, t.wt[q], t.wb[q], t.bad);
             t.vt += t.wt[q];
             t.vd += t.wb[q];
             break;
@@ -504,7 +507,8 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
                         base_d += t.wb[q];
                     }
                     break;
-                case 2: {
+                case 2:
+                case 4: {
                     // the word's frames are walked only when a tile starts among them
                     const uint32_t wt = t.wt[q], wbits = t.wb[q];
                     if (!(m < ntiles && B < base_t + wt)) {
@@ -514,7 +518,7 @@ __global__ __launch_bounds__(kThreads) void gc_locate_emit(LocateArgs a) {
                     }
                     for (int i = 0; i < 4; i++) {
                         const uint32_t byte = (wd >> (8 * i)) & 0xFFu;
-                        const uint32_t b = byte & 63u, F = 8u << (byte >> 6);
+                        const uint32_t b = byte & 63u, F = frame_tuples(byte >> 6);
                         if (m < ntiles && B < base_t + F) {
                             const uint32_t sub = B - base_t;
                             emit(m, 4u * w + (uint32_t)i, sub, base_d + (uint64_t)sub * b, 0);
@@ -551,7 +555,7 @@ __device__ __forceinline__ int codec_class_dev(uint32_t w0) {
     HeaderFields h;
     if (!header_fields(w0, h)) return -1;
     return h.codec == 0 ? kClsSim : h.codec == 1 ? (h.ld == GC_LD_BINARY ? kClsGscB : kClsGscU)
-                                                 : h.codec == 2 ? kClsAfor : kClsPfd;
+                                                 : h.codec == 3 ? kClsPfd : kClsAfor;
 }
 
 struct TileCtx {
@@ -1015,6 +1019,8 @@ __device__ uint32_t wprologue_afor(const TileCtx &c, WaveSmem<TW, kClsAfor> &sm,
                                    const uint32_t (&ce)[CE]) {
     using SM = WaveSmem<TW, kClsAfor>;
     const uint32_t f0 = c.st.unit, sub0 = c.st.sub;
+    const bool vse = c.h.codec == 4;   // Group-VSEncoding: class 3 is a 12-tuple frame
+    // frames hold at least 8 tuples, so a tile meets at most TT / 8 + 2 of them
     const uint32_t nfr = min(c.TT / 8u + 2u, 4u * c.C > f0 ? 4u * c.C - f0 : 0u);
     constexpr int FPT = (SM::TTM / 8 + 2 + 63) / 64;
     static_assert(64 * CE * 4 >= SM::TTM / 8 + 2 + 3, "the frame bytes fit the early words");
@@ -1031,11 +1037,11 @@ __device__ uint32_t wprologue_afor(const TileCtx &c, WaveSmem<TW, kClsAfor> &sm,
             const uint32_t byte = (word >> (8u * (f & 3u))) & 0xFFu;
             uint32_t b = byte & 63u;
             const uint32_t cls = byte >> 6;
-            if (cls == 3u || b > 32u) {
+            if ((cls == 3u && !vse) || b > 32u) {
                 bad = true;
                 b = 0;
             }
-            const uint32_t F = cls == 0u ? 8u : cls == 1u ? 16u : 32u;
+            const uint32_t F = frame_tuples(cls);
             const uint32_t j0 = i == 0u ? sub0 : 0u;
             if (j0 >= F) bad = true;
             else cnt[j] = F - j0;
@@ -2043,10 +2049,10 @@ __device__ __forceinline__ uint32_t pack_units_sim(PackSmem<PI, SW> &sm, const u
     return 0;
 }
 
-// ---- Group-AFOR: frame bytes ------------------------------------------------
+// ---- Group-AFOR / Group-VSEncoding (vse): frame bytes -----------------------
 template <int PI, int SW>
 __device__ __forceinline__ uint32_t pack_units_afor(PackSmem<PI, SW> &sm, const uint32_t *sw, uint32_t lane, uint32_t U,
-                                    uint32_t kq, uint32_t lk, const uint16_t *Tl, const uint16_t *cwl,
+                                    uint32_t kq, uint32_t lk, bool vse, const uint16_t *Tl, const uint16_t *cwl,
                                     const uint16_t *Dl, const uint16_t *d0l) {
     using SM = PackSmem<PI, SW>;
     uint32_t c_t = 0, c_b = 0, nu = 0;
@@ -2059,8 +2065,8 @@ __device__ __forceinline__ uint32_t pack_units_afor(PackSmem<PI, SW> &sm, const 
         const uint32_t Tj = Tl[j];
         const uint32_t byte = in ? (sw[cwl[j] + (s >> 2)] >> (8u * (s & 3u))) & 0xFFu : 0u;
         const uint32_t cls = byte >> 6, b = byte & 63u;
-        const bool fok = cls != 3u && b <= 32u;
-        const uint32_t F = in ? 8u << (fok ? cls : 0u) : 0u;
+        const bool fok = (cls != 3u || vse) && b <= 32u;
+        const uint32_t F = in ? frame_tuples(fok ? cls : 0u) : 0u;
         const uint32_t bb = fok ? b : 0u;
         const int head = seg_head(sm.ub[j], g0);
         const uint32_t st = seg_excl_scan(F, head, c_t);
@@ -2419,7 +2425,7 @@ __device__ __forceinline__ bool pack_one(const PackArgs &a, PackSmem<PI, SW> &sm
     const bool dok = !mine || (d.n >= 1u && (d.words & 3u) == 0u && (C & 3u) == 0u && 4u + C + D <= d.words &&
                                (D & (k - 1u)) == 0u);
     const int cls = hok ? (h.codec == 0 ? kClsSim : h.codec == 1 ? (h.ld == GC_LD_BINARY ? kClsGscB : kClsGscU)
-                                        : h.codec == 2 ? kClsAfor : kClsPfd) : -1;
+                                        : h.codec == 3 ? kClsPfd : kClsAfor) : -1;
     // control units of the list
     const uint32_t units = !mine ? 0u
                          : cls == kClsSim  ? D >> lk
@@ -2509,7 +2515,7 @@ __device__ __forceinline__ bool pack_one(const PackArgs &a, PackSmem<PI, SW> &sm
         for (uint32_t t = lane; t < (uint32_t)SM::TUP; t += 64u) sm.rec[t] = 0u;
         wave_lds_sync();
         err = cls == kClsSim ? pack_units_sim(sm, sw, lane, U, kq, Tl, cwl, Cl, d0l)
-                             : pack_units_afor(sm, sw, lane, U, kq, lk, Tl, cwl, Dl, d0l);
+                             : pack_units_afor(sm, sw, lane, U, kq, lk, h.codec == 4, Tl, cwl, Dl, d0l);
         wave_lds_sync();
         if (!err) pack_expand(sm, lane, kq);
     } else if (cls == kClsGscB) {
@@ -2587,8 +2593,8 @@ int codec_class(uint32_t w0) {
     switch (h.codec) {
     case 0: return kClsSim;
     case 1: return h.ld == GC_LD_BINARY ? kClsGscB : kClsGscU;
-    case 2: return kClsAfor;
-    default: return kClsPfd;
+    case 3: return kClsPfd;
+    default: return kClsAfor;   // Group-AFOR, Group-VSEncoding
     }
 }
 

@@ -157,26 +157,34 @@ void enc_scheme(const uint32_t *x, size_t T, int k, int cg, int ld, const std::v
     a.data.resize((size_t)k * (size_t)((O + 31) / 32));
 }
 
-// ---- Group-AFOR ---------------------------------------------------------
-void enc_afor(const uint32_t *x, size_t M, int k, const std::vector<uint8_t> &W, Areas &a) {
+// ---- Group-AFOR and Group-VSEncoding ----------------------------------------
+// vse: Group-VSEncoding, frames of 8, 12, 16 or 32 tuples starting at multiples
+// of 4 tuples (VSEncoding's frame lengths that fit a group frame; class 3 of
+// the control byte is the 12-tuple frame); otherwise Group-AFOR's 8, 16, 32.
+void enc_afor(const uint32_t *x, size_t M, int k, const std::vector<uint8_t> &W, Areas &a, bool vse) {
     // exact minimum of sum over frames of (8 + k*F*b) by dynamic programming
-    // from the end; frame sizes tried 32, 16, 8 with strict improvement, so
-    // ties keep the larger frame (Section 6.1)
-    const size_t oct = M / 8;
+    // from the end, over groups of g tuples; frame sizes tried largest first
+    // with strict improvement, so ties keep the larger frame (Section 6.1)
+    const size_t g = vse ? 4 : 8;
+    const size_t oct = M / g;
     std::vector<uint64_t> cost(oct + 1, 0);
     std::vector<uint8_t> choice(oct + 1, 0);
-    std::vector<uint8_t> omax(oct + 1, 0);   // max width per octet of tuples
+    std::vector<uint8_t> omax(oct + 1, 0);   // max width per group of tuples
     for (size_t o = 0; o < oct; o++) {
         uint8_t m = 0;
-        for (size_t t = 8 * o; t < 8 * o + 8; t++) m = std::max(m, W[t]);
+        for (size_t t = g * o; t < g * o + g; t++) m = std::max(m, W[t]);
         omax[o] = m;
     }
+    static const int kAfor[3] = {32, 16, 8}, kVse[4] = {32, 16, 12, 8};
+    const int *Fs = vse ? kVse : kAfor;
+    const int nF = vse ? 4 : 3;
     for (size_t o = oct; o-- > 0;) {
         uint64_t best = UINT64_MAX;
         uint8_t bf = 0;
-        for (int F : {32, 16, 8}) {
-            const size_t no = (size_t)F / 8;
-            if (o + no > oct) continue;
+        for (int i = 0; i < nF; i++) {
+            const int F = Fs[i];
+            const size_t no = (size_t)F / g;
+            if (o + no > oct || cost[o + no] == UINT64_MAX) continue;   // the rest cannot be tiled
             uint8_t b = 0;
             for (size_t q = o; q < o + no; q++) b = std::max(b, omax[q]);
             const uint64_t c = 8 + (uint64_t)k * (uint64_t)F * b + cost[o + no];
@@ -191,11 +199,11 @@ void enc_afor(const uint32_t *x, size_t M, int k, const std::vector<uint8_t> &W,
     BitWriter cw(a.ctrl);
     uint64_t O = 0;
     std::vector<std::pair<uint8_t, uint8_t>> frames;
-    for (size_t o = 0; o < oct; o += choice[o] / 8) {
+    for (size_t o = 0; o < oct; o += choice[o] / g) {
         const int F = choice[o];
         uint8_t b = 0;
-        for (size_t q = o; q < o + (size_t)F / 8; q++) b = std::max(b, omax[q]);
-        const uint32_t cls = F == 8 ? 0u : F == 16 ? 1u : 2u;
+        for (size_t q = o; q < o + (size_t)F / g; q++) b = std::max(b, omax[q]);
+        const uint32_t cls = F == 8 ? 0u : F == 16 ? 1u : F == 32 ? 2u : 3u;
         cw.put((uint32_t)b | (cls << 6), 8);
         frames.emplace_back((uint8_t)F, b);
         O += (uint64_t)F * b;
@@ -338,7 +346,7 @@ size_t bound_words(size_t n, int codec, int k) {
 
 int check_params(int codec, const gc_params *p) {
     if (!p) return GC_EINVAL;
-    if (codec < 0 || codec > 3) return GC_EINVAL;
+    if (codec < 0 || codec > 4) return GC_EINVAL;
     if (p->k < 4 || p->k > 64 || (p->k & (p->k - 1)) != 0) return GC_EINVAL;
     if (codec == GC_SCHEME) {
         if (p->cg != 1 && p->cg != 2 && p->cg != 4 && p->cg != 8) return GC_EINVAL;
@@ -359,7 +367,7 @@ int encode_one(const uint32_t *in, size_t n, int codec, const gc_params *p, uint
     if (n > 0xFFFFFFFFull) return GC_EINVAL;
     const int k = (int)p->k;
     const size_t T = (n + (size_t)k - 1) / (size_t)k;
-    const size_t unit = codec == GC_AFOR ? 8 : codec == GC_PFD ? 32 : 1;
+    const size_t unit = codec == GC_AFOR || codec == GC_VSE ? 8 : codec == GC_PFD ? 32 : 1;
     const size_t M = (T + unit - 1) / unit * unit;
     std::vector<uint32_t> x(M * (size_t)k + 1, 0u);
     if (p->flags & GC_DELTA) {
@@ -377,7 +385,8 @@ int encode_one(const uint32_t *in, size_t n, int codec, const gc_params *p, uint
     switch (codec) {
     case GC_SIMPLE: enc_simple(x.data(), T, k, W, a); break;
     case GC_SCHEME: enc_scheme(x.data(), T, k, p->cg, p->ld, W, a); break;
-    case GC_AFOR: enc_afor(x.data(), M, k, W, a); break;
+    case GC_AFOR: enc_afor(x.data(), M, k, W, a, false); break;
+    case GC_VSE: enc_afor(x.data(), M, k, W, a, true); break;
     default: enc_pfd(x.data(), M, k, p->zeta_num, p->zeta_den, p->pfd_pos, W, a); break;
     }
     const size_t C = ((size_t)((a.ctrl_bits + 31) / 32) + 3) / 4 * 4;

@@ -36,7 +36,7 @@ GC_HD inline bool header_fields(uint32_t w0, HeaderFields &h) {
     h.delta = (int)((w0 >> 19) & 1u);
     h.pfd_pos = (int)((w0 >> 20) & 1u);
     if ((w0 & 0xFFu) != GC_FMT_VERSION || (w0 >> 21) != 0u) return false;
-    if (h.codec > 3 || h.lk < 2 || h.lk > 6) return false;
+    if (h.codec > 4 || h.lk < 2 || h.lk > 6) return false;
     if (h.codec == 1) {
         if (h.ld > 2 || (h.ld == 2 && h.cg < 4)) return false;
     } else if (((w0 >> 15) & 15u) != 0u) {
@@ -45,6 +45,11 @@ GC_HD inline bool header_fields(uint32_t w0, HeaderFields &h) {
     if (h.codec != 3 && h.pfd_pos != 0) return false;
     return true;
 }
+
+// Tuples of a Group-AFOR / Group-VSEncoding frame of class cls (bits 6..7 of
+// its control byte): 8, 16, 32, and for Group-VSEncoding 12 (class 3, which
+// Group-AFOR leaves unused).
+GC_HD inline uint32_t frame_tuples(uint32_t cls) { return cls == 3u ? 12u : 8u << cls; }
 
 #include <stddef.h>
 namespace gcfmt {

@@ -85,7 +85,8 @@ uint32_t locate_words_host(const HeaderFields &h, uint32_t T, uint32_t C, uint32
             return std::min(C, (T + fpw - 1u) / fpw);
         }
         return C;
-    case 2: return C;
+    case 2:
+    case 4: return C;
     default: return std::min(C, (T + 31u) >> 5);
     }
 }

@@ -17,7 +17,7 @@ import threading
 
 import numpy as np
 
-SIMPLE, SCHEME, AFOR, PFD = 0, 1, 2, 3
+SIMPLE, SCHEME, AFOR, PFD, VSE = 0, 1, 2, 3, 4   # VSE: Group-VSEncoding (decoded by the AFOR class)
 LD_BINARY, LD_CU, LD_IU = 0, 1, 2
 PFD_LINKED, PFD_BITMAP = 0, 1
 DELTA = 1

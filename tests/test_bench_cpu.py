@@ -61,5 +61,5 @@ def test_traffic_only_for_the_profiled_sources_workload_and_kernel():
 def test_variant_table_covers_every_codec_variant():
     from paper_1502_01916_amd import gc
     names = [v[0] for v in bench.all_variants(gc)]
-    assert len(names) == len(set(names)) == 14    # Simple, ten Group-Scheme, AFOR, PFD, BP128
+    assert len(names) == len(set(names)) == 15    # Simple, ten Group-Scheme, AFOR, PFD, BP128, VSE
     assert sum(1 for n in names if n.startswith("gsc-")) == 10

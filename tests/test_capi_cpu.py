@@ -37,7 +37,7 @@ VARIANTS = [
     (O.SCHEME, dict(cg=1, ld=O.LD_BINARY)), (O.SCHEME, dict(cg=2, ld=O.LD_BINARY)),
     (O.SCHEME, dict(cg=4, ld=O.LD_BINARY)), (O.SCHEME, dict(cg=8, ld=O.LD_BINARY)),
     (O.AFOR, {}), (O.PFD, {}), (O.PFD, dict(pfd_pos=O.PFD_BITMAP)), (O.PFD, dict(zeta=(1, 32))),
-    (O.PFD, dict(zeta=(3, 10))),
+    (O.PFD, dict(zeta=(3, 10))), (O.VSE, {}),
 ]
 
 

@@ -113,6 +113,16 @@ def test_gpu_encoder_capacity(torch_cuda):
         gc.encode_lists_gpu(d, np.array([1000]), gc.SIMPLE, gc.params(delta=True), d_out=small)
 
 
+def test_gpu_encoder_refuses_vse(torch_cuda):
+    """Group-VSEncoding streams come from the host encoder only: the GPU
+    encoder returns GC_EINVAL for that codec."""
+    x = np.arange(1000, dtype=np.uint32) * 7
+    d = gc.to_device(x)
+    with pytest.raises(gc.GcError) as e:
+        gc.encode_lists_gpu(d, np.array([1000]), gc.VSE, gc.params(delta=True))
+    assert e.value.code == gc.EINVAL
+
+
 @pytest.mark.parametrize("k", [4, 64])
 def test_gpu_encoder_cfg2(torch_cuda, k):
     """The full cfg2 lists (10,000 docID lists of 2^26 docIDs and their TF

@@ -23,7 +23,7 @@ VARIANTS = [
     ("gsc2b", O.SCHEME, dict(cg=2, ld=O.LD_BINARY)), ("gsc4b", O.SCHEME, dict(cg=4, ld=O.LD_BINARY)),
     ("gsc8b", O.SCHEME, dict(cg=8, ld=O.LD_BINARY)), ("afor", O.AFOR, {}),
     ("pfd", O.PFD, {}), ("pfdbitmap", O.PFD, dict(pfd_pos=O.PFD_BITMAP)),
-    ("bp128", O.PFD, dict(zeta=(1, 32))),
+    ("bp128", O.PFD, dict(zeta=(1, 32))), ("vse", O.VSE, {}),
 ]
 
 
