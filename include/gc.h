@@ -4,8 +4,9 @@
  *
  * The codecs are those of Zhao et al., "A General SIMD-based Approach to
  * Accelerating Compression Algorithms" (arXiv 1502.01916): Group-Simple
- * (Section 4), Group-Scheme (Section 5), Group-AFOR (Section 6.1) and
- * Group-PFD (Section 6.2), each storing its control patterns apart from the
+ * (Section 4), Group-Scheme (Section 5), Group-AFOR (Section 6.1),
+ * Group-PFD (Section 6.2) and a Group-VSEncoding (named in Section 6.1 without
+ * a format; see GC_VSE), each storing its control patterns apart from the
  * packed data, which uses the k-way vertical layout (Section 3.1; the paper's
  * k is 4, wider k is a GPU-native option).  Decoding is followed by the
  * d-gap prefix sum that restores docIDs (Section 2.1.1).
@@ -128,8 +129,8 @@ gc_status gc_encode_lists(const uint32_t *h_in, const uint64_t *in_offs, size_t 
  * hip_stream).  Its device scratch (about 12 bytes per integer at most) and
  * pinned host staging are kept per device, for later calls, until the
  * process ends, and grow when a call needs more; calls on one device run
- * one at a time.  GC_EINVAL for bad parameters, GC_ENOSPC if the streams do
- * not fit (h_out_offs then holds their sizes), GC_ENOMEM if the scratch
+ * one at a time.  GC_EINVAL for bad parameters or GC_VSE (whose streams
+ * come from gc_encode_lists), GC_ENOSPC if the streams do not fit (h_out_offs then holds their sizes), GC_ENOMEM if the scratch
  * does not fit.                                                            */
 gc_status gc_encode_lists_gpu(const uint32_t *d_in, const uint64_t *h_in_offs, size_t nlists,
                               gc_codec codec, const gc_params *p, uint32_t *d_out,
