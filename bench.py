@@ -198,13 +198,15 @@ def build_cfg2(gc, synth, variants=None):
 _CFG5 = None
 
 
-def build_cfg5(gc, synth, name):
+def build_cfg5(gc, synth, name, spec=None):
+    """The cfg5 lists in the format of CFG5_BATCHES[name], or of `spec`
+    (codec name, params) under that name."""
     global _CFG5
     t = time.time()
     if _CFG5 is None:
         _CFG5 = synth.cfg5()
     lengths, docs = _CFG5
-    codec_name, kw = CFG5_BATCHES[name]
+    codec_name, kw = spec if spec else CFG5_BATCHES[name]
     codec = getattr(gc, codec_name)
     s, offs = gc.encode_lists(docs, lengths, codec, gc.params(delta=True, **kw))
     log("%s: %d lists, %d docIDs, %.2f bits/int (%.1fs)" % (name, lengths.size, docs.size,
@@ -632,6 +634,24 @@ def variants_leg(gc, torch, ctx, synth, args, cfg2_data):
     return out
 
 
+def widths_leg(gc, torch, ctx, synth, args):
+    """The cfg5 lists in Group-AFOR and Group-PFD at the layout widths between
+    the paper's 4-way layout and the 64-way one (Section 3.1's k-way layout):
+    bits/int, Gints/s and % of HBM for k = 8, 16 and 32 (4 and 64 are the
+    cfg5 batches of the full run)."""
+    out = {}
+    for codec_name in ("AFOR", "PFD"):
+        for k in (8, 16, 32):
+            name = "cfg5-%s-k%d" % (codec_name.lower(), k)
+            w5 = build_cfg5(gc, synth, name, (codec_name, dict(k=k)))
+            rec = leg_record(w5, measure(gc, torch, ctx, w5, args))
+            out[name] = {key: rec[key] for key in ("bits_per_int", "value", "path_hbm_frac", "dominant_kernel",
+                                                   "dominant_kernel_hbm_frac", "pack_ints", "verified_bit_exact")}
+            log("%-16s %s" % (name, out[name]))
+            del w5
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -650,9 +670,9 @@ def main():
     ap.add_argument("--pfd-tile", type=int, default=0, help="force the Group-PFD tile size (with --tile)")
     ap.add_argument("--locate-stream", action="store_true",
                     help="run the locate kernels on a second stream, ahead of the other kernels")
-    ap.add_argument("--leg", choices=("encode", "query", "variants"),
-                    help="run only this cfg2 leg (the list encoders, AND queries, or every codec variant) "
-                         "and print its record")
+    ap.add_argument("--leg", choices=("encode", "query", "variants", "widths"),
+                    help="run only this leg (cfg2: the list encoders, AND queries, or every codec variant; "
+                         "widths: the cfg5 lists at k = 8, 16, 32) and print its record")
     ap.add_argument("--carry-pass", type=int, default=0, choices=(0, 1, 2, 3),
                     help="carries of delta lists: 1 look-back in the decode pass, 2 tile-sum pass and carry "
                          "scan, 3 look-back for lists of up to 64 tiles and the tile-sum pass for longer ones, "
@@ -671,14 +691,17 @@ def main():
         sys.exit(1)
     gc.lib()
     if args.leg:
-        data = synth.cfg2()
+        data = synth.cfg2() if args.leg != "widths" else None
         if args.leg == "encode":
             rec = encode_leg(gc, torch, data)
         elif args.leg == "variants":
             rec = variants_leg(gc, torch, gc.Context(0), synth, args, data)
+        elif args.leg == "widths":
+            rec = widths_leg(gc, torch, gc.Context(0), synth, args)
         else:
             rec = query_leg(gc, torch, gc.Context(0), synth, data)
-        print(json.dumps({"leg": args.leg + "_cfg2", "record": rec}), flush=True)
+        print(json.dumps({"leg": args.leg + ("_cfg5" if args.leg == "widths" else "_cfg2"), "record": rec}),
+              flush=True)
         return
     legs = args.workload == "cfg3" and not args.no_extra
 
