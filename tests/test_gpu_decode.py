@@ -438,6 +438,11 @@ def test_corrupt_streams_latch_status(torch_cuda, ctx):
     bad = s.copy()
     bad[4 + 1] |= 0xC0C0C0C0                         # frame class 3
     cases.append(("afor class", bad))
+    s = O.encode(d, O.params(O.VSE, delta=True))
+    bad = s.copy()
+    bad[4 + 1] = 0xE8E8E8E8                          # 12-tuple frames of width 40
+    assert O.decode_status(bad) == O.ECORRUPT
+    cases.append(("vse width", bad))
     s = O.encode(d, O.params(O.PFD, delta=True))
     bad = s.copy()
     bad[4 + 2] = (int(bad[4 + 2]) & ~63) | 45        # b = 45
