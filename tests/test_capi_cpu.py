@@ -92,7 +92,8 @@ def test_encode_rejects_bad_parameters():
     x = np.arange(100, dtype=np.uint32)
     for codec, p in [(gc.SCHEME, gc.params(cg=3)), (gc.SCHEME, gc.params(cg=2, ld=gc.LD_IU)),
                      (gc.PFD, gc.params(zeta=(0, 10))), (gc.PFD, gc.params(zeta=(10, 10))),
-                     (gc.SIMPLE, gc.params(k=6)), (gc.SIMPLE, gc.params(k=128)), (7, gc.params())]:
+                     (gc.SIMPLE, gc.params(k=6)), (gc.SIMPLE, gc.params(k=128)), (7, gc.params()),
+                     (5, gc.params())]:
         with pytest.raises(gc.GcError) as e:
             gc.encode(x, codec, p)
         assert e.value.code == gc.EINVAL

@@ -590,6 +590,11 @@ def test_header_fields():
     assert (p.codec, p.k, p.cg, p.ld, p.delta) == (O.SCHEME, 16, 8, O.LD_IU, 1)
     assert int(s[1]) == 10 and int(s[2]) % 4 == 0 and int(s[3]) % 16 == 0
     assert O.parse_header(int(s[0]) | (1 << 25)) is None
+    # codec 4 (Group-VSEncoding) is the last codec; 5 .. 15 are not streams
+    v = O.encode(np.arange(10, dtype=np.uint32), O.params(O.VSE, k=8))
+    assert O.parse_header(int(v[0])).codec == O.VSE
+    for c in range(5, 16):
+        assert O.parse_header((int(v[0]) & ~(15 << 8)) | (c << 8)) is None
 
 
 # --------------------------------------------------------------------------
